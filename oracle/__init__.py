@@ -1,0 +1,225 @@
+"""FP64 CPU oracle -- test infrastructure.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package. The product path (the HIP library and
+its binding) never does, and shares no code with it. Every function here
+calls the plain C++ implementation in this directory (``oracle.cpp`` and the
+headers it includes), which follows Featherstone's textbook for the dynamics
+and the paper for the task, observation, reward, time-out and GAE rules.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_u8p = C.POINTER(C.c_uint8)
+
+
+class _Robot(C.Structure):
+    _fields_ = [("n_env", C.c_int32), ("max_dof", C.c_int32), ("n_dof", _ip),
+                ("axis", _dp), ("offset", _dp), ("com", _dp), ("mass", _dp), ("inertia", _dp),
+                ("kp", _dp), ("kd", _dp), ("q_lo", _dp), ("q_hi", _dp), ("q0", _dp), ("tip", _dp),
+                ("dt", C.c_double), ("substeps", C.c_int32), ("gravity", C.c_double * 3)]
+
+
+class _Task(C.Structure):
+    _fields_ = [("task", C.c_int32), ("n_waypoints", C.c_int32), ("dwell", C.c_int32),
+                ("ep_len", C.c_int32), ("target", _dp), ("waypoints", _dp)]
+
+
+class _Policy(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 4), ("W", _dp * 3), ("b", _dp * 3), ("log_std", _dp)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build()
+        _lib = C.CDLL(path)
+        _lib.ora_round_bf16.restype = C.c_double
+        _lib.ora_round_bf16.argtypes = [C.c_double]
+        _lib.ora_noise.argtypes = [C.c_uint64, C.c_uint64, C.c_int, C.c_int, _dp]
+        _lib.ora_rollout.argtypes = None
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, t=_dp):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+class Oracle:
+    """Holds contiguous float64 copies of a workload's robot and task arrays."""
+
+    def __init__(self, robot, task=None, policy=None):
+        self.robot = robot
+        self.N, self.J = robot.n_env, robot.max_dof
+        self.W = 2 * self.J + 10
+        self._keep = []
+        k = self._keep
+        arr = {}
+        for name in ("axis", "offset", "com", "mass", "inertia", "kp", "kd", "q_lo", "q_hi", "q0", "tip"):
+            arr[name] = _f64(getattr(robot, name))
+            k.append(arr[name])
+        nd = np.ascontiguousarray(robot.n_dof, dtype=np.int32)
+        k.append(nd)
+        self.r = _Robot(self.N, self.J, _ptr(nd, _ip), *[_ptr(arr[n]) for n in
+                        ("axis", "offset", "com", "mass", "inertia", "kp", "kd", "q_lo", "q_hi", "q0", "tip")],
+                        float(robot.dt), int(robot.substeps), (C.c_double * 3)(*robot.gravity))
+        if task is not None:
+            tgt = None if task.target is None else _f64(task.target)
+            wps = None if task.waypoints is None else _f64(task.waypoints)
+            k.extend([tgt, wps])
+            self.t = _Task(task.task, task.n_waypoints, task.dwell, task.ep_len, _ptr(tgt), _ptr(wps))
+        else:
+            self.t = _Task(0, 0, 1, 0, None, None)
+        self.p = None
+        if policy is not None:
+            Ws = [_f64(w) for w in policy.W]
+            bs = [_f64(b) for b in policy.b]
+            ls = _f64(policy.log_std)
+            k.extend(Ws + bs + [ls])
+            self.p = _Policy((C.c_int32 * 4)(*policy.dims), (_dp * 3)(*[_ptr(w) for w in Ws]),
+                             (_dp * 3)(*[_ptr(b) for b in bs]), _ptr(ls))
+
+    # ---- dynamics -------------------------------------------------------
+    def fk(self, q):
+        out = np.zeros((3, self.N))
+        lib().ora_fk(C.byref(self.r), _ptr(_f64(q)), _ptr(out))
+        return out
+
+    def fk_links(self, q):
+        com = np.zeros((3, self.J, self.N))
+        jw = np.zeros((3, self.J, self.N))
+        R = np.zeros((9, self.J, self.N))
+        lib().ora_fk_links(C.byref(self.r), _ptr(_f64(q)), _ptr(com), _ptr(jw), _ptr(R))
+        return com, jw, R
+
+    def rnea(self, q, qd, qdd):
+        out = np.zeros((self.J, self.N))
+        lib().ora_rnea(C.byref(self.r), _ptr(_f64(q)), _ptr(_f64(qd)), _ptr(_f64(qdd)), _ptr(out))
+        return out
+
+    def crba(self, q):
+        out = np.zeros((self.N, self.J, self.J))
+        lib().ora_crba(C.byref(self.r), _ptr(_f64(q)), _ptr(out))
+        return out
+
+    def aba(self, q, qd, tau, arm=None):
+        out = np.zeros((self.J, self.N))
+        a = None if arm is None else _f64(arm)
+        lib().ora_aba(C.byref(self.r), _ptr(_f64(q)), _ptr(_f64(qd)), _ptr(_f64(tau)), _ptr(a), _ptr(out))
+        return out
+
+    def fd_crba(self, q, qd, tau, arm=None):
+        out = np.zeros((self.J, self.N))
+        a = None if arm is None else _f64(arm)
+        bad = lib().ora_fd_crba(C.byref(self.r), _ptr(_f64(q)), _ptr(_f64(qd)), _ptr(_f64(tau)), _ptr(a),
+                                _ptr(out))
+        return out, bad
+
+    def drive_armature(self):
+        """arm = h kd + h^2 kp per joint [J][N] (the implicit-PD armature)."""
+        h = self.robot.dt / self.robot.substeps
+        return h * _f64(self.robot.kd) + h * h * _f64(self.robot.kp)
+
+    # ---- environment -----------------------------------------------------
+    def observe(self, q, qd, progress):
+        obs = np.zeros((self.W, self.N))
+        pr = np.ascontiguousarray(progress, dtype=np.int32)
+        lib().ora_observe(C.byref(self.r), C.byref(self.t), _ptr(_f64(q)), _ptr(_f64(qd)), _ptr(pr, _ip),
+                          _ptr(obs))
+        return obs
+
+    def step(self, action, q, qd, progress, log_qdd=False, envs=None, threads=1):
+        """One control step. Returns (q, qd, progress, reward, done, obs[, qdd_log])."""
+        q = _f64(q).copy()
+        qd = _f64(qd).copy()
+        pr = np.ascontiguousarray(progress, dtype=np.int32).copy()
+        rew = np.zeros(self.N)
+        done = np.zeros(self.N, dtype=np.uint8)
+        obs = np.zeros((self.W, self.N))
+        qlog = np.zeros((self.robot.substeps, self.J, self.N)) if log_qdd else None
+        e0, e1 = (0, self.N) if envs is None else envs
+        lib().ora_step(C.byref(self.r), C.byref(self.t), _ptr(_f64(action)), _ptr(q), _ptr(qd), _ptr(pr, _ip),
+                       _ptr(rew), _ptr(done, _u8p), _ptr(obs), _ptr(qlog), C.c_int(e0), C.c_int(e1),
+                       C.c_int(threads))
+        out = (q, qd, pr, rew, done, obs)
+        return out + (qlog,) if log_qdd else out
+
+    def opcount_step(self, action, env=0):
+        counts = (C.c_longlong * 10)()
+        lib().ora_opcount_step(C.byref(self.r), C.byref(self.t), C.c_int(env), _ptr(_f64(action)), counts)
+        names = ["add", "mul", "div", "sqrt", "trans"]
+        step = dict(zip(names, counts[:5]))
+        phys = dict(zip(names, counts[5:]))
+        return step, phys
+
+    # ---- learning side ---------------------------------------------------
+    def mlp(self, x, emulate=True):
+        B = x.shape[1]
+        out = np.zeros((self.p.dims[3], B))
+        lib().ora_mlp_forward(C.byref(self.p), _ptr(_f64(x)), _ptr(out), C.c_int(B), C.c_int(int(emulate)))
+        return out
+
+    def rollout(self, T, seed, step0, q, qd, progress, obs0, gamma=0.99, lam=0.95, emulate=True, envs=None):
+        N, J, W = self.N, self.J, self.W
+        q = _f64(q).copy()
+        qd = _f64(qd).copy()
+        pr = np.ascontiguousarray(progress, dtype=np.int32).copy()
+        obs = np.zeros((T + 1, W, N))
+        obs[0] = obs0
+        act = np.zeros((T, J, N))
+        logp = np.zeros((T, N))
+        rew = np.zeros((T, N))
+        done = np.zeros((T, N), dtype=np.uint8)
+        val = np.zeros((T + 1, N))
+        adv = np.zeros((T, N))
+        ret = np.zeros((T, N))
+        e0, e1 = (0, N) if envs is None else envs
+        lib().ora_rollout(C.byref(self.r), C.byref(self.t), C.byref(self.p), C.c_int(T), C.c_uint64(seed),
+                          C.c_uint64(step0), C.c_double(gamma), C.c_double(lam), C.c_int(int(emulate)), _ptr(q),
+                          _ptr(qd), _ptr(pr, _ip), _ptr(obs), _ptr(act), _ptr(logp), _ptr(rew), _ptr(done, _u8p),
+                          _ptr(val), _ptr(adv), _ptr(ret), C.c_int(e0), C.c_int(e1))
+        return dict(q=q, qd=qd, progress=pr, obs=obs, act=act, logp=logp, rew=rew, done=done, val=val, adv=adv,
+                    ret=ret)
+
+
+def philox4x32_10(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (C.c_uint32 * 4)()
+    lib().ora_philox4x32_10(c, k, o)
+    return [o[i] for i in range(4)]
+
+
+def noise(seed, step, n, N):
+    eps = np.zeros((n, N))
+    lib().ora_noise(C.c_uint64(seed), C.c_uint64(step), C.c_int(n), C.c_int(N), _ptr(eps))
+    return eps
+
+
+def round_bf16(x):
+    f = lib().ora_round_bf16
+    return np.vectorize(lambda v: f(float(v)))(np.asarray(x, dtype=np.float64))
+
+
+def gae(rew, val, done, gamma=0.99, lam=0.95):
+    T, N = rew.shape
+    adv = np.zeros((T, N))
+    ret = np.zeros((T, N))
+    lib().ora_gae(C.c_int(T), C.c_int(N), _ptr(_f64(rew)), _ptr(_f64(val)),
+                  _ptr(np.ascontiguousarray(done, dtype=np.uint8), _u8p), C.c_double(gamma), C.c_double(lam),
+                  _ptr(adv), _ptr(ret))
+    return adv, ret

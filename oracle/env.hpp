@@ -1,0 +1,159 @@
+// Test infrastructure: part of the FP64 CPU oracle. Only tests/, the smoke
+// check and the CPU-baseline leg of the benchmark may load or run anything
+// under oracle/; the product path never does.
+//
+// One control step of one environment: PD action mapping, S substeps of
+// implicit-PD forward dynamics with semi-implicit Euler and joint-limit
+// projection, then forward kinematics into reward, episode bookkeeping,
+// auto-reset and the observation vector.
+//
+// Paper passages this follows: actions are PD position targets (Sec. III
+// "Action Space", and joints accept PD targets per Sec. III "Simulation
+// Setup"); the solver advances in substeps (Sec. III "Simulation Setup");
+// the observation concatenates joint positions, velocities, the tool-tip
+// position and the goal (Sec. III "Observation Space"); the target-reaching
+// reward rho * ||eta_t - g|| and the path-following reward
+// -alpha * ||eta_t - P(t)|| (Sec. IV "Environments"); time-outs are told
+// apart from terminations so the critic can bootstrap (Sec. III "Policy
+// learning and control"). Readings where the paper is silent:
+//   * PD drive, implicit: tau~ = kp (q* - q - h qd) - kd qd with armature
+//     arm = h kd + h^2 kp added to the joint inertia, which is exactly
+//     tau = kp (q* - q') - kd qd' on the end-of-substep state;
+//   * q* = mid + half_range * clamp(a, -1, 1) over the joint limits, held
+//     constant over the substeps;
+//   * hard-stop limits after each position update: q clamped, the outward
+//     velocity component zeroed (q == hi counts as inside);
+//   * rho = alpha = -1 / 1 (reward = minus the distance), on the post-step
+//     tip; path waypoint index k = min(K-1, progress_before / dwell);
+//   * episode end at progress == ep_len (bits 0|1: ended, time-out), a
+//     non-finite state ends the episode too (bits 0|2) with reward 0; both
+//     auto-reset to (q0, 0), progress 0; the observation returned is the
+//     post-reset one;
+//   * observation (width 2*Jmax + 10): [q (Jmax), qd (Jmax), tip (3),
+//     goal (3), goal - tip (3), |goal - tip| (1)], unused joint slots zero.
+#pragma once
+#include <cmath>
+#include <cstdint>
+
+#include "chain.hpp"
+
+namespace ora {
+
+enum { kTaskReach = 0, kTaskPath = 1 };
+enum { kDoneEnded = 1, kDoneTimeout = 2, kDoneNonFinite = 4 };
+
+template <class T> struct Drive {
+  T kp[kMaxDof], kd[kMaxDof], lo[kMaxDof], hi[kMaxDof], q0[kMaxDof];
+};
+
+struct TaskSpec {
+  int task;         // kTaskReach or kTaskPath
+  int n_waypoints;  // K (path task)
+  int dwell;        // control steps per waypoint (path task)
+  int ep_len;       // episode length in control steps; <= 0: never times out
+};
+
+template <class T> struct EnvGoal {
+  V3<T> target;       // reach task
+  V3<T> wp[32];       // path task waypoints
+};
+
+template <class T> inline V3<T> goal_for(const TaskSpec& ts, const EnvGoal<T>& g, int progress) {
+  if (ts.task == kTaskReach) return g.target;
+  int k = progress / ts.dwell;
+  if (k > ts.n_waypoints - 1) k = ts.n_waypoints - 1;
+  return g.wp[k];
+}
+
+// Physics part of a control step (substeps only). qdd_log, if non-null,
+// receives the joint accelerations of every substep ([S][n]).
+template <class T>
+inline void physics_step(const Chain<T>& ch, const Drive<T>& dr, T dt, int S, const T* action, T* q, T* qd,
+                         T* qdd_log) {
+  const int n = ch.n;
+  T h = dt / T(double(S));
+  T qstar[kMaxDof], arm[kMaxDof], tau[kMaxDof], qdd[kMaxDof];
+  for (int j = 0; j < n; ++j) {
+    double a = val(action[j]);
+    T ac = a > 1.0 ? T(1.0) : (a < -1.0 ? T(-1.0) : action[j]);
+    T mid = T(0.5) * (dr.hi[j] + dr.lo[j]);
+    T half = T(0.5) * (dr.hi[j] - dr.lo[j]);
+    qstar[j] = mid + half * ac;
+    arm[j] = h * dr.kd[j] + h * h * dr.kp[j];
+  }
+  for (int s = 0; s < S; ++s) {
+    for (int j = 0; j < n; ++j) tau[j] = dr.kp[j] * (qstar[j] - q[j] - h * qd[j]) - dr.kd[j] * qd[j];
+    aba(ch, q, qd, tau, arm, qdd);
+    for (int j = 0; j < n; ++j) {
+      qd[j] = qd[j] + h * qdd[j];
+      q[j] = q[j] + h * qd[j];
+      if (q[j] > dr.hi[j]) {
+        q[j] = dr.hi[j];
+        if (qd[j] > T(0.0)) qd[j] = T(0.0);
+      } else if (q[j] < dr.lo[j]) {
+        q[j] = dr.lo[j];
+        if (qd[j] < T(0.0)) qd[j] = T(0.0);
+      }
+      if (qdd_log) qdd_log[s * n + j] = qdd[j];
+    }
+  }
+}
+
+template <class T> inline T norm3(const V3<T>& a) {
+  using std::sqrt;
+  return sqrt(dot(a, a));
+}
+
+// Observation of the current state. width = 2*Jmax + 10.
+template <class T>
+inline void observe(const Chain<T>& ch, int Jmax, const TaskSpec& ts, const EnvGoal<T>& g, const T* q, const T* qd,
+                    int progress, T* obs) {
+  Pose<T> P;
+  forward_kinematics(ch, q, P);
+  V3<T> goal = goal_for(ts, g, progress);
+  V3<T> d = goal - P.tip;
+  for (int j = 0; j < Jmax; ++j) {
+    obs[j] = j < ch.n ? q[j] : T(0.0);
+    obs[Jmax + j] = j < ch.n ? qd[j] : T(0.0);
+  }
+  T* o = obs + 2 * Jmax;
+  o[0] = P.tip.x; o[1] = P.tip.y; o[2] = P.tip.z;
+  o[3] = goal.x;  o[4] = goal.y;  o[5] = goal.z;
+  o[6] = d.x;     o[7] = d.y;     o[8] = d.z;
+  o[9] = norm3(d);
+}
+
+// Whole control step. Returns the done bits; writes reward and obs.
+template <class T>
+inline uint8_t env_step(const Chain<T>& ch, const Drive<T>& dr, T dt, int S, int Jmax, const TaskSpec& ts,
+                        const EnvGoal<T>& g, const T* action, T* q, T* qd, int* progress, T* reward, T* obs,
+                        T* qdd_log) {
+  physics_step(ch, dr, dt, S, action, q, qd, qdd_log);
+  const int n = ch.n;
+  Pose<T> P;
+  forward_kinematics(ch, q, P);
+  int pre = *progress;
+  V3<T> goal = goal_for(ts, g, pre);
+  *reward = -norm3(P.tip - goal);
+  *progress = pre + 1;
+  uint8_t done = 0;
+  bool finite = true;
+  for (int j = 0; j < n; ++j) finite = finite && std::isfinite(val(q[j])) && std::isfinite(val(qd[j]));
+  if (!finite) {
+    done = kDoneEnded | kDoneNonFinite;
+    *reward = T(0.0);
+  } else if (ts.ep_len > 0 && *progress >= ts.ep_len) {
+    done = kDoneEnded | kDoneTimeout;
+  }
+  if (done) {
+    for (int j = 0; j < n; ++j) {
+      q[j] = dr.q0[j];
+      qd[j] = T(0.0);
+    }
+    *progress = 0;
+  }
+  observe(ch, Jmax, ts, g, q, qd, *progress, obs);
+  return done;
+}
+
+}  // namespace ora

@@ -1,0 +1,427 @@
+// Test infrastructure: the FP64 CPU oracle's C interface. Only tests/, the
+// smoke check and the CPU-baseline leg of the benchmark may load or run this
+// library; the product path never does. It shares no code with the HIP
+// library: it is written independently from the paper and from Featherstone's
+// textbook, and is checked against closed forms, invariants and brute force.
+//
+// Array layout matches the synthetic-input generator: structure of arrays,
+// [field][joint][env] for per-joint data and [field][env] for per-env data,
+// all float64 (done flags uint8, progress int32).
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "chain.hpp"
+#include "counted.hpp"
+#include "env.hpp"
+#include "rl.hpp"
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+using namespace ora;
+
+extern "C" {
+
+typedef struct {
+  int32_t n_env, max_dof;
+  const int32_t* n_dof;   // [N]
+  const double* axis;     // [3][J][N] unit joint axis (parent = child coords)
+  const double* offset;   // [3][J][N] joint origin in the parent link frame
+  const double* com;      // [3][J][N] centre of mass in the link frame
+  const double* mass;     // [J][N]
+  const double* inertia;  // [6][J][N] xx yy zz xy xz yz about the centre of mass
+  const double* kp;       // [J][N]
+  const double* kd;       // [J][N]
+  const double* q_lo;     // [J][N]
+  const double* q_hi;     // [J][N]
+  const double* q0;       // [J][N] reset position
+  const double* tip;      // [3][N] tool tip in the last link frame
+  double dt;
+  int32_t substeps;
+  double gravity[3];
+} ora_robot;
+
+typedef struct {
+  int32_t task, n_waypoints, dwell, ep_len;
+  const double* target;     // [3][N]
+  const double* waypoints;  // [K][3][N]
+} ora_task;
+
+typedef struct {
+  int32_t dims[4];          // n_in, h1, h2, n_out
+  const double* W[3];       // row-major [n_out][n_in] per layer
+  const double* b[3];
+  const double* log_std;    // [n_out - 1]
+} ora_policy;
+
+}  // extern "C"
+
+namespace {
+
+template <class T> Chain<T> load_chain(const ora_robot* r, int e) {
+  const int N = r->n_env, J = r->max_dof;
+  Chain<T> ch;
+  ch.n = r->n_dof[e];
+  for (int j = 0; j < ch.n; ++j) {
+    Link<T>& l = ch.L[j];
+    auto at = [&](const double* a, int f) { return T(a[(f * J + j) * N + e]); };
+    l.axis = v3(at(r->axis, 0), at(r->axis, 1), at(r->axis, 2));
+    l.offset = v3(at(r->offset, 0), at(r->offset, 1), at(r->offset, 2));
+    l.com = v3(at(r->com, 0), at(r->com, 1), at(r->com, 2));
+    l.mass = at(r->mass, 0);
+    T xx = at(r->inertia, 0), yy = at(r->inertia, 1), zz = at(r->inertia, 2);
+    T xy = at(r->inertia, 3), xz = at(r->inertia, 4), yz = at(r->inertia, 5);
+    l.Ic.m[0][0] = xx; l.Ic.m[0][1] = xy; l.Ic.m[0][2] = xz;
+    l.Ic.m[1][0] = xy; l.Ic.m[1][1] = yy; l.Ic.m[1][2] = yz;
+    l.Ic.m[2][0] = xz; l.Ic.m[2][1] = yz; l.Ic.m[2][2] = zz;
+    finalize_link(l);
+  }
+  ch.tip = v3(T(r->tip[0 * N + e]), T(r->tip[1 * N + e]), T(r->tip[2 * N + e]));
+  ch.grav = v3(T(r->gravity[0]), T(r->gravity[1]), T(r->gravity[2]));
+  return ch;
+}
+
+template <class T> Drive<T> load_drive(const ora_robot* r, int e) {
+  const int N = r->n_env;
+  Drive<T> d;
+  for (int j = 0; j < r->n_dof[e]; ++j) {
+    d.kp[j] = T(r->kp[j * N + e]);
+    d.kd[j] = T(r->kd[j * N + e]);
+    d.lo[j] = T(r->q_lo[j * N + e]);
+    d.hi[j] = T(r->q_hi[j * N + e]);
+    d.q0[j] = T(r->q0[j * N + e]);
+  }
+  return d;
+}
+
+TaskSpec load_taskspec(const ora_task* t) {
+  TaskSpec s;
+  s.task = t->task;
+  s.n_waypoints = t->n_waypoints;
+  s.dwell = t->dwell;
+  s.ep_len = t->ep_len;
+  return s;
+}
+
+template <class T> EnvGoal<T> load_goal(const ora_task* t, int N, int e) {
+  EnvGoal<T> g;
+  if (t->target) g.target = v3(T(t->target[0 * N + e]), T(t->target[1 * N + e]), T(t->target[2 * N + e]));
+  else g.target = v3(T(0.0), T(0.0), T(0.0));
+  for (int k = 0; k < t->n_waypoints && t->waypoints; ++k) {
+    const double* w = t->waypoints + (size_t)k * 3 * N;
+    g.wp[k] = v3(T(w[0 * N + e]), T(w[1 * N + e]), T(w[2 * N + e]));
+  }
+  return g;
+}
+
+// Gather per-joint SoA [J][N] column of env e into a dense vector.
+void gather(const double* a, int /*J*/, int N, int e, int n, double* out) {
+  for (int j = 0; j < n; ++j) out[j] = a[j * N + e];
+}
+void scatter(double* a, int /*J*/, int N, int e, int n, const double* in) {
+  for (int j = 0; j < n; ++j) a[j * N + e] = in[j];
+}
+
+}  // namespace
+
+extern "C" {
+
+int ora_max_dof() { return kMaxDof; }
+
+int ora_fk(const ora_robot* r, const double* q, double* tip) {
+  const int N = r->n_env, J = r->max_dof;
+  for (int e = 0; e < N; ++e) {
+    Chain<double> ch = load_chain<double>(r, e);
+    double qe[kMaxDof];
+    gather(q, J, N, e, ch.n, qe);
+    Pose<double> P;
+    forward_kinematics(ch, qe, P);
+    tip[0 * N + e] = P.tip.x;
+    tip[1 * N + e] = P.tip.y;
+    tip[2 * N + e] = P.tip.z;
+  }
+  return 0;
+}
+
+// World position of every link's centre of mass and joint origin, and the
+// link orientations: com_w [3][J][N], joint_w [3][J][N], R_w [9][J][N].
+int ora_fk_links(const ora_robot* r, const double* q, double* com_w, double* joint_w, double* R_w) {
+  const int N = r->n_env, J = r->max_dof;
+  for (int e = 0; e < N; ++e) {
+    Chain<double> ch = load_chain<double>(r, e);
+    double qe[kMaxDof];
+    gather(q, J, N, e, ch.n, qe);
+    Pose<double> P;
+    forward_kinematics(ch, qe, P);
+    for (int j = 0; j < ch.n; ++j) {
+      V3<double> c = P.p[j] + mul(P.R[j], ch.L[j].com);
+      com_w[(0 * J + j) * N + e] = c.x;
+      com_w[(1 * J + j) * N + e] = c.y;
+      com_w[(2 * J + j) * N + e] = c.z;
+      joint_w[(0 * J + j) * N + e] = P.p[j].x;
+      joint_w[(1 * J + j) * N + e] = P.p[j].y;
+      joint_w[(2 * J + j) * N + e] = P.p[j].z;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) R_w[((a * 3 + b) * J + j) * N + e] = P.R[j].m[a][b];
+    }
+  }
+  return 0;
+}
+
+int ora_rnea(const ora_robot* r, const double* q, const double* qd, const double* qdd, double* tau) {
+  const int N = r->n_env, J = r->max_dof;
+  for (int e = 0; e < N; ++e) {
+    Chain<double> ch = load_chain<double>(r, e);
+    double qe[kMaxDof], qde[kMaxDof], qdde[kMaxDof], te[kMaxDof];
+    gather(q, J, N, e, ch.n, qe);
+    gather(qd, J, N, e, ch.n, qde);
+    gather(qdd, J, N, e, ch.n, qdde);
+    rnea(ch, qe, qde, qdde, te);
+    scatter(tau, J, N, e, ch.n, te);
+  }
+  return 0;
+}
+
+// H: [N][J][J] row-major per env (top-left n x n used).
+int ora_crba(const ora_robot* r, const double* q, double* H) {
+  const int N = r->n_env, J = r->max_dof;
+  for (int e = 0; e < N; ++e) {
+    Chain<double> ch = load_chain<double>(r, e);
+    double qe[kMaxDof], He[kMaxDof * kMaxDof];
+    gather(q, J, N, e, ch.n, qe);
+    crba(ch, qe, He);
+    for (int i = 0; i < J * J; ++i) H[(size_t)e * J * J + i] = 0.0;
+    for (int i = 0; i < ch.n; ++i)
+      for (int j = 0; j < ch.n; ++j) H[(size_t)e * J * J + i * J + j] = He[i * ch.n + j];
+  }
+  return 0;
+}
+
+// arm may be null (zero armature).
+int ora_aba(const ora_robot* r, const double* q, const double* qd, const double* tau, const double* arm,
+            double* qdd) {
+  const int N = r->n_env, J = r->max_dof;
+  for (int e = 0; e < N; ++e) {
+    Chain<double> ch = load_chain<double>(r, e);
+    double qe[kMaxDof], qde[kMaxDof], te[kMaxDof], ae[kMaxDof] = {0}, oe[kMaxDof];
+    gather(q, J, N, e, ch.n, qe);
+    gather(qd, J, N, e, ch.n, qde);
+    gather(tau, J, N, e, ch.n, te);
+    if (arm) gather(arm, J, N, e, ch.n, ae);
+    aba(ch, qe, qde, te, ae, oe);
+    scatter(qdd, J, N, e, ch.n, oe);
+  }
+  return 0;
+}
+
+// Second route to the same answer: qdd = (H + diag(arm))^{-1} (tau - C),
+// C = RNEA(q, qd, 0). Returns the number of envs whose matrix failed Cholesky.
+int ora_fd_crba(const ora_robot* r, const double* q, const double* qd, const double* tau, const double* arm,
+                double* qdd) {
+  const int N = r->n_env, J = r->max_dof;
+  int bad = 0;
+  for (int e = 0; e < N; ++e) {
+    Chain<double> ch = load_chain<double>(r, e);
+    const int n = ch.n;
+    double qe[kMaxDof], qde[kMaxDof], te[kMaxDof], ae[kMaxDof] = {0}, zero[kMaxDof] = {0};
+    double C[kMaxDof], H[kMaxDof * kMaxDof], rhs[kMaxDof], x[kMaxDof];
+    gather(q, J, N, e, n, qe);
+    gather(qd, J, N, e, n, qde);
+    gather(tau, J, N, e, n, te);
+    if (arm) gather(arm, J, N, e, n, ae);
+    rnea(ch, qe, qde, zero, C);
+    crba(ch, qe, H);
+    for (int i = 0; i < n; ++i) {
+      H[i * n + i] += ae[i];
+      rhs[i] = te[i] - C[i];
+    }
+    if (!cholesky_solve(n, H, rhs, x)) {
+      ++bad;
+      for (int i = 0; i < n; ++i) x[i] = NAN;
+    }
+    scatter(qdd, J, N, e, n, x);
+  }
+  return bad;
+}
+
+// Observation of the given state, obs [2J+10][N].
+int ora_observe(const ora_robot* r, const ora_task* t, const double* q, const double* qd, const int32_t* progress,
+                double* obs) {
+  const int N = r->n_env, J = r->max_dof, W = 2 * J + 10;
+  TaskSpec ts = load_taskspec(t);
+  for (int e = 0; e < N; ++e) {
+    Chain<double> ch = load_chain<double>(r, e);
+    EnvGoal<double> g = load_goal<double>(t, N, e);
+    double qe[kMaxDof], qde[kMaxDof], oe[64];
+    gather(q, J, N, e, ch.n, qe);
+    gather(qd, J, N, e, ch.n, qde);
+    observe(ch, J, ts, g, qe, qde, progress[e], oe);
+    for (int w = 0; w < W; ++w) obs[w * N + e] = oe[w];
+  }
+  return 0;
+}
+
+// One control step for envs [e0, e1). State (q, qd, progress) updated in
+// place. qdd_log [S][J][N] may be null. Uses OpenMP over envs if compiled
+// with it and n_threads > 1.
+int ora_step(const ora_robot* r, const ora_task* t, const double* action, double* q, double* qd,
+             int32_t* progress, double* reward, uint8_t* done, double* obs, double* qdd_log, int e0, int e1,
+             int n_threads) {
+  const int N = r->n_env, J = r->max_dof, W = 2 * J + 10, S = r->substeps;
+  TaskSpec ts = load_taskspec(t);
+  (void)n_threads;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(n_threads > 0 ? n_threads : 1)
+#endif
+  for (int e = e0; e < e1; ++e) {
+    Chain<double> ch = load_chain<double>(r, e);
+    Drive<double> dr = load_drive<double>(r, e);
+    EnvGoal<double> g = load_goal<double>(t, N, e);
+    const int n = ch.n;
+    double qe[kMaxDof], qde[kMaxDof], ae[kMaxDof], oe[64], rew, qlog[64 * kMaxDof];
+    gather(q, J, N, e, n, qe);
+    gather(qd, J, N, e, n, qde);
+    gather(action, J, N, e, n, ae);
+    int prog = progress[e];
+    uint8_t d = env_step(ch, dr, r->dt, S, J, ts, g, ae, qe, qde, &prog, &rew, oe, qdd_log ? qlog : nullptr);
+    scatter(q, J, N, e, n, qe);
+    scatter(qd, J, N, e, n, qde);
+    progress[e] = prog;
+    reward[e] = rew;
+    done[e] = d;
+    for (int w = 0; w < W; ++w) obs[w * N + e] = oe[w];
+    if (qdd_log)
+      for (int s = 0; s < S; ++s)
+        for (int j = 0; j < n; ++j) qdd_log[((size_t)s * J + j) * N + e] = qlog[s * n + j];
+  }
+  return 0;
+}
+
+// Exact operation count of one control step of env e (physics substeps,
+// kinematics, reward, observation), and separately of the physics substeps
+// alone. counts: [add, mul, div, sqrt, trans] x 2 (step, physics).
+int ora_opcount_step(const ora_robot* r, const ora_task* t, int e, const double* action, long long* counts) {
+  const int N = r->n_env, J = r->max_dof;
+  TaskSpec ts = load_taskspec(t);
+  Chain<Counted> ch = load_chain<Counted>(r, e);
+  Drive<Counted> dr = load_drive<Counted>(r, e);
+  EnvGoal<Counted> g = load_goal<Counted>(t, N, e);
+  const int n = ch.n;
+  Counted qe[kMaxDof], qde[kMaxDof], ae[kMaxDof], oe[64], rew;
+  for (int j = 0; j < n; ++j) {
+    qe[j] = Counted(r->q0[j * N + e]);
+    qde[j] = Counted(0.0);
+    ae[j] = Counted(action[j * N + e]);
+  }
+  int prog = 0;
+  tally() = OpTally();
+  env_step(ch, dr, Counted(r->dt), r->substeps, J, ts, g, ae, qe, qde, &prog, &rew, oe, (Counted*)nullptr);
+  OpTally all = tally();
+  for (int j = 0; j < n; ++j) {
+    qe[j] = Counted(r->q0[j * N + e]);
+    qde[j] = Counted(0.0);
+  }
+  tally() = OpTally();
+  physics_step(ch, dr, Counted(r->dt), r->substeps, ae, qe, qde, (Counted*)nullptr);
+  OpTally phys = tally();
+  counts[0] = all.add; counts[1] = all.mul; counts[2] = all.div; counts[3] = all.sqrt; counts[4] = all.trans;
+  counts[5] = phys.add; counts[6] = phys.mul; counts[7] = phys.div; counts[8] = phys.sqrt; counts[9] = phys.trans;
+  return 0;
+}
+
+// ---- learning side -------------------------------------------------------
+
+void ora_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  Philox4 c = {{ctr[0], ctr[1], ctr[2], ctr[3]}};
+  Philox4 o = philox4x32_10(c, key[0], key[1]);
+  for (int i = 0; i < 4; ++i) out[i] = o.v[i];
+}
+
+// eps [n][N] for envs 0..N-1 at one step.
+void ora_noise(uint64_t seed, uint64_t step, int n, int N, double* eps) {
+  double tmp[kMaxDof];
+  for (int e = 0; e < N; ++e) {
+    gaussian_noise(seed, (uint32_t)e, step, n, tmp);
+    for (int j = 0; j < n; ++j) eps[j * N + e] = tmp[j];
+  }
+}
+
+double ora_round_bf16(double x) { return round_bf16(x); }
+
+// Policy forward on B inputs: x [n_in][B], out [n_out][B] (SoA).
+int ora_mlp_forward(const ora_policy* p, const double* x, double* out, int B, int emulate) {
+  MlpLayer L[3];
+  for (int l = 0; l < 3; ++l) L[l] = {p->dims[l], p->dims[l + 1], p->W[l], p->b[l]};
+  const int n_in = p->dims[0], n_out = p->dims[3];
+  double xe[1024], oe[1024], sa[1024], sb[1024];
+  for (int e = 0; e < B; ++e) {
+    for (int k = 0; k < n_in; ++k) xe[k] = x[k * B + e];
+    mlp_forward(L, 3, xe, oe, emulate != 0, sa, sb);
+    for (int i = 0; i < n_out; ++i) out[i * B + e] = oe[i];
+  }
+  return 0;
+}
+
+int ora_gae(int T, int N, const double* rew, const double* val_, const uint8_t* done, double gamma, double lam,
+            double* adv, double* ret) {
+  for (int e = 0; e < N; ++e) gae_env(T, N, e, rew, val_, done, gamma, lam, adv, ret);
+  return 0;
+}
+
+// Whole rollout of T steps for envs [e0, e1) (paper Sec. III: the policy acts,
+// the simulator steps, rewards are stored; then GAE). Buffers (SoA):
+// obs [T+1][W][N] with obs[0] the input observation; act [T][J][N] (the
+// sampled pre-clamp action); logp, rew [T][N]; done [T][N]; val [T+1][N];
+// adv, ret [T][N]. State q, qd, progress updated in place. Noise uses step
+// counter step0 + t.
+int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int T, uint64_t seed, uint64_t step0,
+                double gamma, double lam, int emulate, double* q, double* qd, int32_t* progress, double* obs,
+                double* act, double* logp, double* rew, uint8_t* done, double* val_, double* adv, double* ret,
+                int e0, int e1) {
+  const int N = r->n_env, J = r->max_dof, W = 2 * J + 10, S = r->substeps;
+  TaskSpec ts = load_taskspec(t);
+  MlpLayer L[3];
+  for (int l = 0; l < 3; ++l) L[l] = {p->dims[l], p->dims[l + 1], p->W[l], p->b[l]};
+  const double half_log_2pi = 0.91893853320467274178032973640562;
+  for (int e = e0; e < e1; ++e) {
+    Chain<double> ch = load_chain<double>(r, e);
+    Drive<double> dr = load_drive<double>(r, e);
+    EnvGoal<double> g = load_goal<double>(t, N, e);
+    const int n = ch.n;
+    double qe[kMaxDof], qde[kMaxDof], x[64], o[64], sa[1024], sb[1024], eps[kMaxDof], a[kMaxDof];
+    gather(q, J, N, e, n, qe);
+    gather(qd, J, N, e, n, qde);
+    int prog = progress[e];
+    for (int w = 0; w < W; ++w) x[w] = obs[(size_t)w * N + e];
+    for (int s = 0; s < T; ++s) {
+      mlp_forward(L, 3, x, o, emulate != 0, sa, sb);
+      gaussian_noise(seed, (uint32_t)e, step0 + (uint64_t)s, n, eps);
+      double lp = 0.0;
+      for (int j = 0; j < n; ++j) {
+        double sigma = std::exp(p->log_std[j]);
+        a[j] = o[j] + sigma * eps[j];
+        lp += -0.5 * eps[j] * eps[j] - p->log_std[j] - half_log_2pi;
+        act[((size_t)s * J + j) * N + e] = a[j];
+      }
+      for (int j = n; j < J; ++j) act[((size_t)s * J + j) * N + e] = 0.0;
+      val_[(size_t)s * N + e] = o[J];
+      logp[(size_t)s * N + e] = lp;
+      double rw;
+      uint8_t d = env_step(ch, dr, r->dt, S, J, ts, g, a, qe, qde, &prog, &rw, x, (double*)nullptr);
+      rew[(size_t)s * N + e] = rw;
+      done[(size_t)s * N + e] = d;
+      for (int w = 0; w < W; ++w) obs[((size_t)(s + 1) * W + w) * N + e] = x[w];
+    }
+    mlp_forward(L, 3, x, o, emulate != 0, sa, sb);
+    val_[(size_t)T * N + e] = o[J];
+    scatter(q, J, N, e, n, qe);
+    scatter(qd, J, N, e, n, qde);
+    progress[e] = prog;
+  }
+  for (int e = e0; e < e1; ++e) gae_env(T, N, e, rew, val_, done, gamma, lam, adv, ret);
+  return 0;
+}
+
+}  // extern "C"
