@@ -1,0 +1,220 @@
+/* surgym.h -- C interface of the MI355X batched serial-chain simulator.
+ *
+ * One context holds N independent environments, each a fixed-base serial
+ * chain of revolute joints driven by joint-space PD targets, on one GPU.
+ * Every call enqueues work on the context's HIP stream and returns without
+ * synchronizing; argument errors are reported synchronously.
+ *
+ * The method (paper: "Surgical Gym", Sec. III "Simulation Setup" and
+ * "Policy learning and control"): physics, observations, rewards and the
+ * policy rollout stay on the GPU and are exposed as device tensors, with a
+ * Gym-like step (Sec. IV "Environments"). The dynamics are the textbook
+ * ones of a contact-free serial chain (Featherstone 2008): RNEA bias
+ * forces, the ABA articulated-inertia sweep, implicit PD drives folded in as
+ * joint armature, semi-implicit Euler substeps, hard joint limits.
+ *
+ * Conventions shared by every call:
+ *   N = n_env, J = max_dof (stride of per-joint arrays), W = 2*J + 10
+ *   (observation width), T = rollout length.
+ *   Device arrays are structure-of-arrays, env index fastest:
+ *     per joint  [J][N]   element (j, e) at j*N + e
+ *     obs        [W][N]   rows: q (J), qd (J), tip (3), goal (3),
+ *                         goal - tip (3), |goal - tip| (1); unused joint
+ *                         rows zero
+ *   Element type "real" is float for SG_F32 contexts and double for SG_F64.
+ *   Device pointers must be 16-byte aligned and hold the stated extents;
+ *   the library never frees caller memory.
+ *
+ * Errors: every function returns sg_status. SG_E_INVAL: a null or
+ * misaligned pointer, a size out of range; the message is available from
+ * sg_last_error(ctx) (or sg_last_error(NULL) after a failed sg_create).
+ * SG_E_UNSUPPORTED: a valid request this build does not implement (e.g. a
+ * rollout on an FP64 context). SG_E_HIP: a HIP runtime error, including an
+ * asynchronous fault surfaced at the next call that synchronizes.
+ * A context is used by one host thread at a time.
+ */
+#ifndef SURGYM_H
+#define SURGYM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sg_ctx sg_ctx;
+
+typedef enum {
+  SG_OK = 0,
+  SG_E_INVAL = -1,
+  SG_E_UNSUPPORTED = -2,
+  SG_E_HIP = -3,
+  SG_E_STATE = -4,
+  SG_E_NOMEM = -5
+} sg_status;
+
+enum { SG_F32 = 0, SG_F64 = 1 };
+enum { SG_TASK_REACH = 0, SG_TASK_PATH = 1 };
+/* done flags (uint8 per env): bit 0 the episode ended (the observation
+ * returned is the reset state's), bit 1 it ended by time-out (the critic
+ * bootstraps, paper Sec. III "Policy learning and control"), bit 2 the
+ * state went non-finite and was reset (reward 0). */
+enum { SG_DONE_ENDED = 1, SG_DONE_TIMEOUT = 2, SG_DONE_NONFINITE = 4 };
+/* armature for sg_forward_dynamics: none, or the implicit-PD drive's
+ * h*kd + h^2*kp with h = dt / substeps. */
+enum { SG_ARM_NONE = 0, SG_ARM_DRIVE = 1 };
+
+#define SG_MAX_DOF 16
+#define SG_MAX_WAYPOINTS 32
+
+/* Robot description. All arrays are HOST memory, float64, copied at
+ * sg_create (values are rounded to the context's dtype there).
+ * Chain geometry: joint j's origin is at offset_j in link j-1's frame (the
+ * base frame for j = 0); link j's frame is that origin rotated by q_j about
+ * the unit axis_j. Joints j >= n_dof[e] of env e are ignored; outputs hold 0 there. */
+typedef struct {
+  int32_t n_env;          /* N >= 1 */
+  int32_t max_dof;        /* J, 1..SG_MAX_DOF */
+  const int32_t* n_dof;   /* [N], 1..J */
+  int32_t dtype;          /* SG_F32 or SG_F64 */
+  const double* axis;     /* [3][J][N] unit joint axis */
+  const double* offset;   /* [3][J][N] joint origin in the parent frame (m) */
+  const double* com;      /* [3][J][N] link centre of mass, link frame (m) */
+  const double* mass;     /* [J][N] > 0 (kg) */
+  const double* inertia;  /* [6][J][N] xx yy zz xy xz yz about the COM, link axes */
+  const double* kp;       /* [J][N] PD stiffness (N m / rad), >= 0 */
+  const double* kd;       /* [J][N] PD damping (N m s / rad), >= 0 */
+  const double* q_lo;     /* [J][N] lower joint limit (rad) */
+  const double* q_hi;     /* [J][N] upper joint limit, > q_lo */
+  const double* q0;       /* [J][N] reset position */
+  const double* tip;      /* [3][N] tool tip in the last link's frame */
+  double dt;              /* control period (s) > 0 */
+  int32_t substeps;       /* S >= 1, substep h = dt / S */
+  double gravity[3];      /* base-frame gravity (m/s^2) */
+} sg_robot_desc;
+
+/* Task description (paper Sec. IV): target reaching, reward -|tip - g|, or
+ * path following, reward -|tip - P(t)| with P(t) the waypoint
+ * min(K-1, progress / dwell). Host memory, float64, copied at create. */
+typedef struct {
+  int32_t task;             /* SG_TASK_REACH or SG_TASK_PATH */
+  int32_t n_waypoints;      /* K (path), 1..SG_MAX_WAYPOINTS */
+  int32_t dwell;            /* control steps per waypoint (path), >= 1 */
+  int32_t ep_len;           /* episode length in steps; <= 0: no time-out */
+  const double* target;     /* [3][N] (reach) */
+  const double* waypoints;  /* [K][3][N] (path) */
+  const int32_t* progress0; /* [N] initial episode progress, may be NULL (0) */
+  uint64_t seed;            /* exploration-noise key */
+} sg_task_desc;
+
+/* Rollout storage, all DEVICE memory, float32 unless noted:
+ *   obs [T+1][W][N]  obs[0] = observation before the first step
+ *   act [T][J][N]    sampled (pre-clamp) actions
+ *   logp, rew [T][N] log-density of act under the policy, reward
+ *   done [T][N]      uint8 flags as above
+ *   val [T+1][N]     critic value of obs[t]
+ *   adv, ret [T][N]  GAE advantage and return */
+typedef struct {
+  float* obs;
+  float* act;
+  float* logp;
+  float* rew;
+  uint8_t* done;
+  float* val;
+  float* adv;
+  float* ret;
+  float gamma; /* discount, paper Sec. III (GAE) */
+  float lam;   /* GAE lambda */
+} sg_rollout_bufs;
+
+/* Library version string. */
+const char* sg_version(void);
+
+/* Message of the last error on ctx (NULL: the calling thread's last
+ * sg_create error). Never NULL. */
+const char* sg_last_error(const sg_ctx* ctx);
+
+/* Create N environments on the current HIP device. Copies the
+ * descriptions, uploads them, and sets the state to (q0, 0, progress0),
+ * noise step counter 0. *out receives the context. */
+sg_status sg_create(const sg_robot_desc* robot, const sg_task_desc* task, sg_ctx** out);
+
+/* Free the context and its device memory (after draining its stream). */
+void sg_destroy(sg_ctx* ctx);
+
+/* Bind the HIP stream (hipStream_t passed as void*; NULL = default). */
+sg_status sg_set_stream(sg_ctx* ctx, void* hip_stream);
+
+/* Wait for the context's stream; reports asynchronous HIP errors. */
+sg_status sg_synchronize(sg_ctx* ctx);
+
+/* Reset every env to (q0, 0, progress0) and the noise counter to 0. */
+sg_status sg_reset(sg_ctx* ctx);
+
+/* One control step of every env (paper Sec. III: actions are PD position
+ * targets, the solver advances in substeps; Sec. IV rewards):
+ *   q* = mid + half_range * clamp(a, -1, 1) over the joint limits, held over
+ *   S substeps of tau = kp (q* - q - h qd) - kd qd with armature
+ *   h kd + h^2 kp, forward dynamics, qd += h qdd, q += h qd, hard limits;
+ *   then tip position, reward, progress, time-out / non-finite reset, and
+ *   the observation of the post-reset state.
+ * actions [J][N] real (device), obs [W][N] real, reward [N] real,
+ * done [N] uint8 (device). obs, reward, done may not alias actions. */
+sg_status sg_step(sg_ctx* ctx, const void* actions, void* obs, void* reward, uint8_t* done);
+
+/* Observation of the current state, obs [W][N] real (device). */
+sg_status sg_observe(sg_ctx* ctx, void* obs);
+
+/* Copy state out / in. q, qd [J][N] real and progress [N] int32 are device
+ * pointers (any may be NULL to skip); rng_step is host memory. */
+sg_status sg_get_state(sg_ctx* ctx, void* q, void* qd, int32_t* progress, uint64_t* rng_step);
+sg_status sg_set_state(sg_ctx* ctx, const void* q, const void* qd, const int32_t* progress, uint64_t rng_step);
+
+/* Forward dynamics (ABA, Featherstone Table 7.1) for the given state:
+ * qdd = (H(q) + diag(arm))^-1 (tau - C(q, qd)) with arm per arm_mode.
+ * q, qd, tau, qdd [J][N] real (device). */
+sg_status sg_forward_dynamics(sg_ctx* ctx, const void* q, const void* qd, const void* tau, int32_t arm_mode,
+                              void* qdd);
+
+/* Inverse dynamics (RNEA, Featherstone Table 5.1): tau = H qdd + C.
+ * q, qd, qdd, tau [J][N] real (device). */
+sg_status sg_inverse_dynamics(sg_ctx* ctx, const void* q, const void* qd, const void* qdd, void* tau);
+
+/* Tool-tip position (forward kinematics) tip [3][N] real for q [J][N]. */
+sg_status sg_tip_position(sg_ctx* ctx, const void* q, void* tip);
+
+/* Policy of the rollout: MLP W -> h1 -> h2 -> J+1 with tanh hidden units;
+ * outputs 0..J-1 are the action mean, output J the critic value.
+ * w_bf16: HOST, BF16 bit patterns of W1 [h1][W], W2 [h2][h1], W3 [J+1][h2]
+ * concatenated row-major; bias: HOST float32 b1 [h1], b2 [h2], b3 [J+1];
+ * log_std: HOST float32 [J]. This build supports h1 = 256, h2 = 128, J <= 7
+ * (SG_E_UNSUPPORTED otherwise); FP32 contexts only. */
+sg_status sg_set_policy(sg_ctx* ctx, int32_t h1, int32_t h2, const uint16_t* w_bf16, const float* bias,
+                        const float* log_std);
+
+/* The policy network alone on n inputs: x [W][n] float32 (device),
+ * out [J+1][n] float32 (device). BF16 matrix-core products with FP32
+ * accumulation; each layer's input is rounded to BF16 (nearest, ties even). */
+sg_status sg_policy_forward(sg_ctx* ctx, const float* x, int32_t n, float* out);
+
+/* T-step rollout (paper Sec. III "Policy learning and control"): for each
+ * step the policy gives mean mu and value V of the current observation;
+ * the action a = mu + exp(log_std) * eps with eps standard normal from
+ * Philox4x32-10 keyed by the seed, counter (env, step lo, step hi, joint
+ * block) and Box-Muller; the env steps on clamp(a); after T steps V of the
+ * last observation, then GAE with the time-out bootstrap
+ * r += gamma * V(s_t) on time-outs. The noise step counter advances by T.
+ * FP32 contexts with a policy set. 1 <= T <= 4096. */
+sg_status sg_rollout(sg_ctx* ctx, int32_t T, const sg_rollout_bufs* bufs);
+
+/* GAE backward scan alone (Schulman et al., cited in paper Sec. III) on
+ * device float32 rew [T][N], val [T+1][N], uint8 done [T][N] ->
+ * adv, ret [T][N]; n = number of envs (columns). */
+sg_status sg_gae(sg_ctx* ctx, int32_t T, int32_t n, const float* rew, const float* val, const uint8_t* done,
+                 float gamma, float lam, float* adv, float* ret);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SURGYM_H */

@@ -173,7 +173,8 @@ class Oracle:
         lib().ora_mlp_forward(C.byref(self.p), _ptr(_f64(x)), _ptr(out), C.c_int(B), C.c_int(int(emulate)))
         return out
 
-    def rollout(self, T, seed, step0, q, qd, progress, obs0, gamma=0.99, lam=0.95, emulate=True, envs=None):
+    def rollout(self, T, seed, step0, q, qd, progress, obs0, gamma=0.99, lam=0.95, emulate=True, envs=None,
+                threads=1):
         N, J, W = self.N, self.J, self.W
         q = _f64(q).copy()
         qd = _f64(qd).copy()
@@ -191,7 +192,7 @@ class Oracle:
         lib().ora_rollout(C.byref(self.r), C.byref(self.t), C.byref(self.p), C.c_int(T), C.c_uint64(seed),
                           C.c_uint64(step0), C.c_double(gamma), C.c_double(lam), C.c_int(int(emulate)), _ptr(q),
                           _ptr(qd), _ptr(pr, _ip), _ptr(obs), _ptr(act), _ptr(logp), _ptr(rew), _ptr(done, _u8p),
-                          _ptr(val), _ptr(adv), _ptr(ret), C.c_int(e0), C.c_int(e1))
+                          _ptr(val), _ptr(adv), _ptr(ret), C.c_int(e0), C.c_int(e1), C.c_int(threads))
         return dict(q=q, qd=qd, progress=pr, obs=obs, act=act, logp=logp, rew=rew, done=done, val=val, adv=adv,
                     ret=ret)
 

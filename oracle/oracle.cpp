@@ -379,12 +379,16 @@ int ora_gae(int T, int N, const double* rew, const double* val_, const uint8_t* 
 int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int T, uint64_t seed, uint64_t step0,
                 double gamma, double lam, int emulate, double* q, double* qd, int32_t* progress, double* obs,
                 double* act, double* logp, double* rew, uint8_t* done, double* val_, double* adv, double* ret,
-                int e0, int e1) {
+                int e0, int e1, int n_threads) {
   const int N = r->n_env, J = r->max_dof, W = 2 * J + 10, S = r->substeps;
   TaskSpec ts = load_taskspec(t);
   MlpLayer L[3];
   for (int l = 0; l < 3; ++l) L[l] = {p->dims[l], p->dims[l + 1], p->W[l], p->b[l]};
   const double half_log_2pi = 0.91893853320467274178032973640562;
+  (void)n_threads;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4) num_threads(n_threads > 0 ? n_threads : 1)
+#endif
   for (int e = e0; e < e1; ++e) {
     Chain<double> ch = load_chain<double>(r, e);
     Drive<double> dr = load_drive<double>(r, e);

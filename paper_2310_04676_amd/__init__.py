@@ -1,0 +1,249 @@
+"""Python binding of the MI355X serial-chain simulator (``libsurgym.so``).
+
+Argument marshalling only: every step of the method runs in the HIP
+kernels behind the C interface declared in ``include/surgym.h``. PyTorch
+provides device memory (tensors) and the current HIP stream. There is no
+CPU fallback: importing this package raises if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsurgym.so")
+
+SG_OK, SG_E_INVAL, SG_E_UNSUPPORTED, SG_E_HIP, SG_E_STATE, SG_E_NOMEM = 0, -1, -2, -3, -4, -5
+SG_F32, SG_F64 = 0, 1
+SG_TASK_REACH, SG_TASK_PATH = 0, 1
+SG_ARM_NONE, SG_ARM_DRIVE = 0, 1
+DONE_ENDED, DONE_TIMEOUT, DONE_NONFINITE = 1, 2, 4
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_vp = C.c_void_p
+
+
+class RobotDesc(C.Structure):
+    _fields_ = [("n_env", C.c_int32), ("max_dof", C.c_int32), ("n_dof", _ip), ("dtype", C.c_int32),
+                ("axis", _dp), ("offset", _dp), ("com", _dp), ("mass", _dp), ("inertia", _dp), ("kp", _dp),
+                ("kd", _dp), ("q_lo", _dp), ("q_hi", _dp), ("q0", _dp), ("tip", _dp), ("dt", C.c_double),
+                ("substeps", C.c_int32), ("gravity", C.c_double * 3)]
+
+
+class TaskDesc(C.Structure):
+    _fields_ = [("task", C.c_int32), ("n_waypoints", C.c_int32), ("dwell", C.c_int32), ("ep_len", C.c_int32),
+                ("target", _dp), ("waypoints", _dp), ("progress0", _ip), ("seed", C.c_uint64)]
+
+
+class RolloutBufs(C.Structure):
+    _fields_ = [("obs", _vp), ("act", _vp), ("logp", _vp), ("rew", _vp), ("done", _vp), ("val", _vp),
+                ("adv", _vp), ("ret", _vp), ("gamma", C.c_float), ("lam", C.c_float)]
+
+
+lib = C.CDLL(LIB_PATH)
+lib.sg_version.restype = C.c_char_p
+lib.sg_last_error.restype = C.c_char_p
+lib.sg_last_error.argtypes = [_vp]
+lib.sg_create.argtypes = [C.POINTER(RobotDesc), C.POINTER(TaskDesc), C.POINTER(_vp)]
+lib.sg_destroy.argtypes = [_vp]
+lib.sg_destroy.restype = None
+lib.sg_set_stream.argtypes = [_vp, _vp]
+lib.sg_synchronize.argtypes = [_vp]
+lib.sg_reset.argtypes = [_vp]
+lib.sg_step.argtypes = [_vp, _vp, _vp, _vp, _vp]
+lib.sg_observe.argtypes = [_vp, _vp]
+lib.sg_get_state.argtypes = [_vp, _vp, _vp, _vp, C.POINTER(C.c_uint64)]
+lib.sg_set_state.argtypes = [_vp, _vp, _vp, _vp, C.c_uint64]
+lib.sg_forward_dynamics.argtypes = [_vp, _vp, _vp, _vp, C.c_int32, _vp]
+lib.sg_inverse_dynamics.argtypes = [_vp, _vp, _vp, _vp, _vp]
+lib.sg_tip_position.argtypes = [_vp, _vp, _vp]
+lib.sg_set_policy.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp]
+lib.sg_policy_forward.argtypes = [_vp, _vp, C.c_int32, _vp]
+lib.sg_rollout.argtypes = [_vp, C.c_int32, C.POINTER(RolloutBufs)]
+lib.sg_gae.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_float, C.c_float, _vp, _vp]
+
+
+class SgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+def version() -> str:
+    return lib.sg_version().decode()
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, t=_dp):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _dptr(t):
+    """Device pointer of a contiguous torch tensor (None passes through)."""
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return t.data_ptr()
+
+
+def make_descs(robot, task, dtype, seed=0):
+    """ctypes descriptions (and the arrays they point at) from numpy arrays."""
+    keep = []
+    arrs = {}
+    for name in ("axis", "offset", "com", "mass", "inertia", "kp", "kd", "q_lo", "q_hi", "q0", "tip"):
+        arrs[name] = _f64(getattr(robot, name))
+        keep.append(arrs[name])
+    nd = np.ascontiguousarray(robot.n_dof, dtype=np.int32)
+    keep.append(nd)
+    rd = RobotDesc(robot.n_env, robot.max_dof, _ptr(nd, _ip), dtype,
+                   *[_ptr(arrs[n]) for n in ("axis", "offset", "com", "mass", "inertia", "kp", "kd", "q_lo",
+                                             "q_hi", "q0", "tip")],
+                   float(robot.dt), int(robot.substeps), (C.c_double * 3)(*robot.gravity))
+    tgt = None if task.target is None else _f64(task.target)
+    wps = None if task.waypoints is None else _f64(task.waypoints)
+    p0 = None if task.progress0 is None else np.ascontiguousarray(task.progress0, dtype=np.int32)
+    keep.extend([tgt, wps, p0])
+    td = TaskDesc(task.task, task.n_waypoints, task.dwell, task.ep_len, _ptr(tgt), _ptr(wps), _ptr(p0, _ip),
+                  seed & 0xFFFFFFFFFFFFFFFF)
+    return rd, td, keep
+
+
+class Sim:
+    """N environments on the current GPU (one ``sg_ctx``)."""
+
+    def __init__(self, robot, task, dtype=np.float32, seed=0, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.N, self.J = robot.n_env, robot.max_dof
+        self.W = 2 * self.J + 10
+        self.tdtype = torch.float64 if dtype == np.float64 else torch.float32
+        sgd = SG_F64 if dtype == np.float64 else SG_F32
+        rd, td, keep = make_descs(robot, task, sgd, seed)
+        ctx = _vp()
+        with torch.cuda.device(self.device):
+            st = lib.sg_create(C.byref(rd), C.byref(td), C.byref(ctx))
+        if st != SG_OK:
+            raise SgError(st, lib.sg_last_error(None).decode())
+        self.ctx = ctx
+        self.policy_dims = None
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib.sg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- plumbing ------------------------------------------------------------
+    def _call(self, fn, *args):
+        lib.sg_set_stream(self.ctx, self.torch.cuda.current_stream(self.device).cuda_stream)
+        st = fn(self.ctx, *args)
+        if st != SG_OK:
+            raise SgError(st, lib.sg_last_error(self.ctx).decode())
+
+    def _empty(self, *shape, dtype=None):
+        return self.torch.empty(*shape, dtype=dtype or self.tdtype, device=self.device)
+
+    def synchronize(self):
+        self._call(lib.sg_synchronize)
+
+    # -- environment ---------------------------------------------------------
+    def reset(self):
+        self._call(lib.sg_reset)
+
+    def step(self, actions, obs=None, reward=None, done=None):
+        """actions [J][N] -> (obs [W][N], reward [N], done [N] uint8)."""
+        obs = self._empty(self.W, self.N) if obs is None else obs
+        reward = self._empty(self.N) if reward is None else reward
+        done = self._empty(self.N, dtype=self.torch.uint8) if done is None else done
+        self._call(lib.sg_step, _dptr(actions), _dptr(obs), _dptr(reward), _dptr(done))
+        return obs, reward, done
+
+    def observe(self, obs=None):
+        obs = self._empty(self.W, self.N) if obs is None else obs
+        self._call(lib.sg_observe, _dptr(obs))
+        return obs
+
+    def get_state(self):
+        q = self._empty(self.J, self.N)
+        qd = self._empty(self.J, self.N)
+        pr = self._empty(self.N, dtype=self.torch.int32)
+        rs = C.c_uint64()
+        self._call(lib.sg_get_state, _dptr(q), _dptr(qd), _dptr(pr), C.byref(rs))
+        return q, qd, pr, rs.value
+
+    def set_state(self, q=None, qd=None, progress=None, rng_step=0):
+        self._call(lib.sg_set_state, _dptr(q), _dptr(qd), _dptr(progress), C.c_uint64(rng_step))
+
+    def forward_dynamics(self, q, qd, tau, arm_mode=SG_ARM_DRIVE, out=None):
+        out = self._empty(self.J, self.N) if out is None else out
+        self._call(lib.sg_forward_dynamics, _dptr(q), _dptr(qd), _dptr(tau), C.c_int32(arm_mode), _dptr(out))
+        return out
+
+    def inverse_dynamics(self, q, qd, qdd, out=None):
+        out = self._empty(self.J, self.N) if out is None else out
+        self._call(lib.sg_inverse_dynamics, _dptr(q), _dptr(qd), _dptr(qdd), _dptr(out))
+        return out
+
+    def tip_position(self, q, out=None):
+        out = self._empty(3, self.N) if out is None else out
+        self._call(lib.sg_tip_position, _dptr(q), _dptr(out))
+        return out
+
+    # -- learning side ----------------------------------------------------------
+    def set_policy(self, policy):
+        w = np.ascontiguousarray(policy.w_bf16_bits())
+        b = np.ascontiguousarray(policy.b_f32())
+        ls = np.ascontiguousarray(policy.log_std.astype(np.float32))
+        self._call(lib.sg_set_policy, C.c_int32(policy.dims[1]), C.c_int32(policy.dims[2]),
+                   w.ctypes.data_as(_vp), b.ctypes.data_as(_vp), ls.ctypes.data_as(_vp))
+        self.policy_dims = tuple(policy.dims)
+
+    def policy_forward(self, x, out=None):
+        n = x.shape[1]
+        out = self._empty(self.J + 1, n, dtype=self.torch.float32) if out is None else out
+        self._call(lib.sg_policy_forward, _dptr(x), C.c_int32(n), _dptr(out))
+        return out
+
+    def rollout_buffers(self, T):
+        t, f = self.torch, self.torch.float32
+        return dict(obs=self._empty(T + 1, self.W, self.N, dtype=f), act=self._empty(T, self.J, self.N, dtype=f),
+                    logp=self._empty(T, self.N, dtype=f), rew=self._empty(T, self.N, dtype=f),
+                    done=self._empty(T, self.N, dtype=t.uint8), val=self._empty(T + 1, self.N, dtype=f),
+                    adv=self._empty(T, self.N, dtype=f), ret=self._empty(T, self.N, dtype=f))
+
+    def rollout(self, T, bufs=None, gamma=0.99, lam=0.95):
+        bufs = self.rollout_buffers(T) if bufs is None else bufs
+        rb = RolloutBufs(*[_dptr(bufs[k]) for k in ("obs", "act", "logp", "rew", "done", "val", "adv", "ret")],
+                         gamma, lam)
+        self._call(lib.sg_rollout, C.c_int32(T), C.byref(rb))
+        return bufs
+
+    def gae(self, rew, val, done, gamma=0.99, lam=0.95):
+        T, n = rew.shape
+        adv = self._empty(T, n, dtype=self.torch.float32)
+        ret = self._empty(T, n, dtype=self.torch.float32)
+        self._call(lib.sg_gae, C.c_int32(T), C.c_int32(n), _dptr(rew), _dptr(val), _dptr(done), C.c_float(gamma),
+                   C.c_float(lam), _dptr(adv), _dptr(ret))
+        return adv, ret
+
+
+def from_workload(w, device=None) -> Sim:
+    sim = Sim(w.robot, w.task, dtype=w.dtype, seed=w.seed, device=device)
+    if w.policy is not None and w.dtype == np.float32 and w.robot.max_dof <= 7:
+        sim.set_policy(w.policy)
+    return sim

@@ -1,0 +1,336 @@
+// C interface: argument checking, context setup (host-side conversion of the
+// robot description to the device parameter block), and dispatch.
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "mlp.hpp"
+
+namespace {
+
+thread_local std::string g_create_err;
+
+sg_status fail(sg_ctx* c, sg_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_err = msg;
+  return s;
+}
+
+sg_status hip_fail(sg_ctx* c, hipError_t e, const char* where) {
+  return fail(c, SG_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool aligned(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+template <typename T> hipError_t upload(void** dst, const std::vector<double>& src) {
+  std::vector<T> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = (T)src[i];
+  hipError_t e = hipMalloc(dst, tmp.size() * sizeof(T) + 16);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void free_ctx(sg_ctx* c) {
+  void* ptrs[] = {c->par, c->tip, c->nd, c->target, c->wp, c->prog0, c->q, c->qd, c->prog, c->w_bf16, c->bias,
+                  c->log_std};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sg_version(void) { return "surgym-mi355x 0.1 (gfx950)"; }
+
+const char* sg_last_error(const sg_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out) {
+  g_create_err.clear();
+  if (!r || !t || !out) return fail(nullptr, SG_E_INVAL, "sg_create: null argument");
+  *out = nullptr;
+  const int N = r->n_env, J = r->max_dof;
+  if (N < 1) return fail(nullptr, SG_E_INVAL, "sg_create: n_env must be >= 1");
+  if (J < 1 || J > SG_MAX_DOF) return fail(nullptr, SG_E_UNSUPPORTED, "sg_create: max_dof must be in 1..16");
+  if (r->dtype != SG_F32 && r->dtype != SG_F64) return fail(nullptr, SG_E_INVAL, "sg_create: bad dtype");
+  if (!r->n_dof || !r->axis || !r->offset || !r->com || !r->mass || !r->inertia || !r->kp || !r->kd || !r->q_lo ||
+      !r->q_hi || !r->q0 || !r->tip)
+    return fail(nullptr, SG_E_INVAL, "sg_create: null robot array");
+  if (!(r->dt > 0) || r->substeps < 1) return fail(nullptr, SG_E_INVAL, "sg_create: dt must be > 0, substeps >= 1");
+  if (t->task != SG_TASK_REACH && t->task != SG_TASK_PATH) return fail(nullptr, SG_E_INVAL, "sg_create: bad task");
+  if (t->task == SG_TASK_REACH && !t->target) return fail(nullptr, SG_E_INVAL, "sg_create: reach task needs target");
+  if (t->task == SG_TASK_PATH &&
+      (!t->waypoints || t->n_waypoints < 1 || t->n_waypoints > SG_MAX_WAYPOINTS || t->dwell < 1))
+    return fail(nullptr, SG_E_INVAL, "sg_create: path task needs 1..32 waypoints and dwell >= 1");
+  const size_t JN = (size_t)J * N;
+  for (int e = 0; e < N; ++e) {
+    const int n = r->n_dof[e];
+    if (n < 1 || n > J) return fail(nullptr, SG_E_INVAL, "sg_create: n_dof out of 1..max_dof");
+    for (int j = 0; j < n; ++j) {
+      const size_t i = (size_t)j * N + e;
+      const double ax = r->axis[i], ay = r->axis[JN + i], az = r->axis[2 * JN + i];
+      if (std::fabs(ax * ax + ay * ay + az * az - 1.0) > 1e-6)
+        return fail(nullptr, SG_E_INVAL, "sg_create: joint axis not unit length");
+      if (!(r->mass[i] > 0)) return fail(nullptr, SG_E_INVAL, "sg_create: link mass must be > 0");
+      if (!(r->q_hi[i] > r->q_lo[i])) return fail(nullptr, SG_E_INVAL, "sg_create: q_hi must exceed q_lo");
+      if (r->kp[i] < 0 || r->kd[i] < 0) return fail(nullptr, SG_E_INVAL, "sg_create: gains must be >= 0");
+    }
+  }
+  sg_ctx* c = new sg_ctx();
+  hipError_t he = hipGetDevice(&c->device);
+  if (he != hipSuccess) {
+    delete c;
+    return hip_fail(nullptr, he, "hipGetDevice");
+  }
+  c->N = N; c->J = J; c->dtype = r->dtype; c->S = r->substeps; c->dt = r->dt;
+  for (int k = 0; k < 3; ++k) c->g[k] = r->gravity[k];
+  c->task = t->task; c->K = t->task == SG_TASK_PATH ? t->n_waypoints : 1;
+  c->dwell = t->dwell > 0 ? t->dwell : 1; c->ep_len = t->ep_len; c->seed = t->seed; c->rng_step = 0;
+
+  // Device parameter block [P_NFIELDS][J][N]; padded joints stay zero.
+  std::vector<double> par((size_t)sgk::P_NFIELDS * JN, 0.0);
+  auto P = [&](int f, size_t i) -> double& { return par[(size_t)f * JN + i]; };
+  for (int e = 0; e < N; ++e) {
+    for (int j = 0; j < r->n_dof[e]; ++j) {
+      const size_t i = (size_t)j * N + e;
+      const double m = r->mass[i];
+      const double cx = r->com[i], cy = r->com[JN + i], cz = r->com[2 * JN + i];
+      const double* I = r->inertia;
+      const double c2 = cx * cx + cy * cy + cz * cz;
+      P(sgk::P_AX, i) = r->axis[i]; P(sgk::P_AY, i) = r->axis[JN + i]; P(sgk::P_AZ, i) = r->axis[2 * JN + i];
+      P(sgk::P_OX, i) = r->offset[i]; P(sgk::P_OY, i) = r->offset[JN + i]; P(sgk::P_OZ, i) = r->offset[2 * JN + i];
+      P(sgk::P_M, i) = m;
+      P(sgk::P_HX, i) = m * cx; P(sgk::P_HY, i) = m * cy; P(sgk::P_HZ, i) = m * cz;
+      // rotational inertia about the link origin: I_c + m (|c|^2 1 - c c^T)
+      P(sgk::P_IXX, i) = I[i] + m * (c2 - cx * cx);
+      P(sgk::P_IYY, i) = I[JN + i] + m * (c2 - cy * cy);
+      P(sgk::P_IZZ, i) = I[2 * JN + i] + m * (c2 - cz * cz);
+      P(sgk::P_IXY, i) = I[3 * JN + i] - m * cx * cy;
+      P(sgk::P_IXZ, i) = I[4 * JN + i] - m * cx * cz;
+      P(sgk::P_IYZ, i) = I[5 * JN + i] - m * cy * cz;
+      P(sgk::P_KP, i) = r->kp[i]; P(sgk::P_KD, i) = r->kd[i];
+      P(sgk::P_LO, i) = r->q_lo[i]; P(sgk::P_HI, i) = r->q_hi[i];
+      P(sgk::P_Q0, i) = r->q0[i];
+    }
+  }
+  std::vector<double> tip(r->tip, r->tip + 3 * (size_t)N);
+  std::vector<double> tgt(3 * (size_t)N, 0.0), wps;
+  if (t->target) tgt.assign(t->target, t->target + 3 * (size_t)N);
+  if (t->task == SG_TASK_PATH) wps.assign(t->waypoints, t->waypoints + (size_t)c->K * 3 * N);
+  else wps.assign(3 * (size_t)N, 0.0);
+  std::vector<double> zeros(JN, 0.0);
+  std::vector<int> nd(r->n_dof, r->n_dof + N), prog0(N, 0);
+  if (t->progress0) prog0.assign(t->progress0, t->progress0 + N);
+
+  auto up = [&](void** d, const std::vector<double>& v) {
+    return c->dtype == SG_F64 ? upload<double>(d, v) : upload<float>(d, v);
+  };
+  hipError_t e = hipSuccess;
+  const size_t esz = c->dtype == SG_F64 ? sizeof(double) : sizeof(float);
+  if (e == hipSuccess) e = up(&c->par, par);
+  if (e == hipSuccess) e = up(&c->tip, tip);
+  if (e == hipSuccess) e = up(&c->target, tgt);
+  if (e == hipSuccess) e = up(&c->wp, wps);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->nd, N * sizeof(int));
+  if (e == hipSuccess) e = hipMemcpy(c->nd, nd.data(), N * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->prog0, N * sizeof(int));
+  if (e == hipSuccess) e = hipMemcpy(c->prog0, prog0.data(), N * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->prog, N * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&c->q, JN * esz);
+  if (e == hipSuccess) e = hipMalloc(&c->qd, JN * esz);
+  if (e == hipSuccess) e = hipMemset(c->q, 0, JN * esz);
+  if (e == hipSuccess) e = hipMemset(c->qd, 0, JN * esz);
+  if (e == hipSuccess) e = sgk::launch_reset(c);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    free_ctx(c);
+    delete c;
+    return hip_fail(nullptr, e, "sg_create");
+  }
+  *out = c;
+  return SG_OK;
+}
+
+void sg_destroy(sg_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_ctx(c);
+  delete c;
+}
+
+sg_status sg_set_stream(sg_ctx* c, void* s) {
+  if (!c) return SG_E_INVAL;
+  c->stream = (hipStream_t)s;
+  return SG_OK;
+}
+
+sg_status sg_synchronize(sg_ctx* c) {
+  if (!c) return SG_E_INVAL;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_synchronize");
+}
+
+sg_status sg_reset(sg_ctx* c) {
+  if (!c) return SG_E_INVAL;
+  c->rng_step = 0;
+  hipError_t e = sgk::launch_reset(c);
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_reset");
+}
+
+sg_status sg_step(sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done) {
+  if (!c) return SG_E_INVAL;
+  if (!act || !obs || !rew || !done) return fail(c, SG_E_INVAL, "sg_step: null buffer");
+  if (!aligned(act) || !aligned(obs) || !aligned(rew)) return fail(c, SG_E_INVAL, "sg_step: misaligned buffer");
+  if (act == obs || act == rew) return fail(c, SG_E_INVAL, "sg_step: outputs alias actions");
+  hipError_t e = sgk::launch_step(c, act, obs, rew, done);
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_step");
+}
+
+sg_status sg_observe(sg_ctx* c, void* obs) {
+  if (!c) return SG_E_INVAL;
+  if (!obs || !aligned(obs)) return fail(c, SG_E_INVAL, "sg_observe: null or misaligned buffer");
+  hipError_t e = sgk::launch_observe(c, obs);
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_observe");
+}
+
+sg_status sg_get_state(sg_ctx* c, void* q, void* qd, int32_t* progress, uint64_t* rng_step) {
+  if (!c) return SG_E_INVAL;
+  const size_t esz = c->dtype == SG_F64 ? sizeof(double) : sizeof(float);
+  const size_t JN = (size_t)c->J * c->N;
+  hipError_t e = hipSuccess;
+  if (q && e == hipSuccess) e = hipMemcpyAsync(q, c->q, JN * esz, hipMemcpyDeviceToDevice, c->stream);
+  if (qd && e == hipSuccess) e = hipMemcpyAsync(qd, c->qd, JN * esz, hipMemcpyDeviceToDevice, c->stream);
+  if (progress && e == hipSuccess)
+    e = hipMemcpyAsync(progress, c->prog, c->N * sizeof(int), hipMemcpyDeviceToDevice, c->stream);
+  if (rng_step) *rng_step = c->rng_step;
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_get_state");
+}
+
+sg_status sg_set_state(sg_ctx* c, const void* q, const void* qd, const int32_t* progress, uint64_t rng_step) {
+  if (!c) return SG_E_INVAL;
+  const size_t esz = c->dtype == SG_F64 ? sizeof(double) : sizeof(float);
+  const size_t JN = (size_t)c->J * c->N;
+  hipError_t e = hipSuccess;
+  if (q && e == hipSuccess) e = hipMemcpyAsync(c->q, q, JN * esz, hipMemcpyDeviceToDevice, c->stream);
+  if (qd && e == hipSuccess) e = hipMemcpyAsync(c->qd, qd, JN * esz, hipMemcpyDeviceToDevice, c->stream);
+  if (progress && e == hipSuccess)
+    e = hipMemcpyAsync(c->prog, progress, c->N * sizeof(int), hipMemcpyDeviceToDevice, c->stream);
+  c->rng_step = rng_step;
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_set_state");
+}
+
+sg_status sg_forward_dynamics(sg_ctx* c, const void* q, const void* qd, const void* tau, int32_t arm_mode, void* qdd) {
+  if (!c) return SG_E_INVAL;
+  if (!q || !qd || !tau || !qdd) return fail(c, SG_E_INVAL, "sg_forward_dynamics: null buffer");
+  if (arm_mode != SG_ARM_NONE && arm_mode != SG_ARM_DRIVE) return fail(c, SG_E_INVAL, "sg_forward_dynamics: bad arm_mode");
+  hipError_t e = sgk::launch_fd(c, q, qd, tau, arm_mode, qdd);
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_forward_dynamics");
+}
+
+sg_status sg_inverse_dynamics(sg_ctx* c, const void* q, const void* qd, const void* qdd, void* tau) {
+  if (!c) return SG_E_INVAL;
+  if (!q || !qd || !qdd || !tau) return fail(c, SG_E_INVAL, "sg_inverse_dynamics: null buffer");
+  hipError_t e = sgk::launch_id(c, q, qd, qdd, tau);
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_inverse_dynamics");
+}
+
+sg_status sg_tip_position(sg_ctx* c, const void* q, void* tip) {
+  if (!c) return SG_E_INVAL;
+  if (!q || !tip) return fail(c, SG_E_INVAL, "sg_tip_position: null buffer");
+  hipError_t e = sgk::launch_tip(c, q, tip);
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_tip_position");
+}
+
+sg_status sg_set_policy(sg_ctx* c, int32_t h1, int32_t h2, const uint16_t* w, const float* b, const float* log_std) {
+  if (!c) return SG_E_INVAL;
+  if (!w || !b || !log_std) return fail(c, SG_E_INVAL, "sg_set_policy: null argument");
+  if (c->dtype != SG_F32) return fail(c, SG_E_UNSUPPORTED, "sg_set_policy: FP32 contexts only");
+  if (h1 != 256 || h2 != 128 || c->J > 7)
+    return fail(c, SG_E_UNSUPPORTED, "sg_set_policy: this build supports h1 = 256, h2 = 128, max_dof <= 7");
+  const int W = 2 * c->J + 10, O = c->J + 1;
+  const uint16_t* W1 = w;
+  const uint16_t* W2 = W1 + (size_t)h1 * W;
+  const uint16_t* W3 = W2 + (size_t)h2 * h1;
+  // Weight image in MFMA fragment order (see mlp.hpp): fragment f, lane
+  // l = 16 g + i, slot s. Layer 1: row 16m + i, input 8g + s. Layers 2 and 3
+  // (K-block kb): input 32 kb + 4 g + s for s < 4, 32 kb + 16 + 4 g + s - 4
+  // otherwise -- the order in which the previous layer's results sit in the
+  // lanes.
+  std::vector<uint16_t> img((size_t)sgk::kWFrags * 8, 0);
+  auto kperm = [](int kb, int g, int s) { return 32 * kb + (s < 4 ? 4 * g + s : 16 + 4 * g + (s - 4)); };
+  for (int m = 0; m < 16; ++m)
+    for (int l = 0; l < 64; ++l)
+      for (int s = 0; s < 8; ++s) {
+        const int row = 16 * m + (l & 15), k = 8 * (l >> 4) + s;
+        img[((size_t)m * 64 + l) * 8 + s] = k < W ? W1[(size_t)row * W + k] : 0;
+      }
+  const size_t o2 = (size_t)sgk::kW1Frags * 8;
+  for (int m = 0; m < 8; ++m)
+    for (int kb = 0; kb < 8; ++kb)
+      for (int l = 0; l < 64; ++l)
+        for (int s = 0; s < 8; ++s) {
+          const int row = 16 * m + (l & 15), k = kperm(kb, l >> 4, s);
+          img[o2 + (((size_t)m * 8 + kb) * 64 + l) * 8 + s] = W2[(size_t)row * h1 + k];
+        }
+  const size_t o3 = o2 + (size_t)sgk::kW2Frags * 8;
+  for (int kb = 0; kb < 4; ++kb)
+    for (int l = 0; l < 64; ++l)
+      for (int s = 0; s < 8; ++s) {
+        const int row = l & 15, k = kperm(kb, l >> 4, s);
+        img[o3 + ((size_t)kb * 64 + l) * 8 + s] = row < O ? W3[(size_t)row * h2 + k] : 0;
+      }
+  std::vector<float> bimg(sgk::kBiasFloats, 0.f);
+  for (int i = 0; i < h1; ++i) bimg[i] = b[i];
+  for (int i = 0; i < h2; ++i) bimg[sgk::kH1 + i] = b[h1 + i];
+  for (int i = 0; i < O; ++i) bimg[sgk::kH1 + sgk::kH2 + i] = b[h1 + h2 + i];
+  hipError_t e = hipSuccess;
+  if (!c->w_bf16) e = hipMalloc((void**)&c->w_bf16, img.size() * sizeof(uint16_t));
+  if (e == hipSuccess && !c->bias) e = hipMalloc((void**)&c->bias, bimg.size() * sizeof(float));
+  if (e == hipSuccess && !c->log_std) e = hipMalloc((void**)&c->log_std, c->J * sizeof(float));
+  if (e == hipSuccess) e = hipMemcpy(c->w_bf16, img.data(), img.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->bias, bimg.data(), bimg.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->log_std, log_std, c->J * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(c, e, "sg_set_policy");
+  c->has_policy = 1;
+  c->h1 = h1;
+  c->h2 = h2;
+  return SG_OK;
+}
+
+sg_status sg_policy_forward(sg_ctx* c, const float* x, int32_t n, float* out) {
+  if (!c) return SG_E_INVAL;
+  if (!c->has_policy) return fail(c, SG_E_STATE, "sg_policy_forward: no policy set");
+  if (!x || !out || n < 1 || !aligned(x) || !aligned(out))
+    return fail(c, SG_E_INVAL, "sg_policy_forward: bad buffer or n");
+  hipError_t e = sgk::launch_policy_forward(c, x, n, out);
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_policy_forward");
+}
+
+sg_status sg_rollout(sg_ctx* c, int32_t T, const sg_rollout_bufs* b) {
+  if (!c) return SG_E_INVAL;
+  if (c->dtype != SG_F32) return fail(c, SG_E_UNSUPPORTED, "sg_rollout: FP32 contexts only");
+  if (!c->has_policy) return fail(c, SG_E_STATE, "sg_rollout: no policy set");
+  if (!b || T < 1 || T > 4096) return fail(c, SG_E_INVAL, "sg_rollout: T must be in 1..4096");
+  if (!b->obs || !b->act || !b->logp || !b->rew || !b->done || !b->val || !b->adv || !b->ret)
+    return fail(c, SG_E_INVAL, "sg_rollout: null buffer");
+  if (!aligned(b->obs) || !aligned(b->act) || !aligned(b->logp) || !aligned(b->rew) || !aligned(b->val) ||
+      !aligned(b->adv) || !aligned(b->ret))
+    return fail(c, SG_E_INVAL, "sg_rollout: misaligned buffer");
+  hipError_t e = sgk::launch_rollout(c, T, b);
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_rollout");
+}
+
+sg_status sg_gae(sg_ctx* c, int32_t T, int32_t n, const float* rew, const float* val, const uint8_t* done, float gamma,
+                 float lam, float* adv, float* ret) {
+  if (!c) return SG_E_INVAL;
+  if (T < 1 || n < 1 || !rew || !val || !done || !adv || !ret) return fail(c, SG_E_INVAL, "sg_gae: bad argument");
+  hipError_t e = sgk::launch_gae(c->stream, T, n, rew, val, done, gamma, lam, adv, ret);
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_gae");
+}
+
+}  // extern "C"

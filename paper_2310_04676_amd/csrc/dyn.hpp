@@ -1,0 +1,387 @@
+// Per-lane rigid-body dynamics of a fixed-base revolute serial chain, for
+// CDNA4 (gfx950): one environment per lane, the whole chain in VGPRs.
+//
+// Algorithms (Featherstone, "Rigid Body Dynamics Algorithms", 2008):
+//   * ABA (Table 7.1): pass 1 outward (joint transforms, velocities,
+//     velocity-product accelerations c, bias forces p = v x* I v), pass 2
+//     inward (articulated inertias IA and bias forces pA; the joint's D gets
+//     the drive armature added), pass 3 outward (accelerations, gravity as
+//     the base acceleration a0 = (0; -g)).
+//   * RNEA (Table 5.1) for inverse dynamics.
+// Spatial conventions: motion (w; v), force (n; f), X_j = rot(R_j^T)
+// xlt(offset_j) from link j-1 to link j coordinates, R_j = rotation by q_j
+// about axis_j (Rodrigues), S_j = (axis_j; 0).
+//
+// Link inertias are rigid-body ones held as (m, h = m c, I_O): mass, first
+// moment and rotational inertia about the link origin, 10 numbers; the
+// articulated inertia of pass 2 is a general symmetric 6x6 held as blocks
+// A (sym), B, C (sym) = 21 numbers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace sgk {
+
+// Parameter fields of the device parameter block [F][J][N].
+enum {
+  P_AX = 0, P_AY, P_AZ,          // joint axis
+  P_OX, P_OY, P_OZ,              // joint origin in the parent frame
+  P_M,                           // mass
+  P_HX, P_HY, P_HZ,              // first moment m c
+  P_IXX, P_IYY, P_IZZ, P_IXY, P_IXZ, P_IYZ,  // inertia about the link origin
+  P_KP, P_KD, P_LO, P_HI, P_Q0,
+  P_NFIELDS
+};
+
+template <typename T> struct Jp {
+  T ax, ay, az, ox, oy, oz, m, hx, hy, hz, ixx, iyy, izz, ixy, ixz, iyz, kp, kd, lo, hi;
+};
+
+__device__ __forceinline__ void sc(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sc(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ float rsq(float x) { return sqrtf(x); }
+__device__ __forceinline__ double rsq(double x) { return sqrt(x); }
+
+template <typename T>
+__device__ __forceinline__ void load_joint(const T* __restrict__ par, int J, int N, int j, int e, Jp<T>& p) {
+  const T* b = par + (size_t)j * N + e;
+  const size_t fs = (size_t)J * N;
+  p.ax = b[P_AX * fs]; p.ay = b[P_AY * fs]; p.az = b[P_AZ * fs];
+  p.ox = b[P_OX * fs]; p.oy = b[P_OY * fs]; p.oz = b[P_OZ * fs];
+  p.m = b[P_M * fs];
+  p.hx = b[P_HX * fs]; p.hy = b[P_HY * fs]; p.hz = b[P_HZ * fs];
+  p.ixx = b[P_IXX * fs]; p.iyy = b[P_IYY * fs]; p.izz = b[P_IZZ * fs];
+  p.ixy = b[P_IXY * fs]; p.ixz = b[P_IXZ * fs]; p.iyz = b[P_IYZ * fs];
+  p.kp = b[P_KP * fs]; p.kd = b[P_KD * fs]; p.lo = b[P_LO * fs]; p.hi = b[P_HI * fs];
+}
+
+// Rotation by angle (s = sin, c = cos) about unit axis a, row-major R[9].
+template <typename T>
+__device__ __forceinline__ void rodrigues(const Jp<T>& p, T s, T c, T* R) {
+  const T t = T(1) - c;
+  const T txy = t * p.ax * p.ay, txz = t * p.ax * p.az, tyz = t * p.ay * p.az;
+  R[0] = c + t * p.ax * p.ax; R[1] = txy - s * p.az;      R[2] = txz + s * p.ay;
+  R[3] = txy + s * p.az;      R[4] = c + t * p.ay * p.ay; R[5] = tyz - s * p.ax;
+  R[6] = txz - s * p.ay;      R[7] = tyz + s * p.ax;      R[8] = c + t * p.az * p.az;
+}
+
+// X m for X = rot(R^T) xlt(o): w' = R^T w, v' = R^T (v - o x w).
+template <typename T>
+__device__ __forceinline__ void xmotion(const T* R, const Jp<T>& p, const T* m, T* out) {
+  const T tx = m[3] - (p.oy * m[2] - p.oz * m[1]);
+  const T ty = m[4] - (p.oz * m[0] - p.ox * m[2]);
+  const T tz = m[5] - (p.ox * m[1] - p.oy * m[0]);
+  out[0] = R[0] * m[0] + R[3] * m[1] + R[6] * m[2];
+  out[1] = R[1] * m[0] + R[4] * m[1] + R[7] * m[2];
+  out[2] = R[2] * m[0] + R[5] * m[1] + R[8] * m[2];
+  out[3] = R[0] * tx + R[3] * ty + R[6] * tz;
+  out[4] = R[1] * tx + R[4] * ty + R[7] * tz;
+  out[5] = R[2] * tx + R[5] * ty + R[8] * tz;
+}
+
+// X^T f (child -> parent): f' = R f, n' = R n + o x f'.
+template <typename T>
+__device__ __forceinline__ void xforce_T(const T* R, const Jp<T>& p, const T* f, T* out) {
+  const T fx = R[0] * f[3] + R[1] * f[4] + R[2] * f[5];
+  const T fy = R[3] * f[3] + R[4] * f[4] + R[5] * f[5];
+  const T fz = R[6] * f[3] + R[7] * f[4] + R[8] * f[5];
+  out[0] = R[0] * f[0] + R[1] * f[1] + R[2] * f[2] + (p.oy * fz - p.oz * fy);
+  out[1] = R[3] * f[0] + R[4] * f[1] + R[5] * f[2] + (p.oz * fx - p.ox * fz);
+  out[2] = R[6] * f[0] + R[7] * f[1] + R[8] * f[2] + (p.ox * fy - p.oy * fx);
+  out[3] = fx; out[4] = fy; out[5] = fz;
+}
+
+// Rigid-body I v with I = [[I_O, h x], [-(h x), m 1]]: n = I_O w + h x v,
+// f = m v - h x w.
+template <typename T>
+__device__ __forceinline__ void rigid_mul(const Jp<T>& p, const T* v, T* out) {
+  out[0] = p.ixx * v[0] + p.ixy * v[1] + p.ixz * v[2] + (p.hy * v[5] - p.hz * v[4]);
+  out[1] = p.ixy * v[0] + p.iyy * v[1] + p.iyz * v[2] + (p.hz * v[3] - p.hx * v[5]);
+  out[2] = p.ixz * v[0] + p.iyz * v[1] + p.izz * v[2] + (p.hx * v[4] - p.hy * v[3]);
+  out[3] = p.m * v[3] - (p.hy * v[2] - p.hz * v[1]);
+  out[4] = p.m * v[4] - (p.hz * v[0] - p.hx * v[2]);
+  out[5] = p.m * v[5] - (p.hx * v[1] - p.hy * v[0]);
+}
+
+// Symmetric 3x3 held as (xx, yy, zz, xy, xz, yz).
+enum { S00 = 0, S11 = 1, S22 = 2, S01 = 3, S02 = 4, S12 = 5 };
+
+// Articulated inertia blocks.
+template <typename T> struct AI {
+  T A[6];  // angular-angular, symmetric
+  T B[9];  // angular-linear, row-major
+  T C[6];  // linear-linear, symmetric
+};
+
+template <typename T> __device__ __forceinline__ T sym_at(const T* S, int i, int j) {
+  const int k = (i == j) ? i : (i + j == 1 ? S01 : (i + j == 2 ? S02 : S12));
+  return S[k];
+}
+
+// R S R^T for symmetric S (both as 6-vectors).
+template <typename T> __device__ __forceinline__ void sym_rot(const T* R, const T* S, T* out) {
+  T RS[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      RS[i * 3 + k] = R[i * 3 + 0] * sym_at(S, 0, k) + R[i * 3 + 1] * sym_at(S, 1, k) + R[i * 3 + 2] * sym_at(S, 2, k);
+  auto e = [&](int i, int j) { return RS[i * 3 + 0] * R[j * 3 + 0] + RS[i * 3 + 1] * R[j * 3 + 1] + RS[i * 3 + 2] * R[j * 3 + 2]; };
+  out[S00] = e(0, 0); out[S11] = e(1, 1); out[S22] = e(2, 2);
+  out[S01] = e(0, 1); out[S02] = e(0, 2); out[S12] = e(1, 2);
+}
+
+// X^T Ia X for X = rot(R^T) xlt(o): rotate (R . R^T) then translate:
+// C2 = C1, B2 = B1 + ox C1, A2 = A1 + ox B1^T - B2 ox. Accumulates into acc.
+template <typename T>
+__device__ __forceinline__ void congruence_acc(const T* R, const Jp<T>& p, const AI<T>& I, AI<T>& acc) {
+  T A1[6], C1[6], B1[9];
+  sym_rot(R, I.A, A1);
+  sym_rot(R, I.C, C1);
+  {
+    T RB[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        RB[i * 3 + k] = R[i * 3 + 0] * I.B[0 * 3 + k] + R[i * 3 + 1] * I.B[1 * 3 + k] + R[i * 3 + 2] * I.B[2 * 3 + k];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        B1[i * 3 + j] = RB[i * 3 + 0] * R[j * 3 + 0] + RB[i * 3 + 1] * R[j * 3 + 1] + RB[i * 3 + 2] * R[j * 3 + 2];
+  }
+  const T o[3] = {p.ox, p.oy, p.oz};
+  // B2 = B1 + o x C1 (column j: o x C1[:, j])
+  T B2[9];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const T c0 = sym_at(C1, 0, j), c1 = sym_at(C1, 1, j), c2 = sym_at(C1, 2, j);
+    B2[0 * 3 + j] = B1[0 * 3 + j] + (o[1] * c2 - o[2] * c1);
+    B2[1 * 3 + j] = B1[1 * 3 + j] + (o[2] * c0 - o[0] * c2);
+    B2[2 * 3 + j] = B1[2 * 3 + j] + (o[0] * c1 - o[1] * c0);
+  }
+  // A2_ij = A1_ij + (o x B1[j, :])_i - (B2[i, :] x o)_j, i <= j
+  auto Y = [&](int i, int j) {
+    const T b0 = B1[j * 3 + 0], b1 = B1[j * 3 + 1], b2 = B1[j * 3 + 2];
+    return i == 0 ? (o[1] * b2 - o[2] * b1) : (i == 1 ? (o[2] * b0 - o[0] * b2) : (o[0] * b1 - o[1] * b0));
+  };
+  auto Z = [&](int i, int j) {
+    const T b0 = B2[i * 3 + 0], b1 = B2[i * 3 + 1], b2 = B2[i * 3 + 2];
+    return j == 0 ? (b1 * o[2] - b2 * o[1]) : (j == 1 ? (b2 * o[0] - b0 * o[2]) : (b0 * o[1] - b1 * o[0]));
+  };
+  acc.A[S00] += A1[S00] + Y(0, 0) - Z(0, 0);
+  acc.A[S11] += A1[S11] + Y(1, 1) - Z(1, 1);
+  acc.A[S22] += A1[S22] + Y(2, 2) - Z(2, 2);
+  acc.A[S01] += A1[S01] + Y(0, 1) - Z(0, 1);
+  acc.A[S02] += A1[S02] + Y(0, 2) - Z(0, 2);
+  acc.A[S12] += A1[S12] + Y(1, 2) - Z(1, 2);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc.B[k] += B2[k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) acc.C[k] += C1[k];
+}
+
+// Forward dynamics for one env: qdd = (H + diag(arm))^-1 (tau - C).
+// Joints j >= n are skipped. grav = base-frame gravity.
+template <typename T, int J>
+__device__ __forceinline__ void aba(const Jp<T> (&P)[J], int n, const T (&q)[J], const T (&qd)[J],
+                                    const T (&tau)[J], const T (&arm)[J], const T* grav, T (&qdd)[J]) {
+  T R[J][9], cj[J][6], pj[J][6], U[J][6], invD[J], uj[J];
+  // pass 1
+  T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < n) {
+      T s, c;
+      sc(q[j], &s, &c);
+      rodrigues(P[j], s, c, R[j]);
+      T vn[6];
+      xmotion(R[j], P[j], v, vn);
+      const T wx = P[j].ax * qd[j], wy = P[j].ay * qd[j], wz = P[j].az * qd[j];
+      vn[0] += wx; vn[1] += wy; vn[2] += wz;
+      // c = v x (S qd) with S qd = (wJ; 0): (w x wJ; v x wJ)
+      cj[j][0] = vn[1] * wz - vn[2] * wy;
+      cj[j][1] = vn[2] * wx - vn[0] * wz;
+      cj[j][2] = vn[0] * wy - vn[1] * wx;
+      cj[j][3] = vn[4] * wz - vn[5] * wy;
+      cj[j][4] = vn[5] * wx - vn[3] * wz;
+      cj[j][5] = vn[3] * wy - vn[4] * wx;
+      T Iv[6];
+      rigid_mul(P[j], vn, Iv);
+      // p = v x* (I v) = (w x n + v x f; w x f)
+      pj[j][0] = (vn[1] * Iv[2] - vn[2] * Iv[1]) + (vn[4] * Iv[5] - vn[5] * Iv[4]);
+      pj[j][1] = (vn[2] * Iv[0] - vn[0] * Iv[2]) + (vn[5] * Iv[3] - vn[3] * Iv[5]);
+      pj[j][2] = (vn[0] * Iv[1] - vn[1] * Iv[0]) + (vn[3] * Iv[4] - vn[4] * Iv[3]);
+      pj[j][3] = vn[1] * Iv[5] - vn[2] * Iv[4];
+      pj[j][4] = vn[2] * Iv[3] - vn[0] * Iv[5];
+      pj[j][5] = vn[0] * Iv[4] - vn[1] * Iv[3];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v[k] = vn[k];
+    }
+  }
+  // pass 2
+  AI<T> acc;
+  T accp[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) { acc.A[k] = T(0); acc.C[k] = T(0); accp[k] = T(0); }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc.B[k] = T(0);
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j) {
+    if (j < n) {
+      const Jp<T>& p = P[j];
+      AI<T> I;
+      I.A[S00] = p.ixx + acc.A[S00]; I.A[S11] = p.iyy + acc.A[S11]; I.A[S22] = p.izz + acc.A[S22];
+      I.A[S01] = p.ixy + acc.A[S01]; I.A[S02] = p.ixz + acc.A[S02]; I.A[S12] = p.iyz + acc.A[S12];
+      I.B[0] = acc.B[0];         I.B[1] = acc.B[1] - p.hz; I.B[2] = acc.B[2] + p.hy;
+      I.B[3] = acc.B[3] + p.hz;  I.B[4] = acc.B[4];        I.B[5] = acc.B[5] - p.hx;
+      I.B[6] = acc.B[6] - p.hy;  I.B[7] = acc.B[7] + p.hx; I.B[8] = acc.B[8];
+      I.C[S00] = p.m + acc.C[S00]; I.C[S11] = p.m + acc.C[S11]; I.C[S22] = p.m + acc.C[S22];
+      I.C[S01] = acc.C[S01];       I.C[S02] = acc.C[S02];       I.C[S12] = acc.C[S12];
+      T pa[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) pa[k] = pj[j][k] + accp[k];
+      // U = IA S = (A a; B^T a)
+      U[j][0] = I.A[S00] * p.ax + I.A[S01] * p.ay + I.A[S02] * p.az;
+      U[j][1] = I.A[S01] * p.ax + I.A[S11] * p.ay + I.A[S12] * p.az;
+      U[j][2] = I.A[S02] * p.ax + I.A[S12] * p.ay + I.A[S22] * p.az;
+      U[j][3] = I.B[0] * p.ax + I.B[3] * p.ay + I.B[6] * p.az;
+      U[j][4] = I.B[1] * p.ax + I.B[4] * p.ay + I.B[7] * p.az;
+      U[j][5] = I.B[2] * p.ax + I.B[5] * p.ay + I.B[8] * p.az;
+      const T D = U[j][0] * p.ax + U[j][1] * p.ay + U[j][2] * p.az + arm[j];
+      invD[j] = T(1) / D;
+      uj[j] = tau[j] - (pa[0] * p.ax + pa[1] * p.ay + pa[2] * p.az);
+      if (j > 0) {
+        T Ud[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Ud[k] = U[j][k] * invD[j];
+        // Ia = IA - U Ud^T
+        I.A[S00] -= U[j][0] * Ud[0]; I.A[S11] -= U[j][1] * Ud[1]; I.A[S22] -= U[j][2] * Ud[2];
+        I.A[S01] -= U[j][0] * Ud[1]; I.A[S02] -= U[j][0] * Ud[2]; I.A[S12] -= U[j][1] * Ud[2];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int s2 = 0; s2 < 3; ++s2) I.B[r * 3 + s2] -= U[j][r] * Ud[3 + s2];
+        I.C[S00] -= U[j][3] * Ud[3]; I.C[S11] -= U[j][4] * Ud[4]; I.C[S22] -= U[j][5] * Ud[5];
+        I.C[S01] -= U[j][3] * Ud[4]; I.C[S02] -= U[j][3] * Ud[5]; I.C[S12] -= U[j][4] * Ud[5];
+        // pa += Ia c + U u / D
+        const T* c = cj[j];
+        const T uD = uj[j] * invD[j];
+        T f[6];
+        f[0] = pa[0] + I.A[S00] * c[0] + I.A[S01] * c[1] + I.A[S02] * c[2] + I.B[0] * c[3] + I.B[1] * c[4] + I.B[2] * c[5] + U[j][0] * uD;
+        f[1] = pa[1] + I.A[S01] * c[0] + I.A[S11] * c[1] + I.A[S12] * c[2] + I.B[3] * c[3] + I.B[4] * c[4] + I.B[5] * c[5] + U[j][1] * uD;
+        f[2] = pa[2] + I.A[S02] * c[0] + I.A[S12] * c[1] + I.A[S22] * c[2] + I.B[6] * c[3] + I.B[7] * c[4] + I.B[8] * c[5] + U[j][2] * uD;
+        f[3] = pa[3] + I.B[0] * c[0] + I.B[3] * c[1] + I.B[6] * c[2] + I.C[S00] * c[3] + I.C[S01] * c[4] + I.C[S02] * c[5] + U[j][3] * uD;
+        f[4] = pa[4] + I.B[1] * c[0] + I.B[4] * c[1] + I.B[7] * c[2] + I.C[S01] * c[3] + I.C[S11] * c[4] + I.C[S12] * c[5] + U[j][4] * uD;
+        f[5] = pa[5] + I.B[2] * c[0] + I.B[5] * c[1] + I.B[8] * c[2] + I.C[S02] * c[3] + I.C[S12] * c[4] + I.C[S22] * c[5] + U[j][5] * uD;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) { acc.A[k] = T(0); acc.C[k] = T(0); }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc.B[k] = T(0);
+        congruence_acc(R[j], p, I, acc);
+        xforce_T(R[j], p, f, accp);
+      }
+    }
+  }
+  // pass 3
+  T a[6] = {T(0), T(0), T(0), -grav[0], -grav[1], -grav[2]};
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < n) {
+      T an[6];
+      xmotion(R[j], P[j], a, an);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) an[k] += cj[j][k];
+      T dot = U[j][0] * an[0] + U[j][1] * an[1] + U[j][2] * an[2] + U[j][3] * an[3] + U[j][4] * an[4] + U[j][5] * an[5];
+      qdd[j] = (uj[j] - dot) * invD[j];
+      an[0] += P[j].ax * qdd[j]; an[1] += P[j].ay * qdd[j]; an[2] += P[j].az * qdd[j];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) a[k] = an[k];
+    } else {
+      qdd[j] = T(0);
+    }
+  }
+}
+
+// Inverse dynamics for one env: tau = H qdd + C (gravity included).
+template <typename T, int J>
+__device__ __forceinline__ void rnea(const Jp<T> (&P)[J], int n, const T (&q)[J], const T (&qd)[J],
+                                     const T (&qdd)[J], const T* grav, T (&tau)[J]) {
+  T R[J][9], f[J][6];
+  T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  T a[6] = {T(0), T(0), T(0), -grav[0], -grav[1], -grav[2]};
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < n) {
+      T s, c;
+      sc(q[j], &s, &c);
+      rodrigues(P[j], s, c, R[j]);
+      T vn[6], an[6];
+      xmotion(R[j], P[j], v, vn);
+      xmotion(R[j], P[j], a, an);
+      const T wx = P[j].ax * qd[j], wy = P[j].ay * qd[j], wz = P[j].az * qd[j];
+      vn[0] += wx; vn[1] += wy; vn[2] += wz;
+      an[0] += P[j].ax * qdd[j] + (vn[1] * wz - vn[2] * wy);
+      an[1] += P[j].ay * qdd[j] + (vn[2] * wx - vn[0] * wz);
+      an[2] += P[j].az * qdd[j] + (vn[0] * wy - vn[1] * wx);
+      an[3] += vn[4] * wz - vn[5] * wy;
+      an[4] += vn[5] * wx - vn[3] * wz;
+      an[5] += vn[3] * wy - vn[4] * wx;
+      T Ia[6], Iv[6];
+      rigid_mul(P[j], an, Ia);
+      rigid_mul(P[j], vn, Iv);
+      f[j][0] = Ia[0] + (vn[1] * Iv[2] - vn[2] * Iv[1]) + (vn[4] * Iv[5] - vn[5] * Iv[4]);
+      f[j][1] = Ia[1] + (vn[2] * Iv[0] - vn[0] * Iv[2]) + (vn[5] * Iv[3] - vn[3] * Iv[5]);
+      f[j][2] = Ia[2] + (vn[0] * Iv[1] - vn[1] * Iv[0]) + (vn[3] * Iv[4] - vn[4] * Iv[3]);
+      f[j][3] = Ia[3] + (vn[1] * Iv[5] - vn[2] * Iv[4]);
+      f[j][4] = Ia[4] + (vn[2] * Iv[3] - vn[0] * Iv[5]);
+      f[j][5] = Ia[5] + (vn[0] * Iv[4] - vn[1] * Iv[3]);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) { v[k] = vn[k]; a[k] = an[k]; }
+    }
+  }
+  T fc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j) {
+    if (j < n) {
+      T ft[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) ft[k] = f[j][k] + fc[k];
+      tau[j] = P[j].ax * ft[0] + P[j].ay * ft[1] + P[j].az * ft[2];
+      xforce_T(R[j], P[j], ft, fc);
+    } else {
+      tau[j] = T(0);
+    }
+  }
+}
+
+// Tool-tip position: p_j = p_{j-1} + R_{j-1} o_j, R_j = R_{j-1} Rot(a_j, q_j),
+// tip = p + R tip_local.
+template <typename T, int J>
+__device__ __forceinline__ void tip_fk(const Jp<T> (&P)[J], int n, const T (&q)[J], const T* tipl, T* out) {
+  T W[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)};
+  T px = T(0), py = T(0), pz = T(0);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < n) {
+      px += W[0] * P[j].ox + W[1] * P[j].oy + W[2] * P[j].oz;
+      py += W[3] * P[j].ox + W[4] * P[j].oy + W[5] * P[j].oz;
+      pz += W[6] * P[j].ox + W[7] * P[j].oy + W[8] * P[j].oz;
+      T s, c, Rj[9], Wn[9];
+      sc(q[j], &s, &c);
+      rodrigues(P[j], s, c, Rj);
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          Wn[r * 3 + k] = W[r * 3 + 0] * Rj[0 * 3 + k] + W[r * 3 + 1] * Rj[1 * 3 + k] + W[r * 3 + 2] * Rj[2 * 3 + k];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) W[k] = Wn[k];
+    }
+  }
+  out[0] = px + W[0] * tipl[0] + W[1] * tipl[1] + W[2] * tipl[2];
+  out[1] = py + W[3] * tipl[0] + W[4] * tipl[1] + W[5] * tipl[2];
+  out[2] = pz + W[6] * tipl[0] + W[7] * tipl[1] + W[8] * tipl[2];
+}
+
+}  // namespace sgk

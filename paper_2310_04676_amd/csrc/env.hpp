@@ -1,0 +1,200 @@
+// Per-lane environment logic around the dynamics: action -> PD target,
+// implicit-PD substeps with semi-implicit Euler and hard limits, then
+// tool-tip kinematics, reward, episode bookkeeping, auto-reset and the
+// observation (paper Sec. III "Simulation Setup", "Action Space",
+// "Observation Space", "Policy learning and control"; Sec. IV target
+// reaching and path following rewards).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dyn.hpp"
+
+namespace sgk {
+
+enum { TASK_REACH = 0, TASK_PATH = 1 };
+enum { DONE_ENDED = 1, DONE_TIMEOUT = 2, DONE_NONFINITE = 4 };
+
+template <typename T> struct EnvDev {
+  int N, J, S, task, K, dwell, ep_len;
+  T dt, h, g[3];
+  const T* par;       // [P_NFIELDS][J][N]
+  const T* tip;       // [3][N]
+  const int* nd;      // [N]
+  const T* target;    // [3][N]
+  const T* wp;        // [K][3][N]
+  const int* prog0;   // [N]
+  T* q;               // [J][N]
+  T* qd;              // [J][N]
+  int* prog;          // [N]
+};
+
+template <typename T, int J>
+__device__ __forceinline__ void load_chain(const EnvDev<T>& E, int e, int n, Jp<T> (&P)[J]) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < n) load_joint(E.par, E.J, E.N, j, e, P[j]);
+  }
+}
+
+template <typename T, int J>
+__device__ __forceinline__ void load_state(const EnvDev<T>& E, int e, int n, T (&q)[J], T (&qd)[J]) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    q[j] = j < n ? E.q[(size_t)j * E.N + e] : T(0);
+    qd[j] = j < n ? E.qd[(size_t)j * E.N + e] : T(0);
+  }
+}
+
+template <typename T> __device__ __forceinline__ T clamp1(T a) { return a > T(1) ? T(1) : (a < T(-1) ? T(-1) : a); }
+
+// S substeps of the implicit-PD step with the action held (zero-order hold).
+template <typename T, int J>
+__device__ __forceinline__ void physics(const EnvDev<T>& E, const Jp<T> (&P)[J], int n, const T (&act)[J],
+                                        T (&q)[J], T (&qd)[J]) {
+  const T h = E.h;
+  T qs[J], arm[J], tau[J], qdd[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const T mid = T(0.5) * (P[j].hi + P[j].lo), half = T(0.5) * (P[j].hi - P[j].lo);
+    qs[j] = j < n ? mid + half * clamp1(act[j]) : T(0);
+    arm[j] = j < n ? h * P[j].kd + h * h * P[j].kp : T(0);
+  }
+  for (int s = 0; s < E.S; ++s) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) tau[j] = j < n ? P[j].kp * (qs[j] - q[j] - h * qd[j]) - P[j].kd * qd[j] : T(0);
+    aba<T, J>(P, n, q, qd, tau, arm, E.g, qdd);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (j < n) {
+        qd[j] = qd[j] + h * qdd[j];
+        q[j] = q[j] + h * qd[j];
+        if (q[j] > P[j].hi) {
+          q[j] = P[j].hi;
+          if (qd[j] > T(0)) qd[j] = T(0);
+        } else if (q[j] < P[j].lo) {
+          q[j] = P[j].lo;
+          if (qd[j] < T(0)) qd[j] = T(0);
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void goal_of(const EnvDev<T>& E, int e, int progress, T* g) {
+  if (E.task == TASK_REACH) {
+    g[0] = E.target[e];
+    g[1] = E.target[E.N + e];
+    g[2] = E.target[2 * E.N + e];
+  } else {
+    int k = progress / E.dwell;
+    k = k > E.K - 1 ? E.K - 1 : k;
+    const T* w = E.wp + (size_t)k * 3 * E.N;
+    g[0] = w[e];
+    g[1] = w[E.N + e];
+    g[2] = w[2 * E.N + e];
+  }
+}
+
+template <typename T, int J>
+__device__ __forceinline__ void write_obs(const EnvDev<T>& E, int e, int n, const T (&q)[J], const T (&qd)[J],
+                                          const T* tip, const T* g, T* __restrict__ obs) {
+  const size_t N = E.N;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < E.J) {
+      obs[(size_t)j * N + e] = j < n ? q[j] : T(0);
+      obs[(size_t)(E.J + j) * N + e] = j < n ? qd[j] : T(0);
+    }
+  }
+  T* o = obs + (size_t)(2 * E.J) * N + e;
+  const T dx = g[0] - tip[0], dy = g[1] - tip[1], dz = g[2] - tip[2];
+  o[0] = tip[0]; o[N] = tip[1]; o[2 * N] = tip[2];
+  o[3 * N] = g[0]; o[4 * N] = g[1]; o[5 * N] = g[2];
+  o[6 * N] = dx; o[7 * N] = dy; o[8 * N] = dz;
+  o[9 * N] = rsq(dx * dx + dy * dy + dz * dz);
+}
+
+template <typename T> __device__ __forceinline__ bool finite_(T x) { return isfinite(x); }
+
+// After the physics: reward on the post-step tip, progress, time-out or
+// non-finite reset, observation of the post-reset state, state store.
+// Returns the done bits; *reward receives the reward.
+// Observation row in registers (width 2*E.J + 10, entries beyond zero-padded
+// up to the caller's array size).
+template <typename T, int J, int WMAX>
+__device__ __forceinline__ void obs_regs(const EnvDev<T>& E, int n, const T (&q)[J], const T (&qd)[J], const T* tip,
+                                         const T* g, T (&x)[WMAX]) {
+#pragma unroll
+  for (int k = 0; k < WMAX; ++k) x[k] = T(0);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < E.J) {
+      x[j] = j < n ? q[j] : T(0);
+      x[E.J + j] = j < n ? qd[j] : T(0);
+    }
+  }
+  const T dx = g[0] - tip[0], dy = g[1] - tip[1], dz = g[2] - tip[2];
+  const int b = 2 * E.J;
+  x[b + 0] = tip[0]; x[b + 1] = tip[1]; x[b + 2] = tip[2];
+  x[b + 3] = g[0];   x[b + 4] = g[1];   x[b + 5] = g[2];
+  x[b + 6] = dx;     x[b + 7] = dy;     x[b + 8] = dz;
+  x[b + 9] = rsq(dx * dx + dy * dy + dz * dz);
+}
+
+template <typename T, int J>
+__device__ __forceinline__ uint8_t post_step(const EnvDev<T>& E, int e, int n, const Jp<T> (&P)[J], T (&q)[J],
+                                             T (&qd)[J], int& prog, T* reward, T* __restrict__ obs,
+                                             T* tip_out = nullptr, T* goal_out = nullptr) {
+  const T tipl[3] = {E.tip[e], E.tip[E.N + e], E.tip[2 * E.N + e]};
+  T tip[3], g[3];
+  tip_fk<T, J>(P, n, q, tipl, tip);
+  goal_of(E, e, prog, g);
+  const T dx = tip[0] - g[0], dy = tip[1] - g[1], dz = tip[2] - g[2];
+  T r = -rsq(dx * dx + dy * dy + dz * dz);
+  prog = prog + 1;
+  bool fin = true;
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+    if (j < n) fin = fin && finite_(q[j]) && finite_(qd[j]);
+  uint8_t done = 0;
+  if (!fin) {
+    done = DONE_ENDED | DONE_NONFINITE;
+    r = T(0);
+  } else if (E.ep_len > 0 && prog >= E.ep_len) {
+    done = DONE_ENDED | DONE_TIMEOUT;
+  }
+  if (done) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (j < n) {
+        q[j] = E.par[((size_t)P_Q0 * E.J + j) * E.N + e];
+        qd[j] = T(0);
+      }
+    }
+    prog = 0;
+    tip_fk<T, J>(P, n, q, tipl, tip);
+  }
+  goal_of(E, e, prog, g);
+  if (obs) write_obs<T, J>(E, e, n, q, qd, tip, g, obs);
+  if (tip_out) { tip_out[0] = tip[0]; tip_out[1] = tip[1]; tip_out[2] = tip[2]; }
+  if (goal_out) { goal_out[0] = g[0]; goal_out[1] = g[1]; goal_out[2] = g[2]; }
+  *reward = r;
+  return done;
+}
+
+template <typename T, int J>
+__device__ __forceinline__ void store_state(const EnvDev<T>& E, int e, int n, const T (&q)[J], const T (&qd)[J],
+                                            int prog) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < n) {
+      E.q[(size_t)j * E.N + e] = q[j];
+      E.qd[(size_t)j * E.N + e] = qd[j];
+    }
+  }
+  E.prog[e] = prog;
+}
+
+}  // namespace sgk

@@ -1,0 +1,67 @@
+// Library-internal context and launcher declarations.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/surgym.h"
+#include "env.hpp"
+
+struct sg_ctx {
+  int device = 0;
+  int N = 0, J = 0, dtype = SG_F32, S = 1;
+  int task = 0, K = 0, dwell = 1, ep_len = 0;
+  double dt = 0, g[3] = {0, 0, 0};
+  uint64_t seed = 0, rng_step = 0;
+  hipStream_t stream = nullptr;
+  // device memory (dtype-typed unless noted)
+  void* par = nullptr;      // [P_NFIELDS][J][N]
+  void* tip = nullptr;      // [3][N]
+  int* nd = nullptr;        // [N]
+  void* target = nullptr;   // [3][N]
+  void* wp = nullptr;       // [K][3][N]
+  int* prog0 = nullptr;     // [N]
+  void* q = nullptr;        // [J][N]
+  void* qd = nullptr;       // [J][N]
+  int* prog = nullptr;      // [N]
+  // policy (FP32 contexts)
+  int has_policy = 0, h1 = 0, h2 = 0;
+  uint16_t* w_bf16 = nullptr;  // W1 | W2 | W3 row-major BF16
+  float* bias = nullptr;       // b1 | b2 | b3
+  float* log_std = nullptr;    // [J]
+  std::string err;
+};
+
+namespace sgk {
+
+template <typename T> inline EnvDev<T> env_view(const sg_ctx* c) {
+  EnvDev<T> E;
+  E.N = c->N; E.J = c->J; E.S = c->S; E.task = c->task; E.K = c->K; E.dwell = c->dwell; E.ep_len = c->ep_len;
+  E.dt = (T)c->dt;
+  E.h = E.dt / (T)c->S;
+  E.g[0] = (T)c->g[0]; E.g[1] = (T)c->g[1]; E.g[2] = (T)c->g[2];
+  E.par = (const T*)c->par; E.tip = (const T*)c->tip; E.nd = c->nd;
+  E.target = (const T*)c->target; E.wp = (const T*)c->wp; E.prog0 = c->prog0;
+  E.q = (T*)c->q; E.qd = (T*)c->qd; E.prog = c->prog;
+  return E;
+}
+
+// Kernel instantiations cover these max-DOF values; a context uses the
+// smallest one >= its J.
+int dof_bucket(int J);
+
+hipError_t launch_step(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done);
+hipError_t launch_observe(const sg_ctx* c, void* obs);
+hipError_t launch_fd(const sg_ctx* c, const void* q, const void* qd, const void* tau, int arm_mode, void* qdd);
+hipError_t launch_id(const sg_ctx* c, const void* q, const void* qd, const void* qdd, void* tau);
+hipError_t launch_tip(const sg_ctx* c, const void* q, void* tip);
+hipError_t launch_reset(const sg_ctx* c);
+
+// Learning side (FP32 contexts).
+hipError_t launch_policy_forward(const sg_ctx* c, const float* x, int n, float* out);
+hipError_t launch_rollout(sg_ctx* c, int T, const sg_rollout_bufs* b);
+hipError_t launch_gae(hipStream_t s, int T, int n, const float* rew, const float* val, const uint8_t* done,
+                      float gamma, float lam, float* adv, float* ret);
+
+}  // namespace sgk

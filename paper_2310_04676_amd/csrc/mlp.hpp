@@ -1,0 +1,136 @@
+// Policy MLP on the matrix cores (gfx950 v_mfma_f32_16x16x32_bf16) for one
+// wave of 64 environments: [W<=24 -> 256 -> 128 -> 8], tanh hidden units,
+// BF16 operands, FP32 accumulation.
+//
+// Formulation: each layer computes Y^T = W X^T, so the MFMA A operand is a
+// 16x32 weight tile, B is a 32x16 activation tile (16 environments), and the
+// 16x16 result tile D has one environment per column. Lane l = 16 g + j
+// holds D rows 4g..4g+3 of column j, exactly the layout it needs as the next
+// layer's B fragment (column j, eight K values) if the next layer's K index
+// is permuted: in K-block kb (features 32kb..32kb+31) lane group g owns
+// features {32kb + 4g + r, 32kb + 16 + 4g + r | r = 0..3}. The weights are
+// stored in LDS already permuted and in fragment order, so every operand
+// read is one 16-byte ds_read per lane and hidden activations never leave
+// the registers. Only the 24-wide input and the 8 outputs pass through LDS
+// (a transpose between "one env per lane" and the fragment layout).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sgk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kH1 = 256, kH2 = 128, kKin = 32, kOut = 16;  // padded sizes
+// LDS image of the weights, in 16-byte fragments (uint4):
+//   W1: [16 row tiles][64 lanes]          (K = 32 input features, padded)
+//   W2: [8 row tiles][8 K-blocks][64 lanes]
+//   W3: [4 K-blocks][64 lanes]            (16 rows, outputs >= J+1 zero)
+constexpr int kW1Frags = 16 * 64, kW2Frags = 8 * 8 * 64, kW3Frags = 4 * 64;
+constexpr int kWFrags = kW1Frags + kW2Frags + kW3Frags;   // 5376 x 16 B = 84 KB
+constexpr int kBiasFloats = kH1 + kH2 + kOut;              // 400
+
+// fast tanh: 1 - 2 / (exp(2x) + 1), hardware exp and reciprocal; the result
+// is rounded to BF16 before use, far coarser than this formula's error.
+__device__ __forceinline__ float tanh_fast(float x) {
+  const float e = __expf(2.f * x);
+  return 1.f - __fdividef(2.f, e + 1.f);
+}
+
+__device__ __forceinline__ f32x4 mfma16x16x32(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 pack_act(const f32x4& lo, const f32x4& hi) {
+  bf16x8 r;
+  r[0] = (__bf16)tanh_fast(lo[0]); r[1] = (__bf16)tanh_fast(lo[1]);
+  r[2] = (__bf16)tanh_fast(lo[2]); r[3] = (__bf16)tanh_fast(lo[3]);
+  r[4] = (__bf16)tanh_fast(hi[0]); r[5] = (__bf16)tanh_fast(hi[1]);
+  r[6] = (__bf16)tanh_fast(hi[2]); r[7] = (__bf16)tanh_fast(hi[3]);
+  return r;
+}
+
+// Stage one env's input row (W floats, lane = env within the wave) into the
+// B-fragment image xs: [4 N-tiles][4 groups][16 cols] x 16 B.
+__device__ __forceinline__ void stage_input(uint4* xs, int lane, const float* x, int W) {
+  const int n = lane >> 4, j = lane & 15;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    bf16x8 v;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = 8 * g + s;
+      v[s] = (__bf16)(k < W ? x[k] : 0.f);
+    }
+    xs[(n * 4 + g) * 16 + j] = *reinterpret_cast<uint4*>(&v);
+  }
+}
+
+// The forward pass for the wave's 64 staged inputs. ws: weight image,
+// bias: [b1 256 | b2 128 | b3 16] floats, xs: staged inputs, os: output
+// image [64 envs][16] floats. Callers synchronize around it.
+__device__ __forceinline__ void mlp_wave(const uint4* __restrict__ ws, const float* __restrict__ bias,
+                                         const uint4* __restrict__ xs, float* __restrict__ os, int lane) {
+  const int g = lane >> 4, j = lane & 15;
+  const uint4* W1 = ws;
+  const uint4* W2 = ws + kW1Frags;
+  const uint4* W3 = W2 + kW2Frags;
+  bf16x8 xb[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    uint4 t = xs[(n * 4 + g) * 16 + j];
+    xb[n] = *reinterpret_cast<bf16x8*>(&t);
+  }
+  f32x4 acc2[8][4];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const float4 bb = *reinterpret_cast<const float4*>(bias + kH1 + 16 * m + 4 * g);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc2[m][n] = f32x4{bb.x, bb.y, bb.z, bb.w};
+  }
+#pragma unroll
+  for (int kb = 0; kb < 8; ++kb) {
+    f32x4 d1[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int m = 2 * kb + h;
+      uint4 t = W1[m * 64 + lane];
+      const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
+      const float4 bb = *reinterpret_cast<const float4*>(bias + 16 * m + 4 * g);
+#pragma unroll
+      for (int n = 0; n < 4; ++n) d1[h][n] = mfma16x16x32(a, xb[n], f32x4{bb.x, bb.y, bb.z, bb.w});
+    }
+    bf16x8 hb[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) hb[n] = pack_act(d1[0][n], d1[1][n]);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      uint4 t = W2[(m * 8 + kb) * 64 + lane];
+      const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
+#pragma unroll
+      for (int n = 0; n < 4; ++n) acc2[m][n] = mfma16x16x32(a, hb[n], acc2[m][n]);
+    }
+  }
+  f32x4 acc3[4];
+  {
+    const float4 bb = *reinterpret_cast<const float4*>(bias + kH1 + kH2 + 4 * g);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc3[n] = f32x4{bb.x, bb.y, bb.z, bb.w};
+  }
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    uint4 t = W3[kb * 64 + lane];
+    const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc3[n] = mfma16x16x32(a, pack_act(acc2[2 * kb][n], acc2[2 * kb + 1][n]), acc3[n]);
+  }
+  if (g < 2) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+      *reinterpret_cast<float4*>(os + (16 * n + j) * kOut + 4 * g) =
+          make_float4(acc3[n][0], acc3[n][1], acc3[n][2], acc3[n][3]);
+  }
+}
+
+}  // namespace sgk

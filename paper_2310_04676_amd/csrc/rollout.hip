@@ -1,0 +1,287 @@
+// Learning-side kernels: the fused T-step rollout (policy on the matrix
+// cores, exploration noise, environment step), the policy alone, and the
+// GAE backward scan.
+#include "internal.hpp"
+#include "mlp.hpp"
+
+namespace sgk {
+
+// ---- Philox4x32-10 (Salmon et al., SC'11) --------------------------------
+// Ten rounds of: two 32x32->64 multiplies by the round constants, with the
+// high halves xored into the other two words together with the key; the key
+// advances by the Weyl constants between rounds.
+struct U4 {
+  uint32_t x, y, z, w;
+};
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t p0_hi = __umulhi(0xD2511F53u, c.x), p0_lo = 0xD2511F53u * c.x;
+    const uint32_t p1_hi = __umulhi(0xCD9E8D57u, c.z), p1_lo = 0xCD9E8D57u * c.z;
+    c = U4{p1_hi ^ c.y ^ k0, p1_lo, p0_hi ^ c.w ^ k1, p0_lo};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Standard normals for joints 0..J-1 of (env, step) by Box-Muller on 24-bit
+// uniforms ((x >> 8) + 0.5) / 2^24, pairs (x, y) and (z, w) of each block.
+template <int J>
+__device__ __forceinline__ void normals(uint64_t seed, uint32_t env, uint64_t step, int n, float (&eps)[J]) {
+#pragma unroll
+  for (int b = 0; 4 * b < J; ++b) {
+    const U4 r = philox10(U4{env, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)b}, (uint32_t)seed,
+                          (uint32_t)(seed >> 32));
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const float u1 = ((float)(w[2 * p] >> 8) + 0.5f) * (1.0f / 16777216.0f);
+      const float u2 = ((float)(w[2 * p + 1] >> 8) + 0.5f) * (1.0f / 16777216.0f);
+      const float rad = sqrtf(-2.f * logf(u1));
+      float s, c;
+      sincospif(2.f * u2, &s, &c);
+      const int j0 = 4 * b + 2 * p;
+      if (j0 < J) eps[j0] = j0 < n ? rad * c : 0.f;
+      if (j0 + 1 < J) eps[j0 + 1] = j0 + 1 < n ? rad * s : 0.f;
+    }
+  }
+}
+
+constexpr int kWave = 64;
+constexpr int kXMax = 32;  // observation width padded to the first layer's K
+
+// LDS layout of the rollout kernel (bytes)
+constexpr size_t kLdsW = (size_t)kWFrags * 16;
+constexpr size_t kLdsBias = (size_t)kBiasFloats * 4;
+constexpr size_t kLdsX = 256 * 16;
+constexpr size_t kLdsO = (size_t)kWave * kOut * 4;
+template <int J> constexpr size_t lds_par_bytes() { return (size_t)P_NFIELDS * J * kWave * 4; }
+template <int J> constexpr size_t rollout_lds_bytes() { return kLdsW + kLdsBias + kLdsX + kLdsO + lds_par_bytes<J>(); }
+
+struct RollArgs {
+  EnvDev<float> E;
+  const uint4* wimg;
+  const float* bias;
+  const float* log_std;
+  int T;
+  uint64_t seed, step0;
+  float* obs;
+  float* act;
+  float* logp;
+  float* rew;
+  uint8_t* done;
+  float* val;
+};
+
+__device__ __forceinline__ void fill_weights(uint4* sw, float* sb, const uint4* __restrict__ wimg,
+                                             const float* __restrict__ bias, int lane) {
+  for (int i = lane; i < kWFrags; i += kWave) sw[i] = wimg[i];
+  for (int i = lane; i < kBiasFloats; i += kWave) sb[i] = bias[i];
+}
+
+template <int J>
+__device__ __forceinline__ void load_joint_lds(const float* sp, int j, int lane, Jp<float>& p) {
+  const float* b = sp + j * kWave + lane;
+  constexpr int fs = J * kWave;
+  p.ax = b[P_AX * fs]; p.ay = b[P_AY * fs]; p.az = b[P_AZ * fs];
+  p.ox = b[P_OX * fs]; p.oy = b[P_OY * fs]; p.oz = b[P_OZ * fs];
+  p.m = b[P_M * fs];
+  p.hx = b[P_HX * fs]; p.hy = b[P_HY * fs]; p.hz = b[P_HZ * fs];
+  p.ixx = b[P_IXX * fs]; p.iyy = b[P_IYY * fs]; p.izz = b[P_IZZ * fs];
+  p.ixy = b[P_IXY * fs]; p.ixz = b[P_IXZ * fs]; p.iyz = b[P_IYZ * fs];
+  p.kp = b[P_KP * fs]; p.kd = b[P_KD * fs]; p.lo = b[P_LO * fs]; p.hi = b[P_HI * fs];
+}
+
+// One workgroup = one wave = 64 envs, for all T steps: weights and the
+// envs' link parameters are staged in LDS once, the chain state stays in
+// VGPRs; every step runs the policy on the matrix cores, samples the action,
+// advances the physics and writes the step's rollout rows.
+template <int J>
+__global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  uint4* s_w = reinterpret_cast<uint4*>(lds);
+  float* s_b = reinterpret_cast<float*>(lds + kLdsW);
+  uint4* s_x = reinterpret_cast<uint4*>(lds + kLdsW + kLdsBias);
+  float* s_o = reinterpret_cast<float*>(lds + kLdsW + kLdsBias + kLdsX);
+  float* s_p = reinterpret_cast<float*>(lds + kLdsW + kLdsBias + kLdsX + kLdsO);
+  const EnvDev<float>& E = A.E;
+  const int lane = threadIdx.x;
+  const int e = blockIdx.x * kWave + lane;
+  const bool active = e < E.N;
+  const int n = active ? E.nd[e] : 0;
+  const int Wd = 2 * E.J + 10;
+  const size_t N = E.N;
+
+  fill_weights(s_w, s_b, A.wimg, A.bias, lane);
+  for (int f = 0; f < P_NFIELDS; ++f)
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+      s_p[(f * J + j) * kWave + lane] = (j < n) ? E.par[((size_t)f * E.J + j) * N + e] : 0.f;
+  float lstd[J], sig[J];
+  float lp_const = 0.f;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    lstd[j] = j < n ? A.log_std[j] : 0.f;
+    sig[j] = __expf(lstd[j]);
+    if (j < n) lp_const -= lstd[j] + 0.91893853320467274f;
+  }
+
+  float q[J], qd[J], x[kXMax];
+  int prog = 0;
+  Jp<float> P[J];
+  if (active) {
+    load_state<float, J>(E, e, n, q, qd);
+    prog = E.prog[e];
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+      if (j < n) load_joint(E.par, E.J, E.N, j, e, P[j]);
+    const float tipl[3] = {E.tip[e], E.tip[N + e], E.tip[2 * N + e]};
+    float tip[3], g[3];
+    tip_fk<float, J>(P, n, q, tipl, tip);
+    goal_of(E, e, prog, g);
+    obs_regs<float, J, kXMax>(E, n, q, qd, tip, g, x);
+    for (int k = 0; k < Wd; ++k) A.obs[(size_t)k * N + e] = x[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < kXMax; ++k) x[k] = 0.f;
+  }
+  __syncthreads();
+
+  for (int t = 0; t <= A.T; ++t) {
+    stage_input(s_x, lane, x, Wd);
+    __syncthreads();
+    mlp_wave(s_w, s_b, s_x, s_o, lane);
+    __syncthreads();
+    float mu[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) mu[j] = s_o[lane * kOut + j];
+    const float V = s_o[lane * kOut + E.J];
+    if (!active) continue;
+    A.val[(size_t)t * N + e] = V;
+    if (t == A.T) break;
+    float eps[J], a[J];
+    normals<J>(A.seed, (uint32_t)e, A.step0 + (uint64_t)t, n, eps);
+    float lp = lp_const;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      a[j] = j < n ? mu[j] + sig[j] * eps[j] : 0.f;
+      lp -= 0.5f * eps[j] * eps[j];
+      if (j < E.J) A.act[((size_t)t * E.J + j) * N + e] = a[j];
+    }
+    A.logp[(size_t)t * N + e] = lp;
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+      if (j < n) load_joint_lds<J>(s_p, j, lane, P[j]);
+    physics<float, J>(E, P, n, a, q, qd);
+    float r, tip[3], g[3];
+    const uint8_t d = post_step<float, J>(E, e, n, P, q, qd, prog, &r, A.obs + (size_t)(t + 1) * Wd * N, tip, g);
+    obs_regs<float, J, kXMax>(E, n, q, qd, tip, g, x);
+    A.rew[(size_t)t * N + e] = r;
+    A.done[(size_t)t * N + e] = d;
+  }
+  if (active) store_state<float, J>(E, e, n, q, qd, prog);
+}
+
+// The policy alone on n inputs x [W][n] -> out [J+1][n].
+__global__ void __launch_bounds__(kWave) k_policy(const uint4* __restrict__ wimg, const float* __restrict__ bias,
+                                                  int Wd, int n_out, int n, const float* __restrict__ xin,
+                                                  float* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  uint4* s_w = reinterpret_cast<uint4*>(lds);
+  float* s_b = reinterpret_cast<float*>(lds + kLdsW);
+  uint4* s_x = reinterpret_cast<uint4*>(lds + kLdsW + kLdsBias);
+  float* s_o = reinterpret_cast<float*>(lds + kLdsW + kLdsBias + kLdsX);
+  const int lane = threadIdx.x;
+  const int e = blockIdx.x * kWave + lane;
+  fill_weights(s_w, s_b, wimg, bias, lane);
+  float x[kXMax];
+#pragma unroll
+  for (int k = 0; k < kXMax; ++k) x[k] = (e < n && k < Wd) ? xin[(size_t)k * n + e] : 0.f;
+  stage_input(s_x, lane, x, Wd);
+  __syncthreads();
+  mlp_wave(s_w, s_b, s_x, s_o, lane);
+  __syncthreads();
+  if (e < n)
+    for (int i = 0; i < n_out; ++i) out[(size_t)i * n + e] = s_o[lane * kOut + i];
+}
+
+// One lane per env walks t = T-1 .. 0; each step reads one coalesced row of
+// rew / val / done and writes one row of adv / ret (HBM-bound).
+// delta_t = r_t + gamma V_{t+1} (1 - d_t) - V_t with r_t += gamma V_t on a
+// time-out; A_t = delta_t + gamma lam (1 - d_t) A_{t+1}; R_t = A_t + V_t.
+__global__ void __launch_bounds__(256) k_gae(int T, int n, const float* __restrict__ rew,
+                                             const float* __restrict__ val, const uint8_t* __restrict__ done,
+                                             float gamma, float lam, float* __restrict__ adv,
+                                             float* __restrict__ ret) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  float A = 0.f;
+  float vnext = val[(size_t)T * n + e];
+  for (int t = T - 1; t >= 0; --t) {
+    const size_t i = (size_t)t * n + e;
+    const uint8_t d = done[i];
+    const float v = val[i];
+    const float nd = (d & DONE_ENDED) ? 0.f : 1.f;
+    const float r = rew[i] + ((d & DONE_TIMEOUT) ? gamma * v : 0.f);
+    const float delta = r + gamma * vnext * nd - v;
+    A = delta + gamma * lam * nd * A;
+    adv[i] = A;
+    ret[i] = A + v;
+    vnext = v;
+  }
+}
+
+hipError_t launch_gae(hipStream_t s, int T, int n, const float* rew, const float* val, const uint8_t* done,
+                      float gamma, float lam, float* adv, float* ret) {
+  k_gae<<<dim3((n + 255) / 256), 256, 0, s>>>(T, n, rew, val, done, gamma, lam, adv, ret);
+  return hipGetLastError();
+}
+
+hipError_t launch_policy_forward(const sg_ctx* c, const float* x, int n, float* out) {
+  const size_t lds = kLdsW + kLdsBias + kLdsX + kLdsO;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_policy, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  k_policy<<<dim3((n + kWave - 1) / kWave), kWave, lds, c->stream>>>(
+      reinterpret_cast<const uint4*>(c->w_bf16), c->bias, 2 * c->J + 10, c->J + 1, n, x, out);
+  return hipGetLastError();
+}
+
+template <int J> static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_bufs* b) {
+  const size_t lds = rollout_lds_bytes<J>();
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_rollout<J>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  RollArgs A;
+  A.E = env_view<float>(c);
+  A.wimg = reinterpret_cast<const uint4*>(c->w_bf16);
+  A.bias = c->bias;
+  A.log_std = c->log_std;
+  A.T = T;
+  A.seed = c->seed;
+  A.step0 = c->rng_step;
+  A.obs = b->obs; A.act = b->act; A.logp = b->logp; A.rew = b->rew; A.done = b->done; A.val = b->val;
+  k_rollout<J><<<dim3((c->N + kWave - 1) / kWave), kWave, lds, c->stream>>>(A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  c->rng_step += (uint64_t)T;
+  return launch_gae(c->stream, T, c->N, b->rew, b->val, b->done, b->gamma, b->lam, b->adv, b->ret);
+}
+
+hipError_t launch_rollout(sg_ctx* c, int T, const sg_rollout_bufs* b) {
+  switch (dof_bucket(c->J)) {
+    case 1: return rollout_j<1>(c, T, b);
+    case 2: return rollout_j<2>(c, T, b);
+    case 4: return rollout_j<4>(c, T, b);
+    default: return rollout_j<7>(c, T, b);
+  }
+}
+
+}  // namespace sgk
