@@ -6,8 +6,11 @@ Tolerances:
   FP32 inputs: the GPU accumulates in FP32 and its tanh differs from the
   exact one by ~1e-7, so a hidden activation can round to the neighbouring
   BF16 value; one such flip moves an output by at most |w| * 2^-8 * |h| with
-  |w| <= 1/sqrt(fan_in), i.e. ~4e-4. Bound: |d out| <= 2e-3 everywhere,
-  median <= 2e-5, and at most 1 % of outputs above 1e-4.
+  |w| <= 1/sqrt(fan_in), i.e. ~4e-4. A pre-activation's FP32 error
+  (~1e-7) makes a flip at one activation about 5e-5 likely, and each output
+  depends on 384 hidden activations, so ~2 % of outputs carry one flip.
+  Bound: |d out| <= 2e-3 everywhere, median <= 2e-5, at most 5 % of outputs
+  above 1e-4.
 * log-density, GAE: relative 1e-5 (FP32 accumulation).
 * env step inside the rollout, replayed by the oracle from the stored
   observation (which holds q and qd exactly): as in the step tests.
@@ -29,7 +32,7 @@ def check_policy_outputs(g, ref):
     d = np.abs(g - ref)
     assert d.max() <= 2e-3, d.max()
     assert np.median(d) <= 2e-5, np.median(d)
-    assert (d > 1e-4).mean() <= 0.01, (d > 1e-4).mean()
+    assert (d > 1e-4).mean() <= 0.05, (d > 1e-4).mean()
 
 
 @pytest.mark.parametrize("n", [1, 64, 100, 1000])
