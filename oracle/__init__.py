@@ -197,6 +197,80 @@ class Oracle:
                     ret=ret)
 
 
+class _Surrogate(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("dims", _ip), ("W", C.POINTER(_dp)), ("b", C.POINTER(_dp)),
+                ("mu_x", _dp), ("sd_x", _dp), ("mu_y", _dp), ("sd_y", _dp)]
+
+
+class SurrogateRef:
+    """FP64 reference of the learned forward-dynamics surrogate: ELU MLP on
+    z-scored features, MSE loss on z-scored targets, chain-rule gradients,
+    Adam. W[l] is [out][in], b[l] [out]; norm = (mu_x, sd_x, mu_y, sd_y)."""
+
+    def __init__(self, W, b, norm):
+        self.set(W, b, norm)
+
+    def set(self, W, b, norm):
+        self.Ws = [_f64(w) for w in W]
+        self.bs = [_f64(x) for x in b]
+        self.norm = [_f64(x) for x in norm]
+        self.dims = np.array([self.Ws[0].shape[1]] + [w.shape[0] for w in self.Ws], dtype=np.int32)
+        L = len(self.Ws)
+        self._Wp = (_dp * L)(*[_ptr(w) for w in self.Ws])
+        self._bp = (_dp * L)(*[_ptr(x) for x in self.bs])
+        self.s = _Surrogate(L, _ptr(self.dims, _ip), C.cast(self._Wp, C.POINTER(_dp)), C.cast(self._bp, C.POINTER(_dp)),
+                            *[_ptr(x) for x in self.norm])
+
+    def forward(self, x_raw, emulate=False):
+        B = x_raw.shape[1]
+        out = np.zeros((self.dims[-1], B))
+        outn = np.zeros((self.dims[-1], B))
+        lib().ora_surrogate_forward(C.byref(self.s), _ptr(_f64(x_raw)), C.c_int(B), C.c_int(int(emulate)), _ptr(out),
+                                    _ptr(outn))
+        return out, outn
+
+    def grad(self, x_raw, target, emulate=False):
+        B = x_raw.shape[1]
+        gW = np.zeros(sum(w.size for w in self.Ws))
+        gb = np.zeros(sum(x.size for x in self.bs))
+        f = lib().ora_surrogate_grad
+        f.restype = C.c_double
+        loss = f(C.byref(self.s), _ptr(_f64(x_raw)), _ptr(_f64(target)), C.c_int(B), C.c_int(int(emulate)), _ptr(gW),
+                 _ptr(gb))
+        outW, outb, ow, ob = [], [], 0, 0
+        for w, x in zip(self.Ws, self.bs):
+            outW.append(gW[ow:ow + w.size].reshape(w.shape))
+            outb.append(gb[ob:ob + x.size])
+            ow += w.size
+            ob += x.size
+        return loss, outW, outb
+
+
+def surrogate_features(orc, q, qd, tau, env):
+    """Raw features [13 J][B] of samples (q, qd, tau [J][B]) of envs env[B]."""
+    B = q.shape[1]
+    x = np.zeros((13 * orc.J, B))
+    e = np.ascontiguousarray(env, dtype=np.int32)
+    lib().ora_surrogate_features(C.byref(orc.r), _ptr(_f64(q)), _ptr(_f64(qd)), _ptr(_f64(tau)), _ptr(e, _ip),
+                                 C.c_int(B), _ptr(x))
+    return x
+
+
+def adam(w, g, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+    w, m, v = _f64(w).copy(), _f64(m).copy(), _f64(v).copy()
+    lib().ora_adam(C.c_int(w.size), _ptr(w), _ptr(_f64(g)), _ptr(m), _ptr(v), C.c_double(lr), C.c_double(beta1),
+                   C.c_double(beta2), C.c_double(eps), C.c_int(t))
+    return w, m, v
+
+
+def residual(orc, q, qd, tau, qdd_hat, arm=None):
+    rel = np.zeros(orc.N)
+    a = None if arm is None else _f64(arm)
+    lib().ora_residual(C.byref(orc.r), _ptr(_f64(q)), _ptr(_f64(qd)), _ptr(_f64(tau)), _ptr(_f64(qdd_hat)), _ptr(a),
+                       _ptr(rel))
+    return rel
+
+
 def philox4x32_10(ctr, key):
     c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
     k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])

@@ -429,3 +429,155 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
 }
 
 }  // extern "C"
+
+// ---- learned surrogate ----------------------------------------------------
+#include "surrogate.hpp"
+
+extern "C" {
+
+typedef struct {
+  int32_t n_layers;
+  const int32_t* dims;        // n_layers + 1
+  const double* const* W;     // per layer [dims[l+1]][dims[l]]
+  const double* const* b;     // per layer [dims[l+1]]
+  const double* mu_x;         // [dims[0]] input normalisation
+  const double* sd_x;
+  const double* mu_y;         // [dims[L]] output normalisation
+  const double* sd_y;
+} ora_surrogate;
+
+}  // extern "C"
+
+namespace {
+
+SurrogateNet make_net(const ora_surrogate* s) {
+  SurrogateNet n;
+  n.n_layers = s->n_layers;
+  n.dims.assign(s->dims, s->dims + s->n_layers + 1);
+  n.W.assign(s->W, s->W + s->n_layers);
+  n.b.assign(s->b, s->b + s->n_layers);
+  return n;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Raw surrogate features of samples with robot env ids env[B]:
+// x [3J + 10J][B] = q, qd, tau (J each), then per joint j the standard
+// inertial parameters (m, m c, I about the link origin: xx yy zz xy xz yz).
+int ora_surrogate_features(const ora_robot* r, const double* q, const double* qd, const double* tau,
+                           const int32_t* env, int B, double* x) {
+  const int J = r->max_dof;
+  const int F = 13 * J;
+  for (int s = 0; s < B; ++s) {
+    const int e = env[s];
+    Chain<double> ch = load_chain<double>(r, e);
+    for (int f = 0; f < F; ++f) x[(size_t)f * B + s] = 0.0;
+    for (int j = 0; j < ch.n; ++j) {
+      x[(size_t)j * B + s] = q[(size_t)j * B + s];
+      x[(size_t)(J + j) * B + s] = qd[(size_t)j * B + s];
+      x[(size_t)(2 * J + j) * B + s] = tau[(size_t)j * B + s];
+      const Link<double>& l = ch.L[j];
+      const double m = l.mass;
+      const V3<double> c = l.com;
+      const double c2 = dot(c, c);
+      const double p[10] = {m, m * c.x, m * c.y, m * c.z,
+                            l.Ic.m[0][0] + m * (c2 - c.x * c.x), l.Ic.m[1][1] + m * (c2 - c.y * c.y),
+                            l.Ic.m[2][2] + m * (c2 - c.z * c.z), l.Ic.m[0][1] - m * c.x * c.y,
+                            l.Ic.m[0][2] - m * c.x * c.z, l.Ic.m[1][2] - m * c.y * c.z};
+      for (int k = 0; k < 10; ++k) x[(size_t)(3 * J + 10 * j + k) * B + s] = p[k];
+    }
+  }
+  return 0;
+}
+
+// Normalised forward: out [dims[L]][B] denormalised prediction. If
+// out_norm is non-null it receives the normalised network output.
+int ora_surrogate_forward(const ora_surrogate* s, const double* x_raw, int B, int emulate, double* out,
+                          double* out_norm) {
+  SurrogateNet net = make_net(s);
+  const int F = net.dims[0], O = net.dims[net.n_layers];
+  std::vector<double> x(F), y(O);
+  std::vector<std::vector<double>> acts, pre;
+  for (int b = 0; b < B; ++b) {
+    for (int f = 0; f < F; ++f) x[f] = (x_raw[(size_t)f * B + b] - s->mu_x[f]) / s->sd_x[f];
+    surrogate_forward(net, x.data(), emulate != 0, acts, pre, y.data());
+    for (int i = 0; i < O; ++i) {
+      if (out_norm) out_norm[(size_t)i * B + b] = y[i];
+      out[(size_t)i * B + b] = y[i] * s->sd_y[i] + s->mu_y[i];
+    }
+  }
+  return 0;
+}
+
+// Mean squared error on normalised targets and its gradients (concatenated
+// per layer into gW [sum dims[l+1]*dims[l]], gb [sum dims[l+1]]). target
+// [O][B] raw accelerations. Returns the loss.
+double ora_surrogate_grad(const ora_surrogate* s, const double* x_raw, const double* target, int B, int emulate,
+                          double* gW_all, double* gb_all) {
+  SurrogateNet net = make_net(s);
+  const int L = net.n_layers, F = net.dims[0], O = net.dims[L];
+  std::vector<std::vector<double>> gW(L), gb(L);
+  for (int l = 0; l < L; ++l) {
+    gW[l].assign((size_t)net.dims[l + 1] * net.dims[l], 0.0);
+    gb[l].assign(net.dims[l + 1], 0.0);
+  }
+  std::vector<double> x(F), y(O), dy(O);
+  std::vector<std::vector<double>> acts, pre;
+  double loss = 0.0;
+  const double scale = 1.0 / ((double)B * O);
+  for (int b = 0; b < B; ++b) {
+    for (int f = 0; f < F; ++f) x[f] = (x_raw[(size_t)f * B + b] - s->mu_x[f]) / s->sd_x[f];
+    surrogate_forward(net, x.data(), emulate != 0, acts, pre, y.data());
+    for (int i = 0; i < O; ++i) {
+      const double t = (target[(size_t)i * B + b] - s->mu_y[i]) / s->sd_y[i];
+      const double d = y[i] - t;
+      loss += d * d * scale;
+      dy[i] = 2.0 * d * scale;
+    }
+    surrogate_backward(net, acts, pre, dy.data(), emulate != 0, gW, gb);
+  }
+  size_t ow = 0, ob = 0;
+  for (int l = 0; l < L; ++l) {
+    for (size_t i = 0; i < gW[l].size(); ++i) gW_all[ow + i] = gW[l][i];
+    for (size_t i = 0; i < gb[l].size(); ++i) gb_all[ob + i] = gb[l][i];
+    ow += gW[l].size();
+    ob += gb[l].size();
+  }
+  return loss;
+}
+
+int ora_adam(int n, double* w, const double* g, double* m, double* v, double lr, double beta1, double beta2,
+             double eps, int t) {
+  adam_update(n, w, g, m, v, lr, beta1, beta2, eps, t);
+  return 0;
+}
+
+// Residual check of a predicted acceleration: rel[e] = |RNEA(q, qd, qdd_hat)
+// + arm qdd_hat - tau| / max(|tau|, 1e-3). arm may be null (zero).
+int ora_residual(const ora_robot* r, const double* q, const double* qd, const double* tau, const double* qdd_hat,
+                 const double* arm, double* rel) {
+  const int N = r->n_env, J = r->max_dof;
+  for (int e = 0; e < N; ++e) {
+    Chain<double> ch = load_chain<double>(r, e);
+    const int n = ch.n;
+    double qe[kMaxDof], qde[kMaxDof], te[kMaxDof], ae[kMaxDof] = {0}, he[kMaxDof], id[kMaxDof];
+    gather(q, J, N, e, n, qe);
+    gather(qd, J, N, e, n, qde);
+    gather(tau, J, N, e, n, te);
+    gather(qdd_hat, J, N, e, n, he);
+    if (arm) gather(arm, J, N, e, n, ae);
+    rnea(ch, qe, qde, he, id);
+    double rr = 0.0, tt = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double d = id[j] + ae[j] * he[j] - te[j];
+      rr += d * d;
+      tt += te[j] * te[j];
+    }
+    rel[e] = std::sqrt(rr) / std::max(std::sqrt(tt), 1e-3);
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -290,6 +290,23 @@ def mixed_dof(n_env: int = 16384, seed: int = 1003, dtype=np.float32) -> Workloa
     return Workload("mixed_dof", _round_robot(r, dtype), _round_task(t, dtype), None, dtype, seed)
 
 
+def surrogate_init(seed: int, dims=(91, 256, 256, 256, 7)):
+    """Initial FP32 master weights of the surrogate network:
+    W U(+-1/sqrt(fan_in)) [out][in], b zero."""
+    Ws, bs = [], []
+    for l in range(len(dims) - 1):
+        bound = 1.0 / np.sqrt(dims[l])
+        Ws.append(stream(seed, f"sW{l}").uniform(-bound, bound, size=(dims[l + 1], dims[l])).astype(np.float32))
+        bs.append(np.zeros(dims[l + 1], dtype=np.float32))
+    return Ws, bs
+
+
+def surrogate_torques(seed: int, n: int, J: int, sigma: float = 20.0, tag: str = "tau") -> np.ndarray:
+    """Joint torques tau ~ N(0, sigma^2) [J][n], FP32 values."""
+    t = stream(seed, tag).normal(0.0, sigma, size=(n, J)).T.copy()
+    return t.astype(np.float32).astype(np.float64)
+
+
 def random_actions(seed: int, n_env: int, J: int, dtype=np.float64, tag: str = "actions") -> np.ndarray:
     """Actions a ~ U(-1, 1) [J][N] (the paper's random-action benchmark input)."""
     a = _per_env(seed, tag, n_env, J, -1.0, 1.0).T.copy()
