@@ -213,6 +213,60 @@ sg_status sg_rollout(sg_ctx* ctx, int32_t T, const sg_rollout_bufs* bufs);
 sg_status sg_gae(sg_ctx* ctx, int32_t T, int32_t n, const float* rew, const float* val, const uint8_t* done,
                  float gamma, float lam, float* adv, float* ret);
 
+/* ---- learned forward-dynamics surrogate -------------------------------
+ * An ELU MLP 13J -> 256 -> 256 -> 256 -> J (J <= 7, FP32 contexts) predicts
+ * the implicit-PD substep's joint accelerations from q, qd, tau~ and the 10
+ * standard inertial parameters of every link (m, m c, rotational inertia
+ * about the link origin xx yy zz xy xz yz), with z-scored inputs and
+ * outputs. Matrix products use BF16 operands and FP32 accumulation on the
+ * matrix cores; training keeps FP32 master weights (Adam). A prediction is
+ * accepted when |RNEA(q, qd, qdd_hat) + arm qdd_hat - tau~| /
+ * max(|tau~|, 1e-3) <= threshold, else the env is solved exactly (ABA).
+ * Training samples are device arrays q, qd, tau, qdd [J][n_total] float32 and
+ * env [n_total] int32 (the context env whose link parameters apply); a batch
+ * selects rows idx [batch] (NULL: the first batch rows). */
+typedef struct sg_surrogate sg_surrogate;
+
+/* Create a surrogate bound to ctx (its link parameters, stream and state);
+ * max_batch bounds training batches (1..4M). */
+sg_status sg_surrogate_create(sg_ctx* ctx, int32_t max_batch, sg_surrogate** out);
+void sg_surrogate_destroy(sg_surrogate* s);
+
+/* HOST float32 parameters packed per layer as W [out][in] row-major then
+ * b [out] (sizes 13J, 256, 256, 256, J); norm: HOST float32
+ * mu_x[13J] sd_x[13J] mu_y[J] sd_y[J], or NULL to keep the current one.
+ * Resets the Adam state. */
+sg_status sg_surrogate_set_params(sg_surrogate* s, const float* params, const float* norm);
+sg_status sg_surrogate_get_params(sg_surrogate* s, float* params, float* norm);
+
+/* Fit the normalisation (mean, std per input feature and output) to n
+ * samples (device arrays as above). */
+sg_status sg_surrogate_fit_norm(sg_surrogate* s, const float* q, const float* qd, const float* tau, const int32_t* env,
+                                const float* qdd, int32_t n);
+
+/* Mean squared error on normalised targets over a batch and its gradient
+ * (device float32, packed like the parameters); loss: device float. */
+sg_status sg_surrogate_grad(sg_surrogate* s, const float* q, const float* qd, const float* tau, const int32_t* env,
+                            const float* qdd, int32_t n_total, const int32_t* idx, int32_t batch, float* grad,
+                            float* loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on a
+ * batch; loss (device float, may be NULL) receives the batch loss. */
+sg_status sg_surrogate_train_step(sg_surrogate* s, const float* q, const float* qd, const float* tau,
+                                  const int32_t* env, const float* qdd, int32_t n_total, const int32_t* idx,
+                                  int32_t batch, float lr, float* loss);
+
+/* Predicted accelerations qdd_hat [J][n] (device) for n samples. */
+sg_status sg_surrogate_predict(sg_surrogate* s, const float* q, const float* qd, const float* tau, const int32_t* env,
+                               int32_t n, float* qdd_hat);
+
+/* One control step of the bound context (same contract as sg_step) with the
+ * surrogate in every substep and the exact solve for the envs whose
+ * residual exceeds threshold; n_fallback: device int32 [substeps] (may be
+ * NULL) receives the number of exact solves per substep. */
+sg_status sg_surrogate_step(sg_surrogate* s, const float* actions, float* obs, float* reward, uint8_t* done,
+                            float threshold, int32_t* n_fallback);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,6 +69,18 @@ lib.sg_rollout.argtypes = [_vp, C.c_int32, C.POINTER(RolloutBufs)]
 lib.sg_gae.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_float, C.c_float, _vp, _vp]
 
 
+lib.sg_surrogate_create.argtypes = [_vp, C.c_int32, C.POINTER(_vp)]
+lib.sg_surrogate_destroy.argtypes = [_vp]
+lib.sg_surrogate_destroy.restype = None
+lib.sg_surrogate_set_params.argtypes = [_vp, _vp, _vp]
+lib.sg_surrogate_get_params.argtypes = [_vp, _vp, _vp]
+lib.sg_surrogate_fit_norm.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int32]
+lib.sg_surrogate_grad.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_int32, _vp, _vp]
+lib.sg_surrogate_train_step.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, C.c_int32, C.c_float, _vp]
+lib.sg_surrogate_predict.argtypes = [_vp, _vp, _vp, _vp, _vp, C.c_int32, _vp]
+lib.sg_surrogate_step.argtypes = [_vp, _vp, _vp, _vp, _vp, C.c_float, _vp]
+
+
 class SgError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"status {status}: {msg}")
@@ -87,11 +99,15 @@ def _ptr(a, t=_dp):
     return None if a is None else a.ctypes.data_as(t)
 
 
-def _dptr(t):
-    """Device pointer of a contiguous torch tensor (None passes through)."""
+def _dptr(t, dtype=None):
+    """Device pointer of a contiguous torch tensor (None passes through);
+    with dtype given, the tensor must have exactly that element type."""
     if t is None:
         return None
-    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    if not (t.is_cuda and t.is_contiguous()):
+        raise TypeError("expected a contiguous device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected a {dtype} tensor, got {t.dtype}")
     return t.data_ptr()
 
 
@@ -170,12 +186,13 @@ class Sim:
         obs = self._empty(self.W, self.N) if obs is None else obs
         reward = self._empty(self.N) if reward is None else reward
         done = self._empty(self.N, dtype=self.torch.uint8) if done is None else done
-        self._call(lib.sg_step, _dptr(actions), _dptr(obs), _dptr(reward), _dptr(done))
+        td, u8 = self.tdtype, self.torch.uint8
+        self._call(lib.sg_step, _dptr(actions, td), _dptr(obs, td), _dptr(reward, td), _dptr(done, u8))
         return obs, reward, done
 
     def observe(self, obs=None):
         obs = self._empty(self.W, self.N) if obs is None else obs
-        self._call(lib.sg_observe, _dptr(obs))
+        self._call(lib.sg_observe, _dptr(obs, self.tdtype))
         return obs
 
     def get_state(self):
@@ -187,21 +204,26 @@ class Sim:
         return q, qd, pr, rs.value
 
     def set_state(self, q=None, qd=None, progress=None, rng_step=0):
-        self._call(lib.sg_set_state, _dptr(q), _dptr(qd), _dptr(progress), C.c_uint64(rng_step))
+        td = self.tdtype
+        self._call(lib.sg_set_state, _dptr(q, td), _dptr(qd, td), _dptr(progress, self.torch.int32),
+                   C.c_uint64(rng_step))
 
     def forward_dynamics(self, q, qd, tau, arm_mode=SG_ARM_DRIVE, out=None):
         out = self._empty(self.J, self.N) if out is None else out
-        self._call(lib.sg_forward_dynamics, _dptr(q), _dptr(qd), _dptr(tau), C.c_int32(arm_mode), _dptr(out))
+        td = self.tdtype
+        self._call(lib.sg_forward_dynamics, _dptr(q, td), _dptr(qd, td), _dptr(tau, td), C.c_int32(arm_mode),
+                   _dptr(out, td))
         return out
 
     def inverse_dynamics(self, q, qd, qdd, out=None):
         out = self._empty(self.J, self.N) if out is None else out
-        self._call(lib.sg_inverse_dynamics, _dptr(q), _dptr(qd), _dptr(qdd), _dptr(out))
+        td = self.tdtype
+        self._call(lib.sg_inverse_dynamics, _dptr(q, td), _dptr(qd, td), _dptr(qdd, td), _dptr(out, td))
         return out
 
     def tip_position(self, q, out=None):
         out = self._empty(3, self.N) if out is None else out
-        self._call(lib.sg_tip_position, _dptr(q), _dptr(out))
+        self._call(lib.sg_tip_position, _dptr(q, self.tdtype), _dptr(out, self.tdtype))
         return out
 
     # -- learning side ----------------------------------------------------------
@@ -216,7 +238,8 @@ class Sim:
     def policy_forward(self, x, out=None):
         n = x.shape[1]
         out = self._empty(self.J + 1, n, dtype=self.torch.float32) if out is None else out
-        self._call(lib.sg_policy_forward, _dptr(x), C.c_int32(n), _dptr(out))
+        f32 = self.torch.float32
+        self._call(lib.sg_policy_forward, _dptr(x, f32), C.c_int32(n), _dptr(out, f32))
         return out
 
     def rollout_buffers(self, T):
@@ -228,7 +251,9 @@ class Sim:
 
     def rollout(self, T, bufs=None, gamma=0.99, lam=0.95):
         bufs = self.rollout_buffers(T) if bufs is None else bufs
-        rb = RolloutBufs(*[_dptr(bufs[k]) for k in ("obs", "act", "logp", "rew", "done", "val", "adv", "ret")],
+        f32, u8 = self.torch.float32, self.torch.uint8
+        rb = RolloutBufs(*[_dptr(bufs[k], u8 if k == "done" else f32)
+                           for k in ("obs", "act", "logp", "rew", "done", "val", "adv", "ret")],
                          gamma, lam)
         self._call(lib.sg_rollout, C.c_int32(T), C.byref(rb))
         return bufs
@@ -237,9 +262,114 @@ class Sim:
         T, n = rew.shape
         adv = self._empty(T, n, dtype=self.torch.float32)
         ret = self._empty(T, n, dtype=self.torch.float32)
-        self._call(lib.sg_gae, C.c_int32(T), C.c_int32(n), _dptr(rew), _dptr(val), _dptr(done), C.c_float(gamma),
-                   C.c_float(lam), _dptr(adv), _dptr(ret))
+        f32, u8 = self.torch.float32, self.torch.uint8
+        self._call(lib.sg_gae, C.c_int32(T), C.c_int32(n), _dptr(rew, f32), _dptr(val, f32), _dptr(done, u8),
+                   C.c_float(gamma), C.c_float(lam), _dptr(adv, f32), _dptr(ret, f32))
         return adv, ret
+
+
+def surrogate_dims(J):
+    return (13 * J, 256, 256, 256, J)
+
+
+def pack_params(W, b):
+    """Per layer W [out][in] then b [out], float32."""
+    return np.concatenate([np.concatenate([np.asarray(w, np.float32).ravel(), np.asarray(x, np.float32).ravel()])
+                           for w, x in zip(W, b)])
+
+
+def unpack_params(flat, dims):
+    W, b, o = [], [], 0
+    for l in range(len(dims) - 1):
+        n = dims[l + 1] * dims[l]
+        W.append(flat[o:o + n].reshape(dims[l + 1], dims[l]))
+        o += n
+        b.append(flat[o:o + dims[l + 1]])
+        o += dims[l + 1]
+    return W, b
+
+
+class Surrogate:
+    """Learned forward-dynamics surrogate bound to a Sim (``sg_surrogate``)."""
+
+    def __init__(self, sim: Sim, max_batch: int):
+        self.sim = sim
+        self.J = sim.J
+        self.dims = surrogate_dims(self.J)
+        h = _vp()
+        sim._call(lib.sg_surrogate_create, C.c_int32(max_batch), C.byref(h))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.sg_surrogate_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, fn, *args):
+        lib.sg_set_stream(self.sim.ctx, self.sim.torch.cuda.current_stream(self.sim.device).cuda_stream)
+        st = fn(self.h, *args)
+        if st != SG_OK:
+            raise SgError(st, lib.sg_last_error(self.sim.ctx).decode())
+
+    def set_params(self, W, b, norm=None):
+        p = np.ascontiguousarray(pack_params(W, b))
+        n = None if norm is None else np.ascontiguousarray(np.concatenate([np.asarray(x, np.float32) for x in norm]))
+        self._call(lib.sg_surrogate_set_params, p.ctypes.data_as(_vp), None if n is None else n.ctypes.data_as(_vp))
+
+    def get_params(self):
+        nparam = sum(self.dims[l + 1] * self.dims[l] + self.dims[l + 1] for l in range(4))
+        p = np.zeros(nparam, np.float32)
+        F, J = self.dims[0], self.J
+        n = np.zeros(2 * F + 2 * J, np.float32)
+        self._call(lib.sg_surrogate_get_params, p.ctypes.data_as(_vp), n.ctypes.data_as(_vp))
+        W, b = unpack_params(p, self.dims)
+        return W, b, (n[:F], n[F:2 * F], n[2 * F:2 * F + J], n[2 * F + J:])
+
+    def fit_norm(self, q, qd, tau, env, qdd):
+        f, i = self.sim.torch.float32, self.sim.torch.int32
+        self._call(lib.sg_surrogate_fit_norm, _dptr(q, f), _dptr(qd, f), _dptr(tau, f), _dptr(env, i), _dptr(qdd, f),
+                   C.c_int32(q.shape[1]))
+
+    def grad(self, q, qd, tau, env, qdd, idx=None, batch=None):
+        torch = self.sim.torch
+        nparam = sum(self.dims[l + 1] * self.dims[l] + self.dims[l + 1] for l in range(4))
+        g = torch.empty(nparam, dtype=torch.float32, device=self.sim.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.sim.device)
+        batch = q.shape[1] if batch is None else batch
+        f, i = torch.float32, torch.int32
+        self._call(lib.sg_surrogate_grad, _dptr(q, f), _dptr(qd, f), _dptr(tau, f), _dptr(env, i), _dptr(qdd, f),
+                   C.c_int32(q.shape[1]), _dptr(idx, i), C.c_int32(batch), _dptr(g, f), _dptr(loss, f))
+        return g, loss
+
+    def train_step(self, q, qd, tau, env, qdd, idx, lr, loss=None):
+        f, i = self.sim.torch.float32, self.sim.torch.int32
+        self._call(lib.sg_surrogate_train_step, _dptr(q, f), _dptr(qd, f), _dptr(tau, f), _dptr(env, i),
+                   _dptr(qdd, f), C.c_int32(q.shape[1]), _dptr(idx, i), C.c_int32(idx.shape[0]), C.c_float(lr),
+                   _dptr(loss, f))
+
+    def predict(self, q, qd, tau, env, out=None):
+        n = q.shape[1]
+        out = self.sim._empty(self.J, n, dtype=self.sim.torch.float32) if out is None else out
+        f, i = self.sim.torch.float32, self.sim.torch.int32
+        self._call(lib.sg_surrogate_predict, _dptr(q, f), _dptr(qd, f), _dptr(tau, f), _dptr(env, i), C.c_int32(n),
+                   _dptr(out, f))
+        return out
+
+    def step(self, actions, threshold, obs=None, reward=None, done=None, n_fallback=None):
+        s = self.sim
+        obs = s._empty(s.W, s.N) if obs is None else obs
+        reward = s._empty(s.N) if reward is None else reward
+        done = s._empty(s.N, dtype=s.torch.uint8) if done is None else done
+        f, u8 = s.torch.float32, s.torch.uint8
+        self._call(lib.sg_surrogate_step, _dptr(actions, f), _dptr(obs, f), _dptr(reward, f), _dptr(done, u8),
+                   C.c_float(threshold), _dptr(n_fallback, s.torch.int32))
+        return obs, reward, done
 
 
 def from_workload(w, device=None) -> Sim:

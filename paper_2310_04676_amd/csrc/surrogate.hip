@@ -1,0 +1,989 @@
+// Learned forward-dynamics surrogate: an ELU MLP (13J -> 256 -> 256 -> 256 ->
+// J, J <= 7) predicts the implicit-PD substep's joint accelerations from
+// (q, qd, tau~, the 10 standard inertial parameters of every link). The
+// prediction is checked by the inverse-dynamics residual
+// |RNEA(q, qd, qdd_hat) + arm qdd_hat - tau~| / max(|tau~|, 1e-3); envs
+// above the threshold go on a device-wide queue and get the exact ABA solve.
+//
+// Kernels:
+//   k_gemm      generic BF16 MFMA GEMM (LDS-staged 64x64 tiles) with fused
+//               epilogues: bias + ELU (forward), ELU' (backward data), plain
+//               (weight gradient) -- the training passes.
+//   k_feat      normalised BF16 features [B][96] of a batch.
+//   k_loss      MSE gradient on normalised targets and the loss.
+//   k_colsum    bias gradients.
+//   k_adam      Adam on the FP32 master weights + BF16 copies.
+//   k_pack      BF16 fragment image for the fused inference kernel.
+//   k_sinfer    fused inference: features -> 4 layers on the matrix cores,
+//               hidden activations in registers, weights streamed from L2.
+//   k_sstep_a/b/f  surrogate control step: inference + residual + queue,
+//               ABA on the queue, integration + episode bookkeeping.
+#include "internal.hpp"
+#include "mlp.hpp"
+
+namespace sgk {
+
+constexpr int kSF = 96;    // padded feature count (13 J <= 91)
+constexpr int kSH = 256;   // hidden width
+constexpr int kSO = 16;    // padded output count (J <= 7)
+constexpr int kSL = 4;     // weight layers
+__host__ __device__ constexpr int s_in(int l) { return l == 0 ? kSF : kSH; }
+__host__ __device__ constexpr int s_out(int l) { return l == 3 ? kSO : kSH; }
+
+__device__ __forceinline__ float elu_f(float x) { return x > 0.f ? x : __expf(x) - 1.f; }
+__device__ __forceinline__ float elu_grad_f(float z) { return z > 0.f ? 1.f : __expf(z); }
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  __bf16 b = (__bf16)x;
+  return *reinterpret_cast<uint16_t*>(&b);
+}
+__device__ __forceinline__ float bf16_val(uint16_t u) { return __uint_as_float((uint32_t)u << 16); }
+
+// ---------------------------------------------------------------------------
+// Generic GEMM: C[m][n] = sum_k A(m, k) B(k, n) (+ epilogue), BF16 inputs,
+// FP32 accumulation. A(m, k) = A[AT ? k*lda + m : m*lda + k],
+// B(k, n) = B[BT ? n*ldb + k : k*ldb + n].
+enum { EPI_FWD_HIDDEN = 0, EPI_FWD_OUT = 1, EPI_PLAIN = 2, EPI_BWD_DX = 3 };
+
+struct GemmArgs {
+  int M, N, K;
+  const uint16_t* A;
+  int lda;
+  const uint16_t* B;
+  int ldb;
+  float* C;          // fp32 output [M][ldc]
+  int ldc;
+  const float* bias; // [N] (forward)
+  uint16_t* Cb;      // bf16 output [M][ldc] (ELU(z) forward, gradient backward)
+  const float* Zp;   // pre-activations of the previous layer [M][ldc] (backward data)
+};
+
+template <int EPI, bool AT, bool BT>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  __shared__ __align__(16) uint16_t As[64][40];  // 32 k + 8 pad
+  __shared__ __align__(16) uint16_t Bs[64][40];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int gi = lane >> 4, li = lane & 15;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int lr = tid >> 2, lk = (tid & 3) * 8;  // loader: row / first k of 8
+  for (int k0 = 0; k0 < g.K; k0 += 32) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int m = m0 + lr, k = k0 + lk + s, n = n0 + lr;
+      uint16_t av = 0, bv = 0;
+      if (m < g.M && k < g.K) av = AT ? g.A[(size_t)k * g.lda + m] : g.A[(size_t)m * g.lda + k];
+      if (n < g.N && k < g.K) bv = BT ? g.B[(size_t)n * g.ldb + k] : g.B[(size_t)k * g.ldb + n];
+      As[lr][lk + s] = av;
+      Bs[lr][lk + s] = bv;
+    }
+    __syncthreads();
+    bf16x8 af[2], bfr[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      af[t] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * t + li][8 * gi]);
+      bfr[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * t + li][8 * gi]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x32(af[a], bfr[b], acc[a][b]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * a + 4 * gi + r, n = n0 + wn + 16 * b + li;
+        if (m >= g.M || n >= g.N) continue;
+        const size_t i = (size_t)m * g.ldc + n;
+        float z = acc[a][b][r];
+        if (EPI == EPI_FWD_HIDDEN || EPI == EPI_FWD_OUT) z += g.bias[n];
+        if (EPI == EPI_BWD_DX) z *= elu_grad_f(g.Zp[i]);
+        g.C[i] = z;
+        if (EPI == EPI_FWD_HIDDEN) g.Cb[i] = bf16_bits(elu_f(z));
+        if (EPI == EPI_BWD_DX) g.Cb[i] = bf16_bits(z);
+      }
+}
+
+template <int EPI, bool AT, bool BT> static void gemm(hipStream_t s, const GemmArgs& a) {
+  dim3 grid((a.N + 63) / 64, (a.M + 63) / 64);
+  k_gemm<EPI, AT, BT><<<grid, 256, 0, s>>>(a);
+}
+
+// ---------------------------------------------------------------------------
+// Features: x = (q, qd, tau, per joint [m, m c, I_O]) normalised with
+// (mu, sd); rows beyond 13 J zero. Samples: q/qd/tau/qdd [J][n_total] with
+// env ids; batch rows pick sample idx[r] (or r if idx is null).
+struct FeatArgs {
+  const float* par;   // context parameter block [P_NFIELDS][J][N]
+  const int* nd;
+  int N, J;
+  const float* q; const float* qd; const float* tau; const int* env;
+  int n_total;
+  const int* idx;
+  int B;
+  const float* norm;  // mu_x[96] sd_x[96] mu_y[16] sd_y[16]
+  uint16_t* X;        // [B][96] bf16 (normalised)
+  float* Xraw;        // optional [96][B] raw features (for the statistics)
+};
+
+__device__ __forceinline__ void raw_features(const FeatArgs& a, int s, float* x) {
+#pragma unroll 1
+  for (int f = 0; f < kSF; ++f) x[f] = 0.f;
+  // out-of-range sample or env ids give all-zero features, never a stray read
+  if (s < 0 || s >= a.n_total) return;
+  const int J = a.J, e = a.env[s];
+  if (e < 0 || e >= a.N) return;
+  const int n = a.nd[e];
+  for (int j = 0; j < J; ++j) {
+    if (j >= n) continue;
+    x[j] = a.q[(size_t)j * a.n_total + s];
+    x[J + j] = a.qd[(size_t)j * a.n_total + s];
+    x[2 * J + j] = a.tau[(size_t)j * a.n_total + s];
+    const size_t fs = (size_t)J * a.N, b = (size_t)j * a.N + e;
+    const int fld[10] = {P_M, P_HX, P_HY, P_HZ, P_IXX, P_IYY, P_IZZ, P_IXY, P_IXZ, P_IYZ};
+    for (int k = 0; k < 10; ++k) x[3 * J + 10 * j + k] = a.par[fld[k] * fs + b];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_feat(FeatArgs a) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= a.B) return;
+  const int s = a.idx ? a.idx[r] : r;
+  float x[kSF];
+  raw_features(a, s, x);
+  for (int f = 0; f < kSF; ++f) {
+    if (a.Xraw) a.Xraw[(size_t)f * a.B + r] = x[f];
+    if (a.X) {
+      const float v = f < 13 * a.J ? (x[f] - a.norm[f]) / a.norm[kSF + f] : 0.f;
+      a.X[(size_t)r * kSF + f] = bf16_bits(v);
+    }
+  }
+}
+
+// Mean and standard deviation per row of a [rows][n] array (one block per
+// row; the std floor keeps constant features finite).
+__global__ void __launch_bounds__(256) k_rowstats(const float* __restrict__ x, int n, float* mu, float* sd) {
+  __shared__ double s1[256], s2[256];
+  const int row = blockIdx.x;
+  double a = 0, b = 0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double v = x[(size_t)row * n + i];
+    a += v;
+    b += v * v;
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double m = s1[0] / n, var = s2[0] / n - m * m;
+    const double s = var > 1e-12 ? sqrt(var) : 1.0;
+    mu[row] = (float)m;
+    sd[row] = (float)s;
+  }
+}
+
+// Loss gradient on normalised targets: G = 2 (z - t) / (B J) for real
+// outputs, 0 for padding; loss += sum (z - t)^2 / (B J).
+__global__ void __launch_bounds__(256) k_loss(const float* __restrict__ Z, const float* __restrict__ qdd, int n_total,
+                                              const int* __restrict__ idx, int B, int J, const float* __restrict__ norm,
+                                              float* __restrict__ G, uint16_t* __restrict__ Gb, float* loss) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  float part = 0.f;
+  if (r < B) {
+    const int s = idx ? idx[r] : r;
+    const bool ok = s >= 0 && s < n_total;
+    const float sc = 1.f / ((float)B * (float)J);
+    for (int o = 0; o < kSO; ++o) {
+      float gval = 0.f;
+      if (o < J && ok) {
+        const float t = (qdd[(size_t)o * n_total + s] - norm[2 * kSF + o]) / norm[2 * kSF + kSO + o];
+        const float d = Z[(size_t)r * kSO + o] - t;
+        part += d * d * sc;
+        gval = 2.f * d * sc;
+      }
+      G[(size_t)r * kSO + o] = gval;
+      Gb[(size_t)r * kSO + o] = bf16_bits(gval);
+    }
+  }
+  // wave reduction, one atomic per wave
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+  if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, part);
+}
+
+// db[c] = sum_r G[r][c].
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ G, int rows, int cols, float* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += G[(size_t)r * cols + c];
+  out[c] = s;
+}
+
+// Adam (Kingma & Ba) with bias correction c1 = 1 - beta1^t, c2 = 1 - beta2^t
+// passed in; optional BF16 copy of the updated weights.
+__global__ void __launch_bounds__(256) k_adam(int n, float* __restrict__ w, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                                              float b2, float eps, float c1, float c2, uint16_t* __restrict__ wb) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  if (wb) wb[i] = bf16_bits(wi);
+}
+
+__global__ void __launch_bounds__(256) k_to_bf16(int n, const float* __restrict__ w, uint16_t* __restrict__ wb) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) wb[i] = bf16_bits(w[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Fragment image for k_sinfer. Layer l has (out/16) M-tiles x (in/32)
+// K-blocks; fragment (mt, kb) is 64 lanes x 8 bf16. Layer 0 uses natural K
+// order (its inputs are staged in that order); layers 1-3 use the permuted
+// order in which the previous layer's results sit in the lanes.
+__host__ __device__ constexpr int s_frag_off(int l) {
+  return l == 0 ? 0 : s_frag_off(l - 1) + (s_out(l - 1) / 16) * (s_in(l - 1) / 32) * 64;
+}
+constexpr int kSFrags = s_frag_off(4);
+
+__global__ void __launch_bounds__(64) k_pack(const uint16_t* __restrict__ W0, const uint16_t* __restrict__ W1,
+                                             const uint16_t* __restrict__ W2, const uint16_t* __restrict__ W3,
+                                             uint16_t* __restrict__ img) {
+  const int l = blockIdx.y, f = blockIdx.x, lane = threadIdx.x;
+  const int nkb = s_in(l) / 32, nmt = s_out(l) / 16;
+  if (f >= nmt * nkb) return;
+  const int mt = f / nkb, kb = f % nkb, g = lane >> 4, i = lane & 15;
+  const uint16_t* W = l == 0 ? W0 : l == 1 ? W1 : l == 2 ? W2 : W3;
+  uint16_t* dst = img + ((size_t)s_frag_off(l) + (size_t)f * 64 + lane) * 8;
+  for (int s = 0; s < 8; ++s) {
+    const int k = l == 0 ? 32 * kb + 8 * g + s : 32 * kb + (s < 4 ? 4 * g + s : 16 + 4 * g + (s - 4));
+    dst[s] = W[(size_t)(16 * mt + i) * s_in(l) + k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused inference for one wave of 64 samples (two passes of 32: two 16-wide
+// N-tiles each). Features are staged through LDS into B fragments; every
+// later layer takes the previous layer's D tiles straight from registers.
+struct InferWeights {
+  const uint4* img;    // fragment image
+  const float* b[4];   // biases [out]
+  const float* norm;   // mu_x sd_x mu_y sd_y
+};
+
+__device__ __forceinline__ bf16x8 pack_elu(const f32x4& lo, const f32x4& hi) {
+  bf16x8 r;
+  r[0] = (__bf16)elu_f(lo[0]); r[1] = (__bf16)elu_f(lo[1]); r[2] = (__bf16)elu_f(lo[2]); r[3] = (__bf16)elu_f(lo[3]);
+  r[4] = (__bf16)elu_f(hi[0]); r[5] = (__bf16)elu_f(hi[1]); r[6] = (__bf16)elu_f(hi[2]); r[7] = (__bf16)elu_f(hi[3]);
+  return r;
+}
+__device__ __forceinline__ bf16x8 ldfrag(const uint4* p) {
+  uint4 t = *p;
+  return *reinterpret_cast<bf16x8*>(&t);
+}
+__device__ __forceinline__ f32x4 bias4(const float* b, int row0) {
+  return f32x4{b[row0], b[row0 + 1], b[row0 + 2], b[row0 + 3]};
+}
+
+// xs: LDS [64 samples][96] bf16 staged as fragments
+// ((tile * 3 + kb) * 4 + g) * 16 + j, tile = sample / 16;
+// os: LDS [64][16] floats (normalised outputs).
+__device__ __forceinline__ void infer_wave(const InferWeights& w, const uint4* xs, float* os, int lane) {
+  const int g = lane >> 4, j = lane & 15;
+  const uint4* F0 = w.img + s_frag_off(0);
+  const uint4* F1 = w.img + s_frag_off(1);
+  const uint4* F2 = w.img + s_frag_off(2);
+  const uint4* F3 = w.img + s_frag_off(3);
+  for (int half = 0; half < 2; ++half) {
+    bf16x8 xb[2][3];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int kb = 0; kb < 3; ++kb) xb[t][kb] = ldfrag(xs + (((2 * half + t) * 3 + kb) * 4 + g) * 16 + j);
+    f32x4 acc2[16][2];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const f32x4 b = bias4(w.b[1], 16 * m + 4 * g);
+      acc2[m][0] = b;
+      acc2[m][1] = b;
+    }
+#pragma unroll 1
+    for (int kb2 = 0; kb2 < 8; ++kb2) {
+      f32x4 d[2][2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int m = 2 * kb2 + h;
+        const f32x4 b = bias4(w.b[0], 16 * m + 4 * g);
+        d[h][0] = b;
+        d[h][1] = b;
+#pragma unroll
+        for (int kb = 0; kb < 3; ++kb) {
+          const bf16x8 a = ldfrag(F0 + (m * 3 + kb) * 64 + lane);
+          d[h][0] = mfma16x16x32(a, xb[0][kb], d[h][0]);
+          d[h][1] = mfma16x16x32(a, xb[1][kb], d[h][1]);
+        }
+      }
+      const bf16x8 hb0 = pack_elu(d[0][0], d[1][0]), hb1 = pack_elu(d[0][1], d[1][1]);
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const bf16x8 a = ldfrag(F1 + (m * 8 + kb2) * 64 + lane);
+        acc2[m][0] = mfma16x16x32(a, hb0, acc2[m][0]);
+        acc2[m][1] = mfma16x16x32(a, hb1, acc2[m][1]);
+      }
+    }
+    bf16x8 h2[8][2];
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      h2[kb][0] = pack_elu(acc2[2 * kb][0], acc2[2 * kb + 1][0]);
+      h2[kb][1] = pack_elu(acc2[2 * kb][1], acc2[2 * kb + 1][1]);
+    }
+    f32x4 acc4[2];
+    acc4[0] = acc4[1] = bias4(w.b[3], 4 * g);
+#pragma unroll 1
+    for (int kb3 = 0; kb3 < 8; ++kb3) {
+      f32x4 d[2][2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int m = 2 * kb3 + h;
+        const f32x4 b = bias4(w.b[2], 16 * m + 4 * g);
+        d[h][0] = b;
+        d[h][1] = b;
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) {
+          const bf16x8 a = ldfrag(F2 + (m * 8 + kb) * 64 + lane);
+          d[h][0] = mfma16x16x32(a, h2[kb][0], d[h][0]);
+          d[h][1] = mfma16x16x32(a, h2[kb][1], d[h][1]);
+        }
+      }
+      const bf16x8 a = ldfrag(F3 + kb3 * 64 + lane);
+      acc4[0] = mfma16x16x32(a, pack_elu(d[0][0], d[1][0]), acc4[0]);
+      acc4[1] = mfma16x16x32(a, pack_elu(d[0][1], d[1][1]), acc4[1]);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int smp = 32 * half + 16 * t + j;
+      *reinterpret_cast<float4*>(os + smp * kSO + 4 * g) = make_float4(acc4[t][0], acc4[t][1], acc4[t][2], acc4[t][3]);
+    }
+  }
+}
+
+__device__ __forceinline__ void stage_features(uint4* xs, int lane, const float* x /*normalised, 96*/) {
+  const int tile = lane >> 4, j = lane & 15;
+#pragma unroll
+  for (int kb = 0; kb < 3; ++kb)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      bf16x8 v;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) v[s] = (__bf16)x[32 * kb + 8 * g + s];
+      xs[((tile * 3 + kb) * 4 + g) * 16 + j] = *reinterpret_cast<uint4*>(&v);
+    }
+}
+
+// Prediction for a batch of samples: qdd_hat [J][B] (denormalised).
+__global__ void __launch_bounds__(64) k_sinfer(FeatArgs a, InferWeights w, float* __restrict__ out) {
+  __shared__ __align__(16) uint4 xs[64 * 12];
+  __shared__ __align__(16) float os[64 * kSO];
+  const int lane = threadIdx.x, r = blockIdx.x * 64 + lane;
+  float x[kSF];
+  if (r < a.B) {
+    raw_features(a, a.idx ? a.idx[r] : r, x);
+#pragma unroll
+    for (int f = 0; f < kSF; ++f) x[f] = f < 13 * a.J ? (x[f] - a.norm[f]) / a.norm[kSF + f] : 0.f;
+  } else {
+#pragma unroll
+    for (int f = 0; f < kSF; ++f) x[f] = 0.f;
+  }
+  stage_features(xs, lane, x);
+  __syncthreads();
+  infer_wave(w, xs, os, lane);
+  __syncthreads();
+  if (r < a.B)
+    for (int o = 0; o < a.J; ++o)
+      out[(size_t)o * a.B + r] = os[lane * kSO + o] * a.norm[2 * kSF + kSO + o] + a.norm[2 * kSF + o];
+}
+
+// ---------------------------------------------------------------------------
+// Surrogate control step.
+struct SStepArgs {
+  EnvDev<float> E;
+  InferWeights w;
+  const float* act;   // [J][N]
+  float* qddbuf;      // [J][N]
+  int* count;         // [S] queue lengths
+  int* list;          // [S][N] queued env ids
+  float thresh;
+  int s;              // substep index
+};
+
+template <int J>
+__device__ __forceinline__ void drive_terms(const EnvDev<float>& E, const Jp<float> (&P)[J], int n, const float* act,
+                                            int e, const float (&q)[J], const float (&qd)[J], float (&tau)[J],
+                                            float (&arm)[J]) {
+  const float h = E.h;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < n) {
+      const float a = clamp1(act[(size_t)j * E.N + e]);
+      const float qs = 0.5f * (P[j].hi + P[j].lo) + 0.5f * (P[j].hi - P[j].lo) * a;
+      tau[j] = P[j].kp * (qs - q[j] - h * qd[j]) - P[j].kd * qd[j];
+      arm[j] = h * P[j].kd + h * h * P[j].kp;
+    } else {
+      tau[j] = 0.f;
+      arm[j] = 0.f;
+    }
+  }
+}
+
+template <int J>
+__device__ __forceinline__ void integrate(const EnvDev<float>& E, const Jp<float> (&P)[J], int n, const float* qddbuf,
+                                          int e, float (&q)[J], float (&qd)[J]) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < n) {
+      qd[j] = qd[j] + E.h * qddbuf[(size_t)j * E.N + e];
+      q[j] = q[j] + E.h * qd[j];
+      if (q[j] > P[j].hi) {
+        q[j] = P[j].hi;
+        if (qd[j] > 0.f) qd[j] = 0.f;
+      } else if (q[j] < P[j].lo) {
+        q[j] = P[j].lo;
+        if (qd[j] < 0.f) qd[j] = 0.f;
+      }
+    }
+  }
+}
+
+// (a) integrate the previous substep (s > 0), then predict qdd for this
+// substep, check the residual, queue the envs that fail.
+template <int J>
+__global__ void __launch_bounds__(64) k_sstep_a(SStepArgs A) {
+  __shared__ __align__(16) uint4 xs[64 * 12];
+  __shared__ __align__(16) float os[64 * kSO];
+  const EnvDev<float>& E = A.E;
+  const int lane = threadIdx.x, e = blockIdx.x * 64 + lane;
+  const bool active = e < E.N;
+  const int n = active ? E.nd[e] : 0;
+  Jp<float> P[J];
+  float q[J], qd[J], tau[J], arm[J];
+  float x[kSF];
+#pragma unroll
+  for (int f = 0; f < kSF; ++f) x[f] = 0.f;
+  if (active) {
+    load_chain<float, J>(E, e, n, P);
+    load_state<float, J>(E, e, n, q, qd);
+    if (A.s > 0) {
+      integrate<J>(E, P, n, A.qddbuf, e, q, qd);
+      store_state<float, J>(E, e, n, q, qd, E.prog[e]);
+    }
+    drive_terms<J>(E, P, n, A.act, e, q, qd, tau, arm);
+    const float* nm = A.w.norm;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (j < n) {
+        x[j] = (q[j] - nm[j]) / nm[kSF + j];
+        x[E.J + j] = (qd[j] - nm[E.J + j]) / nm[kSF + E.J + j];
+        x[2 * E.J + j] = (tau[j] - nm[2 * E.J + j]) / nm[kSF + 2 * E.J + j];
+        const float p[10] = {P[j].m, P[j].hx, P[j].hy, P[j].hz, P[j].ixx, P[j].iyy, P[j].izz, P[j].ixy, P[j].ixz, P[j].iyz};
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+          const int f = 3 * E.J + 10 * j + k;
+          x[f] = (p[k] - nm[f]) / nm[kSF + f];
+        }
+      }
+    }
+  }
+  stage_features(xs, lane, x);
+  __syncthreads();
+  infer_wave(A.w, xs, os, lane);
+  __syncthreads();
+  if (!active) return;
+  const float* nm = A.w.norm;
+  float qh[J], id[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) qh[j] = j < n ? os[lane * kSO + j] * nm[2 * kSF + kSO + j] + nm[2 * kSF + j] : 0.f;
+  rnea<float, J>(P, n, q, qd, qh, E.g, id);
+  float rr = 0.f, tt = 0.f;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < n) {
+      const float d = id[j] + arm[j] * qh[j] - tau[j];
+      rr += d * d;
+      tt += tau[j] * tau[j];
+      A.qddbuf[(size_t)j * E.N + e] = qh[j];
+    }
+  }
+  const float rel = sqrtf(rr) / fmaxf(sqrtf(tt), 1e-3f);
+  if (!(rel <= A.thresh)) {
+    const int slot = atomicAdd(&A.count[A.s], 1);
+    A.list[(size_t)A.s * E.N + slot] = e;
+  }
+}
+
+// (b) exact ABA for the queued envs of substep s.
+template <int J>
+__global__ void __launch_bounds__(256) k_sstep_b(SStepArgs A) {
+  const EnvDev<float>& E = A.E;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= A.count[A.s]) return;
+  const int e = A.list[(size_t)A.s * E.N + i];
+  const int n = E.nd[e];
+  Jp<float> P[J];
+  float q[J], qd[J], tau[J], arm[J], qdd[J];
+  load_chain<float, J>(E, e, n, P);
+  load_state<float, J>(E, e, n, q, qd);
+  drive_terms<J>(E, P, n, A.act, e, q, qd, tau, arm);
+  aba<float, J>(P, n, q, qd, tau, arm, E.g, qdd);
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+    if (j < n) A.qddbuf[(size_t)j * E.N + e] = qdd[j];
+}
+
+// (f) integrate the last substep, then reward / episode / observation; hand
+// the queue lengths out and clear them for the next step.
+template <int J>
+__global__ void __launch_bounds__(256) k_sstep_f(SStepArgs A, float* __restrict__ obs, float* __restrict__ rew,
+                                                 uint8_t* __restrict__ done, int* __restrict__ n_fallback) {
+  const EnvDev<float>& E = A.E;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e == 0) {
+    for (int s = 0; s < E.S; ++s) {
+      if (n_fallback) n_fallback[s] = A.count[s];
+      A.count[s] = 0;
+    }
+  }
+  if (e >= E.N) return;
+  const int n = E.nd[e];
+  Jp<float> P[J];
+  float q[J], qd[J];
+  load_chain<float, J>(E, e, n, P);
+  load_state<float, J>(E, e, n, q, qd);
+  integrate<J>(E, P, n, A.qddbuf, e, q, qd);
+  int prog = E.prog[e];
+  float r;
+  const uint8_t d = post_step<float, J>(E, e, n, P, q, qd, prog, &r, obs);
+  store_state<float, J>(E, e, n, q, qd, prog);
+  rew[e] = r;
+  done[e] = d;
+}
+
+}  // namespace sgk
+
+// ===========================================================================
+// Host side: the surrogate object and its C interface.
+using namespace sgk;
+
+struct sg_surrogate {
+  sg_ctx* ctx = nullptr;
+  int J = 0, maxB = 0, t = 0;
+  float* Wm[kSL] = {};   // FP32 master weights [out][in] (padded)
+  float* bm[kSL] = {};
+  float* mW[kSL] = {};
+  float* vW[kSL] = {};
+  float* mb[kSL] = {};
+  float* vb[kSL] = {};
+  uint16_t* Wb[kSL] = {};  // BF16 copies [out][in]
+  uint16_t* img = nullptr; // inference fragment image
+  float* norm = nullptr;   // mu_x[96] sd_x[96] mu_y[16] sd_y[16]
+  // training scratch
+  uint16_t* X[kSL] = {};   // layer inputs [B][in] bf16
+  float* Z[kSL] = {};      // pre-activations [B][out]
+  float* G = nullptr;      // gradient [B][256] fp32
+  uint16_t* Gb = nullptr;  // gradient [B][256] bf16
+  float* G2 = nullptr;
+  uint16_t* Gb2 = nullptr;
+  float* gW[kSL] = {};
+  float* gb[kSL] = {};
+  float* loss = nullptr;
+  // control step
+  float* qddbuf = nullptr;
+  int* count = nullptr;
+  int* list = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+template <typename T> hipError_t dalloc(sg_surrogate* s, T** p, size_t n) {
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T) + 16);
+  if (e == hipSuccess) {
+    s->allocs.push_back(*p);
+    e = hipMemset(*p, 0, n * sizeof(T) + 16);
+  }
+  return e;
+}
+
+sg_status sfail(sg_ctx* c, sg_status st, const char* msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+InferWeights infer_weights(const sg_surrogate* s) {
+  InferWeights w;
+  w.img = reinterpret_cast<const uint4*>(s->img);
+  for (int l = 0; l < kSL; ++l) w.b[l] = s->bm[l];
+  w.norm = s->norm;
+  return w;
+}
+
+hipError_t repack(sg_surrogate* s, hipStream_t st) {
+  for (int l = 0; l < kSL; ++l) {
+    const int n = s_out(l) * s_in(l);
+    k_to_bf16<<<(n + 255) / 256, 256, 0, st>>>(n, s->Wm[l], s->Wb[l]);
+  }
+  k_pack<<<dim3(16 * 8, kSL), 64, 0, st>>>(s->Wb[0], s->Wb[1], s->Wb[2], s->Wb[3], s->img);
+  return hipGetLastError();
+}
+
+FeatArgs feat_args(const sg_surrogate* s, const float* q, const float* qd, const float* tau, const int* env,
+                   int n_total, const int* idx, int B) {
+  FeatArgs a;
+  a.par = (const float*)s->ctx->par;
+  a.nd = s->ctx->nd;
+  a.N = s->ctx->N;
+  a.J = s->J;
+  a.q = q; a.qd = qd; a.tau = tau; a.env = env;
+  a.n_total = n_total;
+  a.idx = idx;
+  a.B = B;
+  a.norm = s->norm;
+  a.X = nullptr;
+  a.Xraw = nullptr;
+  return a;
+}
+
+// Forward (training layout) + loss + backward; gradients land in gW/gb.
+hipError_t forward_backward(sg_surrogate* s, hipStream_t st, const float* q, const float* qd, const float* tau,
+                            const int* env, const float* qdd, int n_total, const int* idx, int B) {
+  FeatArgs fa = feat_args(s, q, qd, tau, env, n_total, idx, B);
+  fa.X = s->X[0];
+  k_feat<<<(B + 255) / 256, 256, 0, st>>>(fa);
+  for (int l = 0; l < kSL; ++l) {
+    GemmArgs g{};
+    g.M = B; g.N = s_out(l); g.K = s_in(l);
+    g.A = s->X[l]; g.lda = s_in(l);
+    g.B = s->Wb[l]; g.ldb = s_in(l);
+    g.C = s->Z[l]; g.ldc = s_out(l);
+    g.bias = s->bm[l];
+    if (l < kSL - 1) {
+      g.Cb = s->X[l + 1];
+      gemm<EPI_FWD_HIDDEN, false, true>(st, g);
+    } else {
+      gemm<EPI_FWD_OUT, false, true>(st, g);
+    }
+  }
+  hipError_t e = hipMemsetAsync(s->loss, 0, sizeof(float), st);
+  if (e != hipSuccess) return e;
+  float* Gc = s->G;
+  uint16_t* Gbc = s->Gb;
+  float* Gn = s->G2;
+  uint16_t* Gbn = s->Gb2;
+  k_loss<<<(B + 255) / 256, 256, 0, st>>>(s->Z[kSL - 1], qdd, n_total, idx, B, s->J, s->norm, Gc, Gbc, s->loss);
+  for (int l = kSL - 1; l >= 0; --l) {
+    // dW[o][i] = sum_b G[b][o] X[b][i]
+    GemmArgs g{};
+    g.M = s_out(l); g.N = s_in(l); g.K = B;
+    g.A = Gbc; g.lda = s_out(l);
+    g.B = s->X[l]; g.ldb = s_in(l);
+    g.C = s->gW[l]; g.ldc = s_in(l);
+    gemm<EPI_PLAIN, true, false>(st, g);
+    k_colsum<<<(s_out(l) + 255) / 256, 256, 0, st>>>(Gc, B, s_out(l), s->gb[l]);
+    if (l == 0) break;
+    // G_prev[b][i] = (sum_o G[b][o] W[o][i]) * elu'(Z_prev[b][i])
+    GemmArgs d{};
+    d.M = B; d.N = s_in(l); d.K = s_out(l);
+    d.A = Gbc; d.lda = s_out(l);
+    d.B = s->Wb[l]; d.ldb = s_in(l);
+    d.C = Gn; d.ldc = s_in(l);
+    d.Cb = Gbn;
+    d.Zp = s->Z[l - 1];
+    gemm<EPI_BWD_DX, false, false>(st, d);
+    std::swap(Gc, Gn);
+    std::swap(Gbc, Gbn);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_surrogate_create(sg_ctx* c, int32_t max_batch, sg_surrogate** out) {
+  if (!c || !out) return SG_E_INVAL;
+  *out = nullptr;
+  if (c->dtype != SG_F32) return sfail(c, SG_E_UNSUPPORTED, "sg_surrogate_create: FP32 contexts only");
+  if (c->J > 7) return sfail(c, SG_E_UNSUPPORTED, "sg_surrogate_create: max_dof <= 7");
+  if (max_batch < 1 || max_batch > (1 << 22)) return sfail(c, SG_E_INVAL, "sg_surrogate_create: max_batch in 1..4M");
+  sg_surrogate* s = new sg_surrogate();
+  s->ctx = c;
+  s->J = c->J;
+  s->maxB = max_batch;
+  hipError_t e = hipSuccess;
+  const size_t B = (size_t)max_batch;
+  for (int l = 0; l < kSL && e == hipSuccess; ++l) {
+    const size_t nw = (size_t)s_out(l) * s_in(l), nb = s_out(l);
+    if (e == hipSuccess) e = dalloc(s, &s->Wm[l], nw);
+    if (e == hipSuccess) e = dalloc(s, &s->bm[l], nb);
+    if (e == hipSuccess) e = dalloc(s, &s->mW[l], nw);
+    if (e == hipSuccess) e = dalloc(s, &s->vW[l], nw);
+    if (e == hipSuccess) e = dalloc(s, &s->mb[l], nb);
+    if (e == hipSuccess) e = dalloc(s, &s->vb[l], nb);
+    if (e == hipSuccess) e = dalloc(s, &s->Wb[l], nw);
+    if (e == hipSuccess) e = dalloc(s, &s->gW[l], nw);
+    if (e == hipSuccess) e = dalloc(s, &s->gb[l], nb);
+    if (e == hipSuccess) e = dalloc(s, &s->X[l], B * s_in(l));
+    if (e == hipSuccess) e = dalloc(s, &s->Z[l], B * s_out(l));
+  }
+  if (e == hipSuccess) e = dalloc(s, &s->img, (size_t)kSFrags * 8);
+  if (e == hipSuccess) e = dalloc(s, &s->norm, 2 * kSF + 2 * kSO);
+  if (e == hipSuccess) e = dalloc(s, &s->G, B * kSH);
+  if (e == hipSuccess) e = dalloc(s, &s->Gb, B * kSH);
+  if (e == hipSuccess) e = dalloc(s, &s->G2, B * kSH);
+  if (e == hipSuccess) e = dalloc(s, &s->Gb2, B * kSH);
+  if (e == hipSuccess) e = dalloc(s, &s->loss, 1);
+  if (e == hipSuccess) e = dalloc(s, &s->qddbuf, (size_t)c->J * c->N);
+  if (e == hipSuccess) e = dalloc(s, &s->count, 64);
+  if (e == hipSuccess) e = dalloc(s, &s->list, (size_t)c->S * c->N);
+  if (e != hipSuccess) {
+    for (void* p : s->allocs) (void)hipFree(p);
+    delete s;
+    c->err = std::string("sg_surrogate_create: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  *out = s;
+  return SG_OK;
+}
+
+void sg_surrogate_destroy(sg_surrogate* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->ctx->stream);
+  for (void* p : s->allocs) (void)hipFree(p);
+  delete s;
+}
+
+// params: host FP32, per layer W [out][in] then b [out] with the unpadded
+// sizes (13J -> 256 -> 256 -> 256 -> J); norm: host FP32
+// mu_x[13J] sd_x[13J] mu_y[J] sd_y[J] (may be NULL to keep the current).
+sg_status sg_surrogate_set_params(sg_surrogate* s, const float* params, const float* norm) {
+  if (!s || !params) return SG_E_INVAL;
+  sg_ctx* c = s->ctx;
+  const int J = s->J, F = 13 * J;
+  const int din[kSL] = {F, kSH, kSH, kSH}, dout[kSL] = {kSH, kSH, kSH, J};
+  size_t off = 0;
+  hipError_t e = hipSuccess;
+  for (int l = 0; l < kSL && e == hipSuccess; ++l) {
+    std::vector<float> W((size_t)s_out(l) * s_in(l), 0.f), b(s_out(l), 0.f);
+    for (int o = 0; o < dout[l]; ++o)
+      for (int i = 0; i < din[l]; ++i) W[(size_t)o * s_in(l) + i] = params[off + (size_t)o * din[l] + i];
+    off += (size_t)dout[l] * din[l];
+    for (int o = 0; o < dout[l]; ++o) b[o] = params[off + o];
+    off += dout[l];
+    e = hipMemcpy(s->Wm[l], W.data(), W.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->bm[l], b.data(), b.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(s->mW[l], 0, W.size() * 4);
+    if (e == hipSuccess) e = hipMemset(s->vW[l], 0, W.size() * 4);
+    if (e == hipSuccess) e = hipMemset(s->mb[l], 0, b.size() * 4);
+    if (e == hipSuccess) e = hipMemset(s->vb[l], 0, b.size() * 4);
+  }
+  if (e == hipSuccess && norm) {
+    std::vector<float> nm(2 * kSF + 2 * kSO, 0.f);
+    for (int f = 0; f < kSF; ++f) nm[kSF + f] = 1.f;
+    for (int o = 0; o < kSO; ++o) nm[2 * kSF + kSO + o] = 1.f;
+    for (int f = 0; f < F; ++f) { nm[f] = norm[f]; nm[kSF + f] = norm[F + f]; }
+    for (int o = 0; o < J; ++o) { nm[2 * kSF + o] = norm[2 * F + o]; nm[2 * kSF + kSO + o] = norm[2 * F + J + o]; }
+    e = hipMemcpy(s->norm, nm.data(), nm.size() * 4, hipMemcpyHostToDevice);
+  }
+  s->t = 0;
+  if (e == hipSuccess) e = repack(s, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    c->err = std::string("sg_surrogate_set_params: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  return SG_OK;
+}
+
+// Copy the FP32 master parameters (same packing as set_params) and the
+// normalisation back to the host.
+sg_status sg_surrogate_get_params(sg_surrogate* s, float* params, float* norm) {
+  if (!s || !params) return SG_E_INVAL;
+  sg_ctx* c = s->ctx;
+  const int J = s->J, F = 13 * J;
+  const int din[kSL] = {F, kSH, kSH, kSH}, dout[kSL] = {kSH, kSH, kSH, J};
+  hipError_t e = hipStreamSynchronize(c->stream);
+  size_t off = 0;
+  for (int l = 0; l < kSL && e == hipSuccess; ++l) {
+    std::vector<float> W((size_t)s_out(l) * s_in(l)), b(s_out(l));
+    e = hipMemcpy(W.data(), s->Wm[l], W.size() * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(b.data(), s->bm[l], b.size() * 4, hipMemcpyDeviceToHost);
+    for (int o = 0; o < dout[l]; ++o)
+      for (int i = 0; i < din[l]; ++i) params[off + (size_t)o * din[l] + i] = W[(size_t)o * s_in(l) + i];
+    off += (size_t)dout[l] * din[l];
+    for (int o = 0; o < dout[l]; ++o) params[off + o] = b[o];
+    off += dout[l];
+  }
+  if (e == hipSuccess && norm) {
+    std::vector<float> nm(2 * kSF + 2 * kSO);
+    e = hipMemcpy(nm.data(), s->norm, nm.size() * 4, hipMemcpyDeviceToHost);
+    for (int f = 0; f < F; ++f) { norm[f] = nm[f]; norm[F + f] = nm[kSF + f]; }
+    for (int o = 0; o < J; ++o) { norm[2 * F + o] = nm[2 * kSF + o]; norm[2 * F + J + o] = nm[2 * kSF + kSO + o]; }
+  }
+  if (e != hipSuccess) {
+    c->err = std::string("sg_surrogate_get_params: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  return SG_OK;
+}
+
+// Normalisation statistics (mean, std per input feature and output) over n
+// samples: q, qd, tau, qdd [J][n] device float32, env [n] device int32.
+sg_status sg_surrogate_fit_norm(sg_surrogate* s, const float* q, const float* qd, const float* tau, const int32_t* env,
+                                const float* qdd, int32_t n) {
+  if (!s || !q || !qd || !tau || !env || !qdd || n < 2) return SG_E_INVAL;
+  sg_ctx* c = s->ctx;
+  float* xr = nullptr;
+  hipError_t e = hipMalloc((void**)&xr, (size_t)kSF * n * 4);
+  if (e != hipSuccess) return sfail(c, SG_E_NOMEM, "sg_surrogate_fit_norm: out of memory");
+  FeatArgs fa = feat_args(s, q, qd, tau, env, n, nullptr, n);
+  fa.Xraw = xr;
+  k_feat<<<(n + 255) / 256, 256, 0, c->stream>>>(fa);
+  k_rowstats<<<kSF, 256, 0, c->stream>>>(xr, n, s->norm, s->norm + kSF);
+  k_rowstats<<<s->J, 256, 0, c->stream>>>(qdd, n, s->norm + 2 * kSF, s->norm + 2 * kSF + kSO);
+  e = hipStreamSynchronize(c->stream);
+  (void)hipFree(xr);
+  if (e != hipSuccess) {
+    c->err = std::string("sg_surrogate_fit_norm: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  return SG_OK;
+}
+
+// Loss and gradients of one batch without updating: gW, gb device FP32
+// packed like set_params' parameters (unpadded); loss device float.
+sg_status sg_surrogate_grad(sg_surrogate* s, const float* q, const float* qd, const float* tau, const int32_t* env,
+                            const float* qdd, int32_t n_total, const int32_t* idx, int32_t batch, float* grad,
+                            float* loss) {
+  if (!s || !q || !qd || !tau || !env || !qdd || batch < 1 || batch > s->maxB) return SG_E_INVAL;
+  sg_ctx* c = s->ctx;
+  hipError_t e = forward_backward(s, c->stream, q, qd, tau, env, qdd, n_total, idx, batch);
+  const int J = s->J, F = 13 * J;
+  const int din[kSL] = {F, kSH, kSH, kSH}, dout[kSL] = {kSH, kSH, kSH, J};
+  size_t off = 0;
+  for (int l = 0; l < kSL && e == hipSuccess && grad; ++l) {
+    e = hipMemcpy2DAsync(grad + off, din[l] * 4, s->gW[l], s_in(l) * 4, din[l] * 4, dout[l], hipMemcpyDeviceToDevice,
+                         c->stream);
+    off += (size_t)dout[l] * din[l];
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(grad + off, s->gb[l], dout[l] * 4, hipMemcpyDeviceToDevice, c->stream);
+    off += dout[l];
+  }
+  if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, s->loss, 4, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) {
+    c->err = std::string("sg_surrogate_grad: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  return SG_OK;
+}
+
+// One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on a batch.
+sg_status sg_surrogate_train_step(sg_surrogate* s, const float* q, const float* qd, const float* tau,
+                                  const int32_t* env, const float* qdd, int32_t n_total, const int32_t* idx,
+                                  int32_t batch, float lr, float* loss) {
+  if (!s || !q || !qd || !tau || !env || !qdd || batch < 1 || batch > s->maxB || !(lr > 0))
+    return SG_E_INVAL;
+  sg_ctx* c = s->ctx;
+  hipError_t e = forward_backward(s, c->stream, q, qd, tau, env, qdd, n_total, idx, batch);
+  s->t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, (float)s->t), c2 = 1.f - powf(b2, (float)s->t);
+  for (int l = 0; l < kSL && e == hipSuccess; ++l) {
+    const int nw = s_out(l) * s_in(l), nb = s_out(l);
+    k_adam<<<(nw + 255) / 256, 256, 0, c->stream>>>(nw, s->Wm[l], s->gW[l], s->mW[l], s->vW[l], lr, b1, b2, 1e-8f, c1,
+                                                     c2, s->Wb[l]);
+    k_adam<<<(nb + 255) / 256, 256, 0, c->stream>>>(nb, s->bm[l], s->gb[l], s->mb[l], s->vb[l], lr, b1, b2, 1e-8f, c1,
+                                                     c2, nullptr);
+  }
+  if (e == hipSuccess)
+    k_pack<<<dim3(16 * 8, kSL), 64, 0, c->stream>>>(s->Wb[0], s->Wb[1], s->Wb[2], s->Wb[3], s->img);
+  if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, s->loss, 4, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    c->err = std::string("sg_surrogate_train_step: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  return SG_OK;
+}
+
+// Prediction with the fused inference kernel: qdd_hat [J][n] device.
+sg_status sg_surrogate_predict(sg_surrogate* s, const float* q, const float* qd, const float* tau, const int32_t* env,
+                               int32_t n, float* qdd_hat) {
+  if (!s || !q || !qd || !tau || !env || !qdd_hat || n < 1) return SG_E_INVAL;
+  sg_ctx* c = s->ctx;
+  FeatArgs fa = feat_args(s, q, qd, tau, env, n, nullptr, n);
+  k_sinfer<<<(n + 63) / 64, 64, 0, c->stream>>>(fa, infer_weights(s), qdd_hat);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    c->err = std::string("sg_surrogate_predict: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  return SG_OK;
+}
+
+// Control step of the context with the surrogate: per substep, predict,
+// check the residual against thresh, solve the failing envs exactly.
+// n_fallback (device int32 [S], may be NULL) receives the queue lengths.
+sg_status sg_surrogate_step(sg_surrogate* s, const float* actions, float* obs, float* reward, uint8_t* done,
+                            float thresh, int32_t* n_fallback) {
+  if (!s || !actions || !obs || !reward || !done) return SG_E_INVAL;
+  sg_ctx* c = s->ctx;
+  if (c->S > 64) return sfail(c, SG_E_UNSUPPORTED, "sg_surrogate_step: substeps <= 64");
+  SStepArgs A;
+  A.E = env_view<float>(c);
+  A.w = infer_weights(s);
+  A.act = actions;
+  A.qddbuf = s->qddbuf;
+  A.count = s->count;
+  A.list = s->list;
+  A.thresh = thresh;
+  const dim3 gw((c->N + 63) / 64), gb((c->N + 255) / 256);
+  const int b = dof_bucket(c->J);
+  for (int st = 0; st < c->S; ++st) {
+    A.s = st;
+    if (b <= 1) { k_sstep_a<1><<<gw, 64, 0, c->stream>>>(A); k_sstep_b<1><<<gb, 256, 0, c->stream>>>(A); }
+    else if (b <= 2) { k_sstep_a<2><<<gw, 64, 0, c->stream>>>(A); k_sstep_b<2><<<gb, 256, 0, c->stream>>>(A); }
+    else if (b <= 4) { k_sstep_a<4><<<gw, 64, 0, c->stream>>>(A); k_sstep_b<4><<<gb, 256, 0, c->stream>>>(A); }
+    else { k_sstep_a<7><<<gw, 64, 0, c->stream>>>(A); k_sstep_b<7><<<gb, 256, 0, c->stream>>>(A); }
+  }
+  if (b <= 1) k_sstep_f<1><<<gb, 256, 0, c->stream>>>(A, obs, reward, done, n_fallback);
+  else if (b <= 2) k_sstep_f<2><<<gb, 256, 0, c->stream>>>(A, obs, reward, done, n_fallback);
+  else if (b <= 4) k_sstep_f<4><<<gb, 256, 0, c->stream>>>(A, obs, reward, done, n_fallback);
+  else k_sstep_f<7><<<gb, 256, 0, c->stream>>>(A, obs, reward, done, n_fallback);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    c->err = std::string("sg_surrogate_step: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  return SG_OK;
+}
+
+}  // extern "C"

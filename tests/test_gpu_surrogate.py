@@ -1,0 +1,274 @@
+"""Parity of the learned-surrogate kernels against the FP64 oracle.
+
+Tolerances: the network runs BF16 operands with FP32 accumulation, the
+oracle in FP64 with the same BF16 roundings ("emulate"); FP32 accumulation
+and exp() differences (~1e-7) can flip a BF16 rounding of a hidden
+activation, moving a normalised output by ~1e-3 (weights ~1/16, activations
+~O(1), ulp 2^-8). 768 hidden activations per sample make such a flip
+likely in a few percent of samples. Bounds on normalised outputs: max 2e-2,
+median 2e-4, at most 15 % above 2e-3. Gradients: per-layer relative L2
+error <= 2e-2 and cosine >= 0.999.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _setup(sg, n_env=512, seed=7, substeps=4):
+    import torch
+    w = synth.path_rollout(n_env, substeps=substeps)
+    sim = sg.from_workload(w)
+    o = oracle.Oracle(w.robot, w.task)
+    q, qd = synth.random_states(seed, w.robot, dtype=np.float32, qd_scale=3.0)
+    tau = synth.surrogate_torques(seed, n_env, 7)
+    env = np.arange(n_env, dtype=np.int32)
+    arm = o.drive_armature()
+    qdd = o.aba(q, qd, tau, arm)
+    dev = lambda a, dt=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
+    T = dict(q=dev(q), qd=dev(qd), tau=dev(tau), env=dev(env, torch.int32), qdd=dev(qdd))
+    N = dict(q=q, qd=qd, tau=tau, env=env, qdd=qdd)
+    return w, sim, o, T, N
+
+
+def _ref_net(W, b, norm):
+    return oracle.SurrogateRef([np.asarray(x, np.float64) for x in W], [np.asarray(x, np.float64) for x in b],
+                               [np.asarray(x, np.float64) for x in norm])
+
+
+def _check_outputs(g, ref, scale=1.0):
+    d = np.abs(g - ref) / scale
+    assert d.max() <= 2e-2, d.max()
+    assert np.median(d) <= 2e-4, np.median(d)
+    assert (d > 2e-3).mean() <= 0.15, (d > 2e-3).mean()
+
+
+def test_fit_norm_and_predict_match_oracle(sg):
+    w, sim, o, T, N = _setup(sg)
+    S = sg.Surrogate(sim, 1024)
+    W, b = synth.surrogate_init(3)
+    S.set_params(W, b)
+    S.fit_norm(T["q"], T["qd"], T["tau"], T["env"], T["qdd"])
+    _, _, norm = S.get_params()
+    x = oracle.surrogate_features(o, N["q"], N["qd"], N["tau"], N["env"])
+    np.testing.assert_allclose(norm[0], x.mean(1), rtol=1e-4, atol=1e-5)
+    sd = x.std(1)
+    sd[sd < 1e-6] = 1.0
+    np.testing.assert_allclose(norm[1], sd, rtol=1e-3, atol=1e-5)
+    np.testing.assert_allclose(norm[2], N["qdd"].mean(1), rtol=1e-4, atol=1e-3)
+    np.testing.assert_allclose(norm[3], N["qdd"].std(1), rtol=1e-3)
+    g = host(S.predict(T["q"], T["qd"], T["tau"], T["env"]))
+    ref = _ref_net(W, b, norm)
+    out, outn = ref.forward(x, emulate=True)
+    gn = (g - norm[2][:, None]) / norm[3][:, None]
+    _check_outputs(gn, outn)
+    S.close()
+
+
+def test_gradients_match_oracle(sg):
+    w, sim, o, T, N = _setup(sg, n_env=384)
+    S = sg.Surrogate(sim, 1024)
+    W, b = synth.surrogate_init(5)
+    S.set_params(W, b)
+    S.fit_norm(T["q"], T["qd"], T["tau"], T["env"], T["qdd"])
+    _, _, norm = S.get_params()
+    g, loss = S.grad(T["q"], T["qd"], T["tau"], T["env"], T["qdd"])
+    gW, gb = sg.unpack_params(host(g), S.dims)
+    x = oracle.surrogate_features(o, N["q"], N["qd"], N["tau"], N["env"])
+    L, rW, rb = _ref_net(W, b, norm).grad(x, N["qdd"], emulate=True)
+    assert abs(host(loss)[0] - L) <= 1e-3 * L
+    for l in range(4):
+        for a, r in ((gW[l], rW[l]), (gb[l], rb[l])):
+            rel = np.linalg.norm(a - r) / np.linalg.norm(r)
+            cos = (a.ravel() @ r.ravel()) / (np.linalg.norm(a) * np.linalg.norm(r))
+            assert rel <= 2e-2 and cos >= 0.999, (l, rel, cos)
+    S.close()
+
+
+def test_adam_step_matches_oracle_update(sg):
+    import torch
+    w, sim, o, T, N = _setup(sg, n_env=256)
+    S = sg.Surrogate(sim, 512)
+    W, b = synth.surrogate_init(9)
+    S.set_params(W, b)
+    S.fit_norm(T["q"], T["qd"], T["tau"], T["env"], T["qdd"])
+    W0, b0, _ = S.get_params()
+    g, _ = S.grad(T["q"], T["qd"], T["tau"], T["env"], T["qdd"])
+    idx = torch.arange(256, dtype=torch.int32, device="cuda")
+    S.train_step(T["q"], T["qd"], T["tau"], T["env"], T["qdd"], idx, 1e-3)
+    W1, b1, _ = S.get_params()
+    p0 = sg.pack_params(W0, b0).astype(np.float64)
+    p1 = sg.pack_params(W1, b1).astype(np.float64)
+    ref, _, _ = oracle.adam(p0, host(g), np.zeros_like(p0), np.zeros_like(p0), 1e-3, 1)
+    np.testing.assert_allclose(p1, ref, rtol=1e-5, atol=1e-6)
+    S.close()
+
+
+def test_training_reduces_loss(sg):
+    import torch
+    w, sim, o, T, N = _setup(sg, n_env=4096, seed=11)
+    S = sg.Surrogate(sim, 1024)
+    W, b = synth.surrogate_init(13)
+    S.set_params(W, b)
+    S.fit_norm(T["q"], T["qd"], T["tau"], T["env"], T["qdd"])
+    loss = torch.zeros(1, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    losses = []
+    for it in range(300):
+        idx = torch.randint(0, 4096, (1024,), device="cuda", generator=gen, dtype=torch.int32)
+        S.train_step(T["q"], T["qd"], T["tau"], T["env"], T["qdd"], idx, 1e-3, loss)
+        if it % 50 == 0 or it == 299:
+            losses.append(float(loss.item()))
+    assert losses[-1] < 0.5 * losses[0], losses
+    S.close()
+
+
+def test_trained_surrogate_error_bound_and_gain(sg):
+    """Train on the simulator's own transitions, then (a) measure the
+    network's qdd error against the FP64 oracle on held-out samples, (b)
+    check the acceptance guarantee: a prediction whose residual is below the
+    threshold is within thr |tau| / lambda_min(H + arm) of the exact answer,
+    (c) time the surrogate step against plain ABA at 65536 envs and report
+    the ratio (no speed is asserted: the network costs ~312 k MFMA flops per
+    substep against ~3.4 k for ABA)."""
+    import json
+    import os
+    import time
+
+    import torch
+
+    from paper_2310_04676_amd import surrogate_train as st
+    wd = synth.path_rollout(4096, seed=2002)
+    simd = sg.from_workload(wd)
+    data = st.generate(simd, 400_000, seed=3)
+    tr, va = data.split(4096)
+    S = sg.Surrogate(simd, 4096)
+    W, b = synth.surrogate_init(4)
+    S.set_params(W, b)
+    S.fit_norm(tr.q, tr.qd, tr.tau, tr.env, tr.qdd)
+    hist = st.train(S, tr, epochs=4, batch=4096)
+    assert hist[-1] < hist[0]
+    pred = host(S.predict(va.q, va.qd, va.tau, va.env))
+    env = va.env.cpu().numpy()
+    rob = wd.robot
+    import dataclasses
+    sub = synth.Robot(**{f.name: (getattr(rob, f.name)[..., env] if isinstance(getattr(rob, f.name), np.ndarray)
+                                  else getattr(rob, f.name)) for f in dataclasses.fields(rob)})
+    sub.n_env = len(env)
+    osub = oracle.Oracle(sub)
+    q, qd, tau = host(va.q), host(va.qd), host(va.tau)
+    arm = osub.drive_armature()
+    ref = osub.aba(q, qd, tau, arm)
+    err = st.qdd_error(pred, ref)
+    rel = oracle.residual(osub, q, qd, tau, pred, arm)
+    thr = 1e-2
+    H = osub.crba(q)
+    ok = rel <= thr
+    for e in np.nonzero(ok)[0]:
+        lmin = np.linalg.eigvalsh(H[e] + np.diag(arm[:, e])).min()
+        bound = thr * max(np.linalg.norm(tau[:, e]), 1e-3) / lmin
+        assert np.linalg.norm(pred[:, e] - ref[:, e]) <= 1.01 * bound + 1e-3
+    Wt, bt, norm = S.get_params()
+    S.close()
+    simd.close()
+    n_env = 65536
+    w = synth.path_rollout(n_env, seed=2003)
+    sim = sg.from_workload(w)
+    S2 = sg.Surrogate(sim, 64)
+    S2.set_params(Wt, bt, norm)
+    act = torch.rand(7, n_env, device="cuda") * 2 - 1
+    nfb = torch.zeros(4, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        S2.step(act, thr, n_fallback=nfb)
+        sim.step(act)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fb = 0
+    for _ in range(5):
+        S2.step(act, thr, n_fallback=nfb)
+        fb += int(nfb.sum().item())
+    t_sur = (time.perf_counter() - t0) / 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        sim.step(act)
+    torch.cuda.synchronize()
+    t_aba = (time.perf_counter() - t0) / 5
+    report = {"train_loss": hist, "qdd_err_vs_fp64_oracle": {"median": float(np.median(err)),
+                                                            "p99": float(np.quantile(err, 0.99)),
+                                                            "max": float(err.max())},
+              "accepted_fraction_heldout": float(ok.mean()), "fallback_rate_65536": fb / (5 * 4 * n_env),
+              "env_steps_per_s_surrogate": n_env / t_sur, "env_steps_per_s_plain": n_env / t_aba,
+              "surrogate_over_plain": t_aba / t_sur}
+    print(json.dumps(report))
+    out = os.environ.get("SG_REPORT_DIR")
+    if out:
+        with open(os.path.join(out, "surrogate_gain.json"), "w") as f:
+            json.dump(report, f)
+    assert 0.0 <= report["fallback_rate_65536"] <= 1.0
+    S2.close()
+
+
+def test_surrogate_step_threshold_zero_is_the_exact_step(sg):
+    import torch
+    w, sim, o, T, N = _setup(sg, n_env=300)
+    ref = sg.from_workload(w)
+    S = sg.Surrogate(sim, 64)
+    Wt, bt = synth.surrogate_init(1)
+    S.set_params(Wt, bt)
+    S.fit_norm(T["q"], T["qd"], T["tau"], T["env"], T["qdd"])
+    nfb = torch.zeros(4, dtype=torch.int32, device="cuda")
+    for s in range(5):
+        a = torch.from_numpy(synth.random_actions(40 + s, 300, 7, np.float32)).float().cuda()
+        o1, r1, d1 = S.step(a, 0.0, n_fallback=nfb)
+        o2, r2, d2 = ref.step(a)
+        assert np.all(nfb.cpu().numpy() == 300)
+        assert np.array_equal(d1.cpu().numpy(), d2.cpu().numpy())
+        np.testing.assert_allclose(host(o1), host(o2), rtol=1e-5, atol=1e-5)
+        np.testing.assert_allclose(host(r1), host(r2), rtol=1e-5, atol=1e-6)
+    S.close()
+
+
+def test_surrogate_step_accepts_predictions_and_counts_fallbacks(sg):
+    """One substep: with an infinite threshold the step integrates the
+    network's prediction; with a finite one the fallback count equals the
+    number of envs whose oracle residual of that prediction exceeds it
+    (envs within 1e-3 of the threshold are ambiguous and skipped)."""
+    import torch
+    w, sim, o, T, N = _setup(sg, n_env=256, substeps=1)
+    S = sg.Surrogate(sim, 256)
+    Wt, bt = synth.surrogate_init(2)
+    S.set_params(Wt, bt)
+    S.fit_norm(T["q"], T["qd"], T["tau"], T["env"], T["qdd"])
+    q0, qd0, pr0, _ = sim.get_state()
+    a = synth.random_actions(77, 256, 7, np.float32)
+    at = torch.from_numpy(a).float().cuda()
+    h = w.robot.dt
+    tau = w.robot.kp * (a.clip(-1, 1) * w.robot.q_hi - host(q0) - h * host(qd0)) - w.robot.kd * host(qd0)
+    tau32 = torch.from_numpy(tau.astype(np.float32)).cuda()
+    qh = host(S.predict(q0, qd0, tau32, T["env"]))
+    nfb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _, _, done = S.step(at, float("inf"), n_fallback=nfb)
+    assert int(nfb.item()) == 0
+    q1, qd1, _, _ = sim.get_state()
+    qd_ref = host(qd0) + h * qh
+    q_ref = np.clip(host(q0) + h * qd_ref, w.robot.q_lo, w.robot.q_hi)
+    # joints inside their limits, of envs whose episode did not end (reset)
+    inside = (q_ref < w.robot.q_hi) & (q_ref > w.robot.q_lo) & (done.cpu().numpy() == 0)[None, :]
+    np.testing.assert_allclose(host(qd1)[inside], qd_ref[inside], rtol=1e-4, atol=1e-3)
+    # residual decision at a threshold in the bulk of the distribution
+    sim.set_state(q0, qd0, pr0)
+    rel = oracle.residual(o, host(q0), host(qd0), tau, qh, o.drive_armature())
+    thr = float(np.median(rel))
+    S.step(at, thr, n_fallback=nfb)
+    lo, hi = (rel > thr * (1 + 1e-3)).sum(), (rel > thr * (1 - 1e-3)).sum()
+    assert lo <= int(nfb.item()) <= hi, (lo, int(nfb.item()), hi)
+    S.close()
