@@ -87,6 +87,8 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
     return hip_fail(nullptr, he, "hipGetDevice");
   }
   c->N = N; c->J = J; c->dtype = r->dtype; c->S = r->substeps; c->dt = r->dt;
+  c->uniform = sgk::dof_bucket(J) == J;
+  for (int e = 0; e < N && c->uniform; ++e) c->uniform = r->n_dof[e] == J;
   for (int k = 0; k < 3; ++k) c->g[k] = r->gravity[k];
   c->task = t->task; c->K = t->task == SG_TASK_PATH ? t->n_waypoints : 1;
   c->dwell = t->dwell > 0 ? t->dwell : 1; c->ep_len = t->ep_len; c->seed = t->seed; c->rng_step = 0;

@@ -181,23 +181,57 @@ __device__ __forceinline__ void congruence_acc(const T* R, const Jp<T>& p, const
   for (int k = 0; k < 6; ++k) acc.C[k] += C1[k];
 }
 
+// Sources of per-joint link parameters for the dynamics below. RegPar holds
+// them in registers; LdsPar reads them from an LDS block [P_NFIELDS][J][64]
+// on every use. LdsPar::fence() re-derives the lane offset opaquely, so the
+// compiler cannot hoist the reads of one pass into registers held through
+// the next: each pass reloads what it needs instead of keeping ~20 values
+// per joint live across the whole solve.
+template <typename T, int J> struct RegPar {
+  Jp<T> P[J];
+  __device__ __forceinline__ Jp<T> get(int j) const { return P[j]; }
+  __device__ __forceinline__ void fence() {}
+};
+
+template <typename T, int J> struct LdsPar {
+  const T* sp;  // [P_NFIELDS][J][64]
+  int lane;
+  __device__ __forceinline__ void fence() { asm volatile("" : "+v"(lane)); }
+  __device__ __forceinline__ T f(int field, int j) const { return sp[(field * J + j) * 64 + lane]; }
+  __device__ __forceinline__ Jp<T> get(int j) const {
+    Jp<T> p;
+    p.ax = f(P_AX, j); p.ay = f(P_AY, j); p.az = f(P_AZ, j);
+    p.ox = f(P_OX, j); p.oy = f(P_OY, j); p.oz = f(P_OZ, j);
+    p.m = f(P_M, j);
+    p.hx = f(P_HX, j); p.hy = f(P_HY, j); p.hz = f(P_HZ, j);
+    p.ixx = f(P_IXX, j); p.iyy = f(P_IYY, j); p.izz = f(P_IZZ, j);
+    p.ixy = f(P_IXY, j); p.ixz = f(P_IXZ, j); p.iyz = f(P_IYZ, j);
+    p.kp = f(P_KP, j); p.kd = f(P_KD, j); p.lo = f(P_LO, j); p.hi = f(P_HI, j);
+    return p;
+  }
+};
+
 // Forward dynamics for one env: qdd = (H + diag(arm))^-1 (tau - C).
-// Joints j >= n are skipped. grav = base-frame gravity.
-template <typename T, int J>
-__device__ __forceinline__ void aba(const Jp<T> (&P)[J], int n, const T (&q)[J], const T (&qd)[J],
-                                    const T (&tau)[J], const T (&arm)[J], const T* grav, T (&qdd)[J]) {
-  T R[J][9], cj[J][6], pj[J][6], U[J][6], invD[J], uj[J];
+// Joints j >= n are skipped. grav = base-frame gravity. Only sin/cos of each
+// joint angle is kept between the passes; the joint rotation is rebuilt
+// where it is needed (cheaper in registers than holding 9 values per joint).
+template <typename T, int J, class PS>
+__device__ __forceinline__ void aba(PS& ps, int n, const T (&q)[J], const T (&qd)[J], const T (&tau)[J],
+                                    const T (&arm)[J], const T* grav, T (&qdd)[J]) {
+  T sn[J], cs[J], cj[J][6], pj[J][6], U[J][6], invD[J], uj[J];
   // pass 1
+  ps.fence();
   T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j < n) {
-      T s, c;
-      sc(q[j], &s, &c);
-      rodrigues(P[j], s, c, R[j]);
+      const Jp<T> p = ps.get(j);
+      sc(q[j], &sn[j], &cs[j]);
+      T R[9];
+      rodrigues(p, sn[j], cs[j], R);
       T vn[6];
-      xmotion(R[j], P[j], v, vn);
-      const T wx = P[j].ax * qd[j], wy = P[j].ay * qd[j], wz = P[j].az * qd[j];
+      xmotion(R, p, v, vn);
+      const T wx = p.ax * qd[j], wy = p.ay * qd[j], wz = p.az * qd[j];
       vn[0] += wx; vn[1] += wy; vn[2] += wz;
       // c = v x (S qd) with S qd = (wJ; 0): (w x wJ; v x wJ)
       cj[j][0] = vn[1] * wz - vn[2] * wy;
@@ -207,7 +241,7 @@ __device__ __forceinline__ void aba(const Jp<T> (&P)[J], int n, const T (&q)[J],
       cj[j][4] = vn[5] * wx - vn[3] * wz;
       cj[j][5] = vn[3] * wy - vn[4] * wx;
       T Iv[6];
-      rigid_mul(P[j], vn, Iv);
+      rigid_mul(p, vn, Iv);
       // p = v x* (I v) = (w x n + v x f; w x f)
       pj[j][0] = (vn[1] * Iv[2] - vn[2] * Iv[1]) + (vn[4] * Iv[5] - vn[5] * Iv[4]);
       pj[j][1] = (vn[2] * Iv[0] - vn[0] * Iv[2]) + (vn[5] * Iv[3] - vn[3] * Iv[5]);
@@ -220,6 +254,7 @@ __device__ __forceinline__ void aba(const Jp<T> (&P)[J], int n, const T (&q)[J],
     }
   }
   // pass 2
+  ps.fence();
   AI<T> acc;
   T accp[6];
 #pragma unroll
@@ -229,7 +264,7 @@ __device__ __forceinline__ void aba(const Jp<T> (&P)[J], int n, const T (&q)[J],
 #pragma unroll
   for (int j = J - 1; j >= 0; --j) {
     if (j < n) {
-      const Jp<T>& p = P[j];
+      const Jp<T> p = ps.get(j);
       AI<T> I;
       I.A[S00] = p.ixx + acc.A[S00]; I.A[S11] = p.iyy + acc.A[S11]; I.A[S22] = p.izz + acc.A[S22];
       I.A[S01] = p.ixy + acc.A[S01]; I.A[S02] = p.ixz + acc.A[S02]; I.A[S12] = p.iyz + acc.A[S12];
@@ -278,23 +313,29 @@ __device__ __forceinline__ void aba(const Jp<T> (&P)[J], int n, const T (&q)[J],
         for (int k = 0; k < 6; ++k) { acc.A[k] = T(0); acc.C[k] = T(0); }
 #pragma unroll
         for (int k = 0; k < 9; ++k) acc.B[k] = T(0);
-        congruence_acc(R[j], p, I, acc);
-        xforce_T(R[j], p, f, accp);
+        T R[9];
+        rodrigues(p, sn[j], cs[j], R);
+        congruence_acc(R, p, I, acc);
+        xforce_T(R, p, f, accp);
       }
     }
   }
   // pass 3
+  ps.fence();
   T a[6] = {T(0), T(0), T(0), -grav[0], -grav[1], -grav[2]};
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j < n) {
+      const Jp<T> p = ps.get(j);
+      T R[9];
+      rodrigues(p, sn[j], cs[j], R);
       T an[6];
-      xmotion(R[j], P[j], a, an);
+      xmotion(R, p, a, an);
 #pragma unroll
       for (int k = 0; k < 6; ++k) an[k] += cj[j][k];
       T dot = U[j][0] * an[0] + U[j][1] * an[1] + U[j][2] * an[2] + U[j][3] * an[3] + U[j][4] * an[4] + U[j][5] * an[5];
       qdd[j] = (uj[j] - dot) * invD[j];
-      an[0] += P[j].ax * qdd[j]; an[1] += P[j].ay * qdd[j]; an[2] += P[j].az * qdd[j];
+      an[0] += p.ax * qdd[j]; an[1] += p.ay * qdd[j]; an[2] += p.az * qdd[j];
 #pragma unroll
       for (int k = 0; k < 6; ++k) a[k] = an[k];
     } else {
@@ -304,32 +345,34 @@ __device__ __forceinline__ void aba(const Jp<T> (&P)[J], int n, const T (&q)[J],
 }
 
 // Inverse dynamics for one env: tau = H qdd + C (gravity included).
-template <typename T, int J>
-__device__ __forceinline__ void rnea(const Jp<T> (&P)[J], int n, const T (&q)[J], const T (&qd)[J],
-                                     const T (&qdd)[J], const T* grav, T (&tau)[J]) {
-  T R[J][9], f[J][6];
+template <typename T, int J, class PS>
+__device__ __forceinline__ void rnea(PS& ps, int n, const T (&q)[J], const T (&qd)[J], const T (&qdd)[J],
+                                     const T* grav, T (&tau)[J]) {
+  T sn[J], cs[J], f[J][6];
   T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
   T a[6] = {T(0), T(0), T(0), -grav[0], -grav[1], -grav[2]};
+  ps.fence();
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j < n) {
-      T s, c;
-      sc(q[j], &s, &c);
-      rodrigues(P[j], s, c, R[j]);
+      const Jp<T> p = ps.get(j);
+      sc(q[j], &sn[j], &cs[j]);
+      T R[9];
+      rodrigues(p, sn[j], cs[j], R);
       T vn[6], an[6];
-      xmotion(R[j], P[j], v, vn);
-      xmotion(R[j], P[j], a, an);
-      const T wx = P[j].ax * qd[j], wy = P[j].ay * qd[j], wz = P[j].az * qd[j];
+      xmotion(R, p, v, vn);
+      xmotion(R, p, a, an);
+      const T wx = p.ax * qd[j], wy = p.ay * qd[j], wz = p.az * qd[j];
       vn[0] += wx; vn[1] += wy; vn[2] += wz;
-      an[0] += P[j].ax * qdd[j] + (vn[1] * wz - vn[2] * wy);
-      an[1] += P[j].ay * qdd[j] + (vn[2] * wx - vn[0] * wz);
-      an[2] += P[j].az * qdd[j] + (vn[0] * wy - vn[1] * wx);
+      an[0] += p.ax * qdd[j] + (vn[1] * wz - vn[2] * wy);
+      an[1] += p.ay * qdd[j] + (vn[2] * wx - vn[0] * wz);
+      an[2] += p.az * qdd[j] + (vn[0] * wy - vn[1] * wx);
       an[3] += vn[4] * wz - vn[5] * wy;
       an[4] += vn[5] * wx - vn[3] * wz;
       an[5] += vn[3] * wy - vn[4] * wx;
       T Ia[6], Iv[6];
-      rigid_mul(P[j], an, Ia);
-      rigid_mul(P[j], vn, Iv);
+      rigid_mul(p, an, Ia);
+      rigid_mul(p, vn, Iv);
       f[j][0] = Ia[0] + (vn[1] * Iv[2] - vn[2] * Iv[1]) + (vn[4] * Iv[5] - vn[5] * Iv[4]);
       f[j][1] = Ia[1] + (vn[2] * Iv[0] - vn[0] * Iv[2]) + (vn[5] * Iv[3] - vn[3] * Iv[5]);
       f[j][2] = Ia[2] + (vn[0] * Iv[1] - vn[1] * Iv[0]) + (vn[3] * Iv[4] - vn[4] * Iv[3]);
@@ -340,15 +383,19 @@ __device__ __forceinline__ void rnea(const Jp<T> (&P)[J], int n, const T (&q)[J]
       for (int k = 0; k < 6; ++k) { v[k] = vn[k]; a[k] = an[k]; }
     }
   }
+  ps.fence();
   T fc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int j = J - 1; j >= 0; --j) {
     if (j < n) {
+      const Jp<T> p = ps.get(j);
       T ft[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) ft[k] = f[j][k] + fc[k];
-      tau[j] = P[j].ax * ft[0] + P[j].ay * ft[1] + P[j].az * ft[2];
-      xforce_T(R[j], P[j], ft, fc);
+      tau[j] = p.ax * ft[0] + p.ay * ft[1] + p.az * ft[2];
+      T R[9];
+      rodrigues(p, sn[j], cs[j], R);
+      xforce_T(R, p, ft, fc);
     } else {
       tau[j] = T(0);
     }
@@ -357,19 +404,21 @@ __device__ __forceinline__ void rnea(const Jp<T> (&P)[J], int n, const T (&q)[J]
 
 // Tool-tip position: p_j = p_{j-1} + R_{j-1} o_j, R_j = R_{j-1} Rot(a_j, q_j),
 // tip = p + R tip_local.
-template <typename T, int J>
-__device__ __forceinline__ void tip_fk(const Jp<T> (&P)[J], int n, const T (&q)[J], const T* tipl, T* out) {
+template <typename T, int J, class PS>
+__device__ __forceinline__ void tip_fk(PS& ps, int n, const T (&q)[J], const T* tipl, T* out) {
   T W[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)};
   T px = T(0), py = T(0), pz = T(0);
+  ps.fence();
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j < n) {
-      px += W[0] * P[j].ox + W[1] * P[j].oy + W[2] * P[j].oz;
-      py += W[3] * P[j].ox + W[4] * P[j].oy + W[5] * P[j].oz;
-      pz += W[6] * P[j].ox + W[7] * P[j].oy + W[8] * P[j].oz;
+      const Jp<T> p = ps.get(j);
+      px += W[0] * p.ox + W[1] * p.oy + W[2] * p.oz;
+      py += W[3] * p.ox + W[4] * p.oy + W[5] * p.oz;
+      pz += W[6] * p.ox + W[7] * p.oy + W[8] * p.oz;
       T s, c, Rj[9], Wn[9];
       sc(q[j], &s, &c);
-      rodrigues(P[j], s, c, Rj);
+      rodrigues(p, s, c, Rj);
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll

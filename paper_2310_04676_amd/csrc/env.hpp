@@ -29,12 +29,24 @@ template <typename T> struct EnvDev {
   int* prog;          // [N]
 };
 
+// Link parameters of env e into registers (joints < n).
 template <typename T, int J>
-__device__ __forceinline__ void load_chain(const EnvDev<T>& E, int e, int n, Jp<T> (&P)[J]) {
+__device__ __forceinline__ void load_chain(const EnvDev<T>& E, int e, int n, RegPar<T, J>& rp) {
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    if (j < n) load_joint(E.par, E.J, E.N, j, e, P[j]);
+    if (j < n) load_joint(E.par, E.J, E.N, j, e, rp.P[j]);
   }
+}
+
+// Stage the link parameters of a 64-env block into LDS [P_NFIELDS][J][64]
+// (joints >= n zero). Every lane of the block calls it; the caller
+// synchronizes before use.
+template <typename T, int J>
+__device__ __forceinline__ void stage_chain(const EnvDev<T>& E, int e, int n, int lane, T* sp) {
+  for (int f = 0; f < P_NFIELDS; ++f)
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+      sp[(f * J + j) * 64 + lane] = (j < n) ? E.par[((size_t)f * E.J + j) * E.N + e] : T(0);
 }
 
 template <typename T, int J>
@@ -49,31 +61,48 @@ __device__ __forceinline__ void load_state(const EnvDev<T>& E, int e, int n, T (
 template <typename T> __device__ __forceinline__ T clamp1(T a) { return a > T(1) ? T(1) : (a < T(-1) ? T(-1) : a); }
 
 // S substeps of the implicit-PD step with the action held (zero-order hold).
-template <typename T, int J>
-__device__ __forceinline__ void physics(const EnvDev<T>& E, const Jp<T> (&P)[J], int n, const T (&act)[J],
-                                        T (&q)[J], T (&qd)[J]) {
+template <typename T, int J, class PS>
+__device__ __forceinline__ void physics(const EnvDev<T>& E, PS& ps, int n, const T (&act)[J], T (&q)[J],
+                                        T (&qd)[J]) {
   const T h = E.h;
   T qs[J], arm[J], tau[J], qdd[J];
+  ps.fence();
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const T mid = T(0.5) * (P[j].hi + P[j].lo), half = T(0.5) * (P[j].hi - P[j].lo);
-    qs[j] = j < n ? mid + half * clamp1(act[j]) : T(0);
-    arm[j] = j < n ? h * P[j].kd + h * h * P[j].kp : T(0);
+    if (j < n) {
+      const Jp<T> p = ps.get(j);
+      const T mid = T(0.5) * (p.hi + p.lo), half = T(0.5) * (p.hi - p.lo);
+      qs[j] = mid + half * clamp1(act[j]);
+      arm[j] = h * p.kd + h * h * p.kp;
+    } else {
+      qs[j] = T(0);
+      arm[j] = T(0);
+    }
   }
   for (int s = 0; s < E.S; ++s) {
-#pragma unroll
-    for (int j = 0; j < J; ++j) tau[j] = j < n ? P[j].kp * (qs[j] - q[j] - h * qd[j]) - P[j].kd * qd[j] : T(0);
-    aba<T, J>(P, n, q, qd, tau, arm, E.g, qdd);
+    ps.fence();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       if (j < n) {
+        const Jp<T> p = ps.get(j);
+        tau[j] = p.kp * (qs[j] - q[j] - h * qd[j]) - p.kd * qd[j];
+      } else {
+        tau[j] = T(0);
+      }
+    }
+    aba<T, J>(ps, n, q, qd, tau, arm, E.g, qdd);
+    ps.fence();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (j < n) {
+        const Jp<T> p = ps.get(j);
         qd[j] = qd[j] + h * qdd[j];
         q[j] = q[j] + h * qd[j];
-        if (q[j] > P[j].hi) {
-          q[j] = P[j].hi;
+        if (q[j] > p.hi) {
+          q[j] = p.hi;
           if (qd[j] > T(0)) qd[j] = T(0);
-        } else if (q[j] < P[j].lo) {
-          q[j] = P[j].lo;
+        } else if (q[j] < p.lo) {
+          q[j] = p.lo;
           if (qd[j] < T(0)) qd[j] = T(0);
         }
       }
@@ -118,9 +147,6 @@ __device__ __forceinline__ void write_obs(const EnvDev<T>& E, int e, int n, cons
 
 template <typename T> __device__ __forceinline__ bool finite_(T x) { return isfinite(x); }
 
-// After the physics: reward on the post-step tip, progress, time-out or
-// non-finite reset, observation of the post-reset state, state store.
-// Returns the done bits; *reward receives the reward.
 // Observation row in registers (width 2*E.J + 10, entries beyond zero-padded
 // up to the caller's array size).
 template <typename T, int J, int WMAX>
@@ -143,13 +169,16 @@ __device__ __forceinline__ void obs_regs(const EnvDev<T>& E, int n, const T (&q)
   x[b + 9] = rsq(dx * dx + dy * dy + dz * dz);
 }
 
-template <typename T, int J>
-__device__ __forceinline__ uint8_t post_step(const EnvDev<T>& E, int e, int n, const Jp<T> (&P)[J], T (&q)[J],
-                                             T (&qd)[J], int& prog, T* reward, T* __restrict__ obs,
-                                             T* tip_out = nullptr, T* goal_out = nullptr) {
+// After the physics: reward on the post-step tip, progress, time-out or
+// non-finite reset, observation of the post-reset state. Returns the done
+// bits; *reward receives the reward.
+template <typename T, int J, class PS>
+__device__ __forceinline__ uint8_t post_step(const EnvDev<T>& E, int e, int n, PS& ps, T (&q)[J], T (&qd)[J],
+                                             int& prog, T* reward, T* __restrict__ obs, T* tip_out = nullptr,
+                                             T* goal_out = nullptr) {
   const T tipl[3] = {E.tip[e], E.tip[E.N + e], E.tip[2 * E.N + e]};
   T tip[3], g[3];
-  tip_fk<T, J>(P, n, q, tipl, tip);
+  tip_fk<T, J>(ps, n, q, tipl, tip);
   goal_of(E, e, prog, g);
   const T dx = tip[0] - g[0], dy = tip[1] - g[1], dz = tip[2] - g[2];
   T r = -rsq(dx * dx + dy * dy + dz * dz);
@@ -174,7 +203,7 @@ __device__ __forceinline__ uint8_t post_step(const EnvDev<T>& E, int e, int n, c
       }
     }
     prog = 0;
-    tip_fk<T, J>(P, n, q, tipl, tip);
+    tip_fk<T, J>(ps, n, q, tipl, tip);
   }
   goal_of(E, e, prog, g);
   if (obs) write_obs<T, J>(E, e, n, q, qd, tip, g, obs);

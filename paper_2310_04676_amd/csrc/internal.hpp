@@ -11,6 +11,7 @@
 struct sg_ctx {
   int device = 0;
   int N = 0, J = 0, dtype = SG_F32, S = 1;
+  bool uniform = false;  // every env has J joints and J is a kernel instantiation
   int task = 0, K = 0, dwell = 1, ep_len = 0;
   double dt = 0, g[3] = {0, 0, 0};
   uint64_t seed = 0, rng_step = 0;

@@ -80,24 +80,11 @@ __device__ __forceinline__ void fill_weights(uint4* sw, float* sb, const uint4* 
   for (int i = lane; i < kBiasFloats; i += kWave) sb[i] = bias[i];
 }
 
-template <int J>
-__device__ __forceinline__ void load_joint_lds(const float* sp, int j, int lane, Jp<float>& p) {
-  const float* b = sp + j * kWave + lane;
-  constexpr int fs = J * kWave;
-  p.ax = b[P_AX * fs]; p.ay = b[P_AY * fs]; p.az = b[P_AZ * fs];
-  p.ox = b[P_OX * fs]; p.oy = b[P_OY * fs]; p.oz = b[P_OZ * fs];
-  p.m = b[P_M * fs];
-  p.hx = b[P_HX * fs]; p.hy = b[P_HY * fs]; p.hz = b[P_HZ * fs];
-  p.ixx = b[P_IXX * fs]; p.iyy = b[P_IYY * fs]; p.izz = b[P_IZZ * fs];
-  p.ixy = b[P_IXY * fs]; p.ixz = b[P_IXZ * fs]; p.iyz = b[P_IYZ * fs];
-  p.kp = b[P_KP * fs]; p.kd = b[P_KD * fs]; p.lo = b[P_LO * fs]; p.hi = b[P_HI * fs];
-}
-
 // One workgroup = one wave = 64 envs, for all T steps: weights and the
 // envs' link parameters are staged in LDS once, the chain state stays in
 // VGPRs; every step runs the policy on the matrix cores, samples the action,
 // advances the physics and writes the step's rollout rows.
-template <int J>
+template <int J, bool UNI>
 __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
   extern __shared__ __align__(16) unsigned char lds[];
   uint4* s_w = reinterpret_cast<uint4*>(lds);
@@ -109,15 +96,14 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
   const int lane = threadIdx.x;
   const int e = blockIdx.x * kWave + lane;
   const bool active = e < E.N;
-  const int n = active ? E.nd[e] : 0;
+  const int n = UNI ? J : (active ? E.nd[e] : 0);
   const int Wd = 2 * E.J + 10;
   const size_t N = E.N;
 
   fill_weights(s_w, s_b, A.wimg, A.bias, lane);
-  for (int f = 0; f < P_NFIELDS; ++f)
-#pragma unroll
-    for (int j = 0; j < J; ++j)
-      s_p[(f * J + j) * kWave + lane] = (j < n) ? E.par[((size_t)f * E.J + j) * N + e] : 0.f;
+  stage_chain<float, J>(E, e, active ? n : 0, lane, s_p);
+  __syncthreads();
+  LdsPar<float, J> ps{s_p, lane};
   float lstd[J], sig[J];
   float lp_const = 0.f;
 #pragma unroll
@@ -129,16 +115,12 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
 
   float q[J], qd[J], x[kXMax];
   int prog = 0;
-  Jp<float> P[J];
   if (active) {
     load_state<float, J>(E, e, n, q, qd);
     prog = E.prog[e];
-#pragma unroll
-    for (int j = 0; j < J; ++j)
-      if (j < n) load_joint(E.par, E.J, E.N, j, e, P[j]);
     const float tipl[3] = {E.tip[e], E.tip[N + e], E.tip[2 * N + e]};
     float tip[3], g[3];
-    tip_fk<float, J>(P, n, q, tipl, tip);
+    tip_fk<float, J>(ps, n, q, tipl, tip);
     goal_of(E, e, prog, g);
     obs_regs<float, J, kXMax>(E, n, q, qd, tip, g, x);
     for (int k = 0; k < Wd; ++k) A.obs[(size_t)k * N + e] = x[k];
@@ -170,12 +152,9 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
       if (j < E.J) A.act[((size_t)t * E.J + j) * N + e] = a[j];
     }
     A.logp[(size_t)t * N + e] = lp;
-#pragma unroll
-    for (int j = 0; j < J; ++j)
-      if (j < n) load_joint_lds<J>(s_p, j, lane, P[j]);
-    physics<float, J>(E, P, n, a, q, qd);
+    physics<float, J>(E, ps, n, a, q, qd);
     float r, tip[3], g[3];
-    const uint8_t d = post_step<float, J>(E, e, n, P, q, qd, prog, &r, A.obs + (size_t)(t + 1) * Wd * N, tip, g);
+    const uint8_t d = post_step<float, J>(E, e, n, ps, q, qd, prog, &r, A.obs + (size_t)(t + 1) * Wd * N, tip, g);
     obs_regs<float, J, kXMax>(E, n, q, qd, tip, g, x);
     A.rew[(size_t)t * N + e] = r;
     A.done[(size_t)t * N + e] = d;
@@ -251,11 +230,12 @@ hipError_t launch_policy_forward(const sg_ctx* c, const float* x, int n, float* 
   return hipGetLastError();
 }
 
-template <int J> static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_bufs* b) {
+template <int J, bool UNI> static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_bufs* b) {
   const size_t lds = rollout_lds_bytes<J>();
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_rollout<J>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e =
+        hipFuncSetAttribute((const void*)k_rollout<J, UNI>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
@@ -268,7 +248,7 @@ template <int J> static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_
   A.seed = c->seed;
   A.step0 = c->rng_step;
   A.obs = b->obs; A.act = b->act; A.logp = b->logp; A.rew = b->rew; A.done = b->done; A.val = b->val;
-  k_rollout<J><<<dim3((c->N + kWave - 1) / kWave), kWave, lds, c->stream>>>(A);
+  k_rollout<J, UNI><<<dim3((c->N + kWave - 1) / kWave), kWave, lds, c->stream>>>(A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   c->rng_step += (uint64_t)T;
@@ -276,11 +256,12 @@ template <int J> static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_
 }
 
 hipError_t launch_rollout(sg_ctx* c, int T, const sg_rollout_bufs* b) {
+  const bool u = c->uniform;
   switch (dof_bucket(c->J)) {
-    case 1: return rollout_j<1>(c, T, b);
-    case 2: return rollout_j<2>(c, T, b);
-    case 4: return rollout_j<4>(c, T, b);
-    default: return rollout_j<7>(c, T, b);
+    case 1: return rollout_j<1, true>(c, T, b);
+    case 2: return u ? rollout_j<2, true>(c, T, b) : rollout_j<2, false>(c, T, b);
+    case 4: return u ? rollout_j<4, true>(c, T, b) : rollout_j<4, false>(c, T, b);
+    default: return u ? rollout_j<7, true>(c, T, b) : rollout_j<7, false>(c, T, b);
   }
 }
 

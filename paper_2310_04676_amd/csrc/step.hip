@@ -1,11 +1,13 @@
-// Environment-step kernels: one environment per lane, state and chain in
-// VGPRs, structure-of-arrays global layout so each per-joint field is one
-// coalesced 64-lane access.
+// Environment-step kernels: one environment per lane, chain state in VGPRs,
+// the block's link parameters staged in LDS ([P_NFIELDS][J][64]) and read
+// per pass, structure-of-arrays global layout so each per-joint field is one
+// coalesced 64-lane access. UNI = every env has max_dof joints (the per-joint
+// guards then fold away at compile time).
 #include "internal.hpp"
 
 namespace sgk {
 
-constexpr int kBlock = 256;
+constexpr int kBlk = 64;
 
 int dof_bucket(int J) {
   if (J <= 1) return 1;
@@ -16,75 +18,97 @@ int dof_bucket(int J) {
   return 16;
 }
 
-template <typename T, int J>
-__global__ void __launch_bounds__(kBlock) k_step(EnvDev<T> E, const T* __restrict__ act, T* __restrict__ obs,
-                                                 T* __restrict__ rew, uint8_t* __restrict__ done) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= E.N) return;
-  const int n = E.nd[e];
-  Jp<T> P[J];
+template <typename T, int J> constexpr size_t par_lds_bytes() { return sizeof(T) * P_NFIELDS * J * kBlk; }
+// LDS staging when the block's parameters fit comfortably, else registers.
+template <typename T, int J> constexpr bool use_lds() { return par_lds_bytes<T, J>() <= 96 * 1024; }
+
+// Parameter source for env e of this block: LDS-staged (after a barrier) or
+// register-held. Every lane of the block must call it (barrier inside).
+template <typename T, int J, bool LDS> struct ParOf;
+template <typename T, int J> struct ParOf<T, J, true> {
+  using type = LdsPar<T, J>;
+  static __device__ __forceinline__ type make(const EnvDev<T>& E, int e, int n, bool active, T* sp) {
+    stage_chain<T, J>(E, e, active ? n : 0, threadIdx.x, sp);
+    __syncthreads();
+    return type{sp, (int)threadIdx.x};
+  }
+};
+template <typename T, int J> struct ParOf<T, J, false> {
+  using type = RegPar<T, J>;
+  static __device__ __forceinline__ type make(const EnvDev<T>& E, int e, int n, bool active, T*) {
+    type r;
+    if (active) load_chain<T, J>(E, e, n, r);
+    return r;
+  }
+};
+
+#define SG_PAR_SETUP                                                                 \
+  extern __shared__ __align__(16) unsigned char smem_raw[];                          \
+  T* sp = reinterpret_cast<T*>(smem_raw);                                            \
+  const int e = blockIdx.x * kBlk + threadIdx.x;                                     \
+  const bool active = e < E.N;                                                       \
+  const int n = UNI ? J : (active ? E.nd[e] : 0);                                    \
+  auto ps = ParOf<T, J, use_lds<T, J>()>::make(E, e, n, active, sp);                 \
+  if (!active) return;
+
+template <typename T, int J, bool UNI>
+__global__ void __launch_bounds__(kBlk) k_step(EnvDev<T> E, const T* __restrict__ act, T* __restrict__ obs,
+                                               T* __restrict__ rew, uint8_t* __restrict__ done) {
+  SG_PAR_SETUP
   T q[J], qd[J], a[J];
-  load_chain<T, J>(E, e, n, P);
   load_state<T, J>(E, e, n, q, qd);
 #pragma unroll
   for (int j = 0; j < J; ++j) a[j] = j < n ? act[(size_t)j * E.N + e] : T(0);
-  physics<T, J>(E, P, n, a, q, qd);
+  physics<T, J>(E, ps, n, a, q, qd);
   int prog = E.prog[e];
   T r;
-  const uint8_t d = post_step<T, J>(E, e, n, P, q, qd, prog, &r, obs);
+  const uint8_t d = post_step<T, J>(E, e, n, ps, q, qd, prog, &r, obs);
   store_state<T, J>(E, e, n, q, qd, prog);
   rew[e] = r;
   done[e] = d;
 }
 
-template <typename T, int J>
-__global__ void __launch_bounds__(kBlock) k_observe(EnvDev<T> E, T* __restrict__ obs) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= E.N) return;
-  const int n = E.nd[e];
-  Jp<T> P[J];
+template <typename T, int J, bool UNI>
+__global__ void __launch_bounds__(kBlk) k_observe(EnvDev<T> E, T* __restrict__ obs) {
+  SG_PAR_SETUP
   T q[J], qd[J];
-  load_chain<T, J>(E, e, n, P);
   load_state<T, J>(E, e, n, q, qd);
   const T tipl[3] = {E.tip[e], E.tip[E.N + e], E.tip[2 * E.N + e]};
   T tip[3], g[3];
-  tip_fk<T, J>(P, n, q, tipl, tip);
+  tip_fk<T, J>(ps, n, q, tipl, tip);
   goal_of(E, e, E.prog[e], g);
   write_obs<T, J>(E, e, n, q, qd, tip, g, obs);
 }
 
-template <typename T, int J>
-__global__ void __launch_bounds__(kBlock) k_fd(EnvDev<T> E, const T* __restrict__ qin, const T* __restrict__ qdin,
-                                               const T* __restrict__ tauin, int arm_mode, T* __restrict__ qddout) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= E.N) return;
-  const int n = E.nd[e];
-  Jp<T> P[J];
+template <typename T, int J, bool UNI>
+__global__ void __launch_bounds__(kBlk) k_fd(EnvDev<T> E, const T* __restrict__ qin, const T* __restrict__ qdin,
+                                             const T* __restrict__ tauin, int arm_mode, T* __restrict__ qddout) {
+  SG_PAR_SETUP
   T q[J], qd[J], tau[J], arm[J], qdd[J];
-  load_chain<T, J>(E, e, n, P);
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const size_t i = (size_t)j * E.N + e;
     q[j] = j < n ? qin[i] : T(0);
     qd[j] = j < n ? qdin[i] : T(0);
     tau[j] = j < n ? tauin[i] : T(0);
-    arm[j] = (j < n && arm_mode == SG_ARM_DRIVE) ? E.h * P[j].kd + E.h * E.h * P[j].kp : T(0);
+    if (j < n && arm_mode == SG_ARM_DRIVE) {
+      const Jp<T> p = ps.get(j);
+      arm[j] = E.h * p.kd + E.h * E.h * p.kp;
+    } else {
+      arm[j] = T(0);
+    }
   }
-  aba<T, J>(P, n, q, qd, tau, arm, E.g, qdd);
+  aba<T, J>(ps, n, q, qd, tau, arm, E.g, qdd);
 #pragma unroll
   for (int j = 0; j < J; ++j)
     if (j < E.J) qddout[(size_t)j * E.N + e] = j < n ? qdd[j] : T(0);
 }
 
-template <typename T, int J>
-__global__ void __launch_bounds__(kBlock) k_id(EnvDev<T> E, const T* __restrict__ qin, const T* __restrict__ qdin,
-                                               const T* __restrict__ qddin, T* __restrict__ tauout) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= E.N) return;
-  const int n = E.nd[e];
-  Jp<T> P[J];
+template <typename T, int J, bool UNI>
+__global__ void __launch_bounds__(kBlk) k_id(EnvDev<T> E, const T* __restrict__ qin, const T* __restrict__ qdin,
+                                             const T* __restrict__ qddin, T* __restrict__ tauout) {
+  SG_PAR_SETUP
   T q[J], qd[J], qdd[J], tau[J];
-  load_chain<T, J>(E, e, n, P);
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const size_t i = (size_t)j * E.N + e;
@@ -92,33 +116,29 @@ __global__ void __launch_bounds__(kBlock) k_id(EnvDev<T> E, const T* __restrict_
     qd[j] = j < n ? qdin[i] : T(0);
     qdd[j] = j < n ? qddin[i] : T(0);
   }
-  rnea<T, J>(P, n, q, qd, qdd, E.g, tau);
+  rnea<T, J>(ps, n, q, qd, qdd, E.g, tau);
 #pragma unroll
   for (int j = 0; j < J; ++j)
     if (j < E.J) tauout[(size_t)j * E.N + e] = j < n ? tau[j] : T(0);
 }
 
-template <typename T, int J>
-__global__ void __launch_bounds__(kBlock) k_tip(EnvDev<T> E, const T* __restrict__ qin, T* __restrict__ out) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= E.N) return;
-  const int n = E.nd[e];
-  Jp<T> P[J];
+template <typename T, int J, bool UNI>
+__global__ void __launch_bounds__(kBlk) k_tip(EnvDev<T> E, const T* __restrict__ qin, T* __restrict__ out) {
+  SG_PAR_SETUP
   T q[J];
-  load_chain<T, J>(E, e, n, P);
 #pragma unroll
   for (int j = 0; j < J; ++j) q[j] = j < n ? qin[(size_t)j * E.N + e] : T(0);
   const T tipl[3] = {E.tip[e], E.tip[E.N + e], E.tip[2 * E.N + e]};
   T tip[3];
-  tip_fk<T, J>(P, n, q, tipl, tip);
+  tip_fk<T, J>(ps, n, q, tipl, tip);
   out[e] = tip[0];
   out[E.N + e] = tip[1];
   out[2 * E.N + e] = tip[2];
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_reset(EnvDev<T> E) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
+__global__ void __launch_bounds__(256) k_reset(EnvDev<T> E) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= E.N) return;
   for (int j = 0; j < E.J; ++j) {
     const size_t i = (size_t)j * E.N + e;
@@ -128,49 +148,60 @@ __global__ void __launch_bounds__(kBlock) k_reset(EnvDev<T> E) {
   E.prog[e] = E.prog0[e];
 }
 
-static inline dim3 grid_for(int N) { return dim3((N + kBlock - 1) / kBlock); }
-
-#define SG_DISPATCH_J(J_, CALL)          \
-  switch (dof_bucket(J_)) {              \
-    case 1: { constexpr int JJ = 1; CALL; break; } \
-    case 2: { constexpr int JJ = 2; CALL; break; } \
-    case 4: { constexpr int JJ = 4; CALL; break; } \
-    case 7: { constexpr int JJ = 7; CALL; break; } \
-    case 9: { constexpr int JJ = 9; CALL; break; } \
-    default: { constexpr int JJ = 16; CALL; break; } \
+// Launch with the block's dynamic LDS; raising the per-kernel LDS limit
+// above the 64 KB default once per instantiation.
+template <typename T, int J, typename K, typename... Args>
+static hipError_t launch_par(K kernel, const sg_ctx* c, Args... args) {
+  constexpr size_t lds = use_lds<T, J>() ? par_lds_bytes<T, J>() : 0;
+  static bool attr = false;
+  if (!attr && lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
   }
+  attr = true;
+  kernel<<<dim3((c->N + kBlk - 1) / kBlk), kBlk, lds, c->stream>>>(args...);
+  return hipGetLastError();
+}
+
+#define SG_DISPATCH(KERNEL, T_, ...)                                                               \
+  do {                                                                                             \
+    const bool uni = c->uniform;                                                                   \
+    switch (dof_bucket(c->J)) {                                                                    \
+      case 1: return launch_par<T_, 1>(KERNEL<T_, 1, true>, c, __VA_ARGS__);                       \
+      case 2: return uni ? launch_par<T_, 2>(KERNEL<T_, 2, true>, c, __VA_ARGS__)                  \
+                         : launch_par<T_, 2>(KERNEL<T_, 2, false>, c, __VA_ARGS__);                \
+      case 4: return uni ? launch_par<T_, 4>(KERNEL<T_, 4, true>, c, __VA_ARGS__)                  \
+                         : launch_par<T_, 4>(KERNEL<T_, 4, false>, c, __VA_ARGS__);                \
+      case 7: return uni ? launch_par<T_, 7>(KERNEL<T_, 7, true>, c, __VA_ARGS__)                  \
+                         : launch_par<T_, 7>(KERNEL<T_, 7, false>, c, __VA_ARGS__);                \
+      case 9: return uni ? launch_par<T_, 9>(KERNEL<T_, 9, true>, c, __VA_ARGS__)                  \
+                         : launch_par<T_, 9>(KERNEL<T_, 9, false>, c, __VA_ARGS__);                \
+      default: return launch_par<T_, 16>(KERNEL<T_, 16, false>, c, __VA_ARGS__);                   \
+    }                                                                                              \
+  } while (0)
 
 template <typename T>
 static hipError_t step_t(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done) {
   EnvDev<T> E = env_view<T>(c);
-  SG_DISPATCH_J(c->J, (k_step<T, JJ><<<grid_for(c->N), kBlock, 0, c->stream>>>(E, (const T*)act, (T*)obs, (T*)rew, done)));
-  return hipGetLastError();
+  SG_DISPATCH(k_step, T, E, (const T*)act, (T*)obs, (T*)rew, done);
 }
-
 template <typename T> static hipError_t observe_t(const sg_ctx* c, void* obs) {
   EnvDev<T> E = env_view<T>(c);
-  SG_DISPATCH_J(c->J, (k_observe<T, JJ><<<grid_for(c->N), kBlock, 0, c->stream>>>(E, (T*)obs)));
-  return hipGetLastError();
+  SG_DISPATCH(k_observe, T, E, (T*)obs);
 }
-
 template <typename T>
 static hipError_t fd_t(const sg_ctx* c, const void* q, const void* qd, const void* tau, int arm_mode, void* qdd) {
   EnvDev<T> E = env_view<T>(c);
-  SG_DISPATCH_J(c->J, (k_fd<T, JJ><<<grid_for(c->N), kBlock, 0, c->stream>>>(E, (const T*)q, (const T*)qd, (const T*)tau, arm_mode, (T*)qdd)));
-  return hipGetLastError();
+  SG_DISPATCH(k_fd, T, E, (const T*)q, (const T*)qd, (const T*)tau, arm_mode, (T*)qdd);
 }
-
 template <typename T>
 static hipError_t id_t(const sg_ctx* c, const void* q, const void* qd, const void* qdd, void* tau) {
   EnvDev<T> E = env_view<T>(c);
-  SG_DISPATCH_J(c->J, (k_id<T, JJ><<<grid_for(c->N), kBlock, 0, c->stream>>>(E, (const T*)q, (const T*)qd, (const T*)qdd, (T*)tau)));
-  return hipGetLastError();
+  SG_DISPATCH(k_id, T, E, (const T*)q, (const T*)qd, (const T*)qdd, (T*)tau);
 }
-
 template <typename T> static hipError_t tip_t(const sg_ctx* c, const void* q, void* tip) {
   EnvDev<T> E = env_view<T>(c);
-  SG_DISPATCH_J(c->J, (k_tip<T, JJ><<<grid_for(c->N), kBlock, 0, c->stream>>>(E, (const T*)q, (T*)tip)));
-  return hipGetLastError();
+  SG_DISPATCH(k_tip, T, E, (const T*)q, (T*)tip);
 }
 
 hipError_t launch_step(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done) {
@@ -189,8 +220,9 @@ hipError_t launch_tip(const sg_ctx* c, const void* q, void* tip) {
   return c->dtype == SG_F64 ? tip_t<double>(c, q, tip) : tip_t<float>(c, q, tip);
 }
 hipError_t launch_reset(const sg_ctx* c) {
-  if (c->dtype == SG_F64) k_reset<double><<<grid_for(c->N), kBlock, 0, c->stream>>>(env_view<double>(c));
-  else k_reset<float><<<grid_for(c->N), kBlock, 0, c->stream>>>(env_view<float>(c));
+  const dim3 g((c->N + 255) / 256);
+  if (c->dtype == SG_F64) k_reset<double><<<g, 256, 0, c->stream>>>(env_view<double>(c));
+  else k_reset<float><<<g, 256, 0, c->stream>>>(env_view<float>(c));
   return hipGetLastError();
 }
 

@@ -437,10 +437,11 @@ struct SStepArgs {
 };
 
 template <int J>
-__device__ __forceinline__ void drive_terms(const EnvDev<float>& E, const Jp<float> (&P)[J], int n, const float* act,
+__device__ __forceinline__ void drive_terms(const EnvDev<float>& E, const RegPar<float, J>& ps, int n, const float* act,
                                             int e, const float (&q)[J], const float (&qd)[J], float (&tau)[J],
                                             float (&arm)[J]) {
   const float h = E.h;
+  const Jp<float>* P = ps.P;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j < n) {
@@ -456,8 +457,9 @@ __device__ __forceinline__ void drive_terms(const EnvDev<float>& E, const Jp<flo
 }
 
 template <int J>
-__device__ __forceinline__ void integrate(const EnvDev<float>& E, const Jp<float> (&P)[J], int n, const float* qddbuf,
-                                          int e, float (&q)[J], float (&qd)[J]) {
+__device__ __forceinline__ void integrate(const EnvDev<float>& E, const RegPar<float, J>& ps, int n,
+                                          const float* qddbuf, int e, float (&q)[J], float (&qd)[J]) {
+  const Jp<float>* P = ps.P;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j < n) {
@@ -484,7 +486,7 @@ __global__ void __launch_bounds__(64) k_sstep_a(SStepArgs A) {
   const int lane = threadIdx.x, e = blockIdx.x * 64 + lane;
   const bool active = e < E.N;
   const int n = active ? E.nd[e] : 0;
-  Jp<float> P[J];
+  RegPar<float, J> P;
   float q[J], qd[J], tau[J], arm[J];
   float x[kSF];
 #pragma unroll
@@ -504,7 +506,8 @@ __global__ void __launch_bounds__(64) k_sstep_a(SStepArgs A) {
         x[j] = (q[j] - nm[j]) / nm[kSF + j];
         x[E.J + j] = (qd[j] - nm[E.J + j]) / nm[kSF + E.J + j];
         x[2 * E.J + j] = (tau[j] - nm[2 * E.J + j]) / nm[kSF + 2 * E.J + j];
-        const float p[10] = {P[j].m, P[j].hx, P[j].hy, P[j].hz, P[j].ixx, P[j].iyy, P[j].izz, P[j].ixy, P[j].ixz, P[j].iyz};
+        const Jp<float>& pj = P.P[j];
+        const float p[10] = {pj.m, pj.hx, pj.hy, pj.hz, pj.ixx, pj.iyy, pj.izz, pj.ixy, pj.ixz, pj.iyz};
 #pragma unroll
         for (int k = 0; k < 10; ++k) {
           const int f = 3 * E.J + 10 * j + k;
@@ -548,7 +551,7 @@ __global__ void __launch_bounds__(256) k_sstep_b(SStepArgs A) {
   if (i >= A.count[A.s]) return;
   const int e = A.list[(size_t)A.s * E.N + i];
   const int n = E.nd[e];
-  Jp<float> P[J];
+  RegPar<float, J> P;
   float q[J], qd[J], tau[J], arm[J], qdd[J];
   load_chain<float, J>(E, e, n, P);
   load_state<float, J>(E, e, n, q, qd);
@@ -574,7 +577,7 @@ __global__ void __launch_bounds__(256) k_sstep_f(SStepArgs A, float* __restrict_
   }
   if (e >= E.N) return;
   const int n = E.nd[e];
-  Jp<float> P[J];
+  RegPar<float, J> P;
   float q[J], qd[J];
   load_chain<float, J>(E, e, n, P);
   load_state<float, J>(E, e, n, q, qd);
