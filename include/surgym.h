@@ -64,6 +64,8 @@ enum { SG_DONE_ENDED = 1, SG_DONE_TIMEOUT = 2, SG_DONE_NONFINITE = 4 };
  * h*kd + h^2*kp with h = dt / substeps. */
 enum { SG_ARM_NONE = 0, SG_ARM_DRIVE = 1 };
 
+enum { SG_JOINT_REVOLUTE = 0, SG_JOINT_PRISMATIC = 1 };
+
 #define SG_MAX_DOF 16
 #define SG_MAX_WAYPOINTS 32
 
@@ -71,7 +73,11 @@ enum { SG_ARM_NONE = 0, SG_ARM_DRIVE = 1 };
  * sg_create (values are rounded to the context's dtype there).
  * Chain geometry: joint j's origin is at offset_j in link j-1's frame (the
  * base frame for j = 0); link j's frame is that origin rotated by q_j about
- * the unit axis_j. Joints j >= n_dof[e] of env e are ignored; outputs hold 0 there. */
+ * the unit axis_j (revolute joint), or moved by q_j along axis_j without
+ * rotation (prismatic joint; the paper's PSM and ECM arms each have one,
+ * Sec. III "Robot Descriptions"). For a prismatic joint q is in m, kp in
+ * N/m, kd in N s/m and limits in m. Joints j >= n_dof[e] of env e are
+ * ignored; outputs hold 0 there. */
 typedef struct {
   int32_t n_env;          /* N >= 1 */
   int32_t max_dof;        /* J, 1..SG_MAX_DOF */
@@ -91,6 +97,10 @@ typedef struct {
   double dt;              /* control period (s) > 0 */
   int32_t substeps;       /* S >= 1, substep h = dt / S */
   double gravity[3];      /* base-frame gravity (m/s^2) */
+  const int32_t* joint_type; /* [J][N] SG_JOINT_REVOLUTE or SG_JOINT_PRISMATIC;
+                              * NULL = all revolute. A context with any
+                              * prismatic joint keeps the padded schedule and
+                              * takes no surrogate (SG_E_UNSUPPORTED there). */
 } sg_robot_desc;
 
 /* Task description (paper Sec. IV): target reaching, reward -|tip - g|, or
@@ -161,6 +171,27 @@ sg_status sg_reset(sg_ctx* ctx);
  * actions [J][N] real (device), obs [W][N] real, reward [N] real,
  * done [N] uint8 (device). obs, reward, done may not alias actions. */
 sg_status sg_step(sg_ctx* ctx, const void* actions, void* obs, void* reward, uint8_t* done);
+
+/* Step schedules for batches of uneven DOF (envs differ in n_dof). The
+ * results do not depend on the schedule.
+ *   SG_SCHED_PADDED     one launch, env order, every env padded to max_dof
+ *                       with per-joint guards (the default);
+ *   SG_SCHED_SORTED     one launch over 64-env tiles of one DOF class each
+ *                       (tiles built at create), class-specialised code;
+ *   SG_SCHED_PER_CLASS  the same tiles, one launch per DOF class;
+ *   SG_SCHED_PERSISTENT the same tiles walked by at most 512 resident
+ *                       blocks in one launch.
+ * Tiled schedules are available on FP32 contexts without prismatic joints. */
+enum { SG_SCHED_PADDED = 0, SG_SCHED_SORTED = 1, SG_SCHED_PER_CLASS = 2, SG_SCHED_PERSISTENT = 3 };
+sg_status sg_set_schedule(sg_ctx* ctx, int32_t schedule);
+sg_status sg_get_schedule(const sg_ctx* ctx, int32_t* schedule);
+
+/* Autotuner: time `trials` steps (after one warm-up) of every available
+ * schedule with the given actions [J][N] (device), restoring the state after
+ * each, select the fastest and report ms per step per schedule in
+ * ms_per_step (host float[4], -1 for unavailable; may be NULL) and the
+ * choice in *best. Synchronizes the context's stream. */
+sg_status sg_autotune_step(sg_ctx* ctx, const void* actions, int32_t trials, int32_t* best, float* ms_per_step);
 
 /* Observation of the current state, obs [W][N] real (device). */
 sg_status sg_observe(sg_ctx* ctx, void* obs);
@@ -266,6 +297,59 @@ sg_status sg_surrogate_predict(sg_surrogate* s, const float* q, const float* qd,
  * NULL) receives the number of exact solves per substep. */
 sg_status sg_surrogate_step(sg_surrogate* s, const float* actions, float* obs, float* reward, uint8_t* done,
                             float threshold, int32_t* n_fallback);
+
+/* ---- PPO update (paper Sec. III "Policy learning and control": the GPU
+ * PPO of Rudin et al.; clipped surrogate objective of Schulman et al.) ----
+ * Trains the rollout policy of the bound context from its rollout buffers:
+ * advantages normalised over the batch (mean, unbiased std + 1e-8); per
+ * minibatch L = L_pi + value_coef L_v - entropy_coef H with
+ *   L_pi = -mean(min(r A, clip(r, 1 - clip, 1 + clip) A)), r = pi / pi_old,
+ *   L_v  = mean(max((V - R)^2, (V_old + clip(V - V_old, +-clip) - R)^2)),
+ *   H    = sum_j (log_std_j + 0.5 + 0.5 log 2 pi);
+ * gradient through the network (BF16 matrix products, FP32 accumulation,
+ * FP32 master weights), global-norm clip, Adam. Every call is asynchronous
+ * on the context's stream; results are deterministic for given inputs. */
+typedef struct sg_ppo sg_ppo;
+
+typedef struct {
+  float clip;           /* ratio and value clip, > 0 (0.2) */
+  float value_coef;     /* >= 0 (1.0) */
+  float entropy_coef;   /* (0.01) */
+  float max_grad_norm;  /* global gradient-norm bound; <= 0: none (1.0) */
+  float lr, beta1, beta2, adam_eps;  /* Adam (1e-3, 0.9, 0.999, 1e-8) */
+  int32_t epochs;       /* passes over the batch, >= 1 (5) */
+  int32_t minibatches;  /* per pass, >= 1, dividing T N (4) */
+} sg_ppo_config;
+
+/* Create a trainer bound to an FP32 context (J <= 7) with initial FP32
+ * parameters params (HOST, flat: W1 [256][W], b1 [256], W2 [128][256],
+ * b2 [128], W3 [J+1][128], b3 [J+1], log_std [J]; W = 2 J + 10). The
+ * context's rollout policy is set to them (BF16, round to nearest even).
+ * max_samples bounds T N of later calls (1..16M). Synchronizes. */
+sg_status sg_ppo_create(sg_ctx* ctx, const float* params, int32_t max_samples, sg_ppo** out);
+void sg_ppo_destroy(sg_ppo* ppo);
+/* Number of parameters P of the flat vector. */
+int32_t sg_ppo_param_count(const sg_ppo* ppo);
+/* Current master parameters into params (HOST float[P]); synchronizes. */
+sg_status sg_ppo_get_params(sg_ppo* ppo, float* params);
+
+/* Gradient of L over one minibatch of `rows` samples of a T-step rollout
+ * (sample s = t N + env; idx: DEVICE int32 [rows] sample ids, or NULL for
+ * 0..rows-1), with advantages normalised over all T N samples first, the
+ * entropy term included and no norm clip: grad DEVICE float[P]. stats
+ * (DEVICE float[8], may be NULL): loss_pi, loss_v, entropy, approx_kl
+ * (mean log pi_old - log pi), clip fraction, |grad|. */
+sg_status sg_ppo_grad(sg_ppo* ppo, const sg_rollout_bufs* bufs, int32_t T, const int32_t* idx, int32_t rows,
+                      const sg_ppo_config* cfg, float* grad, float* stats);
+
+/* One PPO update on a T-step rollout: cfg->epochs passes; pass ep visits
+ * the samples perm[ep T N .. (ep + 1) T N) (DEVICE int32, a permutation of
+ * 0..T N - 1 per pass; NULL: in order) cut into cfg->minibatches
+ * minibatches; each takes a clipped Adam step. Then the context's rollout
+ * policy is rewritten from the updated parameters. stats (DEVICE float[8],
+ * may be NULL): the sg_ppo_grad statistics averaged over the minibatches. */
+sg_status sg_ppo_update(sg_ppo* ppo, const sg_rollout_bufs* bufs, int32_t T, const sg_ppo_config* cfg,
+                        const int32_t* perm, float* stats);
 
 #ifdef __cplusplus
 }

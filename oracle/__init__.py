@@ -27,7 +27,7 @@ class _Robot(C.Structure):
     _fields_ = [("n_env", C.c_int32), ("max_dof", C.c_int32), ("n_dof", _ip),
                 ("axis", _dp), ("offset", _dp), ("com", _dp), ("mass", _dp), ("inertia", _dp),
                 ("kp", _dp), ("kd", _dp), ("q_lo", _dp), ("q_hi", _dp), ("q0", _dp), ("tip", _dp),
-                ("dt", C.c_double), ("substeps", C.c_int32), ("gravity", C.c_double * 3)]
+                ("dt", C.c_double), ("substeps", C.c_int32), ("gravity", C.c_double * 3), ("joint_type", _ip)]
 
 
 class _Task(C.Structure):
@@ -73,10 +73,11 @@ class Oracle:
             arr[name] = _f64(getattr(robot, name))
             k.append(arr[name])
         nd = np.ascontiguousarray(robot.n_dof, dtype=np.int32)
-        k.append(nd)
+        jt = None if getattr(robot, "joint_type", None) is None else np.ascontiguousarray(robot.joint_type, np.int32)
+        k.extend([nd, jt])
         self.r = _Robot(self.N, self.J, _ptr(nd, _ip), *[_ptr(arr[n]) for n in
                         ("axis", "offset", "com", "mass", "inertia", "kp", "kd", "q_lo", "q_hi", "q0", "tip")],
-                        float(robot.dt), int(robot.substeps), (C.c_double * 3)(*robot.gravity))
+                        float(robot.dt), int(robot.substeps), (C.c_double * 3)(*robot.gravity), _ptr(jt, _ip))
         if task is not None:
             tgt = None if task.target is None else _f64(task.target)
             wps = None if task.waypoints is None else _f64(task.waypoints)
@@ -298,3 +299,67 @@ def gae(rew, val, done, gamma=0.99, lam=0.95):
                   _ptr(np.ascontiguousarray(done, dtype=np.uint8), _u8p), C.c_double(gamma), C.c_double(lam),
                   _ptr(adv), _ptr(ret))
     return adv, ret
+
+
+# ---- PPO update -------------------------------------------------------------
+PPO_DEFAULTS = dict(clip=0.2, c_v=1.0, c_e=0.01, max_norm=1.0, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8)
+
+
+def _ppo_cfg(cfg):
+    c = dict(PPO_DEFAULTS)
+    c.update(cfg or {})
+    return (C.c_double * 8)(*[float(c[k]) for k in ("clip", "c_v", "c_e", "max_norm", "lr", "beta1", "beta2",
+                                                       "adam_eps")])
+
+
+def ppo_flat(policy):
+    """Flat parameter vector W1, b1, W2, b2, W3, b3, log_std."""
+    parts = []
+    for W, b in zip(policy.W, policy.b):
+        parts += [np.ravel(W), np.ravel(b)]
+    parts.append(np.ravel(policy.log_std))
+    return np.concatenate([_f64(p) for p in parts])
+
+
+def ppo_grad(dims, p, x, a, logp_old, adv, ret, v_old, cfg=None, emulate=True):
+    """One minibatch: (loss, gradient [P], stats dict). x [n_in][B], a [J][B]."""
+    B = x.shape[1]
+    g = np.zeros(p.size)
+    st = np.zeros(5)
+    d = (C.c_int * 4)(*dims)
+    f = lib().ora_ppo_grad
+    f.restype = C.c_double
+    loss = f(d, _ptr(_f64(p)), _ptr(_f64(x)), _ptr(_f64(a)), _ptr(_f64(logp_old)), _ptr(_f64(adv)), _ptr(_f64(ret)),
+             _ptr(_f64(v_old)), C.c_int(B), _ppo_cfg(cfg), C.c_int(int(emulate)), _ptr(g), _ptr(st))
+    return loss, g, dict(zip(("loss_pi", "loss_v", "entropy", "approx_kl", "clip_frac"), st))
+
+
+def ppo_normalise(adv):
+    a = _f64(adv).ravel()
+    out = np.zeros_like(a)
+    lib().ora_ppo_normalise(C.c_int(a.size), _ptr(a), _ptr(out))
+    return out.reshape(np.shape(adv))
+
+
+def clip_grad_norm(g, max_norm):
+    g = _f64(g).copy()
+    f = lib().ora_clip_grad_norm
+    f.restype = C.c_double
+    n = f(C.c_int(g.size), _ptr(g), C.c_double(max_norm))
+    return g, n
+
+
+def ppo_update(dims, p, m, v, t, bufs, T, N, perm=None, epochs=5, n_mb=4, cfg=None, emulate=True):
+    """Whole update on rollout buffers (dict of obs, act, logp, adv, ret, val
+    arrays in the rollout layouts). Returns (p, m, v, t, stats)."""
+    p, m, v = _f64(p).copy(), _f64(m).copy(), _f64(v).copy()
+    tt = C.c_int(t)
+    st = np.zeros(5)
+    pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+    rc = lib().ora_ppo_update((C.c_int * 4)(*dims), _ptr(p), _ptr(m), _ptr(v), C.byref(tt),
+                              *[_ptr(_f64(bufs[k])) for k in ("obs", "act", "logp", "adv", "ret", "val")],
+                              C.c_int(T), C.c_int(N), _ptr(pm, _ip), C.c_int(epochs), C.c_int(n_mb), _ppo_cfg(cfg),
+                              C.c_int(int(emulate)), _ptr(st))
+    if rc != 0:
+        raise ValueError("ppo_update: T*N must be a multiple of n_mb")
+    return p, m, v, tt.value, dict(zip(("loss_pi", "loss_v", "entropy", "approx_kl", "clip_frac"), st))

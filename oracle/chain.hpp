@@ -30,7 +30,10 @@ namespace ora {
 
 constexpr int kMaxDof = 16;
 
+enum { kRevolute = 0, kPrismatic = 1 };
+
 template <class T> struct Link {
+  int type;  // kRevolute or kPrismatic
   V3<T> axis, offset, com;
   T mass;
   M3<T> Ic;  // rotational inertia about the centre of mass, link axes
@@ -44,11 +47,25 @@ template <class T> struct Chain {
   V3<T> grav;  // gravity vector in base coordinates, e.g. (0, 0, -9.81)
 };
 
+// Joint transform X_j = X_J(q) X_T: a revolute joint rotates by q about its
+// axis, a prismatic joint translates by q along it (Featherstone Table 4.1).
 template <class T> inline PX<T> joint_transform(const Link<T>& l, T q) {
   PX<T> X;
-  X.E = transpose(axis_rotation(l.axis, q));
-  X.r = l.offset;
+  if (l.type == kPrismatic) {
+    X.E = m3_identity<T>();
+    X.r = l.offset + scale(l.axis, q);
+  } else {
+    X.E = transpose(axis_rotation(l.axis, q));
+    X.r = l.offset;
+  }
   return X;
+}
+
+// Motion subspace: (axis; 0) for a revolute joint, (0; axis) for a
+// prismatic one (link coordinates).
+template <class T> inline SV<T> motion_subspace(const Link<T>& l) {
+  const V3<T> z = v3(T(0.0), T(0.0), T(0.0));
+  return l.type == kPrismatic ? SV<T>{z, l.axis} : SV<T>{l.axis, z};
 }
 
 // The spatial inertia of a link is constant in link coordinates: it is formed
@@ -67,8 +84,12 @@ template <class T> inline void forward_kinematics(const Chain<T>& ch, const T* q
   M3<T> R = m3_identity<T>();
   V3<T> p = v3(T(0.0), T(0.0), T(0.0));
   for (int j = 0; j < ch.n; ++j) {
-    p = p + mul(R, ch.L[j].offset);
-    R = mul(R, axis_rotation(ch.L[j].axis, q[j]));
+    if (ch.L[j].type == kPrismatic) {
+      p = p + mul(R, ch.L[j].offset + scale(ch.L[j].axis, q[j]));
+    } else {
+      p = p + mul(R, ch.L[j].offset);
+      R = mul(R, axis_rotation(ch.L[j].axis, q[j]));
+    }
     out.R[j] = R;
     out.p[j] = p;
   }
@@ -84,7 +105,7 @@ template <class T> inline void rnea(const Chain<T>& ch, const T* q, const T* qd,
   for (int j = 0; j < ch.n; ++j) {
     const Link<T>& l = ch.L[j];
     X[j] = joint_transform(l, q[j]);
-    SV<T> S = {l.axis, v3(T(0.0), T(0.0), T(0.0))};
+    SV<T> S = motion_subspace(l);
     SV<T> vJ = scale(S, qd[j]);
     SV<T> v = xform_motion(X[j], v_par) + vJ;
     SV<T> a = xform_motion(X[j], a_par) + scale(S, qdd[j]) + crm(v, vJ);
@@ -94,7 +115,7 @@ template <class T> inline void rnea(const Chain<T>& ch, const T* q, const T* qd,
     a_par = a;
   }
   for (int j = ch.n - 1; j >= 0; --j) {
-    SV<T> S = {ch.L[j].axis, v3(T(0.0), T(0.0), T(0.0))};
+    SV<T> S = motion_subspace(ch.L[j]);
     tau[j] = sdot(S, f[j]);
     if (j > 0) f[j - 1] = f[j - 1] + xform_force_T(X[j], f[j]);
   }
@@ -111,14 +132,14 @@ template <class T> inline void crba(const Chain<T>& ch, const T* q, T* H) {
   }
   for (int i = n - 1; i >= 0; --i) {
     if (i > 0) Ic[i - 1] = add(Ic[i - 1], congruence(X[i], Ic[i]));
-    SV<T> Si = {ch.L[i].axis, v3(T(0.0), T(0.0), T(0.0))};
+    SV<T> Si = motion_subspace(ch.L[i]);
     SV<T> F = mul(Ic[i], Si);
     H[i * n + i] = sdot(Si, F);
     int j = i;
     while (j > 0) {
       F = xform_force_T(X[j], F);
       j = j - 1;
-      SV<T> Sj = {ch.L[j].axis, v3(T(0.0), T(0.0), T(0.0))};
+      SV<T> Sj = motion_subspace(ch.L[j]);
       H[i * n + j] = sdot(Sj, F);
       H[j * n + i] = H[i * n + j];
     }
@@ -168,7 +189,7 @@ template <class T> inline void aba(const Chain<T>& ch, const T* q, const T* qd, 
   for (int i = 0; i < n; ++i) {
     const Link<T>& l = ch.L[i];
     X[i] = joint_transform(l, q[i]);
-    S[i] = {l.axis, v3(T(0.0), T(0.0), T(0.0))};
+    S[i] = motion_subspace(l);
     SV<T> vJ = scale(S[i], qd[i]);
     SV<T> v = xform_motion(X[i], v_par) + vJ;
     c[i] = crm(v, vJ);

@@ -41,6 +41,7 @@ typedef struct {
   double dt;
   int32_t substeps;
   double gravity[3];
+  const int32_t* joint_type;  // [J][N] 0 revolute, 1 prismatic; null: all revolute
 } ora_robot;
 
 typedef struct {
@@ -66,6 +67,7 @@ template <class T> Chain<T> load_chain(const ora_robot* r, int e) {
   ch.n = r->n_dof[e];
   for (int j = 0; j < ch.n; ++j) {
     Link<T>& l = ch.L[j];
+    l.type = r->joint_type ? r->joint_type[j * N + e] : kRevolute;
     auto at = [&](const double* a, int f) { return T(a[(f * J + j) * N + e]); };
     l.axis = v3(at(r->axis, 0), at(r->axis, 1), at(r->axis, 2));
     l.offset = v3(at(r->offset, 0), at(r->offset, 1), at(r->offset, 2));
@@ -576,6 +578,89 @@ int ora_residual(const ora_robot* r, const double* q, const double* qd, const do
       tt += te[j] * te[j];
     }
     rel[e] = std::sqrt(rr) / std::max(std::sqrt(tt), 1e-3);
+  }
+  return 0;
+}
+
+
+// ---- PPO update (paper Sec. III "Policy learning and control") ----------
+}  // extern "C"
+#include "ppo.hpp"
+extern "C" {
+
+// cfg = {clip, c_v, c_e, max_norm, lr, beta1, beta2, adam_eps}
+static PpoCfg ppo_cfg(const double* c) { return PpoCfg{c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7]}; }
+
+// Gradient of one minibatch (no clipping, no update). dims = {n_in, h1, h2,
+// J}; x [n_in][B], a [J][B], logp_old, adv (already normalised), ret, v_old
+// [B]. g [P] is overwritten; stats = {loss_pi, loss_v, entropy, approx_kl,
+// clip_frac}. Returns the total loss.
+double ora_ppo_grad(const int* dims, const double* p, const double* x, const double* a, const double* logp_old,
+                    const double* adv, const double* ret, const double* v_old, int B, const double* cfg, int emulate,
+                    double* g, double* stats) {
+  const PpoNet net(dims[0], dims[1], dims[2], dims[3]);
+  const PpoCfg c = ppo_cfg(cfg);
+  std::vector<std::vector<double>> xs(B, std::vector<double>(net.n_in)), as(B, std::vector<double>(net.J));
+  std::vector<PpoSample> mb(B);
+  for (int r = 0; r < B; ++r) {
+    for (int k = 0; k < net.n_in; ++k) xs[r][k] = x[(size_t)k * B + r];
+    for (int j = 0; j < net.J; ++j) as[r][j] = a[(size_t)j * B + r];
+    mb[r] = PpoSample{xs[r].data(), as[r].data(), logp_old[r], adv[r], ret[r], v_old[r]};
+  }
+  std::fill(g, g + net.size, 0.0);
+  const PpoStats st = ppo_minibatch(net, p, mb, c, emulate != 0, g);
+  stats[0] = st.loss_pi; stats[1] = st.loss_v; stats[2] = st.entropy; stats[3] = st.approx_kl;
+  stats[4] = st.clip_frac;
+  return ppo_loss(st, c);
+}
+
+// Advantage normalisation over n values.
+void ora_ppo_normalise(int n, const double* adv, double* out) { normalise_adv(n, adv, out); }
+
+// Global-norm gradient clipping in place; returns the norm before clipping.
+double ora_clip_grad_norm(int n, double* g, double max_norm) { return clip_grad_norm(n, g, max_norm); }
+
+// A whole update on rollout buffers of T steps x N envs (layouts of
+// ora_rollout): advantages normalised over all T N samples, then for each
+// epoch the samples perm[ep][.] (identity if perm is null) are cut into
+// n_mb minibatches of T N / n_mb; each minibatch: gradient, norm clip,
+// Adam step (t counts the steps taken so far, updated). p, m, v [P] in place.
+// stats: the mean over minibatches of {loss_pi, loss_v, entropy, approx_kl,
+// clip_frac}.
+int ora_ppo_update(const int* dims, double* p, double* m, double* v, int* t, const double* obs, const double* act,
+                   const double* logp, const double* adv, const double* ret, const double* val_, int T, int N,
+                   const int* perm, int epochs, int n_mb, const double* cfg, int emulate, double* stats) {
+  const PpoNet net(dims[0], dims[1], dims[2], dims[3]);
+  const PpoCfg c = ppo_cfg(cfg);
+  const int W = net.n_in, J = net.J, B = T * N, mbs = B / n_mb;
+  if (mbs * n_mb != B) return -1;
+  std::vector<double> an(B), xs((size_t)B * W), as((size_t)B * J);
+  normalise_adv(B, adv, an.data());
+  for (int s = 0; s < B; ++s) {
+    const int tt = s / N, e = s % N;
+    for (int k = 0; k < W; ++k) xs[(size_t)s * W + k] = obs[((size_t)tt * W + k) * N + e];
+    for (int j = 0; j < J; ++j) as[(size_t)s * J + j] = act[((size_t)tt * J + j) * N + e];
+  }
+  std::vector<double> g(net.size);
+  for (int k = 0; k < 5; ++k) stats[k] = 0;
+  for (int ep = 0; ep < epochs; ++ep) {
+    for (int k = 0; k < n_mb; ++k) {
+      std::vector<PpoSample> mb(mbs);
+      for (int r = 0; r < mbs; ++r) {
+        const int s = perm ? perm[(size_t)ep * B + (size_t)k * mbs + r] : k * mbs + r;
+        const int tt = s / N, e = s % N;
+        mb[r] = PpoSample{&xs[(size_t)s * W], &as[(size_t)s * J], logp[(size_t)tt * N + e], an[s],
+                          ret[(size_t)tt * N + e], val_[(size_t)tt * N + e]};
+      }
+      std::fill(g.begin(), g.end(), 0.0);
+      const PpoStats st = ppo_minibatch(net, p, mb, c, emulate != 0, g.data());
+      clip_grad_norm(net.size, g.data(), c.max_norm);
+      *t += 1;
+      adam_update(net.size, p, g.data(), m, v, c.lr, c.beta1, c.beta2, c.adam_eps, *t);
+      const double w = 1.0 / (epochs * n_mb);
+      stats[0] += st.loss_pi * w; stats[1] += st.loss_v * w; stats[2] += st.entropy * w;
+      stats[3] += st.approx_kl * w; stats[4] += st.clip_frac * w;
+    }
   }
   return 0;
 }

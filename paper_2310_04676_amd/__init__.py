@@ -33,7 +33,7 @@ class RobotDesc(C.Structure):
     _fields_ = [("n_env", C.c_int32), ("max_dof", C.c_int32), ("n_dof", _ip), ("dtype", C.c_int32),
                 ("axis", _dp), ("offset", _dp), ("com", _dp), ("mass", _dp), ("inertia", _dp), ("kp", _dp),
                 ("kd", _dp), ("q_lo", _dp), ("q_hi", _dp), ("q0", _dp), ("tip", _dp), ("dt", C.c_double),
-                ("substeps", C.c_int32), ("gravity", C.c_double * 3)]
+                ("substeps", C.c_int32), ("gravity", C.c_double * 3), ("joint_type", _ip)]
 
 
 class TaskDesc(C.Structure):
@@ -119,11 +119,13 @@ def make_descs(robot, task, dtype, seed=0):
         arrs[name] = _f64(getattr(robot, name))
         keep.append(arrs[name])
     nd = np.ascontiguousarray(robot.n_dof, dtype=np.int32)
-    keep.append(nd)
+    jt = getattr(robot, "joint_type", None)
+    jt = None if jt is None else np.ascontiguousarray(jt, dtype=np.int32)
+    keep.extend([nd, jt])
     rd = RobotDesc(robot.n_env, robot.max_dof, _ptr(nd, _ip), dtype,
                    *[_ptr(arrs[n]) for n in ("axis", "offset", "com", "mass", "inertia", "kp", "kd", "q_lo",
                                              "q_hi", "q0", "tip")],
-                   float(robot.dt), int(robot.substeps), (C.c_double * 3)(*robot.gravity))
+                   float(robot.dt), int(robot.substeps), (C.c_double * 3)(*robot.gravity), _ptr(jt, _ip))
     tgt = None if task.target is None else _f64(task.target)
     wps = None if task.waypoints is None else _f64(task.waypoints)
     p0 = None if task.progress0 is None else np.ascontiguousarray(task.progress0, dtype=np.int32)
@@ -377,3 +379,138 @@ def from_workload(w, device=None) -> Sim:
     if w.policy is not None and w.dtype == np.float32 and w.robot.max_dof <= 7:
         sim.set_policy(w.policy)
     return sim
+
+
+SG_SCHED_PADDED, SG_SCHED_SORTED, SG_SCHED_PER_CLASS, SG_SCHED_PERSISTENT = 0, 1, 2, 3
+SCHEDULE_NAMES = ("padded", "sorted", "per_class", "persistent")
+lib.sg_set_schedule.argtypes = [_vp, C.c_int32]
+lib.sg_get_schedule.argtypes = [_vp, C.POINTER(C.c_int32)]
+lib.sg_autotune_step.argtypes = [_vp, _vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+
+
+def _set_schedule(self, schedule):
+    self._call(lib.sg_set_schedule, C.c_int32(schedule))
+
+
+def _get_schedule(self):
+    s = C.c_int32()
+    self._call(lib.sg_get_schedule, C.byref(s))
+    return s.value
+
+
+def _autotune_step(self, actions, trials=5):
+    """Time every step schedule on these actions (state restored after
+    each); the fastest becomes the context's schedule. Returns
+    (best, {name: ms per step})."""
+    best = C.c_int32()
+    ms = (C.c_float * 4)()
+    self._call(lib.sg_autotune_step, _dptr(actions, self.tdtype), C.c_int32(trials), C.byref(best), ms)
+    return best.value, {SCHEDULE_NAMES[i]: ms[i] for i in range(4) if ms[i] >= 0}
+
+
+Sim.set_schedule = _set_schedule
+Sim.get_schedule = _get_schedule
+Sim.autotune_step = _autotune_step
+
+
+# ---- PPO update ---------------------------------------------------------------
+class PpoConfig(C.Structure):
+    _fields_ = [("clip", C.c_float), ("value_coef", C.c_float), ("entropy_coef", C.c_float),
+                ("max_grad_norm", C.c_float), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("adam_eps", C.c_float), ("epochs", C.c_int32), ("minibatches", C.c_int32)]
+
+
+PPO_DEFAULTS = dict(clip=0.2, value_coef=1.0, entropy_coef=0.01, max_grad_norm=1.0, lr=1e-3, beta1=0.9,
+                    beta2=0.999, adam_eps=1e-8, epochs=5, minibatches=4)
+PPO_STATS = ("loss_pi", "loss_v", "entropy", "approx_kl", "clip_frac", "grad_norm")
+
+lib.sg_ppo_create.argtypes = [_vp, _vp, C.c_int32, C.POINTER(_vp)]
+lib.sg_ppo_destroy.argtypes = [_vp]
+lib.sg_ppo_destroy.restype = None
+lib.sg_ppo_param_count.argtypes = [_vp]
+lib.sg_ppo_param_count.restype = C.c_int32
+lib.sg_ppo_get_params.argtypes = [_vp, _vp]
+lib.sg_ppo_grad.argtypes = [_vp, _vp, C.c_int32, _vp, C.c_int32, _vp, _vp, _vp]
+lib.sg_ppo_update.argtypes = [_vp, _vp, C.c_int32, _vp, _vp, _vp]
+
+
+def ppo_flat_params(policy):
+    """Flat FP32 parameter vector W1, b1, W2, b2, W3, b3, log_std."""
+    parts = []
+    for W, b in zip(policy.W, policy.b):
+        parts += [np.asarray(W, np.float32).ravel(), np.asarray(b, np.float32).ravel()]
+    parts.append(np.asarray(policy.log_std, np.float32).ravel())
+    return np.ascontiguousarray(np.concatenate(parts), dtype=np.float32)
+
+
+def _ppo_cfg(cfg):
+    c = dict(PPO_DEFAULTS)
+    c.update(cfg or {})
+    return PpoConfig(*[c[k] for k, _ in PpoConfig._fields_])
+
+
+class Ppo:
+    """PPO trainer of a Sim's rollout policy (``sg_ppo``)."""
+
+    def __init__(self, sim: Sim, params, max_samples: int):
+        self.sim = sim
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        W, J = 2 * sim.J + 10, sim.J
+        want = 256 * W + 256 + 128 * 256 + 128 + (J + 1) * 128 + (J + 1) + J
+        if p.size != want:
+            raise ValueError(f"expected {want} parameters, got {p.size}")
+        h = _vp()
+        sim._call(lib.sg_ppo_create, p.ctypes.data_as(_vp), C.c_int32(max_samples), C.byref(h))
+        self.h = h
+        self.P = lib.sg_ppo_param_count(h)
+        sim.policy_dims = (W, 256, 128, J + 1)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.sg_ppo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, fn, *args):
+        s = self.sim
+        lib.sg_set_stream(s.ctx, s.torch.cuda.current_stream(s.device).cuda_stream)
+        st = fn(self.h, *args)
+        if st != SG_OK:
+            raise SgError(st, lib.sg_last_error(s.ctx).decode())
+
+    def params(self):
+        out = np.zeros(self.P, dtype=np.float32)
+        self._call(lib.sg_ppo_get_params, out.ctypes.data_as(_vp))
+        return out
+
+    def _bufs(self, bufs):
+        f32, u8 = self.sim.torch.float32, self.sim.torch.uint8
+        return RolloutBufs(*[_dptr(bufs[k], u8 if k == "done" else f32)
+                             for k in ("obs", "act", "logp", "rew", "done", "val", "adv", "ret")], 0.99, 0.95)
+
+    def grad(self, bufs, T, idx=None, rows=None, cfg=None):
+        """Gradient of one minibatch: (grad [P], stats dict of device scalars)."""
+        t = self.sim.torch
+        rows = (idx.numel() if idx is not None else T * self.sim.N) if rows is None else rows
+        g = t.empty(self.P, dtype=t.float32, device=self.sim.device)
+        st = t.empty(8, dtype=t.float32, device=self.sim.device)
+        rb = self._bufs(bufs)
+        c = _ppo_cfg(cfg)
+        self._call(lib.sg_ppo_grad, C.byref(rb), C.c_int32(T), None if idx is None else _dptr(idx, t.int32),
+                   C.c_int32(rows), C.byref(c), _dptr(g, t.float32), _dptr(st, t.float32))
+        return g, st
+
+    def update(self, bufs, T, cfg=None, perm=None, stats=None):
+        """One PPO update; returns the device stats tensor [8]."""
+        t = self.sim.torch
+        st = t.empty(8, dtype=t.float32, device=self.sim.device) if stats is None else stats
+        rb = self._bufs(bufs)
+        c = _ppo_cfg(cfg)
+        self._call(lib.sg_ppo_update, C.byref(rb), C.c_int32(T), C.byref(c),
+                   None if perm is None else _dptr(perm, t.int32), _dptr(st, t.float32))
+        return st

@@ -36,7 +36,7 @@ template <typename T> hipError_t upload(void** dst, const std::vector<double>& s
 
 void free_ctx(sg_ctx* c) {
   void* ptrs[] = {c->par, c->tip, c->nd, c->target, c->wp, c->prog0, c->q, c->qd, c->prog, c->w_bf16, c->bias,
-                  c->log_std};
+                  c->log_std, c->slot_env, c->tile_dof};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -78,6 +78,8 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
       if (!(r->mass[i] > 0)) return fail(nullptr, SG_E_INVAL, "sg_create: link mass must be > 0");
       if (!(r->q_hi[i] > r->q_lo[i])) return fail(nullptr, SG_E_INVAL, "sg_create: q_hi must exceed q_lo");
       if (r->kp[i] < 0 || r->kd[i] < 0) return fail(nullptr, SG_E_INVAL, "sg_create: gains must be >= 0");
+      if (r->joint_type && r->joint_type[i] != SG_JOINT_REVOLUTE && r->joint_type[i] != SG_JOINT_PRISMATIC)
+        return fail(nullptr, SG_E_INVAL, "sg_create: joint_type must be 0 (revolute) or 1 (prismatic)");
     }
   }
   sg_ctx* c = new sg_ctx();
@@ -117,6 +119,10 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
       P(sgk::P_KP, i) = r->kp[i]; P(sgk::P_KD, i) = r->kd[i];
       P(sgk::P_LO, i) = r->q_lo[i]; P(sgk::P_HI, i) = r->q_hi[i];
       P(sgk::P_Q0, i) = r->q0[i];
+      if (r->joint_type && r->joint_type[i] == SG_JOINT_PRISMATIC) {
+        P(sgk::P_PR, i) = 1.0;
+        c->prismatic = true;
+      }
     }
   }
   std::vector<double> tip(r->tip, r->tip + 3 * (size_t)N);
@@ -124,8 +130,23 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
   if (t->target) tgt.assign(t->target, t->target + 3 * (size_t)N);
   if (t->task == SG_TASK_PATH) wps.assign(t->waypoints, t->waypoints + (size_t)c->K * 3 * N);
   else wps.assign(3 * (size_t)N, 0.0);
-  std::vector<double> zeros(JN, 0.0);
   std::vector<int> nd(r->n_dof, r->n_dof + N), prog0(N, 0);
+  // DOF-class tiles: envs of each class in env order, padded to 64 slots
+  std::vector<int> slot_env, tile_dof;
+  for (int d = 1; d <= J; ++d) {
+    std::vector<int> members;
+    for (int e = 0; e < N; ++e)
+      if (nd[e] == d) members.push_back(e);
+    if (members.empty()) continue;
+    const int nt = ((int)members.size() + 63) / 64;
+    c->cls_dof.push_back(d);
+    c->cls_tile0.push_back((int)tile_dof.size());
+    c->cls_ntiles.push_back(nt);
+    for (int t = 0; t < nt; ++t) tile_dof.push_back(d);
+    members.resize((size_t)nt * 64, -1);
+    slot_env.insert(slot_env.end(), members.begin(), members.end());
+  }
+  c->n_tiles = (int)tile_dof.size();
   if (t->progress0) prog0.assign(t->progress0, t->progress0 + N);
 
   auto up = [&](void** d, const std::vector<double>& v) {
@@ -142,6 +163,12 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
   if (e == hipSuccess) e = hipMalloc((void**)&c->prog0, N * sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(c->prog0, prog0.data(), N * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc((void**)&c->prog, N * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->slot_env, slot_env.size() * sizeof(int));
+  if (e == hipSuccess)
+    e = hipMemcpy(c->slot_env, slot_env.data(), slot_env.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->tile_dof, tile_dof.size() * sizeof(int));
+  if (e == hipSuccess)
+    e = hipMemcpy(c->tile_dof, tile_dof.data(), tile_dof.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&c->q, JN * esz);
   if (e == hipSuccess) e = hipMalloc(&c->qd, JN * esz);
   if (e == hipSuccess) e = hipMemset(c->q, 0, JN * esz);
@@ -191,6 +218,82 @@ sg_status sg_step(sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* don
   if (act == obs || act == rew) return fail(c, SG_E_INVAL, "sg_step: outputs alias actions");
   hipError_t e = sgk::launch_step(c, act, obs, rew, done);
   return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_step");
+}
+
+sg_status sg_set_schedule(sg_ctx* c, int32_t schedule) {
+  if (!c) return SG_E_INVAL;
+  if (schedule < SG_SCHED_PADDED || schedule > SG_SCHED_PERSISTENT)
+    return fail(c, SG_E_INVAL, "sg_set_schedule: unknown schedule");
+  if (schedule != SG_SCHED_PADDED && c->dtype != SG_F32)
+    return fail(c, SG_E_UNSUPPORTED, "sg_set_schedule: tiled schedules need an FP32 context");
+  if (schedule != SG_SCHED_PADDED && c->prismatic)
+    return fail(c, SG_E_UNSUPPORTED, "sg_set_schedule: tiled schedules need an all-revolute context");
+  c->schedule = schedule;
+  return SG_OK;
+}
+
+sg_status sg_get_schedule(const sg_ctx* c, int32_t* schedule) {
+  if (!c || !schedule) return SG_E_INVAL;
+  *schedule = c->schedule;
+  return SG_OK;
+}
+
+sg_status sg_autotune_step(sg_ctx* c, const void* act, int32_t trials, int32_t* best, float* ms_per_step) {
+  if (!c) return SG_E_INVAL;
+  if (!act || !aligned(act) || trials < 1 || trials > 10000) return fail(c, SG_E_INVAL, "sg_autotune_step: bad argument");
+  const size_t esz = c->dtype == SG_F64 ? sizeof(double) : sizeof(float);
+  const size_t JN = (size_t)c->J * c->N, W = 2 * (size_t)c->J + 10;
+  void *q = nullptr, *qd = nullptr, *obs = nullptr, *rew = nullptr;
+  int* pr = nullptr;
+  uint8_t* done = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&q, JN * esz);
+  if (e == hipSuccess) e = hipMalloc(&qd, JN * esz);
+  if (e == hipSuccess) e = hipMalloc((void**)&pr, c->N * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&obs, W * c->N * esz);
+  if (e == hipSuccess) e = hipMalloc(&rew, c->N * esz);
+  if (e == hipSuccess) e = hipMalloc((void**)&done, c->N);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  // save the state; every candidate starts from it and it is restored after
+  if (e == hipSuccess) e = hipMemcpyAsync(q, c->q, JN * esz, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(qd, c->qd, JN * esz, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(pr, c->prog, c->N * sizeof(int), hipMemcpyDeviceToDevice, c->stream);
+  const int saved = c->schedule;
+  const int n_sched = (c->dtype == SG_F32 && !c->prismatic) ? 4 : 1;
+  float best_ms = 0.f;
+  int best_s = SG_SCHED_PADDED;
+  for (int s = 0; s < 4 && e == hipSuccess; ++s) {
+    if (ms_per_step) ms_per_step[s] = -1.f;
+    if (s >= n_sched) continue;
+    c->schedule = s;
+    for (int k = 0; k <= trials && e == hipSuccess; ++k) {
+      if (k == 1) e = hipEventRecord(e0, c->stream);
+      if (e == hipSuccess) e = sgk::launch_step(c, act, obs, rew, done);
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)trials;
+    if (ms_per_step) ms_per_step[s] = ms;
+    if (s == 0 || ms < best_ms) {
+      best_ms = ms;
+      best_s = s;
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(c->q, q, JN * esz, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->qd, qd, JN * esz, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->prog, pr, c->N * sizeof(int), hipMemcpyDeviceToDevice, c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  c->schedule = e == hipSuccess ? best_s : saved;
+  if (best && e == hipSuccess) *best = best_s;
+  void* ptrs[] = {q, qd, pr, obs, rew, done};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_autotune_step");
 }
 
 sg_status sg_observe(sg_ctx* c, void* obs) {

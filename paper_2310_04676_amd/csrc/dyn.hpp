@@ -1,5 +1,6 @@
-// Per-lane rigid-body dynamics of a fixed-base revolute serial chain, for
-// CDNA4 (gfx950): one environment per lane, the whole chain in VGPRs.
+// Per-lane rigid-body dynamics of a fixed-base serial chain of revolute and
+// prismatic joints, for CDNA4 (gfx950): one environment per lane, the whole
+// chain in VGPRs.
 //
 // Algorithms (Featherstone, "Rigid Body Dynamics Algorithms", 2008):
 //   * ABA (Table 7.1): pass 1 outward (joint transforms, velocities,
@@ -9,8 +10,11 @@
 //     the base acceleration a0 = (0; -g)).
 //   * RNEA (Table 5.1) for inverse dynamics.
 // Spatial conventions: motion (w; v), force (n; f), X_j = rot(R_j^T)
-// xlt(offset_j) from link j-1 to link j coordinates, R_j = rotation by q_j
-// about axis_j (Rodrigues), S_j = (axis_j; 0).
+// xlt(offset_j) from link j-1 to link j coordinates. Revolute joint:
+// R_j = rotation by q_j about axis_j (Rodrigues), S_j = (axis_j; 0).
+// Prismatic joint (Featherstone Table 4.1): R_j = 1, the origin slides to
+// offset_j + q_j axis_j, S_j = (0; axis_j). Parameter sources whose kPris is
+// false compile the revolute-only code.
 //
 // Link inertias are rigid-body ones held as (m, h = m c, I_O): mass, first
 // moment and rotational inertia about the link origin, 10 numbers; the
@@ -28,12 +32,15 @@ enum {
   P_M,                           // mass
   P_HX, P_HY, P_HZ,              // first moment m c
   P_IXX, P_IYY, P_IZZ, P_IXY, P_IXZ, P_IYZ,  // inertia about the link origin
-  P_KP, P_KD, P_LO, P_HI, P_Q0,
-  P_NFIELDS
+  P_KP, P_KD, P_LO, P_HI,
+  P_PR,                          // 1 prismatic, 0 revolute
+  P_Q0,                          // reset position (not staged)
+  P_NFIELDS,
+  P_NSTAGE = P_Q0                // fields the kernels read per pass
 };
 
 template <typename T> struct Jp {
-  T ax, ay, az, ox, oy, oz, m, hx, hy, hz, ixx, iyy, izz, ixy, ixz, iyz, kp, kd, lo, hi;
+  T ax, ay, az, ox, oy, oz, m, hx, hy, hz, ixx, iyy, izz, ixy, ixz, iyz, kp, kd, lo, hi, pr;
 };
 
 __device__ __forceinline__ void sc(float x, float* s, float* c) { sincosf(x, s, c); }
@@ -52,6 +59,7 @@ __device__ __forceinline__ void load_joint(const T* __restrict__ par, int J, int
   p.ixx = b[P_IXX * fs]; p.iyy = b[P_IYY * fs]; p.izz = b[P_IZZ * fs];
   p.ixy = b[P_IXY * fs]; p.ixz = b[P_IXZ * fs]; p.iyz = b[P_IYZ * fs];
   p.kp = b[P_KP * fs]; p.kd = b[P_KD * fs]; p.lo = b[P_LO * fs]; p.hi = b[P_HI * fs];
+  p.pr = b[P_PR * fs];
 }
 
 // Rotation by angle (s = sin, c = cos) about unit axis a, row-major R[9].
@@ -182,19 +190,22 @@ __device__ __forceinline__ void congruence_acc(const T* R, const Jp<T>& p, const
 }
 
 // Sources of per-joint link parameters for the dynamics below. RegPar holds
-// them in registers; LdsPar reads them from an LDS block [P_NFIELDS][J][64]
+// them in registers; LdsPar reads them from an LDS block [P_NSTAGE][J][64]
 // on every use. LdsPar::fence() re-derives the lane offset opaquely, so the
 // compiler cannot hoist the reads of one pass into registers held through
 // the next: each pass reloads what it needs instead of keeping ~20 values
-// per joint live across the whole solve.
-template <typename T, int J> struct RegPar {
+// per joint live across the whole solve. PR selects chains that may hold
+// prismatic joints.
+template <typename T, int J, bool PR = false> struct RegPar {
+  static constexpr bool kPris = PR;
   Jp<T> P[J];
   __device__ __forceinline__ Jp<T> get(int j) const { return P[j]; }
   __device__ __forceinline__ void fence() {}
 };
 
-template <typename T, int J> struct LdsPar {
-  const T* sp;  // [P_NFIELDS][J][64]
+template <typename T, int J, bool PR = false> struct LdsPar {
+  static constexpr bool kPris = PR;
+  const T* sp;  // [P_NSTAGE][J][64]
   int lane;
   __device__ __forceinline__ void fence() { asm volatile("" : "+v"(lane)); }
   __device__ __forceinline__ T f(int field, int j) const { return sp[(field * J + j) * 64 + lane]; }
@@ -207,9 +218,24 @@ template <typename T, int J> struct LdsPar {
     p.ixx = f(P_IXX, j); p.iyy = f(P_IYY, j); p.izz = f(P_IZZ, j);
     p.ixy = f(P_IXY, j); p.ixz = f(P_IXZ, j); p.iyz = f(P_IYZ, j);
     p.kp = f(P_KP, j); p.kd = f(P_KD, j); p.lo = f(P_LO, j); p.hi = f(P_HI, j);
+    p.pr = PR ? f(P_PR, j) : T(0);
     return p;
   }
 };
+
+// Joint kind of p under source PS. For a prismatic joint the origin is moved
+// along the axis by q (the joint's rotation is the identity, taken as
+// sin 0 = 0, cos 0 = 1). Returns true for a prismatic joint.
+template <class PS, typename T> __device__ __forceinline__ bool slide(Jp<T>& p, T q) {
+  if constexpr (PS::kPris) {
+    const bool pr = p.pr != T(0);
+    const T d = pr ? q : T(0);
+    p.ox += d * p.ax; p.oy += d * p.ay; p.oz += d * p.az;
+    return pr;
+  } else {
+    return false;
+  }
+}
 
 // Forward dynamics for one env: qdd = (H + diag(arm))^-1 (tau - C).
 // Joints j >= n are skipped. grav = base-frame gravity. Only sin/cos of each
@@ -225,21 +251,31 @@ __device__ __forceinline__ void aba(PS& ps, int n, const T (&q)[J], const T (&qd
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j < n) {
-      const Jp<T> p = ps.get(j);
-      sc(q[j], &sn[j], &cs[j]);
+      Jp<T> p = ps.get(j);
+      const bool pr = slide<PS>(p, q[j]);
+      sc(pr ? T(0) : q[j], &sn[j], &cs[j]);
       T R[9];
       rodrigues(p, sn[j], cs[j], R);
       T vn[6];
       xmotion(R, p, v, vn);
-      const T wx = p.ax * qd[j], wy = p.ay * qd[j], wz = p.az * qd[j];
+      const T qw = pr ? T(0) : qd[j];
+      const T wx = p.ax * qw, wy = p.ay * qw, wz = p.az * qw;
       vn[0] += wx; vn[1] += wy; vn[2] += wz;
-      // c = v x (S qd) with S qd = (wJ; 0): (w x wJ; v x wJ)
+      // c = v x (S qd) with S qd = (wJ; lJ): (w x wJ; v x wJ + w x lJ)
       cj[j][0] = vn[1] * wz - vn[2] * wy;
       cj[j][1] = vn[2] * wx - vn[0] * wz;
       cj[j][2] = vn[0] * wy - vn[1] * wx;
       cj[j][3] = vn[4] * wz - vn[5] * wy;
       cj[j][4] = vn[5] * wx - vn[3] * wz;
       cj[j][5] = vn[3] * wy - vn[4] * wx;
+      if constexpr (PS::kPris) {
+        const T qv = pr ? qd[j] : T(0);
+        const T lx = p.ax * qv, ly = p.ay * qv, lz = p.az * qv;
+        vn[3] += lx; vn[4] += ly; vn[5] += lz;
+        cj[j][3] += vn[1] * lz - vn[2] * ly;
+        cj[j][4] += vn[2] * lx - vn[0] * lz;
+        cj[j][5] += vn[0] * ly - vn[1] * lx;
+      }
       T Iv[6];
       rigid_mul(p, vn, Iv);
       // p = v x* (I v) = (w x n + v x f; w x f)
@@ -264,7 +300,8 @@ __device__ __forceinline__ void aba(PS& ps, int n, const T (&q)[J], const T (&qd
 #pragma unroll
   for (int j = J - 1; j >= 0; --j) {
     if (j < n) {
-      const Jp<T> p = ps.get(j);
+      Jp<T> p = ps.get(j);
+      const bool pr = slide<PS>(p, q[j]);
       AI<T> I;
       I.A[S00] = p.ixx + acc.A[S00]; I.A[S11] = p.iyy + acc.A[S11]; I.A[S22] = p.izz + acc.A[S22];
       I.A[S01] = p.ixy + acc.A[S01]; I.A[S02] = p.ixz + acc.A[S02]; I.A[S12] = p.iyz + acc.A[S12];
@@ -276,16 +313,27 @@ __device__ __forceinline__ void aba(PS& ps, int n, const T (&q)[J], const T (&qd
       T pa[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) pa[k] = pj[j][k] + accp[k];
-      // U = IA S = (A a; B^T a)
-      U[j][0] = I.A[S00] * p.ax + I.A[S01] * p.ay + I.A[S02] * p.az;
-      U[j][1] = I.A[S01] * p.ax + I.A[S11] * p.ay + I.A[S12] * p.az;
-      U[j][2] = I.A[S02] * p.ax + I.A[S12] * p.ay + I.A[S22] * p.az;
-      U[j][3] = I.B[0] * p.ax + I.B[3] * p.ay + I.B[6] * p.az;
-      U[j][4] = I.B[1] * p.ax + I.B[4] * p.ay + I.B[7] * p.az;
-      U[j][5] = I.B[2] * p.ax + I.B[5] * p.ay + I.B[8] * p.az;
-      const T D = U[j][0] * p.ax + U[j][1] * p.ay + U[j][2] * p.az + arm[j];
-      invD[j] = T(1) / D;
-      uj[j] = tau[j] - (pa[0] * p.ax + pa[1] * p.ay + pa[2] * p.az);
+      if (!pr) {
+        // U = IA S = (A a; B^T a)
+        U[j][0] = I.A[S00] * p.ax + I.A[S01] * p.ay + I.A[S02] * p.az;
+        U[j][1] = I.A[S01] * p.ax + I.A[S11] * p.ay + I.A[S12] * p.az;
+        U[j][2] = I.A[S02] * p.ax + I.A[S12] * p.ay + I.A[S22] * p.az;
+        U[j][3] = I.B[0] * p.ax + I.B[3] * p.ay + I.B[6] * p.az;
+        U[j][4] = I.B[1] * p.ax + I.B[4] * p.ay + I.B[7] * p.az;
+        U[j][5] = I.B[2] * p.ax + I.B[5] * p.ay + I.B[8] * p.az;
+        invD[j] = T(1) / (U[j][0] * p.ax + U[j][1] * p.ay + U[j][2] * p.az + arm[j]);
+        uj[j] = tau[j] - (pa[0] * p.ax + pa[1] * p.ay + pa[2] * p.az);
+      } else {
+        // prismatic: U = IA (0; a) = (B a; C a)
+        U[j][0] = I.B[0] * p.ax + I.B[1] * p.ay + I.B[2] * p.az;
+        U[j][1] = I.B[3] * p.ax + I.B[4] * p.ay + I.B[5] * p.az;
+        U[j][2] = I.B[6] * p.ax + I.B[7] * p.ay + I.B[8] * p.az;
+        U[j][3] = I.C[S00] * p.ax + I.C[S01] * p.ay + I.C[S02] * p.az;
+        U[j][4] = I.C[S01] * p.ax + I.C[S11] * p.ay + I.C[S12] * p.az;
+        U[j][5] = I.C[S02] * p.ax + I.C[S12] * p.ay + I.C[S22] * p.az;
+        invD[j] = T(1) / (U[j][3] * p.ax + U[j][4] * p.ay + U[j][5] * p.az + arm[j]);
+        uj[j] = tau[j] - (pa[3] * p.ax + pa[4] * p.ay + pa[5] * p.az);
+      }
       if (j > 0) {
         T Ud[6];
 #pragma unroll
@@ -326,7 +374,8 @@ __device__ __forceinline__ void aba(PS& ps, int n, const T (&q)[J], const T (&qd
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j < n) {
-      const Jp<T> p = ps.get(j);
+      Jp<T> p = ps.get(j);
+      const bool pr = slide<PS>(p, q[j]);
       T R[9];
       rodrigues(p, sn[j], cs[j], R);
       T an[6];
@@ -335,7 +384,12 @@ __device__ __forceinline__ void aba(PS& ps, int n, const T (&q)[J], const T (&qd
       for (int k = 0; k < 6; ++k) an[k] += cj[j][k];
       T dot = U[j][0] * an[0] + U[j][1] * an[1] + U[j][2] * an[2] + U[j][3] * an[3] + U[j][4] * an[4] + U[j][5] * an[5];
       qdd[j] = (uj[j] - dot) * invD[j];
-      an[0] += p.ax * qdd[j]; an[1] += p.ay * qdd[j]; an[2] += p.az * qdd[j];
+      const T qw = pr ? T(0) : qdd[j];
+      an[0] += p.ax * qw; an[1] += p.ay * qw; an[2] += p.az * qw;
+      if constexpr (PS::kPris) {
+        const T qv = pr ? qdd[j] : T(0);
+        an[3] += p.ax * qv; an[4] += p.ay * qv; an[5] += p.az * qv;
+      }
 #pragma unroll
       for (int k = 0; k < 6; ++k) a[k] = an[k];
     } else {
@@ -355,18 +409,28 @@ __device__ __forceinline__ void rnea(PS& ps, int n, const T (&q)[J], const T (&q
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j < n) {
-      const Jp<T> p = ps.get(j);
-      sc(q[j], &sn[j], &cs[j]);
+      Jp<T> p = ps.get(j);
+      const bool pr = slide<PS>(p, q[j]);
+      sc(pr ? T(0) : q[j], &sn[j], &cs[j]);
       T R[9];
       rodrigues(p, sn[j], cs[j], R);
       T vn[6], an[6];
       xmotion(R, p, v, vn);
       xmotion(R, p, a, an);
-      const T wx = p.ax * qd[j], wy = p.ay * qd[j], wz = p.az * qd[j];
+      const T qw = pr ? T(0) : qd[j], qaw = pr ? T(0) : qdd[j];
+      const T wx = p.ax * qw, wy = p.ay * qw, wz = p.az * qw;
       vn[0] += wx; vn[1] += wy; vn[2] += wz;
-      an[0] += p.ax * qdd[j] + (vn[1] * wz - vn[2] * wy);
-      an[1] += p.ay * qdd[j] + (vn[2] * wx - vn[0] * wz);
-      an[2] += p.az * qdd[j] + (vn[0] * wy - vn[1] * wx);
+      if constexpr (PS::kPris) {
+        const T qv = pr ? qd[j] : T(0), qav = pr ? qdd[j] : T(0);
+        const T lx = p.ax * qv, ly = p.ay * qv, lz = p.az * qv;
+        vn[3] += lx; vn[4] += ly; vn[5] += lz;
+        an[3] += p.ax * qav + (vn[1] * lz - vn[2] * ly);
+        an[4] += p.ay * qav + (vn[2] * lx - vn[0] * lz);
+        an[5] += p.az * qav + (vn[0] * ly - vn[1] * lx);
+      }
+      an[0] += p.ax * qaw + (vn[1] * wz - vn[2] * wy);
+      an[1] += p.ay * qaw + (vn[2] * wx - vn[0] * wz);
+      an[2] += p.az * qaw + (vn[0] * wy - vn[1] * wx);
       an[3] += vn[4] * wz - vn[5] * wy;
       an[4] += vn[5] * wx - vn[3] * wz;
       an[5] += vn[3] * wy - vn[4] * wx;
@@ -388,11 +452,12 @@ __device__ __forceinline__ void rnea(PS& ps, int n, const T (&q)[J], const T (&q
 #pragma unroll
   for (int j = J - 1; j >= 0; --j) {
     if (j < n) {
-      const Jp<T> p = ps.get(j);
+      Jp<T> p = ps.get(j);
+      const bool pr = slide<PS>(p, q[j]);
       T ft[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) ft[k] = f[j][k] + fc[k];
-      tau[j] = p.ax * ft[0] + p.ay * ft[1] + p.az * ft[2];
+      tau[j] = pr ? p.ax * ft[3] + p.ay * ft[4] + p.az * ft[5] : p.ax * ft[0] + p.ay * ft[1] + p.az * ft[2];
       T R[9];
       rodrigues(p, sn[j], cs[j], R);
       xforce_T(R, p, ft, fc);
@@ -403,7 +468,7 @@ __device__ __forceinline__ void rnea(PS& ps, int n, const T (&q)[J], const T (&q
 }
 
 // Tool-tip position: p_j = p_{j-1} + R_{j-1} o_j, R_j = R_{j-1} Rot(a_j, q_j),
-// tip = p + R tip_local.
+// tip = p + R tip_local (prismatic: o_j + q_j a_j, no rotation).
 template <typename T, int J, class PS>
 __device__ __forceinline__ void tip_fk(PS& ps, int n, const T (&q)[J], const T* tipl, T* out) {
   T W[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)};
@@ -412,12 +477,13 @@ __device__ __forceinline__ void tip_fk(PS& ps, int n, const T (&q)[J], const T* 
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j < n) {
-      const Jp<T> p = ps.get(j);
+      Jp<T> p = ps.get(j);
+      const bool pr = slide<PS>(p, q[j]);
       px += W[0] * p.ox + W[1] * p.oy + W[2] * p.oz;
       py += W[3] * p.ox + W[4] * p.oy + W[5] * p.oz;
       pz += W[6] * p.ox + W[7] * p.oy + W[8] * p.oz;
       T s, c, Rj[9], Wn[9];
-      sc(q[j], &s, &c);
+      sc(pr ? T(0) : q[j], &s, &c);
       rodrigues(p, s, c, Rj);
 #pragma unroll
       for (int r = 0; r < 3; ++r)

@@ -13,6 +13,10 @@
 namespace sgk {
 
 enum { TASK_REACH = 0, TASK_PATH = 1 };
+// Kernel variants: per-env joint counts (M_GEN); every env with exactly the
+// kernel's J joints, so the per-joint guards fold away (M_UNI); per-env
+// joint counts with revolute and prismatic joints (M_PRI).
+enum { M_GEN = 0, M_UNI = 1, M_PRI = 2 };
 enum { DONE_ENDED = 1, DONE_TIMEOUT = 2, DONE_NONFINITE = 4 };
 
 template <typename T> struct EnvDev {
@@ -30,20 +34,20 @@ template <typename T> struct EnvDev {
 };
 
 // Link parameters of env e into registers (joints < n).
-template <typename T, int J>
-__device__ __forceinline__ void load_chain(const EnvDev<T>& E, int e, int n, RegPar<T, J>& rp) {
+template <typename T, int J, bool PR>
+__device__ __forceinline__ void load_chain(const EnvDev<T>& E, int e, int n, RegPar<T, J, PR>& rp) {
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j < n) load_joint(E.par, E.J, E.N, j, e, rp.P[j]);
   }
 }
 
-// Stage the link parameters of a 64-env block into LDS [P_NFIELDS][J][64]
+// Stage the link parameters of a 64-env block into LDS [P_NSTAGE][J][64]
 // (joints >= n zero). Every lane of the block calls it; the caller
 // synchronizes before use.
 template <typename T, int J>
 __device__ __forceinline__ void stage_chain(const EnvDev<T>& E, int e, int n, int lane, T* sp) {
-  for (int f = 0; f < P_NFIELDS; ++f)
+  for (int f = 0; f < P_NSTAGE; ++f)
 #pragma unroll
     for (int j = 0; j < J; ++j)
       sp[(f * J + j) * 64 + lane] = (j < n) ? E.par[((size_t)f * E.J + j) * E.N + e] : T(0);
@@ -136,6 +140,12 @@ __device__ __forceinline__ void write_obs(const EnvDev<T>& E, int e, int n, cons
       obs[(size_t)j * N + e] = j < n ? q[j] : T(0);
       obs[(size_t)(E.J + j) * N + e] = j < n ? qd[j] : T(0);
     }
+  }
+  // a kernel specialised for fewer joints than the context's max_dof (DOF-
+  // class tiles) still owns the padded rows
+  for (int j = J; j < E.J; ++j) {
+    obs[(size_t)j * N + e] = T(0);
+    obs[(size_t)(E.J + j) * N + e] = T(0);
   }
   T* o = obs + (size_t)(2 * E.J) * N + e;
   const T dx = g[0] - tip[0], dy = g[1] - tip[1], dz = g[2] - tip[2];

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/surgym.h"
 #include "env.hpp"
@@ -11,7 +12,8 @@
 struct sg_ctx {
   int device = 0;
   int N = 0, J = 0, dtype = SG_F32, S = 1;
-  bool uniform = false;  // every env has J joints and J is a kernel instantiation
+  bool uniform = false;    // every env has J joints and J is a kernel instantiation
+  bool prismatic = false;  // some env has a prismatic joint
   int task = 0, K = 0, dwell = 1, ep_len = 0;
   double dt = 0, g[3] = {0, 0, 0};
   uint64_t seed = 0, rng_step = 0;
@@ -26,6 +28,13 @@ struct sg_ctx {
   void* q = nullptr;        // [J][N]
   void* qd = nullptr;       // [J][N]
   int* prog = nullptr;      // [N]
+  // DOF-class tiling for uneven batches: slots sorted by n_dof, each class
+  // padded to whole 64-slot tiles (slot_env = -1 for padding).
+  int schedule = 0;               // SG_SCHED_*
+  int n_tiles = 0;
+  int* slot_env = nullptr;        // [n_tiles * 64]
+  int* tile_dof = nullptr;        // [n_tiles]
+  std::vector<int> cls_dof, cls_tile0, cls_ntiles;  // per DOF class (host)
   // policy (FP32 contexts)
   int has_policy = 0, h1 = 0, h2 = 0;
   uint16_t* w_bf16 = nullptr;  // W1 | W2 | W3 row-major BF16

@@ -1,0 +1,192 @@
+// Training primitives shared by the learned surrogate and the PPO update:
+// a BF16 MFMA GEMM (gfx950 v_mfma_f32_16x16x32_bf16, FP32 accumulation)
+// with fused epilogues, a deterministic split-K path for the batch
+// reductions of weight gradients, column sums and Adam.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mlp.hpp"
+
+namespace sgk {
+
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  __bf16 b = (__bf16)x;  // round to nearest even
+  return *reinterpret_cast<uint16_t*>(&b);
+}
+__device__ __forceinline__ float bf16_val(uint16_t u) { return __uint_as_float((uint32_t)u << 16); }
+
+__device__ __forceinline__ float elu_f(float x) { return x > 0.f ? x : __expf(x) - 1.f; }
+__device__ __forceinline__ float elu_grad_f(float z) { return z > 0.f ? 1.f : __expf(z); }
+
+// Hidden-unit activations: ELU (surrogate), tanh (policy; the same formula
+// as the rollout's forward pass, so both see the same activations).
+enum { ACT_ELU = 0, ACT_TANH = 1 };
+template <int ACT> __device__ __forceinline__ float act_f(float z) {
+  return ACT == ACT_ELU ? elu_f(z) : tanh_fast(z);
+}
+template <int ACT> __device__ __forceinline__ float act_grad(float z) {
+  if (ACT == ACT_ELU) return elu_grad_f(z);
+  const float t = tanh_fast(z);
+  return 1.f - t * t;
+}
+
+// C[m][n] = sum_k A(m, k) B(k, n) (+ epilogue), BF16 inputs, FP32
+// accumulation. A(m, k) = A[AT ? k*lda + m : m*lda + k],
+// B(k, n) = B[BT ? n*ldb + k : k*ldb + n]. Epilogues:
+//   EPI_FWD_HIDDEN  z + bias -> C (FP32), act(z) -> Cb (BF16)
+//   EPI_FWD_OUT     z + bias -> C
+//   EPI_PLAIN       z -> C
+//   EPI_BWD_DX      z act'(Zp) -> C and Cb (backward through the unit)
+//   EPI_PARTIAL     block z of the grid sums K in [z kchunk, (z+1) kchunk)
+//                   and writes its partial to C + z M ldc (split-K; reduce
+//                   with k_sum_splits)
+enum { EPI_FWD_HIDDEN = 0, EPI_FWD_OUT = 1, EPI_PLAIN = 2, EPI_BWD_DX = 3, EPI_PARTIAL = 4 };
+
+struct GemmArgs {
+  int M, N, K;
+  const uint16_t* A;
+  int lda;
+  const uint16_t* B;
+  int ldb;
+  float* C;          // fp32 output [M][ldc] (split-K: [splits][M][ldc])
+  int ldc;
+  const float* bias; // [N] (forward)
+  uint16_t* Cb;      // bf16 output [M][ldc] (act(z) forward, gradient backward)
+  const float* Zp;   // pre-activations of the previous layer [M][ldc] (backward data)
+  int kchunk;        // split-K chunk (multiple of 32)
+};
+
+template <int EPI, bool AT, bool BT, int ACT>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  __shared__ __align__(16) uint16_t As[64][40];  // 32 k + 8 pad
+  __shared__ __align__(16) uint16_t Bs[64][40];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int gi = lane >> 4, li = lane & 15;
+  int kbeg = 0, kend = g.K;
+  float* C = g.C;
+  if (EPI == EPI_PARTIAL) {
+    kbeg = blockIdx.z * g.kchunk;
+    kend = min(g.K, kbeg + g.kchunk);
+    C += (size_t)blockIdx.z * g.M * g.ldc;
+  }
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int lr = tid >> 2, lk = (tid & 3) * 8;  // loader: row / first k of 8
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int m = m0 + lr, k = k0 + lk + s, n = n0 + lr;
+      uint16_t av = 0, bv = 0;
+      if (m < g.M && k < kend) av = AT ? g.A[(size_t)k * g.lda + m] : g.A[(size_t)m * g.lda + k];
+      if (n < g.N && k < kend) bv = BT ? g.B[(size_t)n * g.ldb + k] : g.B[(size_t)k * g.ldb + n];
+      As[lr][lk + s] = av;
+      Bs[lr][lk + s] = bv;
+    }
+    __syncthreads();
+    bf16x8 af[2], bfr[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      af[t] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * t + li][8 * gi]);
+      bfr[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * t + li][8 * gi]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x32(af[a], bfr[b], acc[a][b]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * a + 4 * gi + r, n = n0 + wn + 16 * b + li;
+        if (m >= g.M || n >= g.N) continue;
+        const size_t i = (size_t)m * g.ldc + n;
+        float z = acc[a][b][r];
+        if (EPI == EPI_FWD_HIDDEN || EPI == EPI_FWD_OUT) z += g.bias[n];
+        if (EPI == EPI_BWD_DX) z *= act_grad<ACT>(g.Zp[i]);
+        C[i] = z;
+        if (EPI == EPI_FWD_HIDDEN) g.Cb[i] = bf16_bits(act_f<ACT>(z));
+        if (EPI == EPI_BWD_DX) g.Cb[i] = bf16_bits(z);
+      }
+}
+
+template <int EPI, bool AT, bool BT, int ACT>
+static inline void launch_gemm(hipStream_t s, const GemmArgs& a, int splits = 1) {
+  dim3 grid((a.N + 63) / 64, (a.M + 63) / 64, EPI == EPI_PARTIAL ? splits : 1);
+  k_gemm<EPI, AT, BT, ACT><<<grid, 256, 0, s>>>(a);
+}
+
+// out[i * ldo + j] = sum_z part[z][i][j] over `splits` slabs of [M][N]
+// (fixed order: deterministic).
+static __global__ void __launch_bounds__(256) k_sum_splits(const float* __restrict__ part, int splits, int M, int N,
+                                                           float* __restrict__ out, int ldo) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= M * N) return;
+  const int i = t / N, j = t % N;
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += part[(size_t)z * M * N + t];
+  out[(size_t)i * ldo + j] = s;
+}
+
+// db[c] = sum_r G[r][c].
+static __global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ G, int rows, int cols,
+                                                       float* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += G[(size_t)r * cols + c];
+  out[c] = s;
+}
+
+// Column sums of G [rows][ldg] (cols used) in row chunks: partial
+// [gridDim.y][cols]; block (x, y) covers 64 columns of rows
+// [y chunk, (y+1) chunk), four threads per column.
+static __global__ void __launch_bounds__(256) k_colsum_part(const float* __restrict__ G, int rows, int cols, int ldg,
+                                                            int chunk, float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
+  float s = 0.f;
+  if (c < cols)
+    for (int r = r0 + q; r < r1; r += 4) s += G[(size_t)r * ldg + c];
+  red[q][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (q == 0 && c < cols)
+    part[(size_t)blockIdx.y * cols + c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                          (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// Adam (Kingma & Ba) with bias correction c1 = 1 - beta1^t, c2 = 1 - beta2^t
+// passed in; optional BF16 copy of the updated weights.
+static __global__ void __launch_bounds__(256) k_adam(int n, float* __restrict__ w, const float* __restrict__ g,
+                                                     float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                                                     float b2, float eps, float c1, float c2,
+                                                     uint16_t* __restrict__ wb) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  if (wb) wb[i] = bf16_bits(wi);
+}
+
+static __global__ void __launch_bounds__(256) k_to_bf16(int n, const float* __restrict__ w,
+                                                        uint16_t* __restrict__ wb) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) wb[i] = bf16_bits(w[i]);
+}
+
+}  // namespace sgk

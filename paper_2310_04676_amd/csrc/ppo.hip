@@ -1,0 +1,581 @@
+// PPO update of the rollout policy on the GPU (the paper trains its policies
+// with the GPU PPO of Rudin et al., Sec. III "Policy learning and control";
+// objective: the clipped surrogate of Schulman et al., 2017, with a clipped
+// value loss and an entropy bonus).
+//
+// One minibatch of B samples (rows) taken from the rollout buffers:
+//   k_ppo_gather   obs rows -> BF16 X [B][32]
+//   forward        three BF16 MFMA GEMMs (nn.hpp), tanh units; the
+//                  pre-activations stay in HBM for the backward pass
+//   k_ppo_loss     ratio, clipped objectives, dL/d(outputs) [B][8] and the
+//                  per-row log_std gradient; loss statistics
+//   backward       data gradients as GEMMs with the tanh' epilogue; weight
+//                  gradients as split-K GEMMs (the batch is the reduction
+//                  axis) summed in a fixed order; bias and log_std
+//                  gradients as split column sums -- deterministic
+//   k_ppo_gnorm    entropy term and the global gradient norm
+//   k_ppo_adam     norm clip + Adam on the FP32 master weights + BF16 copy
+// After an update k_ppo_pack rewrites the context's rollout weight image
+// (the MFMA fragment order of mlp.hpp), biases and log_std from the master
+// weights, so the next rollout samples from the updated policy.
+#include <cmath>
+
+#include "internal.hpp"
+#include "mlp.hpp"
+#include "nn.hpp"
+
+struct sg_ppo {
+  sg_ctx* ctx = nullptr;
+  int J = 0, W = 0, O = 0, P = 0;
+  int off[7] = {0, 0, 0, 0, 0, 0, 0};  // W1 b1 W2 b2 W3 b3 log_std
+  int max_samples = 0;
+  int t = 0;                 // Adam steps taken
+  float* p = nullptr;        // master parameters [P]
+  uint16_t* pb = nullptr;    // BF16 copy [P]
+  float* g = nullptr;        // gradient [P]
+  float* m = nullptr;        // Adam moments [P]
+  float* v = nullptr;
+  float* an = nullptr;       // normalised advantages [max_samples]
+  float* scal = nullptr;     // [0] adv mean, [1] adv sd, [2] |g|
+  uint16_t* X = nullptr;     // [rows][32]
+  float* Z1 = nullptr;       // [rows][256]
+  uint16_t* H1 = nullptr;
+  float* Z2 = nullptr;       // [rows][128]
+  uint16_t* H2 = nullptr;
+  float* Z3 = nullptr;       // [rows][8]
+  float* G3 = nullptr;       // [rows][8]
+  uint16_t* G3b = nullptr;
+  float* DL = nullptr;       // [rows][8] per-row log_std gradient
+  float* D2 = nullptr;       // [rows][128]
+  uint16_t* D2b = nullptr;
+  float* D1 = nullptr;       // [rows][256]
+  uint16_t* D1b = nullptr;
+  float* ws = nullptr;       // split-K / column-sum partials
+  size_t ws_floats = 0;
+  std::vector<void*> allocs;
+};
+
+namespace sgk {
+
+constexpr int kPX = 32;   // padded input width
+constexpr int kPO = 8;    // padded output width (J + 1 <= 8)
+constexpr int kColChunk = 256;  // rows per column-sum partial
+
+struct PpoRows {
+  const float* obs;   // [T+1][W][N]
+  const float* act;   // [T][J][N]
+  const float* logp;  // [T][N]
+  const float* val;   // [T+1][N]
+  const float* ret;   // [T][N]
+  const float* an;    // normalised advantages [T N]
+  const int* idx;     // sample of row r (null: r0 + r)
+  int r0, rows, N, J, W, total;
+};
+
+__device__ __forceinline__ int ppo_sample(const PpoRows& a, int r) { return a.idx ? a.idx[r] : a.r0 + r; }
+
+__global__ void __launch_bounds__(256) k_ppo_gather(PpoRows a, uint16_t* __restrict__ X) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= a.rows) return;
+  const int s = ppo_sample(a, r);
+  const bool ok = s >= 0 && s < a.total;
+  const int t = ok ? s / a.N : 0, e = ok ? s % a.N : 0;
+  for (int k = 0; k < kPX; ++k) {
+    const float x = (ok && k < a.W) ? a.obs[((size_t)t * a.W + k) * a.N + e] : 0.f;
+    X[(size_t)r * kPX + k] = bf16_bits(x);
+  }
+}
+
+// Mean and unbiased standard deviation of n values (one block, two passes
+// in double): out[0] = mean, out[1] = sd.
+__global__ void __launch_bounds__(1024) k_adv_stats(const float* __restrict__ x, int n, float* __restrict__ out) {
+  __shared__ double red[1024];
+  double s = 0;
+  for (int i = threadIdx.x; i < n; i += 1024) s += x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double mean = red[0] / n;
+  __syncthreads();
+  double q = 0;
+  for (int i = threadIdx.x; i < n; i += 1024) q += (x[i] - mean) * (x[i] - mean);
+  red[threadIdx.x] = q;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = (float)mean;
+    out[1] = n > 1 ? (float)sqrt(red[0] / (n - 1)) : 0.f;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_adv_norm(const float* __restrict__ adv, int n, const float* __restrict__ st,
+                                                  float* __restrict__ an) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) an[i] = (adv[i] - st[0]) / (st[1] + 1e-8f);
+}
+
+struct PpoLossArgs {
+  PpoRows rows;
+  const float* Z3;      // [rows][8] network outputs (mu | V)
+  const float* ls;      // log_std [J]
+  float clip, c_v;
+  float inv_b;          // 1 / rows
+  float w_stats;        // weight of this minibatch in the statistics
+  float* G3;            // [rows][8]
+  uint16_t* G3b;
+  float* DL;            // [rows][8]
+  float* stats;         // loss_pi, loss_v, entropy, approx_kl, clip_frac, |g|
+};
+
+// Per row: log pi(a) under the current outputs, ratio, clipped objectives,
+// gradients w.r.t. the outputs (mu, V) and log_std.
+__global__ void __launch_bounds__(256) k_ppo_loss(PpoLossArgs a) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const PpoRows& R = a.rows;
+  float lpi = 0.f, lv = 0.f, kl = 0.f, cf = 0.f;
+  if (r < R.rows) {
+    const int s = ppo_sample(R, r);
+    const bool ok = s >= 0 && s < R.total;
+    float g[kPO], dl[kPO];
+#pragma unroll
+    for (int k = 0; k < kPO; ++k) { g[k] = 0.f; dl[k] = 0.f; }
+    if (ok) {
+      const int t = s / R.N, e = s % R.N, J = R.J;
+      const float* z = a.Z3 + (size_t)r * kPO;
+      float logp = 0.f;
+      float u[kPO];
+      for (int j = 0; j < J; ++j) {
+        const float sig = __expf(a.ls[j]);
+        u[j] = (R.act[((size_t)t * J + j) * R.N + e] - z[j]) / sig;
+        logp += -0.5f * u[j] * u[j] - a.ls[j] - 0.91893853320467274f;
+      }
+      const float lold = R.logp[(size_t)t * R.N + e];
+      const float A = R.an[s];
+      const float ratio = __expf(logp - lold);
+      const float rc = fminf(fmaxf(ratio, 1.f - a.clip), 1.f + a.clip);
+      lpi = -fminf(ratio * A, rc * A);
+      kl = lold - logp;
+      cf = fabsf(ratio - 1.f) > a.clip ? 1.f : 0.f;
+      const bool live = A >= 0.f ? ratio <= 1.f + a.clip : ratio >= 1.f - a.clip;
+      const float dlogp = live ? -A * ratio * a.inv_b : 0.f;
+      for (int j = 0; j < J; ++j) {
+        const float sig = __expf(a.ls[j]);
+        g[j] = dlogp * u[j] / sig;
+        dl[j] = dlogp * (u[j] * u[j] - 1.f);
+      }
+      const float V = z[J], vold = R.val[(size_t)t * R.N + e], ret = R.ret[(size_t)t * R.N + e];
+      const float dv = V - vold;
+      const float Vc = vold + fminf(fmaxf(dv, -a.clip), a.clip);
+      const float e1 = (V - ret) * (V - ret), e2 = (Vc - ret) * (Vc - ret);
+      lv = fmaxf(e1, e2);
+      float dV;
+      if (e1 >= e2) dV = 2.f * (V - ret);
+      else dV = fabsf(dv) <= a.clip ? 2.f * (Vc - ret) : 0.f;
+      g[J] = a.c_v * dV * a.inv_b;
+    }
+#pragma unroll
+    for (int k = 0; k < kPO; ++k) {
+      a.G3[(size_t)r * kPO + k] = g[k];
+      a.G3b[(size_t)r * kPO + k] = bf16_bits(g[k]);
+      a.DL[(size_t)r * kPO + k] = dl[k];
+    }
+  }
+  if (a.stats) {
+    const float w = a.w_stats * a.inv_b;
+    float v4[4] = {lpi * w, lv * w, kl * w, cf * w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      for (int o = 32; o > 0; o >>= 1) v4[k] += __shfl_down(v4[k], o, 64);
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(&a.stats[0], v4[0]);
+      atomicAdd(&a.stats[1], v4[1]);
+      atomicAdd(&a.stats[3], v4[2]);
+      atomicAdd(&a.stats[4], v4[3]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      float H = 0.f;
+      for (int j = 0; j < R.J; ++j) H += a.ls[j] + 0.5f + 0.91893853320467274f;
+      atomicAdd(&a.stats[2], H * a.w_stats);
+    }
+  }
+}
+
+// Entropy bonus on the log_std gradient, then |g| (one block, double
+// accumulation) into scal[2]; optionally into stats[5] with weight w.
+__global__ void __launch_bounds__(1024) k_ppo_gnorm(float* __restrict__ g, int P, int ls0, int J, float c_e,
+                                                    float* __restrict__ scal, float* __restrict__ stats, float w) {
+  __shared__ double red[1024];
+  double s = 0;
+  for (int i = threadIdx.x; i < P; i += 1024) {
+    float gi = g[i];
+    if (i >= ls0 && i < ls0 + J) {
+      gi -= c_e;
+      g[i] = gi;
+    }
+    s += (double)gi * gi;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 512; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float n = (float)sqrt(red[0]);
+    scal[2] = n;
+    if (stats) stats[5] += n * w;
+  }
+}
+
+// g <- g min(1, max_norm / (|g| + 1e-6)) (no clip for max_norm <= 0), then
+// Adam; BF16 copy of every updated parameter.
+__global__ void __launch_bounds__(256) k_ppo_adam(int P, float* __restrict__ p, const float* __restrict__ g,
+                                                  float* __restrict__ m, float* __restrict__ v,
+                                                  const float* __restrict__ scal, float max_norm, float lr, float b1,
+                                                  float b2, float eps, float c1, float c2, uint16_t* __restrict__ pb) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= P) return;
+  const float coef = max_norm > 0.f ? fminf(1.f, max_norm / (scal[2] + 1e-6f)) : 1.f;
+  const float gi = g[i] * coef;
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = wi;
+  pb[i] = bf16_bits(wi);
+}
+
+// Rollout weight image (fragment order of mlp.hpp; see sg_set_policy),
+// bias image and log_std from the master parameters.
+__global__ void __launch_bounds__(256) k_ppo_pack(const float* __restrict__ p, int W, int O, int J, int o1, int ob1,
+                                                  int o2, int ob2, int o3, int ob3, int ols, uint16_t* __restrict__ img,
+                                                  float* __restrict__ bias, float* __restrict__ log_std) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int n1 = kW1Frags * 8, n2 = kW2Frags * 8, n3 = kW3Frags * 8;
+  if (i < n1 + n2 + n3) {
+    const int s = i & 7, l = (i >> 3) & 63, f = i >> 9;  // slot, lane, fragment
+    const int gg = l >> 4, li = l & 15;
+    float x = 0.f;
+    if (i < n1) {
+      const int row = 16 * f + li, k = 8 * gg + s;
+      x = k < W ? p[o1 + row * W + k] : 0.f;
+    } else if (i < n1 + n2) {
+      const int f2 = f - kW1Frags, mt = f2 >> 3, kb = f2 & 7;
+      const int row = 16 * mt + li, k = 32 * kb + (s < 4 ? 4 * gg + s : 16 + 4 * gg + (s - 4));
+      x = p[o2 + row * kH1 + k];
+    } else {
+      const int kb = f - kW1Frags - kW2Frags;
+      const int row = li, k = 32 * kb + (s < 4 ? 4 * gg + s : 16 + 4 * gg + (s - 4));
+      x = row < O ? p[o3 + row * kH2 + k] : 0.f;
+    }
+    img[i] = bf16_bits(x);
+  }
+  if (i < kBiasFloats) {
+    float b = 0.f;
+    if (i < kH1) b = p[ob1 + i];
+    else if (i < kH1 + kH2) b = p[ob2 + i - kH1];
+    else if (i - kH1 - kH2 < O) b = p[ob3 + i - kH1 - kH2];
+    bias[i] = b;
+  }
+  if (i < J) log_std[i] = p[ols + i];
+}
+
+// A fill kernel rather than a memset node, so the update can be captured.
+__global__ void __launch_bounds__(256) k_zero(float* __restrict__ x, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] = 0.f;
+}
+
+static int splits_for(int tiles, int K) {
+  int s = 256 / (tiles > 0 ? tiles : 1);
+  const int kmax = (K + 31) / 32;
+  if (s > kmax) s = kmax;
+  return s < 1 ? 1 : s;
+}
+static int chunk_for(int K, int splits) { return ((K + splits - 1) / splits + 31) / 32 * 32; }
+
+// dW [M][N] (leading dim ldo) = sum over the batch with split-K.
+template <bool AT, bool BT>
+static void weight_grad(sg_ppo* o, hipStream_t st, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B,
+                        int ldb, float* out, int ldo) {
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  const int S = splits_for(tiles, K);
+  GemmArgs g{};
+  g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = o->ws; g.ldc = N;
+  g.kchunk = chunk_for(K, S);
+  const int S_eff = (K + g.kchunk - 1) / g.kchunk;
+  launch_gemm<EPI_PARTIAL, AT, BT, ACT_TANH>(st, g, S_eff);
+  k_sum_splits<<<(M * N + 255) / 256, 256, 0, st>>>(o->ws, S_eff, M, N, out, ldo);
+}
+
+static void col_sums(sg_ppo* o, hipStream_t st, const float* G, int rows, int cols, int ldg, float* out) {
+  const int nch = (rows + kColChunk - 1) / kColChunk;
+  k_colsum_part<<<dim3((cols + 63) / 64, nch), 256, 0, st>>>(G, rows, cols, ldg, kColChunk, o->ws);
+  k_sum_splits<<<(cols + 255) / 256, 256, 0, st>>>(o->ws, nch, 1, cols, out, cols);
+}
+
+// Gradient of one minibatch into o->g (entropy term included, no clip).
+static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_config* cfg, float w_stats,
+                                 float* stats) {
+  sg_ctx* c = o->ctx;
+  hipStream_t st = c->stream;
+  const int B = rows.rows, W = o->W, O = o->O, J = o->J;
+  const int gb = (B + 255) / 256;
+  k_zero<<<(o->P + 255) / 256, 256, 0, st>>>(o->g, o->P);
+  k_ppo_gather<<<gb, 256, 0, st>>>(rows, o->X);
+  GemmArgs f{};
+  // layer 1: Z1 = X W1^T + b1, H1 = tanh(Z1)
+  f.M = B; f.N = kH1; f.K = W; f.A = o->X; f.lda = kPX; f.B = o->pb + o->off[0]; f.ldb = W;
+  f.C = o->Z1; f.ldc = kH1; f.bias = o->p + o->off[1]; f.Cb = o->H1;
+  launch_gemm<EPI_FWD_HIDDEN, false, true, ACT_TANH>(st, f);
+  // layer 2
+  f.N = kH2; f.K = kH1; f.A = o->H1; f.lda = kH1; f.B = o->pb + o->off[2]; f.ldb = kH1;
+  f.C = o->Z2; f.ldc = kH2; f.bias = o->p + o->off[3]; f.Cb = o->H2;
+  launch_gemm<EPI_FWD_HIDDEN, false, true, ACT_TANH>(st, f);
+  // layer 3 (linear): [mu | V]
+  f.N = O; f.K = kH2; f.A = o->H2; f.lda = kH2; f.B = o->pb + o->off[4]; f.ldb = kH2;
+  f.C = o->Z3; f.ldc = kPO; f.bias = o->p + o->off[5]; f.Cb = nullptr;
+  launch_gemm<EPI_FWD_OUT, false, true, ACT_TANH>(st, f);
+  PpoLossArgs la;
+  la.rows = rows; la.Z3 = o->Z3; la.ls = o->p + o->off[6]; la.clip = cfg->clip; la.c_v = cfg->value_coef;
+  la.inv_b = 1.f / (float)B; la.w_stats = w_stats; la.G3 = o->G3; la.G3b = o->G3b; la.DL = o->DL; la.stats = stats;
+  k_ppo_loss<<<gb, 256, 0, st>>>(la);
+  // output layer gradients
+  weight_grad<true, false>(o, st, O, kH2, B, o->G3b, kPO, o->H2, kH2, o->g + o->off[4], kH2);
+  col_sums(o, st, o->G3, B, O, kPO, o->g + o->off[5]);
+  col_sums(o, st, o->DL, B, J, kPO, o->g + o->off[6]);
+  // dZ2 = (G3 W3) * tanh'(Z2)
+  GemmArgs d{};
+  d.M = B; d.N = kH2; d.K = O; d.A = o->G3b; d.lda = kPO; d.B = o->pb + o->off[4]; d.ldb = kH2;
+  d.C = o->D2; d.ldc = kH2; d.Cb = o->D2b; d.Zp = o->Z2;
+  launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
+  weight_grad<true, false>(o, st, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->off[2], kH1);
+  col_sums(o, st, o->D2, B, kH2, kH2, o->g + o->off[3]);
+  // dZ1 = (dZ2 W2) * tanh'(Z1)
+  d.N = kH1; d.K = kH2; d.A = o->D2b; d.lda = kH2; d.B = o->pb + o->off[2]; d.ldb = kH1;
+  d.C = o->D1; d.ldc = kH1; d.Cb = o->D1b; d.Zp = o->Z1;
+  launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
+  weight_grad<true, false>(o, st, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->off[0], W);
+  col_sums(o, st, o->D1, B, kH1, kH1, o->g + o->off[1]);
+  k_ppo_gnorm<<<1, 1024, 0, st>>>(o->g, o->P, o->off[6], J, cfg->entropy_coef, o->scal, stats, w_stats);
+  return hipGetLastError();
+}
+
+static PpoRows rows_of(const sg_ppo* o, const sg_rollout_bufs* b, int T) {
+  PpoRows r{};
+  r.obs = b->obs; r.act = b->act; r.logp = b->logp; r.val = b->val; r.ret = b->ret; r.an = o->an;
+  r.N = o->ctx->N; r.J = o->J; r.W = o->W; r.total = T * o->ctx->N;
+  return r;
+}
+
+static hipError_t normalise_adv(sg_ppo* o, const sg_rollout_bufs* b, int n) {
+  hipStream_t st = o->ctx->stream;
+  k_adv_stats<<<1, 1024, 0, st>>>(b->adv, n, o->scal);
+  k_adv_norm<<<(n + 255) / 256, 256, 0, st>>>(b->adv, n, o->scal, o->an);
+  return hipGetLastError();
+}
+
+static hipError_t pack_policy(sg_ppo* o) {
+  sg_ctx* c = o->ctx;
+  const int n = (kW1Frags + kW2Frags + kW3Frags) * 8;
+  k_ppo_pack<<<(n + 255) / 256, 256, 0, c->stream>>>(o->p, o->W, o->O, o->J, o->off[0], o->off[1], o->off[2],
+                                                     o->off[3], o->off[4], o->off[5], o->off[6], c->w_bf16, c->bias,
+                                                     c->log_std);
+  return hipGetLastError();
+}
+
+}  // namespace sgk
+
+using namespace sgk;
+
+namespace {
+
+sg_status pfail(sg_ctx* c, sg_status st, const char* msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+template <typename T> hipError_t palloc(sg_ppo* o, T** p, size_t n) {
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T) + 16);
+  if (e == hipSuccess) {
+    o->allocs.push_back(*p);
+    e = hipMemset(*p, 0, n * sizeof(T) + 16);
+  }
+  return e;
+}
+
+bool ok_cfg(const sg_ppo_config* k) {
+  return k && k->clip > 0.f && k->value_coef >= 0.f && k->lr > 0.f && k->beta1 >= 0.f && k->beta1 < 1.f &&
+         k->beta2 >= 0.f && k->beta2 < 1.f && k->adam_eps > 0.f && k->epochs >= 1 && k->minibatches >= 1;
+}
+
+bool ok_bufs(const sg_rollout_bufs* b) {
+  return b && b->obs && b->act && b->logp && b->val && b->adv && b->ret;
+}
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_ppo** out) {
+  if (!c || !out) return SG_E_INVAL;
+  *out = nullptr;
+  if (!params) return pfail(c, SG_E_INVAL, "sg_ppo_create: null params");
+  if (c->dtype != SG_F32) return pfail(c, SG_E_UNSUPPORTED, "sg_ppo_create: FP32 contexts only");
+  if (c->J > 7) return pfail(c, SG_E_UNSUPPORTED, "sg_ppo_create: max_dof <= 7");
+  if (max_samples < 1 || max_samples > (1 << 24)) return pfail(c, SG_E_INVAL, "sg_ppo_create: max_samples in 1..16M");
+  sg_ppo* o = new sg_ppo();
+  o->ctx = c;
+  o->J = c->J;
+  o->W = 2 * c->J + 10;
+  o->O = c->J + 1;
+  o->max_samples = max_samples;
+  const int sz[7] = {kH1 * o->W, kH1, kH2 * kH1, kH2, o->O * kH2, o->O, o->J};
+  int acc = 0;
+  for (int i = 0; i < 7; ++i) {
+    o->off[i] = acc;
+    acc += sz[i];
+  }
+  o->P = acc;
+  const size_t R = (size_t)max_samples, P = (size_t)o->P;
+  // split-K partials: at most 256 tiles x splits x 64 x 64, and the column
+  // sums' chunks
+  o->ws_floats = (size_t)256 * 64 * 64 + ((R + kColChunk - 1) / kColChunk) * kH1;
+  hipError_t e = palloc(o, &o->p, P);
+  if (e == hipSuccess) e = palloc(o, &o->pb, P);
+  if (e == hipSuccess) e = palloc(o, &o->g, P);
+  if (e == hipSuccess) e = palloc(o, &o->m, P);
+  if (e == hipSuccess) e = palloc(o, &o->v, P);
+  if (e == hipSuccess) e = palloc(o, &o->an, R);
+  if (e == hipSuccess) e = palloc(o, &o->scal, 8);
+  if (e == hipSuccess) e = palloc(o, &o->X, R * kPX);
+  if (e == hipSuccess) e = palloc(o, &o->Z1, R * kH1);
+  if (e == hipSuccess) e = palloc(o, &o->H1, R * kH1);
+  if (e == hipSuccess) e = palloc(o, &o->Z2, R * kH2);
+  if (e == hipSuccess) e = palloc(o, &o->H2, R * kH2);
+  if (e == hipSuccess) e = palloc(o, &o->Z3, R * kPO);
+  if (e == hipSuccess) e = palloc(o, &o->G3, R * kPO);
+  if (e == hipSuccess) e = palloc(o, &o->G3b, R * kPO);
+  if (e == hipSuccess) e = palloc(o, &o->DL, R * kPO);
+  if (e == hipSuccess) e = palloc(o, &o->D2, R * kH2);
+  if (e == hipSuccess) e = palloc(o, &o->D2b, R * kH2);
+  if (e == hipSuccess) e = palloc(o, &o->D1, R * kH1);
+  if (e == hipSuccess) e = palloc(o, &o->D1b, R * kH1);
+  if (e == hipSuccess) e = palloc(o, &o->ws, o->ws_floats);
+  if (e == hipSuccess && !c->w_bf16) e = hipMalloc((void**)&c->w_bf16, (size_t)kWFrags * 16);
+  if (e == hipSuccess && !c->bias) e = hipMalloc((void**)&c->bias, (size_t)kBiasFloats * sizeof(float));
+  if (e == hipSuccess && !c->log_std) e = hipMalloc((void**)&c->log_std, (size_t)c->J * sizeof(float));
+  if (e == hipSuccess) e = hipMemcpy(o->p, params, P * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    k_to_bf16<<<(o->P + 255) / 256, 256, 0, c->stream>>>(o->P, o->p, o->pb);
+    e = pack_policy(o);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    for (void* p : o->allocs) (void)hipFree(p);
+    delete o;
+    c->err = std::string("sg_ppo_create: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  c->has_policy = 1;
+  c->h1 = kH1;
+  c->h2 = kH2;
+  *out = o;
+  return SG_OK;
+}
+
+void sg_ppo_destroy(sg_ppo* o) {
+  if (!o) return;
+  (void)hipStreamSynchronize(o->ctx->stream);
+  for (void* p : o->allocs) (void)hipFree(p);
+  delete o;
+}
+
+int32_t sg_ppo_param_count(const sg_ppo* o) { return o ? o->P : 0; }
+
+sg_status sg_ppo_get_params(sg_ppo* o, float* params) {
+  if (!o || !params) return SG_E_INVAL;
+  hipError_t e = hipStreamSynchronize(o->ctx->stream);
+  if (e == hipSuccess) e = hipMemcpy(params, o->p, (size_t)o->P * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    o->ctx->err = std::string("sg_ppo_get_params: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  return SG_OK;
+}
+
+sg_status sg_ppo_grad(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const int32_t* idx, int32_t rows,
+                      const sg_ppo_config* cfg, float* grad, float* stats) {
+  if (!o) return SG_E_INVAL;
+  sg_ctx* c = o->ctx;
+  if (!ok_bufs(b) || !ok_cfg(cfg) || !grad) return pfail(c, SG_E_INVAL, "sg_ppo_grad: bad argument");
+  const long long total = (long long)T * c->N;
+  if (T < 1 || total > o->max_samples || rows < 1 || rows > total)
+    return pfail(c, SG_E_INVAL, "sg_ppo_grad: T N must be <= max_samples and 1 <= rows <= T N");
+  hipStream_t st = c->stream;
+  if (stats) k_zero<<<1, 256, 0, st>>>(stats, 8);
+  hipError_t e = normalise_adv(o, b, (int)total);
+  PpoRows r = rows_of(o, b, T);
+  r.idx = idx;
+  r.r0 = 0;
+  r.rows = rows;
+  if (e == hipSuccess) e = minibatch_grad(o, r, cfg, 1.f, stats);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(grad, o->g, (size_t)o->P * sizeof(float), hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) {
+    c->err = std::string("sg_ppo_grad: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  return SG_OK;
+}
+
+sg_status sg_ppo_update(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const sg_ppo_config* cfg,
+                        const int32_t* perm, float* stats) {
+  if (!o) return SG_E_INVAL;
+  sg_ctx* c = o->ctx;
+  if (!ok_bufs(b) || !ok_cfg(cfg)) return pfail(c, SG_E_INVAL, "sg_ppo_update: bad argument");
+  const long long total = (long long)T * c->N;
+  if (T < 1 || total > o->max_samples) return pfail(c, SG_E_INVAL, "sg_ppo_update: T N must be <= max_samples");
+  if (total % cfg->minibatches != 0) return pfail(c, SG_E_INVAL, "sg_ppo_update: minibatches must divide T N");
+  hipStream_t st = c->stream;
+  const int mb = (int)(total / cfg->minibatches);
+  const float w = 1.f / (float)(cfg->epochs * cfg->minibatches);
+  if (stats) k_zero<<<1, 256, 0, st>>>(stats, 8);
+  hipError_t e = normalise_adv(o, b, (int)total);
+  for (int ep = 0; ep < cfg->epochs && e == hipSuccess; ++ep) {
+    for (int k = 0; k < cfg->minibatches && e == hipSuccess; ++k) {
+      PpoRows r = rows_of(o, b, T);
+      r.rows = mb;
+      if (perm) {
+        r.idx = perm + (size_t)ep * total + (size_t)k * mb;
+        r.r0 = 0;
+      } else {
+        r.idx = nullptr;
+        r.r0 = k * mb;
+      }
+      e = minibatch_grad(o, r, cfg, w, stats);
+      if (e != hipSuccess) break;
+      o->t += 1;
+      const float c1 = 1.f - (float)std::pow((double)cfg->beta1, o->t);
+      const float c2 = 1.f - (float)std::pow((double)cfg->beta2, o->t);
+      k_ppo_adam<<<(o->P + 255) / 256, 256, 0, st>>>(o->P, o->p, o->g, o->m, o->v, o->scal, cfg->max_grad_norm,
+                                                     cfg->lr, cfg->beta1, cfg->beta2, cfg->adam_eps, c1, c2, o->pb);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess) e = pack_policy(o);
+  if (e != hipSuccess) {
+    c->err = std::string("sg_ppo_update: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  return SG_OK;
+}
+
+}  // extern "C"

@@ -56,7 +56,7 @@ constexpr size_t kLdsW = (size_t)kWFrags * 16;
 constexpr size_t kLdsBias = (size_t)kBiasFloats * 4;
 constexpr size_t kLdsX = 256 * 16;
 constexpr size_t kLdsO = (size_t)kWave * kOut * 4;
-template <int J> constexpr size_t lds_par_bytes() { return (size_t)P_NFIELDS * J * kWave * 4; }
+template <int J> constexpr size_t lds_par_bytes() { return (size_t)P_NSTAGE * J * kWave * 4; }
 template <int J> constexpr size_t rollout_lds_bytes() { return kLdsW + kLdsBias + kLdsX + kLdsO + lds_par_bytes<J>(); }
 
 struct RollArgs {
@@ -84,7 +84,7 @@ __device__ __forceinline__ void fill_weights(uint4* sw, float* sb, const uint4* 
 // envs' link parameters are staged in LDS once, the chain state stays in
 // VGPRs; every step runs the policy on the matrix cores, samples the action,
 // advances the physics and writes the step's rollout rows.
-template <int J, bool UNI>
+template <int J, int M>
 __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
   extern __shared__ __align__(16) unsigned char lds[];
   uint4* s_w = reinterpret_cast<uint4*>(lds);
@@ -96,14 +96,14 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
   const int lane = threadIdx.x;
   const int e = blockIdx.x * kWave + lane;
   const bool active = e < E.N;
-  const int n = UNI ? J : (active ? E.nd[e] : 0);
+  const int n = M == M_UNI ? J : (active ? E.nd[e] : 0);
   const int Wd = 2 * E.J + 10;
   const size_t N = E.N;
 
   fill_weights(s_w, s_b, A.wimg, A.bias, lane);
   stage_chain<float, J>(E, e, active ? n : 0, lane, s_p);
   __syncthreads();
-  LdsPar<float, J> ps{s_p, lane};
+  LdsPar<float, J, M == M_PRI> ps{s_p, lane};
   float lstd[J], sig[J];
   float lp_const = 0.f;
 #pragma unroll
@@ -230,12 +230,12 @@ hipError_t launch_policy_forward(const sg_ctx* c, const float* x, int n, float* 
   return hipGetLastError();
 }
 
-template <int J, bool UNI> static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_bufs* b) {
+template <int J, int M> static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_bufs* b) {
   const size_t lds = rollout_lds_bytes<J>();
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e =
-        hipFuncSetAttribute((const void*)k_rollout<J, UNI>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipFuncSetAttribute((const void*)k_rollout<J, M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
@@ -248,7 +248,7 @@ template <int J, bool UNI> static hipError_t rollout_j(sg_ctx* c, int T, const s
   A.seed = c->seed;
   A.step0 = c->rng_step;
   A.obs = b->obs; A.act = b->act; A.logp = b->logp; A.rew = b->rew; A.done = b->done; A.val = b->val;
-  k_rollout<J, UNI><<<dim3((c->N + kWave - 1) / kWave), kWave, lds, c->stream>>>(A);
+  k_rollout<J, M><<<dim3((c->N + kWave - 1) / kWave), kWave, lds, c->stream>>>(A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   c->rng_step += (uint64_t)T;
@@ -257,11 +257,12 @@ template <int J, bool UNI> static hipError_t rollout_j(sg_ctx* c, int T, const s
 
 hipError_t launch_rollout(sg_ctx* c, int T, const sg_rollout_bufs* b) {
   const bool u = c->uniform;
+  if (c->prismatic) return c->J <= 4 ? rollout_j<4, M_PRI>(c, T, b) : rollout_j<7, M_PRI>(c, T, b);
   switch (dof_bucket(c->J)) {
-    case 1: return rollout_j<1, true>(c, T, b);
-    case 2: return u ? rollout_j<2, true>(c, T, b) : rollout_j<2, false>(c, T, b);
-    case 4: return u ? rollout_j<4, true>(c, T, b) : rollout_j<4, false>(c, T, b);
-    default: return u ? rollout_j<7, true>(c, T, b) : rollout_j<7, false>(c, T, b);
+    case 1: return rollout_j<1, M_UNI>(c, T, b);
+    case 2: return u ? rollout_j<2, M_UNI>(c, T, b) : rollout_j<2, M_GEN>(c, T, b);
+    case 4: return u ? rollout_j<4, M_UNI>(c, T, b) : rollout_j<4, M_GEN>(c, T, b);
+    default: return u ? rollout_j<7, M_UNI>(c, T, b) : rollout_j<7, M_GEN>(c, T, b);
   }
 }
 

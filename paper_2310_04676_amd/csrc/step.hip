@@ -1,8 +1,8 @@
 // Environment-step kernels: one environment per lane, chain state in VGPRs,
-// the block's link parameters staged in LDS ([P_NFIELDS][J][64]) and read
+// the block's link parameters staged in LDS ([P_NSTAGE][J][64]) and read
 // per pass, structure-of-arrays global layout so each per-joint field is one
-// coalesced 64-lane access. UNI = every env has max_dof joints (the per-joint
-// guards then fold away at compile time).
+// coalesced 64-lane access. The kernel variant M (M_GEN, M_UNI, M_PRI) picks
+// per-env joint counts, exactly J joints, or chains with prismatic joints.
 #include "internal.hpp"
 
 namespace sgk {
@@ -18,23 +18,24 @@ int dof_bucket(int J) {
   return 16;
 }
 
-template <typename T, int J> constexpr size_t par_lds_bytes() { return sizeof(T) * P_NFIELDS * J * kBlk; }
+template <typename T, int J> constexpr size_t par_lds_bytes() { return sizeof(T) * P_NSTAGE * J * kBlk; }
 // LDS staging when the block's parameters fit comfortably, else registers.
 template <typename T, int J> constexpr bool use_lds() { return par_lds_bytes<T, J>() <= 96 * 1024; }
 
 // Parameter source for env e of this block: LDS-staged (after a barrier) or
 // register-held. Every lane of the block must call it (barrier inside).
-template <typename T, int J, bool LDS> struct ParOf;
-template <typename T, int J> struct ParOf<T, J, true> {
-  using type = LdsPar<T, J>;
+template <typename T, int J, bool LDS, bool PR> struct ParOf;
+template <typename T, int J, bool PR> struct ParOf<T, J, true, PR> {
+  using type = LdsPar<T, J, PR>;
   static __device__ __forceinline__ type make(const EnvDev<T>& E, int e, int n, bool active, T* sp) {
+    __syncthreads();  // the block may be re-staging for its next tile
     stage_chain<T, J>(E, e, active ? n : 0, threadIdx.x, sp);
     __syncthreads();
     return type{sp, (int)threadIdx.x};
   }
 };
-template <typename T, int J> struct ParOf<T, J, false> {
-  using type = RegPar<T, J>;
+template <typename T, int J, bool PR> struct ParOf<T, J, false, PR> {
+  using type = RegPar<T, J, PR>;
   static __device__ __forceinline__ type make(const EnvDev<T>& E, int e, int n, bool active, T*) {
     type r;
     if (active) load_chain<T, J>(E, e, n, r);
@@ -47,14 +48,17 @@ template <typename T, int J> struct ParOf<T, J, false> {
   T* sp = reinterpret_cast<T*>(smem_raw);                                            \
   const int e = blockIdx.x * kBlk + threadIdx.x;                                     \
   const bool active = e < E.N;                                                       \
-  const int n = UNI ? J : (active ? E.nd[e] : 0);                                    \
-  auto ps = ParOf<T, J, use_lds<T, J>()>::make(E, e, n, active, sp);                 \
+  const int n = M == M_UNI ? J : (active ? E.nd[e] : 0);                            \
+  auto ps = ParOf<T, J, use_lds<T, J>(), M == M_PRI>::make(E, e, n, active, sp);     \
   if (!active) return;
 
-template <typename T, int J, bool UNI>
-__global__ void __launch_bounds__(kBlk) k_step(EnvDev<T> E, const T* __restrict__ act, T* __restrict__ obs,
-                                               T* __restrict__ rew, uint8_t* __restrict__ done) {
-  SG_PAR_SETUP
+// One control step of env e (inactive lanes only help stage parameters).
+template <typename T, int J, int M>
+__device__ __forceinline__ void step_body(const EnvDev<T>& E, int e, bool active, T* sp, const T* __restrict__ act,
+                                          T* __restrict__ obs, T* __restrict__ rew, uint8_t* __restrict__ done) {
+  const int n = M == M_UNI ? J : (active ? E.nd[e] : 0);
+  auto ps = ParOf<T, J, use_lds<T, J>(), M == M_PRI>::make(E, e, n, active, sp);
+  if (!active) return;
   T q[J], qd[J], a[J];
   load_state<T, J>(E, e, n, q, qd);
 #pragma unroll
@@ -68,7 +72,50 @@ __global__ void __launch_bounds__(kBlk) k_step(EnvDev<T> E, const T* __restrict_
   done[e] = d;
 }
 
-template <typename T, int J, bool UNI>
+template <typename T, int J, int M>
+__global__ void __launch_bounds__(kBlk) k_step(EnvDev<T> E, const T* __restrict__ act, T* __restrict__ obs,
+                                               T* __restrict__ rew, uint8_t* __restrict__ done) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int e = blockIdx.x * kBlk + threadIdx.x;
+  step_body<T, J, M>(E, e, e < E.N, reinterpret_cast<T*>(smem_raw), act, obs, rew, done);
+}
+
+// Uneven batches: envs bucketed by DOF class into 64-slot tiles, so every
+// block is class-homogeneous and runs the class's specialised code (exact
+// joint count where instantiated, else the next size with per-joint guards).
+// Tiles [tile0, tile0 + ntiles) are walked with a grid-stride loop, so one
+// launch can cover all classes (fused), one class (per-class launches), or
+// all tiles with fewer resident blocks (persistent).
+template <typename T, int JB>
+__device__ __forceinline__ void step_tile(const EnvDev<T>& E, int nd, int e, T* sp, const T* act, T* obs, T* rew,
+                                          uint8_t* done) {
+  const bool active = e >= 0;
+  if (nd == 1) step_body<T, 1, M_UNI>(E, e, active, sp, act, obs, rew, done);
+  else if (nd == 2) step_body<T, 2, M_UNI>(E, e, active, sp, act, obs, rew, done);
+  else if (nd == 4) step_body<T, 4, M_UNI>(E, e, active, sp, act, obs, rew, done);
+  else if (nd == 3) step_body<T, 4, M_GEN>(E, e, active, sp, act, obs, rew, done);
+  else if (JB >= 6 && nd == 6) step_body<T, (JB >= 6 ? 6 : 4), M_UNI>(E, e, active, sp, act, obs, rew, done);
+  else if (JB >= 6 && nd == 5) step_body<T, (JB >= 6 ? 6 : 4), M_GEN>(E, e, active, sp, act, obs, rew, done);
+  else if (JB >= 7 && nd == 7) step_body<T, (JB >= 7 ? 7 : 4), M_UNI>(E, e, active, sp, act, obs, rew, done);
+  else if (JB >= 9 && nd == 9) step_body<T, (JB >= 9 ? 9 : 4), M_UNI>(E, e, active, sp, act, obs, rew, done);
+  else if (JB >= 9 && nd == 8) step_body<T, (JB >= 9 ? 9 : 4), M_GEN>(E, e, active, sp, act, obs, rew, done);
+  else step_body<T, JB, M_GEN>(E, e, active, sp, act, obs, rew, done);
+}
+
+template <typename T, int JB>
+__global__ void __launch_bounds__(kBlk) k_step_tiles(EnvDev<T> E, const int* __restrict__ slot_env,
+                                                     const int* __restrict__ tile_dof, int tile0, int ntiles,
+                                                     const T* __restrict__ act, T* __restrict__ obs,
+                                                     T* __restrict__ rew, uint8_t* __restrict__ done) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sp = reinterpret_cast<T*>(smem_raw);
+  for (int t = tile0 + blockIdx.x; t < tile0 + ntiles; t += gridDim.x) {
+    const int e = slot_env[(size_t)t * kBlk + threadIdx.x];
+    step_tile<T, JB>(E, tile_dof[t], e, sp, act, obs, rew, done);
+  }
+}
+
+template <typename T, int J, int M>
 __global__ void __launch_bounds__(kBlk) k_observe(EnvDev<T> E, T* __restrict__ obs) {
   SG_PAR_SETUP
   T q[J], qd[J];
@@ -80,7 +127,7 @@ __global__ void __launch_bounds__(kBlk) k_observe(EnvDev<T> E, T* __restrict__ o
   write_obs<T, J>(E, e, n, q, qd, tip, g, obs);
 }
 
-template <typename T, int J, bool UNI>
+template <typename T, int J, int M>
 __global__ void __launch_bounds__(kBlk) k_fd(EnvDev<T> E, const T* __restrict__ qin, const T* __restrict__ qdin,
                                              const T* __restrict__ tauin, int arm_mode, T* __restrict__ qddout) {
   SG_PAR_SETUP
@@ -104,7 +151,7 @@ __global__ void __launch_bounds__(kBlk) k_fd(EnvDev<T> E, const T* __restrict__ 
     if (j < E.J) qddout[(size_t)j * E.N + e] = j < n ? qdd[j] : T(0);
 }
 
-template <typename T, int J, bool UNI>
+template <typename T, int J, int M>
 __global__ void __launch_bounds__(kBlk) k_id(EnvDev<T> E, const T* __restrict__ qin, const T* __restrict__ qdin,
                                              const T* __restrict__ qddin, T* __restrict__ tauout) {
   SG_PAR_SETUP
@@ -122,7 +169,7 @@ __global__ void __launch_bounds__(kBlk) k_id(EnvDev<T> E, const T* __restrict__ 
     if (j < E.J) tauout[(size_t)j * E.N + e] = j < n ? tau[j] : T(0);
 }
 
-template <typename T, int J, bool UNI>
+template <typename T, int J, int M>
 __global__ void __launch_bounds__(kBlk) k_tip(EnvDev<T> E, const T* __restrict__ qin, T* __restrict__ out) {
   SG_PAR_SETUP
   T q[J];
@@ -166,25 +213,79 @@ static hipError_t launch_par(K kernel, const sg_ctx* c, Args... args) {
 #define SG_DISPATCH(KERNEL, T_, ...)                                                               \
   do {                                                                                             \
     const bool uni = c->uniform;                                                                   \
+    if (c->prismatic) {                                                                            \
+      switch (dof_bucket(c->J)) {                                                                  \
+        case 1: case 2: case 4: return launch_par<T_, 4>(KERNEL<T_, 4, M_PRI>, c, __VA_ARGS__);    \
+        case 7: return launch_par<T_, 7>(KERNEL<T_, 7, M_PRI>, c, __VA_ARGS__);                    \
+        case 9: return launch_par<T_, 9>(KERNEL<T_, 9, M_PRI>, c, __VA_ARGS__);                    \
+        default: return launch_par<T_, 16>(KERNEL<T_, 16, M_PRI>, c, __VA_ARGS__);                 \
+      }                                                                                            \
+    }                                                                                              \
     switch (dof_bucket(c->J)) {                                                                    \
-      case 1: return launch_par<T_, 1>(KERNEL<T_, 1, true>, c, __VA_ARGS__);                       \
-      case 2: return uni ? launch_par<T_, 2>(KERNEL<T_, 2, true>, c, __VA_ARGS__)                  \
-                         : launch_par<T_, 2>(KERNEL<T_, 2, false>, c, __VA_ARGS__);                \
-      case 4: return uni ? launch_par<T_, 4>(KERNEL<T_, 4, true>, c, __VA_ARGS__)                  \
-                         : launch_par<T_, 4>(KERNEL<T_, 4, false>, c, __VA_ARGS__);                \
-      case 7: return uni ? launch_par<T_, 7>(KERNEL<T_, 7, true>, c, __VA_ARGS__)                  \
-                         : launch_par<T_, 7>(KERNEL<T_, 7, false>, c, __VA_ARGS__);                \
-      case 9: return uni ? launch_par<T_, 9>(KERNEL<T_, 9, true>, c, __VA_ARGS__)                  \
-                         : launch_par<T_, 9>(KERNEL<T_, 9, false>, c, __VA_ARGS__);                \
-      default: return launch_par<T_, 16>(KERNEL<T_, 16, false>, c, __VA_ARGS__);                   \
+      case 1: return launch_par<T_, 1>(KERNEL<T_, 1, M_UNI>, c, __VA_ARGS__);                      \
+      case 2: return uni ? launch_par<T_, 2>(KERNEL<T_, 2, M_UNI>, c, __VA_ARGS__)                 \
+                         : launch_par<T_, 2>(KERNEL<T_, 2, M_GEN>, c, __VA_ARGS__);                \
+      case 4: return uni ? launch_par<T_, 4>(KERNEL<T_, 4, M_UNI>, c, __VA_ARGS__)                 \
+                         : launch_par<T_, 4>(KERNEL<T_, 4, M_GEN>, c, __VA_ARGS__);                \
+      case 7: return uni ? launch_par<T_, 7>(KERNEL<T_, 7, M_UNI>, c, __VA_ARGS__)                 \
+                         : launch_par<T_, 7>(KERNEL<T_, 7, M_GEN>, c, __VA_ARGS__);                \
+      case 9: return uni ? launch_par<T_, 9>(KERNEL<T_, 9, M_UNI>, c, __VA_ARGS__)                 \
+                         : launch_par<T_, 9>(KERNEL<T_, 9, M_GEN>, c, __VA_ARGS__);                \
+      default: return launch_par<T_, 16>(KERNEL<T_, 16, M_GEN>, c, __VA_ARGS__);                   \
     }                                                                                              \
   } while (0)
 
+template <typename T, int JB>
+static hipError_t step_tiles_t(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done, int tile0,
+                               int ntiles, int grid) {
+  constexpr size_t lds = use_lds<T, JB>() ? par_lds_bytes<T, JB>() : 0;
+  static bool attr = false;
+  if (!attr && lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_step_tiles<T, JB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  attr = true;
+  EnvDev<T> E = env_view<T>(c);
+  k_step_tiles<T, JB><<<dim3(grid), kBlk, lds, c->stream>>>(E, c->slot_env, c->tile_dof, tile0, ntiles, (const T*)act,
+                                                           (T*)obs, (T*)rew, done);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t tiles_t(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done, int tile0, int ntiles,
+                          int grid) {
+  switch (dof_bucket(c->J)) {
+    case 1: return step_tiles_t<T, 1>(c, act, obs, rew, done, tile0, ntiles, grid);
+    case 2: return step_tiles_t<T, 2>(c, act, obs, rew, done, tile0, ntiles, grid);
+    case 4: return step_tiles_t<T, 4>(c, act, obs, rew, done, tile0, ntiles, grid);
+    case 7: return step_tiles_t<T, 7>(c, act, obs, rew, done, tile0, ntiles, grid);
+    case 9: return step_tiles_t<T, 9>(c, act, obs, rew, done, tile0, ntiles, grid);
+    default: return step_tiles_t<T, 16>(c, act, obs, rew, done, tile0, ntiles, grid);
+  }
+}
+
 template <typename T>
 static hipError_t step_t(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done) {
+  // tiled schedules: FP32 revolute contexts only (sg_set_schedule enforces it)
+  if constexpr (sizeof(T) == sizeof(float)) {
+    if (c->schedule == SG_SCHED_SORTED) return tiles_t<T>(c, act, obs, rew, done, 0, c->n_tiles, c->n_tiles);
+    if (c->schedule == SG_SCHED_PERSISTENT) {
+      const int grid = c->n_tiles < 512 ? c->n_tiles : 512;
+      return tiles_t<T>(c, act, obs, rew, done, 0, c->n_tiles, grid);
+    }
+    if (c->schedule == SG_SCHED_PER_CLASS) {
+      for (size_t k = 0; k < c->cls_dof.size(); ++k) {
+        hipError_t e = tiles_t<T>(c, act, obs, rew, done, c->cls_tile0[k], c->cls_ntiles[k], c->cls_ntiles[k]);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    }
+  }
   EnvDev<T> E = env_view<T>(c);
   SG_DISPATCH(k_step, T, E, (const T*)act, (T*)obs, (T*)rew, done);
 }
+
 template <typename T> static hipError_t observe_t(const sg_ctx* c, void* obs) {
   EnvDev<T> E = env_view<T>(c);
   SG_DISPATCH(k_observe, T, E, (T*)obs);

@@ -5,14 +5,10 @@
 // |RNEA(q, qd, qdd_hat) + arm qdd_hat - tau~| / max(|tau~|, 1e-3); envs
 // above the threshold go on a device-wide queue and get the exact ABA solve.
 //
-// Kernels:
-//   k_gemm      generic BF16 MFMA GEMM (LDS-staged 64x64 tiles) with fused
-//               epilogues: bias + ELU (forward), ELU' (backward data), plain
-//               (weight gradient) -- the training passes.
+// Kernels (the training GEMM, column sums and Adam are the shared ones of
+// nn.hpp, with ELU units):
 //   k_feat      normalised BF16 features [B][96] of a batch.
 //   k_loss      MSE gradient on normalised targets and the loss.
-//   k_colsum    bias gradients.
-//   k_adam      Adam on the FP32 master weights + BF16 copies.
 //   k_pack      BF16 fragment image for the fused inference kernel.
 //   k_sinfer    fused inference: features -> 4 layers on the matrix cores,
 //               hidden activations in registers, weights streamed from L2.
@@ -20,6 +16,7 @@
 //               ABA on the queue, integration + episode bookkeeping.
 #include "internal.hpp"
 #include "mlp.hpp"
+#include "nn.hpp"
 
 namespace sgk {
 
@@ -29,93 +26,6 @@ constexpr int kSO = 16;    // padded output count (J <= 7)
 constexpr int kSL = 4;     // weight layers
 __host__ __device__ constexpr int s_in(int l) { return l == 0 ? kSF : kSH; }
 __host__ __device__ constexpr int s_out(int l) { return l == 3 ? kSO : kSH; }
-
-__device__ __forceinline__ float elu_f(float x) { return x > 0.f ? x : __expf(x) - 1.f; }
-__device__ __forceinline__ float elu_grad_f(float z) { return z > 0.f ? 1.f : __expf(z); }
-__device__ __forceinline__ uint16_t bf16_bits(float x) {
-  __bf16 b = (__bf16)x;
-  return *reinterpret_cast<uint16_t*>(&b);
-}
-__device__ __forceinline__ float bf16_val(uint16_t u) { return __uint_as_float((uint32_t)u << 16); }
-
-// ---------------------------------------------------------------------------
-// Generic GEMM: C[m][n] = sum_k A(m, k) B(k, n) (+ epilogue), BF16 inputs,
-// FP32 accumulation. A(m, k) = A[AT ? k*lda + m : m*lda + k],
-// B(k, n) = B[BT ? n*ldb + k : k*ldb + n].
-enum { EPI_FWD_HIDDEN = 0, EPI_FWD_OUT = 1, EPI_PLAIN = 2, EPI_BWD_DX = 3 };
-
-struct GemmArgs {
-  int M, N, K;
-  const uint16_t* A;
-  int lda;
-  const uint16_t* B;
-  int ldb;
-  float* C;          // fp32 output [M][ldc]
-  int ldc;
-  const float* bias; // [N] (forward)
-  uint16_t* Cb;      // bf16 output [M][ldc] (ELU(z) forward, gradient backward)
-  const float* Zp;   // pre-activations of the previous layer [M][ldc] (backward data)
-};
-
-template <int EPI, bool AT, bool BT>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-  __shared__ __align__(16) uint16_t As[64][40];  // 32 k + 8 pad
-  __shared__ __align__(16) uint16_t Bs[64][40];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int gi = lane >> 4, li = lane & 15;
-  f32x4 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int lr = tid >> 2, lk = (tid & 3) * 8;  // loader: row / first k of 8
-  for (int k0 = 0; k0 < g.K; k0 += 32) {
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int m = m0 + lr, k = k0 + lk + s, n = n0 + lr;
-      uint16_t av = 0, bv = 0;
-      if (m < g.M && k < g.K) av = AT ? g.A[(size_t)k * g.lda + m] : g.A[(size_t)m * g.lda + k];
-      if (n < g.N && k < g.K) bv = BT ? g.B[(size_t)n * g.ldb + k] : g.B[(size_t)k * g.ldb + n];
-      As[lr][lk + s] = av;
-      Bs[lr][lk + s] = bv;
-    }
-    __syncthreads();
-    bf16x8 af[2], bfr[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      af[t] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * t + li][8 * gi]);
-      bfr[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * t + li][8 * gi]);
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x32(af[a], bfr[b], acc[a][b]);
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + 16 * a + 4 * gi + r, n = n0 + wn + 16 * b + li;
-        if (m >= g.M || n >= g.N) continue;
-        const size_t i = (size_t)m * g.ldc + n;
-        float z = acc[a][b][r];
-        if (EPI == EPI_FWD_HIDDEN || EPI == EPI_FWD_OUT) z += g.bias[n];
-        if (EPI == EPI_BWD_DX) z *= elu_grad_f(g.Zp[i]);
-        g.C[i] = z;
-        if (EPI == EPI_FWD_HIDDEN) g.Cb[i] = bf16_bits(elu_f(z));
-        if (EPI == EPI_BWD_DX) g.Cb[i] = bf16_bits(z);
-      }
-}
-
-template <int EPI, bool AT, bool BT> static void gemm(hipStream_t s, const GemmArgs& a) {
-  dim3 grid((a.N + 63) / 64, (a.M + 63) / 64);
-  k_gemm<EPI, AT, BT><<<grid, 256, 0, s>>>(a);
-}
 
 // ---------------------------------------------------------------------------
 // Features: x = (q, qd, tau, per joint [m, m c, I_O]) normalised with
@@ -225,36 +135,6 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ Z, const
   if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, part);
 }
 
-// db[c] = sum_r G[r][c].
-__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ G, int rows, int cols, float* __restrict__ out) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= cols) return;
-  float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += G[(size_t)r * cols + c];
-  out[c] = s;
-}
-
-// Adam (Kingma & Ba) with bias correction c1 = 1 - beta1^t, c2 = 1 - beta2^t
-// passed in; optional BF16 copy of the updated weights.
-__global__ void __launch_bounds__(256) k_adam(int n, float* __restrict__ w, const float* __restrict__ g,
-                                              float* __restrict__ m, float* __restrict__ v, float lr, float b1,
-                                              float b2, float eps, float c1, float c2, uint16_t* __restrict__ wb) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-  w[i] = wi;
-  if (wb) wb[i] = bf16_bits(wi);
-}
-
-__global__ void __launch_bounds__(256) k_to_bf16(int n, const float* __restrict__ w, uint16_t* __restrict__ wb) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) wb[i] = bf16_bits(w[i]);
-}
 
 // ---------------------------------------------------------------------------
 // Fragment image for k_sinfer. Layer l has (out/16) M-tiles x (in/32)
@@ -690,9 +570,9 @@ hipError_t forward_backward(sg_surrogate* s, hipStream_t st, const float* q, con
     g.bias = s->bm[l];
     if (l < kSL - 1) {
       g.Cb = s->X[l + 1];
-      gemm<EPI_FWD_HIDDEN, false, true>(st, g);
+      launch_gemm<EPI_FWD_HIDDEN, false, true, ACT_ELU>(st, g);
     } else {
-      gemm<EPI_FWD_OUT, false, true>(st, g);
+      launch_gemm<EPI_FWD_OUT, false, true, ACT_ELU>(st, g);
     }
   }
   hipError_t e = hipMemsetAsync(s->loss, 0, sizeof(float), st);
@@ -709,7 +589,7 @@ hipError_t forward_backward(sg_surrogate* s, hipStream_t st, const float* q, con
     g.A = Gbc; g.lda = s_out(l);
     g.B = s->X[l]; g.ldb = s_in(l);
     g.C = s->gW[l]; g.ldc = s_in(l);
-    gemm<EPI_PLAIN, true, false>(st, g);
+    launch_gemm<EPI_PLAIN, true, false, ACT_ELU>(st, g);
     k_colsum<<<(s_out(l) + 255) / 256, 256, 0, st>>>(Gc, B, s_out(l), s->gb[l]);
     if (l == 0) break;
     // G_prev[b][i] = (sum_o G[b][o] W[o][i]) * elu'(Z_prev[b][i])
@@ -720,7 +600,7 @@ hipError_t forward_backward(sg_surrogate* s, hipStream_t st, const float* q, con
     d.C = Gn; d.ldc = s_in(l);
     d.Cb = Gbn;
     d.Zp = s->Z[l - 1];
-    gemm<EPI_BWD_DX, false, false>(st, d);
+    launch_gemm<EPI_BWD_DX, false, false, ACT_ELU>(st, d);
     std::swap(Gc, Gn);
     std::swap(Gbc, Gbn);
   }
@@ -736,6 +616,7 @@ sg_status sg_surrogate_create(sg_ctx* c, int32_t max_batch, sg_surrogate** out) 
   *out = nullptr;
   if (c->dtype != SG_F32) return sfail(c, SG_E_UNSUPPORTED, "sg_surrogate_create: FP32 contexts only");
   if (c->J > 7) return sfail(c, SG_E_UNSUPPORTED, "sg_surrogate_create: max_dof <= 7");
+  if (c->prismatic) return sfail(c, SG_E_UNSUPPORTED, "sg_surrogate_create: all-revolute contexts only");
   if (max_batch < 1 || max_batch > (1 << 22)) return sfail(c, SG_E_INVAL, "sg_surrogate_create: max_batch in 1..4M");
   sg_surrogate* s = new sg_surrogate();
   s->ctx = c;

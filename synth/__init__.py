@@ -72,6 +72,7 @@ class Robot:
     dt: float
     substeps: int
     gravity: tuple = (0.0, 0.0, -9.81)
+    joint_type: np.ndarray | None = None  # int32 [J][N]: 0 revolute, 1 prismatic (None: all revolute)
 
 
 @dataclasses.dataclass
@@ -120,8 +121,11 @@ def _axis_pattern(j):
 
 
 def make_chain(n_env: int, n_dof, seed: int, *, dt: float, substeps: int, max_dof: int | None = None,
-               q0_frac: float = 0.0, gain_jitter: bool = False, radius: float = 0.05) -> Robot:
-    """Seeded revolute serial chains. ``n_dof`` is an int or an int array [N]."""
+               q0_frac: float = 0.0, gain_jitter: bool = False, radius: float = 0.05,
+               pattern: str | None = None) -> Robot:
+    """Seeded serial chains. ``n_dof`` is an int or an int array [N].
+    ``pattern`` (e.g. "RRPRRR") marks prismatic joints: they slide along the
+    link axis (+z), limits +-U[0.05, 0.15] m, gains kp 400 N/m, kd 40 N s/m."""
     n_dof = np.broadcast_to(np.asarray(n_dof, dtype=np.int32), (n_env,)).copy()
     J = int(max_dof if max_dof is not None else n_dof.max())
     mass = _per_env(seed, "mass", n_env, J, 0.5, 3.0)
@@ -165,9 +169,26 @@ def make_chain(n_env: int, n_dof, seed: int, *, dt: float, substeps: int, max_do
         arr[z] = 0.0
     kpT = kp.T.copy(); kpT[z] = 0.0
     kdT = kd.T.copy(); kdT[z] = 0.0
+    jt = None
+    if pattern is not None:
+        jt = np.zeros((J, n_env), dtype=np.int32)
+        ph = _per_env(seed, "plimit", n_env, J, 0.05, 0.15).T
+        for j in range(J):
+            if pattern[j % len(pattern)] == "P":
+                jt[j] = 1
+                axis[:, j, :] = 0.0
+                axis[2, j, :] = 1.0
+                q_hi[j] = ph[j]
+                q_lo[j] = -ph[j]
+                q0[j] = 0.0
+                kpT[j] = 400.0
+                kdT[j] = 40.0
+        jt[z] = 0
+        for arr in (q_hi, q_lo, q0, kpT, kdT):
+            arr[z] = 0.0
     return Robot(n_env=n_env, max_dof=J, n_dof=n_dof, axis=axis, offset=offset, com=com, mass=m,
                  inertia=inertia, kp=kpT, kd=kdT, q_lo=q_lo, q_hi=q_hi, q0=q0, tip=tip, dt=dt,
-                 substeps=substeps)
+                 substeps=substeps, joint_type=jt)
 
 
 def _natural_cubic_coeffs(u, y):
@@ -223,7 +244,7 @@ def _as_dtype(arr, dtype):
 def _round_robot(r: Robot, dtype) -> Robot:
     fields = {f.name: getattr(r, f.name) for f in dataclasses.fields(r)}
     for k, v in fields.items():
-        if isinstance(v, np.ndarray):
+        if isinstance(v, np.ndarray) and v.dtype.kind == "f":
             fields[k] = _as_dtype(v, dtype)
     fields["dt"] = float(np.asarray(r.dt, dtype=dtype))
     fields["gravity"] = tuple(float(np.asarray(g, dtype=dtype)) for g in r.gravity)
@@ -274,6 +295,16 @@ def path_rollout(n_env: int = 4096, seed: int = 1002, dtype=np.float32, substeps
     pol = make_policy(seed)
     return Workload("path_rollout", _round_robot(r, dtype), _round_task(t, dtype), pol, dtype, seed,
                     extra={"knots": knots})
+
+
+def psm_like(n_env: int = 4096, seed: int = 1004, dtype=np.float32) -> Workload:
+    """6-DOF RRPRRR chains (the joint sequence of the paper's PSM/ECM arms,
+    Sec. III "Robot Descriptions"), FP32, 4 substeps, target reaching."""
+    r = make_chain(n_env, 6, seed, dt=1.0 / 120.0, substeps=4, q0_frac=0.25, pattern="RRPRRR")
+    tgt = (WORK_CENTRE[None, :] + _per_env(seed, "target", n_env, 3, -0.25, 0.25)).T.copy()
+    t = Task(task=TASK_REACH, target=tgt, waypoints=None, dwell=1, ep_len=128,
+             progress0=stream(seed, "progress0").integers(0, 128, size=n_env).astype(np.int32))
+    return Workload("psm_like", _round_robot(r, dtype), _round_task(t, dtype), None, dtype, seed)
 
 
 def mixed_dof(n_env: int = 16384, seed: int = 1003, dtype=np.float32) -> Workload:

@@ -17,8 +17,10 @@ def chain_of(robot, e):
     links = []
     for j in range(n):
         xx, yy, zz, xy, xz, yz = robot.inertia[:, j, e]
+        jt = 0 if getattr(robot, "joint_type", None) is None else int(robot.joint_type[j, e])
         links.append(dict(axis=robot.axis[:, j, e], offset=robot.offset[:, j, e], com=robot.com[:, j, e],
-                          m=robot.mass[j, e], Ic=np.array([[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]])))
+                          m=robot.mass[j, e], Ic=np.array([[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]]),
+                          prismatic=jt == 1))
     return links, robot.tip[:, e], np.asarray(robot.gravity, dtype=float)
 
 
@@ -28,8 +30,11 @@ def fk(links, tip, q):
     p = np.zeros(3)
     Rs, ps, coms = [], [], []
     for j, l in enumerate(links):
-        p = p + R @ l["offset"]
-        R = R @ rot(l["axis"], q[j])
+        if l.get("prismatic"):
+            p = p + R @ (l["offset"] + q[j] * np.asarray(l["axis"]))
+        else:
+            p = p + R @ l["offset"]
+            R = R @ rot(l["axis"], q[j])
         Rs.append(R)
         ps.append(p)
         coms.append(p + R @ l["com"])
@@ -46,8 +51,11 @@ def mass_matrix(links, tip, q):
         Jv = np.zeros((3, n))
         Jw = np.zeros((3, n))
         for i in range(k + 1):
-            Jv[:, i] = np.cross(z[i], coms[k] - ps[i])
-            Jw[:, i] = z[i]
+            if links[i].get("prismatic"):
+                Jv[:, i] = z[i]
+            else:
+                Jv[:, i] = np.cross(z[i], coms[k] - ps[i])
+                Jw[:, i] = z[i]
         Iw = Rs[k] @ links[k]["Ic"] @ Rs[k].T
         M += links[k]["m"] * Jv.T @ Jv + Jw.T @ Iw @ Jw
     return M
