@@ -363,3 +363,20 @@ def ppo_update(dims, p, m, v, t, bufs, T, N, perm=None, epochs=5, n_mb=4, cfg=No
     if rc != 0:
         raise ValueError("ppo_update: T*N must be a multiple of n_mb")
     return p, m, v, tt.value, dict(zip(("loss_pi", "loss_v", "entropy", "approx_kl", "clip_frac"), st))
+
+
+# ---- adjoint of an open-loop rollout -------------------------------------------
+def adjoint(orc, T, act, q0, qd0, progress0=None, mass_scale=None, want_grad=True, threads=1):
+    """Loss L [N] = sum_t |tip(q_{t+1}) - goal_t| of an open-loop rollout with
+    actions act [T][J][N]; with want_grad also dL/da [T][J][N] and dL/dm
+    [J][N]. mass_scale [J][N] multiplies link masses and inertias."""
+    N, J = orc.N, orc.J
+    loss = np.zeros(N)
+    ga = np.zeros((T, J, N)) if want_grad else None
+    gm = np.zeros((J, N)) if want_grad else None
+    pr = None if progress0 is None else np.ascontiguousarray(progress0, dtype=np.int32)
+    ms = None if mass_scale is None else _f64(mass_scale)
+    lib().ora_adjoint(C.byref(orc.r), C.byref(orc.t), C.c_int(T), _ptr(_f64(act)), _ptr(_f64(q0)), _ptr(_f64(qd0)),
+                      _ptr(pr, _ip), _ptr(ms), C.c_int(int(want_grad)), _ptr(loss), _ptr(ga), _ptr(gm),
+                      C.c_int(threads))
+    return (loss, ga, gm) if want_grad else loss

@@ -665,4 +665,50 @@ int ora_ppo_update(const int* dims, double* p, double* m, double* v, int* t, con
   return 0;
 }
 
+
+// ---- adjoint of an open-loop rollout (differentiation row) ---------------
+}  // extern "C"
+#include "adjoint.hpp"
+extern "C" {
+
+// Loss L_e = sum_t |tip(q_{t+1}) - goal_t| of a T-step open-loop rollout per
+// env, from (q0, qd0, progress0) with actions act [T][J][N]; mass_scale
+// [J][N] (may be null) multiplies each link's mass and inertia. With
+// want_grad: g_act [T][J][N] = dL/da and g_mass [J][N] = dL/dm (d/d of the
+// scaled mass). Envs [0, N) over `threads` OpenMP threads.
+int ora_adjoint(const ora_robot* r, const ora_task* t, int T, const double* act, const double* q0, const double* qd0,
+                const int32_t* prog0, const double* mass_scale, int want_grad, double* loss, double* g_act,
+                double* g_mass, int threads) {
+  const int N = r->n_env, J = r->max_dof;
+  const TaskSpec ts = load_taskspec(t);
+#pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : 1)
+  for (int e = 0; e < N; ++e) {
+    Chain<double> ch = load_chain<double>(r, e);
+    const int n = ch.n;
+    if (mass_scale)
+      for (int j = 0; j < n; ++j) scale_link_mass(ch.L[j], mass_scale[j * N + e]);
+    Drive<double> dr = load_drive<double>(r, e);
+    EnvGoal<double> g = load_goal<double>(t, N, e);
+    std::vector<double> a((size_t)T * n);
+    double qe[kMaxDof], qde[kMaxDof];
+    for (int k = 0; k < T; ++k)
+      for (int j = 0; j < n; ++j) a[(size_t)k * n + j] = act[((size_t)k * J + j) * N + e];
+    for (int j = 0; j < n; ++j) {
+      qe[j] = q0[j * N + e];
+      qde[j] = qd0[j * N + e];
+    }
+    AdjointOut o = rollout_adjoint(ch, dr, r->dt, r->substeps, ts, g, T, a.data(), qe, qde, prog0 ? prog0[e] : 0,
+                                   want_grad != 0);
+    loss[e] = o.loss;
+    if (want_grad) {
+      for (int j = 0; j < J; ++j) {
+        if (g_mass) g_mass[j * N + e] = j < n ? o.g_mass[j] : 0.0;
+        for (int k = 0; k < T; ++k)
+          if (g_act) g_act[((size_t)k * J + j) * N + e] = j < n ? o.g_act[(size_t)k * n + j] : 0.0;
+      }
+    }
+  }
+  return 0;
+}
+
 }  // extern "C"
