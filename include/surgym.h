@@ -54,7 +54,7 @@ typedef enum {
 } sg_status;
 
 enum { SG_F32 = 0, SG_F64 = 1 };
-enum { SG_TASK_REACH = 0, SG_TASK_PATH = 1 };
+enum { SG_TASK_REACH = 0, SG_TASK_PATH = 1, SG_TASK_TRACK = 2 };
 /* done flags (uint8 per env): bit 0 the episode ended (the observation
  * returned is the reset state's), bit 1 it ended by time-out (the critic
  * bootstraps, paper Sec. III "Policy learning and control"), bit 2 the
@@ -103,18 +103,30 @@ typedef struct {
                               * takes no surrogate (SG_E_UNSUPPORTED there). */
 } sg_robot_desc;
 
-/* Task description (paper Sec. IV): target reaching, reward -|tip - g|, or
+/* Task description (paper Sec. IV): target reaching, reward -|tip - g|;
  * path following, reward -|tip - P(t)| with P(t) the waypoint
- * min(K-1, progress / dwell). Host memory, float64, copied at create. */
+ * min(K-1, progress / dwell); or active tracking, reward -|tip - g_t| with a
+ * moving goal: after each step that does not end the episode
+ * g <- g + gd (held within +-offset of the episode centre per axis, the
+ * outward velocity component dropped at the wall), then
+ * gd <- gd + sigma N(0, 1); each new episode draws its centre as
+ * track_centre + reset_std N(0, 1) per axis and starts the goal there at
+ * rest (Philox counter (env, step, block 8 / 9) under `seed`). Rewards use
+ * the goal active during the step; the observation holds the updated one.
+ * Host memory, float64, copied at create. */
 typedef struct {
-  int32_t task;             /* SG_TASK_REACH or SG_TASK_PATH */
+  int32_t task;             /* SG_TASK_REACH, SG_TASK_PATH or SG_TASK_TRACK */
   int32_t n_waypoints;      /* K (path), 1..SG_MAX_WAYPOINTS */
   int32_t dwell;            /* control steps per waypoint (path), >= 1 */
   int32_t ep_len;           /* episode length in steps; <= 0: no time-out */
-  const double* target;     /* [3][N] (reach) */
+  const double* target;     /* [3][N] (reach; tracking: the first episode's centre) */
   const double* waypoints;  /* [K][3][N] (path) */
   const int32_t* progress0; /* [N] initial episode progress, may be NULL (0) */
-  uint64_t seed;            /* exploration-noise key */
+  uint64_t seed;            /* noise key (exploration and the tracking goal) */
+  double track_sigma;       /* tracking: goal-velocity increment std per step (m) */
+  double track_offset;      /* tracking: half-width of the goal box (m), > 0 */
+  double track_reset_std;   /* tracking: spread of a new episode's centre (m) */
+  double track_centre[3];   /* tracking: nominal centre (m) */
 } sg_task_desc;
 
 /* Rollout storage, all DEVICE memory, float32 unless noted:
@@ -158,7 +170,8 @@ sg_status sg_set_stream(sg_ctx* ctx, void* hip_stream);
 /* Wait for the context's stream; reports asynchronous HIP errors. */
 sg_status sg_synchronize(sg_ctx* ctx);
 
-/* Reset every env to (q0, 0, progress0) and the noise counter to 0. */
+/* Reset every env to (q0, 0, progress0), the tracking goals to their values
+ * at create, and the noise counter to 0. */
 sg_status sg_reset(sg_ctx* ctx);
 
 /* One control step of every env (paper Sec. III: actions are PD position
@@ -171,6 +184,7 @@ sg_status sg_reset(sg_ctx* ctx);
  * actions [J][N] real (device), obs [W][N] real, reward [N] real,
  * done [N] uint8 (device). obs, reward, done may not alias actions. */
 sg_status sg_step(sg_ctx* ctx, const void* actions, void* obs, void* reward, uint8_t* done);
+/* (sg_step advances the noise counter rng_step by one, sg_rollout by T.) */
 
 /* Step schedules for batches of uneven DOF (envs differ in n_dof). The
  * results do not depend on the schedule.
@@ -200,6 +214,10 @@ sg_status sg_observe(sg_ctx* ctx, void* obs);
  * pointers (any may be NULL to skip); rng_step is host memory. */
 sg_status sg_get_state(sg_ctx* ctx, void* q, void* qd, int32_t* progress, uint64_t* rng_step);
 sg_status sg_set_state(sg_ctx* ctx, const void* q, const void* qd, const int32_t* progress, uint64_t rng_step);
+/* Tracking task's goal state [9][N] real (device): goal (3), goal velocity
+ * (3), episode centre (3). SG_E_STATE for other tasks. */
+sg_status sg_get_goal_state(sg_ctx* ctx, void* goal_state);
+sg_status sg_set_goal_state(sg_ctx* ctx, const void* goal_state);
 
 /* Forward dynamics (ABA, Featherstone Table 7.1) for the given state:
  * qdd = (H(q) + diag(arm))^-1 (tau - C(q, qd)) with arm per arm_mode.
@@ -297,6 +315,27 @@ sg_status sg_surrogate_predict(sg_surrogate* s, const float* q, const float* qd,
  * NULL) receives the number of exact solves per substep. */
 sg_status sg_surrogate_step(sg_surrogate* s, const float* actions, float* obs, float* reward, uint8_t* done,
                             float threshold, int32_t* n_fallback);
+
+/* ---- Differentiation ----------------------------------------------------
+ * Adjoint of an open-loop rollout of T control steps from the context's
+ * current state (left unchanged) with actions [T][J][N] (DEVICE float32):
+ * loss [N] = sum_t |tip(q_{t+1}) - goal_t| (the negated reward sum of
+ * paper Sec. IV's reaching / path-following tasks), g_act [T][J][N] = dL/da
+ * (0 for saturated actions |a| >= 1) and g_mass [J][N] = dL/dm for each
+ * link's mass with its geometry fixed (all of its inertial parameters scale
+ * with m). The state is checkpointed every K steps (1 <= K <= T) and each
+ * segment is recomputed in the reverse sweep; a clamped coordinate passes no
+ * gradient, and an episode that ends inside the rollout cuts the gradient
+ * at its reset. FP32 contexts with max_dof <= 7. The library keeps a
+ * workspace of sg_adjoint_workspace_bytes(T, K) per context, (re)allocated
+ * on first use of a larger size (that call synchronizes the stream). */
+sg_status sg_adjoint(sg_ctx* ctx, int32_t T, int32_t K, const float* actions, float* loss, float* g_act,
+                     float* g_mass);
+/* Device workspace sg_adjoint needs for (T, K), in bytes; -1 if invalid. */
+int64_t sg_adjoint_workspace_bytes(const sg_ctx* ctx, int32_t T, int32_t K);
+/* Replace the link masses by masses [J][N] (DEVICE, context dtype), scaling
+ * each link's first moment and rotational inertia with it (geometry fixed). */
+sg_status sg_set_link_masses(sg_ctx* ctx, const void* masses);
 
 /* ---- PPO update (paper Sec. III "Policy learning and control": the GPU
  * PPO of Rudin et al.; clipped surrogate objective of Schulman et al.) ----

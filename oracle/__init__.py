@@ -32,7 +32,17 @@ class _Robot(C.Structure):
 
 class _Task(C.Structure):
     _fields_ = [("task", C.c_int32), ("n_waypoints", C.c_int32), ("dwell", C.c_int32),
-                ("ep_len", C.c_int32), ("target", _dp), ("waypoints", _dp)]
+                ("ep_len", C.c_int32), ("target", _dp), ("waypoints", _dp), ("trk_sigma", C.c_double),
+                ("trk_offset", C.c_double), ("trk_reset_std", C.c_double), ("trk_centre", C.c_double * 3)]
+
+
+TASK_TRACK = 2
+
+
+def _track_params(task):
+    tr = getattr(task, "track", None) or {}
+    return (float(tr.get("sigma", 0.0)), float(tr.get("offset", 0.0)), float(tr.get("reset_std", 0.0)),
+            (C.c_double * 3)(*tr.get("centre", (0.0, 0.0, 0.0))))
 
 
 class _Policy(C.Structure):
@@ -82,9 +92,11 @@ class Oracle:
             tgt = None if task.target is None else _f64(task.target)
             wps = None if task.waypoints is None else _f64(task.waypoints)
             k.extend([tgt, wps])
-            self.t = _Task(task.task, task.n_waypoints, task.dwell, task.ep_len, _ptr(tgt), _ptr(wps))
+            self.t = _Task(task.task, task.n_waypoints, task.dwell, task.ep_len, _ptr(tgt), _ptr(wps),
+                           *_track_params(task))
         else:
-            self.t = _Task(0, 0, 1, 0, None, None)
+            self.t = _Task(0, 0, 1, 0, None, None, 0.0, 0.0, 0.0, (C.c_double * 3)(0.0, 0.0, 0.0))
+        self.seed = int(getattr(task, "seed", 0) or 0) if task is not None else 0
         self.p = None
         if policy is not None:
             Ws = [_f64(w) for w in policy.W]
@@ -136,15 +148,19 @@ class Oracle:
         return h * _f64(self.robot.kd) + h * h * _f64(self.robot.kp)
 
     # ---- environment -----------------------------------------------------
-    def observe(self, q, qd, progress):
+    def observe(self, q, qd, progress, goal_state=None):
+        """goal_state [9][N] (tracking task): goal, goal velocity, centre."""
         obs = np.zeros((self.W, self.N))
         pr = np.ascontiguousarray(progress, dtype=np.int32)
+        gs = None if goal_state is None else _f64(goal_state)
         lib().ora_observe(C.byref(self.r), C.byref(self.t), _ptr(_f64(q)), _ptr(_f64(qd)), _ptr(pr, _ip),
-                          _ptr(obs))
+                          _ptr(obs), _ptr(gs))
         return obs
 
-    def step(self, action, q, qd, progress, log_qdd=False, envs=None, threads=1):
-        """One control step. Returns (q, qd, progress, reward, done, obs[, qdd_log])."""
+    def step(self, action, q, qd, progress, log_qdd=False, envs=None, threads=1, goal_state=None, seed=0, step=0):
+        """One control step. Returns (q, qd, progress, reward, done, obs[, qdd_log]).
+        Tracking task: goal_state [9][N] is updated in place with the draws of
+        Philox counter (seed; env, step)."""
         q = _f64(q).copy()
         qd = _f64(qd).copy()
         pr = np.ascontiguousarray(progress, dtype=np.int32).copy()
@@ -153,9 +169,13 @@ class Oracle:
         obs = np.zeros((self.W, self.N))
         qlog = np.zeros((self.robot.substeps, self.J, self.N)) if log_qdd else None
         e0, e1 = (0, self.N) if envs is None else envs
+        gs = None
+        if goal_state is not None:
+            assert goal_state.dtype == np.float64 and goal_state.flags.c_contiguous
+            gs = goal_state
         lib().ora_step(C.byref(self.r), C.byref(self.t), _ptr(_f64(action)), _ptr(q), _ptr(qd), _ptr(pr, _ip),
                        _ptr(rew), _ptr(done, _u8p), _ptr(obs), _ptr(qlog), C.c_int(e0), C.c_int(e1),
-                       C.c_int(threads))
+                       C.c_int(threads), _ptr(gs), C.c_uint64(seed), C.c_uint64(step))
         out = (q, qd, pr, rew, done, obs)
         return out + (qlog,) if log_qdd else out
 
@@ -175,7 +195,7 @@ class Oracle:
         return out
 
     def rollout(self, T, seed, step0, q, qd, progress, obs0, gamma=0.99, lam=0.95, emulate=True, envs=None,
-                threads=1):
+                threads=1, goal_state=None):
         N, J, W = self.N, self.J, self.W
         q = _f64(q).copy()
         qd = _f64(qd).copy()
@@ -193,7 +213,8 @@ class Oracle:
         lib().ora_rollout(C.byref(self.r), C.byref(self.t), C.byref(self.p), C.c_int(T), C.c_uint64(seed),
                           C.c_uint64(step0), C.c_double(gamma), C.c_double(lam), C.c_int(int(emulate)), _ptr(q),
                           _ptr(qd), _ptr(pr, _ip), _ptr(obs), _ptr(act), _ptr(logp), _ptr(rew), _ptr(done, _u8p),
-                          _ptr(val), _ptr(adv), _ptr(ret), C.c_int(e0), C.c_int(e1), C.c_int(threads))
+                          _ptr(val), _ptr(adv), _ptr(ret), C.c_int(e0), C.c_int(e1), C.c_int(threads),
+                          _ptr(goal_state))
         return dict(q=q, qd=qd, progress=pr, obs=obs, act=act, logp=logp, rew=rew, done=done, val=val, adv=adv,
                     ret=ret)
 

@@ -36,10 +36,14 @@
 #include <cstdint>
 
 #include "chain.hpp"
+#include "rl.hpp"
 
 namespace ora {
 
-enum { kTaskReach = 0, kTaskPath = 1 };
+enum { kTaskReach = 0, kTaskPath = 1, kTaskTrack = 2 };
+// Philox blocks of the tracking task's draws (the action noise uses blocks
+// 0..3 of the same (env, step) counter).
+enum { kBlockGoalAccel = 8, kBlockGoalReset = 9 };
 enum { kDoneEnded = 1, kDoneTimeout = 2, kDoneNonFinite = 4 };
 
 template <class T> struct Drive {
@@ -47,11 +51,57 @@ template <class T> struct Drive {
 };
 
 struct TaskSpec {
-  int task;         // kTaskReach or kTaskPath
+  int task;         // kTaskReach, kTaskPath or kTaskTrack
   int n_waypoints;  // K (path task)
   int dwell;        // control steps per waypoint (path task)
   int ep_len;       // episode length in control steps; <= 0: never times out
+  // active tracking (paper Sec. IV): goal random walk g += gd,
+  // gd += sigma N(0, 1) per step; |g - centre| <= offset per axis; at each
+  // reset a new centre = (cx, cy, cz) + reset_std N(0, 1) per axis
+  double trk_sigma, trk_offset, trk_reset_std, trk_centre[3];
 };
+
+// Moving goal of one env (tracking task): position, velocity (per control
+// step) and the episode's centre.
+template <class T> struct Track {
+  V3<T> g, gd, gc;
+};
+
+// Goal update of the tracking task after a step that did not end the
+// episode: position by the velocity, clamp to the offset box (the outward
+// velocity component is dropped at the wall), then the velocity's random
+// increment.
+template <class T>
+inline void track_advance(const TaskSpec& ts, Track<T>& tr, uint64_t seed, uint32_t env, uint64_t step) {
+  T* g = &tr.g.x;
+  T* gd = &tr.gd.x;
+  const T* gc = &tr.gc.x;
+  double n4[4];
+  gaussian_block(seed, env, step, kBlockGoalAccel, n4);
+  for (int k = 0; k < 3; ++k) {
+    g[k] = g[k] + gd[k];
+    const T hi = gc[k] + T(ts.trk_offset), lo = gc[k] - T(ts.trk_offset);
+    if (g[k] > hi) {
+      g[k] = hi;
+      if (gd[k] > T(0.0)) gd[k] = T(0.0);
+    } else if (g[k] < lo) {
+      g[k] = lo;
+      if (gd[k] < T(0.0)) gd[k] = T(0.0);
+    }
+    gd[k] = gd[k] + T(ts.trk_sigma * n4[k]);
+  }
+}
+
+// New episode of the tracking task: a new centre, the goal on it, at rest.
+template <class T>
+inline void track_reset(const TaskSpec& ts, Track<T>& tr, uint64_t seed, uint32_t env, uint64_t step) {
+  double n4[4];
+  gaussian_block(seed, env, step, kBlockGoalReset, n4);
+  T* gc = &tr.gc.x;
+  for (int k = 0; k < 3; ++k) gc[k] = T(ts.trk_centre[k] + ts.trk_reset_std * n4[k]);
+  tr.g = tr.gc;
+  tr.gd = v3(T(0.0), T(0.0), T(0.0));
+}
 
 template <class T> struct EnvGoal {
   V3<T> target;       // reach task
@@ -107,10 +157,10 @@ template <class T> inline T norm3(const V3<T>& a) {
 // Observation of the current state. width = 2*Jmax + 10.
 template <class T>
 inline void observe(const Chain<T>& ch, int Jmax, const TaskSpec& ts, const EnvGoal<T>& g, const T* q, const T* qd,
-                    int progress, T* obs) {
+                    int progress, T* obs, const Track<T>* tr = nullptr) {
   Pose<T> P;
   forward_kinematics(ch, q, P);
-  V3<T> goal = goal_for(ts, g, progress);
+  V3<T> goal = tr ? tr->g : goal_for(ts, g, progress);
   V3<T> d = goal - P.tip;
   for (int j = 0; j < Jmax; ++j) {
     obs[j] = j < ch.n ? q[j] : T(0.0);
@@ -124,16 +174,19 @@ inline void observe(const Chain<T>& ch, int Jmax, const TaskSpec& ts, const EnvG
 }
 
 // Whole control step. Returns the done bits; writes reward and obs.
+// tr (tracking task only): the env's moving goal, advanced with the draws of
+// counter (seed; env, step).
 template <class T>
 inline uint8_t env_step(const Chain<T>& ch, const Drive<T>& dr, T dt, int S, int Jmax, const TaskSpec& ts,
                         const EnvGoal<T>& g, const T* action, T* q, T* qd, int* progress, T* reward, T* obs,
-                        T* qdd_log) {
+                        T* qdd_log, Track<T>* tr = nullptr, uint64_t seed = 0, uint32_t env = 0,
+                        uint64_t step = 0) {
   physics_step(ch, dr, dt, S, action, q, qd, qdd_log);
   const int n = ch.n;
   Pose<T> P;
   forward_kinematics(ch, q, P);
   int pre = *progress;
-  V3<T> goal = goal_for(ts, g, pre);
+  V3<T> goal = tr ? tr->g : goal_for(ts, g, pre);
   *reward = -norm3(P.tip - goal);
   *progress = pre + 1;
   uint8_t done = 0;
@@ -151,8 +204,11 @@ inline uint8_t env_step(const Chain<T>& ch, const Drive<T>& dr, T dt, int S, int
       qd[j] = T(0.0);
     }
     *progress = 0;
+    if (tr) track_reset(ts, *tr, seed, env, step);
+  } else if (tr) {
+    track_advance(ts, *tr, seed, env, step);
   }
-  observe(ch, Jmax, ts, g, q, qd, *progress, obs);
+  observe(ch, Jmax, ts, g, q, qd, *progress, obs, tr);
   return done;
 }
 

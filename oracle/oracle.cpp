@@ -46,8 +46,9 @@ typedef struct {
 
 typedef struct {
   int32_t task, n_waypoints, dwell, ep_len;
-  const double* target;     // [3][N]
+  const double* target;     // [3][N] (reach; tracking: the first episode's centre)
   const double* waypoints;  // [K][3][N]
+  double trk_sigma, trk_offset, trk_reset_std, trk_centre[3];  // tracking task
 } ora_task;
 
 typedef struct {
@@ -104,6 +105,10 @@ TaskSpec load_taskspec(const ora_task* t) {
   s.n_waypoints = t->n_waypoints;
   s.dwell = t->dwell;
   s.ep_len = t->ep_len;
+  s.trk_sigma = t->trk_sigma;
+  s.trk_offset = t->trk_offset;
+  s.trk_reset_std = t->trk_reset_std;
+  for (int k = 0; k < 3; ++k) s.trk_centre[k] = t->trk_centre[k];
   return s;
 }
 
@@ -249,8 +254,22 @@ int ora_fd_crba(const ora_robot* r, const double* q, const double* qd, const dou
 }
 
 // Observation of the given state, obs [2J+10][N].
+// Tracking task: goal_state [9][N] = (goal, goal velocity, centre), updated
+// in place; draws from Philox counter (seed; env, step).
+static Track<double> load_track(const double* gs, int N, int e) {
+  Track<double> tr;
+  tr.g = v3(gs[0 * N + e], gs[1 * N + e], gs[2 * N + e]);
+  tr.gd = v3(gs[3 * N + e], gs[4 * N + e], gs[5 * N + e]);
+  tr.gc = v3(gs[6 * N + e], gs[7 * N + e], gs[8 * N + e]);
+  return tr;
+}
+static void store_track(double* gs, int N, int e, const Track<double>& tr) {
+  const double v[9] = {tr.g.x, tr.g.y, tr.g.z, tr.gd.x, tr.gd.y, tr.gd.z, tr.gc.x, tr.gc.y, tr.gc.z};
+  for (int k = 0; k < 9; ++k) gs[k * N + e] = v[k];
+}
+
 int ora_observe(const ora_robot* r, const ora_task* t, const double* q, const double* qd, const int32_t* progress,
-                double* obs) {
+                double* obs, const double* goal_state) {
   const int N = r->n_env, J = r->max_dof, W = 2 * J + 10;
   TaskSpec ts = load_taskspec(t);
   for (int e = 0; e < N; ++e) {
@@ -259,7 +278,9 @@ int ora_observe(const ora_robot* r, const ora_task* t, const double* q, const do
     double qe[kMaxDof], qde[kMaxDof], oe[64];
     gather(q, J, N, e, ch.n, qe);
     gather(qd, J, N, e, ch.n, qde);
-    observe(ch, J, ts, g, qe, qde, progress[e], oe);
+    Track<double> tr;
+    if (ts.task == kTaskTrack) tr = load_track(goal_state, N, e);
+    observe(ch, J, ts, g, qe, qde, progress[e], oe, ts.task == kTaskTrack ? &tr : nullptr);
     for (int w = 0; w < W; ++w) obs[w * N + e] = oe[w];
   }
   return 0;
@@ -270,7 +291,7 @@ int ora_observe(const ora_robot* r, const ora_task* t, const double* q, const do
 // with it and n_threads > 1.
 int ora_step(const ora_robot* r, const ora_task* t, const double* action, double* q, double* qd,
              int32_t* progress, double* reward, uint8_t* done, double* obs, double* qdd_log, int e0, int e1,
-             int n_threads) {
+             int n_threads, double* goal_state, uint64_t seed, uint64_t step) {
   const int N = r->n_env, J = r->max_dof, W = 2 * J + 10, S = r->substeps;
   TaskSpec ts = load_taskspec(t);
   (void)n_threads;
@@ -287,7 +308,15 @@ int ora_step(const ora_robot* r, const ora_task* t, const double* action, double
     gather(qd, J, N, e, n, qde);
     gather(action, J, N, e, n, ae);
     int prog = progress[e];
-    uint8_t d = env_step(ch, dr, r->dt, S, J, ts, g, ae, qe, qde, &prog, &rew, oe, qdd_log ? qlog : nullptr);
+    Track<double> tr;
+    Track<double>* trp = nullptr;
+    if (ts.task == kTaskTrack) {
+      tr = load_track(goal_state, N, e);
+      trp = &tr;
+    }
+    uint8_t d = env_step(ch, dr, r->dt, S, J, ts, g, ae, qe, qde, &prog, &rew, oe, qdd_log ? qlog : nullptr, trp,
+                         seed, (uint32_t)e, step);
+    if (trp) store_track(goal_state, N, e, tr);
     scatter(q, J, N, e, n, qe);
     scatter(qd, J, N, e, n, qde);
     progress[e] = prog;
@@ -381,7 +410,7 @@ int ora_gae(int T, int N, const double* rew, const double* val_, const uint8_t* 
 int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int T, uint64_t seed, uint64_t step0,
                 double gamma, double lam, int emulate, double* q, double* qd, int32_t* progress, double* obs,
                 double* act, double* logp, double* rew, uint8_t* done, double* val_, double* adv, double* ret,
-                int e0, int e1, int n_threads) {
+                int e0, int e1, int n_threads, double* goal_state) {
   const int N = r->n_env, J = r->max_dof, W = 2 * J + 10, S = r->substeps;
   TaskSpec ts = load_taskspec(t);
   MlpLayer L[3];
@@ -400,6 +429,12 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
     gather(q, J, N, e, n, qe);
     gather(qd, J, N, e, n, qde);
     int prog = progress[e];
+    Track<double> tr;
+    Track<double>* trp = nullptr;
+    if (ts.task == kTaskTrack) {
+      tr = load_track(goal_state, N, e);
+      trp = &tr;
+    }
     for (int w = 0; w < W; ++w) x[w] = obs[(size_t)w * N + e];
     for (int s = 0; s < T; ++s) {
       mlp_forward(L, 3, x, o, emulate != 0, sa, sb);
@@ -415,13 +450,15 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
       val_[(size_t)s * N + e] = o[J];
       logp[(size_t)s * N + e] = lp;
       double rw;
-      uint8_t d = env_step(ch, dr, r->dt, S, J, ts, g, a, qe, qde, &prog, &rw, x, (double*)nullptr);
+      uint8_t d = env_step(ch, dr, r->dt, S, J, ts, g, a, qe, qde, &prog, &rw, x, (double*)nullptr, trp, seed,
+                           (uint32_t)e, step0 + (uint64_t)s);
       rew[(size_t)s * N + e] = rw;
       done[(size_t)s * N + e] = d;
       for (int w = 0; w < W; ++w) obs[((size_t)(s + 1) * W + w) * N + e] = x[w];
     }
     mlp_forward(L, 3, x, o, emulate != 0, sa, sb);
     val_[(size_t)T * N + e] = o[J];
+    if (trp) store_track(goal_state, N, e, tr);
     scatter(q, J, N, e, n, qe);
     scatter(qd, J, N, e, n, qde);
     progress[e] = prog;

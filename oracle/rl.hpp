@@ -88,6 +88,20 @@ inline void gaussian_noise(uint64_t seed, uint32_t env, uint64_t step, int n, do
   }
 }
 
+// Four standard normals from one Philox block (env, step, block): the
+// Box-Muller pairs (x0, x1) and (x2, x3) as above.
+inline void gaussian_block(uint64_t seed, uint32_t env, uint64_t step, uint32_t block, double* out) {
+  const double two_pi = 6.283185307179586476925286766559;
+  Philox4 c = {{env, (uint32_t)step, (uint32_t)(step >> 32), block}};
+  Philox4 r = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  for (int p = 0; p < 2; ++p) {
+    double u1 = u24(r.v[2 * p]), u2 = u24(r.v[2 * p + 1]);
+    double rad = std::sqrt(-2.0 * std::log(u1));
+    out[2 * p] = rad * std::cos(two_pi * u2);
+    out[2 * p + 1] = rad * std::sin(two_pi * u2);
+  }
+}
+
 // ---- policy MLP ----------------------------------------------------------
 // Layer l maps n_in -> n_out with W row-major [n_out][n_in]. tanh after every
 // layer but the last.

@@ -38,7 +38,9 @@ class RobotDesc(C.Structure):
 
 class TaskDesc(C.Structure):
     _fields_ = [("task", C.c_int32), ("n_waypoints", C.c_int32), ("dwell", C.c_int32), ("ep_len", C.c_int32),
-                ("target", _dp), ("waypoints", _dp), ("progress0", _ip), ("seed", C.c_uint64)]
+                ("target", _dp), ("waypoints", _dp), ("progress0", _ip), ("seed", C.c_uint64),
+                ("track_sigma", C.c_double), ("track_offset", C.c_double), ("track_reset_std", C.c_double),
+                ("track_centre", C.c_double * 3)]
 
 
 class RolloutBufs(C.Structure):
@@ -130,8 +132,10 @@ def make_descs(robot, task, dtype, seed=0):
     wps = None if task.waypoints is None else _f64(task.waypoints)
     p0 = None if task.progress0 is None else np.ascontiguousarray(task.progress0, dtype=np.int32)
     keep.extend([tgt, wps, p0])
+    tr = getattr(task, "track", None) or {}
     td = TaskDesc(task.task, task.n_waypoints, task.dwell, task.ep_len, _ptr(tgt), _ptr(wps), _ptr(p0, _ip),
-                  seed & 0xFFFFFFFFFFFFFFFF)
+                  seed & 0xFFFFFFFFFFFFFFFF, float(tr.get("sigma", 0.0)), float(tr.get("offset", 0.0)),
+                  float(tr.get("reset_std", 0.0)), (C.c_double * 3)(*tr.get("centre", (0.0, 0.0, 0.0))))
     return rd, td, keep
 
 
@@ -514,3 +518,85 @@ class Ppo:
         self._call(lib.sg_ppo_update, C.byref(rb), C.c_int32(T), C.byref(c),
                    None if perm is None else _dptr(perm, t.int32), _dptr(st, t.float32))
         return st
+
+
+# ---- differentiation ------------------------------------------------------------
+lib.sg_adjoint.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
+lib.sg_adjoint_workspace_bytes.argtypes = [_vp, C.c_int32, C.c_int32]
+lib.sg_adjoint_workspace_bytes.restype = C.c_int64
+lib.sg_set_link_masses.argtypes = [_vp, _vp]
+
+
+def _adjoint(self, actions, K=8):
+    """Loss [N] and its gradients (g_act [T][J][N], g_mass [J][N]) of an
+    open-loop rollout with actions [T][J][N] from the current state."""
+    T = actions.shape[0]
+    f32 = self.torch.float32
+    loss = self._empty(self.N, dtype=f32)
+    g_act = self._empty(T, self.J, self.N, dtype=f32)
+    g_mass = self._empty(self.J, self.N, dtype=f32)
+    self._call(lib.sg_adjoint, C.c_int32(T), C.c_int32(K), _dptr(actions, f32), _dptr(loss, f32), _dptr(g_act, f32),
+               _dptr(g_mass, f32))
+    return loss, g_act, g_mass
+
+
+def _adjoint_workspace_bytes(self, T, K):
+    return int(lib.sg_adjoint_workspace_bytes(self.ctx, C.c_int32(T), C.c_int32(K)))
+
+
+def _set_link_masses(self, masses):
+    self._call(lib.sg_set_link_masses, _dptr(masses, self.tdtype))
+
+
+Sim.adjoint = _adjoint
+Sim.adjoint_workspace_bytes = _adjoint_workspace_bytes
+Sim.set_link_masses = _set_link_masses
+
+_RolloutLoss = None
+
+
+def rollout_loss(sim, actions, masses, K=8):
+    """Differentiable loss [N] of an open-loop rollout: a
+    torch.autograd.Function whose inputs are the actions [T][J][N] and the
+    link masses [J][N] (installed into the context by the forward pass);
+    the backward pass returns the adjoint's gradients."""
+    global _RolloutLoss
+    if _RolloutLoss is None:
+        import torch
+
+        class RolloutLossFn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, act, m, sim_, k):
+                sim_.set_link_masses(m.detach().contiguous())
+                loss, ga, gm = sim_.adjoint(act.detach().contiguous(), k)
+                ctx.save_for_backward(ga, gm)
+                return loss
+
+            @staticmethod
+            def backward(ctx, gl):
+                ga, gm = ctx.saved_tensors
+                return ga * gl[None, None, :], gm * gl[None, :], None, None
+
+        _RolloutLoss = RolloutLossFn
+    return _RolloutLoss.apply(actions, masses, sim, K)
+
+
+# ---- tracking task ------------------------------------------------------------------
+SG_TASK_REACH, SG_TASK_PATH, SG_TASK_TRACK = 0, 1, 2
+lib.sg_get_goal_state.argtypes = [_vp, _vp]
+lib.sg_set_goal_state.argtypes = [_vp, _vp]
+
+
+def _get_goal_state(self):
+    """Tracking task: goal, goal velocity, episode centre [9][N]."""
+    gs = self._empty(9, self.N)
+    self._call(lib.sg_get_goal_state, _dptr(gs))
+    return gs
+
+
+def _set_goal_state(self, gs):
+    self._call(lib.sg_set_goal_state, _dptr(gs, self.tdtype))
+
+
+Sim.get_goal_state = _get_goal_state
+Sim.set_goal_state = _set_goal_state

@@ -36,7 +36,7 @@ template <typename T> hipError_t upload(void** dst, const std::vector<double>& s
 
 void free_ctx(sg_ctx* c) {
   void* ptrs[] = {c->par, c->tip, c->nd, c->target, c->wp, c->prog0, c->q, c->qd, c->prog, c->w_bf16, c->bias,
-                  c->log_std, c->slot_env, c->tile_dof};
+                  c->log_std, c->slot_env, c->tile_dof, c->adj_ws, c->gs, c->gs0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -61,8 +61,12 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
       !r->q_hi || !r->q0 || !r->tip)
     return fail(nullptr, SG_E_INVAL, "sg_create: null robot array");
   if (!(r->dt > 0) || r->substeps < 1) return fail(nullptr, SG_E_INVAL, "sg_create: dt must be > 0, substeps >= 1");
-  if (t->task != SG_TASK_REACH && t->task != SG_TASK_PATH) return fail(nullptr, SG_E_INVAL, "sg_create: bad task");
-  if (t->task == SG_TASK_REACH && !t->target) return fail(nullptr, SG_E_INVAL, "sg_create: reach task needs target");
+  if (t->task != SG_TASK_REACH && t->task != SG_TASK_PATH && t->task != SG_TASK_TRACK)
+    return fail(nullptr, SG_E_INVAL, "sg_create: bad task");
+  if ((t->task == SG_TASK_REACH || t->task == SG_TASK_TRACK) && !t->target)
+    return fail(nullptr, SG_E_INVAL, "sg_create: reach and tracking tasks need target");
+  if (t->task == SG_TASK_TRACK && (!(t->track_sigma >= 0) || !(t->track_offset > 0) || !(t->track_reset_std >= 0)))
+    return fail(nullptr, SG_E_INVAL, "sg_create: tracking needs sigma >= 0, offset > 0, reset_std >= 0");
   if (t->task == SG_TASK_PATH &&
       (!t->waypoints || t->n_waypoints < 1 || t->n_waypoints > SG_MAX_WAYPOINTS || t->dwell < 1))
     return fail(nullptr, SG_E_INVAL, "sg_create: path task needs 1..32 waypoints and dwell >= 1");
@@ -94,6 +98,10 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
   for (int k = 0; k < 3; ++k) c->g[k] = r->gravity[k];
   c->task = t->task; c->K = t->task == SG_TASK_PATH ? t->n_waypoints : 1;
   c->dwell = t->dwell > 0 ? t->dwell : 1; c->ep_len = t->ep_len; c->seed = t->seed; c->rng_step = 0;
+  if (t->task == SG_TASK_TRACK) {
+    c->trk_sigma = t->track_sigma; c->trk_offset = t->track_offset; c->trk_reset_std = t->track_reset_std;
+    for (int k = 0; k < 3; ++k) c->trk_c[k] = t->track_centre[k];
+  }
 
   // Device parameter block [P_NFIELDS][J][N]; padded joints stay zero.
   std::vector<double> par((size_t)sgk::P_NFIELDS * JN, 0.0);
@@ -158,6 +166,14 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
   if (e == hipSuccess) e = up(&c->tip, tip);
   if (e == hipSuccess) e = up(&c->target, tgt);
   if (e == hipSuccess) e = up(&c->wp, wps);
+  if (e == hipSuccess && t->task == SG_TASK_TRACK) {
+    // goal on the first episode's centre (the target), at rest
+    std::vector<double> gs0(9 * (size_t)N, 0.0);
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < N; ++i) gs0[k * (size_t)N + i] = gs0[(6 + k) * (size_t)N + i] = tgt[k * (size_t)N + i];
+    e = up(&c->gs0, gs0);
+    if (e == hipSuccess) e = up(&c->gs, gs0);
+  }
   if (e == hipSuccess) e = hipMalloc((void**)&c->nd, N * sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(c->nd, nd.data(), N * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc((void**)&c->prog0, N * sizeof(int));
@@ -217,6 +233,7 @@ sg_status sg_step(sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* don
   if (!aligned(act) || !aligned(obs) || !aligned(rew)) return fail(c, SG_E_INVAL, "sg_step: misaligned buffer");
   if (act == obs || act == rew) return fail(c, SG_E_INVAL, "sg_step: outputs alias actions");
   hipError_t e = sgk::launch_step(c, act, obs, rew, done);
+  c->rng_step += 1;
   return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_step");
 }
 
@@ -259,6 +276,10 @@ sg_status sg_autotune_step(sg_ctx* c, const void* act, int32_t trials, int32_t* 
   if (e == hipSuccess) e = hipMemcpyAsync(q, c->q, JN * esz, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(qd, c->qd, JN * esz, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(pr, c->prog, c->N * sizeof(int), hipMemcpyDeviceToDevice, c->stream);
+  void* gsv = nullptr;
+  const size_t gsb = 9 * (size_t)c->N * esz;
+  if (e == hipSuccess && c->gs) e = hipMalloc(&gsv, gsb);
+  if (e == hipSuccess && c->gs) e = hipMemcpyAsync(gsv, c->gs, gsb, hipMemcpyDeviceToDevice, c->stream);
   const int saved = c->schedule;
   const int n_sched = (c->dtype == SG_F32 && !c->prismatic) ? 4 : 1;
   float best_ms = 0.f;
@@ -284,10 +305,12 @@ sg_status sg_autotune_step(sg_ctx* c, const void* act, int32_t trials, int32_t* 
     if (e == hipSuccess) e = hipMemcpyAsync(c->q, q, JN * esz, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->qd, qd, JN * esz, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->prog, pr, c->N * sizeof(int), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && c->gs) e = hipMemcpyAsync(c->gs, gsv, gsb, hipMemcpyDeviceToDevice, c->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   c->schedule = e == hipSuccess ? best_s : saved;
   if (best && e == hipSuccess) *best = best_s;
+  if (gsv) (void)hipFree(gsv);
   void* ptrs[] = {q, qd, pr, obs, rew, done};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -327,6 +350,24 @@ sg_status sg_set_state(sg_ctx* c, const void* q, const void* qd, const int32_t* 
     e = hipMemcpyAsync(c->prog, progress, c->N * sizeof(int), hipMemcpyDeviceToDevice, c->stream);
   c->rng_step = rng_step;
   return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_set_state");
+}
+
+sg_status sg_get_goal_state(sg_ctx* c, void* gs) {
+  if (!c) return SG_E_INVAL;
+  if (!c->gs) return fail(c, SG_E_STATE, "sg_get_goal_state: not a tracking task");
+  if (!gs) return fail(c, SG_E_INVAL, "sg_get_goal_state: null buffer");
+  const size_t b = 9 * (size_t)c->N * (c->dtype == SG_F64 ? sizeof(double) : sizeof(float));
+  hipError_t e = hipMemcpyAsync(gs, c->gs, b, hipMemcpyDeviceToDevice, c->stream);
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_get_goal_state");
+}
+
+sg_status sg_set_goal_state(sg_ctx* c, const void* gs) {
+  if (!c) return SG_E_INVAL;
+  if (!c->gs) return fail(c, SG_E_STATE, "sg_set_goal_state: not a tracking task");
+  if (!gs) return fail(c, SG_E_INVAL, "sg_set_goal_state: null buffer");
+  const size_t b = 9 * (size_t)c->N * (c->dtype == SG_F64 ? sizeof(double) : sizeof(float));
+  hipError_t e = hipMemcpyAsync(c->gs, gs, b, hipMemcpyDeviceToDevice, c->stream);
+  return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_set_goal_state");
 }
 
 sg_status sg_forward_dynamics(sg_ctx* c, const void* q, const void* qd, const void* tau, int32_t arm_mode, void* qdd) {

@@ -9,10 +9,11 @@
 #include <stdint.h>
 
 #include "dyn.hpp"
+#include "rng.hpp"
 
 namespace sgk {
 
-enum { TASK_REACH = 0, TASK_PATH = 1 };
+enum { TASK_REACH = 0, TASK_PATH = 1, TASK_TRACK = 2 };
 // Kernel variants: per-env joint counts (M_GEN); every env with exactly the
 // kernel's J joints, so the per-joint guards fold away (M_UNI); per-env
 // joint counts with revolute and prismatic joints (M_PRI).
@@ -31,6 +32,12 @@ template <typename T> struct EnvDev {
   T* q;               // [J][N]
   T* qd;              // [J][N]
   int* prog;          // [N]
+  // tracking task: moving goal [9][N] = goal, goal velocity, episode centre;
+  // random walk sigma, offset box, reset spread and nominal centre
+  T* gs;
+  T trk_sigma, trk_offset, trk_reset_std, trk_c[3];
+  uint64_t seed;      // noise key
+  uint64_t step;      // control-step counter of this launch's first step
 };
 
 // Link parameters of env e into registers (joints < n).
@@ -52,6 +59,34 @@ __device__ __forceinline__ void stage_chain(const EnvDev<T>& E, int e, int n, in
     for (int j = 0; j < J; ++j)
       sp[(f * J + j) * 64 + lane] = (j < n) ? E.par[((size_t)f * E.J + j) * E.N + e] : T(0);
 }
+
+// ---- per-block parameter sources ----------------------------------------
+constexpr int kBlk = 64;
+
+template <typename T, int J> constexpr size_t par_lds_bytes() { return sizeof(T) * P_NSTAGE * J * kBlk; }
+// LDS staging when the block's parameters fit comfortably, else registers.
+template <typename T, int J> constexpr bool use_lds() { return par_lds_bytes<T, J>() <= 96 * 1024; }
+
+// Parameter source for env e of this block: LDS-staged (after a barrier) or
+// register-held. Every lane of the block must call it (barrier inside).
+template <typename T, int J, bool LDS, bool PR> struct ParOf;
+template <typename T, int J, bool PR> struct ParOf<T, J, true, PR> {
+  using type = LdsPar<T, J, PR>;
+  static __device__ __forceinline__ type make(const EnvDev<T>& E, int e, int n, bool active, T* sp) {
+    __syncthreads();  // the block may be re-staging for its next tile
+    stage_chain<T, J>(E, e, active ? n : 0, threadIdx.x, sp);
+    __syncthreads();
+    return type{sp, (int)threadIdx.x};
+  }
+};
+template <typename T, int J, bool PR> struct ParOf<T, J, false, PR> {
+  using type = RegPar<T, J, PR>;
+  static __device__ __forceinline__ type make(const EnvDev<T>& E, int e, int n, bool active, T*) {
+    type r;
+    if (active) load_chain<T, J>(E, e, n, r);
+    return r;
+  }
+};
 
 template <typename T, int J>
 __device__ __forceinline__ void load_state(const EnvDev<T>& E, int e, int n, T (&q)[J], T (&qd)[J]) {
@@ -116,7 +151,11 @@ __device__ __forceinline__ void physics(const EnvDev<T>& E, PS& ps, int n, const
 
 template <typename T>
 __device__ __forceinline__ void goal_of(const EnvDev<T>& E, int e, int progress, T* g) {
-  if (E.task == TASK_REACH) {
+  if (E.task == TASK_TRACK) {
+    g[0] = E.gs[e];
+    g[1] = E.gs[E.N + e];
+    g[2] = E.gs[2 * E.N + e];
+  } else if (E.task == TASK_REACH) {
     g[0] = E.target[e];
     g[1] = E.target[E.N + e];
     g[2] = E.target[2 * E.N + e];
@@ -179,13 +218,55 @@ __device__ __forceinline__ void obs_regs(const EnvDev<T>& E, int n, const T (&q)
   x[b + 9] = rsq(dx * dx + dy * dy + dz * dz);
 }
 
-// After the physics: reward on the post-step tip, progress, time-out or
-// non-finite reset, observation of the post-reset state. Returns the done
-// bits; *reward receives the reward.
+// Tracking task (paper Sec. IV "Active Tracking"): after a step that did not
+// end the episode the goal moves by its velocity, is held inside the offset
+// box around the episode centre (dropping the outward velocity component),
+// and the velocity takes a random increment; a new episode draws a new
+// centre and starts the goal on it at rest.
+template <typename T>
+__device__ __forceinline__ void track_update(const EnvDev<T>& E, int e, bool reset, uint64_t step) {
+  const size_t N = E.N;
+  T* gs = E.gs + e;
+  float n4[4];
+  if (reset) {
+    normals4(E.seed, (uint32_t)e, step, RNG_BLOCK_GOAL_RESET, n4);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T c = E.trk_c[k] + E.trk_reset_std * (T)n4[k];
+      gs[k * N] = c;
+      gs[(3 + k) * N] = T(0);
+      gs[(6 + k) * N] = c;
+    }
+    return;
+  }
+  normals4(E.seed, (uint32_t)e, step, RNG_BLOCK_GOAL_ACCEL, n4);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T g = gs[k * N], gd = gs[(3 + k) * N];
+    const T c = gs[(6 + k) * N];
+    g = g + gd;
+    const T hi = c + E.trk_offset, lo = c - E.trk_offset;
+    if (g > hi) {
+      g = hi;
+      if (gd > T(0)) gd = T(0);
+    } else if (g < lo) {
+      g = lo;
+      if (gd < T(0)) gd = T(0);
+    }
+    gs[k * N] = g;
+    gs[(3 + k) * N] = gd + E.trk_sigma * (T)n4[k];
+  }
+}
+
+// After the physics: reward on the post-step tip against the goal active
+// during the step, progress, time-out or non-finite reset, the tracking
+// goal's update, observation of the post-reset state. step = this control
+// step's counter (noise of the tracking task). Returns the done bits;
+// *reward receives the reward.
 template <typename T, int J, class PS>
 __device__ __forceinline__ uint8_t post_step(const EnvDev<T>& E, int e, int n, PS& ps, T (&q)[J], T (&qd)[J],
                                              int& prog, T* reward, T* __restrict__ obs, T* tip_out = nullptr,
-                                             T* goal_out = nullptr) {
+                                             T* goal_out = nullptr, uint64_t step = 0) {
   const T tipl[3] = {E.tip[e], E.tip[E.N + e], E.tip[2 * E.N + e]};
   T tip[3], g[3];
   tip_fk<T, J>(ps, n, q, tipl, tip);
@@ -215,6 +296,7 @@ __device__ __forceinline__ uint8_t post_step(const EnvDev<T>& E, int e, int n, P
     prog = 0;
     tip_fk<T, J>(ps, n, q, tipl, tip);
   }
+  if (E.task == TASK_TRACK) track_update(E, e, done != 0, step);
   goal_of(E, e, prog, g);
   if (obs) write_obs<T, J>(E, e, n, q, qd, tip, g, obs);
   if (tip_out) { tip_out[0] = tip[0]; tip_out[1] = tip[1]; tip_out[2] = tip[2]; }

@@ -28,6 +28,11 @@ struct sg_ctx {
   void* q = nullptr;        // [J][N]
   void* qd = nullptr;       // [J][N]
   int* prog = nullptr;      // [N]
+  // tracking task: goal state [9][N] (goal, goal velocity, centre) and its
+  // value at create (restored by sg_reset)
+  void* gs = nullptr;
+  void* gs0 = nullptr;
+  double trk_sigma = 0, trk_offset = 0, trk_reset_std = 0, trk_c[3] = {0, 0, 0};
   // DOF-class tiling for uneven batches: slots sorted by n_dof, each class
   // padded to whole 64-slot tiles (slot_env = -1 for padding).
   int schedule = 0;               // SG_SCHED_*
@@ -40,6 +45,9 @@ struct sg_ctx {
   uint16_t* w_bf16 = nullptr;  // W1 | W2 | W3 row-major BF16
   float* bias = nullptr;       // b1 | b2 | b3
   float* log_std = nullptr;    // [J]
+  // adjoint workspace (grown on demand)
+  float* adj_ws = nullptr;
+  size_t adj_ws_floats = 0;
   std::string err;
 };
 
@@ -54,6 +62,11 @@ template <typename T> inline EnvDev<T> env_view(const sg_ctx* c) {
   E.par = (const T*)c->par; E.tip = (const T*)c->tip; E.nd = c->nd;
   E.target = (const T*)c->target; E.wp = (const T*)c->wp; E.prog0 = c->prog0;
   E.q = (T*)c->q; E.qd = (T*)c->qd; E.prog = c->prog;
+  E.gs = (T*)c->gs;
+  E.trk_sigma = (T)c->trk_sigma; E.trk_offset = (T)c->trk_offset; E.trk_reset_std = (T)c->trk_reset_std;
+  for (int k = 0; k < 3; ++k) E.trk_c[k] = (T)c->trk_c[k];
+  E.seed = c->seed;
+  E.step = c->rng_step;
   return E;
 }
 
@@ -69,6 +82,11 @@ hipError_t launch_tip(const sg_ctx* c, const void* q, void* tip);
 hipError_t launch_reset(const sg_ctx* c);
 
 // Learning side (FP32 contexts).
+hipError_t launch_adjoint(const sg_ctx* c, int T, int K, const float* act, float* loss, float* g_act, float* g_mass,
+                          float* ws);
+size_t adjoint_ws_floats(const sg_ctx* c, int T, int K);
+hipError_t launch_set_masses(sg_ctx* c, const void* m);
+
 hipError_t launch_policy_forward(const sg_ctx* c, const float* x, int n, float* out);
 hipError_t launch_rollout(sg_ctx* c, int T, const sg_rollout_bufs* b);
 hipError_t launch_gae(hipStream_t s, int T, int n, const float* rew, const float* val, const uint8_t* done,

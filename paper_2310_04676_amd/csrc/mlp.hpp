@@ -31,11 +31,13 @@ constexpr int kW1Frags = 16 * 64, kW2Frags = 8 * 8 * 64, kW3Frags = 4 * 64;
 constexpr int kWFrags = kW1Frags + kW2Frags + kW3Frags;   // 5376 x 16 B = 84 KB
 constexpr int kBiasFloats = kH1 + kH2 + kOut;              // 400
 
-// fast tanh: 1 - 2 / (exp(2x) + 1), hardware exp and reciprocal; the result
-// is rounded to BF16 before use, far coarser than this formula's error.
+// fast tanh: 1 - 2 / (exp(2x) + 1) with the hardware exp and reciprocal
+// (v_exp_f32, v_rcp_f32: about 1 ulp each) instead of an IEEE division
+// sequence; the result is rounded to BF16 before use, far coarser than this
+// formula's error. Saturates to +-1 (exp overflow gives rcp(inf) = 0).
 __device__ __forceinline__ float tanh_fast(float x) {
   const float e = __expf(2.f * x);
-  return 1.f - __fdividef(2.f, e + 1.f);
+  return 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
 }
 
 __device__ __forceinline__ f32x4 mfma16x16x32(const bf16x8& a, const bf16x8& b, const f32x4& c) {

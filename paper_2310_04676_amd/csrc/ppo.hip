@@ -260,18 +260,20 @@ __global__ void __launch_bounds__(256) k_ppo_pack(const float* __restrict__ p, i
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int n1 = kW1Frags * 8, n2 = kW2Frags * 8, n3 = kW3Frags * 8;
   if (i < n1 + n2 + n3) {
-    const int s = i & 7, l = (i >> 3) & 63, f = i >> 9;  // slot, lane, fragment
+    // slot, lane and 64-lane fragment of the image; kW*Frags count 16-byte
+    // lane entries, so a layer spans kW*Frags / 64 fragments
+    const int s = i & 7, l = (i >> 3) & 63, f = i >> 9;
     const int gg = l >> 4, li = l & 15;
     float x = 0.f;
     if (i < n1) {
       const int row = 16 * f + li, k = 8 * gg + s;
       x = k < W ? p[o1 + row * W + k] : 0.f;
     } else if (i < n1 + n2) {
-      const int f2 = f - kW1Frags, mt = f2 >> 3, kb = f2 & 7;
+      const int f2 = f - kW1Frags / 64, mt = f2 >> 3, kb = f2 & 7;
       const int row = 16 * mt + li, k = 32 * kb + (s < 4 ? 4 * gg + s : 16 + 4 * gg + (s - 4));
       x = p[o2 + row * kH1 + k];
     } else {
-      const int kb = f - kW1Frags - kW2Frags;
+      const int kb = f - (kW1Frags + kW2Frags) / 64;
       const int row = li, k = 32 * kb + (s < 4 ? 4 * gg + s : 16 + 4 * gg + (s - 4));
       x = row < O ? p[o3 + row * kH2 + k] : 0.f;
     }

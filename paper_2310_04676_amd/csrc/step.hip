@@ -7,8 +7,6 @@
 
 namespace sgk {
 
-constexpr int kBlk = 64;
-
 int dof_bucket(int J) {
   if (J <= 1) return 1;
   if (J <= 2) return 2;
@@ -17,31 +15,6 @@ int dof_bucket(int J) {
   if (J <= 9) return 9;
   return 16;
 }
-
-template <typename T, int J> constexpr size_t par_lds_bytes() { return sizeof(T) * P_NSTAGE * J * kBlk; }
-// LDS staging when the block's parameters fit comfortably, else registers.
-template <typename T, int J> constexpr bool use_lds() { return par_lds_bytes<T, J>() <= 96 * 1024; }
-
-// Parameter source for env e of this block: LDS-staged (after a barrier) or
-// register-held. Every lane of the block must call it (barrier inside).
-template <typename T, int J, bool LDS, bool PR> struct ParOf;
-template <typename T, int J, bool PR> struct ParOf<T, J, true, PR> {
-  using type = LdsPar<T, J, PR>;
-  static __device__ __forceinline__ type make(const EnvDev<T>& E, int e, int n, bool active, T* sp) {
-    __syncthreads();  // the block may be re-staging for its next tile
-    stage_chain<T, J>(E, e, active ? n : 0, threadIdx.x, sp);
-    __syncthreads();
-    return type{sp, (int)threadIdx.x};
-  }
-};
-template <typename T, int J, bool PR> struct ParOf<T, J, false, PR> {
-  using type = RegPar<T, J, PR>;
-  static __device__ __forceinline__ type make(const EnvDev<T>& E, int e, int n, bool active, T*) {
-    type r;
-    if (active) load_chain<T, J>(E, e, n, r);
-    return r;
-  }
-};
 
 #define SG_PAR_SETUP                                                                 \
   extern __shared__ __align__(16) unsigned char smem_raw[];                          \
@@ -66,7 +39,7 @@ __device__ __forceinline__ void step_body(const EnvDev<T>& E, int e, bool active
   physics<T, J>(E, ps, n, a, q, qd);
   int prog = E.prog[e];
   T r;
-  const uint8_t d = post_step<T, J>(E, e, n, ps, q, qd, prog, &r, obs);
+  const uint8_t d = post_step<T, J>(E, e, n, ps, q, qd, prog, &r, obs, nullptr, nullptr, E.step);
   store_state<T, J>(E, e, n, q, qd, prog);
   rew[e] = r;
   done[e] = d;
@@ -324,6 +297,11 @@ hipError_t launch_reset(const sg_ctx* c) {
   const dim3 g((c->N + 255) / 256);
   if (c->dtype == SG_F64) k_reset<double><<<g, 256, 0, c->stream>>>(env_view<double>(c));
   else k_reset<float><<<g, 256, 0, c->stream>>>(env_view<float>(c));
+  if (c->gs) {
+    const size_t b = 9 * (size_t)c->N * (c->dtype == SG_F64 ? sizeof(double) : sizeof(float));
+    hipError_t e = hipMemcpyAsync(c->gs, c->gs0, b, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

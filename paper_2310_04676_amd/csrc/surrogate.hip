@@ -464,7 +464,7 @@ __global__ void __launch_bounds__(256) k_sstep_f(SStepArgs A, float* __restrict_
   integrate<J>(E, P, n, A.qddbuf, e, q, qd);
   int prog = E.prog[e];
   float r;
-  const uint8_t d = post_step<float, J>(E, e, n, P, q, qd, prog, &r, obs);
+  const uint8_t d = post_step<float, J>(E, e, n, P, q, qd, prog, &r, obs, nullptr, nullptr, E.step);
   store_state<float, J>(E, e, n, q, qd, prog);
   rew[e] = r;
   done[e] = d;

@@ -34,11 +34,12 @@ import numpy as np
 
 __all__ = [
     "Robot", "Task", "Policy", "Workload", "stream", "make_chain", "reach_fp64", "path_rollout",
-    "mixed_dof", "make_policy", "random_actions", "random_states",
+    "mixed_dof", "tracking", "psm_like", "make_policy", "random_actions", "random_states",
 ]
 
 TASK_REACH = 0
 TASK_PATH = 1
+TASK_TRACK = 2
 WORK_CENTRE = np.array([0.4, 0.0, 0.6])
 
 
@@ -83,6 +84,7 @@ class Task:
     dwell: int
     ep_len: int
     progress0: np.ndarray          # int32 [N]
+    track: dict | None = None      # tracking task: sigma, offset, reset_std, centre
 
     @property
     def n_waypoints(self):
@@ -252,8 +254,13 @@ def _round_robot(r: Robot, dtype) -> Robot:
 
 
 def _round_task(t: Task, dtype) -> Task:
+    tr = None
+    if t.track is not None:
+        f = lambda v: float(np.asarray(v, dtype=dtype))
+        tr = dict(sigma=f(t.track["sigma"]), offset=f(t.track["offset"]), reset_std=f(t.track["reset_std"]),
+                  centre=tuple(f(c) for c in t.track["centre"]))
     return Task(task=t.task, target=_as_dtype(t.target, dtype), waypoints=_as_dtype(t.waypoints, dtype),
-                dwell=t.dwell, ep_len=t.ep_len, progress0=t.progress0)
+                dwell=t.dwell, ep_len=t.ep_len, progress0=t.progress0, track=tr)
 
 
 def make_policy(seed: int, dims=(24, 256, 128, 8), log_std: float = np.log(0.5)) -> Policy:
@@ -305,6 +312,20 @@ def psm_like(n_env: int = 4096, seed: int = 1004, dtype=np.float32) -> Workload:
     t = Task(task=TASK_REACH, target=tgt, waypoints=None, dwell=1, ep_len=128,
              progress0=stream(seed, "progress0").integers(0, 128, size=n_env).astype(np.int32))
     return Workload("psm_like", _round_robot(r, dtype), _round_task(t, dtype), None, dtype, seed)
+
+
+def tracking(n_env: int = 4096, seed: int = 1005, dtype=np.float32) -> Workload:
+    """Active tracking (paper Sec. IV): 7-DOF FP32 chains, 4 substeps; the
+    first episode's goal centre is W + N(0, 0.05^2) per axis, then a random
+    walk with velocity increments of std 1e-4 m per step inside a +-0.2 m
+    box; new centres drawn on the device at each reset; 128-step episodes
+    with staggered start progress; policy 24-256-128-8."""
+    r = make_chain(n_env, 7, seed, dt=1.0 / 120.0, substeps=4, q0_frac=0.25)
+    tgt = (WORK_CENTRE[None, :] + 0.05 * stream(seed, "centre").standard_normal((n_env, 3))).T.copy()
+    t = Task(task=TASK_TRACK, target=tgt, waypoints=None, dwell=1, ep_len=128,
+             progress0=stream(seed, "progress0").integers(0, 128, size=n_env).astype(np.int32),
+             track=dict(sigma=1e-4, offset=0.2, reset_std=0.05, centre=tuple(WORK_CENTRE)))
+    return Workload("tracking", _round_robot(r, dtype), _round_task(t, dtype), make_policy(seed + 7), dtype, seed)
 
 
 def mixed_dof(n_env: int = 16384, seed: int = 1003, dtype=np.float32) -> Workload:
