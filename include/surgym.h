@@ -127,6 +127,15 @@ typedef struct {
   double track_offset;      /* tracking: half-width of the goal box (m), > 0 */
   double track_reset_std;   /* tracking: spread of a new episode's centre (m) */
   double track_centre[3];   /* tracking: nominal centre (m) */
+  int32_t chains_per_env;   /* multi-tool reaching (Sec. IV): C = 1, 2 or 4
+                             * consecutive env indices (chains) form one env;
+                             * its reward is the sum of the chains' rewards
+                             * (each toward its own goal), its episode is
+                             * shared (progress0 equal within the group) and
+                             * a non-finite chain resets all of them. Every
+                             * output stays per chain (the reward repeated).
+                             * 0 or 1: one chain per env. Tiled schedules
+                             * need C = 1. */
 } sg_task_desc;
 
 /* Rollout storage, all DEVICE memory, float32 unless noted:

@@ -33,7 +33,8 @@ class _Robot(C.Structure):
 class _Task(C.Structure):
     _fields_ = [("task", C.c_int32), ("n_waypoints", C.c_int32), ("dwell", C.c_int32),
                 ("ep_len", C.c_int32), ("target", _dp), ("waypoints", _dp), ("trk_sigma", C.c_double),
-                ("trk_offset", C.c_double), ("trk_reset_std", C.c_double), ("trk_centre", C.c_double * 3)]
+                ("trk_offset", C.c_double), ("trk_reset_std", C.c_double), ("trk_centre", C.c_double * 3),
+                ("chains", C.c_int32)]
 
 
 TASK_TRACK = 2
@@ -93,9 +94,9 @@ class Oracle:
             wps = None if task.waypoints is None else _f64(task.waypoints)
             k.extend([tgt, wps])
             self.t = _Task(task.task, task.n_waypoints, task.dwell, task.ep_len, _ptr(tgt), _ptr(wps),
-                           *_track_params(task))
+                           *_track_params(task), int(getattr(task, "chains", 1) or 1))
         else:
-            self.t = _Task(0, 0, 1, 0, None, None, 0.0, 0.0, 0.0, (C.c_double * 3)(0.0, 0.0, 0.0))
+            self.t = _Task(0, 0, 1, 0, None, None, 0.0, 0.0, 0.0, (C.c_double * 3)(0.0, 0.0, 0.0), 1)
         self.seed = int(getattr(task, "seed", 0) or 0) if task is not None else 0
         self.p = None
         if policy is not None:

@@ -29,6 +29,7 @@
 namespace ora {
 
 constexpr int kMaxDof = 16;
+constexpr int kMaxChains = 4;  // chains per env (multi-tool reaching)
 
 enum { kRevolute = 0, kPrismatic = 1 };
 

@@ -59,6 +59,8 @@ struct TaskSpec {
   // gd += sigma N(0, 1) per step; |g - centre| <= offset per axis; at each
   // reset a new centre = (cx, cy, cz) + reset_std N(0, 1) per axis
   double trk_sigma, trk_offset, trk_reset_std, trk_centre[3];
+  // multi-tool reaching (paper Sec. IV): C consecutive chains form one env
+  int chains = 1;
 };
 
 // Moving goal of one env (tracking task): position, velocity (per control
@@ -209,6 +211,53 @@ inline uint8_t env_step(const Chain<T>& ch, const Drive<T>& dr, T dt, int S, int
     track_advance(ts, *tr, seed, env, step);
   }
   observe(ch, Jmax, ts, g, q, qd, *progress, obs, tr);
+  return done;
+}
+
+// One control step of an env made of C chains (paper Sec. IV multi-tool
+// reaching): every chain is driven by its own action towards its own goal;
+// the env's reward is the sum of the chains' rewards (rho = -1), the episode
+// (progress, time-out) is shared, and a non-finite state of any chain ends
+// the episode of all of them with reward 0. Returns the done bits; tr (per
+// chain, tracking task only) uses Philox env ids lane[c].
+template <class T>
+inline uint8_t group_step(int C, const Chain<T>* ch, const Drive<T>* dr, T dt, int S, int Jmax, const TaskSpec& ts,
+                          const EnvGoal<T>* g, const T* const* action, T* const* q, T* const* qd, int* progress,
+                          T* reward, T* const* obs, Track<T>* tr, uint64_t seed, const uint32_t* lane,
+                          uint64_t step) {
+  const int pre = *progress;
+  T rsum = T(0.0);
+  bool finite = true;
+  for (int c = 0; c < C; ++c) {
+    physics_step(ch[c], dr[c], dt, S, action[c], q[c], qd[c], (T*)nullptr);
+    Pose<T> P;
+    forward_kinematics(ch[c], q[c], P);
+    const V3<T> goal = tr ? tr[c].g : goal_for(ts, g[c], pre);
+    rsum = rsum - norm3(P.tip - goal);
+    for (int j = 0; j < ch[c].n; ++j) finite = finite && std::isfinite(val(q[c][j])) && std::isfinite(val(qd[c][j]));
+  }
+  *progress = pre + 1;
+  uint8_t done = 0;
+  if (!finite) {
+    done = kDoneEnded | kDoneNonFinite;
+    rsum = T(0.0);
+  } else if (ts.ep_len > 0 && *progress >= ts.ep_len) {
+    done = kDoneEnded | kDoneTimeout;
+  }
+  for (int c = 0; c < C; ++c) {
+    if (done) {
+      for (int j = 0; j < ch[c].n; ++j) {
+        q[c][j] = dr[c].q0[j];
+        qd[c][j] = T(0.0);
+      }
+      if (tr) track_reset(ts, tr[c], seed, lane[c], step);
+    } else if (tr) {
+      track_advance(ts, tr[c], seed, lane[c], step);
+    }
+  }
+  if (done) *progress = 0;
+  for (int c = 0; c < C; ++c) observe(ch[c], Jmax, ts, g[c], q[c], qd[c], *progress, obs[c], tr ? &tr[c] : nullptr);
+  *reward = rsum;
   return done;
 }
 

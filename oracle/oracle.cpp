@@ -49,6 +49,7 @@ typedef struct {
   const double* target;     // [3][N] (reach; tracking: the first episode's centre)
   const double* waypoints;  // [K][3][N]
   double trk_sigma, trk_offset, trk_reset_std, trk_centre[3];  // tracking task
+  int32_t chains;           // chains per env (multi-tool reaching); <= 1: one
 } ora_task;
 
 typedef struct {
@@ -109,6 +110,7 @@ TaskSpec load_taskspec(const ora_task* t) {
   s.trk_offset = t->trk_offset;
   s.trk_reset_std = t->trk_reset_std;
   for (int k = 0; k < 3; ++k) s.trk_centre[k] = t->trk_centre[k];
+  s.chains = t->chains > 1 ? t->chains : 1;
   return s;
 }
 
@@ -295,6 +297,53 @@ int ora_step(const ora_robot* r, const ora_task* t, const double* action, double
   const int N = r->n_env, J = r->max_dof, W = 2 * J + 10, S = r->substeps;
   TaskSpec ts = load_taskspec(t);
   (void)n_threads;
+  if (ts.chains > 1) {
+    // multi-chain envs: chains [k C, (k + 1) C) form env k
+    const int C = ts.chains;
+    if (e0 % C || e1 % C || N % C) return -1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(n_threads > 0 ? n_threads : 1)
+#endif
+    for (int k = e0 / C; k < e1 / C; ++k) {
+      Chain<double> ch[kMaxChains];
+      Drive<double> dr[kMaxChains];
+      EnvGoal<double> g[kMaxChains];
+      Track<double> tr[kMaxChains];
+      double qe[kMaxChains][kMaxDof], qde[kMaxChains][kMaxDof], ae[kMaxChains][kMaxDof], oe[kMaxChains][64];
+      double* qp[kMaxChains];
+      double* qdp[kMaxChains];
+      double* op[kMaxChains];
+      const double* ap[kMaxChains];
+      uint32_t lane[kMaxChains];
+      for (int c = 0; c < C; ++c) {
+        const int e = k * C + c;
+        ch[c] = load_chain<double>(r, e);
+        dr[c] = load_drive<double>(r, e);
+        g[c] = load_goal<double>(t, N, e);
+        if (ts.task == kTaskTrack) tr[c] = load_track(goal_state, N, e);
+        gather(q, J, N, e, ch[c].n, qe[c]);
+        gather(qd, J, N, e, ch[c].n, qde[c]);
+        gather(action, J, N, e, ch[c].n, ae[c]);
+        qp[c] = qe[c]; qdp[c] = qde[c]; op[c] = oe[c]; ap[c] = ae[c];
+        lane[c] = (uint32_t)e;
+      }
+      int prog = progress[k * C];
+      double rew;
+      const uint8_t d = group_step(C, ch, dr, r->dt, S, J, ts, g, ap, qp, qdp, &prog, &rew, op,
+                                   ts.task == kTaskTrack ? tr : nullptr, seed, lane, step);
+      for (int c = 0; c < C; ++c) {
+        const int e = k * C + c;
+        if (ts.task == kTaskTrack) store_track(goal_state, N, e, tr[c]);
+        scatter(q, J, N, e, ch[c].n, qe[c]);
+        scatter(qd, J, N, e, ch[c].n, qde[c]);
+        progress[e] = prog;
+        reward[e] = rew;
+        done[e] = d;
+        for (int w = 0; w < W; ++w) obs[w * N + e] = oe[c][w];
+      }
+    }
+    return 0;
+  }
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) num_threads(n_threads > 0 ? n_threads : 1)
 #endif
@@ -416,6 +465,78 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
   MlpLayer L[3];
   for (int l = 0; l < 3; ++l) L[l] = {p->dims[l], p->dims[l + 1], p->W[l], p->b[l]};
   const double half_log_2pi = 0.91893853320467274178032973640562;
+  if (ts.chains > 1) {
+    // multi-chain envs: each chain acts on its own observation with the
+    // shared policy; the env's reward and episode are shared (group_step)
+    const int C = ts.chains;
+    if (e0 % C || e1 % C || N % C) return -1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+#endif
+    for (int kk = e0 / C; kk < e1 / C; ++kk) {
+      Chain<double> ch[kMaxChains];
+      Drive<double> dr[kMaxChains];
+      EnvGoal<double> g[kMaxChains];
+      Track<double> tr[kMaxChains];
+      double qe[kMaxChains][kMaxDof], qde[kMaxChains][kMaxDof], a[kMaxChains][kMaxDof], x[kMaxChains][64];
+      double o[64], sa[1024], sb[1024], eps[kMaxDof];
+      double* qp[kMaxChains];
+      double* qdp[kMaxChains];
+      double* xp[kMaxChains];
+      const double* ap[kMaxChains];
+      uint32_t lane[kMaxChains];
+      for (int c = 0; c < C; ++c) {
+        const int e = kk * C + c;
+        ch[c] = load_chain<double>(r, e);
+        dr[c] = load_drive<double>(r, e);
+        g[c] = load_goal<double>(t, N, e);
+        if (ts.task == kTaskTrack) tr[c] = load_track(goal_state, N, e);
+        gather(q, J, N, e, ch[c].n, qe[c]);
+        gather(qd, J, N, e, ch[c].n, qde[c]);
+        for (int w = 0; w < W; ++w) x[c][w] = obs[(size_t)w * N + e];
+        qp[c] = qe[c]; qdp[c] = qde[c]; xp[c] = x[c]; ap[c] = a[c];
+        lane[c] = (uint32_t)e;
+      }
+      int prog = progress[kk * C];
+      for (int s = 0; s < T; ++s) {
+        for (int c = 0; c < C; ++c) {
+          const int e = kk * C + c, n = ch[c].n;
+          mlp_forward(L, 3, x[c], o, emulate != 0, sa, sb);
+          gaussian_noise(seed, (uint32_t)e, step0 + (uint64_t)s, n, eps);
+          double lp = 0.0;
+          for (int j = 0; j < n; ++j) {
+            const double sigma = std::exp(p->log_std[j]);
+            a[c][j] = o[j] + sigma * eps[j];
+            lp += -0.5 * eps[j] * eps[j] - p->log_std[j] - half_log_2pi;
+            act[((size_t)s * J + j) * N + e] = a[c][j];
+          }
+          for (int j = n; j < J; ++j) act[((size_t)s * J + j) * N + e] = 0.0;
+          val_[(size_t)s * N + e] = o[J];
+          logp[(size_t)s * N + e] = lp;
+        }
+        double rw;
+        const uint8_t d = group_step(C, ch, dr, r->dt, S, J, ts, g, ap, qp, qdp, &prog, &rw, xp,
+                                     ts.task == kTaskTrack ? tr : nullptr, seed, lane, step0 + (uint64_t)s);
+        for (int c = 0; c < C; ++c) {
+          const int e = kk * C + c;
+          rew[(size_t)s * N + e] = rw;
+          done[(size_t)s * N + e] = d;
+          for (int w = 0; w < W; ++w) obs[((size_t)(s + 1) * W + w) * N + e] = x[c][w];
+        }
+      }
+      for (int c = 0; c < C; ++c) {
+        const int e = kk * C + c;
+        mlp_forward(L, 3, x[c], o, emulate != 0, sa, sb);
+        val_[(size_t)T * N + e] = o[J];
+        if (ts.task == kTaskTrack) store_track(goal_state, N, e, tr[c]);
+        scatter(q, J, N, e, ch[c].n, qe[c]);
+        scatter(qd, J, N, e, ch[c].n, qde[c]);
+        progress[e] = prog;
+      }
+    }
+    for (int e = e0; e < e1; ++e) gae_env(T, N, e, rew, val_, done, gamma, lam, adv, ret);
+    return 0;
+  }
   (void)n_threads;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 4) num_threads(n_threads > 0 ? n_threads : 1)

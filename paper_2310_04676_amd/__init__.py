@@ -40,7 +40,7 @@ class TaskDesc(C.Structure):
     _fields_ = [("task", C.c_int32), ("n_waypoints", C.c_int32), ("dwell", C.c_int32), ("ep_len", C.c_int32),
                 ("target", _dp), ("waypoints", _dp), ("progress0", _ip), ("seed", C.c_uint64),
                 ("track_sigma", C.c_double), ("track_offset", C.c_double), ("track_reset_std", C.c_double),
-                ("track_centre", C.c_double * 3)]
+                ("track_centre", C.c_double * 3), ("chains_per_env", C.c_int32)]
 
 
 class RolloutBufs(C.Structure):
@@ -135,7 +135,8 @@ def make_descs(robot, task, dtype, seed=0):
     tr = getattr(task, "track", None) or {}
     td = TaskDesc(task.task, task.n_waypoints, task.dwell, task.ep_len, _ptr(tgt), _ptr(wps), _ptr(p0, _ip),
                   seed & 0xFFFFFFFFFFFFFFFF, float(tr.get("sigma", 0.0)), float(tr.get("offset", 0.0)),
-                  float(tr.get("reset_std", 0.0)), (C.c_double * 3)(*tr.get("centre", (0.0, 0.0, 0.0))))
+                  float(tr.get("reset_std", 0.0)), (C.c_double * 3)(*tr.get("centre", (0.0, 0.0, 0.0))),
+                  int(getattr(task, "chains", 1) or 1))
     return rd, td, keep
 
 

@@ -70,6 +70,13 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
   if (t->task == SG_TASK_PATH &&
       (!t->waypoints || t->n_waypoints < 1 || t->n_waypoints > SG_MAX_WAYPOINTS || t->dwell < 1))
     return fail(nullptr, SG_E_INVAL, "sg_create: path task needs 1..32 waypoints and dwell >= 1");
+  const int C = t->chains_per_env > 1 ? t->chains_per_env : 1;
+  if (C != 1 && C != 2 && C != 4) return fail(nullptr, SG_E_UNSUPPORTED, "sg_create: chains_per_env must be 1, 2 or 4");
+  if (N % C) return fail(nullptr, SG_E_INVAL, "sg_create: n_env must be a multiple of chains_per_env");
+  if (C > 1 && t->progress0)
+    for (int e = 0; e < N; ++e)
+      if (t->progress0[e] != t->progress0[e - e % C])
+        return fail(nullptr, SG_E_INVAL, "sg_create: the chains of an env must share progress0");
   const size_t JN = (size_t)J * N;
   for (int e = 0; e < N; ++e) {
     const int n = r->n_dof[e];
@@ -98,6 +105,7 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
   for (int k = 0; k < 3; ++k) c->g[k] = r->gravity[k];
   c->task = t->task; c->K = t->task == SG_TASK_PATH ? t->n_waypoints : 1;
   c->dwell = t->dwell > 0 ? t->dwell : 1; c->ep_len = t->ep_len; c->seed = t->seed; c->rng_step = 0;
+  c->chains = C;
   if (t->task == SG_TASK_TRACK) {
     c->trk_sigma = t->track_sigma; c->trk_offset = t->track_offset; c->trk_reset_std = t->track_reset_std;
     for (int k = 0; k < 3; ++k) c->trk_c[k] = t->track_centre[k];
@@ -245,6 +253,8 @@ sg_status sg_set_schedule(sg_ctx* c, int32_t schedule) {
     return fail(c, SG_E_UNSUPPORTED, "sg_set_schedule: tiled schedules need an FP32 context");
   if (schedule != SG_SCHED_PADDED && c->prismatic)
     return fail(c, SG_E_UNSUPPORTED, "sg_set_schedule: tiled schedules need an all-revolute context");
+  if (schedule != SG_SCHED_PADDED && c->chains > 1)
+    return fail(c, SG_E_UNSUPPORTED, "sg_set_schedule: tiled schedules need one chain per env");
   c->schedule = schedule;
   return SG_OK;
 }
@@ -281,7 +291,7 @@ sg_status sg_autotune_step(sg_ctx* c, const void* act, int32_t trials, int32_t* 
   if (e == hipSuccess && c->gs) e = hipMalloc(&gsv, gsb);
   if (e == hipSuccess && c->gs) e = hipMemcpyAsync(gsv, c->gs, gsb, hipMemcpyDeviceToDevice, c->stream);
   const int saved = c->schedule;
-  const int n_sched = (c->dtype == SG_F32 && !c->prismatic) ? 4 : 1;
+  const int n_sched = (c->dtype == SG_F32 && !c->prismatic && c->chains == 1) ? 4 : 1;
   float best_ms = 0.f;
   int best_s = SG_SCHED_PADDED;
   for (int s = 0; s < 4 && e == hipSuccess; ++s) {

@@ -22,6 +22,7 @@ enum { DONE_ENDED = 1, DONE_TIMEOUT = 2, DONE_NONFINITE = 4 };
 
 template <typename T> struct EnvDev {
   int N, J, S, task, K, dwell, ep_len;
+  int chains;         // consecutive lanes (chains) per env: 1, 2 or 4
   T dt, h, g[3];
   const T* par;       // [P_NFIELDS][J][N]
   const T* tip;       // [3][N]
@@ -278,6 +279,16 @@ __device__ __forceinline__ uint8_t post_step(const EnvDev<T>& E, int e, int n, P
 #pragma unroll
   for (int j = 0; j < J; ++j)
     if (j < n) fin = fin && finite_(q[j]) && finite_(qd[j]);
+  if (E.chains > 1) {
+    // an env of several chains (consecutive lanes of one wave, all active):
+    // the reward is their sum and any non-finite chain ends the episode of all
+    int bad = fin ? 0 : 1;
+    for (int m = 1; m < E.chains; m <<= 1) {
+      r += __shfl_xor(r, m, 64);
+      bad |= __shfl_xor(bad, m, 64);
+    }
+    fin = bad == 0;
+  }
   uint8_t done = 0;
   if (!fin) {
     done = DONE_ENDED | DONE_NONFINITE;

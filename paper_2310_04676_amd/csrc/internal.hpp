@@ -15,6 +15,7 @@ struct sg_ctx {
   bool uniform = false;    // every env has J joints and J is a kernel instantiation
   bool prismatic = false;  // some env has a prismatic joint
   int task = 0, K = 0, dwell = 1, ep_len = 0;
+  int chains = 1;  // chains per env (consecutive env indices)
   double dt = 0, g[3] = {0, 0, 0};
   uint64_t seed = 0, rng_step = 0;
   hipStream_t stream = nullptr;
@@ -56,6 +57,7 @@ namespace sgk {
 template <typename T> inline EnvDev<T> env_view(const sg_ctx* c) {
   EnvDev<T> E;
   E.N = c->N; E.J = c->J; E.S = c->S; E.task = c->task; E.K = c->K; E.dwell = c->dwell; E.ep_len = c->ep_len;
+  E.chains = c->chains;
   E.dt = (T)c->dt;
   E.h = E.dt / (T)c->S;
   E.g[0] = (T)c->g[0]; E.g[1] = (T)c->g[1]; E.g[2] = (T)c->g[2];

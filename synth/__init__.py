@@ -34,7 +34,7 @@ import numpy as np
 
 __all__ = [
     "Robot", "Task", "Policy", "Workload", "stream", "make_chain", "reach_fp64", "path_rollout",
-    "mixed_dof", "tracking", "psm_like", "make_policy", "random_actions", "random_states",
+    "mixed_dof", "tracking", "psm_like", "multi_arm", "make_policy", "random_actions", "random_states",
 ]
 
 TASK_REACH = 0
@@ -85,6 +85,7 @@ class Task:
     ep_len: int
     progress0: np.ndarray          # int32 [N]
     track: dict | None = None      # tracking task: sigma, offset, reset_std, centre
+    chains: int = 1                # chains per env (consecutive env indices)
 
     @property
     def n_waypoints(self):
@@ -260,7 +261,7 @@ def _round_task(t: Task, dtype) -> Task:
         tr = dict(sigma=f(t.track["sigma"]), offset=f(t.track["offset"]), reset_std=f(t.track["reset_std"]),
                   centre=tuple(f(c) for c in t.track["centre"]))
     return Task(task=t.task, target=_as_dtype(t.target, dtype), waypoints=_as_dtype(t.waypoints, dtype),
-                dwell=t.dwell, ep_len=t.ep_len, progress0=t.progress0, track=tr)
+                dwell=t.dwell, ep_len=t.ep_len, progress0=t.progress0, track=tr, chains=t.chains)
 
 
 def make_policy(seed: int, dims=(24, 256, 128, 8), log_std: float = np.log(0.5)) -> Policy:
@@ -326,6 +327,23 @@ def tracking(n_env: int = 4096, seed: int = 1005, dtype=np.float32) -> Workload:
              progress0=stream(seed, "progress0").integers(0, 128, size=n_env).astype(np.int32),
              track=dict(sigma=1e-4, offset=0.2, reset_std=0.05, centre=tuple(WORK_CENTRE)))
     return Workload("tracking", _round_robot(r, dtype), _round_task(t, dtype), make_policy(seed + 7), dtype, seed)
+
+
+def multi_arm(n_env: int = 2048, chains: int = 2, seed: int = 1006, dtype=np.float32) -> Workload:
+    """Multi-tool reaching (paper Sec. IV): `chains` 7-DOF arms per env
+    (env k owns chains k*C .. k*C + C - 1), bases spread along y (0.6 m
+    apart), each arm with its own target U[-0.15, 0.15]^3 around the point
+    0.4 m in front of and 0.6 m above its base; FP32, 4 substeps, 128-step
+    episodes with a start progress shared by an env's arms."""
+    N = n_env * chains
+    r = make_chain(N, 7, seed, dt=1.0 / 120.0, substeps=4, q0_frac=0.25)
+    base_y = (np.arange(N) % chains - 0.5 * (chains - 1)) * 0.6
+    r.offset[1, 0, :] = base_y
+    centre = np.stack([np.full(N, 0.4), base_y, np.full(N, 0.6)], axis=1)
+    tgt = (centre + _per_env(seed, "target", N, 3, -0.15, 0.15)).T.copy()
+    p0 = np.repeat(stream(seed, "progress0").integers(0, 128, size=n_env).astype(np.int32), chains)
+    t = Task(task=TASK_REACH, target=tgt, waypoints=None, dwell=1, ep_len=128, progress0=p0, chains=chains)
+    return Workload("multi_arm", _round_robot(r, dtype), _round_task(t, dtype), make_policy(seed + 7), dtype, seed)
 
 
 def mixed_dof(n_env: int = 16384, seed: int = 1003, dtype=np.float32) -> Workload:
