@@ -37,7 +37,9 @@ template <int ACT> __device__ __forceinline__ float act_grad(float z) {
 //   EPI_FWD_HIDDEN  z + bias -> C (FP32), act(z) -> Cb (BF16)
 //   EPI_FWD_OUT     z + bias -> C
 //   EPI_PLAIN       z -> C
-//   EPI_BWD_DX      z act'(Zp) -> C and Cb (backward through the unit)
+//   EPI_BWD_DX      z act'(Zp) -> C (if non-null) and Cb (backward through
+//                   the unit); with colpart, the column sums of the block's
+//                   64 rows as well (bias gradients without a second pass)
 //   EPI_PARTIAL     block z of the grid sums K in [z kchunk, (z+1) kchunk)
 //                   and writes its partial to C + z M ldc (split-K; reduce
 //                   with k_sum_splits)
@@ -55,6 +57,7 @@ struct GemmArgs {
   uint16_t* Cb;      // bf16 output [M][ldc] (act(z) forward, gradient backward)
   const float* Zp;   // pre-activations of the previous layer [M][ldc] (backward data)
   int kchunk;        // split-K chunk (multiple of 32)
+  float* colpart;    // EPI_BWD_DX: per-block column sums of the result [gridDim.y][N] (may be null)
 };
 
 template <int EPI, bool AT, bool BT, int ACT>
@@ -77,16 +80,68 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int lr = tid >> 2, lk = (tid & 3) * 8;  // loader: row / first k of 8
+  // Loaders. Contiguous-k operands (A row-major, B transposed): thread t
+  // takes 8 consecutive k of row t / 4. Contiguous-m/n operands: thread t
+  // takes 8 consecutive rows at k = t / 8. With 16-byte aligned rows each is
+  // one vector load; otherwise (or at a ragged edge) element by element.
+  const int lr = tid >> 2, lk = (tid & 3) * 8;
+  const int tk = tid >> 3, tm = (tid & 7) * 8;
+  const bool avec = (((uintptr_t)g.A) & 15) == 0 && (g.lda & 7) == 0;
+  const bool bvec = (((uintptr_t)g.B) & 15) == 0 && (g.ldb & 7) == 0;
   for (int k0 = kbeg; k0 < kend; k0 += 32) {
+    if (!AT) {
+      const int m = m0 + lr, k = k0 + lk;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (m < g.M && k < kend) {
+        if (avec && k + 8 <= kend) {
+          v = *reinterpret_cast<const uint4*>(g.A + (size_t)m * g.lda + k);
+        } else {
+          uint16_t t[8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int m = m0 + lr, k = k0 + lk + s, n = n0 + lr;
-      uint16_t av = 0, bv = 0;
-      if (m < g.M && k < kend) av = AT ? g.A[(size_t)k * g.lda + m] : g.A[(size_t)m * g.lda + k];
-      if (n < g.N && k < kend) bv = BT ? g.B[(size_t)n * g.ldb + k] : g.B[(size_t)k * g.ldb + n];
-      As[lr][lk + s] = av;
-      Bs[lr][lk + s] = bv;
+          for (int s = 0; s < 8; ++s) t[s] = (k + s < kend) ? g.A[(size_t)m * g.lda + k + s] : 0;
+          v = *reinterpret_cast<uint4*>(t);
+        }
+      }
+      *reinterpret_cast<uint4*>(&As[lr][lk]) = v;
+    } else {
+      const int k = k0 + tk, m = m0 + tm;
+      uint16_t t[8];
+      if (k < kend && avec && m + 8 <= g.M) {
+        const uint4 v = *reinterpret_cast<const uint4*>(g.A + (size_t)k * g.lda + m);
+        *reinterpret_cast<uint4*>(t) = v;
+      } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) t[s] = (k < kend && m + s < g.M) ? g.A[(size_t)k * g.lda + m + s] : 0;
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) As[tm + s][tk] = t[s];
+    }
+    if (BT) {
+      const int n = n0 + lr, k = k0 + lk;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (n < g.N && k < kend) {
+        if (bvec && k + 8 <= kend) {
+          v = *reinterpret_cast<const uint4*>(g.B + (size_t)n * g.ldb + k);
+        } else {
+          uint16_t t[8];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) t[s] = (k + s < kend) ? g.B[(size_t)n * g.ldb + k + s] : 0;
+          v = *reinterpret_cast<uint4*>(t);
+        }
+      }
+      *reinterpret_cast<uint4*>(&Bs[lr][lk]) = v;
+    } else {
+      const int k = k0 + tk, n = n0 + tm;
+      uint16_t t[8];
+      if (k < kend && bvec && n + 8 <= g.N) {
+        const uint4 v = *reinterpret_cast<const uint4*>(g.B + (size_t)k * g.ldb + n);
+        *reinterpret_cast<uint4*>(t) = v;
+      } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) t[s] = (k < kend && n + s < g.N) ? g.B[(size_t)k * g.ldb + n + s] : 0;
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) Bs[tm + s][tk] = t[s];
     }
     __syncthreads();
     bf16x8 af[2], bfr[2];
@@ -101,6 +156,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x32(af[a], bfr[b], acc[a][b]);
     __syncthreads();
   }
+  float cs[2] = {0.f, 0.f};  // EPI_BWD_DX: this lane's share of two column sums
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -112,11 +168,30 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         const size_t i = (size_t)m * g.ldc + n;
         float z = acc[a][b][r];
         if (EPI == EPI_FWD_HIDDEN || EPI == EPI_FWD_OUT) z += g.bias[n];
-        if (EPI == EPI_BWD_DX) z *= act_grad<ACT>(g.Zp[i]);
-        C[i] = z;
+        if (EPI == EPI_BWD_DX) {
+          z *= act_grad<ACT>(g.Zp[i]);
+          cs[b] += z;
+        }
+        if (EPI != EPI_BWD_DX || C) C[i] = z;
         if (EPI == EPI_FWD_HIDDEN) g.Cb[i] = bf16_bits(act_f<ACT>(z));
         if (EPI == EPI_BWD_DX) g.Cb[i] = bf16_bits(z);
       }
+  if (EPI == EPI_BWD_DX && g.colpart) {
+    // columns n0 + wn + 16 b + li: add the four row groups of the wave, then
+    // the two waves that share the columns, in a fixed order
+    __shared__ float csum[2][2][32];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cs[b] += __shfl_xor(cs[b], 16, 64);
+      cs[b] += __shfl_xor(cs[b], 32, 64);
+      if (gi == 0) csum[wm >> 5][wn >> 5][16 * b + li] = cs[b];
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int n = n0 + tid;
+      if (n < g.N) g.colpart[(size_t)blockIdx.y * g.N + n] = csum[0][tid >> 5][tid & 31] + csum[1][tid >> 5][tid & 31];
+    }
+  }
 }
 
 template <int EPI, bool AT, bool BT, int ACT>
@@ -125,16 +200,25 @@ static inline void launch_gemm(hipStream_t s, const GemmArgs& a, int splits = 1)
   k_gemm<EPI, AT, BT, ACT><<<grid, 256, 0, s>>>(a);
 }
 
-// out[i * ldo + j] = sum_z part[z][i][j] over `splits` slabs of [M][N]
-// (fixed order: deterministic).
+// out[i * ldo + j] = sum_z part[z * stride + i N + j] over `splits` slabs
+// (stride 0: M N); 16 outputs per block, 16 thread groups each summing every
+// 16th slab, combined in a fixed order: deterministic.
 static __global__ void __launch_bounds__(256) k_sum_splits(const float* __restrict__ part, int splits, int M, int N,
-                                                           float* __restrict__ out, int ldo) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= M * N) return;
-  const int i = t / N, j = t % N;
+                                                           float* __restrict__ out, int ldo, int stride = 0) {
+  __shared__ float red[16][16];
+  const int o = blockIdx.x * 16 + (threadIdx.x & 15), grp = threadIdx.x >> 4;
+  const size_t st = stride > 0 ? (size_t)stride : (size_t)M * N;
   float s = 0.f;
-  for (int z = 0; z < splits; ++z) s += part[(size_t)z * M * N + t];
-  out[(size_t)i * ldo + j] = s;
+  if (o < M * N)
+    for (int z = grp; z < splits; z += 16) s += part[(size_t)z * st + o];
+  red[grp][threadIdx.x & 15] = s;
+  __syncthreads();
+  if (grp == 0 && o < M * N) {
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t += red[k][threadIdx.x];
+    out[(size_t)(o / N) * ldo + o % N] = t;
+  }
 }
 
 // db[c] = sum_r G[r][c].

@@ -7,12 +7,14 @@
 //   k_ppo_gather   obs rows -> BF16 X [B][32]
 //   forward        three BF16 MFMA GEMMs (nn.hpp), tanh units; the
 //                  pre-activations stay in HBM for the backward pass
-//   k_ppo_loss     ratio, clipped objectives, dL/d(outputs) [B][8] and the
-//                  per-row log_std gradient; loss statistics
-//   backward       data gradients as GEMMs with the tanh' epilogue; weight
-//                  gradients as split-K GEMMs (the batch is the reduction
-//                  axis) summed in a fixed order; bias and log_std
-//                  gradients as split column sums -- deterministic
+//   k_ppo_loss     ratio, clipped objectives, dL/d(outputs) [B][8] (BF16
+//                  for the GEMMs) and per-block sums of the output-bias and
+//                  log_std gradients; loss statistics
+//   backward       data gradients as GEMMs with the tanh' epilogue, which
+//                  also emits per-block column sums (the hidden biases'
+//                  gradients); weight gradients as split-K GEMMs (the batch
+//                  is the reduction axis); every partial is summed in a
+//                  fixed order -- deterministic
 //   k_ppo_gnorm    entropy term and the global gradient norm
 //   k_ppo_adam     norm clip + Adam on the FP32 master weights + BF16 copy
 // After an update k_ppo_pack rewrites the context's rollout weight image
@@ -43,15 +45,12 @@ struct sg_ppo {
   float* Z2 = nullptr;       // [rows][128]
   uint16_t* H2 = nullptr;
   float* Z3 = nullptr;       // [rows][8]
-  float* G3 = nullptr;       // [rows][8]
-  uint16_t* G3b = nullptr;
-  float* DL = nullptr;       // [rows][8] per-row log_std gradient
-  float* D2 = nullptr;       // [rows][128]
-  uint16_t* D2b = nullptr;
-  float* D1 = nullptr;       // [rows][256]
-  uint16_t* D1b = nullptr;
-  float* ws = nullptr;       // split-K / column-sum partials
+  uint16_t* G3b = nullptr;   // [rows][8] dL/d(outputs)
+  uint16_t* D2b = nullptr;   // [rows][128]
+  uint16_t* D1b = nullptr;   // [rows][256]
+  float* ws = nullptr;       // split-K partials
   size_t ws_floats = 0;
+  float* cpart = nullptr;    // per-block column sums [rows / 64 (or / 256)][256]
   std::vector<void*> allocs;
 };
 
@@ -59,7 +58,6 @@ namespace sgk {
 
 constexpr int kPX = 32;   // padded input width
 constexpr int kPO = 8;    // padded output width (J + 1 <= 8)
-constexpr int kColChunk = 256;  // rows per column-sum partial
 
 struct PpoRows {
   const float* obs;   // [T+1][W][N]
@@ -127,9 +125,8 @@ struct PpoLossArgs {
   float clip, c_v;
   float inv_b;          // 1 / rows
   float w_stats;        // weight of this minibatch in the statistics
-  float* G3;            // [rows][8]
-  uint16_t* G3b;
-  float* DL;            // [rows][8]
+  uint16_t* G3b;        // [rows][8] BF16 dL/d(outputs)
+  float* part;          // [gridDim.x][16]: block sums of dL/d(outputs) (0..7) and dL/dlog_std (8..15)
   float* stats;         // loss_pi, loss_v, entropy, approx_kl, clip_frac, |g|
 };
 
@@ -139,12 +136,12 @@ __global__ void __launch_bounds__(256) k_ppo_loss(PpoLossArgs a) {
   const int r = blockIdx.x * 256 + threadIdx.x;
   const PpoRows& R = a.rows;
   float lpi = 0.f, lv = 0.f, kl = 0.f, cf = 0.f;
+  float g[kPO], dl[kPO];
+#pragma unroll
+  for (int k = 0; k < kPO; ++k) { g[k] = 0.f; dl[k] = 0.f; }
   if (r < R.rows) {
     const int s = ppo_sample(R, r);
     const bool ok = s >= 0 && s < R.total;
-    float g[kPO], dl[kPO];
-#pragma unroll
-    for (int k = 0; k < kPO; ++k) { g[k] = 0.f; dl[k] = 0.f; }
     if (ok) {
       const int t = s / R.N, e = s % R.N, J = R.J;
       const float* z = a.Z3 + (size_t)r * kPO;
@@ -180,11 +177,27 @@ __global__ void __launch_bounds__(256) k_ppo_loss(PpoLossArgs a) {
       g[J] = a.c_v * dV * a.inv_b;
     }
 #pragma unroll
-    for (int k = 0; k < kPO; ++k) {
-      a.G3[(size_t)r * kPO + k] = g[k];
-      a.G3b[(size_t)r * kPO + k] = bf16_bits(g[k]);
-      a.DL[(size_t)r * kPO + k] = dl[k];
-    }
+    for (int k = 0; k < kPO; ++k) a.G3b[(size_t)r * kPO + k] = bf16_bits(g[k]);
+  }
+  {
+    // block sums of the FP32 gradients, in a fixed order
+    __shared__ float red[4][2 * kPO];
+#pragma unroll
+    for (int k = 0; k < kPO; ++k)
+      for (int o = 32; o > 0; o >>= 1) {
+        g[k] += __shfl_xor(g[k], o, 64);
+        dl[k] += __shfl_xor(dl[k], o, 64);
+      }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int k = 0; k < kPO; ++k) {
+        red[threadIdx.x >> 6][k] = g[k];
+        red[threadIdx.x >> 6][kPO + k] = dl[k];
+      }
+    __syncthreads();
+    if (threadIdx.x < 2 * kPO)
+      a.part[(size_t)blockIdx.x * 2 * kPO + threadIdx.x] =
+          (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
   }
   if (a.stats) {
     const float w = a.w_stats * a.inv_b;
@@ -314,13 +327,12 @@ static void weight_grad(sg_ppo* o, hipStream_t st, int M, int N, int K, const ui
   g.kchunk = chunk_for(K, S);
   const int S_eff = (K + g.kchunk - 1) / g.kchunk;
   launch_gemm<EPI_PARTIAL, AT, BT, ACT_TANH>(st, g, S_eff);
-  k_sum_splits<<<(M * N + 255) / 256, 256, 0, st>>>(o->ws, S_eff, M, N, out, ldo);
+  k_sum_splits<<<(M * N + 15) / 16, 256, 0, st>>>(o->ws, S_eff, M, N, out, ldo);
 }
 
-static void col_sums(sg_ppo* o, hipStream_t st, const float* G, int rows, int cols, int ldg, float* out) {
-  const int nch = (rows + kColChunk - 1) / kColChunk;
-  k_colsum_part<<<dim3((cols + 63) / 64, nch), 256, 0, st>>>(G, rows, cols, ldg, kColChunk, o->ws);
-  k_sum_splits<<<(cols + 255) / 256, 256, 0, st>>>(o->ws, nch, 1, cols, out, cols);
+// out[c] = sum over `blocks` partial rows part[b][c] (row stride `stride`).
+static void sum_partials(hipStream_t st, const float* part, int blocks, int cols, int stride, float* out) {
+  k_sum_splits<<<(cols + 15) / 16, 256, 0, st>>>(part, blocks, 1, cols, out, cols, stride);
 }
 
 // Gradient of one minibatch into o->g (entropy term included, no clip).
@@ -347,25 +359,26 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
   launch_gemm<EPI_FWD_OUT, false, true, ACT_TANH>(st, f);
   PpoLossArgs la;
   la.rows = rows; la.Z3 = o->Z3; la.ls = o->p + o->off[6]; la.clip = cfg->clip; la.c_v = cfg->value_coef;
-  la.inv_b = 1.f / (float)B; la.w_stats = w_stats; la.G3 = o->G3; la.G3b = o->G3b; la.DL = o->DL; la.stats = stats;
+  la.inv_b = 1.f / (float)B; la.w_stats = w_stats; la.G3b = o->G3b; la.part = o->cpart; la.stats = stats;
   k_ppo_loss<<<gb, 256, 0, st>>>(la);
   // output layer gradients
   weight_grad<true, false>(o, st, O, kH2, B, o->G3b, kPO, o->H2, kH2, o->g + o->off[4], kH2);
-  col_sums(o, st, o->G3, B, O, kPO, o->g + o->off[5]);
-  col_sums(o, st, o->DL, B, J, kPO, o->g + o->off[6]);
-  // dZ2 = (G3 W3) * tanh'(Z2)
+  sum_partials(st, o->cpart, gb, O, 2 * kPO, o->g + o->off[5]);
+  sum_partials(st, o->cpart + kPO, gb, J, 2 * kPO, o->g + o->off[6]);
+  // dZ2 = (G3 W3) * tanh'(Z2), with the column sums of dZ2 (hidden-2 bias)
+  const int rb = (B + 63) / 64;
   GemmArgs d{};
   d.M = B; d.N = kH2; d.K = O; d.A = o->G3b; d.lda = kPO; d.B = o->pb + o->off[4]; d.ldb = kH2;
-  d.C = o->D2; d.ldc = kH2; d.Cb = o->D2b; d.Zp = o->Z2;
+  d.C = nullptr; d.ldc = kH2; d.Cb = o->D2b; d.Zp = o->Z2; d.colpart = o->cpart;
   launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
+  sum_partials(st, o->cpart, rb, kH2, kH2, o->g + o->off[3]);
   weight_grad<true, false>(o, st, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->off[2], kH1);
-  col_sums(o, st, o->D2, B, kH2, kH2, o->g + o->off[3]);
-  // dZ1 = (dZ2 W2) * tanh'(Z1)
+  // dZ1 = (dZ2 W2) * tanh'(Z1), with the column sums of dZ1 (hidden-1 bias)
   d.N = kH1; d.K = kH2; d.A = o->D2b; d.lda = kH2; d.B = o->pb + o->off[2]; d.ldb = kH1;
-  d.C = o->D1; d.ldc = kH1; d.Cb = o->D1b; d.Zp = o->Z1;
+  d.C = nullptr; d.ldc = kH1; d.Cb = o->D1b; d.Zp = o->Z1; d.colpart = o->cpart;
   launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
+  sum_partials(st, o->cpart, rb, kH1, kH1, o->g + o->off[1]);
   weight_grad<true, false>(o, st, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->off[0], W);
-  col_sums(o, st, o->D1, B, kH1, kH1, o->g + o->off[1]);
   k_ppo_gnorm<<<1, 1024, 0, st>>>(o->g, o->P, o->off[6], J, cfg->entropy_coef, o->scal, stats, w_stats);
   return hipGetLastError();
 }
@@ -447,9 +460,8 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   }
   o->P = acc;
   const size_t R = (size_t)max_samples, P = (size_t)o->P;
-  // split-K partials: at most 256 tiles x splits x 64 x 64, and the column
-  // sums' chunks
-  o->ws_floats = (size_t)256 * 64 * 64 + ((R + kColChunk - 1) / kColChunk) * kH1;
+  // split-K partials: at most 256 tiles x splits x 64 x 64
+  o->ws_floats = (size_t)256 * 64 * 64;
   hipError_t e = palloc(o, &o->p, P);
   if (e == hipSuccess) e = palloc(o, &o->pb, P);
   if (e == hipSuccess) e = palloc(o, &o->g, P);
@@ -463,14 +475,11 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   if (e == hipSuccess) e = palloc(o, &o->Z2, R * kH2);
   if (e == hipSuccess) e = palloc(o, &o->H2, R * kH2);
   if (e == hipSuccess) e = palloc(o, &o->Z3, R * kPO);
-  if (e == hipSuccess) e = palloc(o, &o->G3, R * kPO);
   if (e == hipSuccess) e = palloc(o, &o->G3b, R * kPO);
-  if (e == hipSuccess) e = palloc(o, &o->DL, R * kPO);
-  if (e == hipSuccess) e = palloc(o, &o->D2, R * kH2);
   if (e == hipSuccess) e = palloc(o, &o->D2b, R * kH2);
-  if (e == hipSuccess) e = palloc(o, &o->D1, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->D1b, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->ws, o->ws_floats);
+  if (e == hipSuccess) e = palloc(o, &o->cpart, ((R + 63) / 64) * (size_t)kH1);
   if (e == hipSuccess && !c->w_bf16) e = hipMalloc((void**)&c->w_bf16, (size_t)kWFrags * 16);
   if (e == hipSuccess && !c->bias) e = hipMalloc((void**)&c->bias, (size_t)kBiasFloats * sizeof(float));
   if (e == hipSuccess && !c->log_std) e = hipMalloc((void**)&c->log_std, (size_t)c->J * sizeof(float));
