@@ -1,7 +1,11 @@
 /* surgym.h -- C interface of the MI355X batched serial-chain simulator.
  *
  * One context holds N independent environments, each a fixed-base serial
- * chain of revolute joints driven by joint-space PD targets, on one GPU.
+ * chain of revolute and prismatic joints driven by joint-space PD targets
+ * (or C = 2 or 4 such chains sharing an episode), on one GPU. Beside the
+ * step and the fused policy rollout it offers the learned dynamics
+ * surrogate, step schedules for uneven joint counts, the PPO update of the
+ * rollout policy and the adjoint of open-loop rollouts.
  * Every call enqueues work on the context's HIP stream and returns without
  * synchronizing; argument errors are reported synchronously.
  *

@@ -1,0 +1,99 @@
+"""Edge cases through the HIP library: every DOF bucket from 1 to the
+maximum of 16 joints (uniform and per-env joint counts, FP32 and FP64)
+against the FP64 oracle; invalid sizes rejected at create; the control step
+captured in a HIP graph and replayed, each replay checked against the same
+step run eagerly."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from test_gpu_step import _run_handoff, dev, host, rel_qdd_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _chain_workload(N, n_dof, dtype, seed=2024, max_dof=None):
+    r = synth.make_chain(N, n_dof, seed, dt=1 / 120, substeps=2, max_dof=max_dof, q0_frac=0.2)
+    tgt = (synth.WORK_CENTRE[None, :] + synth.stream(seed, "tg").uniform(-0.25, 0.25, (N, 3))).T.copy()
+    t = synth.Task(task=synth.TASK_REACH, target=tgt, waypoints=None, dwell=1, ep_len=64,
+                   progress0=synth.stream(seed, "p0").integers(0, 64, N).astype(np.int32))
+    return synth.Workload("chain", synth._round_robot(r, dtype), synth._round_task(t, dtype), None, dtype, seed)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("J,mixed", [(1, False), (2, False), (3, False), (4, False), (5, True), (8, False),
+                                     (12, True), (16, False)])
+def test_every_dof_bucket(sg, J, mixed, dtype):
+    import torch
+    N = 70
+    n_dof = np.array([(k % J) + 1 for k in range(N)]) if mixed else J
+    w = _chain_workload(N, n_dof, dtype, max_dof=J)
+    td = torch.float64 if dtype == np.float64 else torch.float32
+    sim = sg.Sim(w.robot, w.task, dtype=dtype)
+    o = oracle.Oracle(w.robot, w.task)
+    q, qd = synth.random_states(21, w.robot, dtype=dtype)
+    tau = synth._as_dtype(np.random.default_rng(J).normal(0, 5, q.shape), dtype)
+    tau[np.arange(J)[:, None] >= w.robot.n_dof[None, :]] = 0
+    g = host(sim.forward_dynamics(dev(q, torch, td), dev(qd, torch, td), dev(tau, torch, td), sg.SG_ARM_DRIVE))
+    tol = 1e-10 if dtype == np.float64 else 1e-4
+    assert rel_qdd_err(g, o.aba(q, qd, tau, o.drive_armature())) <= tol
+    tip = host(sim.tip_position(dev(q, torch, td)))
+    assert np.abs(tip - o.fk(q)).max() <= (1e-13 if dtype == np.float64 else 3e-6)
+    _run_handoff(sg, w, 6, 7000 + J, qtol=1e-11 if dtype == np.float64 else 2e-5,
+                 tol_qdd=1e-10 if dtype == np.float64 else 1e-4)
+
+
+def test_create_rejects_invalid_sizes(sg):
+    w = _chain_workload(8, 3, np.float32)
+    bad = synth._round_robot(synth.make_chain(8, 17, 1, dt=0.01, substeps=1), np.float32)
+    with pytest.raises(sg.SgError):
+        sg.Sim(bad, w.task)   # more than 16 joints
+    r = synth.make_chain(8, 3, 1, dt=0.01, substeps=1)
+    r.n_dof[2] = 4            # above max_dof
+    with pytest.raises(sg.SgError):
+        sg.Sim(synth._round_robot(r, np.float32), w.task)
+    r = synth.make_chain(8, 3, 1, dt=0.01, substeps=1)
+    r.mass[1, 3] = 0.0        # massless link
+    with pytest.raises(sg.SgError):
+        sg.Sim(synth._round_robot(r, np.float32), w.task)
+    r = synth.make_chain(8, 3, 1, dt=0.0, substeps=1)
+    with pytest.raises(sg.SgError):
+        sg.Sim(synth._round_robot(r, np.float32), w.task)
+
+
+def test_step_replayed_from_a_captured_graph(sg):
+    import torch
+    N = 512
+    w = synth.path_rollout(N)
+    sim_g = sg.Sim(w.robot, w.task)
+    sim_e = sg.Sim(w.robot, w.task)
+    a = torch.from_numpy(synth.random_actions(55, N, 7, np.float32).astype(np.float32)).cuda()
+    obs = torch.empty(24, N, device="cuda")
+    rew = torch.empty(N, device="cuda")
+    done = torch.empty(N, dtype=torch.uint8, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        # warm-up on the capture stream, then rewind both contexts
+        sim_g.step(a, obs, rew, done)
+    torch.cuda.current_stream().wait_stream(side)
+    sim_g.reset()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        sim_g.step(a, obs, rew, done)
+    # capture records the launch without running it
+    sim_g.reset()
+    torch.cuda.synchronize()
+    for k in range(4):
+        graph.replay()
+        oe, re, de = sim_e.step(a)
+        torch.cuda.synchronize()
+        assert torch.equal(obs, oe) and torch.equal(rew, re) and torch.equal(done, de), k
+        qg, qdg, pg, _ = sim_g.get_state()
+        qe, qde, pe, _ = sim_e.get_state()
+        assert torch.equal(qg, qe) and torch.equal(qdg, qde) and torch.equal(pg, pe), k
+        # eager work of the program between replays
+        assert torch.equal(sim_g.observe(), sim_e.observe())
+        torch.cuda.synchronize()
