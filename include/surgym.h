@@ -403,6 +403,18 @@ sg_status sg_ppo_grad(sg_ppo* ppo, const sg_rollout_bufs* bufs, int32_t T, const
 sg_status sg_ppo_update(sg_ppo* ppo, const sg_rollout_bufs* bufs, int32_t T, const sg_ppo_config* cfg,
                         const int32_t* perm, float* stats);
 
+/* ---- Measured device peaks ----
+ * Times microkernels on the current device and stream 0 and returns (HOST
+ * doubles) the FP32 vector FMA rate without packed-FP32 instructions over
+ * the whole chip (TFLOP/s, 16 independent FMA chains per lane, two waves
+ * per SIMD) and for one wave alone on its SIMD (GFLOP/s per wave, the same
+ * FMA stream), the BF16 16x16x32 matrix-core rate (TFLOP/s) and a 1 GiB
+ * device-to-device copy rate (read + write bytes, GB/s). Allocates 2 GiB
+ * for the duration of the call; synchronizes. For context beside the
+ * datasheet peaks a roofline fraction is quoted against. */
+sg_status sg_measure_peaks(double* fp32_fma_tflops, double* fp32_fma_wave_gflops, double* bf16_mfma_tflops,
+                           double* copy_gbps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -601,3 +601,19 @@ def _set_goal_state(self, gs):
 
 Sim.get_goal_state = _get_goal_state
 Sim.set_goal_state = _set_goal_state
+
+
+# ---- measured device peaks -----------------------------------------------------------
+lib.sg_measure_peaks.argtypes = [C.POINTER(C.c_double)] * 4
+
+
+def measure_peaks():
+    """Measured rates of the current device: FP32 FMA without packed FP32
+    (whole chip, TFLOP/s; one wave alone on its SIMD, GFLOP/s per wave),
+    BF16 MFMA (TFLOP/s) and a device copy (GB/s)."""
+    f, fw, m, c = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    st = lib.sg_measure_peaks(C.byref(f), C.byref(fw), C.byref(m), C.byref(c))
+    if st != 0:
+        raise SgError(st, lib.sg_last_error(None).decode())
+    return {"fp32_fma_tflops": f.value, "fp32_fma_wave_gflops": fw.value, "bf16_mfma_tflops": m.value,
+            "copy_gbps": c.value}

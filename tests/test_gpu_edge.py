@@ -97,3 +97,14 @@ def test_step_replayed_from_a_captured_graph(sg):
         # eager work of the program between replays
         assert torch.equal(sim_g.observe(), sim_e.observe())
         torch.cuda.synchronize()
+
+
+def test_measured_peaks_are_sane(sg):
+    pk = sg.measure_peaks()
+    assert all(np.isfinite(v) and v > 0 for v in pk.values())
+    # below the datasheet figures (FP32 vector 157.3 TFLOP/s, BF16 dense
+    # 2.5 PFLOP/s, HBM 8 TB/s) and a lone wave slower than a full chip
+    assert pk["fp32_fma_tflops"] < 157.3 * 1.05
+    assert pk["bf16_mfma_tflops"] < 2500 * 1.05
+    assert pk["copy_gbps"] < 8000 * 1.05
+    assert pk["fp32_fma_wave_gflops"] * 1e-3 < pk["fp32_fma_tflops"]
