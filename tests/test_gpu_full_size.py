@@ -1,0 +1,106 @@
+"""Parity at the sizes and launch configurations bench.py times.
+
+* The fused path-following rollout at 4096 envs (two consecutive T = 32
+  rollouts, as the timed loop runs them) and at 16384 envs: the oracle
+  replays every env's control step from the stored observations (which hold
+  q and qd exactly) and recomputes GAE for every env; the policy outputs
+  (action means plus the Philox noise, values, log-densities) are checked on
+  512 envs spread over all waves: the first and last 64 and a seeded draw.
+* The uneven 4/6/7/9-DOF batch at 16384 envs under every step schedule the
+  autotuner times, each step checked for every env against the oracle's
+  step from the state the GPU handed over.
+
+Tolerances are those of the smaller parity tests: see test_gpu_rollout.py
+(policy outputs, log-density, GAE, replayed step) and test_gpu_step.py
+(hand-off step).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from test_gpu_rollout import check_policy_outputs, host
+
+pytestmark = pytest.mark.gpu
+
+THREADS = 16
+
+
+def _sample(N, seed=5, k=384):
+    rng = np.random.default_rng(seed)
+    mid = rng.choice(np.arange(64, N - 64), size=min(k, max(N - 128, 0)), replace=False)
+    return np.unique(np.concatenate([np.arange(min(64, N)), np.arange(max(N - 64, 0), N), mid]))
+
+
+def _replay_full(sg, w, T, n_rollouts):
+    sim = sg.from_workload(w)
+    o = oracle.Oracle(w.robot, w.task, w.policy)
+    N, J = w.robot.n_env, w.robot.max_dof
+    idx = _sample(N)
+    sigma = np.exp(w.policy.log_std)
+    bufs = sim.rollout_buffers(T)
+    prog = w.task.progress0.astype(np.int32).copy()
+    step0 = 0
+    for r in range(n_rollouts):
+        sim.rollout(T, bufs)
+        obs, act, logp = host(bufs["obs"]), host(bufs["act"]), host(bufs["logp"])
+        rew, done, val = host(bufs["rew"]), bufs["done"].cpu().numpy(), host(bufs["val"])
+        adv, ret = host(bufs["adv"]), host(bufs["ret"])
+        for t in range(T + 1):
+            mv = o.mlp(obs[t][:, idx], emulate=True)
+            check_policy_outputs(val[t][idx][None], mv[J][None])
+            if t == T:
+                break
+            eps = oracle.noise(w.seed, step0 + t, J, N)
+            check_policy_outputs(act[t][:, idx], mv[:J] + sigma[:, None] * eps[:, idx])
+            lp = (-0.5 * eps ** 2 - w.policy.log_std[:, None] - 0.5 * np.log(2 * np.pi)).sum(0)
+            np.testing.assert_allclose(logp[t], lp, rtol=1e-5, atol=1e-4)
+            q, qd = obs[t][:J], obs[t][J:2 * J]
+            qn, qdn, prn, rw, dn, ob = o.step(act[t], q, qd, prog, threads=THREADS)
+            assert np.array_equal(done[t], dn), (r, t)
+            assert np.abs(rew[t] - rw).max() <= 2e-4, (r, t, np.abs(rew[t] - rw).max())
+            scale = np.maximum(1.0, np.abs(ob))
+            assert (np.abs(obs[t + 1] - ob) / scale).max() <= 2e-3, (r, t)
+            prog = prn
+        ra, rr = oracle.gae(rew, val, done, 0.99, 0.95)
+        np.testing.assert_allclose(adv, ra, rtol=1e-5, atol=1e-4)
+        np.testing.assert_allclose(ret, rr, rtol=1e-5, atol=1e-4)
+        step0 += T
+    q, qd, pr, rs = sim.get_state()
+    assert rs == step0
+    np.testing.assert_array_equal(host(q), obs[T][:J])
+    np.testing.assert_array_equal(pr.cpu().numpy(), prog)
+    sim.close()
+
+
+def test_path_rollout_4096_two_rollouts(sg):
+    _replay_full(sg, synth.path_rollout(4096), 32, 2)
+
+
+def test_path_rollout_16384(sg):
+    _replay_full(sg, synth.path_rollout(16384), 32, 1)
+
+
+@pytest.mark.parametrize("schedule", ["padded", "sorted", "per_class", "persistent"])
+def test_mixed_dof_16384_every_schedule(sg, schedule):
+    import torch
+    w = synth.mixed_dof(16384)
+    sim = sg.Sim(w.robot, w.task)
+    sim.set_schedule(sg.SCHEDULE_NAMES.index(schedule))
+    o = oracle.Oracle(w.robot, w.task)
+    J, N = w.robot.max_dof, w.robot.n_env
+    qtol = 2e-5
+    for s in range(3):
+        q0, qd0, pr0, _ = sim.get_state()
+        a = synth.random_actions(900 + s, N, J, dtype=np.float32).astype(np.float32)
+        obs, rew, done = sim.step(torch.from_numpy(a).cuda())
+        q1, qd1, pr1, _ = sim.get_state()
+        qn, qdn, prn, rw, dn, ob = o.step(a, host(q0), host(qd0), host(pr0).astype(np.int32), threads=THREADS)
+        assert np.array_equal(host(done).astype(np.uint8), dn), s
+        assert np.array_equal(host(pr1).astype(np.int32), prn), s
+        dq = np.abs(host(q1) - qn) / (1 + np.abs(qn))
+        assert dq.max() <= qtol, (s, dq.max())
+        assert np.abs(host(qd1) - qdn).max() <= qtol * 100 * max(1.0, np.abs(qdn).max()), s
+        assert np.abs(host(rew) - rw).max() <= qtol * 10, s
+        assert np.abs(host(obs) - ob).max() <= qtol * 100 * max(1.0, np.abs(ob).max()), s
+    sim.close()
