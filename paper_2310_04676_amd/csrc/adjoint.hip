@@ -61,7 +61,9 @@ __global__ void __launch_bounds__(64) k_adjoint(AdjArgs A) {
     half[j] = j < n ? 0.5f * (p.hi - p.lo) : 0.f;
   }
   // one control step; optionally records substep states into the tape
-  auto step = [&](int t, float* tp, float* te, int* ti) {
+  // (inlined: as a called function its captured arrays would live in
+  // scratch memory)
+  auto step = [&](int t, float* tp, float* te, int* ti) __attribute__((always_inline)) {
     float a[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) a[j] = j < n ? A.act[((size_t)t * E.J + j) * N + e] : 0.f;

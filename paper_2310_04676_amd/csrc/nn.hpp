@@ -84,66 +84,59 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   // takes 8 consecutive k of row t / 4. Contiguous-m/n operands: thread t
   // takes 8 consecutive rows at k = t / 8. With 16-byte aligned rows each is
   // one vector load; otherwise (or at a ragged edge) element by element.
+  // The next k-slice is fetched into registers while the current one is
+  // multiplied (one slice in flight).
   const int lr = tid >> 2, lk = (tid & 3) * 8;
   const int tk = tid >> 3, tm = (tid & 7) * 8;
   const bool avec = (((uintptr_t)g.A) & 15) == 0 && (g.lda & 7) == 0;
   const bool bvec = (((uintptr_t)g.B) & 15) == 0 && (g.ldb & 7) == 0;
+  auto fetch = [&](const uint16_t* X, int ld, bool vec, int rows, int r0, bool trans, int k0) -> uint4 {
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (!trans) {
+      const int m = r0 + lr, k = k0 + lk;
+      if (m < rows && k < kend) {
+        if (vec && k + 8 <= kend) {
+          v = *reinterpret_cast<const uint4*>(X + (size_t)m * ld + k);
+        } else {
+          uint16_t t[8];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) t[s] = (k + s < kend) ? X[(size_t)m * ld + k + s] : 0;
+          v = *reinterpret_cast<uint4*>(t);
+        }
+      }
+    } else {
+      const int k = k0 + tk, m = r0 + tm;
+      if (k < kend && vec && m + 8 <= rows) {
+        v = *reinterpret_cast<const uint4*>(X + (size_t)k * ld + m);
+      } else {
+        uint16_t t[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) t[s] = (k < kend && m + s < rows) ? X[(size_t)k * ld + m + s] : 0;
+        v = *reinterpret_cast<uint4*>(t);
+      }
+    }
+    return v;
+  };
+  auto stash = [&](uint16_t (*S)[40], bool trans, const uint4& v) {
+    if (!trans) {
+      *reinterpret_cast<uint4*>(&S[lr][lk]) = v;
+    } else {
+      uint16_t t[8];
+      *reinterpret_cast<uint4*>(t) = v;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) S[tm + s][tk] = t[s];
+    }
+  };
+  uint4 ra = fetch(g.A, g.lda, avec, g.M, m0, AT, kbeg);
+  uint4 rb = fetch(g.B, g.ldb, bvec, g.N, n0, !BT, kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += 32) {
-    if (!AT) {
-      const int m = m0 + lr, k = k0 + lk;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (m < g.M && k < kend) {
-        if (avec && k + 8 <= kend) {
-          v = *reinterpret_cast<const uint4*>(g.A + (size_t)m * g.lda + k);
-        } else {
-          uint16_t t[8];
-#pragma unroll
-          for (int s = 0; s < 8; ++s) t[s] = (k + s < kend) ? g.A[(size_t)m * g.lda + k + s] : 0;
-          v = *reinterpret_cast<uint4*>(t);
-        }
-      }
-      *reinterpret_cast<uint4*>(&As[lr][lk]) = v;
-    } else {
-      const int k = k0 + tk, m = m0 + tm;
-      uint16_t t[8];
-      if (k < kend && avec && m + 8 <= g.M) {
-        const uint4 v = *reinterpret_cast<const uint4*>(g.A + (size_t)k * g.lda + m);
-        *reinterpret_cast<uint4*>(t) = v;
-      } else {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) t[s] = (k < kend && m + s < g.M) ? g.A[(size_t)k * g.lda + m + s] : 0;
-      }
-#pragma unroll
-      for (int s = 0; s < 8; ++s) As[tm + s][tk] = t[s];
-    }
-    if (BT) {
-      const int n = n0 + lr, k = k0 + lk;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (n < g.N && k < kend) {
-        if (bvec && k + 8 <= kend) {
-          v = *reinterpret_cast<const uint4*>(g.B + (size_t)n * g.ldb + k);
-        } else {
-          uint16_t t[8];
-#pragma unroll
-          for (int s = 0; s < 8; ++s) t[s] = (k + s < kend) ? g.B[(size_t)n * g.ldb + k + s] : 0;
-          v = *reinterpret_cast<uint4*>(t);
-        }
-      }
-      *reinterpret_cast<uint4*>(&Bs[lr][lk]) = v;
-    } else {
-      const int k = k0 + tk, n = n0 + tm;
-      uint16_t t[8];
-      if (k < kend && bvec && n + 8 <= g.N) {
-        const uint4 v = *reinterpret_cast<const uint4*>(g.B + (size_t)k * g.ldb + n);
-        *reinterpret_cast<uint4*>(t) = v;
-      } else {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) t[s] = (k < kend && n + s < g.N) ? g.B[(size_t)k * g.ldb + n + s] : 0;
-      }
-#pragma unroll
-      for (int s = 0; s < 8; ++s) Bs[tm + s][tk] = t[s];
-    }
+    stash(As, AT, ra);
+    stash(Bs, !BT, rb);
     __syncthreads();
+    if (k0 + 32 < kend) {
+      ra = fetch(g.A, g.lda, avec, g.M, m0, AT, k0 + 32);
+      rb = fetch(g.B, g.ldb, bvec, g.N, n0, !BT, k0 + 32);
+    }
     bf16x8 af[2], bfr[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {

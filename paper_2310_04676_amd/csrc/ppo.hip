@@ -9,13 +9,14 @@
 //                  pre-activations stay in HBM for the backward pass
 //   k_ppo_loss     ratio, clipped objectives, dL/d(outputs) [B][8] (BF16
 //                  for the GEMMs) and per-block sums of the output-bias and
-//                  log_std gradients; loss statistics
+//                  log_std gradients and of the loss statistics
 //   backward       data gradients as GEMMs with the tanh' epilogue, which
 //                  also emits per-block column sums (the hidden biases'
 //                  gradients); weight gradients as split-K GEMMs (the batch
 //                  is the reduction axis); every partial is summed in a
 //                  fixed order -- deterministic
-//   k_ppo_gnorm    entropy term and the global gradient norm
+//   k_gnorm_part   entropy term and per-block sums of squares of the
+//                  gradient; k_ppo_finish: the global norm and statistics
 //   k_ppo_adam     norm clip + Adam on the FP32 master weights + BF16 copy
 // After an update k_ppo_pack rewrites the context's rollout weight image
 // (the MFMA fragment order of mlp.hpp), biases and log_std from the master
@@ -51,6 +52,8 @@ struct sg_ppo {
   float* ws = nullptr;       // split-K partials
   size_t ws_floats = 0;
   float* cpart = nullptr;    // per-block column sums [rows / 64 (or / 256)][256]
+  float* lpart = nullptr;    // k_ppo_loss block sums [rows / 256][kLossPart]
+  double* gpart = nullptr;   // k_gnorm_part block sums [kGnormBlocks]
   std::vector<void*> allocs;
 };
 
@@ -58,6 +61,11 @@ namespace sgk {
 
 constexpr int kPX = 32;   // padded input width
 constexpr int kPO = 8;    // padded output width (J + 1 <= 8)
+// k_ppo_loss block row: dL/d(outputs) sums (O columns) then dL/dlog_std
+// sums (J columns), zero to column 16, then the four weighted loss sums.
+constexpr int kLossPart = 20;
+constexpr int kGnormChunk = 1024;  // gradient entries per k_gnorm_part block
+constexpr int kGnormBlocks = 128;  // capacity of the partial-norm buffer
 
 struct PpoRows {
   const float* obs;   // [T+1][W][N]
@@ -126,8 +134,7 @@ struct PpoLossArgs {
   float inv_b;          // 1 / rows
   float w_stats;        // weight of this minibatch in the statistics
   uint16_t* G3b;        // [rows][8] BF16 dL/d(outputs)
-  float* part;          // [gridDim.x][16]: block sums of dL/d(outputs) (0..7) and dL/dlog_std (8..15)
-  float* stats;         // loss_pi, loss_v, entropy, approx_kl, clip_frac, |g|
+  float* part;          // [gridDim.x][kLossPart] block sums (see kLossPart)
 };
 
 // Per row: log pi(a) under the current outputs, ratio, clipped objectives,
@@ -180,69 +187,105 @@ __global__ void __launch_bounds__(256) k_ppo_loss(PpoLossArgs a) {
     for (int k = 0; k < kPO; ++k) a.G3b[(size_t)r * kPO + k] = bf16_bits(g[k]);
   }
   {
-    // block sums of the FP32 gradients, in a fixed order
-    __shared__ float red[4][2 * kPO];
+    // block sums of the FP32 gradients and of the weighted loss terms, in a
+    // fixed order (no atomics: the statistics are summed by k_ppo_finish)
+    const float w = a.w_stats * a.inv_b;
+    float v4[4] = {lpi * w, lv * w, kl * w, cf * w};
+    __shared__ float red[4][2 * kPO + 4];
 #pragma unroll
     for (int k = 0; k < kPO; ++k)
       for (int o = 32; o > 0; o >>= 1) {
         g[k] += __shfl_xor(g[k], o, 64);
         dl[k] += __shfl_xor(dl[k], o, 64);
       }
-    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      for (int o = 32; o > 0; o >>= 1) v4[k] += __shfl_xor(v4[k], o, 64);
+    if ((threadIdx.x & 63) == 0) {
 #pragma unroll
       for (int k = 0; k < kPO; ++k) {
         red[threadIdx.x >> 6][k] = g[k];
         red[threadIdx.x >> 6][kPO + k] = dl[k];
       }
-    __syncthreads();
-    if (threadIdx.x < 2 * kPO)
-      a.part[(size_t)blockIdx.x * 2 * kPO + threadIdx.x] =
-          (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
-  }
-  if (a.stats) {
-    const float w = a.w_stats * a.inv_b;
-    float v4[4] = {lpi * w, lv * w, kl * w, cf * w};
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      for (int o = 32; o > 0; o >>= 1) v4[k] += __shfl_down(v4[k], o, 64);
-    if ((threadIdx.x & 63) == 0) {
-      atomicAdd(&a.stats[0], v4[0]);
-      atomicAdd(&a.stats[1], v4[1]);
-      atomicAdd(&a.stats[3], v4[2]);
-      atomicAdd(&a.stats[4], v4[3]);
+      for (int k = 0; k < 4; ++k) red[threadIdx.x >> 6][2 * kPO + k] = v4[k];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      float H = 0.f;
-      for (int j = 0; j < R.J; ++j) H += a.ls[j] + 0.5f + 0.91893853320467274f;
-      atomicAdd(&a.stats[2], H * a.w_stats);
+    __syncthreads();
+    const int c = threadIdx.x, O = R.J + 1;
+    if (c < kLossPart) {
+      // column c of the row: output c, log_std c - O, zero, or statistic
+      const int src = c < O ? c : (c < O + R.J ? kPO + c - O : (c >= 16 ? 2 * kPO + c - 16 : -1));
+      a.part[(size_t)blockIdx.x * kLossPart + c] =
+          src < 0 ? 0.f : (red[0][src] + red[1][src]) + (red[2][src] + red[3][src]);
     }
   }
 }
 
-// Entropy bonus on the log_std gradient, then |g| (one block, double
-// accumulation) into scal[2]; optionally into stats[5] with weight w.
-__global__ void __launch_bounds__(1024) k_ppo_gnorm(float* __restrict__ g, int P, int ls0, int J, float c_e,
-                                                    float* __restrict__ scal, float* __restrict__ stats, float w) {
-  __shared__ double red[1024];
+// Entropy bonus on the log_std gradient, then per-block sums of squares
+// (double) of kGnormChunk gradient entries into gpart[blockIdx.x].
+__global__ void __launch_bounds__(256) k_gnorm_part(float* __restrict__ g, int P, int ls0, int J, float c_e,
+                                                    double* __restrict__ gpart) {
+  __shared__ double red[256];
   double s = 0;
-  for (int i = threadIdx.x; i < P; i += 1024) {
-    float gi = g[i];
-    if (i >= ls0 && i < ls0 + J) {
-      gi -= c_e;
-      g[i] = gi;
+#pragma unroll
+  for (int k = 0; k < kGnormChunk / 256; ++k) {
+    const int i = blockIdx.x * kGnormChunk + k * 256 + threadIdx.x;
+    if (i < P) {
+      float gi = g[i];
+      if (i >= ls0 && i < ls0 + J) {
+        gi -= c_e;
+        g[i] = gi;
+      }
+      s += (double)gi * gi;
     }
-    s += (double)gi * gi;
   }
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int k = 512; k > 0; k >>= 1) {
+  for (int k = 128; k > 0; k >>= 1) {
     if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const float n = (float)sqrt(red[0]);
+  if (threadIdx.x == 0) gpart[blockIdx.x] = red[0];
+}
+
+// |g| from the partial sums into scal[2]; with stats, the minibatch's loss
+// statistics (block sums of k_ppo_loss), entropy and |g| added with weight
+// w. One block; every sum in a fixed order.
+__global__ void __launch_bounds__(256) k_ppo_finish(const double* __restrict__ gpart, int nb,
+                                                    const float* __restrict__ lpart, int lb,
+                                                    const float* __restrict__ ls, int J, float* __restrict__ scal,
+                                                    float* __restrict__ stats, float w) {
+  __shared__ double red[4][256];
+  const int t = threadIdx.x;
+  double v[4] = {0, 0, 0, 0};
+  if (stats)
+    for (int b = t; b < lb; b += 256)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] += lpart[(size_t)b * kLossPart + 16 + k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k][t] = v[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k][t] += red[k][t + s];
+    __syncthreads();
+  }
+  if (t == 0) {
+    double q = 0;
+    for (int b = 0; b < nb; ++b) q += gpart[b];
+    const float n = (float)sqrt(q);
     scal[2] = n;
-    if (stats) stats[5] += n * w;
+    if (stats) {
+      float H = 0.f;
+      for (int j = 0; j < J; ++j) H += ls[j] + 0.5f + 0.91893853320467274f;
+      stats[0] += (float)red[0][0];
+      stats[1] += (float)red[1][0];
+      stats[2] += H * w;
+      stats[3] += (float)red[2][0];
+      stats[4] += (float)red[3][0];
+      stats[5] += n * w;
+    }
   }
 }
 
@@ -342,7 +385,7 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
   hipStream_t st = c->stream;
   const int B = rows.rows, W = o->W, O = o->O, J = o->J;
   const int gb = (B + 255) / 256;
-  k_zero<<<(o->P + 255) / 256, 256, 0, st>>>(o->g, o->P);
+  // every entry of o->g is written below (weight and bias sums), so no clear
   k_ppo_gather<<<gb, 256, 0, st>>>(rows, o->X);
   GemmArgs f{};
   // layer 1: Z1 = X W1^T + b1, H1 = tanh(Z1)
@@ -359,12 +402,12 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
   launch_gemm<EPI_FWD_OUT, false, true, ACT_TANH>(st, f);
   PpoLossArgs la;
   la.rows = rows; la.Z3 = o->Z3; la.ls = o->p + o->off[6]; la.clip = cfg->clip; la.c_v = cfg->value_coef;
-  la.inv_b = 1.f / (float)B; la.w_stats = w_stats; la.G3b = o->G3b; la.part = o->cpart; la.stats = stats;
+  la.inv_b = 1.f / (float)B; la.w_stats = w_stats; la.G3b = o->G3b; la.part = o->lpart;
   k_ppo_loss<<<gb, 256, 0, st>>>(la);
   // output layer gradients
   weight_grad<true, false>(o, st, O, kH2, B, o->G3b, kPO, o->H2, kH2, o->g + o->off[4], kH2);
-  sum_partials(st, o->cpart, gb, O, 2 * kPO, o->g + o->off[5]);
-  sum_partials(st, o->cpart + kPO, gb, J, 2 * kPO, o->g + o->off[6]);
+  // output biases and log_std are adjacent in the flat vector (off[6] = off[5] + O)
+  sum_partials(st, o->lpart, gb, O + J, kLossPart, o->g + o->off[5]);
   // dZ2 = (G3 W3) * tanh'(Z2), with the column sums of dZ2 (hidden-2 bias)
   const int rb = (B + 63) / 64;
   GemmArgs d{};
@@ -379,7 +422,9 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
   launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
   sum_partials(st, o->cpart, rb, kH1, kH1, o->g + o->off[1]);
   weight_grad<true, false>(o, st, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->off[0], W);
-  k_ppo_gnorm<<<1, 1024, 0, st>>>(o->g, o->P, o->off[6], J, cfg->entropy_coef, o->scal, stats, w_stats);
+  const int nb = (o->P + kGnormChunk - 1) / kGnormChunk;
+  k_gnorm_part<<<nb, 256, 0, st>>>(o->g, o->P, o->off[6], J, cfg->entropy_coef, o->gpart);
+  k_ppo_finish<<<1, 256, 0, st>>>(o->gpart, nb, o->lpart, gb, o->p + o->off[6], J, o->scal, stats, w_stats);
   return hipGetLastError();
 }
 
@@ -480,6 +525,9 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   if (e == hipSuccess) e = palloc(o, &o->D1b, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->ws, o->ws_floats);
   if (e == hipSuccess) e = palloc(o, &o->cpart, ((R + 63) / 64) * (size_t)kH1);
+  if (e == hipSuccess) e = palloc(o, &o->lpart, ((R + 255) / 256) * (size_t)kLossPart);
+  if (e == hipSuccess) e = palloc(o, &o->gpart, (size_t)kGnormBlocks);
+  if (e == hipSuccess && (o->P + kGnormChunk - 1) / kGnormChunk > kGnormBlocks) e = hipErrorInvalidValue;
   if (e == hipSuccess && !c->w_bf16) e = hipMalloc((void**)&c->w_bf16, (size_t)kWFrags * 16);
   if (e == hipSuccess && !c->bias) e = hipMalloc((void**)&c->bias, (size_t)kBiasFloats * sizeof(float));
   if (e == hipSuccess && !c->log_std) e = hipMalloc((void**)&c->log_std, (size_t)c->J * sizeof(float));
