@@ -36,6 +36,15 @@
  * rollout on an FP64 context). SG_E_HIP: a HIP runtime error, including an
  * asynchronous fault surfaced at the next call that synchronizes.
  * A context is used by one host thread at a time.
+ *
+ * HIP graph capture: the device work of sg_step, sg_observe, sg_rollout,
+ * sg_gae, the dynamics calls, the surrogate calls and sg_ppo_update is
+ * kernels only (no memset or memcpy nodes), so a call can be captured on
+ * the context's stream. A replay repeats the call exactly as captured,
+ * including its host-side counters: the noise counter (rng_step; the
+ * rollout's action noise and the tracking task's goal draws) and the Adam
+ * step count of sg_ppo_update do not advance across replays, and
+ * sg_get_state reports the count of eager calls only.
  */
 #ifndef SURGYM_H
 #define SURGYM_H
