@@ -42,7 +42,7 @@ template <int ACT> __device__ __forceinline__ float act_grad(float z) {
 //                   64 rows as well (bias gradients without a second pass)
 //   EPI_PARTIAL     block z of the grid sums K in [z kchunk, (z+1) kchunk)
 //                   and writes its partial to C + z M ldc (split-K; reduce
-//                   with k_sum_splits)
+//                   with k_sum_two)
 enum { EPI_FWD_HIDDEN = 0, EPI_FWD_OUT = 1, EPI_PLAIN = 2, EPI_BWD_DX = 3, EPI_PARTIAL = 4 };
 
 struct GemmArgs {
@@ -193,24 +193,36 @@ static inline void launch_gemm(hipStream_t s, const GemmArgs& a, int splits = 1)
   k_gemm<EPI, AT, BT, ACT><<<grid, 256, 0, s>>>(a);
 }
 
-// out[i * ldo + j] = sum_z part[z * stride + i N + j] over `splits` slabs
-// (stride 0: M N); 16 outputs per block, 16 thread groups each summing every
-// 16th slab, combined in a fixed order: deterministic.
-static __global__ void __launch_bounds__(256) k_sum_splits(const float* __restrict__ part, int splits, int M, int N,
-                                                           float* __restrict__ out, int ldo, int stride = 0) {
+// Split sums: out[i * ldo + j] = sum_z part[z * stride + i N + j] over
+// `splits` slabs (stride 0: M N); 16 outputs per block, 16 thread groups
+// each summing every 16th slab, combined in a fixed order: deterministic.
+// Two independent jobs share one launch: blocks [0, blocks_a) reduce job
+// a, the rest job b.
+struct SumJob {
+  const float* part;
+  int splits, M, N;
+  float* out;
+  int ldo, stride;
+};
+static inline int sum_job_blocks(const SumJob& j) { return (j.M * j.N + 15) / 16; }
+static __global__ void __launch_bounds__(256) k_sum_two(SumJob a, int blocks_a, SumJob b) {
   __shared__ float red[16][16];
-  const int o = blockIdx.x * 16 + (threadIdx.x & 15), grp = threadIdx.x >> 4;
-  const size_t st = stride > 0 ? (size_t)stride : (size_t)M * N;
+  const bool first = (int)blockIdx.x < blocks_a;
+  const SumJob& j = first ? a : b;
+  const int blk = first ? blockIdx.x : blockIdx.x - blocks_a;
+  const int o = blk * 16 + (threadIdx.x & 15), grp = threadIdx.x >> 4;
+  const int MN = j.M * j.N;
+  const size_t st = j.stride > 0 ? (size_t)j.stride : (size_t)MN;
   float s = 0.f;
-  if (o < M * N)
-    for (int z = grp; z < splits; z += 16) s += part[(size_t)z * st + o];
+  if (o < MN)
+    for (int z = grp; z < j.splits; z += 16) s += j.part[(size_t)z * st + o];
   red[grp][threadIdx.x & 15] = s;
   __syncthreads();
-  if (grp == 0 && o < M * N) {
+  if (grp == 0 && o < MN) {
     float t = 0.f;
 #pragma unroll
     for (int k = 0; k < 16; ++k) t += red[k][threadIdx.x];
-    out[(size_t)(o / N) * ldo + o % N] = t;
+    j.out[(size_t)(o / j.N) * j.ldo + o % j.N] = t;
   }
 }
 

@@ -3,8 +3,10 @@
 // objective: the clipped surrogate of Schulman et al., 2017, with a clipped
 // value loss and an entropy bonus).
 //
+// Once per call: advantage mean and standard deviation, the normalised
+// advantages, and the observations as sample-major BF16 rows (k_ppo_xall).
 // One minibatch of B samples (rows) taken from the rollout buffers:
-//   k_ppo_gather   obs rows -> BF16 X [B][32]
+//   k_ppo_gather   the minibatch's rows -> X [B][32]
 //   forward        three BF16 MFMA GEMMs (nn.hpp), tanh units; the
 //                  pre-activations stay in HBM for the backward pass
 //   k_ppo_loss     ratio, clipped objectives, dL/d(outputs) [B][8] (BF16
@@ -14,7 +16,8 @@
 //                  also emits per-block column sums (the hidden biases'
 //                  gradients); weight gradients as split-K GEMMs (the batch
 //                  is the reduction axis); every partial is summed in a
-//                  fixed order -- deterministic
+//                  fixed order -- deterministic; each split sum shares its
+//                  launch with a bias gradient's sum (k_sum_two)
 //   k_gnorm_part   entropy term and per-block sums of squares of the
 //                  gradient; k_ppo_finish: the global norm and statistics
 //   k_ppo_adam     norm clip + Adam on the FP32 master weights + BF16 copy
@@ -41,6 +44,7 @@ struct sg_ppo {
   float* an = nullptr;       // normalised advantages [max_samples]
   float* scal = nullptr;     // [0] adv mean, [1] adv sd, [2] |g|
   uint16_t* X = nullptr;     // [rows][32]
+  uint16_t* Xall = nullptr;  // [max_samples][32] sample-major BF16 observations
   float* Z1 = nullptr;       // [rows][256]
   uint16_t* H1 = nullptr;
   float* Z2 = nullptr;       // [rows][128]
@@ -74,22 +78,42 @@ struct PpoRows {
   const float* val;   // [T+1][N]
   const float* ret;   // [T][N]
   const float* an;    // normalised advantages [T N]
+  const uint16_t* xall;  // BF16 observations, sample-major [T N][kPX]
   const int* idx;     // sample of row r (null: r0 + r)
   int r0, rows, N, J, W, total;
 };
 
 __device__ __forceinline__ int ppo_sample(const PpoRows& a, int r) { return a.idx ? a.idx[r] : a.r0 + r; }
 
+// The rollout's observations, BF16 and sample-major (one 64-byte row per
+// sample s = t N + e, zero past W), so a minibatch gathers whole rows.
+__global__ void __launch_bounds__(256) k_ppo_xall(const float* __restrict__ obs, int total, int N, int W,
+                                                  uint16_t* __restrict__ xall) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= total) return;
+  const int t = s / N, e = s % N;
+  uint32_t w[kPX / 2];
+#pragma unroll
+  for (int k = 0; k < kPX; k += 2) {
+    const float x0 = k < W ? obs[((size_t)t * W + k) * N + e] : 0.f;
+    const float x1 = k + 1 < W ? obs[((size_t)t * W + k + 1) * N + e] : 0.f;
+    w[k / 2] = (uint32_t)bf16_bits(x0) | ((uint32_t)bf16_bits(x1) << 16);
+  }
+  uint4* dst = reinterpret_cast<uint4*>(xall + (size_t)s * kPX);
+#pragma unroll
+  for (int q = 0; q < kPX / 8; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+}
+
+// Minibatch input rows; a sample id outside [0, T N) gives a zero row.
 __global__ void __launch_bounds__(256) k_ppo_gather(PpoRows a, uint16_t* __restrict__ X) {
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= a.rows) return;
   const int s = ppo_sample(a, r);
   const bool ok = s >= 0 && s < a.total;
-  const int t = ok ? s / a.N : 0, e = ok ? s % a.N : 0;
-  for (int k = 0; k < kPX; ++k) {
-    const float x = (ok && k < a.W) ? a.obs[((size_t)t * a.W + k) * a.N + e] : 0.f;
-    X[(size_t)r * kPX + k] = bf16_bits(x);
-  }
+  const uint4* src = reinterpret_cast<const uint4*>(a.xall + (size_t)(ok ? s : 0) * kPX);
+  uint4* dst = reinterpret_cast<uint4*>(X + (size_t)r * kPX);
+#pragma unroll
+  for (int q = 0; q < kPX / 8; ++q) dst[q] = ok ? src[q] : make_uint4(0, 0, 0, 0);
 }
 
 // Mean and unbiased standard deviation of n values (one block, two passes
@@ -359,10 +383,12 @@ static int splits_for(int tiles, int K) {
 }
 static int chunk_for(int K, int splits) { return ((K + splits - 1) / splits + 31) / 32 * 32; }
 
-// dW [M][N] (leading dim ldo) = sum over the batch with split-K.
+// dW [M][N] (leading dim ldo) = sum over the batch with split-K; the
+// split sums share their launch with `bias`, the reduction of a bias
+// gradient's per-block partial rows.
 template <bool AT, bool BT>
 static void weight_grad(sg_ppo* o, hipStream_t st, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B,
-                        int ldb, float* out, int ldo) {
+                        int ldb, float* out, int ldo, const SumJob& bias) {
   const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
   const int S = splits_for(tiles, K);
   GemmArgs g{};
@@ -370,12 +396,14 @@ static void weight_grad(sg_ppo* o, hipStream_t st, int M, int N, int K, const ui
   g.kchunk = chunk_for(K, S);
   const int S_eff = (K + g.kchunk - 1) / g.kchunk;
   launch_gemm<EPI_PARTIAL, AT, BT, ACT_TANH>(st, g, S_eff);
-  k_sum_splits<<<(M * N + 15) / 16, 256, 0, st>>>(o->ws, S_eff, M, N, out, ldo);
+  const SumJob w{o->ws, S_eff, M, N, out, ldo, 0};
+  const int bw = sum_job_blocks(w);
+  k_sum_two<<<bw + sum_job_blocks(bias), 256, 0, st>>>(w, bw, bias);
 }
 
 // out[c] = sum over `blocks` partial rows part[b][c] (row stride `stride`).
-static void sum_partials(hipStream_t st, const float* part, int blocks, int cols, int stride, float* out) {
-  k_sum_splits<<<(cols + 15) / 16, 256, 0, st>>>(part, blocks, 1, cols, out, cols, stride);
+static SumJob partial_rows(const float* part, int blocks, int cols, int stride, float* out) {
+  return SumJob{part, blocks, 1, cols, out, cols, stride};
 }
 
 // Gradient of one minibatch into o->g (entropy term included, no clip).
@@ -404,24 +432,24 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
   la.rows = rows; la.Z3 = o->Z3; la.ls = o->p + o->off[6]; la.clip = cfg->clip; la.c_v = cfg->value_coef;
   la.inv_b = 1.f / (float)B; la.w_stats = w_stats; la.G3b = o->G3b; la.part = o->lpart;
   k_ppo_loss<<<gb, 256, 0, st>>>(la);
-  // output layer gradients
-  weight_grad<true, false>(o, st, O, kH2, B, o->G3b, kPO, o->H2, kH2, o->g + o->off[4], kH2);
-  // output biases and log_std are adjacent in the flat vector (off[6] = off[5] + O)
-  sum_partials(st, o->lpart, gb, O + J, kLossPart, o->g + o->off[5]);
+  // output layer gradients; output biases and log_std are adjacent in the
+  // flat vector (off[6] = off[5] + O)
+  weight_grad<true, false>(o, st, O, kH2, B, o->G3b, kPO, o->H2, kH2, o->g + o->off[4], kH2,
+                           partial_rows(o->lpart, gb, O + J, kLossPart, o->g + o->off[5]));
   // dZ2 = (G3 W3) * tanh'(Z2), with the column sums of dZ2 (hidden-2 bias)
   const int rb = (B + 63) / 64;
   GemmArgs d{};
   d.M = B; d.N = kH2; d.K = O; d.A = o->G3b; d.lda = kPO; d.B = o->pb + o->off[4]; d.ldb = kH2;
   d.C = nullptr; d.ldc = kH2; d.Cb = o->D2b; d.Zp = o->Z2; d.colpart = o->cpart;
   launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
-  sum_partials(st, o->cpart, rb, kH2, kH2, o->g + o->off[3]);
-  weight_grad<true, false>(o, st, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->off[2], kH1);
+  weight_grad<true, false>(o, st, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->off[2], kH1,
+                           partial_rows(o->cpart, rb, kH2, kH2, o->g + o->off[3]));
   // dZ1 = (dZ2 W2) * tanh'(Z1), with the column sums of dZ1 (hidden-1 bias)
   d.N = kH1; d.K = kH2; d.A = o->D2b; d.lda = kH2; d.B = o->pb + o->off[2]; d.ldb = kH1;
   d.C = nullptr; d.ldc = kH1; d.Cb = o->D1b; d.Zp = o->Z1; d.colpart = o->cpart;
   launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
-  sum_partials(st, o->cpart, rb, kH1, kH1, o->g + o->off[1]);
-  weight_grad<true, false>(o, st, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->off[0], W);
+  weight_grad<true, false>(o, st, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->off[0], W,
+                           partial_rows(o->cpart, rb, kH1, kH1, o->g + o->off[1]));
   const int nb = (o->P + kGnormChunk - 1) / kGnormChunk;
   k_gnorm_part<<<nb, 256, 0, st>>>(o->g, o->P, o->off[6], J, cfg->entropy_coef, o->gpart);
   k_ppo_finish<<<1, 256, 0, st>>>(o->gpart, nb, o->lpart, gb, o->p + o->off[6], J, o->scal, stats, w_stats);
@@ -431,14 +459,17 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
 static PpoRows rows_of(const sg_ppo* o, const sg_rollout_bufs* b, int T) {
   PpoRows r{};
   r.obs = b->obs; r.act = b->act; r.logp = b->logp; r.val = b->val; r.ret = b->ret; r.an = o->an;
+  r.xall = o->Xall;
   r.N = o->ctx->N; r.J = o->J; r.W = o->W; r.total = T * o->ctx->N;
   return r;
 }
 
-static hipError_t normalise_adv(sg_ppo* o, const sg_rollout_bufs* b, int n) {
+// Per update: normalised advantages and the sample-major observation rows.
+static hipError_t prepare_batch(sg_ppo* o, const sg_rollout_bufs* b, int n) {
   hipStream_t st = o->ctx->stream;
   k_adv_stats<<<1, 1024, 0, st>>>(b->adv, n, o->scal);
   k_adv_norm<<<(n + 255) / 256, 256, 0, st>>>(b->adv, n, o->scal, o->an);
+  k_ppo_xall<<<(n + 255) / 256, 256, 0, st>>>(b->obs, n, o->ctx->N, o->W, o->Xall);
   return hipGetLastError();
 }
 
@@ -515,6 +546,7 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   if (e == hipSuccess) e = palloc(o, &o->an, R);
   if (e == hipSuccess) e = palloc(o, &o->scal, 8);
   if (e == hipSuccess) e = palloc(o, &o->X, R * kPX);
+  if (e == hipSuccess) e = palloc(o, &o->Xall, R * kPX);
   if (e == hipSuccess) e = palloc(o, &o->Z1, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->H1, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->Z2, R * kH2);
@@ -580,7 +612,7 @@ sg_status sg_ppo_grad(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const int3
     return pfail(c, SG_E_INVAL, "sg_ppo_grad: T N must be <= max_samples and 1 <= rows <= T N");
   hipStream_t st = c->stream;
   if (stats) k_zero<<<1, 256, 0, st>>>(stats, 8);
-  hipError_t e = normalise_adv(o, b, (int)total);
+  hipError_t e = prepare_batch(o, b, (int)total);
   PpoRows r = rows_of(o, b, T);
   r.idx = idx;
   r.r0 = 0;
@@ -607,7 +639,7 @@ sg_status sg_ppo_update(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const sg
   const int mb = (int)(total / cfg->minibatches);
   const float w = 1.f / (float)(cfg->epochs * cfg->minibatches);
   if (stats) k_zero<<<1, 256, 0, st>>>(stats, 8);
-  hipError_t e = normalise_adv(o, b, (int)total);
+  hipError_t e = prepare_batch(o, b, (int)total);
   for (int ep = 0; ep < cfg->epochs && e == hipSuccess; ++ep) {
     for (int k = 0; k < cfg->minibatches && e == hipSuccess; ++k) {
       PpoRows r = rows_of(o, b, T);
