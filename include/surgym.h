@@ -346,7 +346,8 @@ sg_status sg_surrogate_step(sg_surrogate* s, const float* actions, float* obs, f
  * (0 for saturated actions |a| >= 1) and g_mass [J][N] = dL/dm for each
  * link's mass with its geometry fixed (all of its inertial parameters scale
  * with m). The state is checkpointed every K steps (1 <= K <= T) and each
- * segment is recomputed in the reverse sweep; a clamped coordinate passes no
+ * segment is recomputed (its substep states and accelerations kept for the
+ * reverse sweep); a clamped coordinate passes no
  * gradient, and an episode that ends inside the rollout cuts the gradient
  * at its reset. FP32 contexts with max_dof <= 7. The library keeps a
  * workspace of sg_adjoint_workspace_bytes(T, K) per context, (re)allocated

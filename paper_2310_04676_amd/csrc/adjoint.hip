@@ -8,8 +8,9 @@
 //             (checkpoints, [T/K][2J+1][N]);
 //   reverse   segment by segment from the last: the segment's K steps are
 //             recomputed from its checkpoint, keeping each substep's
-//             starting state in a tape [K S][2J][N] (plus the post-step
-//             state and episode flags per step), then walked backwards:
+//             starting state and acceleration in a tape [K S][3J][N] (plus
+//             the post-step state and episode flags per step), then walked
+//             backwards:
 //             tip-distance gradient, hard stops, semi-implicit Euler, the
 //             implicit forward-dynamics rule (an ABA solve with zero
 //             velocity and gravity gives lambda = (H + arm)^-1 qdd_bar, then
@@ -30,7 +31,7 @@ struct AdjArgs {
   float* g_mass;       // [J][N]
   float* ckpt;         // [nseg][2J][N] q, qd
   int* ckpt_prog;      // [nseg][N]
-  float* tape;         // [K S][2J][N] substep starting states
+  float* tape;         // [K S][3J][N] substep starting states q, qd and accelerations qdd
   float* tend;         // [K][J][N] post-step state before any reset
   int* tinfo;          // [K][N] progress before the step | reset flag << 30
 };
@@ -77,7 +78,7 @@ __global__ void __launch_bounds__(64) k_adjoint(AdjArgs A) {
         qs[j] = j < n ? 0.5f * (p.hi + p.lo) + half[j] * clamp1(a[j]) : 0.f;
       }
       for (int s = 0; s < S; ++s) {
-        float* dst = tp + (size_t)s * 2 * E.J * N;
+        float* dst = tp + (size_t)s * 3 * E.J * N;
         ps.fence();
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -96,6 +97,7 @@ __global__ void __launch_bounds__(64) k_adjoint(AdjArgs A) {
         for (int j = 0; j < J; ++j) {
           if (j < n) {
             const Jp<float> p = ps.get(j);
+            dst[(size_t)(2 * E.J + j) * N + e] = qdd[j];
             qd[j] = qd[j] + h * qdd[j];
             q[j] = q[j] + h * qd[j];
             if (q[j] > p.hi) {
@@ -170,7 +172,7 @@ __global__ void __launch_bounds__(64) k_adjoint(AdjArgs A) {
     }
     prog = A.ckpt_prog[(size_t)sg * N + e];
     for (int t = t0; t < t1; ++t)
-      step(t, A.tape + (size_t)(t - t0) * S * 2 * E.J * N, A.tend + (size_t)(t - t0) * E.J * N,
+      step(t, A.tape + (size_t)(t - t0) * S * 3 * E.J * N, A.tend + (size_t)(t - t0) * E.J * N,
            A.tinfo + (size_t)(t - t0) * N);
     for (int t = t1 - 1; t >= t0; --t) {
       const int info = A.tinfo[(size_t)(t - t0) * N + e];
@@ -193,29 +195,24 @@ __global__ void __launch_bounds__(64) k_adjoint(AdjArgs A) {
         d[0] *= inv; d[1] *= inv; d[2] *= inv;
         tip_vjp<float, J>(ps, n, qe, tipl, d, qb);
       }
-      float a[J], qs[J], qsb[J];
-      ps.fence();
+      float a[J], qsb[J];
 #pragma unroll
       for (int j = 0; j < J; ++j) {
-        const Jp<float> p = ps.get(j);
         a[j] = j < n ? A.act[((size_t)t * E.J + j) * N + e] : 0.f;
-        qs[j] = j < n ? 0.5f * (p.hi + p.lo) + half[j] * clamp1(a[j]) : 0.f;
         qsb[j] = 0.f;
       }
       for (int s = S - 1; s >= 0; --s) {
-        const float* src = A.tape + ((size_t)(t - t0) * S + s) * 2 * E.J * N;
-        float q0[J], qd0[J], tau[J], qdd[J], qddb[J], lam[J], zero[J], gq[J], gqd[J];
-        ps.fence();
+        // the substep's state and the accelerations the recomputation found
+        const float* src = A.tape + ((size_t)(t - t0) * S + s) * 3 * E.J * N;
+        float q0[J], qd0[J], qdd[J], qddb[J], lam[J], zero[J], gq[J], gqd[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-          const Jp<float> p = ps.get(j);
           q0[j] = j < n ? src[(size_t)j * N + e] : 0.f;
           qd0[j] = j < n ? src[(size_t)(E.J + j) * N + e] : 0.f;
-          tau[j] = j < n ? p.kp * (qs[j] - q0[j] - h * qd0[j]) - p.kd * qd0[j] : 0.f;
+          qdd[j] = j < n ? src[(size_t)(2 * E.J + j) * N + e] : 0.f;
           zero[j] = 0.f;
           gq[j] = gqd[j] = 0.f;
         }
-        aba<float, J>(ps, n, q0, qd0, tau, arm, E.g, qdd);
         ps.fence();
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -275,19 +272,19 @@ hipError_t launch_adjoint(const sg_ctx* c, int T, int K, const float* act, float
   AdjArgs A;
   A.E = env_view<float>(c);
   A.T = T; A.K = K; A.act = act; A.loss = loss; A.g_act = g_act; A.g_mass = g_mass;
-  const size_t N = c->N, J2 = 2 * (size_t)c->J, nseg = (T + K - 1) / K;
+  const size_t N = c->N, J2 = 2 * (size_t)c->J, J3 = 3 * (size_t)c->J, nseg = (T + K - 1) / K;
   A.ckpt = ws;
   A.ckpt_prog = reinterpret_cast<int*>(ws + nseg * J2 * N);
   A.tape = ws + nseg * (J2 + 1) * N;
-  A.tend = A.tape + (size_t)K * c->S * J2 * N;
+  A.tend = A.tape + (size_t)K * c->S * J3 * N;
   A.tinfo = reinterpret_cast<int*>(A.tend + (size_t)K * c->J * N);
   if (c->prismatic) return c->J <= 4 ? adjoint_j<4, M_PRI>(c, A) : adjoint_j<7, M_PRI>(c, A);
   return c->J <= 4 ? adjoint_j<4, M_GEN>(c, A) : adjoint_j<7, M_GEN>(c, A);
 }
 
 size_t adjoint_ws_floats(const sg_ctx* c, int T, int K) {
-  const size_t N = c->N, J2 = 2 * (size_t)c->J, nseg = (T + K - 1) / K;
-  return nseg * (J2 + 1) * N + (size_t)K * c->S * J2 * N + (size_t)K * c->J * N + (size_t)K * N;
+  const size_t N = c->N, J2 = 2 * (size_t)c->J, J3 = 3 * (size_t)c->J, nseg = (T + K - 1) / K;
+  return nseg * (J2 + 1) * N + (size_t)K * c->S * J3 * N + (size_t)K * c->J * N + (size_t)K * N;
 }
 
 // Rescale every inertial parameter of each link to new masses m [J][N]

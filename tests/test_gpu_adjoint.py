@@ -75,7 +75,8 @@ def test_checkpoint_interval_does_not_change_results(sg):
 def test_full_size_on_sampled_envs_and_memory(sg):
     """4096 envs x 64 steps x 4 substeps, checkpoints every 8 steps; the first
     24 envs (inputs are prefix-stable) checked against the oracle; workspace
-    against the full tape of substep states."""
+    against the full tape the reverse sweep reads (each substep's q, qd and
+    accelerations for all T steps)."""
     import torch
     N, T, K = 4096, 64, 8
     w = synth.path_rollout(N)
@@ -94,7 +95,7 @@ def test_full_size_on_sampled_envs_and_memory(sg):
     for g, r in ((host(ga)[:, :, :n], ra), (host(gm)[:, :n], rm)):
         rel, cos = _rel_cos(g, r)
         assert rel <= 1e-3 and cos >= 0.9999, (rel, cos)
-    full_tape = T * 4 * 2 * 7 * N * 4
+    full_tape = T * 4 * 3 * 7 * N * 4
     assert sim.adjoint_workspace_bytes(T, K) < full_tape / 4
 
 
