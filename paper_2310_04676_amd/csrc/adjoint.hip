@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(64) k_adjoint(AdjArgs A) {
             qddb[j] = 0.f;
           }
         }
-        aba<float, J>(ps, n, q0, zero, qddb, arm, zero_g, lam);
+        aba<float, J, true>(ps, n, q0, zero, qddb, arm, zero_g, lam);
         vjp_rnea<float, J>(ps, n, q0, qd0, qdd, lam, E.g, gq, gqd, gm);
         ps.fence();
 #pragma unroll

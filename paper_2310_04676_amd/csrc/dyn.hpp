@@ -245,7 +245,9 @@ template <class PS, typename T> __device__ __forceinline__ bool slide(Jp<T>& p, 
 // Joints j >= n are skipped. grav = base-frame gravity. Only sin/cos of each
 // joint angle is kept between the passes; the joint rotation is rebuilt
 // where it is needed (cheaper in registers than holding 9 values per joint).
-template <typename T, int J, class PS>
+// STATIC: qd = 0 and no gravity (qd and grav are not read), so the bias
+// terms vanish and qdd = (H + diag(arm))^-1 tau.
+template <typename T, int J, bool STATIC = false, class PS>
 __device__ __forceinline__ void aba(PS& ps, int n, const T (&q)[J], const T (&qd)[J], const T (&tau)[J],
                                     const T (&arm)[J], const T* grav, T (&qdd)[J]) {
   T sn[J], cs[J], cj[J][6], pj[J][6], U[J][6], invD[J], uj[J];
@@ -258,6 +260,11 @@ __device__ __forceinline__ void aba(PS& ps, int n, const T (&q)[J], const T (&qd
       Jp<T> p = ps.get(j);
       const bool pr = slide<PS>(p, q[j]);
       sc(pr ? T(0) : q[j], &sn[j], &cs[j]);
+      if constexpr (STATIC) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) cj[j][k] = pj[j][k] = T(0);
+        continue;
+      }
       T R[9];
       rodrigues(p, sn[j], cs[j], R);
       T vn[6];
@@ -351,16 +358,21 @@ __device__ __forceinline__ void aba(PS& ps, int n, const T (&q)[J], const T (&qd
           for (int s2 = 0; s2 < 3; ++s2) I.B[r * 3 + s2] -= U[j][r] * Ud[3 + s2];
         I.C[S00] -= U[j][3] * Ud[3]; I.C[S11] -= U[j][4] * Ud[4]; I.C[S22] -= U[j][5] * Ud[5];
         I.C[S01] -= U[j][3] * Ud[4]; I.C[S02] -= U[j][3] * Ud[5]; I.C[S12] -= U[j][4] * Ud[5];
-        // pa += Ia c + U u / D
+        // pa += Ia c + U u / D (c = 0 when STATIC)
         const T* c = cj[j];
         const T uD = uj[j] * invD[j];
         T f[6];
+        if constexpr (STATIC) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) f[k] = pa[k] + U[j][k] * uD;
+        } else {
         f[0] = pa[0] + I.A[S00] * c[0] + I.A[S01] * c[1] + I.A[S02] * c[2] + I.B[0] * c[3] + I.B[1] * c[4] + I.B[2] * c[5] + U[j][0] * uD;
         f[1] = pa[1] + I.A[S01] * c[0] + I.A[S11] * c[1] + I.A[S12] * c[2] + I.B[3] * c[3] + I.B[4] * c[4] + I.B[5] * c[5] + U[j][1] * uD;
         f[2] = pa[2] + I.A[S02] * c[0] + I.A[S12] * c[1] + I.A[S22] * c[2] + I.B[6] * c[3] + I.B[7] * c[4] + I.B[8] * c[5] + U[j][2] * uD;
         f[3] = pa[3] + I.B[0] * c[0] + I.B[3] * c[1] + I.B[6] * c[2] + I.C[S00] * c[3] + I.C[S01] * c[4] + I.C[S02] * c[5] + U[j][3] * uD;
         f[4] = pa[4] + I.B[1] * c[0] + I.B[4] * c[1] + I.B[7] * c[2] + I.C[S01] * c[3] + I.C[S11] * c[4] + I.C[S12] * c[5] + U[j][4] * uD;
         f[5] = pa[5] + I.B[2] * c[0] + I.B[5] * c[1] + I.B[8] * c[2] + I.C[S02] * c[3] + I.C[S12] * c[4] + I.C[S22] * c[5] + U[j][5] * uD;
+        }
 #pragma unroll
         for (int k = 0; k < 6; ++k) { acc.A[k] = T(0); acc.C[k] = T(0); }
 #pragma unroll
@@ -374,7 +386,7 @@ __device__ __forceinline__ void aba(PS& ps, int n, const T (&q)[J], const T (&qd
   }
   // pass 3
   ps.fence();
-  T a[6] = {T(0), T(0), T(0), -grav[0], -grav[1], -grav[2]};
+  T a[6] = {T(0), T(0), T(0), STATIC ? T(0) : -grav[0], STATIC ? T(0) : -grav[1], STATIC ? T(0) : -grav[2]};
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j < n) {
