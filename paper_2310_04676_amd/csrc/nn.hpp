@@ -194,8 +194,10 @@ static inline void launch_gemm(hipStream_t s, const GemmArgs& a, int splits = 1)
 }
 
 // Split sums: out[i * ldo + j] = sum_z part[z * stride + i N + j] over
-// `splits` slabs (stride 0: M N); 16 outputs per block, 16 thread groups
-// each summing every 16th slab, combined in a fixed order: deterministic.
+// `splits` slabs (stride 0: M N). A block covers 256 / G consecutive outputs
+// with G thread groups, group g summing slabs g, g + G, ...; the G partial
+// sums are then added in group order: deterministic for a given G. G (a
+// power of two, 1..64) is chosen so each thread reads about eight slabs.
 // Two independent jobs share one launch: blocks [0, blocks_a) reduce job
 // a, the rest job b.
 struct SumJob {
@@ -203,25 +205,35 @@ struct SumJob {
   int splits, M, N;
   float* out;
   int ldo, stride;
+  int groups;
 };
-static inline int sum_job_blocks(const SumJob& j) { return (j.M * j.N + 15) / 16; }
+static inline SumJob sum_job(const float* part, int splits, int M, int N, float* out, int ldo, int stride) {
+  int g = 1;
+  while (g < 64 && g * 8 < splits) g *= 2;
+  return SumJob{part, splits, M, N, out, ldo, stride, g};
+}
+static inline int sum_job_blocks(const SumJob& j) {
+  const int per = 256 / j.groups;
+  return (j.M * j.N + per - 1) / per;
+}
 static __global__ void __launch_bounds__(256) k_sum_two(SumJob a, int blocks_a, SumJob b) {
-  __shared__ float red[16][16];
+  __shared__ float red[256];
   const bool first = (int)blockIdx.x < blocks_a;
   const SumJob& j = first ? a : b;
   const int blk = first ? blockIdx.x : blockIdx.x - blocks_a;
-  const int o = blk * 16 + (threadIdx.x & 15), grp = threadIdx.x >> 4;
+  const int G = j.groups, per = 256 / G;
+  const int slot = threadIdx.x % per, grp = threadIdx.x / per;
+  const int o = blk * per + slot;
   const int MN = j.M * j.N;
   const size_t st = j.stride > 0 ? (size_t)j.stride : (size_t)MN;
   float s = 0.f;
   if (o < MN)
-    for (int z = grp; z < j.splits; z += 16) s += j.part[(size_t)z * st + o];
-  red[grp][threadIdx.x & 15] = s;
+    for (int z = grp; z < j.splits; z += G) s += j.part[(size_t)z * st + o];
+  red[threadIdx.x] = s;
   __syncthreads();
   if (grp == 0 && o < MN) {
     float t = 0.f;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) t += red[k][threadIdx.x];
+    for (int k = 0; k < G; ++k) t += red[k * per + slot];
     j.out[(size_t)(o / j.N) * j.ldo + o % j.N] = t;
   }
 }

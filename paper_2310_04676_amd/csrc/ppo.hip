@@ -396,14 +396,14 @@ static void weight_grad(sg_ppo* o, hipStream_t st, int M, int N, int K, const ui
   g.kchunk = chunk_for(K, S);
   const int S_eff = (K + g.kchunk - 1) / g.kchunk;
   launch_gemm<EPI_PARTIAL, AT, BT, ACT_TANH>(st, g, S_eff);
-  const SumJob w{o->ws, S_eff, M, N, out, ldo, 0};
+  const SumJob w = sum_job(o->ws, S_eff, M, N, out, ldo, 0);
   const int bw = sum_job_blocks(w);
   k_sum_two<<<bw + sum_job_blocks(bias), 256, 0, st>>>(w, bw, bias);
 }
 
 // out[c] = sum over `blocks` partial rows part[b][c] (row stride `stride`).
 static SumJob partial_rows(const float* part, int blocks, int cols, int stride, float* out) {
-  return SumJob{part, blocks, 1, cols, out, cols, stride};
+  return sum_job(part, blocks, 1, cols, out, cols, stride);
 }
 
 // Gradient of one minibatch into o->g (entropy term included, no clip).
