@@ -57,7 +57,7 @@ struct sg_ppo {
   size_t ws_floats = 0;
   float* cpart = nullptr;    // per-block column sums [rows / 64 (or / 256)][256]
   float* lpart = nullptr;    // k_ppo_loss block sums [rows / 256][kLossPart]
-  double* gpart = nullptr;   // k_gnorm_part block sums [kGnormBlocks]
+  double* gpart = nullptr;   // block sums [kGnormBlocks]: advantage statistics, then gradient norm
   std::vector<void*> allocs;
 };
 
@@ -69,7 +69,7 @@ constexpr int kPO = 8;    // padded output width (J + 1 <= 8)
 // sums (J columns), zero to column 16, then the four weighted loss sums.
 constexpr int kLossPart = 20;
 constexpr int kGnormChunk = 1024;  // gradient entries per k_gnorm_part block
-constexpr int kGnormBlocks = 128;  // capacity of the partial-norm buffer
+constexpr int kGnormBlocks = 128;  // capacity of the partial-sum buffer (norm; advantage statistics)
 
 struct PpoRows {
   const float* obs;   // [T+1][W][N]
@@ -116,38 +116,60 @@ __global__ void __launch_bounds__(256) k_ppo_gather(PpoRows a, uint16_t* __restr
   for (int q = 0; q < kPX / 8; ++q) dst[q] = ok ? src[q] : make_uint4(0, 0, 0, 0);
 }
 
-// Mean and unbiased standard deviation of n values (one block, two passes
-// in double): out[0] = mean, out[1] = sd.
-__global__ void __launch_bounds__(1024) k_adv_stats(const float* __restrict__ x, int n, float* __restrict__ out) {
-  __shared__ double red[1024];
-  double s = 0;
-  for (int i = threadIdx.x; i < n; i += 1024) s += x[i];
-  red[threadIdx.x] = s;
+// Mean and unbiased standard deviation of the n advantages, two passes in
+// double over kAdvBlocks blocks: k_adv_sum leaves per-block sums in
+// part[0..kAdvBlocks), k_adv_sq the per-block sums of squared deviations
+// from the mean in part[kAdvBlocks..2 kAdvBlocks); every reader adds the
+// partials in block order. k_adv_norm writes an = (adv - mean) / (sd +
+// 1e-8) and, from block 0, scal[0] = mean, scal[1] = sd.
+constexpr int kAdvBlocks = 64;
+static_assert(2 * kAdvBlocks <= kGnormBlocks, "advantage partials share the partial-sum buffer");
+
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  red[threadIdx.x] = v;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  const double mean = red[0] / n;
-  __syncthreads();
-  double q = 0;
-  for (int i = threadIdx.x; i < n; i += 1024) q += (x[i] - mean) * (x[i] - mean);
-  red[threadIdx.x] = q;
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out[0] = (float)mean;
-    out[1] = n > 1 ? (float)sqrt(red[0] / (n - 1)) : 0.f;
-  }
+  return red[0];
 }
 
-__global__ void __launch_bounds__(256) k_adv_norm(const float* __restrict__ adv, int n, const float* __restrict__ st,
-                                                  float* __restrict__ an) {
+__device__ __forceinline__ double adv_mean(const double* part, int n) {
+  double s = 0;
+  for (int b = 0; b < kAdvBlocks; ++b) s += part[b];
+  return s / n;
+}
+
+__global__ void __launch_bounds__(256) k_adv_sum(const float* __restrict__ x, int n, double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += kAdvBlocks * 256) s += x[i];
+  const double t = block_sum256(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256) k_adv_sq(const float* __restrict__ x, int n, double* __restrict__ part) {
+  __shared__ double red[256];
+  const double mean = adv_mean(part, n);
+  double q = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += kAdvBlocks * 256) q += (x[i] - mean) * (x[i] - mean);
+  const double t = block_sum256(q, red);
+  if (threadIdx.x == 0) part[kAdvBlocks + blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256) k_adv_norm(const float* __restrict__ adv, int n, const double* __restrict__ part,
+                                                  float* __restrict__ an, float* __restrict__ scal) {
+  const double mean = adv_mean(part, n);
+  double q = 0;
+  for (int b = 0; b < kAdvBlocks; ++b) q += part[kAdvBlocks + b];
+  const float m = (float)mean, sd = n > 1 ? (float)sqrt(q / (n - 1)) : 0.f;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[0] = m;
+    scal[1] = sd;
+  }
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) an[i] = (adv[i] - st[0]) / (st[1] + 1e-8f);
+  if (i < n) an[i] = (adv[i] - m) / (sd + 1e-8f);
 }
 
 struct PpoLossArgs {
@@ -467,8 +489,9 @@ static PpoRows rows_of(const sg_ppo* o, const sg_rollout_bufs* b, int T) {
 // Per update: normalised advantages and the sample-major observation rows.
 static hipError_t prepare_batch(sg_ppo* o, const sg_rollout_bufs* b, int n) {
   hipStream_t st = o->ctx->stream;
-  k_adv_stats<<<1, 1024, 0, st>>>(b->adv, n, o->scal);
-  k_adv_norm<<<(n + 255) / 256, 256, 0, st>>>(b->adv, n, o->scal, o->an);
+  k_adv_sum<<<kAdvBlocks, 256, 0, st>>>(b->adv, n, o->gpart);
+  k_adv_sq<<<kAdvBlocks, 256, 0, st>>>(b->adv, n, o->gpart);
+  k_adv_norm<<<(n + 255) / 256, 256, 0, st>>>(b->adv, n, o->gpart, o->an, o->scal);
   k_ppo_xall<<<(n + 255) / 256, 256, 0, st>>>(b->obs, n, o->ctx->N, o->W, o->Xall);
   return hipGetLastError();
 }
