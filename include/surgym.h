@@ -38,8 +38,9 @@
  * A context is used by one host thread at a time.
  *
  * HIP graph capture: the device work of sg_step, sg_observe, sg_rollout,
- * sg_gae, the dynamics calls, the surrogate calls and sg_ppo_update is
- * kernels only (no memset or memcpy nodes), so a call can be captured on
+ * sg_gae, the dynamics calls, sg_surrogate_train_step, sg_surrogate_predict,
+ * sg_surrogate_step and sg_ppo_update is kernels only (no memset or memcpy
+ * nodes), so a call can be captured on
  * the context's stream. A replay repeats the call exactly as captured,
  * including its host-side counters: the noise counter (rng_step; the
  * rollout's action noise and the tracking task's goal draws) and the Adam

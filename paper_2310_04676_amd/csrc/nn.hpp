@@ -1,7 +1,7 @@
 // Training primitives shared by the learned surrogate and the PPO update:
 // a BF16 MFMA GEMM (gfx950 v_mfma_f32_16x16x32_bf16, FP32 accumulation)
 // with fused epilogues, a deterministic split-K path for the batch
-// reductions of weight gradients, column sums and Adam.
+// reductions of weight and bias gradients, and Adam.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -238,32 +238,48 @@ static __global__ void __launch_bounds__(256) k_sum_two(SumJob a, int blocks_a, 
   }
 }
 
-// db[c] = sum_r G[r][c].
-static __global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ G, int rows, int cols,
-                                                       float* __restrict__ out) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= cols) return;
-  float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += G[(size_t)r * cols + c];
-  out[c] = s;
+// Split-K shape for a weight gradient: about 256 blocks over the output
+// tiles, each summing a chunk (multiple of 32) of the batch.
+static inline int splits_for(int tiles, int K) {
+  int s = 256 / (tiles > 0 ? tiles : 1);
+  const int kmax = (K + 31) / 32;
+  if (s > kmax) s = kmax;
+  return s < 1 ? 1 : s;
+}
+static inline int chunk_for(int K, int splits) { return ((K + splits - 1) / splits + 31) / 32 * 32; }
+// Floats of split-K partials the helper below may write: 256 tiles x 64 x 64.
+constexpr size_t kWeightGradWs = (size_t)256 * 64 * 64;
+
+// dW [M][N] (leading dim ldo) = sum_b A(b, m) B(b, n) over a batch of K
+// rows (A [K][lda], B [K][ldb], BF16) with split-K partials in ws
+// (kWeightGradWs floats); the split sums share their launch with `bias`,
+// the reduction of a bias gradient's per-block partial rows.
+template <int ACT>
+static inline void launch_weight_grad(hipStream_t st, int M, int N, int K, const uint16_t* A, int lda,
+                                      const uint16_t* B, int ldb, float* out, int ldo, float* ws,
+                                      const SumJob& bias) {
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  const int S = splits_for(tiles, K);
+  GemmArgs g{};
+  g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = ws; g.ldc = N;
+  g.kchunk = chunk_for(K, S);
+  const int S_eff = (K + g.kchunk - 1) / g.kchunk;
+  launch_gemm<EPI_PARTIAL, true, false, ACT>(st, g, S_eff);
+  const SumJob w = sum_job(ws, S_eff, M, N, out, ldo, 0);
+  const int bw = sum_job_blocks(w);
+  k_sum_two<<<bw + sum_job_blocks(bias), 256, 0, st>>>(w, bw, bias);
 }
 
-// Column sums of G [rows][ldg] (cols used) in row chunks: partial
-// [gridDim.y][cols]; block (x, y) covers 64 columns of rows
-// [y chunk, (y+1) chunk), four threads per column.
-static __global__ void __launch_bounds__(256) k_colsum_part(const float* __restrict__ G, int rows, int cols, int ldg,
-                                                            int chunk, float* __restrict__ part) {
-  __shared__ float red[4][64];
-  const int c = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
-  const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
-  float s = 0.f;
-  if (c < cols)
-    for (int r = r0 + q; r < r1; r += 4) s += G[(size_t)r * ldg + c];
-  red[q][threadIdx.x & 63] = s;
-  __syncthreads();
-  if (q == 0 && c < cols)
-    part[(size_t)blockIdx.y * cols + c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
-                                          (red[2][threadIdx.x] + red[3][threadIdx.x]);
+// out[c] = sum over `blocks` partial rows part[b][c] (row stride `stride`).
+static inline SumJob partial_rows(const float* part, int blocks, int cols, int stride, float* out) {
+  return sum_job(part, blocks, 1, cols, out, cols, stride);
+}
+
+// dst[i] = src[i] (a kernel rather than a copy node, so callers stay
+// capturable).
+static __global__ void __launch_bounds__(256) k_copy_f(const float* __restrict__ src, float* __restrict__ dst, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 // Adam (Kingma & Ba) with bias correction c1 = 1 - beta1^t, c2 = 1 - beta2^t

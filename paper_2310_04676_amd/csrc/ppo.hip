@@ -397,35 +397,10 @@ __global__ void __launch_bounds__(256) k_zero(float* __restrict__ x, int n) {
   if (i < n) x[i] = 0.f;
 }
 
-static int splits_for(int tiles, int K) {
-  int s = 256 / (tiles > 0 ? tiles : 1);
-  const int kmax = (K + 31) / 32;
-  if (s > kmax) s = kmax;
-  return s < 1 ? 1 : s;
-}
-static int chunk_for(int K, int splits) { return ((K + splits - 1) / splits + 31) / 32 * 32; }
-
-// dW [M][N] (leading dim ldo) = sum over the batch with split-K; the
-// split sums share their launch with `bias`, the reduction of a bias
-// gradient's per-block partial rows.
-template <bool AT, bool BT>
+// dW [M][N] (leading dim ldo) over the minibatch, split-K in o->ws.
 static void weight_grad(sg_ppo* o, hipStream_t st, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B,
                         int ldb, float* out, int ldo, const SumJob& bias) {
-  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
-  const int S = splits_for(tiles, K);
-  GemmArgs g{};
-  g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = o->ws; g.ldc = N;
-  g.kchunk = chunk_for(K, S);
-  const int S_eff = (K + g.kchunk - 1) / g.kchunk;
-  launch_gemm<EPI_PARTIAL, AT, BT, ACT_TANH>(st, g, S_eff);
-  const SumJob w = sum_job(o->ws, S_eff, M, N, out, ldo, 0);
-  const int bw = sum_job_blocks(w);
-  k_sum_two<<<bw + sum_job_blocks(bias), 256, 0, st>>>(w, bw, bias);
-}
-
-// out[c] = sum over `blocks` partial rows part[b][c] (row stride `stride`).
-static SumJob partial_rows(const float* part, int blocks, int cols, int stride, float* out) {
-  return sum_job(part, blocks, 1, cols, out, cols, stride);
+  launch_weight_grad<ACT_TANH>(st, M, N, K, A, lda, B, ldb, out, ldo, o->ws, bias);
 }
 
 // Gradient of one minibatch into o->g (entropy term included, no clip).
@@ -456,7 +431,7 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
   k_ppo_loss<<<gb, 256, 0, st>>>(la);
   // output layer gradients; output biases and log_std are adjacent in the
   // flat vector (off[6] = off[5] + O)
-  weight_grad<true, false>(o, st, O, kH2, B, o->G3b, kPO, o->H2, kH2, o->g + o->off[4], kH2,
+  weight_grad(o, st, O, kH2, B, o->G3b, kPO, o->H2, kH2, o->g + o->off[4], kH2,
                            partial_rows(o->lpart, gb, O + J, kLossPart, o->g + o->off[5]));
   // dZ2 = (G3 W3) * tanh'(Z2), with the column sums of dZ2 (hidden-2 bias)
   const int rb = (B + 63) / 64;
@@ -464,13 +439,13 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
   d.M = B; d.N = kH2; d.K = O; d.A = o->G3b; d.lda = kPO; d.B = o->pb + o->off[4]; d.ldb = kH2;
   d.C = nullptr; d.ldc = kH2; d.Cb = o->D2b; d.Zp = o->Z2; d.colpart = o->cpart;
   launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
-  weight_grad<true, false>(o, st, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->off[2], kH1,
+  weight_grad(o, st, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->off[2], kH1,
                            partial_rows(o->cpart, rb, kH2, kH2, o->g + o->off[3]));
   // dZ1 = (dZ2 W2) * tanh'(Z1), with the column sums of dZ1 (hidden-1 bias)
   d.N = kH1; d.K = kH2; d.A = o->D2b; d.lda = kH2; d.B = o->pb + o->off[2]; d.ldb = kH1;
   d.C = nullptr; d.ldc = kH1; d.Cb = o->D1b; d.Zp = o->Z1; d.colpart = o->cpart;
   launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
-  weight_grad<true, false>(o, st, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->off[0], W,
+  weight_grad(o, st, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->off[0], W,
                            partial_rows(o->cpart, rb, kH1, kH1, o->g + o->off[1]));
   const int nb = (o->P + kGnormChunk - 1) / kGnormChunk;
   k_gnorm_part<<<nb, 256, 0, st>>>(o->g, o->P, o->off[6], J, cfg->entropy_coef, o->gpart);
@@ -560,7 +535,7 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   o->P = acc;
   const size_t R = (size_t)max_samples, P = (size_t)o->P;
   // split-K partials: at most 256 tiles x splits x 64 x 64
-  o->ws_floats = (size_t)256 * 64 * 64;
+  o->ws_floats = kWeightGradWs;
   hipError_t e = palloc(o, &o->p, P);
   if (e == hipSuccess) e = palloc(o, &o->pb, P);
   if (e == hipSuccess) e = palloc(o, &o->g, P);

@@ -8,7 +8,8 @@
 // Kernels (the training GEMM, column sums and Adam are the shared ones of
 // nn.hpp, with ELU units):
 //   k_feat      normalised BF16 features [B][96] of a batch.
-//   k_loss      MSE gradient on normalised targets and the loss.
+//   k_loss      MSE gradient on normalised targets; per-block sums of the
+//               output bias gradient and of the loss.
 //   k_pack      BF16 fragment image for the fused inference kernel.
 //   k_sinfer    fused inference: features -> 4 layers on the matrix cores,
 //               hidden activations in registers, weights streamed from L2.
@@ -108,31 +109,44 @@ __global__ void __launch_bounds__(256) k_rowstats(const float* __restrict__ x, i
 }
 
 // Loss gradient on normalised targets: G = 2 (z - t) / (B J) for real
-// outputs, 0 for padding; loss += sum (z - t)^2 / (B J).
+// outputs, 0 for padding (BF16 for the GEMMs); per block of 256 rows, the
+// column sums of the FP32 G (the output bias gradient) in part[b][0..kSO)
+// and the block's share of the loss sum (z - t)^2 / (B J) in part[b][kSO],
+// each added in a fixed order.
+constexpr int kSLossRow = 32;  // row stride of the k_loss block sums
 __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ Z, const float* __restrict__ qdd, int n_total,
                                               const int* __restrict__ idx, int B, int J, const float* __restrict__ norm,
-                                              float* __restrict__ G, uint16_t* __restrict__ Gb, float* loss) {
+                                              uint16_t* __restrict__ Gb, float* __restrict__ part) {
+  __shared__ float red[4][kSO + 1];
   const int r = blockIdx.x * 256 + threadIdx.x;
-  float part = 0.f;
+  float g[kSO + 1];
+#pragma unroll
+  for (int o = 0; o <= kSO; ++o) g[o] = 0.f;
   if (r < B) {
     const int s = idx ? idx[r] : r;
     const bool ok = s >= 0 && s < n_total;
     const float sc = 1.f / ((float)B * (float)J);
+#pragma unroll
     for (int o = 0; o < kSO; ++o) {
-      float gval = 0.f;
       if (o < J && ok) {
         const float t = (qdd[(size_t)o * n_total + s] - norm[2 * kSF + o]) / norm[2 * kSF + kSO + o];
         const float d = Z[(size_t)r * kSO + o] - t;
-        part += d * d * sc;
-        gval = 2.f * d * sc;
+        g[kSO] += d * d * sc;
+        g[o] = 2.f * d * sc;
       }
-      G[(size_t)r * kSO + o] = gval;
-      Gb[(size_t)r * kSO + o] = bf16_bits(gval);
+      Gb[(size_t)r * kSO + o] = bf16_bits(g[o]);
     }
   }
-  // wave reduction, one atomic per wave
-  for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
-  if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, part);
+#pragma unroll
+  for (int o = 0; o <= kSO; ++o)
+    for (int off = 32; off > 0; off >>= 1) g[o] += __shfl_xor(g[o], off, 64);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int o = 0; o <= kSO; ++o) red[threadIdx.x >> 6][o] = g[o];
+  __syncthreads();
+  if (threadIdx.x <= kSO)
+    part[(size_t)blockIdx.x * kSLossRow + threadIdx.x] =
+        (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
 
@@ -491,13 +505,14 @@ struct sg_surrogate {
   // training scratch
   uint16_t* X[kSL] = {};   // layer inputs [B][in] bf16
   float* Z[kSL] = {};      // pre-activations [B][out]
-  float* G = nullptr;      // gradient [B][256] fp32
   uint16_t* Gb = nullptr;  // gradient [B][256] bf16
-  float* G2 = nullptr;
   uint16_t* Gb2 = nullptr;
+  float* ws = nullptr;     // split-K partials of the weight gradients
+  float* cpart = nullptr;  // per-block column sums of a layer's gradient [B / 64][256]
+  float* lpart = nullptr;  // k_loss block sums [B / 256][kSLossRow]
   float* gW[kSL] = {};
-  float* gb[kSL] = {};
-  float* loss = nullptr;
+  float* gb[kSL] = {};     // gb[kSL - 1][kSO] holds the batch loss
+  float* loss = nullptr;   // = gb[kSL - 1] + kSO
   // control step
   float* qddbuf = nullptr;
   int* count = nullptr;
@@ -575,33 +590,29 @@ hipError_t forward_backward(sg_surrogate* s, hipStream_t st, const float* q, con
       launch_gemm<EPI_FWD_OUT, false, true, ACT_ELU>(st, g);
     }
   }
-  hipError_t e = hipMemsetAsync(s->loss, 0, sizeof(float), st);
-  if (e != hipSuccess) return e;
-  float* Gc = s->G;
   uint16_t* Gbc = s->Gb;
-  float* Gn = s->G2;
   uint16_t* Gbn = s->Gb2;
-  k_loss<<<(B + 255) / 256, 256, 0, st>>>(s->Z[kSL - 1], qdd, n_total, idx, B, s->J, s->norm, Gc, Gbc, s->loss);
+  const int gb = (B + 255) / 256, rb = (B + 63) / 64;
+  k_loss<<<gb, 256, 0, st>>>(s->Z[kSL - 1], qdd, n_total, idx, B, s->J, s->norm, Gbc, s->lpart);
+  // the output layer's bias gradient and the loss (adjacent in gb[kSL - 1])
+  SumJob bias = partial_rows(s->lpart, gb, kSO + 1, kSLossRow, s->gb[kSL - 1]);
   for (int l = kSL - 1; l >= 0; --l) {
-    // dW[o][i] = sum_b G[b][o] X[b][i]
-    GemmArgs g{};
-    g.M = s_out(l); g.N = s_in(l); g.K = B;
-    g.A = Gbc; g.lda = s_out(l);
-    g.B = s->X[l]; g.ldb = s_in(l);
-    g.C = s->gW[l]; g.ldc = s_in(l);
-    launch_gemm<EPI_PLAIN, true, false, ACT_ELU>(st, g);
-    k_colsum<<<(s_out(l) + 255) / 256, 256, 0, st>>>(Gc, B, s_out(l), s->gb[l]);
+    // dW[o][i] = sum_b G[b][o] X[b][i]; with it the bias gradient's sum
+    launch_weight_grad<ACT_ELU>(st, s_out(l), s_in(l), B, Gbc, s_out(l), s->X[l], s_in(l), s->gW[l], s_in(l), s->ws,
+                                bias);
     if (l == 0) break;
-    // G_prev[b][i] = (sum_o G[b][o] W[o][i]) * elu'(Z_prev[b][i])
+    // G_prev[b][i] = (sum_o G[b][o] W[o][i]) * elu'(Z_prev[b][i]), with the
+    // per-block column sums of G_prev (the previous layer's bias gradient)
     GemmArgs d{};
     d.M = B; d.N = s_in(l); d.K = s_out(l);
     d.A = Gbc; d.lda = s_out(l);
     d.B = s->Wb[l]; d.ldb = s_in(l);
-    d.C = Gn; d.ldc = s_in(l);
+    d.C = nullptr; d.ldc = s_in(l);
     d.Cb = Gbn;
     d.Zp = s->Z[l - 1];
+    d.colpart = s->cpart;
     launch_gemm<EPI_BWD_DX, false, false, ACT_ELU>(st, d);
-    std::swap(Gc, Gn);
+    bias = partial_rows(s->cpart, rb, s_out(l - 1), s_out(l - 1), s->gb[l - 1]);
     std::swap(Gbc, Gbn);
   }
   return hipGetLastError();
@@ -634,17 +645,19 @@ sg_status sg_surrogate_create(sg_ctx* c, int32_t max_batch, sg_surrogate** out) 
     if (e == hipSuccess) e = dalloc(s, &s->vb[l], nb);
     if (e == hipSuccess) e = dalloc(s, &s->Wb[l], nw);
     if (e == hipSuccess) e = dalloc(s, &s->gW[l], nw);
-    if (e == hipSuccess) e = dalloc(s, &s->gb[l], nb);
+    // the output layer's bias gradient is followed by the batch loss
+    if (e == hipSuccess) e = dalloc(s, &s->gb[l], l == kSL - 1 ? nb + 1 : nb);
     if (e == hipSuccess) e = dalloc(s, &s->X[l], B * s_in(l));
     if (e == hipSuccess) e = dalloc(s, &s->Z[l], B * s_out(l));
   }
   if (e == hipSuccess) e = dalloc(s, &s->img, (size_t)kSFrags * 8);
   if (e == hipSuccess) e = dalloc(s, &s->norm, 2 * kSF + 2 * kSO);
-  if (e == hipSuccess) e = dalloc(s, &s->G, B * kSH);
   if (e == hipSuccess) e = dalloc(s, &s->Gb, B * kSH);
-  if (e == hipSuccess) e = dalloc(s, &s->G2, B * kSH);
   if (e == hipSuccess) e = dalloc(s, &s->Gb2, B * kSH);
-  if (e == hipSuccess) e = dalloc(s, &s->loss, 1);
+  if (e == hipSuccess) e = dalloc(s, &s->ws, kWeightGradWs);
+  if (e == hipSuccess) e = dalloc(s, &s->cpart, ((B + 63) / 64) * (size_t)kSH);
+  if (e == hipSuccess) e = dalloc(s, &s->lpart, ((B + 255) / 256) * (size_t)kSLossRow);
+  if (e == hipSuccess) s->loss = s->gb[kSL - 1] + kSO;
   if (e == hipSuccess) e = dalloc(s, &s->qddbuf, (size_t)c->J * c->N);
   if (e == hipSuccess) e = dalloc(s, &s->count, 64);
   if (e == hipSuccess) e = dalloc(s, &s->list, (size_t)c->S * c->N);
@@ -809,7 +822,7 @@ sg_status sg_surrogate_train_step(sg_surrogate* s, const float* q, const float* 
   }
   if (e == hipSuccess)
     k_pack<<<dim3(16 * 8, kSL), 64, 0, c->stream>>>(s->Wb[0], s->Wb[1], s->Wb[2], s->Wb[3], s->img);
-  if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, s->loss, 4, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && loss) k_copy_f<<<1, 256, 0, c->stream>>>(s->loss, loss, 1);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) {
     c->err = std::string("sg_surrogate_train_step: ") + hipGetErrorString(e);
