@@ -64,19 +64,35 @@ __device__ __forceinline__ void raw_features(const FeatArgs& a, int s, float* x)
   }
 }
 
+// One thread per (row, feature): the same values as raw_features.
+// Consecutive threads take consecutive features of a row when writing the
+// row-major X, consecutive rows of a feature when writing only the
+// feature-major Xraw, so the stores are contiguous either way.
+static_assert(P_IYZ == P_M + 9, "link inertial fields are contiguous");
 __global__ void __launch_bounds__(256) k_feat(FeatArgs a) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= a.B) return;
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (size_t)a.B * kSF) return;
+  const bool rows = a.X != nullptr;
+  const int r = rows ? (int)(i / kSF) : (int)(i % a.B), f = rows ? (int)(i % kSF) : (int)(i / a.B);
   const int s = a.idx ? a.idx[r] : r;
-  float x[kSF];
-  raw_features(a, s, x);
-  for (int f = 0; f < kSF; ++f) {
-    if (a.Xraw) a.Xraw[(size_t)f * a.B + r] = x[f];
-    if (a.X) {
-      const float v = f < 13 * a.J ? (x[f] - a.norm[f]) / a.norm[kSF + f] : 0.f;
-      a.X[(size_t)r * kSF + f] = bf16_bits(v);
+  const int J = a.J;
+  float x = 0.f;
+  if (s >= 0 && s < a.n_total) {
+    const int e = a.env[s];
+    if (e >= 0 && e < a.N) {
+      const int n = a.nd[e];
+      if (f < 3 * J) {
+        const int kind = f / J, j = f % J;
+        const float* src = kind == 0 ? a.q : (kind == 1 ? a.qd : a.tau);
+        if (j < n) x = src[(size_t)j * a.n_total + s];
+      } else if (f < 13 * J) {
+        const int g = f - 3 * J, j = g / 10, k = g % 10;
+        if (j < n) x = a.par[(size_t)(P_M + k) * J * a.N + (size_t)j * a.N + e];
+      }
     }
   }
+  if (a.Xraw) a.Xraw[(size_t)f * a.B + r] = x;
+  if (a.X) a.X[(size_t)r * kSF + f] = bf16_bits(f < 13 * J ? (x - a.norm[f]) / a.norm[kSF + f] : 0.f);
 }
 
 // Mean and standard deviation per row of a [rows][n] array (one block per
@@ -575,7 +591,7 @@ hipError_t forward_backward(sg_surrogate* s, hipStream_t st, const float* q, con
                             const int* env, const float* qdd, int n_total, const int* idx, int B) {
   FeatArgs fa = feat_args(s, q, qd, tau, env, n_total, idx, B);
   fa.X = s->X[0];
-  k_feat<<<(B + 255) / 256, 256, 0, st>>>(fa);
+  k_feat<<<(unsigned)(((size_t)B * kSF + 255) / 256), 256, 0, st>>>(fa);
   for (int l = 0; l < kSL; ++l) {
     GemmArgs g{};
     g.M = B; g.N = s_out(l); g.K = s_in(l);
@@ -763,7 +779,7 @@ sg_status sg_surrogate_fit_norm(sg_surrogate* s, const float* q, const float* qd
   if (e != hipSuccess) return sfail(c, SG_E_NOMEM, "sg_surrogate_fit_norm: out of memory");
   FeatArgs fa = feat_args(s, q, qd, tau, env, n, nullptr, n);
   fa.Xraw = xr;
-  k_feat<<<(n + 255) / 256, 256, 0, c->stream>>>(fa);
+  k_feat<<<(unsigned)(((size_t)n * kSF + 255) / 256), 256, 0, c->stream>>>(fa);
   k_rowstats<<<kSF, 256, 0, c->stream>>>(xr, n, s->norm, s->norm + kSF);
   k_rowstats<<<s->J, 256, 0, c->stream>>>(qdd, n, s->norm + 2 * kSF, s->norm + 2 * kSF + kSO);
   e = hipStreamSynchronize(c->stream);
