@@ -61,6 +61,38 @@ __device__ __forceinline__ void stage_chain(const EnvDev<T>& E, int e, int n, in
       sp[(f * J + j) * 64 + lane] = (j < n) ? E.par[((size_t)f * E.J + j) * E.N + e] : T(0);
 }
 
+// The same staging for a block whose 64 envs are contiguous (e0 .. e0 + 63):
+// every [field][joint] row of the block is 64 consecutive values of the
+// parameter block, copied by 16 lanes as 16-byte pieces (FP32); values of
+// envs past the last one, and of joints past max_dof, zero. The parameter
+// block holds zeros for joints >= an env's n_dof, as stage_chain writes.
+template <typename T, int J>
+__device__ __forceinline__ void stage_block(const EnvDev<T>& E, int e0, int lane, T* sp) {
+  if constexpr (sizeof(T) != 4) {
+    stage_chain<T, J>(E, e0 + lane, e0 + lane < E.N ? J : 0, lane, sp);
+  } else {
+    constexpr int rows = P_NSTAGE * J;
+    const int sub = lane >> 4, c = (lane & 15) * 4;
+    const bool vec = (E.N & 3) == 0;
+    for (int r = sub; r < rows; r += 4) {
+      const int f = r / J, j = r % J;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (j < E.J) {
+        const T* src = E.par + ((size_t)f * E.J + j) * E.N + e0 + c;
+        if (vec && e0 + c + 3 < E.N) {
+          v = *reinterpret_cast<const float4*>(src);
+        } else {
+          v.x = e0 + c < E.N ? src[0] : 0.f;
+          v.y = e0 + c + 1 < E.N ? src[1] : 0.f;
+          v.z = e0 + c + 2 < E.N ? src[2] : 0.f;
+          v.w = e0 + c + 3 < E.N ? src[3] : 0.f;
+        }
+      }
+      *reinterpret_cast<float4*>(sp + r * 64 + c) = v;
+    }
+  }
+}
+
 // ---- per-block parameter sources ----------------------------------------
 constexpr int kBlk = 64;
 
@@ -79,12 +111,26 @@ template <typename T, int J, bool PR> struct ParOf<T, J, true, PR> {
     __syncthreads();
     return type{sp, (int)threadIdx.x};
   }
+  // blocks of 64 contiguous envs: e = 64 blockIdx.x + threadIdx.x
+  static __device__ __forceinline__ type make_contiguous(const EnvDev<T>& E, T* sp) {
+    __syncthreads();
+    stage_block<T, J>(E, (int)blockIdx.x * kBlk, threadIdx.x, sp);
+    __syncthreads();
+    return type{sp, (int)threadIdx.x};
+  }
 };
 template <typename T, int J, bool PR> struct ParOf<T, J, false, PR> {
   using type = RegPar<T, J, PR>;
   static __device__ __forceinline__ type make(const EnvDev<T>& E, int e, int n, bool active, T*) {
     type r;
     if (active) load_chain<T, J>(E, e, n, r);
+    return r;
+  }
+  static __device__ __forceinline__ type make_contiguous(const EnvDev<T>& E, T*) {
+    const int e = (int)blockIdx.x * kBlk + threadIdx.x;
+    const int n = e < E.N ? E.nd[e] : 0;
+    type r;
+    if (e < E.N) load_chain<T, J>(E, e, n, r);
     return r;
   }
 };

@@ -26,16 +26,29 @@ int dof_bucket(int J) {
   if (!active) return;
 
 // One control step of env e (inactive lanes only help stage parameters).
-template <typename T, int J, int M>
+// CONTIG: the block's envs are 64 blockIdx.x .. + 63: the parameters are
+// staged as contiguous rows, and (FP32) the state and action loads are
+// issued before the staging, overlapping it.
+template <typename T, int J, int M, bool CONTIG = false>
 __device__ __forceinline__ void step_body(const EnvDev<T>& E, int e, bool active, T* sp, const T* __restrict__ act,
                                           T* __restrict__ obs, T* __restrict__ rew, uint8_t* __restrict__ done) {
   const int n = M == M_UNI ? J : (active ? E.nd[e] : 0);
-  auto ps = ParOf<T, J, use_lds<T, J>(), M == M_PRI>::make(E, e, n, active, sp);
-  if (!active) return;
+  // (FP64 keeps the later loads: its state held across the staging spills)
+  constexpr bool EARLY = CONTIG && sizeof(T) == 4;
   T q[J], qd[J], a[J];
-  load_state<T, J>(E, e, n, q, qd);
+  if (EARLY && active) {
+    load_state<T, J>(E, e, n, q, qd);
 #pragma unroll
-  for (int j = 0; j < J; ++j) a[j] = j < n ? act[(size_t)j * E.N + e] : T(0);
+    for (int j = 0; j < J; ++j) a[j] = j < n ? act[(size_t)j * E.N + e] : T(0);
+  }
+  using Src = ParOf<T, J, use_lds<T, J>(), M == M_PRI>;
+  auto ps = CONTIG ? Src::make_contiguous(E, sp) : Src::make(E, e, n, active, sp);
+  if (!active) return;
+  if (!EARLY) {
+    load_state<T, J>(E, e, n, q, qd);
+#pragma unroll
+    for (int j = 0; j < J; ++j) a[j] = j < n ? act[(size_t)j * E.N + e] : T(0);
+  }
   physics<T, J>(E, ps, n, a, q, qd);
   int prog = E.prog[e];
   T r;
@@ -50,7 +63,7 @@ __global__ void __launch_bounds__(kBlk) k_step(EnvDev<T> E, const T* __restrict_
                                                T* __restrict__ rew, uint8_t* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int e = blockIdx.x * kBlk + threadIdx.x;
-  step_body<T, J, M>(E, e, e < E.N, reinterpret_cast<T*>(smem_raw), act, obs, rew, done);
+  step_body<T, J, M, true>(E, e, e < E.N, reinterpret_cast<T*>(smem_raw), act, obs, rew, done);
 }
 
 // Uneven batches: envs bucketed by DOF class into 64-slot tiles, so every
