@@ -283,21 +283,42 @@ static __global__ void __launch_bounds__(256) k_copy_f(const float* __restrict__
 }
 
 // Adam (Kingma & Ba) with bias correction c1 = 1 - beta1^t, c2 = 1 - beta2^t
-// passed in; optional BF16 copy of the updated weights.
-static __global__ void __launch_bounds__(256) k_adam(int n, float* __restrict__ w, const float* __restrict__ g,
-                                                     float* __restrict__ m, float* __restrict__ v, float lr, float b1,
-                                                     float b2, float eps, float c1, float c2,
-                                                     uint16_t* __restrict__ wb) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-  w[i] = wi;
-  if (wb) wb[i] = bf16_bits(wi);
+// passed in, over up to kAdamSegs parameter arrays in one launch: segment
+// k owns blocks [blk0_k, blk0_{k+1}); optional BF16 copy of the updated
+// weights.
+constexpr int kAdamSegs = 8;
+struct AdamSeg {
+  float* w;
+  const float* g;
+  float* m;
+  float* v;
+  uint16_t* wb;  // may be null
+  int n, blk0;
+};
+struct AdamSegs {
+  AdamSeg s[kAdamSegs];
+  int count, blocks;
+};
+static inline void adam_add(AdamSegs& a, float* w, const float* g, float* m, float* v, uint16_t* wb, int n) {
+  a.s[a.count] = AdamSeg{w, g, m, v, wb, n, a.blocks};
+  a.blocks += (n + 255) / 256;
+  a.count += 1;
+}
+static __global__ void __launch_bounds__(256) k_adam_segs(AdamSegs a, float lr, float b1, float b2, float eps, float c1,
+                                                          float c2) {
+  int k = 0;
+  while (k + 1 < a.count && (int)blockIdx.x >= a.s[k + 1].blk0) ++k;
+  const AdamSeg& sg = a.s[k];
+  const int i = ((int)blockIdx.x - sg.blk0) * 256 + threadIdx.x;
+  if (i >= sg.n) return;
+  const float gi = sg.g[i];
+  const float mi = b1 * sg.m[i] + (1.f - b1) * gi;
+  const float vi = b2 * sg.v[i] + (1.f - b2) * gi * gi;
+  sg.m[i] = mi;
+  sg.v[i] = vi;
+  const float wi = sg.w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  sg.w[i] = wi;
+  if (sg.wb) sg.wb[i] = bf16_bits(wi);
 }
 
 static __global__ void __launch_bounds__(256) k_to_bf16(int n, const float* __restrict__ w,

@@ -829,13 +829,13 @@ sg_status sg_surrogate_train_step(sg_surrogate* s, const float* q, const float* 
   s->t += 1;
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - powf(b1, (float)s->t), c2 = 1.f - powf(b2, (float)s->t);
-  for (int l = 0; l < kSL && e == hipSuccess; ++l) {
-    const int nw = s_out(l) * s_in(l), nb = s_out(l);
-    k_adam<<<(nw + 255) / 256, 256, 0, c->stream>>>(nw, s->Wm[l], s->gW[l], s->mW[l], s->vW[l], lr, b1, b2, 1e-8f, c1,
-                                                     c2, s->Wb[l]);
-    k_adam<<<(nb + 255) / 256, 256, 0, c->stream>>>(nb, s->bm[l], s->gb[l], s->mb[l], s->vb[l], lr, b1, b2, 1e-8f, c1,
-                                                     c2, nullptr);
+  static_assert(2 * kSL <= kAdamSegs, "one Adam launch covers every layer");
+  AdamSegs segs{};
+  for (int l = 0; l < kSL; ++l) {
+    adam_add(segs, s->Wm[l], s->gW[l], s->mW[l], s->vW[l], s->Wb[l], s_out(l) * s_in(l));
+    adam_add(segs, s->bm[l], s->gb[l], s->mb[l], s->vb[l], nullptr, s_out(l));
   }
+  if (e == hipSuccess) k_adam_segs<<<segs.blocks, 256, 0, c->stream>>>(segs, lr, b1, b2, 1e-8f, c1, c2);
   if (e == hipSuccess)
     k_pack<<<dim3(16 * 8, kSL), 64, 0, c->stream>>>(s->Wb[0], s->Wb[1], s->Wb[2], s->Wb[3], s->img);
   if (e == hipSuccess && loss) k_copy_f<<<1, 256, 0, c->stream>>>(s->loss, loss, 1);
