@@ -296,7 +296,9 @@ sg_status sg_gae(sg_ctx* ctx, int32_t T, int32_t n, const float* rew, const floa
  * max(|tau~|, 1e-3) <= threshold, else the env is solved exactly (ABA).
  * Training samples are device arrays q, qd, tau, qdd [J][n_total] float32 and
  * env [n_total] int32 (the context env whose link parameters apply); a batch
- * selects rows idx [batch] (NULL: the first batch rows). */
+ * selects rows idx [batch] (NULL: the first batch rows). A sample or env id
+ * out of range gives an all-zero feature row and no loss or gradient
+ * contribution (it still counts in the batch size); it is never read. */
 typedef struct sg_surrogate sg_surrogate;
 
 /* Create a surrogate bound to ctx (its link parameters, stream and state);
@@ -398,7 +400,9 @@ sg_status sg_ppo_get_params(sg_ppo* ppo, float* params);
 
 /* Gradient of L over one minibatch of `rows` samples of a T-step rollout
  * (sample s = t N + env; idx: DEVICE int32 [rows] sample ids, or NULL for
- * 0..rows-1), with advantages normalised over all T N samples first, the
+ * 0..rows-1; an id outside [0, T N) gives a zero input row and no loss or
+ * gradient contribution, though it counts in the minibatch size), with
+ * advantages normalised over all T N samples first, the
  * entropy term included and no norm clip: grad DEVICE float[P]. stats
  * (DEVICE float[8], may be NULL): loss_pi, loss_v, entropy, approx_kl
  * (mean log pi_old - log pi), clip fraction, |grad|. */
