@@ -296,9 +296,10 @@ sg_status sg_gae(sg_ctx* ctx, int32_t T, int32_t n, const float* rew, const floa
  * max(|tau~|, 1e-3) <= threshold, else the env is solved exactly (ABA).
  * Training samples are device arrays q, qd, tau, qdd [J][n_total] float32 and
  * env [n_total] int32 (the context env whose link parameters apply); a batch
- * selects rows idx [batch] (NULL: the first batch rows). A sample or env id
- * out of range gives an all-zero feature row and no loss or gradient
- * contribution (it still counts in the batch size); it is never read. */
+ * selects rows idx [batch] (NULL: the first batch rows). A sample id out of
+ * range gives an all-zero feature row and no loss or gradient contribution
+ * (it still counts in the batch size); an env id out of range gives an
+ * all-zero feature row. Neither is used to read memory. */
 typedef struct sg_surrogate sg_surrogate;
 
 /* Create a surrogate bound to ctx (its link parameters, stream and state);
