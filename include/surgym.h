@@ -32,7 +32,7 @@
  * Errors: every function returns sg_status. SG_E_INVAL: a null or
  * misaligned pointer, a size out of range; the message is available from
  * sg_last_error(ctx) (or sg_last_error(NULL) after a failed sg_create).
- * SG_E_UNSUPPORTED: a valid request this build does not implement (e.g. a
+ * SG_E_UNSUPPORTED: a valid request the library does not implement (e.g. a
  * rollout on an FP64 context). SG_E_HIP: a HIP runtime error, including an
  * asynchronous fault surfaced at the next call that synchronizes.
  * A context is used by one host thread at a time.
@@ -259,7 +259,7 @@ sg_status sg_tip_position(sg_ctx* ctx, const void* q, void* tip);
  * outputs 0..J-1 are the action mean, output J the critic value.
  * w_bf16: HOST, BF16 bit patterns of W1 [h1][W], W2 [h2][h1], W3 [J+1][h2]
  * concatenated row-major; bias: HOST float32 b1 [h1], b2 [h2], b3 [J+1];
- * log_std: HOST float32 [J]. This build supports h1 = 256, h2 = 128, J <= 7
+ * log_std: HOST float32 [J]. The library supports h1 = 256, h2 = 128, J <= 7
  * (SG_E_UNSUPPORTED otherwise); FP32 contexts only. */
 sg_status sg_set_policy(sg_ctx* ctx, int32_t h1, int32_t h2, const uint16_t* w_bf16, const float* bias,
                         const float* log_std);

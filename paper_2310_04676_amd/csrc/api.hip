@@ -407,7 +407,7 @@ sg_status sg_set_policy(sg_ctx* c, int32_t h1, int32_t h2, const uint16_t* w, co
   if (!w || !b || !log_std) return fail(c, SG_E_INVAL, "sg_set_policy: null argument");
   if (c->dtype != SG_F32) return fail(c, SG_E_UNSUPPORTED, "sg_set_policy: FP32 contexts only");
   if (h1 != 256 || h2 != 128 || c->J > 7)
-    return fail(c, SG_E_UNSUPPORTED, "sg_set_policy: this build supports h1 = 256, h2 = 128, max_dof <= 7");
+    return fail(c, SG_E_UNSUPPORTED, "sg_set_policy: supported are h1 = 256, h2 = 128, max_dof <= 7");
   const int W = 2 * c->J + 10, O = c->J + 1;
   const uint16_t* W1 = w;
   const uint16_t* W2 = W1 + (size_t)h1 * W;

@@ -1,6 +1,6 @@
 // Measured peaks of the device, the denominators a roofline fraction can be
 // quoted against besides the datasheet ones: FP32 VALU FMA issue (with the
-// packed-FP32 instructions this build disables, as every kernel here sees
+// packed-FP32 instructions the library is compiled without, as every kernel sees
 // it) for a full chip and for a wave alone on its SIMD, BF16 matrix-core
 // issue (v_mfma_f32_16x16x32_bf16), and a streaming device-to-device copy.
 #include <hip/hip_runtime.h>

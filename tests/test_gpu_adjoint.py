@@ -44,7 +44,7 @@ def _case(sg, w, T, seed, K):
 def test_adjoint_matches_oracle(sg, kind, N, T, K):
     w = {"path": synth.path_rollout, "psm": synth.psm_like, "mixed": synth.mixed_dof}[kind](N)
     if kind == "mixed":
-        # this build's adjoint covers max_dof <= 7
+        # the adjoint covers max_dof <= 7
         w = synth.Workload("mixed7", synth._round_robot(synth.make_chain(N, np.array([4, 6, 7, 5] * N)[:N], 1003,
                                                                          dt=1 / 120, substeps=4, gain_jitter=True,
                                                                          q0_frac=0.25), np.float32),
