@@ -9,6 +9,9 @@
 * The uneven 4/6/7/9-DOF batch at 16384 envs under every step schedule the
   autotuner times, each step checked for every env against the oracle's
   step from the state the GPU handed over.
+* The surrogate step at 65536 envs: the exact-fallback path against the
+  oracle's step, and the accept/fallback decisions against the oracle's
+  residuals.
 
 Tolerances are those of the smaller parity tests: see test_gpu_rollout.py
 (policy outputs, log-density, GAE, replayed step) and test_gpu_step.py
@@ -104,3 +107,80 @@ def test_mixed_dof_16384_every_schedule(sg, schedule):
         assert np.abs(host(rew) - rw).max() <= qtol * 10, s
         assert np.abs(host(obs) - ob).max() <= qtol * 100 * max(1.0, np.abs(ob).max()), s
     sim.close()
+
+
+def test_surrogate_step_65536_threshold_zero_is_the_oracle_step(sg):
+    """The surrogate step at its 65536-env size with threshold 0: every env
+    takes the exact solve, so each step matches the oracle's step for every
+    env (tolerances of the hand-off step)."""
+    import torch
+    from test_gpu_surrogate import _setup
+    N = 65536
+    w, sim, o, T, _ = _setup(sg, n_env=N)
+    S = sg.Surrogate(sim, 64)
+    W, b = synth.surrogate_init(1)
+    S.set_params(W, b)
+    S.fit_norm(T["q"], T["qd"], T["tau"], T["env"], T["qdd"])
+    nfb = torch.zeros(4, dtype=torch.int32, device="cuda")
+    qtol = 2e-5
+    for s in range(2):
+        q0, qd0, pr0, _ = sim.get_state()
+        a = synth.random_actions(60 + s, N, 7, np.float32).astype(np.float32)
+        obs, rew, done = S.step(torch.from_numpy(a).cuda(), 0.0, n_fallback=nfb)
+        assert np.all(nfb.cpu().numpy() == N)
+        q1, qd1, pr1, _ = sim.get_state()
+        qn, qdn, prn, rw, dn, ob = o.step(a, host(q0), host(qd0), host(pr0).astype(np.int32), threads=THREADS)
+        assert np.array_equal(host(done).astype(np.uint8), dn), s
+        assert np.array_equal(host(pr1).astype(np.int32), prn), s
+        assert (np.abs(host(q1) - qn) / (1 + np.abs(qn))).max() <= qtol, s
+        assert np.abs(host(qd1) - qdn).max() <= qtol * 100 * max(1.0, np.abs(qdn).max()), s
+        assert np.abs(host(rew) - rw).max() <= qtol * 10, s
+        assert np.abs(host(obs) - ob).max() <= qtol * 100 * max(1.0, np.abs(ob).max()), s
+    S.close()
+
+
+def test_surrogate_step_65536_accepts_predictions_and_counts_fallbacks(sg):
+    """One substep at 65536 envs: with an infinite threshold the step
+    integrates the network's prediction (the library's predict call, itself
+    checked against the FP64 network in test_gpu_surrogate.py); with a
+    finite one the fallback count equals the number of envs whose oracle
+    residual of that prediction exceeds it, up to envs within 1e-3 of the
+    threshold."""
+    import torch
+    from test_gpu_surrogate import _setup
+    N = 65536
+    w, sim, o, T, _ = _setup(sg, n_env=N, substeps=1)
+    S = sg.Surrogate(sim, 256)
+    Wt, bt = synth.surrogate_init(2)
+    S.set_params(Wt, bt)
+    S.fit_norm(T["q"], T["qd"], T["tau"], T["env"], T["qdd"])
+    q0, qd0, pr0, _ = sim.get_state()
+    a = synth.random_actions(77, N, 7, np.float32)
+    at = torch.from_numpy(a).float().cuda()
+    h = w.robot.dt
+    tau = w.robot.kp * (a.clip(-1, 1) * w.robot.q_hi - host(q0) - h * host(qd0)) - w.robot.kd * host(qd0)
+    tau32 = torch.from_numpy(tau.astype(np.float32)).cuda()
+    qh = host(S.predict(q0, qd0, tau32, T["env"]))
+    nfb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _, _, done = S.step(at, float("inf"), n_fallback=nfb)
+    assert int(nfb.item()) == 0
+    q1, qd1, _, _ = sim.get_state()
+    qd_ref = host(qd0) + h * qh
+    q_ref = np.clip(host(q0) + h * qd_ref, w.robot.q_lo, w.robot.q_hi)
+    inside = (q_ref < w.robot.q_hi) & (q_ref > w.robot.q_lo) & (done.cpu().numpy() == 0)[None, :]
+    # The step forms tau in FP32 from its own state, the reference in FP64:
+    # features differing in the last bits can flip one BF16 rounding of a
+    # hidden activation (test_gpu_surrogate.py's bound: ~1e-3 on a
+    # normalised output), which moves qd by up to ~1e-3 after the factor h.
+    # Over 455 k coordinates a few such flips occur: bound the tail.
+    d = np.abs(host(qd1)[inside] - qd_ref[inside]) / np.maximum(1.0, np.abs(qd_ref[inside]))
+    assert np.median(d) <= 1e-6, np.median(d)
+    assert d.max() <= 1e-2, d.max()
+    assert (d > 1e-3).mean() <= 1e-4, (d > 1e-3).mean()
+    sim.set_state(q0, qd0, pr0)
+    rel = oracle.residual(o, host(q0), host(qd0), tau, qh, o.drive_armature())
+    thr = float(np.median(rel))
+    S.step(at, thr, n_fallback=nfb)
+    lo, hi = (rel > thr * (1 + 1e-3)).sum(), (rel > thr * (1 - 1e-3)).sum()
+    assert lo <= int(nfb.item()) <= hi, (lo, int(nfb.item()), hi)
+    S.close()
