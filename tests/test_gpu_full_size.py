@@ -12,6 +12,8 @@
 * The surrogate step at 65536 envs: the exact-fallback path against the
   oracle's step, and the accept/fallback decisions against the oracle's
   residuals.
+* The PPO gradient of a 32,768-sample minibatch of a 4096-env T = 32
+  rollout against the oracle's.
 
 Tolerances are those of the smaller parity tests: see test_gpu_rollout.py
 (policy outputs, log-density, GAE, replayed step) and test_gpu_step.py
@@ -184,3 +186,34 @@ def test_surrogate_step_65536_accepts_predictions_and_counts_fallbacks(sg):
     lo, hi = (rel > thr * (1 + 1e-3)).sum(), (rel > thr * (1 - 1e-3)).sum()
     assert lo <= int(nfb.item()) <= hi, (lo, int(nfb.item()), hi)
     S.close()
+
+
+def test_ppo_minibatch_gradient_4096_envs(sg):
+    """The PPO gradient at the benchmark's size: a T = 32 rollout of 4096
+    envs (advantages normalised over all 131,072 samples) and one minibatch
+    of 32,768 sample ids drawn across the whole rollout, the minibatch the
+    timed update uses; statistics and each parameter block's gradient
+    against the oracle's FP64 gradient of the same samples (tolerances of
+    test_gpu_ppo.py)."""
+    import torch
+    from test_gpu_ppo import DIMS, _blocks, _rows, _setup
+    T, N = 32, 4096
+    w, sim, ppo, params, bufs = _setup(sg, N, T)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    bufs["logp"] += 0.3 * torch.randn(bufs["logp"].shape, device="cuda", generator=g)
+    idx = torch.randperm(T * N, device="cuda", generator=g)[:32768].to(torch.int32)
+    gg, st = ppo.grad(bufs, T, idx)
+    h, x, a = _rows(bufs, T, N)
+    an = oracle.ppo_normalise(h["adv"]).ravel()
+    s = idx.cpu().numpy()
+    L, gr, so = oracle.ppo_grad(DIMS, params.astype(np.float64), x[:, s], a[:, s], h["logp"].ravel()[s], an[s],
+                                h["ret"].ravel()[s], h["val"][:T].ravel()[s], emulate=True)
+    st = host(st)
+    for k, name in enumerate(("loss_pi", "loss_v", "entropy", "approx_kl", "clip_frac")):
+        assert abs(st[k] - so[name]) <= 1e-3 * max(1.0, abs(so[name])) + 1e-5, (name, st[k], so[name])
+    assert 0.05 < so["clip_frac"] < 0.95
+    for i, (gb, rb) in enumerate(zip(_blocks(host(gg)), _blocks(gr))):
+        rel = np.linalg.norm(gb - rb) / np.linalg.norm(rb)
+        cos = (gb @ rb) / (np.linalg.norm(gb) * np.linalg.norm(rb))
+        assert rel <= 2e-2 and cos >= 0.999, (i, rel, cos)
+    ppo.close()
