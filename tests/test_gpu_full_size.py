@@ -14,6 +14,8 @@
   residuals.
 * The PPO gradient of a 32,768-sample minibatch of a 4096-env T = 32
   rollout against the oracle's.
+* The prismatic and multi-arm variants through the fused rollout at 4096
+  chains, replayed like the path rollout.
 
 Tolerances are those of the smaller parity tests: see test_gpu_rollout.py
 (policy outputs, log-density, GAE, replayed step) and test_gpu_step.py
@@ -37,7 +39,7 @@ def _sample(N, seed=5, k=384):
     return np.unique(np.concatenate([np.arange(min(64, N)), np.arange(max(N - 64, 0), N), mid]))
 
 
-def _replay_full(sg, w, T, n_rollouts):
+def _replay_full(sg, w, T, n_rollouts, rew_tol=2e-4):
     sim = sg.from_workload(w)
     o = oracle.Oracle(w.robot, w.task, w.policy)
     N, J = w.robot.n_env, w.robot.max_dof
@@ -63,7 +65,7 @@ def _replay_full(sg, w, T, n_rollouts):
             q, qd = obs[t][:J], obs[t][J:2 * J]
             qn, qdn, prn, rw, dn, ob = o.step(act[t], q, qd, prog, threads=THREADS)
             assert np.array_equal(done[t], dn), (r, t)
-            assert np.abs(rew[t] - rw).max() <= 2e-4, (r, t, np.abs(rew[t] - rw).max())
+            assert np.abs(rew[t] - rw).max() <= rew_tol, (r, t, np.abs(rew[t] - rw).max())
             scale = np.maximum(1.0, np.abs(ob))
             assert (np.abs(obs[t + 1] - ob) / scale).max() <= 2e-3, (r, t)
             prog = prn
@@ -84,6 +86,20 @@ def test_path_rollout_4096_two_rollouts(sg):
 
 def test_path_rollout_16384(sg):
     _replay_full(sg, synth.path_rollout(16384), 32, 1)
+
+
+@pytest.mark.parametrize("name", ["prismatic_rrprrr", "multi_arm_2", "multi_arm_4"])
+def test_variant_rollouts_4096_chains(sg, name):
+    """The joint and task variants bench.py times, at its 4096 chains: RRPRRR
+    chains, and 2 or 4 arms per env whose reward is the sum over the env's
+    arms (the reward tolerance scales with the number of summed terms)."""
+    if name == "prismatic_rrprrr":
+        w = synth.psm_like(4096)
+        w.policy = synth.make_policy(w.seed + 7, dims=(22, 256, 128, 7))
+        _replay_full(sg, w, 32, 1)
+    else:
+        C = int(name[-1])
+        _replay_full(sg, synth.multi_arm(4096 // C, chains=C), 32, 1, rew_tol=2e-4 * C)
 
 
 @pytest.mark.parametrize("schedule", ["padded", "sorted", "per_class", "persistent"])
