@@ -14,8 +14,8 @@
   residuals.
 * The PPO gradient of a 32,768-sample minibatch of a 4096-env T = 32
   rollout against the oracle's.
-* The prismatic and multi-arm variants through the fused rollout at 4096
-  chains, replayed like the path rollout.
+* The prismatic, tracking and multi-arm variants through the fused rollout
+  at 4096 chains, replayed like the path rollout.
 
 Tolerances are those of the smaller parity tests: see test_gpu_rollout.py
 (policy outputs, log-density, GAE, replayed step) and test_gpu_step.py
@@ -39,8 +39,10 @@ def _sample(N, seed=5, k=384):
     return np.unique(np.concatenate([np.arange(min(64, N)), np.arange(max(N - 64, 0), N), mid]))
 
 
-def _replay_full(sg, w, T, n_rollouts, rew_tol=2e-4):
+def _replay_full(sg, w, T, n_rollouts, rew_tol=2e-4, track=False):
     sim = sg.from_workload(w)
+    # tracking task: the oracle advances its own copy of the goal state
+    gs = np.ascontiguousarray(host(sim.get_goal_state())) if track else None
     o = oracle.Oracle(w.robot, w.task, w.policy)
     N, J = w.robot.n_env, w.robot.max_dof
     idx = _sample(N)
@@ -63,7 +65,8 @@ def _replay_full(sg, w, T, n_rollouts, rew_tol=2e-4):
             lp = (-0.5 * eps ** 2 - w.policy.log_std[:, None] - 0.5 * np.log(2 * np.pi)).sum(0)
             np.testing.assert_allclose(logp[t], lp, rtol=1e-5, atol=1e-4)
             q, qd = obs[t][:J], obs[t][J:2 * J]
-            qn, qdn, prn, rw, dn, ob = o.step(act[t], q, qd, prog, threads=THREADS)
+            qn, qdn, prn, rw, dn, ob = o.step(act[t], q, qd, prog, threads=THREADS, goal_state=gs, seed=w.seed,
+                                              step=step0 + t)
             assert np.array_equal(done[t], dn), (r, t)
             assert np.abs(rew[t] - rw).max() <= rew_tol, (r, t, np.abs(rew[t] - rw).max())
             scale = np.maximum(1.0, np.abs(ob))
@@ -75,6 +78,8 @@ def _replay_full(sg, w, T, n_rollouts, rew_tol=2e-4):
         step0 += T
     q, qd, pr, rs = sim.get_state()
     assert rs == step0
+    if track:
+        assert np.abs(host(sim.get_goal_state()) - gs).max() <= 2e-6
     np.testing.assert_array_equal(host(q), obs[T][:J])
     np.testing.assert_array_equal(pr.cpu().numpy(), prog)
     sim.close()
@@ -88,15 +93,19 @@ def test_path_rollout_16384(sg):
     _replay_full(sg, synth.path_rollout(16384), 32, 1)
 
 
-@pytest.mark.parametrize("name", ["prismatic_rrprrr", "multi_arm_2", "multi_arm_4"])
+@pytest.mark.parametrize("name", ["prismatic_rrprrr", "tracking", "multi_arm_2", "multi_arm_4"])
 def test_variant_rollouts_4096_chains(sg, name):
     """The joint and task variants bench.py times, at its 4096 chains: RRPRRR
-    chains, and 2 or 4 arms per env whose reward is the sum over the env's
-    arms (the reward tolerance scales with the number of summed terms)."""
+    chains, active tracking (two rollouts; the oracle draws the goal walk and
+    re-draws from the same counters), and 2 or 4 arms per env whose reward is
+    the sum over the env's arms (the reward tolerance scales with the number
+    of summed terms)."""
     if name == "prismatic_rrprrr":
         w = synth.psm_like(4096)
         w.policy = synth.make_policy(w.seed + 7, dims=(22, 256, 128, 7))
         _replay_full(sg, w, 32, 1)
+    elif name == "tracking":
+        _replay_full(sg, synth.tracking(4096), 32, 2, track=True)
     else:
         C = int(name[-1])
         _replay_full(sg, synth.multi_arm(4096 // C, chains=C), 32, 1, rew_tol=2e-4 * C)
