@@ -277,7 +277,7 @@ static inline SumJob partial_rows(const float* part, int blocks, int cols, int s
 
 // dst[i] = src[i] (a kernel rather than a copy node, so callers stay
 // capturable).
-static __global__ void __launch_bounds__(256) k_copy_f(const float* __restrict__ src, float* __restrict__ dst, int n) {
+static __global__ void __launch_bounds__(256) __attribute__((unused)) k_copy_f(const float* __restrict__ src, float* __restrict__ dst, int n) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) dst[i] = src[i];
 }
@@ -304,7 +304,7 @@ static inline void adam_add(AdamSegs& a, float* w, const float* g, float* m, flo
   a.blocks += (n + 255) / 256;
   a.count += 1;
 }
-static __global__ void __launch_bounds__(256) k_adam_segs(AdamSegs a, float lr, float b1, float b2, float eps, float c1,
+static __global__ void __launch_bounds__(256) __attribute__((unused)) k_adam_segs(AdamSegs a, float lr, float b1, float b2, float eps, float c1,
                                                           float c2) {
   int k = 0;
   while (k + 1 < a.count && (int)blockIdx.x >= a.s[k + 1].blk0) ++k;

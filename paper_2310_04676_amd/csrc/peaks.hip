@@ -75,15 +75,16 @@ extern "C" sg_status sg_measure_peaks(double* fp32_fma_tflops, double* fp32_fma_
   // eight 256-thread blocks per CU: two waves per SIMD
   const int blocks = 8 * (n_cu > 0 ? n_cu : 256);
   float ms = 0.f;
+  // average milliseconds per launch; a HIP error is kept in e
   auto timed = [&](auto launch, int reps) -> float {
     launch();  // warm-up
-    hipEventRecord(e0, nullptr);
-    for (int r = 0; r < reps; ++r) launch();
-    hipEventRecord(e1, nullptr);
-    hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
     float t = 0.f;
-    hipEventElapsedTime(&t, e0, e1);
-    return t / reps;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    return e == hipSuccess && t > 0.f ? t / reps : 1.f;
   };
   if (e == hipSuccess) {
     const int iters = 4096;
@@ -100,7 +101,7 @@ extern "C" sg_status sg_measure_peaks(double* fp32_fma_tflops, double* fp32_fma_
     const size_t n4 = copy_bytes / 16;
     ms = timed([&] { sgk::k_peak_copy<<<blocks, 256>>>((const float4*)src, (float4*)dst, n4); }, 5);
     *copy_gbps = 2.0 * copy_bytes / (ms * 1e-3) / 1e9;
-    e = hipGetLastError();
+    if (e == hipSuccess) e = hipGetLastError();
   }
   void* ptrs[] = {sink, src, dst};
   for (void* p : ptrs)

@@ -129,7 +129,7 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
   red[threadIdx.x] = v;
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
   return red[0];
@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(256) k_gnorm_part(float* __restrict__ g, int P
   red[threadIdx.x] = s;
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
   if (threadIdx.x == 0) gpart[blockIdx.x] = red[0];

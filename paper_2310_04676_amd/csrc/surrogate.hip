@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(256) k_rowstats(const float* __restrict__ x, i
   s2[threadIdx.x] = b;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
       s1[threadIdx.x] += s1[threadIdx.x + w];
       s2[threadIdx.x] += s2[threadIdx.x + w];
     }
