@@ -2,7 +2,9 @@
 maximum of 16 joints (uniform and per-env joint counts, FP32 and FP64)
 against the FP64 oracle; invalid sizes rejected at create; the control step
 captured in a HIP graph and replayed, each replay checked against the same
-step run eagerly."""
+step run eagerly; the measured device rates; degenerate dynamics (no drive,
+no gravity: exactly at rest) and the joint-limit property at the uneven
+batch's full size."""
 import numpy as np
 import pytest
 
@@ -108,3 +110,51 @@ def test_measured_peaks_are_sane(sg):
     assert pk["bf16_mfma_tflops"] < 2500 * 1.05
     assert pk["copy_gbps"] < 8000 * 1.05
     assert pk["fp32_fma_wave_gflops"] * 1e-3 < pk["fp32_fma_tflops"]
+
+
+def test_undriven_chain_without_gravity_stays_at_rest(sg):
+    """Degenerate dynamics: no gravity and zero PD gains, at rest. Every bias
+    and drive term is exactly zero, so ABA returns exactly zero accelerations
+    and the state must not move at all, whatever the actions (ragged 300
+    envs, mixed joint counts)."""
+    import torch
+    N = 300
+    n_dof = np.array([(k % 7) + 1 for k in range(N)])
+    r = synth.make_chain(N, n_dof, 77, dt=1 / 120, substeps=4, max_dof=7, q0_frac=0.3)
+    r.kp[:] = 0.0
+    r.kd[:] = 0.0
+    r.gravity = (0.0, 0.0, 0.0)
+    tgt = (synth.WORK_CENTRE[None, :] + synth.stream(77, "tg").uniform(-0.25, 0.25, (N, 3))).T.copy()
+    t = synth.Task(task=synth.TASK_REACH, target=tgt, waypoints=None, dwell=1, ep_len=1000,
+                   progress0=np.zeros(N, dtype=np.int32))
+    w = synth.Workload("rest", synth._round_robot(r, np.float32), synth._round_task(t, np.float32), None,
+                       np.float32, 77)
+    sim = sg.Sim(w.robot, w.task)
+    q0, qd0, _, _ = sim.get_state()
+    for s in range(5):
+        a = torch.from_numpy(synth.random_actions(500 + s, N, 7, np.float32).astype(np.float32)).cuda()
+        sim.step(a)
+    q1, qd1, _, _ = sim.get_state()
+    assert torch.equal(q1, q0)
+    assert torch.count_nonzero(qd1).item() == 0
+    assert torch.count_nonzero(qd0).item() == 0
+
+
+def test_mixed_batch_stays_within_limits(sg):
+    """Property at the uneven batch's full size, any schedule: after every
+    step each joint lies within its limits (compared in the context's FP32)
+    and every observation is finite."""
+    import torch
+    w = synth.mixed_dof(16384)
+    lo = torch.from_numpy(w.robot.q_lo.astype(np.float32)).cuda()
+    hi = torch.from_numpy(w.robot.q_hi.astype(np.float32)).cuda()
+    for sched in (sg.SG_SCHED_PADDED, sg.SG_SCHED_SORTED):
+        sim = sg.Sim(w.robot, w.task)
+        sim.set_schedule(sched)
+        for s in range(10):
+            a = torch.from_numpy(synth.random_actions(600 + s, 16384, 9, np.float32).astype(np.float32)).cuda()
+            obs, _, _ = sim.step(a)
+            q, _, _, _ = sim.get_state()
+            assert bool(((q >= lo) & (q <= hi)).all()), (sched, s)
+            assert bool(torch.isfinite(obs).all()), (sched, s)
+        sim.close()
