@@ -62,18 +62,31 @@ struct GemmArgs {
 
 template <int EPI, bool AT, bool BT, int ACT>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-  __shared__ __align__(16) uint16_t As[64][40];  // 32 k + 8 pad
+  // LDS tiles [row][k], 32 k + 8 pad; the four 8-k blocks of a row are
+  // stored XOR-swizzled by (row / 8) mod 4, which spreads the transposing
+  // stores below (one column of eight rows 8 apart per instruction) over
+  // four banks instead of one
+  __shared__ __align__(16) uint16_t As[64][40];
   __shared__ __align__(16) uint16_t Bs[64][40];
+  auto swz = [](int row, int kb) { return (kb ^ ((row >> 3) & 3)) * 8; };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  // Tile coordinates. Work-groups go to the 8 XCDs round-robin by linear id;
+  // the remap hands each XCD a contiguous range of tiles (x fastest), so the
+  // tiles that share a row slab (and a K-chunk) run on one XCD and re-read
+  // it from that XCD's L2 instead of across the fabric.
+  const int gx = gridDim.x, gy = gridDim.y, nblk = gx * gy * gridDim.z;
+  int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if ((nblk & 7) == 0) lin = (lin & 7) * (nblk >> 3) + (lin >> 3);
+  const int bx = lin % gx, by = (lin / gx) % gy, bz = lin / (gx * gy);
+  const int m0 = by * 64, n0 = bx * 64;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int gi = lane >> 4, li = lane & 15;
   int kbeg = 0, kend = g.K;
   float* C = g.C;
   if (EPI == EPI_PARTIAL) {
-    kbeg = blockIdx.z * g.kchunk;
+    kbeg = bz * g.kchunk;
     kend = min(g.K, kbeg + g.kchunk);
-    C += (size_t)blockIdx.z * g.M * g.ldc;
+    C += (size_t)bz * g.M * g.ldc;
   }
   f32x4 acc[2][2];
 #pragma unroll
@@ -119,12 +132,12 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   };
   auto stash = [&](uint16_t (*S)[40], bool trans, const uint4& v) {
     if (!trans) {
-      *reinterpret_cast<uint4*>(&S[lr][lk]) = v;
+      *reinterpret_cast<uint4*>(&S[lr][swz(lr, lk >> 3)]) = v;
     } else {
       uint16_t t[8];
       *reinterpret_cast<uint4*>(t) = v;
 #pragma unroll
-      for (int s = 0; s < 8; ++s) S[tm + s][tk] = t[s];
+      for (int s = 0; s < 8; ++s) S[tm + s][swz(tm, tk >> 3) + (tk & 7)] = t[s];
     }
   };
   uint4 ra = fetch(g.A, g.lda, avec, g.M, m0, AT, kbeg);
@@ -140,8 +153,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     bf16x8 af[2], bfr[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      af[t] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * t + li][8 * gi]);
-      bfr[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * t + li][8 * gi]);
+      af[t] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * t + li][swz(wm + 16 * t + li, gi)]);
+      bfr[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * t + li][swz(wn + 16 * t + li, gi)]);
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -182,7 +195,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     __syncthreads();
     if (tid < 64) {
       const int n = n0 + tid;
-      if (n < g.N) g.colpart[(size_t)blockIdx.y * g.N + n] = csum[0][tid >> 5][tid & 31] + csum[1][tid >> 5][tid & 31];
+      if (n < g.N) g.colpart[(size_t)by * g.N + n] = csum[0][tid >> 5][tid & 31] + csum[1][tid >> 5][tid & 31];
     }
   }
 }

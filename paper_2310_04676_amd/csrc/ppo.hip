@@ -18,9 +18,10 @@
 //                  is the reduction axis); every partial is summed in a
 //                  fixed order -- deterministic; each split sum shares its
 //                  launch with a bias gradient's sum (k_sum_two)
-//   k_gnorm_part   entropy term and per-block sums of squares of the
-//                  gradient; k_ppo_finish: the global norm and statistics
-//   k_ppo_adam     norm clip + Adam on the FP32 master weights + BF16 copy
+//   k_ppo_norm_adam  entropy term, global gradient norm, statistics, norm
+//                  clip and Adam on the FP32 master weights + BF16 copy, in
+//                  one launch (sg_ppo_grad: k_gnorm_part and k_ppo_finish
+//                  give the norm and statistics without the Adam step)
 // After an update k_ppo_pack rewrites the context's rollout weight image
 // (the MFMA fragment order of mlp.hpp), biases and log_std from the master
 // weights, so the next rollout samples from the updated policy.
@@ -294,22 +295,21 @@ __global__ void __launch_bounds__(256) k_gnorm_part(float* __restrict__ g, int P
   if (threadIdx.x == 0) gpart[blockIdx.x] = red[0];
 }
 
-// |g| from the partial sums into scal[2]; with stats, the minibatch's loss
-// statistics (block sums of k_ppo_loss), entropy and |g| added with weight
-// w. One block; every sum in a fixed order.
-__global__ void __launch_bounds__(256) k_ppo_finish(const double* __restrict__ gpart, int nb,
-                                                    const float* __restrict__ lpart, int lb,
-                                                    const float* __restrict__ ls, int J, float* __restrict__ scal,
-                                                    float* __restrict__ stats, float w) {
+// Block-wide: the minibatch's loss statistics (block sums of k_ppo_loss,
+// in a fixed order), entropy and the gradient norm n, added to stats with
+// weight w.
+__device__ void add_stats(const float* __restrict__ lpart, int lb, const float* __restrict__ ls, int J, float n,
+                          float* __restrict__ stats, float w) {
   __shared__ double red[4][256];
   const int t = threadIdx.x;
-  double v[4] = {0, 0, 0, 0};
-  if (stats)
+  if (t < 256) {  // the first 256 threads sum; the others only meet the barriers
+    double v[4] = {0, 0, 0, 0};
     for (int b = t; b < lb; b += 256)
 #pragma unroll
       for (int k = 0; k < 4; ++k) v[k] += lpart[(size_t)b * kLossPart + 16 + k];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) red[k][t] = v[k];
+    for (int k = 0; k < 4; ++k) red[k][t] = v[k];
+  }
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (t < s)
@@ -318,33 +318,38 @@ __global__ void __launch_bounds__(256) k_ppo_finish(const double* __restrict__ g
     __syncthreads();
   }
   if (t == 0) {
-    double q = 0;
-    for (int b = 0; b < nb; ++b) q += gpart[b];
-    const float n = (float)sqrt(q);
-    scal[2] = n;
-    if (stats) {
-      float H = 0.f;
-      for (int j = 0; j < J; ++j) H += ls[j] + 0.5f + 0.91893853320467274f;
-      stats[0] += (float)red[0][0];
-      stats[1] += (float)red[1][0];
-      stats[2] += H * w;
-      stats[3] += (float)red[2][0];
-      stats[4] += (float)red[3][0];
-      stats[5] += n * w;
-    }
+    float H = 0.f;
+    for (int j = 0; j < J; ++j) H += ls[j] + 0.5f + 0.91893853320467274f;
+    stats[0] += (float)red[0][0];
+    stats[1] += (float)red[1][0];
+    stats[2] += H * w;
+    stats[3] += (float)red[2][0];
+    stats[4] += (float)red[3][0];
+    stats[5] += n * w;
   }
 }
 
-// g <- g min(1, max_norm / (|g| + 1e-6)) (no clip for max_norm <= 0), then
-// Adam; BF16 copy of every updated parameter.
-__global__ void __launch_bounds__(256) k_ppo_adam(int P, float* __restrict__ p, const float* __restrict__ g,
-                                                  float* __restrict__ m, float* __restrict__ v,
-                                                  const float* __restrict__ scal, float max_norm, float lr, float b1,
-                                                  float b2, float eps, float c1, float c2, uint16_t* __restrict__ pb) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= P) return;
-  const float coef = max_norm > 0.f ? fminf(1.f, max_norm / (scal[2] + 1e-6f)) : 1.f;
-  const float gi = g[i] * coef;
+// |g| from the partial sums of k_gnorm_part into scal[2]; with stats, the
+// statistics of add_stats. One block.
+__global__ void __launch_bounds__(256) k_ppo_finish(const double* __restrict__ gpart, int nb,
+                                                    const float* __restrict__ lpart, int lb,
+                                                    const float* __restrict__ ls, int J, float* __restrict__ scal,
+                                                    float* __restrict__ stats, float w) {
+  __shared__ float nsh;
+  if (threadIdx.x == 0) {
+    double q = 0;
+    for (int b = 0; b < nb; ++b) q += gpart[b];
+    nsh = (float)sqrt(q);
+    scal[2] = nsh;
+  }
+  __syncthreads();
+  if (stats) add_stats(lpart, lb, ls, J, nsh, stats, w);
+}
+
+__device__ __forceinline__ void adam_one(int i, float gi, float coef, float* __restrict__ p, float* __restrict__ m,
+                                         float* __restrict__ v, float lr, float b1, float b2, float eps, float c1,
+                                         float c2, uint16_t* __restrict__ pb) {
+  gi *= coef;
   const float mi = b1 * m[i] + (1.f - b1) * gi;
   const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
   m[i] = mi;
@@ -352,6 +357,84 @@ __global__ void __launch_bounds__(256) k_ppo_adam(int P, float* __restrict__ p, 
   const float wi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
   p[i] = wi;
   pb[i] = bf16_bits(wi);
+}
+
+__device__ __forceinline__ float clip_coef(float max_norm, float n) {
+  return max_norm > 0.f ? fminf(1.f, max_norm / (n + 1e-6f)) : 1.f;
+}
+
+struct NormAdamArgs {
+  int P, ls0, J;
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  uint16_t* pb;
+  float* scal;
+  float c_e, max_norm, lr, b1, b2, eps, c1, c2;
+  const float* lpart;
+  int lb;
+  float* stats;
+  float w;
+};
+
+constexpr int kNormAdamThreads = 1024;  // threads per k_ppo_norm_adam block = parameters it updates
+
+// The step after a minibatch gradient in one launch (the norm and
+// statistics of k_gnorm_part and k_ppo_finish, then Adam): every block sums the squares of the
+// whole gradient (entropy term on the log_std entries included) in the same
+// fixed order, so each holds the same |g| without a grid-wide barrier, then
+// clips and applies Adam to its own kNormAdamThreads parameters. The log_std
+// entries (the last J parameters) all belong to the block whose range holds
+// the first of them: it stores |g| in scal[2] and adds the statistics
+// (which read log_std) before it updates them, and no other block writes
+// them.
+__global__ void __launch_bounds__(kNormAdamThreads) k_ppo_norm_adam(NormAdamArgs a) {
+  constexpr int NT = kNormAdamThreads, NL = 16;
+  __shared__ double red[NT];
+  __shared__ float nsh;
+  const int t = threadIdx.x;
+  // entries below ls0 as 16-byte vectors, NL loads in flight per thread;
+  // the rest (at most 3 + J entries) one per thread
+  double s = 0;
+  const int n4 = a.ls0 >> 2;
+  const float4* g4 = reinterpret_cast<const float4*>(a.g);
+  for (int base = 0; base < n4; base += NL * NT) {
+    float4 x[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int i4 = base + u * NT + t;
+      x[u] = i4 < n4 ? g4[i4] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u)
+      s += ((double)x[u].x * x[u].x + (double)x[u].y * x[u].y) + ((double)x[u].z * x[u].z + (double)x[u].w * x[u].w);
+  }
+  for (int i = 4 * n4 + t; i < a.P; i += NT) {
+    float gi = a.g[i];
+    if (i >= a.ls0) gi -= a.c_e;
+    s += (double)gi * gi;
+  }
+  red[t] = s;
+  __syncthreads();
+  for (int k = NT / 2; k > 0; k >>= 1) {
+    if (t < k) red[t] += red[t + k];
+    __syncthreads();
+  }
+  if (t == 0) nsh = (float)sqrt(red[0]);
+  __syncthreads();
+  const float n = nsh;
+  const float coef = clip_coef(a.max_norm, n);
+  const int i0 = blockIdx.x * NT;
+  const int i = i0 + t;
+  if (i < a.ls0) adam_one(i, a.g[i], coef, a.p, a.m, a.v, a.lr, a.b1, a.b2, a.eps, a.c1, a.c2, a.pb);
+  if (a.ls0 >= i0 && a.ls0 < i0 + NT) {
+    if (t == 0) a.scal[2] = n;
+    if (a.stats) add_stats(a.lpart, a.lb, a.p + a.ls0, a.J, n, a.stats, a.w);
+    __syncthreads();
+    for (int j = a.ls0 + t; j < a.ls0 + a.J; j += NT)
+      adam_one(j, a.g[j] - a.c_e, coef, a.p, a.m, a.v, a.lr, a.b1, a.b2, a.eps, a.c1, a.c2, a.pb);
+  }
 }
 
 // Rollout weight image (fragment order of mlp.hpp; see sg_set_policy),
@@ -403,9 +486,11 @@ static void weight_grad(sg_ppo* o, hipStream_t st, int M, int N, int K, const ui
   launch_weight_grad<ACT_TANH>(st, M, N, K, A, lda, B, ldb, out, ldo, o->ws, bias);
 }
 
-// Gradient of one minibatch into o->g (entropy term included, no clip).
+// Gradient of one minibatch into o->g. With `finish`, the entropy term is
+// added to o->g, its norm goes to scal[2] and the statistics (weight
+// w_stats) to stats; without, k_ppo_norm_adam does both next.
 static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_config* cfg, float w_stats,
-                                 float* stats) {
+                                 float* stats, bool finish) {
   sg_ctx* c = o->ctx;
   hipStream_t st = c->stream;
   const int B = rows.rows, W = o->W, O = o->O, J = o->J;
@@ -447,9 +532,11 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
   launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
   weight_grad(o, st, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->off[0], W,
                            partial_rows(o->cpart, rb, kH1, kH1, o->g + o->off[1]));
-  const int nb = (o->P + kGnormChunk - 1) / kGnormChunk;
-  k_gnorm_part<<<nb, 256, 0, st>>>(o->g, o->P, o->off[6], J, cfg->entropy_coef, o->gpart);
-  k_ppo_finish<<<1, 256, 0, st>>>(o->gpart, nb, o->lpart, gb, o->p + o->off[6], J, o->scal, stats, w_stats);
+  if (finish) {
+    const int nb = (o->P + kGnormChunk - 1) / kGnormChunk;
+    k_gnorm_part<<<nb, 256, 0, st>>>(o->g, o->P, o->off[6], J, cfg->entropy_coef, o->gpart);
+    k_ppo_finish<<<1, 256, 0, st>>>(o->gpart, nb, o->lpart, gb, o->p + o->off[6], J, o->scal, stats, w_stats);
+  }
   return hipGetLastError();
 }
 
@@ -615,7 +702,7 @@ sg_status sg_ppo_grad(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const int3
   r.idx = idx;
   r.r0 = 0;
   r.rows = rows;
-  if (e == hipSuccess) e = minibatch_grad(o, r, cfg, 1.f, stats);
+  if (e == hipSuccess) e = minibatch_grad(o, r, cfg, 1.f, stats, true);
   if (e == hipSuccess)
     e = hipMemcpyAsync(grad, o->g, (size_t)o->P * sizeof(float), hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) {
@@ -649,13 +736,18 @@ sg_status sg_ppo_update(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const sg
         r.idx = nullptr;
         r.r0 = k * mb;
       }
-      e = minibatch_grad(o, r, cfg, w, stats);
+      e = minibatch_grad(o, r, cfg, w, stats, false);
       if (e != hipSuccess) break;
       o->t += 1;
-      const float c1 = 1.f - (float)std::pow((double)cfg->beta1, o->t);
-      const float c2 = 1.f - (float)std::pow((double)cfg->beta2, o->t);
-      k_ppo_adam<<<(o->P + 255) / 256, 256, 0, st>>>(o->P, o->p, o->g, o->m, o->v, o->scal, cfg->max_grad_norm,
-                                                     cfg->lr, cfg->beta1, cfg->beta2, cfg->adam_eps, c1, c2, o->pb);
+      NormAdamArgs na;
+      na.P = o->P; na.ls0 = o->off[6]; na.J = o->J;
+      na.p = o->p; na.g = o->g; na.m = o->m; na.v = o->v; na.pb = o->pb; na.scal = o->scal;
+      na.c_e = cfg->entropy_coef; na.max_norm = cfg->max_grad_norm; na.lr = cfg->lr;
+      na.b1 = cfg->beta1; na.b2 = cfg->beta2; na.eps = cfg->adam_eps;
+      na.c1 = 1.f - (float)std::pow((double)cfg->beta1, o->t);
+      na.c2 = 1.f - (float)std::pow((double)cfg->beta2, o->t);
+      na.lpart = o->lpart; na.lb = (mb + 255) / 256; na.stats = stats; na.w = w;
+      k_ppo_norm_adam<<<(o->P + kNormAdamThreads - 1) / kNormAdamThreads, kNormAdamThreads, 0, st>>>(na);
       e = hipGetLastError();
     }
   }
