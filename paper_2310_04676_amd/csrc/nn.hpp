@@ -34,12 +34,17 @@ template <int ACT> __device__ __forceinline__ float act_grad(float z) {
 // C[m][n] = sum_k A(m, k) B(k, n) (+ epilogue), BF16 inputs, FP32
 // accumulation. A(m, k) = A[AT ? k*lda + m : m*lda + k],
 // B(k, n) = B[BT ? n*ldb + k : k*ldb + n]. Epilogues:
-//   EPI_FWD_HIDDEN  z + bias -> C (FP32), act(z) -> Cb (BF16)
+//   EPI_FWD_HIDDEN  z + bias -> C (FP32, if non-null), act(z) -> Cb (BF16)
 //   EPI_FWD_OUT     z + bias -> C
 //   EPI_PLAIN       z -> C
 //   EPI_BWD_DX      z act'(Zp) -> C (if non-null) and Cb (backward through
 //                   the unit); with colpart, the column sums of the block's
-//                   64 rows as well (bias gradients without a second pass)
+//                   64 rows as well (bias gradients without a second pass).
+//                   Without Zp the pre-activations are recomputed from the
+//                   forward's own operands (RA RB^T + rbias): the same MFMAs
+//                   on the same BF16 data give the forward's FP32 values
+//                   exactly, and for a narrow input layer this is cheaper
+//                   than storing and re-reading them
 //   EPI_PARTIAL     block z of the grid sums K in [z kchunk, (z+1) kchunk)
 //                   and writes its partial to C + z M ldc (split-K; reduce
 //                   with k_sum_two)
@@ -56,12 +61,19 @@ struct GemmArgs {
   const float* bias; // [N] (forward)
   uint16_t* Cb;      // bf16 output [M][ldc] (act(z) forward, gradient backward)
   const float* Zp;   // pre-activations of the previous layer [M][ldc] (backward data)
+  const uint16_t* RA;  // EPI_BWD_DX without Zp: the forward's A [M][rlda],
+  int rlda;            // B [N][rldb] (row n = unit n), RK inputs, and bias
+  const uint16_t* RB;
+  int rldb, RK;
+  const float* rbias;
   int kchunk;        // split-K chunk (multiple of 32)
   float* colpart;    // EPI_BWD_DX: per-block column sums of the result [gridDim.y][N] (may be null)
 };
 
+// At most 64 VGPRs (8 waves per SIMD), so 8 blocks fit on a CU: the wide
+// forward and data-gradient GEMMs launch 8 blocks per CU.
 template <int EPI, bool AT, bool BT, int ACT>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+__global__ void __launch_bounds__(256, 8) k_gemm(GemmArgs g) {
   // LDS tiles [row][k], 32 k + 8 pad; the four 8-k blocks of a row are
   // stored XOR-swizzled by (row / 8) mod 4, which spreads the transposing
   // stores below (one column of eight rows 8 apart per instruction) over
@@ -140,13 +152,30 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       for (int s = 0; s < 8; ++s) S[tm + s][swz(tm, tk >> 3) + (tk & 7)] = t[s];
     }
   };
+  // The split-K weight gradients (long K loops, two blocks per CU) keep two
+  // slices in flight: slice k0 is stashed while k0 + 32 is loading and
+  // k0 + 64 is requested (a slice at or past kend loads as zeros). The
+  // other GEMMs (K <= 256, eight blocks per CU) prefetch one.
+  constexpr bool kPF2 = EPI == EPI_PARTIAL;
   uint4 ra = fetch(g.A, g.lda, avec, g.M, m0, AT, kbeg);
   uint4 rb = fetch(g.B, g.ldb, bvec, g.N, n0, !BT, kbeg);
+  uint4 ra2 = make_uint4(0, 0, 0, 0), rb2 = make_uint4(0, 0, 0, 0);
+  if (kPF2) {
+    ra2 = fetch(g.A, g.lda, avec, g.M, m0, AT, kbeg + 32);
+    rb2 = fetch(g.B, g.ldb, bvec, g.N, n0, !BT, kbeg + 32);
+  }
   for (int k0 = kbeg; k0 < kend; k0 += 32) {
     stash(As, AT, ra);
     stash(Bs, !BT, rb);
     __syncthreads();
-    if (k0 + 32 < kend) {
+    if (kPF2) {
+      ra = ra2;
+      rb = rb2;
+      if (k0 + 64 < kend) {
+        ra2 = fetch(g.A, g.lda, avec, g.M, m0, AT, k0 + 64);
+        rb2 = fetch(g.B, g.ldb, bvec, g.N, n0, !BT, k0 + 64);
+      }
+    } else if (k0 + 32 < kend) {
       ra = fetch(g.A, g.lda, avec, g.M, m0, AT, k0 + 32);
       rb = fetch(g.B, g.ldb, bvec, g.N, n0, !BT, k0 + 32);
     }
@@ -162,6 +191,33 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x32(af[a], bfr[b], acc[a][b]);
     __syncthreads();
   }
+  f32x4 zr[2][2];  // EPI_BWD_DX without Zp: recomputed pre-activations
+  if (EPI == EPI_BWD_DX && !g.Zp) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) zr[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    kend = g.RK;
+    const bool rav = (((uintptr_t)g.RA) & 15) == 0 && (g.rlda & 7) == 0;
+    const bool rbv = (((uintptr_t)g.RB) & 15) == 0 && (g.rldb & 7) == 0;
+    for (int k0 = 0; k0 < g.RK; k0 += 32) {
+      // the tiles are free: the main loop ended on a barrier
+      stash(As, false, fetch(g.RA, g.rlda, rav, g.M, m0, false, k0));
+      stash(Bs, false, fetch(g.RB, g.rldb, rbv, g.N, n0, false, k0));
+      __syncthreads();
+      bf16x8 af[2], bfr[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        af[t] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * t + li][swz(wm + 16 * t + li, gi)]);
+        bfr[t] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * t + li][swz(wn + 16 * t + li, gi)]);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) zr[a][b] = mfma16x16x32(af[a], bfr[b], zr[a][b]);
+      __syncthreads();
+    }
+  }
   float cs[2] = {0.f, 0.f};  // EPI_BWD_DX: this lane's share of two column sums
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -175,10 +231,10 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         float z = acc[a][b][r];
         if (EPI == EPI_FWD_HIDDEN || EPI == EPI_FWD_OUT) z += g.bias[n];
         if (EPI == EPI_BWD_DX) {
-          z *= act_grad<ACT>(g.Zp[i]);
+          z *= act_grad<ACT>(g.Zp ? g.Zp[i] : zr[a][b][r] + g.rbias[n]);
           cs[b] += z;
         }
-        if (EPI != EPI_BWD_DX || C) C[i] = z;
+        if ((EPI != EPI_BWD_DX && EPI != EPI_FWD_HIDDEN) || C) C[i] = z;
         if (EPI == EPI_FWD_HIDDEN) g.Cb[i] = bf16_bits(act_f<ACT>(z));
         if (EPI == EPI_BWD_DX) g.Cb[i] = bf16_bits(z);
       }
@@ -252,16 +308,19 @@ static __global__ void __launch_bounds__(256) k_sum_two(SumJob a, int blocks_a, 
 }
 
 // Split-K shape for a weight gradient: about 256 blocks over the output
-// tiles, each summing a chunk (multiple of 32) of the batch.
+// tiles, 512 (two per CU) for batches of 8192 rows and more, where a single
+// block per CU would leave the long K loop waiting on memory latency; each
+// block sums a chunk (multiple of 32) of the batch.
 static inline int splits_for(int tiles, int K) {
-  int s = 256 / (tiles > 0 ? tiles : 1);
+  int s = (K >= 8192 ? 512 : 256) / (tiles > 0 ? tiles : 1);
   const int kmax = (K + 31) / 32;
   if (s > kmax) s = kmax;
   return s < 1 ? 1 : s;
 }
 static inline int chunk_for(int K, int splits) { return ((K + splits - 1) / splits + 31) / 32 * 32; }
-// Floats of split-K partials the helper below may write: 256 tiles x 64 x 64.
-constexpr size_t kWeightGradWs = (size_t)256 * 64 * 64;
+// Floats of split-K partials the helper below may write: at most
+// 512 / tiles splits of tiles x 64 x 64 outputs.
+constexpr size_t kWeightGradWs = (size_t)512 * 64 * 64;
 
 // dW [M][N] (leading dim ldo) = sum_b A(b, m) B(b, n) over a batch of K
 // rows (A [K][lda], B [K][ldb], BF16) with split-K partials in ws

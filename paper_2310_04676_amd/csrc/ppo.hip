@@ -7,8 +7,9 @@
 // advantages, and the observations as sample-major BF16 rows (k_ppo_xall).
 // One minibatch of B samples (rows) taken from the rollout buffers:
 //   k_ppo_gather   the minibatch's rows -> X [B][32]
-//   forward        three BF16 MFMA GEMMs (nn.hpp), tanh units; the
-//                  pre-activations stay in HBM for the backward pass
+//   forward        three BF16 MFMA GEMMs (nn.hpp), tanh units; layer 2's
+//                  pre-activations stay in HBM for the backward pass, layer
+//                  1's (W = 2J + 10 inputs) are recomputed there
 //   k_ppo_loss     ratio, clipped objectives, dL/d(outputs) [B][8] (BF16
 //                  for the GEMMs) and per-block sums of the output-bias and
 //                  log_std gradients and of the loss statistics
@@ -46,8 +47,7 @@ struct sg_ppo {
   float* scal = nullptr;     // [0] adv mean, [1] adv sd, [2] |g|
   uint16_t* X = nullptr;     // [rows][32]
   uint16_t* Xall = nullptr;  // [max_samples][32] sample-major BF16 observations
-  float* Z1 = nullptr;       // [rows][256]
-  uint16_t* H1 = nullptr;
+  uint16_t* H1 = nullptr;    // [rows][256] (layer 1's pre-activations are recomputed, not kept)
   float* Z2 = nullptr;       // [rows][128]
   uint16_t* H2 = nullptr;
   float* Z3 = nullptr;       // [rows][8]
@@ -500,7 +500,7 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
   GemmArgs f{};
   // layer 1: Z1 = X W1^T + b1, H1 = tanh(Z1)
   f.M = B; f.N = kH1; f.K = W; f.A = o->X; f.lda = kPX; f.B = o->pb + o->off[0]; f.ldb = W;
-  f.C = o->Z1; f.ldc = kH1; f.bias = o->p + o->off[1]; f.Cb = o->H1;
+  f.C = nullptr; f.ldc = kH1; f.bias = o->p + o->off[1]; f.Cb = o->H1;
   launch_gemm<EPI_FWD_HIDDEN, false, true, ACT_TANH>(st, f);
   // layer 2
   f.N = kH2; f.K = kH1; f.A = o->H1; f.lda = kH1; f.B = o->pb + o->off[2]; f.ldb = kH1;
@@ -526,9 +526,12 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
   launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
   weight_grad(o, st, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->off[2], kH1,
                            partial_rows(o->cpart, rb, kH2, kH2, o->g + o->off[3]));
-  // dZ1 = (dZ2 W2) * tanh'(Z1), with the column sums of dZ1 (hidden-1 bias)
+  // dZ1 = (dZ2 W2) * tanh'(Z1), with the column sums of dZ1 (hidden-1 bias);
+  // Z1 (W inputs) is recomputed in the epilogue rather than stored
   d.N = kH1; d.K = kH2; d.A = o->D2b; d.lda = kH2; d.B = o->pb + o->off[2]; d.ldb = kH1;
-  d.C = nullptr; d.ldc = kH1; d.Cb = o->D1b; d.Zp = o->Z1; d.colpart = o->cpart;
+  d.C = nullptr; d.ldc = kH1; d.Cb = o->D1b; d.colpart = o->cpart;
+  d.Zp = nullptr;
+  d.RA = o->X; d.rlda = kPX; d.RB = o->pb + o->off[0]; d.rldb = W; d.RK = W; d.rbias = o->p + o->off[1];
   launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
   weight_grad(o, st, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->off[0], W,
                            partial_rows(o->cpart, rb, kH1, kH1, o->g + o->off[1]));
@@ -632,7 +635,6 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   if (e == hipSuccess) e = palloc(o, &o->scal, 8);
   if (e == hipSuccess) e = palloc(o, &o->X, R * kPX);
   if (e == hipSuccess) e = palloc(o, &o->Xall, R * kPX);
-  if (e == hipSuccess) e = palloc(o, &o->Z1, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->H1, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->Z2, R * kH2);
   if (e == hipSuccess) e = palloc(o, &o->H2, R * kH2);
