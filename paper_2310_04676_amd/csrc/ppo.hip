@@ -4,7 +4,9 @@
 // value loss and an entropy bonus).
 //
 // Once per call: advantage mean and standard deviation, the normalised
-// advantages, and the observations as sample-major BF16 rows (k_ppo_xall).
+// advantages, the observations as sample-major BF16 rows and the loss inputs
+// (action, old log-probability, advantage, value, return) as sample-major
+// FP32 rows (k_ppo_xall).
 // One minibatch of B samples (rows) taken from the rollout buffers:
 //   k_ppo_gather   the minibatch's rows -> X [B][32]
 //   forward        three BF16 MFMA GEMMs (nn.hpp), tanh units; layer 2's
@@ -47,6 +49,7 @@ struct sg_ppo {
   float* scal = nullptr;     // [0] adv mean, [1] adv sd, [2] |g|
   uint16_t* X = nullptr;     // [rows][32]
   uint16_t* Xall = nullptr;  // [max_samples][32] sample-major BF16 observations
+  float* Aux = nullptr;      // [max_samples][kAux] sample-major act, logp, adv, value, return
   uint16_t* H1 = nullptr;    // [rows][256] (layer 1's pre-activations are recomputed, not kept)
   float* Z2 = nullptr;       // [rows][128]
   uint16_t* H2 = nullptr;
@@ -65,6 +68,9 @@ struct sg_ppo {
 namespace sgk {
 
 constexpr int kPX = 32;   // padded input width
+// Sample-major per-sample row of the loss inputs: act[0..J), then logp,
+// normalised advantage, old value and return at kAux - 4 .. kAux - 1.
+constexpr int kAux = 12;
 constexpr int kPO = 8;    // padded output width (J + 1 <= 8)
 // k_ppo_loss block row: dL/d(outputs) sums (O columns) then dL/dlog_std
 // sums (J columns), zero to column 16, then the four weighted loss sums.
@@ -80,6 +86,7 @@ struct PpoRows {
   const float* ret;   // [T][N]
   const float* an;    // normalised advantages [T N]
   const uint16_t* xall;  // BF16 observations, sample-major [T N][kPX]
+  const float* aux;      // loss inputs, sample-major [T N][kAux]
   const int* idx;     // sample of row r (null: r0 + r)
   int r0, rows, N, J, W, total;
 };
@@ -89,10 +96,23 @@ __device__ __forceinline__ int ppo_sample(const PpoRows& a, int r) { return a.id
 // The rollout's observations, BF16 and sample-major (one 64-byte row per
 // sample s = t N + e, zero past W), so a minibatch gathers whole rows.
 __global__ void __launch_bounds__(256) k_ppo_xall(const float* __restrict__ obs, int total, int N, int W,
-                                                  uint16_t* __restrict__ xall) {
+                                                  uint16_t* __restrict__ xall, PpoRows r, float* __restrict__ aux) {
   const int s = blockIdx.x * 256 + threadIdx.x;
   if (s >= total) return;
   const int t = s / N, e = s % N;
+  {
+    // the loss inputs of sample s as one 48-byte row
+    float v[kAux];
+#pragma unroll
+    for (int j = 0; j < kAux - 4; ++j) v[j] = j < r.J ? r.act[((size_t)t * r.J + j) * N + e] : 0.f;
+    v[kAux - 4] = r.logp[(size_t)t * N + e];
+    v[kAux - 3] = r.an[s];
+    v[kAux - 2] = r.val[(size_t)t * N + e];
+    v[kAux - 1] = r.ret[(size_t)t * N + e];
+    float4* d = reinterpret_cast<float4*>(aux + (size_t)s * kAux);
+#pragma unroll
+    for (int q = 0; q < kAux / 4; ++q) d[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  }
   uint32_t w[kPX / 2];
 #pragma unroll
   for (int k = 0; k < kPX; k += 2) {
@@ -197,17 +217,24 @@ __global__ void __launch_bounds__(256) k_ppo_loss(PpoLossArgs a) {
     const int s = ppo_sample(R, r);
     const bool ok = s >= 0 && s < R.total;
     if (ok) {
-      const int t = s / R.N, e = s % R.N, J = R.J;
+      const int J = R.J;
       const float* z = a.Z3 + (size_t)r * kPO;
+      float x[kAux];
+      const float4* src = reinterpret_cast<const float4*>(R.aux + (size_t)s * kAux);
+#pragma unroll
+      for (int q = 0; q < kAux / 4; ++q) {
+        const float4 v = src[q];
+        x[4 * q] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
+      }
       float logp = 0.f;
       float u[kPO];
       for (int j = 0; j < J; ++j) {
         const float sig = __expf(a.ls[j]);
-        u[j] = (R.act[((size_t)t * J + j) * R.N + e] - z[j]) / sig;
+        u[j] = (x[j] - z[j]) / sig;
         logp += -0.5f * u[j] * u[j] - a.ls[j] - 0.91893853320467274f;
       }
-      const float lold = R.logp[(size_t)t * R.N + e];
-      const float A = R.an[s];
+      const float lold = x[kAux - 4];
+      const float A = x[kAux - 3];
       const float ratio = __expf(logp - lold);
       const float rc = fminf(fmaxf(ratio, 1.f - a.clip), 1.f + a.clip);
       lpi = -fminf(ratio * A, rc * A);
@@ -220,7 +247,7 @@ __global__ void __launch_bounds__(256) k_ppo_loss(PpoLossArgs a) {
         g[j] = dlogp * u[j] / sig;
         dl[j] = dlogp * (u[j] * u[j] - 1.f);
       }
-      const float V = z[J], vold = R.val[(size_t)t * R.N + e], ret = R.ret[(size_t)t * R.N + e];
+      const float V = z[J], vold = x[kAux - 2], ret = x[kAux - 1];
       const float dv = V - vold;
       const float Vc = vold + fminf(fmaxf(dv, -a.clip), a.clip);
       const float e1 = (V - ret) * (V - ret), e2 = (Vc - ret) * (Vc - ret);
@@ -547,6 +574,7 @@ static PpoRows rows_of(const sg_ppo* o, const sg_rollout_bufs* b, int T) {
   PpoRows r{};
   r.obs = b->obs; r.act = b->act; r.logp = b->logp; r.val = b->val; r.ret = b->ret; r.an = o->an;
   r.xall = o->Xall;
+  r.aux = o->Aux;
   r.N = o->ctx->N; r.J = o->J; r.W = o->W; r.total = T * o->ctx->N;
   return r;
 }
@@ -557,7 +585,9 @@ static hipError_t prepare_batch(sg_ppo* o, const sg_rollout_bufs* b, int n) {
   k_adv_sum<<<kAdvBlocks, 256, 0, st>>>(b->adv, n, o->gpart);
   k_adv_sq<<<kAdvBlocks, 256, 0, st>>>(b->adv, n, o->gpart);
   k_adv_norm<<<(n + 255) / 256, 256, 0, st>>>(b->adv, n, o->gpart, o->an, o->scal);
-  k_ppo_xall<<<(n + 255) / 256, 256, 0, st>>>(b->obs, n, o->ctx->N, o->W, o->Xall);
+  PpoRows r{};
+  r.act = b->act; r.logp = b->logp; r.val = b->val; r.ret = b->ret; r.an = o->an; r.J = o->J;
+  k_ppo_xall<<<(n + 255) / 256, 256, 0, st>>>(b->obs, n, o->ctx->N, o->W, o->Xall, r, o->Aux);
   return hipGetLastError();
 }
 
@@ -635,6 +665,7 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   if (e == hipSuccess) e = palloc(o, &o->scal, 8);
   if (e == hipSuccess) e = palloc(o, &o->X, R * kPX);
   if (e == hipSuccess) e = palloc(o, &o->Xall, R * kPX);
+  if (e == hipSuccess) e = palloc(o, &o->Aux, R * kAux);
   if (e == hipSuccess) e = palloc(o, &o->H1, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->Z2, R * kH2);
   if (e == hipSuccess) e = palloc(o, &o->H2, R * kH2);
