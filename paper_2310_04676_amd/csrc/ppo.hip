@@ -418,7 +418,7 @@ constexpr int kNormAdamThreads = 1024;  // threads per k_ppo_norm_adam block = p
 // them.
 __global__ void __launch_bounds__(kNormAdamThreads) k_ppo_norm_adam(NormAdamArgs a) {
   constexpr int NT = kNormAdamThreads, NL = 16;
-  __shared__ double red[NT];
+  __shared__ double red[NT / 64];
   __shared__ float nsh;
   const int t = threadIdx.x;
   // entries below ls0 as 16-byte vectors, NL loads in flight per thread;
@@ -442,13 +442,17 @@ __global__ void __launch_bounds__(kNormAdamThreads) k_ppo_norm_adam(NormAdamArgs
     if (i >= a.ls0) gi -= a.c_e;
     s += (double)gi * gi;
   }
-  red[t] = s;
+  // wave sums (xor butterfly), then the 16 wave sums in order: every block
+  // adds in the same fixed order
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((t & 63) == 0) red[t >> 6] = s;
   __syncthreads();
-  for (int k = NT / 2; k > 0; k >>= 1) {
-    if (t < k) red[t] += red[t + k];
-    __syncthreads();
+  if (t == 0) {
+    double q = 0;
+    for (int w = 0; w < NT / 64; ++w) q += red[w];
+    nsh = (float)sqrt(q);
   }
-  if (t == 0) nsh = (float)sqrt(red[0]);
   __syncthreads();
   const float n = nsh;
   const float coef = clip_coef(a.max_norm, n);
