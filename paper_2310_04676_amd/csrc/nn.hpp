@@ -285,11 +285,9 @@ static inline int sum_job_blocks(const SumJob& j) {
   const int per = 256 / j.groups;
   return (j.M * j.N + per - 1) / per;
 }
-static __global__ void __launch_bounds__(256) k_sum_two(SumJob a, int blocks_a, SumJob b) {
+// Block blk of job j (256 threads).
+__device__ __forceinline__ void sum_block(const SumJob& j, int blk) {
   __shared__ float red[256];
-  const bool first = (int)blockIdx.x < blocks_a;
-  const SumJob& j = first ? a : b;
-  const int blk = first ? blockIdx.x : blockIdx.x - blocks_a;
   const int G = j.groups, per = 256 / G;
   const int slot = threadIdx.x % per, grp = threadIdx.x / per;
   const int o = blk * per + slot;
@@ -305,6 +303,35 @@ static __global__ void __launch_bounds__(256) k_sum_two(SumJob a, int blocks_a, 
     for (int k = 0; k < G; ++k) t += red[k * per + slot];
     j.out[(size_t)(o / j.N) * j.ldo + o % j.N] = t;
   }
+}
+static __global__ void __launch_bounds__(256) k_sum_two(SumJob a, int blocks_a, SumJob b) {
+  if ((int)blockIdx.x < blocks_a) sum_block(a, blockIdx.x);
+  else sum_block(b, blockIdx.x - blocks_a);
+}
+// Up to kMaxSumJobs independent jobs in one launch: blocks
+// [blk0[k], blk0[k + 1]) reduce job k.
+constexpr int kMaxSumJobs = 6;
+struct SumJobs {
+  SumJob j[kMaxSumJobs];
+  int blk0[kMaxSumJobs + 1];
+  int count;
+};
+static __global__ void __launch_bounds__(256) k_sum_jobs(SumJobs a) {
+  int k = 0;
+  while (k + 1 < a.count && (int)blockIdx.x >= a.blk0[k + 1]) ++k;
+  sum_block(a.j[k], blockIdx.x - a.blk0[k]);
+}
+static inline void launch_sums(hipStream_t st, const SumJob* jobs, int n) {
+  SumJobs a{};
+  a.count = n;
+  int b = 0;
+  for (int k = 0; k < n; ++k) {
+    a.j[k] = jobs[k];
+    a.blk0[k] = b;
+    b += sum_job_blocks(jobs[k]);
+  }
+  a.blk0[n] = b;
+  k_sum_jobs<<<b, 256, 0, st>>>(a);
 }
 
 // Split-K shape for a weight gradient: about 256 blocks over the output
@@ -323,13 +350,11 @@ static inline int chunk_for(int K, int splits) { return ((K + splits - 1) / spli
 constexpr size_t kWeightGradWs = (size_t)512 * 64 * 64;
 
 // dW [M][N] (leading dim ldo) = sum_b A(b, m) B(b, n) over a batch of K
-// rows (A [K][lda], B [K][ldb], BF16) with split-K partials in ws
-// (kWeightGradWs floats); the split sums share their launch with `bias`,
-// the reduction of a bias gradient's per-block partial rows.
+// rows (A [K][lda], B [K][ldb], BF16): the split-K GEMM writes its partials
+// to ws (kWeightGradWs floats); the returned job sums them into out.
 template <int ACT>
-static inline void launch_weight_grad(hipStream_t st, int M, int N, int K, const uint16_t* A, int lda,
-                                      const uint16_t* B, int ldb, float* out, int ldo, float* ws,
-                                      const SumJob& bias) {
+static inline SumJob launch_weight_grad_partials(hipStream_t st, int M, int N, int K, const uint16_t* A, int lda,
+                                                 const uint16_t* B, int ldb, float* out, int ldo, float* ws) {
   const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
   const int S = splits_for(tiles, K);
   GemmArgs g{};
@@ -337,7 +362,15 @@ static inline void launch_weight_grad(hipStream_t st, int M, int N, int K, const
   g.kchunk = chunk_for(K, S);
   const int S_eff = (K + g.kchunk - 1) / g.kchunk;
   launch_gemm<EPI_PARTIAL, true, false, ACT>(st, g, S_eff);
-  const SumJob w = sum_job(ws, S_eff, M, N, out, ldo, 0);
+  return sum_job(ws, S_eff, M, N, out, ldo, 0);
+}
+// The same with the split sums launched at once, sharing their launch with
+// `bias`, the reduction of a bias gradient's per-block partial rows.
+template <int ACT>
+static inline void launch_weight_grad(hipStream_t st, int M, int N, int K, const uint16_t* A, int lda,
+                                      const uint16_t* B, int ldb, float* out, int ldo, float* ws,
+                                      const SumJob& bias) {
+  const SumJob w = launch_weight_grad_partials<ACT>(st, M, N, K, A, lda, B, ldb, out, ldo, ws);
   const int bw = sum_job_blocks(w);
   k_sum_two<<<bw + sum_job_blocks(bias), 256, 0, st>>>(w, bw, bias);
 }

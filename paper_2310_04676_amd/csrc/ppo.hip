@@ -19,8 +19,8 @@
 //                  also emits per-block column sums (the hidden biases'
 //                  gradients); weight gradients as split-K GEMMs (the batch
 //                  is the reduction axis); every partial is summed in a
-//                  fixed order -- deterministic; each split sum shares its
-//                  launch with a bias gradient's sum (k_sum_two)
+//                  fixed order -- deterministic; the three split sums and
+//                  the three bias sums share one launch (k_sum_jobs)
 //   k_ppo_norm_adam  entropy term, global gradient norm, statistics, norm
 //                  clip and Adam on the FP32 master weights + BF16 copy, in
 //                  one launch (sg_ppo_grad: k_gnorm_part and k_ppo_finish
@@ -57,9 +57,10 @@ struct sg_ppo {
   uint16_t* G3b = nullptr;   // [rows][8] dL/d(outputs)
   uint16_t* D2b = nullptr;   // [rows][128]
   uint16_t* D1b = nullptr;   // [rows][256]
-  float* ws = nullptr;       // split-K partials
+  float* ws = nullptr;       // split-K partials, one kWeightGradWs region per layer
   size_t ws_floats = 0;
-  float* cpart = nullptr;    // per-block column sums [rows / 64 (or / 256)][256]
+  float* cpart = nullptr;    // per-block column sums of dZ1 [rows / 64][256]
+  float* cpart2 = nullptr;   // per-block column sums of dZ2 [rows / 64][128]
   float* lpart = nullptr;    // k_ppo_loss block sums [rows / 256][kLossPart]
   double* gpart = nullptr;   // block sums [kGnormBlocks]: advantage statistics, then gradient norm
   std::vector<void*> allocs;
@@ -511,10 +512,11 @@ __global__ void __launch_bounds__(256) k_zero(float* __restrict__ x, int n) {
   if (i < n) x[i] = 0.f;
 }
 
-// dW [M][N] (leading dim ldo) over the minibatch, split-K in o->ws.
-static void weight_grad(sg_ppo* o, hipStream_t st, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B,
-                        int ldb, float* out, int ldo, const SumJob& bias) {
-  launch_weight_grad<ACT_TANH>(st, M, N, K, A, lda, B, ldb, out, ldo, o->ws, bias);
+// dW [M][N] (leading dim ldo) over the minibatch: the split-K GEMM into
+// layer l's region of o->ws; returns the job that sums the partials.
+static SumJob weight_grad(sg_ppo* o, hipStream_t st, int l, int M, int N, int K, const uint16_t* A, int lda,
+                          const uint16_t* B, int ldb, float* out, int ldo) {
+  return launch_weight_grad_partials<ACT_TANH>(st, M, N, K, A, lda, B, ldb, out, ldo, o->ws + l * kWeightGradWs);
 }
 
 // Gradient of one minibatch into o->g. With `finish`, the entropy term is
@@ -545,18 +547,20 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
   la.rows = rows; la.Z3 = o->Z3; la.ls = o->p + o->off[6]; la.clip = cfg->clip; la.c_v = cfg->value_coef;
   la.inv_b = 1.f / (float)B; la.w_stats = w_stats; la.G3b = o->G3b; la.part = o->lpart;
   k_ppo_loss<<<gb, 256, 0, st>>>(la);
-  // output layer gradients; output biases and log_std are adjacent in the
-  // flat vector (off[6] = off[5] + O)
-  weight_grad(o, st, O, kH2, B, o->G3b, kPO, o->H2, kH2, o->g + o->off[4], kH2,
-                           partial_rows(o->lpart, gb, O + J, kLossPart, o->g + o->off[5]));
+  // weight gradients as split-K partials; their sums and the bias sums
+  // (six jobs) run in one launch at the end. Output biases and log_std are
+  // adjacent in the flat vector (off[6] = off[5] + O).
+  SumJob jobs[6];
+  jobs[0] = weight_grad(o, st, 2, O, kH2, B, o->G3b, kPO, o->H2, kH2, o->g + o->off[4], kH2);
+  jobs[1] = partial_rows(o->lpart, gb, O + J, kLossPart, o->g + o->off[5]);
   // dZ2 = (G3 W3) * tanh'(Z2), with the column sums of dZ2 (hidden-2 bias)
   const int rb = (B + 63) / 64;
   GemmArgs d{};
   d.M = B; d.N = kH2; d.K = O; d.A = o->G3b; d.lda = kPO; d.B = o->pb + o->off[4]; d.ldb = kH2;
-  d.C = nullptr; d.ldc = kH2; d.Cb = o->D2b; d.Zp = o->Z2; d.colpart = o->cpart;
+  d.C = nullptr; d.ldc = kH2; d.Cb = o->D2b; d.Zp = o->Z2; d.colpart = o->cpart2;
   launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
-  weight_grad(o, st, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->off[2], kH1,
-                           partial_rows(o->cpart, rb, kH2, kH2, o->g + o->off[3]));
+  jobs[2] = weight_grad(o, st, 1, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->off[2], kH1);
+  jobs[3] = partial_rows(o->cpart2, rb, kH2, kH2, o->g + o->off[3]);
   // dZ1 = (dZ2 W2) * tanh'(Z1), with the column sums of dZ1 (hidden-1 bias);
   // Z1 (W inputs) is recomputed in the epilogue rather than stored
   d.N = kH1; d.K = kH2; d.A = o->D2b; d.lda = kH2; d.B = o->pb + o->off[2]; d.ldb = kH1;
@@ -564,8 +568,9 @@ static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_co
   d.Zp = nullptr;
   d.RA = o->X; d.rlda = kPX; d.RB = o->pb + o->off[0]; d.rldb = W; d.RK = W; d.rbias = o->p + o->off[1];
   launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
-  weight_grad(o, st, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->off[0], W,
-                           partial_rows(o->cpart, rb, kH1, kH1, o->g + o->off[1]));
+  jobs[4] = weight_grad(o, st, 0, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->off[0], W);
+  jobs[5] = partial_rows(o->cpart, rb, kH1, kH1, o->g + o->off[1]);
+  launch_sums(st, jobs, 6);
   if (finish) {
     const int nb = (o->P + kGnormChunk - 1) / kGnormChunk;
     k_gnorm_part<<<nb, 256, 0, st>>>(o->g, o->P, o->off[6], J, cfg->entropy_coef, o->gpart);
@@ -658,8 +663,8 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   }
   o->P = acc;
   const size_t R = (size_t)max_samples, P = (size_t)o->P;
-  // split-K partials: at most 256 tiles x splits x 64 x 64
-  o->ws_floats = kWeightGradWs;
+  // split-K partials: one region per layer (launch_weight_grad_partials bound)
+  o->ws_floats = 3 * kWeightGradWs;
   hipError_t e = palloc(o, &o->p, P);
   if (e == hipSuccess) e = palloc(o, &o->pb, P);
   if (e == hipSuccess) e = palloc(o, &o->g, P);
@@ -679,6 +684,7 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   if (e == hipSuccess) e = palloc(o, &o->D1b, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->ws, o->ws_floats);
   if (e == hipSuccess) e = palloc(o, &o->cpart, ((R + 63) / 64) * (size_t)kH1);
+  if (e == hipSuccess) e = palloc(o, &o->cpart2, ((R + 63) / 64) * (size_t)kH2);
   if (e == hipSuccess) e = palloc(o, &o->lpart, ((R + 255) / 256) * (size_t)kLossPart);
   if (e == hipSuccess) e = palloc(o, &o->gpart, (size_t)kGnormBlocks);
   if (e == hipSuccess && (o->P + kGnormChunk - 1) / kGnormChunk > kGnormBlocks) e = hipErrorInvalidValue;
