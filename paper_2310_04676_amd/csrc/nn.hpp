@@ -310,7 +310,7 @@ static __global__ void __launch_bounds__(256) k_sum_two(SumJob a, int blocks_a, 
 }
 // Up to kMaxSumJobs independent jobs in one launch: blocks
 // [blk0[k], blk0[k + 1]) reduce job k.
-constexpr int kMaxSumJobs = 6;
+constexpr int kMaxSumJobs = 8;
 struct SumJobs {
   SumJob j[kMaxSumJobs];
   int blk0[kMaxSumJobs + 1];

@@ -523,8 +523,8 @@ struct sg_surrogate {
   float* Z[kSL] = {};      // pre-activations [B][out]
   uint16_t* Gb = nullptr;  // gradient [B][256] bf16
   uint16_t* Gb2 = nullptr;
-  float* ws = nullptr;     // split-K partials of the weight gradients
-  float* cpart = nullptr;  // per-block column sums of a layer's gradient [B / 64][256]
+  float* ws = nullptr;     // split-K partials of the weight gradients, one kWeightGradWs region per layer
+  float* cpart = nullptr;  // per-block column sums of the hidden layers' gradients [kSL - 1][B / 64][256]
   float* lpart = nullptr;  // k_loss block sums [B / 256][kSLossRow]
   float* gW[kSL] = {};
   float* gb[kSL] = {};     // gb[kSL - 1][kSO] holds the batch loss
@@ -610,12 +610,17 @@ hipError_t forward_backward(sg_surrogate* s, hipStream_t st, const float* q, con
   uint16_t* Gbn = s->Gb2;
   const int gb = (B + 255) / 256, rb = (B + 63) / 64;
   k_loss<<<gb, 256, 0, st>>>(s->Z[kSL - 1], qdd, n_total, idx, B, s->J, s->norm, Gbc, s->lpart);
-  // the output layer's bias gradient and the loss (adjacent in gb[kSL - 1])
-  SumJob bias = partial_rows(s->lpart, gb, kSO + 1, kSLossRow, s->gb[kSL - 1]);
+  // Weight gradients as split-K partials (layer l in region l of ws); their
+  // sums, the bias sums and the loss (adjacent to the output layer's bias
+  // gradient in gb[kSL - 1]) run as one launch of 2 kSL jobs at the end.
+  SumJob jobs[2 * kSL];
+  int nj = 0;
+  jobs[nj++] = partial_rows(s->lpart, gb, kSO + 1, kSLossRow, s->gb[kSL - 1]);
+  const size_t cstride = (size_t)((s->maxB + 63) / 64) * kSH;
   for (int l = kSL - 1; l >= 0; --l) {
-    // dW[o][i] = sum_b G[b][o] X[b][i]; with it the bias gradient's sum
-    launch_weight_grad<ACT_ELU>(st, s_out(l), s_in(l), B, Gbc, s_out(l), s->X[l], s_in(l), s->gW[l], s_in(l), s->ws,
-                                bias);
+    // dW[o][i] = sum_b G[b][o] X[b][i]
+    jobs[nj++] = launch_weight_grad_partials<ACT_ELU>(st, s_out(l), s_in(l), B, Gbc, s_out(l), s->X[l], s_in(l),
+                                                      s->gW[l], s_in(l), s->ws + (size_t)l * kWeightGradWs);
     if (l == 0) break;
     // G_prev[b][i] = (sum_o G[b][o] W[o][i]) * elu'(Z_prev[b][i]), with the
     // per-block column sums of G_prev (the previous layer's bias gradient)
@@ -626,11 +631,12 @@ hipError_t forward_backward(sg_surrogate* s, hipStream_t st, const float* q, con
     d.C = nullptr; d.ldc = s_in(l);
     d.Cb = Gbn;
     d.Zp = s->Z[l - 1];
-    d.colpart = s->cpart;
+    d.colpart = s->cpart + (size_t)(l - 1) * cstride;
     launch_gemm<EPI_BWD_DX, false, false, ACT_ELU>(st, d);
-    bias = partial_rows(s->cpart, rb, s_out(l - 1), s_out(l - 1), s->gb[l - 1]);
+    jobs[nj++] = partial_rows(d.colpart, rb, s_out(l - 1), s_out(l - 1), s->gb[l - 1]);
     std::swap(Gbc, Gbn);
   }
+  launch_sums(st, jobs, nj);
   return hipGetLastError();
 }
 
@@ -670,8 +676,8 @@ sg_status sg_surrogate_create(sg_ctx* c, int32_t max_batch, sg_surrogate** out) 
   if (e == hipSuccess) e = dalloc(s, &s->norm, 2 * kSF + 2 * kSO);
   if (e == hipSuccess) e = dalloc(s, &s->Gb, B * kSH);
   if (e == hipSuccess) e = dalloc(s, &s->Gb2, B * kSH);
-  if (e == hipSuccess) e = dalloc(s, &s->ws, kWeightGradWs);
-  if (e == hipSuccess) e = dalloc(s, &s->cpart, ((B + 63) / 64) * (size_t)kSH);
+  if (e == hipSuccess) e = dalloc(s, &s->ws, kSL * kWeightGradWs);
+  if (e == hipSuccess) e = dalloc(s, &s->cpart, (kSL - 1) * ((B + 63) / 64) * (size_t)kSH);
   if (e == hipSuccess) e = dalloc(s, &s->lpart, ((B + 255) / 256) * (size_t)kSLossRow);
   if (e == hipSuccess) s->loss = s->gb[kSL - 1] + kSO;
   if (e == hipSuccess) e = dalloc(s, &s->qddbuf, (size_t)c->J * c->N);
