@@ -8,7 +8,9 @@
 // (action, old log-probability, advantage, value, return) as sample-major
 // FP32 rows (k_ppo_xall).
 // One minibatch of B samples (rows) taken from the rollout buffers:
-//   k_ppo_gather   the minibatch's rows -> X [B][32]
+//   k_ppo_gather   the minibatch's rows -> X [B][32] (in sg_ppo_update
+//                  only for the first minibatch: later ones are gathered
+//                  by extra blocks of the previous k_ppo_norm_adam launch)
 //   forward        three BF16 MFMA GEMMs (nn.hpp), tanh units; layer 2's
 //                  pre-activations stay in HBM for the backward pass, layer
 //                  1's (W = 2J + 10 inputs) are recomputed there
@@ -127,15 +129,17 @@ __global__ void __launch_bounds__(256) k_ppo_xall(const float* __restrict__ obs,
 }
 
 // Minibatch input rows; a sample id outside [0, T N) gives a zero row.
-__global__ void __launch_bounds__(256) k_ppo_gather(PpoRows a, uint16_t* __restrict__ X) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= a.rows) return;
+__device__ __forceinline__ void gather_row(const PpoRows& a, int r, uint16_t* __restrict__ X) {
   const int s = ppo_sample(a, r);
   const bool ok = s >= 0 && s < a.total;
   const uint4* src = reinterpret_cast<const uint4*>(a.xall + (size_t)(ok ? s : 0) * kPX);
   uint4* dst = reinterpret_cast<uint4*>(X + (size_t)r * kPX);
 #pragma unroll
   for (int q = 0; q < kPX / 8; ++q) dst[q] = ok ? src[q] : make_uint4(0, 0, 0, 0);
+}
+__global__ void __launch_bounds__(256) k_ppo_gather(PpoRows a, uint16_t* __restrict__ X) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r < a.rows) gather_row(a, r, X);
 }
 
 // Mean and unbiased standard deviation of the n advantages, two passes in
@@ -404,6 +408,9 @@ struct NormAdamArgs {
   int lb;
   float* stats;
   float w;
+  int nadam;       // blocks [0, nadam) take the Adam step
+  PpoRows next;    // blocks from nadam on gather the next minibatch's rows
+  uint16_t* X;     // into X (its reads by this minibatch are done)
 };
 
 constexpr int kNormAdamThreads = 1024;  // threads per k_ppo_norm_adam block = parameters it updates
@@ -416,12 +423,17 @@ constexpr int kNormAdamThreads = 1024;  // threads per k_ppo_norm_adam block = p
 // entries (the last J parameters) all belong to the block whose range holds
 // the first of them: it stores |g| in scal[2] and adds the statistics
 // (which read log_std) before it updates them, and no other block writes
-// them.
+// them. Blocks past the Adam blocks gather the next minibatch's rows.
 __global__ void __launch_bounds__(kNormAdamThreads) k_ppo_norm_adam(NormAdamArgs a) {
   constexpr int NT = kNormAdamThreads, NL = 16;
   __shared__ double red[NT / 64];
   __shared__ float nsh;
   const int t = threadIdx.x;
+  if ((int)blockIdx.x >= a.nadam) {
+    const int r = ((int)blockIdx.x - a.nadam) * NT + t;
+    if (r < a.next.rows) gather_row(a.next, r, a.X);
+    return;
+  }
   // entries below ls0 as 16-byte vectors, NL loads in flight per thread;
   // the rest (at most 3 + J entries) one per thread
   double s = 0;
@@ -523,13 +535,13 @@ static SumJob weight_grad(sg_ppo* o, hipStream_t st, int l, int M, int N, int K,
 // added to o->g, its norm goes to scal[2] and the statistics (weight
 // w_stats) to stats; without, k_ppo_norm_adam does both next.
 static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_config* cfg, float w_stats,
-                                 float* stats, bool finish) {
+                                 float* stats, bool finish, bool gathered = false) {
   sg_ctx* c = o->ctx;
   hipStream_t st = c->stream;
   const int B = rows.rows, W = o->W, O = o->O, J = o->J;
   const int gb = (B + 255) / 256;
   // every entry of o->g is written below (weight and bias sums), so no clear
-  k_ppo_gather<<<gb, 256, 0, st>>>(rows, o->X);
+  if (!gathered) k_ppo_gather<<<gb, 256, 0, st>>>(rows, o->X);
   GemmArgs f{};
   // layer 1: Z1 = X W1^T + b1, H1 = tanh(Z1)
   f.M = B; f.N = kH1; f.K = W; f.A = o->X; f.lda = kPX; f.B = o->pb + o->off[0]; f.ldb = W;
@@ -768,18 +780,25 @@ sg_status sg_ppo_update(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const sg
   const float w = 1.f / (float)(cfg->epochs * cfg->minibatches);
   if (stats) k_zero<<<1, 256, 0, st>>>(stats, 8);
   hipError_t e = prepare_batch(o, b, (int)total);
+  // minibatch (ep, k) of the update
+  auto rows_at = [&](int ep, int k) {
+    PpoRows r = rows_of(o, b, T);
+    r.rows = mb;
+    if (perm) {
+      r.idx = perm + (size_t)ep * total + (size_t)k * mb;
+      r.r0 = 0;
+    } else {
+      r.idx = nullptr;
+      r.r0 = k * mb;
+    }
+    return r;
+  };
   for (int ep = 0; ep < cfg->epochs && e == hipSuccess; ++ep) {
     for (int k = 0; k < cfg->minibatches && e == hipSuccess; ++k) {
-      PpoRows r = rows_of(o, b, T);
-      r.rows = mb;
-      if (perm) {
-        r.idx = perm + (size_t)ep * total + (size_t)k * mb;
-        r.r0 = 0;
-      } else {
-        r.idx = nullptr;
-        r.r0 = k * mb;
-      }
-      e = minibatch_grad(o, r, cfg, w, stats, false);
+      const PpoRows r = rows_at(ep, k);
+      // the rows of every minibatch but the first were gathered by the
+      // previous minibatch's k_ppo_norm_adam
+      e = minibatch_grad(o, r, cfg, w, stats, false, ep > 0 || k > 0);
       if (e != hipSuccess) break;
       o->t += 1;
       NormAdamArgs na;
@@ -790,7 +809,12 @@ sg_status sg_ppo_update(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const sg
       na.c1 = 1.f - (float)std::pow((double)cfg->beta1, o->t);
       na.c2 = 1.f - (float)std::pow((double)cfg->beta2, o->t);
       na.lpart = o->lpart; na.lb = (mb + 255) / 256; na.stats = stats; na.w = w;
-      k_ppo_norm_adam<<<(o->P + kNormAdamThreads - 1) / kNormAdamThreads, kNormAdamThreads, 0, st>>>(na);
+      na.nadam = (o->P + kNormAdamThreads - 1) / kNormAdamThreads;
+      const bool last = k + 1 == cfg->minibatches && ep + 1 == cfg->epochs;
+      na.next = last ? PpoRows{} : rows_at(k + 1 < cfg->minibatches ? ep : ep + 1, (k + 1) % cfg->minibatches);
+      na.X = o->X;
+      const int ng = last ? 0 : (mb + kNormAdamThreads - 1) / kNormAdamThreads;
+      k_ppo_norm_adam<<<na.nadam + ng, kNormAdamThreads, 0, st>>>(na);
       e = hipGetLastError();
     }
   }
