@@ -294,6 +294,20 @@ def residual(orc, q, qd, tau, qdd_hat, arm=None):
     return rel
 
 
+OPCOUNT_PRIMITIVES = ("dot", "cross", "m3v3", "m3m3", "xform_motion", "xform_force_T", "crm", "crf", "si_mul",
+                      "sdot", "congruence", "si_add", "axis_rotation")
+
+
+def opcount_primitives():
+    """Operation tallies of single spatial-algebra primitives on the op
+    counter: {name: {add, mul, div, sqrt, trans}}."""
+    out = np.zeros((len(OPCOUNT_PRIMITIVES), 5), dtype=np.int64)
+    k = lib().ora_opcount_primitives(out.ctypes.data_as(C.POINTER(C.c_longlong)))
+    assert k == len(OPCOUNT_PRIMITIVES)
+    keys = ("add", "mul", "div", "sqrt", "trans")
+    return {n: dict(zip(keys, map(int, out[i]))) for i, n in enumerate(OPCOUNT_PRIMITIVES)}
+
+
 def philox4x32_10(ctr, key):
     c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
     k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])

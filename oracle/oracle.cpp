@@ -411,6 +411,51 @@ int ora_opcount_step(const ora_robot* r, const ora_task* t, int e, const double*
   return 0;
 }
 
+// Operation tallies of single spatial-algebra primitives applied once to
+// Counted operands, in the order: dot, cross, 3x3 matrix-vector, 3x3
+// matrix-matrix, motion transform, transposed force transform, motion cross
+// product, force cross product, spatial inertia times vector, motion-force
+// pairing, inertia congruence, inertia sum, axis rotation. out: [13][5] =
+// add, mul, div, sqrt, trans per primitive. Returns the primitive count.
+int ora_opcount_primitives(long long* out) {
+  auto V = [](double a, double b, double c) { return v3(Counted(a), Counted(b), Counted(c)); };
+  M3<Counted> A, B;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      A.m[i][j] = Counted(0.1 * (i + 1) + 0.01 * j);
+      B.m[i][j] = Counted(0.2 * (j + 1) - 0.03 * i);
+    }
+  const V3<Counted> a = V(0.3, -0.2, 0.9), b = V(-0.4, 0.5, 0.1);
+  const SV<Counted> m = {a, b}, f = {b, a};
+  PX<Counted> X;
+  X.E = A;
+  X.r = b;
+  SI<Counted> I = {A, B, A};
+  int k = 0;
+  auto rec = [&](auto&& fn) {
+    tally() = OpTally();
+    fn();
+    const OpTally t = tally();
+    long long* o = out + 5 * k++;
+    o[0] = t.add; o[1] = t.mul; o[2] = t.div; o[3] = t.sqrt; o[4] = t.trans;
+  };
+  rec([&] { (void)dot(a, b); });
+  rec([&] { (void)cross(a, b); });
+  rec([&] { (void)mul(A, a); });
+  rec([&] { (void)mul(A, B); });
+  rec([&] { (void)xform_motion(X, m); });
+  rec([&] { (void)xform_force_T(X, f); });
+  rec([&] { (void)crm(m, f); });
+  rec([&] { (void)crf(m, f); });
+  rec([&] { (void)mul(I, m); });
+  rec([&] { (void)sdot(m, f); });
+  rec([&] { (void)congruence(X, I); });
+  rec([&] { (void)add(I, I); });
+  rec([&] { (void)axis_rotation(a, Counted(0.7)); });
+  tally() = OpTally();
+  return k;
+}
+
 // ---- learning side -------------------------------------------------------
 
 void ora_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {

@@ -263,6 +263,8 @@ __global__ void __launch_bounds__(64) k_adjoint(AdjArgs A) {
 
 template <int J, int M> static hipError_t adjoint_j(const sg_ctx* c, const AdjArgs& A) {
   constexpr size_t lds = use_lds<float, J>() ? par_lds_bytes<float, J>() : 0;
+  hipError_t e = lds_limit((const void*)k_adjoint<J, M>, lds);
+  if (e != hipSuccess) return e;
   k_adjoint<J, M><<<dim3((c->N + 63) / 64), 64, lds, c->stream>>>(A);
   return hipGetLastError();
 }

@@ -76,6 +76,10 @@ template <typename T> inline EnvDev<T> env_view(const sg_ctx* c) {
 // smallest one >= its J.
 int dof_bucket(int J);
 
+// Raise the dynamic-LDS limit of kernel fn to bytes (when above the 64 KB
+// default) on the current device, once per (device, kernel address).
+hipError_t lds_limit(const void* fn, size_t bytes);
+
 hipError_t launch_step(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done);
 hipError_t launch_observe(const sg_ctx* c, void* obs);
 hipError_t launch_fd(const sg_ctx* c, const void* q, const void* qd, const void* tau, int arm_mode, void* qdd);

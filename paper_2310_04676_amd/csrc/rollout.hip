@@ -178,12 +178,8 @@ hipError_t launch_gae(hipStream_t s, int T, int n, const float* rew, const float
 
 hipError_t launch_policy_forward(const sg_ctx* c, const float* x, int n, float* out) {
   const size_t lds = kLdsW + kLdsBias + kLdsX + kLdsO;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_policy, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  hipError_t e = lds_limit((const void*)k_policy, lds);
+  if (e != hipSuccess) return e;
   k_policy<<<dim3((n + kWave - 1) / kWave), kWave, lds, c->stream>>>(
       reinterpret_cast<const uint4*>(c->w_bf16), c->bias, 2 * c->J + 10, c->J + 1, n, x, out);
   return hipGetLastError();
@@ -191,13 +187,8 @@ hipError_t launch_policy_forward(const sg_ctx* c, const float* x, int n, float* 
 
 template <int J, int M> static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_bufs* b) {
   const size_t lds = rollout_lds_bytes<J>();
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e =
-        hipFuncSetAttribute((const void*)k_rollout<J, M>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  hipError_t e = lds_limit((const void*)k_rollout<J, M>, lds);
+  if (e != hipSuccess) return e;
   RollArgs A;
   A.E = env_view<float>(c);
   A.wimg = reinterpret_cast<const uint4*>(c->w_bf16);
@@ -208,7 +199,7 @@ template <int J, int M> static hipError_t rollout_j(sg_ctx* c, int T, const sg_r
   A.step0 = c->rng_step;
   A.obs = b->obs; A.act = b->act; A.logp = b->logp; A.rew = b->rew; A.done = b->done; A.val = b->val;
   k_rollout<J, M><<<dim3((c->N + kWave - 1) / kWave), kWave, lds, c->stream>>>(A);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   c->rng_step += (uint64_t)T;
   return launch_gae(c->stream, T, c->N, b->rew, b->val, b->done, b->gamma, b->lam, b->adv, b->ret);

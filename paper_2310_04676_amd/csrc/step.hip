@@ -3,9 +3,27 @@
 // per pass, structure-of-arrays global layout so each per-joint field is one
 // coalesced 64-lane access. The kernel variant M (M_GEN, M_UNI, M_PRI) picks
 // per-env joint counts, exactly J joints, or chains with prismatic joints.
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "internal.hpp"
 
 namespace sgk {
+
+hipError_t lds_limit(const void* fn, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  static std::mutex mu;
+  static std::set<std::pair<int, const void*>> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count({dev, fn})) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) done.insert({dev, fn});
+  return e;
+}
 
 int dof_bucket(int J) {
   if (J <= 1) return 1;
@@ -181,17 +199,13 @@ __global__ void __launch_bounds__(256) k_reset(EnvDev<T> E) {
   E.prog[e] = E.prog0[e];
 }
 
-// Launch with the block's dynamic LDS; raising the per-kernel LDS limit
-// above the 64 KB default once per instantiation.
+// Launch with the block's dynamic LDS (the kernel's LDS limit raised above
+// the 64 KB default where needed).
 template <typename T, int J, typename K, typename... Args>
 static hipError_t launch_par(K kernel, const sg_ctx* c, Args... args) {
   constexpr size_t lds = use_lds<T, J>() ? par_lds_bytes<T, J>() : 0;
-  static bool attr = false;
-  if (!attr && lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  attr = true;
+  hipError_t e = lds_limit((const void*)kernel, lds);
+  if (e != hipSuccess) return e;
   kernel<<<dim3((c->N + kBlk - 1) / kBlk), kBlk, lds, c->stream>>>(args...);
   return hipGetLastError();
 }
@@ -225,13 +239,8 @@ template <typename T, int JB>
 static hipError_t step_tiles_t(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done, int tile0,
                                int ntiles, int grid) {
   constexpr size_t lds = use_lds<T, JB>() ? par_lds_bytes<T, JB>() : 0;
-  static bool attr = false;
-  if (!attr && lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_step_tiles<T, JB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  attr = true;
+  hipError_t e = lds_limit((const void*)k_step_tiles<T, JB>, lds);
+  if (e != hipSuccess) return e;
   EnvDev<T> E = env_view<T>(c);
   k_step_tiles<T, JB><<<dim3(grid), kBlk, lds, c->stream>>>(E, c->slot_env, c->tile_dof, tile0, ntiles, (const T*)act,
                                                            (T*)obs, (T*)rew, done);

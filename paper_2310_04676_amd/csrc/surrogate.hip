@@ -98,26 +98,33 @@ __global__ void __launch_bounds__(256) k_feat(FeatArgs a) {
 // Mean and standard deviation per row of a [rows][n] array (one block per
 // row; the std floor keeps constant features finite).
 __global__ void __launch_bounds__(256) k_rowstats(const float* __restrict__ x, int n, float* mu, float* sd) {
-  __shared__ double s1[256], s2[256];
+  // two passes in double: the mean, then the mean squared deviation from it
+  // (no E[x^2] - m^2 cancellation for features with a large mean and a
+  // small spread)
+  __shared__ double red[256];
   const int row = blockIdx.x;
-  double a = 0, b = 0;
-  for (int i = threadIdx.x; i < n; i += 256) {
-    const double v = x[(size_t)row * n + i];
-    a += v;
-    b += v * v;
-  }
-  s1[threadIdx.x] = a;
-  s2[threadIdx.x] = b;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      s1[threadIdx.x] += s1[threadIdx.x + w];
-      s2[threadIdx.x] += s2[threadIdx.x + w];
-    }
+  const float* xr = x + (size_t)row * n;
+  auto block_sum = [&](double a) {
+    red[threadIdx.x] = a;
     __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    const double t = red[0];
+    __syncthreads();
+    return t;
+  };
+  double a = 0;
+  for (int i = threadIdx.x; i < n; i += 256) a += (double)xr[i];
+  const double m = block_sum(a) / n;
+  double b = 0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double d = (double)xr[i] - m;
+    b += d * d;
   }
+  const double var = block_sum(b) / n;
   if (threadIdx.x == 0) {
-    const double m = s1[0] / n, var = s2[0] / n - m * m;
     const double s = var > 1e-12 ? sqrt(var) : 1.0;
     mu[row] = (float)m;
     sd[row] = (float)s;
