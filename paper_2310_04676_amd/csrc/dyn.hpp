@@ -414,6 +414,242 @@ __device__ __forceinline__ void aba(PS& ps, int n, const T (&q)[J], const T (&qd
   }
 }
 
+// Translation part of a congruence: moves the reference point of a
+// symmetric 6x6 inertia I (blocks A, B, C) from the child origin to the
+// parent origin, o = child origin - parent origin in the common orientation:
+// C' = C, B' = B + o x C, A' = A + o x B^T - B' o x. Written into out.
+template <typename T>
+__device__ __forceinline__ void shift_inertia(const T* o, const AI<T>& I, AI<T>& out) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const T c0 = sym_at(I.C, 0, j), c1 = sym_at(I.C, 1, j), c2 = sym_at(I.C, 2, j);
+    out.B[0 * 3 + j] = I.B[0 * 3 + j] + (o[1] * c2 - o[2] * c1);
+    out.B[1 * 3 + j] = I.B[1 * 3 + j] + (o[2] * c0 - o[0] * c2);
+    out.B[2 * 3 + j] = I.B[2 * 3 + j] + (o[0] * c1 - o[1] * c0);
+  }
+  auto Y = [&](int i, int j) {
+    const T b0 = I.B[j * 3 + 0], b1 = I.B[j * 3 + 1], b2 = I.B[j * 3 + 2];
+    return i == 0 ? (o[1] * b2 - o[2] * b1) : (i == 1 ? (o[2] * b0 - o[0] * b2) : (o[0] * b1 - o[1] * b0));
+  };
+  auto Z = [&](int i, int j) {
+    const T b0 = out.B[i * 3 + 0], b1 = out.B[i * 3 + 1], b2 = out.B[i * 3 + 2];
+    return j == 0 ? (b1 * o[2] - b2 * o[1]) : (j == 1 ? (b2 * o[0] - b0 * o[2]) : (b0 * o[1] - b1 * o[0]));
+  };
+  out.A[S00] = I.A[S00] + Y(0, 0) - Z(0, 0);
+  out.A[S11] = I.A[S11] + Y(1, 1) - Z(1, 1);
+  out.A[S22] = I.A[S22] + Y(2, 2) - Z(2, 2);
+  out.A[S01] = I.A[S01] + Y(0, 1) - Z(0, 1);
+  out.A[S02] = I.A[S02] + Y(0, 2) - Z(0, 2);
+  out.A[S12] = I.A[S12] + Y(1, 2) - Z(1, 2);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) out.C[k] = I.C[k];
+}
+
+// Forward dynamics for one env, the same result as aba() computed in
+// world-oriented frames placed at the joint origins (each link's spatial
+// quantities are expressed at its own joint origin with the axes of the
+// base frame). Pass 1 accumulates the link rotations W_j and rotates each
+// link's inertia (m, m c, I_O) into the base orientation once; then passes 2
+// and 3 only move reference points between neighbouring joint origins
+// (translations by the joint offsets W_{j-1} o_j), so the articulated
+// inertia recursion needs no rotations. Per joint the passes keep the
+// base-oriented axis, offset, velocity-product acceleration c, bias force
+// p and rotated link inertia; offsets stay at link scale, so no precision
+// is lost to distant reference points.
+template <typename T, int J, class PS>
+__device__ __forceinline__ void aba_lwa(PS& ps, int n, const T (&q)[J], const T (&qd)[J], const T (&tau)[J],
+                                        const T (&arm)[J], const T* grav, T (&qdd)[J]) {
+  T aw[J][3], ow[J][3], cj[J][6], pj[J][6], Iw[J][6], hw[J][3], U[J][6], invD[J], uj[J];
+  // pass 1
+  ps.fence();
+  {
+    T W[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)};
+    T w[3] = {T(0), T(0), T(0)}, vl[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (j < n) {
+        Jp<T> p = ps.get(j);
+        const bool pr = slide<PS>(p, q[j]);
+        const T o[3] = {W[0] * p.ox + W[1] * p.oy + W[2] * p.oz, W[3] * p.ox + W[4] * p.oy + W[5] * p.oz,
+                        W[6] * p.ox + W[7] * p.oy + W[8] * p.oz};
+        const T a[3] = {W[0] * p.ax + W[1] * p.ay + W[2] * p.az, W[3] * p.ax + W[4] * p.ay + W[5] * p.az,
+                        W[6] * p.ax + W[7] * p.ay + W[8] * p.az};
+        // the parent's velocity at this joint's origin
+        vl[0] += w[1] * o[2] - w[2] * o[1];
+        vl[1] += w[2] * o[0] - w[0] * o[2];
+        vl[2] += w[0] * o[1] - w[1] * o[0];
+        const T qv = qd[j];
+        const T sx = a[0] * qv, sy = a[1] * qv, sz = a[2] * qv;
+        if (!pr) {
+          w[0] += sx; w[1] += sy; w[2] += sz;
+          // c = v x (S qd), S qd = (s; 0): (w x s; vl x s)
+          cj[j][0] = w[1] * sz - w[2] * sy;
+          cj[j][1] = w[2] * sx - w[0] * sz;
+          cj[j][2] = w[0] * sy - w[1] * sx;
+          cj[j][3] = vl[1] * sz - vl[2] * sy;
+          cj[j][4] = vl[2] * sx - vl[0] * sz;
+          cj[j][5] = vl[0] * sy - vl[1] * sx;
+          T s, c, R[9], Wn[9];
+          sc(q[j], &s, &c);
+          rodrigues(p, s, c, R);
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+              Wn[r * 3 + k] = W[r * 3 + 0] * R[0 * 3 + k] + W[r * 3 + 1] * R[1 * 3 + k] + W[r * 3 + 2] * R[2 * 3 + k];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) W[k] = Wn[k];
+        } else {
+          // prismatic: S qd = (0; s), c = (0; w x s), no rotation
+          vl[0] += sx; vl[1] += sy; vl[2] += sz;
+          cj[j][0] = T(0); cj[j][1] = T(0); cj[j][2] = T(0);
+          cj[j][3] = w[1] * sz - w[2] * sy;
+          cj[j][4] = w[2] * sx - w[0] * sz;
+          cj[j][5] = w[0] * sy - w[1] * sx;
+        }
+        // the link's inertia in the base orientation: W I_O W^T, W h
+        {
+          const T S6[6] = {p.ixx, p.iyy, p.izz, p.ixy, p.ixz, p.iyz};
+          sym_rot(W, S6, Iw[j]);
+          hw[j][0] = W[0] * p.hx + W[1] * p.hy + W[2] * p.hz;
+          hw[j][1] = W[3] * p.hx + W[4] * p.hy + W[5] * p.hz;
+          hw[j][2] = W[6] * p.hx + W[7] * p.hy + W[8] * p.hz;
+        }
+        // p = v x* (I v), I v = (Iw w + h x vl; m vl - h x w)
+        {
+          const T* I = Iw[j];
+          const T* h = hw[j];
+          const T n0 = I[S00] * w[0] + I[S01] * w[1] + I[S02] * w[2] + (h[1] * vl[2] - h[2] * vl[1]);
+          const T n1 = I[S01] * w[0] + I[S11] * w[1] + I[S12] * w[2] + (h[2] * vl[0] - h[0] * vl[2]);
+          const T n2 = I[S02] * w[0] + I[S12] * w[1] + I[S22] * w[2] + (h[0] * vl[1] - h[1] * vl[0]);
+          const T f0 = p.m * vl[0] - (h[1] * w[2] - h[2] * w[1]);
+          const T f1 = p.m * vl[1] - (h[2] * w[0] - h[0] * w[2]);
+          const T f2 = p.m * vl[2] - (h[0] * w[1] - h[1] * w[0]);
+          pj[j][0] = (w[1] * n2 - w[2] * n1) + (vl[1] * f2 - vl[2] * f1);
+          pj[j][1] = (w[2] * n0 - w[0] * n2) + (vl[2] * f0 - vl[0] * f2);
+          pj[j][2] = (w[0] * n1 - w[1] * n0) + (vl[0] * f1 - vl[1] * f0);
+          pj[j][3] = w[1] * f2 - w[2] * f1;
+          pj[j][4] = w[2] * f0 - w[0] * f2;
+          pj[j][5] = w[0] * f1 - w[1] * f0;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { aw[j][k] = a[k]; ow[j][k] = o[k]; }
+      }
+    }
+  }
+  // pass 2
+  ps.fence();
+  AI<T> acc;
+  T accp[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) { acc.A[k] = T(0); acc.C[k] = T(0); accp[k] = T(0); }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc.B[k] = T(0);
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j) {
+    if (j < n) {
+      T m, pr_;
+      {
+        const Jp<T> p = ps.get(j);
+        m = p.m;
+        pr_ = p.pr;
+      }
+      const bool pr = PS::kPris && pr_ != T(0);
+      const T* h = hw[j];
+      AI<T> I;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) I.A[k] = Iw[j][k] + acc.A[k];
+      I.B[0] = acc.B[0];        I.B[1] = acc.B[1] - h[2]; I.B[2] = acc.B[2] + h[1];
+      I.B[3] = acc.B[3] + h[2]; I.B[4] = acc.B[4];        I.B[5] = acc.B[5] - h[0];
+      I.B[6] = acc.B[6] - h[1]; I.B[7] = acc.B[7] + h[0]; I.B[8] = acc.B[8];
+      I.C[S00] = m + acc.C[S00]; I.C[S11] = m + acc.C[S11]; I.C[S22] = m + acc.C[S22];
+      I.C[S01] = acc.C[S01];     I.C[S02] = acc.C[S02];     I.C[S12] = acc.C[S12];
+      T pa[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) pa[k] = pj[j][k] + accp[k];
+      const T ax = aw[j][0], ay = aw[j][1], az = aw[j][2];
+      if (!pr) {
+        U[j][0] = I.A[S00] * ax + I.A[S01] * ay + I.A[S02] * az;
+        U[j][1] = I.A[S01] * ax + I.A[S11] * ay + I.A[S12] * az;
+        U[j][2] = I.A[S02] * ax + I.A[S12] * ay + I.A[S22] * az;
+        U[j][3] = I.B[0] * ax + I.B[3] * ay + I.B[6] * az;
+        U[j][4] = I.B[1] * ax + I.B[4] * ay + I.B[7] * az;
+        U[j][5] = I.B[2] * ax + I.B[5] * ay + I.B[8] * az;
+        invD[j] = recip(U[j][0] * ax + U[j][1] * ay + U[j][2] * az + arm[j]);
+        uj[j] = tau[j] - (pa[0] * ax + pa[1] * ay + pa[2] * az);
+      } else {
+        U[j][0] = I.B[0] * ax + I.B[1] * ay + I.B[2] * az;
+        U[j][1] = I.B[3] * ax + I.B[4] * ay + I.B[5] * az;
+        U[j][2] = I.B[6] * ax + I.B[7] * ay + I.B[8] * az;
+        U[j][3] = I.C[S00] * ax + I.C[S01] * ay + I.C[S02] * az;
+        U[j][4] = I.C[S01] * ax + I.C[S11] * ay + I.C[S12] * az;
+        U[j][5] = I.C[S02] * ax + I.C[S12] * ay + I.C[S22] * az;
+        invD[j] = recip(U[j][3] * ax + U[j][4] * ay + U[j][5] * az + arm[j]);
+        uj[j] = tau[j] - (pa[3] * ax + pa[4] * ay + pa[5] * az);
+      }
+      if (j > 0) {
+        T Ud[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Ud[k] = U[j][k] * invD[j];
+        I.A[S00] -= U[j][0] * Ud[0]; I.A[S11] -= U[j][1] * Ud[1]; I.A[S22] -= U[j][2] * Ud[2];
+        I.A[S01] -= U[j][0] * Ud[1]; I.A[S02] -= U[j][0] * Ud[2]; I.A[S12] -= U[j][1] * Ud[2];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int s2 = 0; s2 < 3; ++s2) I.B[r * 3 + s2] -= U[j][r] * Ud[3 + s2];
+        I.C[S00] -= U[j][3] * Ud[3]; I.C[S11] -= U[j][4] * Ud[4]; I.C[S22] -= U[j][5] * Ud[5];
+        I.C[S01] -= U[j][3] * Ud[4]; I.C[S02] -= U[j][3] * Ud[5]; I.C[S12] -= U[j][4] * Ud[5];
+        const T* c = cj[j];
+        const T uD = uj[j] * invD[j];
+        T f[6];
+        f[0] = pa[0] + I.A[S00] * c[0] + I.A[S01] * c[1] + I.A[S02] * c[2] + I.B[0] * c[3] + I.B[1] * c[4] + I.B[2] * c[5] + U[j][0] * uD;
+        f[1] = pa[1] + I.A[S01] * c[0] + I.A[S11] * c[1] + I.A[S12] * c[2] + I.B[3] * c[3] + I.B[4] * c[4] + I.B[5] * c[5] + U[j][1] * uD;
+        f[2] = pa[2] + I.A[S02] * c[0] + I.A[S12] * c[1] + I.A[S22] * c[2] + I.B[6] * c[3] + I.B[7] * c[4] + I.B[8] * c[5] + U[j][2] * uD;
+        f[3] = pa[3] + I.B[0] * c[0] + I.B[3] * c[1] + I.B[6] * c[2] + I.C[S00] * c[3] + I.C[S01] * c[4] + I.C[S02] * c[5] + U[j][3] * uD;
+        f[4] = pa[4] + I.B[1] * c[0] + I.B[4] * c[1] + I.B[7] * c[2] + I.C[S01] * c[3] + I.C[S11] * c[4] + I.C[S12] * c[5] + U[j][4] * uD;
+        f[5] = pa[5] + I.B[2] * c[0] + I.B[5] * c[1] + I.B[8] * c[2] + I.C[S02] * c[3] + I.C[S12] * c[4] + I.C[S22] * c[5] + U[j][5] * uD;
+        // to the parent's origin: translate by o = this joint's offset
+        const T* o = ow[j];
+        shift_inertia(o, I, acc);
+        accp[0] = f[0] + (o[1] * f[5] - o[2] * f[4]);
+        accp[1] = f[1] + (o[2] * f[3] - o[0] * f[5]);
+        accp[2] = f[2] + (o[0] * f[4] - o[1] * f[3]);
+        accp[3] = f[3]; accp[4] = f[4]; accp[5] = f[5];
+      }
+    }
+  }
+  // pass 3
+  T a[6] = {T(0), T(0), T(0), -grav[0], -grav[1], -grav[2]};
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j < n) {
+      const T* o = ow[j];
+      T an[6];
+      an[0] = a[0] + cj[j][0];
+      an[1] = a[1] + cj[j][1];
+      an[2] = a[2] + cj[j][2];
+      an[3] = a[3] + (a[1] * o[2] - a[2] * o[1]) + cj[j][3];
+      an[4] = a[4] + (a[2] * o[0] - a[0] * o[2]) + cj[j][4];
+      an[5] = a[5] + (a[0] * o[1] - a[1] * o[0]) + cj[j][5];
+      const T dot = U[j][0] * an[0] + U[j][1] * an[1] + U[j][2] * an[2] + U[j][3] * an[3] + U[j][4] * an[4] +
+                    U[j][5] * an[5];
+      qdd[j] = (uj[j] - dot) * invD[j];
+      bool pr = false;
+      if constexpr (PS::kPris) pr = ps.get(j).pr != T(0);
+      const T qa = qdd[j];
+      if (!pr) {
+        an[0] += aw[j][0] * qa; an[1] += aw[j][1] * qa; an[2] += aw[j][2] * qa;
+      } else {
+        an[3] += aw[j][0] * qa; an[4] += aw[j][1] * qa; an[5] += aw[j][2] * qa;
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) a[k] = an[k];
+    } else {
+      qdd[j] = T(0);
+    }
+  }
+}
+
 // Inverse dynamics for one env: tau = H qdd + C (gravity included).
 template <typename T, int J, class PS>
 __device__ __forceinline__ void rnea(PS& ps, int n, const T (&q)[J], const T (&qd)[J], const T (&qdd)[J],

@@ -176,7 +176,7 @@ __device__ __forceinline__ void physics(const EnvDev<T>& E, PS& ps, int n, const
         tau[j] = T(0);
       }
     }
-    aba<T, J>(ps, n, q, qd, tau, arm, E.g, qdd);
+    aba_lwa<T, J>(ps, n, q, qd, tau, arm, E.g, qdd);
     ps.fence();
 #pragma unroll
     for (int j = 0; j < J; ++j) {

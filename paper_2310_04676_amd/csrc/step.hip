@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kBlk) k_fd(EnvDev<T> E, const T* __restrict__ 
       arm[j] = T(0);
     }
   }
-  aba<T, J>(ps, n, q, qd, tau, arm, E.g, qdd);
+  aba_lwa<T, J>(ps, n, q, qd, tau, arm, E.g, qdd);
 #pragma unroll
   for (int j = 0; j < J; ++j)
     if (j < E.J) qddout[(size_t)j * E.N + e] = j < n ? qdd[j] : T(0);

@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(256) k_sstep_b(SStepArgs A) {
   load_chain<float, J>(E, e, n, P);
   load_state<float, J>(E, e, n, q, qd);
   drive_terms<J>(E, P, n, A.act, e, q, qd, tau, arm);
-  aba<float, J>(P, n, q, qd, tau, arm, E.g, qdd);
+  aba_lwa<float, J>(P, n, q, qd, tau, arm, E.g, qdd);
 #pragma unroll
   for (int j = 0; j < J; ++j)
     if (j < n) A.qddbuf[(size_t)j * E.N + e] = qdd[j];
