@@ -47,6 +47,13 @@ __device__ __forceinline__ void sc(float x, float* s, float* c) { sincosf(x, s, 
 __device__ __forceinline__ void sc(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ float rsq(float x) { return sqrtf(x); }
 __device__ __forceinline__ double rsq(double x) { return sqrt(x); }
+// sin and cos of a joint angle for the forward-dynamics solve: the hardware
+// v_sin_f32 / v_cos_f32 (argument scaled to revolutions) in FP32, whose
+// absolute error (a few 1e-7 for joint angles within a few radians) is below
+// the FP32 rounding the rest of the solve accumulates; the library sincos in
+// FP64.
+__device__ __forceinline__ void sc_hw(float x, float* s, float* c) { *s = __sinf(x); *c = __cosf(x); }
+__device__ __forceinline__ void sc_hw(double x, double* s, double* c) { sincos(x, s, c); }
 // Reciprocal of an articulated inertia D > 0: the hardware v_rcp_f32 (about
 // 1 ulp) in FP32, an exact division in FP64.
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -490,7 +497,7 @@ __device__ __forceinline__ void aba_lwa(PS& ps, int n, const T (&q)[J], const T 
           cj[j][4] = vl[2] * sx - vl[0] * sz;
           cj[j][5] = vl[0] * sy - vl[1] * sx;
           T s, c, R[9], Wn[9];
-          sc(q[j], &s, &c);
+          sc_hw(q[j], &s, &c);
           rodrigues(p, s, c, R);
 #pragma unroll
           for (int r = 0; r < 3; ++r)
