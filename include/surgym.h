@@ -358,6 +358,20 @@ sg_status sg_surrogate_step(sg_surrogate* s, const float* actions, float* obs, f
  * on first use of a larger size (that call synchronizes the stream). */
 sg_status sg_adjoint(sg_ctx* ctx, int32_t T, int32_t K, const float* actions, float* loss, float* g_act,
                      float* g_mass);
+/* sg_adjoint for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): the same computation, arguments, errors and results, with the
+ * checkpoints and segment tape in a fixed library workspace of 16 MiB
+ * (16,777,216 bytes) per GPU, a static device array held until the process
+ * ends. No call allocates or frees memory. A (T, K) whose
+ * sg_adjoint_workspace_bytes exceeds 16 MiB returns SG_E_INVAL before any
+ * work is enqueued (at 4096 envs x 7 DOF x 4 substeps, T = 64 with K = 8
+ * needs 14.0 MB). Every call on one GPU shares that GPU's workspace: calls
+ * that overlap in time on one GPU (two streams, two host threads) race and
+ * must be serialized by the caller; calls in one stream order are safe. The
+ * workspace needs no clearing (every entry is written before it is read). */
+sg_status sg_adjoint_static(sg_ctx* ctx, int32_t T, int32_t K, const float* actions, float* loss, float* g_act,
+                            float* g_mass);
 /* Device workspace sg_adjoint needs for (T, K), in bytes; -1 if invalid. */
 int64_t sg_adjoint_workspace_bytes(const sg_ctx* ctx, int32_t T, int32_t K);
 /* Replace the link masses by masses [J][N] (DEVICE, context dtype), scaling

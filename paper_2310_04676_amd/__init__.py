@@ -523,20 +523,23 @@ class Ppo:
 
 # ---- differentiation ------------------------------------------------------------
 lib.sg_adjoint.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
+lib.sg_adjoint_static.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
 lib.sg_adjoint_workspace_bytes.argtypes = [_vp, C.c_int32, C.c_int32]
 lib.sg_adjoint_workspace_bytes.restype = C.c_int64
 lib.sg_set_link_masses.argtypes = [_vp, _vp]
 
 
-def _adjoint(self, actions, K=8):
+def _adjoint(self, actions, K=8, static=False):
     """Loss [N] and its gradients (g_act [T][J][N], g_mass [J][N]) of an
-    open-loop rollout with actions [T][J][N] from the current state."""
+    open-loop rollout with actions [T][J][N] from the current state.
+    static=True calls sg_adjoint_static (the library's fixed workspace, no
+    device allocation; outputs are still allocated here)."""
     T = actions.shape[0]
     f32 = self.torch.float32
     loss = self._empty(self.N, dtype=f32)
     g_act = self._empty(T, self.J, self.N, dtype=f32)
     g_mass = self._empty(self.J, self.N, dtype=f32)
-    self._call(lib.sg_adjoint, C.c_int32(T), C.c_int32(K), _dptr(actions, f32), _dptr(loss, f32), _dptr(g_act, f32),
+    self._call(lib.sg_adjoint_static if static else lib.sg_adjoint, C.c_int32(T), C.c_int32(K), _dptr(actions, f32), _dptr(loss, f32), _dptr(g_act, f32),
                _dptr(g_mass, f32))
     return loss, g_act, g_mass
 

@@ -17,6 +17,9 @@
 //             vjp_rnea), and the PD torque.
 // Memory: checkpoints + one segment's tape instead of the full tape
 // (T S 2J floats per env).
+#include <map>
+#include <mutex>
+
 #include "adj.hpp"
 #include "internal.hpp"
 
@@ -314,6 +317,38 @@ hipError_t launch_set_masses(sg_ctx* c, const void* m) {
   return hipGetLastError();
 }
 
+// Fixed workspace of sg_adjoint_static: 16 MiB of device memory per GPU,
+// held until the process ends. Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address): it takes the
+// address hipGetSymbolAddress returns for the device, once per device.
+constexpr size_t kAdjStaticFloats = (size_t)4 << 20;
+static __device__ __align__(256) float scratch[kAdjStaticFloats];
+
+// This device's copy of scratch (dev current while the address is taken).
+static hipError_t scratch_ptr(int dev, float** out) {
+  static std::mutex mu;
+  static std::map<int, float*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+  float* ptr = nullptr;
+  if (e == hipSuccess) e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (cur != dev) {
+    const hipError_t e2 = hipSetDevice(cur);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e != hipSuccess) return e;
+  addr[dev] = ptr;
+  *out = ptr;
+  return hipSuccess;
+}
+
 }  // namespace sgk
 
 using namespace sgk;
@@ -344,6 +379,34 @@ sg_status sg_adjoint(sg_ctx* c, int32_t T, int32_t K, const float* actions, floa
   if (e == hipSuccess) e = launch_adjoint(c, T, K, actions, loss, g_act, g_mass, c->adj_ws);
   if (e != hipSuccess) {
     c->err = std::string("sg_adjoint: ") + hipGetErrorString(e);
+    return SG_E_HIP;
+  }
+  return SG_OK;
+}
+
+sg_status sg_adjoint_static(sg_ctx* c, int32_t T, int32_t K, const float* actions, float* loss, float* g_act,
+                            float* g_mass) {
+  if (!c) return SG_E_INVAL;
+  if (c->dtype != SG_F32 || c->J > 7 || c->task == SG_TASK_TRACK) {
+    c->err = "sg_adjoint_static: FP32 reaching or path-following contexts with max_dof <= 7 only";
+    return SG_E_UNSUPPORTED;
+  }
+  if (T < 1 || K < 1 || K > T || !actions || !loss || !g_act || !g_mass) {
+    c->err = "sg_adjoint_static: need 1 <= K <= T and non-null buffers";
+    return SG_E_INVAL;
+  }
+  const size_t need = adjoint_ws_floats(c, T, K);
+  if (need > kAdjStaticFloats) {
+    c->err = "sg_adjoint_static: workspace of " + std::to_string(need * sizeof(float)) +
+             " bytes exceeds the fixed " + std::to_string(kAdjStaticFloats * sizeof(float)) +
+             " bytes (use sg_adjoint, or fewer envs, steps or a smaller K)";
+    return SG_E_INVAL;
+  }
+  float* ws = nullptr;
+  hipError_t e = scratch_ptr(c->device, &ws);
+  if (e == hipSuccess) e = launch_adjoint(c, T, K, actions, loss, g_act, g_mass, ws);
+  if (e != hipSuccess) {
+    c->err = std::string("sg_adjoint_static: ") + hipGetErrorString(e);
     return SG_E_HIP;
   }
   return SG_OK;
