@@ -41,11 +41,13 @@
  * sg_gae, the dynamics calls, sg_surrogate_train_step, sg_surrogate_predict,
  * sg_surrogate_step and sg_ppo_update is kernels only (no memset or memcpy
  * nodes), so a call can be captured on
- * the context's stream. A replay repeats the call exactly as captured,
- * including its host-side counters: the noise counter (rng_step; the
- * rollout's action noise and the tracking task's goal draws) and the Adam
- * step count of sg_ppo_update do not advance across replays, and
- * sg_get_state reports the count of eager calls only.
+ * the context's stream. The counters these calls advance live in device
+ * memory and are advanced by the captured kernels themselves: the noise
+ * counter (rng_step: the rollout's action noise, the tracking task's goal
+ * draws) and the Adam step count of sg_ppo_update. Each replay of a
+ * captured sg_step / sg_rollout / sg_surrogate_step therefore draws the next
+ * steps' noise, each replay of a captured sg_ppo_update takes the next Adam
+ * steps, exactly as the same number of eager calls would.
  */
 #ifndef SURGYM_H
 #define SURGYM_H
@@ -207,7 +209,8 @@ sg_status sg_reset(sg_ctx* ctx);
  * actions [J][N] real (device), obs [W][N] real, reward [N] real,
  * done [N] uint8 (device). obs, reward, done may not alias actions. */
 sg_status sg_step(sg_ctx* ctx, const void* actions, void* obs, void* reward, uint8_t* done);
-/* (sg_step advances the noise counter rng_step by one, sg_rollout by T.) */
+/* (sg_step and sg_surrogate_step advance the noise counter rng_step by one,
+ * sg_rollout by T; the counter is device memory, see HIP graph capture.) */
 
 /* Step schedules for batches of uneven DOF (envs differ in n_dof). The
  * results do not depend on the schedule.
@@ -234,7 +237,9 @@ sg_status sg_autotune_step(sg_ctx* ctx, const void* actions, int32_t trials, int
 sg_status sg_observe(sg_ctx* ctx, void* obs);
 
 /* Copy state out / in. q, qd [J][N] real and progress [N] int32 are device
- * pointers (any may be NULL to skip); rng_step is host memory. */
+ * pointers (any may be NULL to skip); rng_step is host memory
+ * (sg_get_state with rng_step non-NULL copies the device counter out and
+ * synchronizes the stream; sg_set_state enqueues a kernel that sets it). */
 sg_status sg_get_state(sg_ctx* ctx, void* q, void* qd, int32_t* progress, uint64_t* rng_step);
 sg_status sg_set_state(sg_ctx* ctx, const void* q, const void* qd, const int32_t* progress, uint64_t rng_step);
 /* Tracking task's goal state [9][N] real (device): goal (3), goal velocity

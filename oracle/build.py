@@ -5,6 +5,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SOURCES = ["oracle.cpp"]
+# compiler flags of the oracle library (reported with its CPU timing)
+CFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-Wall"]
 HEADERS = ["chain.hpp", "counted.hpp", "env.hpp", "rl.hpp", "spatial.hpp", "surrogate.hpp"]
 
 
@@ -14,8 +16,7 @@ def build(force: bool = False) -> str:
     if not force and os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(d) for d in deps):
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-Wall",
-           "-o", tmp] + srcs
+    cmd = ["g++", *CFLAGS, "-o", tmp] + srcs
     subprocess.run(cmd, check=True, cwd=HERE)
     os.replace(tmp, LIB)
     return LIB

@@ -36,7 +36,7 @@ template <typename T> hipError_t upload(void** dst, const std::vector<double>& s
 
 void free_ctx(sg_ctx* c) {
   void* ptrs[] = {c->par, c->tip, c->nd, c->target, c->wp, c->prog0, c->q, c->qd, c->prog, c->w_bf16, c->bias,
-                  c->log_std, c->slot_env, c->tile_dof, c->adj_ws, c->gs, c->gs0};
+                  c->log_std, c->slot_env, c->tile_dof, c->adj_ws, c->gs, c->gs0, c->rng_dev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -104,7 +104,7 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
   for (int e = 0; e < N && c->uniform; ++e) c->uniform = r->n_dof[e] == J;
   for (int k = 0; k < 3; ++k) c->g[k] = r->gravity[k];
   c->task = t->task; c->K = t->task == SG_TASK_PATH ? t->n_waypoints : 1;
-  c->dwell = t->dwell > 0 ? t->dwell : 1; c->ep_len = t->ep_len; c->seed = t->seed; c->rng_step = 0;
+  c->dwell = t->dwell > 0 ? t->dwell : 1; c->ep_len = t->ep_len; c->seed = t->seed;
   c->chains = C;
   if (t->task == SG_TASK_TRACK) {
     c->trk_sigma = t->track_sigma; c->trk_offset = t->track_offset; c->trk_reset_std = t->track_reset_std;
@@ -193,6 +193,10 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
   if (e == hipSuccess) e = hipMalloc((void**)&c->tile_dof, tile_dof.size() * sizeof(int));
   if (e == hipSuccess)
     e = hipMemcpy(c->tile_dof, tile_dof.data(), tile_dof.size() * sizeof(int), hipMemcpyHostToDevice);
+  // the noise counter (8 bytes) and its completion count (4 bytes), zeroed
+  if (e == hipSuccess) e = hipMalloc((void**)&c->rng_dev, 16);
+  if (e == hipSuccess) e = hipMemset(c->rng_dev, 0, 16);
+  if (e == hipSuccess) c->rng_tick = reinterpret_cast<unsigned*>(c->rng_dev + 1);
   if (e == hipSuccess) e = hipMalloc(&c->q, JN * esz);
   if (e == hipSuccess) e = hipMalloc(&c->qd, JN * esz);
   if (e == hipSuccess) e = hipMemset(c->q, 0, JN * esz);
@@ -230,8 +234,8 @@ sg_status sg_synchronize(sg_ctx* c) {
 
 sg_status sg_reset(sg_ctx* c) {
   if (!c) return SG_E_INVAL;
-  c->rng_step = 0;
   hipError_t e = sgk::launch_reset(c);
+  if (e == hipSuccess) e = sgk::launch_set_counter(c, 0);
   return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_reset");
 }
 
@@ -240,8 +244,7 @@ sg_status sg_step(sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* don
   if (!act || !obs || !rew || !done) return fail(c, SG_E_INVAL, "sg_step: null buffer");
   if (!aligned(act) || !aligned(obs) || !aligned(rew)) return fail(c, SG_E_INVAL, "sg_step: misaligned buffer");
   if (act == obs || act == rew) return fail(c, SG_E_INVAL, "sg_step: outputs alias actions");
-  hipError_t e = sgk::launch_step(c, act, obs, rew, done);
-  c->rng_step += 1;
+  hipError_t e = sgk::launch_step(c, act, obs, rew, done, 1);
   return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_step");
 }
 
@@ -300,7 +303,7 @@ sg_status sg_autotune_step(sg_ctx* c, const void* act, int32_t trials, int32_t* 
     c->schedule = s;
     for (int k = 0; k <= trials && e == hipSuccess; ++k) {
       if (k == 1) e = hipEventRecord(e0, c->stream);
-      if (e == hipSuccess) e = sgk::launch_step(c, act, obs, rew, done);
+      if (e == hipSuccess) e = sgk::launch_step(c, act, obs, rew, done, 0);
     }
     if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -345,7 +348,12 @@ sg_status sg_get_state(sg_ctx* c, void* q, void* qd, int32_t* progress, uint64_t
   if (qd && e == hipSuccess) e = hipMemcpyAsync(qd, c->qd, JN * esz, hipMemcpyDeviceToDevice, c->stream);
   if (progress && e == hipSuccess)
     e = hipMemcpyAsync(progress, c->prog, c->N * sizeof(int), hipMemcpyDeviceToDevice, c->stream);
-  if (rng_step) *rng_step = c->rng_step;
+  if (rng_step && e == hipSuccess) {
+    uint64_t v = 0;
+    e = hipMemcpyAsync(&v, c->rng_dev, sizeof(v), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) *rng_step = v;
+  }
   return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_get_state");
 }
 
@@ -358,7 +366,7 @@ sg_status sg_set_state(sg_ctx* c, const void* q, const void* qd, const int32_t* 
   if (qd && e == hipSuccess) e = hipMemcpyAsync(c->qd, qd, JN * esz, hipMemcpyDeviceToDevice, c->stream);
   if (progress && e == hipSuccess)
     e = hipMemcpyAsync(c->prog, progress, c->N * sizeof(int), hipMemcpyDeviceToDevice, c->stream);
-  c->rng_step = rng_step;
+  if (e == hipSuccess) e = sgk::launch_set_counter(c, rng_step);
   return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_set_state");
 }
 

@@ -38,8 +38,45 @@ template <typename T> struct EnvDev {
   T* gs;
   T trk_sigma, trk_offset, trk_reset_std, trk_c[3];
   uint64_t seed;      // noise key
-  uint64_t step;      // control-step counter of this launch's first step
+  uint64_t* rng;      // device noise counter: control steps drawn so far
+  unsigned* tick;     // blocks of the current launch that have read *rng
+  uint32_t rng_add;   // this launch advances *rng by rng_add (0: leaves it)
 };
+
+// The noise counter at the start of this launch (read by every thread that
+// needs it, before advance_counter runs in its block).
+template <typename T> __device__ __forceinline__ uint64_t read_counter(const EnvDev<T>& E) {
+  return __atomic_load_n(E.rng, __ATOMIC_RELAXED);
+}
+
+// Waits until a value loaded from memory has returned (its register is an
+// operand here, so the compiler waits for the load before this point).
+__device__ __forceinline__ void settle(uint64_t v) {
+  asm volatile("" ::"v"((uint32_t)v), "v"((uint32_t)(v >> 32)));
+}
+
+// With E.rng_add != 0, advances the counter by rng_add so that the next
+// launch (or the next replay of a captured graph) draws fresh noise. One
+// thread per block calls it at the block's end. If the launch read the
+// counter (readers: v = the value this block read, and every thread of the
+// block has read it), each block takes a ticket once its read has returned
+// and the last block stores v + rng_add; the counter and ticket are written
+// by plain stores that the next launch sees. If no block read it, block 0
+// alone adds rng_add.
+template <typename T>
+__device__ __forceinline__ void advance_counter(const EnvDev<T>& E, uint64_t v, bool readers) {
+  if (!E.rng_add) return;
+  if (!readers) {
+    if (blockIdx.x == 0) *E.rng = *E.rng + E.rng_add;
+    return;
+  }
+  settle(v);  // this wave's read has returned before the ticket is taken
+  const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+  if (atomicAdd(E.tick, 1u) == nb - 1) {
+    *E.rng = v + E.rng_add;
+    *E.tick = 0u;
+  }
+}
 
 // Link parameters of env e into registers (joints < n).
 template <typename T, int J, bool PR>

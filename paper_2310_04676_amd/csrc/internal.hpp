@@ -17,7 +17,11 @@ struct sg_ctx {
   int task = 0, K = 0, dwell = 1, ep_len = 0;
   int chains = 1;  // chains per env (consecutive env indices)
   double dt = 0, g[3] = {0, 0, 0};
-  uint64_t seed = 0, rng_step = 0;
+  uint64_t seed = 0;
+  // noise counter (control steps drawn so far) and the completion count the
+  // kernel advancing it uses: device memory, so captured calls advance it
+  uint64_t* rng_dev = nullptr;
+  unsigned* rng_tick = nullptr;
   hipStream_t stream = nullptr;
   // device memory (dtype-typed unless noted)
   void* par = nullptr;      // [P_NFIELDS][J][N]
@@ -68,7 +72,9 @@ template <typename T> inline EnvDev<T> env_view(const sg_ctx* c) {
   E.trk_sigma = (T)c->trk_sigma; E.trk_offset = (T)c->trk_offset; E.trk_reset_std = (T)c->trk_reset_std;
   for (int k = 0; k < 3; ++k) E.trk_c[k] = (T)c->trk_c[k];
   E.seed = c->seed;
-  E.step = c->rng_step;
+  E.rng = c->rng_dev;
+  E.tick = c->rng_tick;
+  E.rng_add = 0;
   return E;
 }
 
@@ -80,7 +86,10 @@ int dof_bucket(int J);
 // default) on the current device, once per (device, kernel address).
 hipError_t lds_limit(const void* fn, size_t bytes);
 
-hipError_t launch_step(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done);
+// rng_add: how far the launch advances the device noise counter (sg_step: 1;
+// the autotuner's trial steps: 0).
+hipError_t launch_step(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done, int rng_add);
+hipError_t launch_set_counter(const sg_ctx* c, uint64_t value);
 hipError_t launch_observe(const sg_ctx* c, void* obs);
 hipError_t launch_fd(const sg_ctx* c, const void* q, const void* qd, const void* tau, int arm_mode, void* qdd);
 hipError_t launch_id(const sg_ctx* c, const void* q, const void* qd, const void* qdd, void* tau);

@@ -41,7 +41,8 @@ struct sg_ppo {
   int J = 0, W = 0, O = 0, P = 0;
   int off[7] = {0, 0, 0, 0, 0, 0, 0};  // W1 b1 W2 b2 W3 b3 log_std
   int max_samples = 0;
-  int t = 0;                 // Adam steps taken
+  uint64_t* tstep = nullptr; // Adam steps taken (device, so captured updates advance it)
+  unsigned* ttick = nullptr; // blocks of the current norm+Adam launch that have read it
   float* p = nullptr;        // master parameters [P]
   uint16_t* pb = nullptr;    // BF16 copy [P]
   float* g = nullptr;        // gradient [P]
@@ -403,7 +404,9 @@ struct NormAdamArgs {
   float* v;
   uint16_t* pb;
   float* scal;
-  float c_e, max_norm, lr, b1, b2, eps, c1, c2;
+  float c_e, max_norm, lr, b1, b2, eps;
+  uint64_t* tstep;  // Adam steps taken before this one; the launch advances it by one
+  unsigned* ttick;
   const float* lpart;
   int lb;
   float* stats;
@@ -414,6 +417,22 @@ struct NormAdamArgs {
 };
 
 constexpr int kNormAdamThreads = 1024;  // threads per k_ppo_norm_adam block = parameters it updates
+
+// End of a k_ppo_norm_adam Adam block (every thread calls it): once all of
+// the block's threads have read the step count, its first thread takes a
+// ticket; the last Adam block's ticket stores the new count (the gather
+// blocks do not read it).
+__device__ __forceinline__ void norm_adam_ticket(const NormAdamArgs& a, uint64_t step) {
+  // every wave's read of the count has returned before the ticket is taken
+  asm volatile("" ::"v"((uint32_t)step), "v"((uint32_t)(step >> 32)));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (atomicAdd(a.ttick, 1u) == (unsigned)a.nadam - 1) {
+      *a.tstep = step;
+      *a.ttick = 0u;
+    }
+  }
+}
 
 // The step after a minibatch gradient in one launch (the norm and
 // statistics of k_gnorm_part and k_ppo_finish, then Adam): every block sums the squares of the
@@ -428,12 +447,16 @@ __global__ void __launch_bounds__(kNormAdamThreads) k_ppo_norm_adam(NormAdamArgs
   constexpr int NT = kNormAdamThreads, NL = 16;
   __shared__ double red[NT / 64];
   __shared__ float nsh;
+  __shared__ float csh[2];
   const int t = threadIdx.x;
+  // this Adam step's number: every block reads the count; at the end the
+  // last block to have read it advances it
   if ((int)blockIdx.x >= a.nadam) {
     const int r = ((int)blockIdx.x - a.nadam) * NT + t;
     if (r < a.next.rows) gather_row(a.next, r, a.X);
     return;
   }
+  const uint64_t step = __atomic_load_n(a.tstep, __ATOMIC_RELAXED) + 1;
   // entries below ls0 as 16-byte vectors, NL loads in flight per thread;
   // the rest (at most 3 + J entries) one per thread
   double s = 0;
@@ -465,20 +488,25 @@ __global__ void __launch_bounds__(kNormAdamThreads) k_ppo_norm_adam(NormAdamArgs
     double q = 0;
     for (int w = 0; w < NT / 64; ++w) q += red[w];
     nsh = (float)sqrt(q);
+    // Adam's bias corrections 1 - beta^step
+    csh[0] = 1.f - (float)pow((double)a.b1, (double)step);
+    csh[1] = 1.f - (float)pow((double)a.b2, (double)step);
   }
   __syncthreads();
   const float n = nsh;
   const float coef = clip_coef(a.max_norm, n);
+  const float c1 = csh[0], c2 = csh[1];
   const int i0 = blockIdx.x * NT;
   const int i = i0 + t;
-  if (i < a.ls0) adam_one(i, a.g[i], coef, a.p, a.m, a.v, a.lr, a.b1, a.b2, a.eps, a.c1, a.c2, a.pb);
+  if (i < a.ls0) adam_one(i, a.g[i], coef, a.p, a.m, a.v, a.lr, a.b1, a.b2, a.eps, c1, c2, a.pb);
   if (a.ls0 >= i0 && a.ls0 < i0 + NT) {
     if (t == 0) a.scal[2] = n;
     if (a.stats) add_stats(a.lpart, a.lb, a.p + a.ls0, a.J, n, a.stats, a.w);
     __syncthreads();
     for (int j = a.ls0 + t; j < a.ls0 + a.J; j += NT)
-      adam_one(j, a.g[j] - a.c_e, coef, a.p, a.m, a.v, a.lr, a.b1, a.b2, a.eps, a.c1, a.c2, a.pb);
+      adam_one(j, a.g[j] - a.c_e, coef, a.p, a.m, a.v, a.lr, a.b1, a.b2, a.eps, c1, c2, a.pb);
   }
+  norm_adam_ticket(a, step);
 }
 
 // Rollout weight image (fragment order of mlp.hpp; see sg_set_policy),
@@ -678,6 +706,9 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   // split-K partials: one region per layer (launch_weight_grad_partials bound)
   o->ws_floats = 3 * kWeightGradWs;
   hipError_t e = palloc(o, &o->p, P);
+  uint64_t* tcount = nullptr;
+  if (e == hipSuccess) e = palloc(o, &tcount, 1);  // the step count and (after it) the completion count, zeroed
+  if (e == hipSuccess) { o->tstep = tcount; o->ttick = reinterpret_cast<unsigned*>(tcount + 1); }
   if (e == hipSuccess) e = palloc(o, &o->pb, P);
   if (e == hipSuccess) e = palloc(o, &o->g, P);
   if (e == hipSuccess) e = palloc(o, &o->m, P);
@@ -800,14 +831,12 @@ sg_status sg_ppo_update(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const sg
       // previous minibatch's k_ppo_norm_adam
       e = minibatch_grad(o, r, cfg, w, stats, false, ep > 0 || k > 0);
       if (e != hipSuccess) break;
-      o->t += 1;
       NormAdamArgs na;
       na.P = o->P; na.ls0 = o->off[6]; na.J = o->J;
       na.p = o->p; na.g = o->g; na.m = o->m; na.v = o->v; na.pb = o->pb; na.scal = o->scal;
       na.c_e = cfg->entropy_coef; na.max_norm = cfg->max_grad_norm; na.lr = cfg->lr;
       na.b1 = cfg->beta1; na.b2 = cfg->beta2; na.eps = cfg->adam_eps;
-      na.c1 = 1.f - (float)std::pow((double)cfg->beta1, o->t);
-      na.c2 = 1.f - (float)std::pow((double)cfg->beta2, o->t);
+      na.tstep = o->tstep; na.ttick = o->ttick;
       na.lpart = o->lpart; na.lb = (mb + 255) / 256; na.stats = stats; na.w = w;
       na.nadam = (o->P + kNormAdamThreads - 1) / kNormAdamThreads;
       const bool last = k + 1 == cfg->minibatches && ep + 1 == cfg->epochs;

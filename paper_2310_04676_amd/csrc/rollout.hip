@@ -23,7 +23,7 @@ struct RollArgs {
   const float* bias;
   const float* log_std;
   int T;
-  uint64_t seed, step0;
+  uint64_t seed;
   float* obs;
   float* act;
   float* logp;
@@ -57,6 +57,7 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
   const int n = M == M_UNI ? J : (active ? E.nd[e] : 0);
   const int Wd = 2 * E.J + 10;
   const size_t N = E.N;
+  const uint64_t step0 = read_counter(E);
 
   fill_weights(s_w, s_b, A.wimg, A.bias, lane);
   stage_chain<float, J>(E, e, active ? n : 0, lane, s_p);
@@ -101,7 +102,7 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
     A.val[(size_t)t * N + e] = V;
     if (t == A.T) break;
     float eps[J], a[J];
-    normals<J>(A.seed, (uint32_t)e, A.step0 + (uint64_t)t, n, eps);
+    normals<J>(A.seed, (uint32_t)e, step0 + (uint64_t)t, n, eps);
     float lp = lp_const;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -113,12 +114,13 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
     physics<float, J>(E, ps, n, a, q, qd);
     float r, tip[3], g[3];
     const uint8_t d = post_step<float, J>(E, e, n, ps, q, qd, prog, &r, A.obs + (size_t)(t + 1) * Wd * N, tip, g,
-                                          A.step0 + (uint64_t)t);
+                                          step0 + (uint64_t)t);
     obs_regs<float, J, kXMax>(E, n, q, qd, tip, g, x);
     A.rew[(size_t)t * N + e] = r;
     A.done[(size_t)t * N + e] = d;
   }
   if (active) store_state<float, J>(E, e, n, q, qd, prog);
+  if (lane == 0) advance_counter(E, step0, true);  // one wave per block
 }
 
 // The policy alone on n inputs x [W][n] -> out [J+1][n].
@@ -191,17 +193,16 @@ template <int J, int M> static hipError_t rollout_j(sg_ctx* c, int T, const sg_r
   if (e != hipSuccess) return e;
   RollArgs A;
   A.E = env_view<float>(c);
+  A.E.rng_add = (uint32_t)T;
   A.wimg = reinterpret_cast<const uint4*>(c->w_bf16);
   A.bias = c->bias;
   A.log_std = c->log_std;
   A.T = T;
   A.seed = c->seed;
-  A.step0 = c->rng_step;
   A.obs = b->obs; A.act = b->act; A.logp = b->logp; A.rew = b->rew; A.done = b->done; A.val = b->val;
   k_rollout<J, M><<<dim3((c->N + kWave - 1) / kWave), kWave, lds, c->stream>>>(A);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  c->rng_step += (uint64_t)T;
   return launch_gae(c->stream, T, c->N, b->rew, b->val, b->done, b->gamma, b->lam, b->adv, b->ret);
 }
 

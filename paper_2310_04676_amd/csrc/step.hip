@@ -49,7 +49,8 @@ int dof_bucket(int J) {
 // issued before the staging, overlapping it.
 template <typename T, int J, int M, bool CONTIG = false>
 __device__ __forceinline__ void step_body(const EnvDev<T>& E, int e, bool active, T* sp, const T* __restrict__ act,
-                                          T* __restrict__ obs, T* __restrict__ rew, uint8_t* __restrict__ done) {
+                                          T* __restrict__ obs, T* __restrict__ rew, uint8_t* __restrict__ done,
+                                          uint64_t step) {
   const int n = M == M_UNI ? J : (active ? E.nd[e] : 0);
   // (FP64 keeps the later loads: its state held across the staging spills)
   constexpr bool EARLY = CONTIG && sizeof(T) == 4;
@@ -70,7 +71,7 @@ __device__ __forceinline__ void step_body(const EnvDev<T>& E, int e, bool active
   physics<T, J>(E, ps, n, a, q, qd);
   int prog = E.prog[e];
   T r;
-  const uint8_t d = post_step<T, J>(E, e, n, ps, q, qd, prog, &r, obs, nullptr, nullptr, E.step);
+  const uint8_t d = post_step<T, J>(E, e, n, ps, q, qd, prog, &r, obs, nullptr, nullptr, step);
   store_state<T, J>(E, e, n, q, qd, prog);
   rew[e] = r;
   done[e] = d;
@@ -81,7 +82,12 @@ __global__ void __launch_bounds__(kBlk) k_step(EnvDev<T> E, const T* __restrict_
                                                T* __restrict__ rew, uint8_t* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int e = blockIdx.x * kBlk + threadIdx.x;
-  step_body<T, J, M, true>(E, e, e < E.N, reinterpret_cast<T*>(smem_raw), act, obs, rew, done);
+  // only the tracking task draws noise in the step
+  const bool reads = E.task == TASK_TRACK;
+  const uint64_t step = reads ? read_counter(E) : 0;
+  step_body<T, J, M, true>(E, e, e < E.N, reinterpret_cast<T*>(smem_raw), act, obs, rew, done, step);
+  // one wave per block: every lane read the counter above
+  if (threadIdx.x == 0) advance_counter(E, step, reads);
 }
 
 // Uneven batches: envs bucketed by DOF class into 64-slot tiles, so every
@@ -92,18 +98,18 @@ __global__ void __launch_bounds__(kBlk) k_step(EnvDev<T> E, const T* __restrict_
 // all tiles with fewer resident blocks (persistent).
 template <typename T, int JB>
 __device__ __forceinline__ void step_tile(const EnvDev<T>& E, int nd, int e, T* sp, const T* act, T* obs, T* rew,
-                                          uint8_t* done) {
+                                          uint8_t* done, uint64_t st) {
   const bool active = e >= 0;
-  if (nd == 1) step_body<T, 1, M_UNI>(E, e, active, sp, act, obs, rew, done);
-  else if (nd == 2) step_body<T, 2, M_UNI>(E, e, active, sp, act, obs, rew, done);
-  else if (nd == 4) step_body<T, 4, M_UNI>(E, e, active, sp, act, obs, rew, done);
-  else if (nd == 3) step_body<T, 4, M_GEN>(E, e, active, sp, act, obs, rew, done);
-  else if (JB >= 6 && nd == 6) step_body<T, (JB >= 6 ? 6 : 4), M_UNI>(E, e, active, sp, act, obs, rew, done);
-  else if (JB >= 6 && nd == 5) step_body<T, (JB >= 6 ? 6 : 4), M_GEN>(E, e, active, sp, act, obs, rew, done);
-  else if (JB >= 7 && nd == 7) step_body<T, (JB >= 7 ? 7 : 4), M_UNI>(E, e, active, sp, act, obs, rew, done);
-  else if (JB >= 9 && nd == 9) step_body<T, (JB >= 9 ? 9 : 4), M_UNI>(E, e, active, sp, act, obs, rew, done);
-  else if (JB >= 9 && nd == 8) step_body<T, (JB >= 9 ? 9 : 4), M_GEN>(E, e, active, sp, act, obs, rew, done);
-  else step_body<T, JB, M_GEN>(E, e, active, sp, act, obs, rew, done);
+  if (nd == 1) step_body<T, 1, M_UNI>(E, e, active, sp, act, obs, rew, done, st);
+  else if (nd == 2) step_body<T, 2, M_UNI>(E, e, active, sp, act, obs, rew, done, st);
+  else if (nd == 4) step_body<T, 4, M_UNI>(E, e, active, sp, act, obs, rew, done, st);
+  else if (nd == 3) step_body<T, 4, M_GEN>(E, e, active, sp, act, obs, rew, done, st);
+  else if (JB >= 6 && nd == 6) step_body<T, (JB >= 6 ? 6 : 4), M_UNI>(E, e, active, sp, act, obs, rew, done, st);
+  else if (JB >= 6 && nd == 5) step_body<T, (JB >= 6 ? 6 : 4), M_GEN>(E, e, active, sp, act, obs, rew, done, st);
+  else if (JB >= 7 && nd == 7) step_body<T, (JB >= 7 ? 7 : 4), M_UNI>(E, e, active, sp, act, obs, rew, done, st);
+  else if (JB >= 9 && nd == 9) step_body<T, (JB >= 9 ? 9 : 4), M_UNI>(E, e, active, sp, act, obs, rew, done, st);
+  else if (JB >= 9 && nd == 8) step_body<T, (JB >= 9 ? 9 : 4), M_GEN>(E, e, active, sp, act, obs, rew, done, st);
+  else step_body<T, JB, M_GEN>(E, e, active, sp, act, obs, rew, done, st);
 }
 
 template <typename T, int JB>
@@ -113,10 +119,13 @@ __global__ void __launch_bounds__(kBlk) k_step_tiles(EnvDev<T> E, const int* __r
                                                      T* __restrict__ rew, uint8_t* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sp = reinterpret_cast<T*>(smem_raw);
+  const bool reads = E.task == TASK_TRACK;
+  const uint64_t st = reads ? read_counter(E) : 0;
   for (int t = tile0 + blockIdx.x; t < tile0 + ntiles; t += gridDim.x) {
     const int e = slot_env[(size_t)t * kBlk + threadIdx.x];
-    step_tile<T, JB>(E, tile_dof[t], e, sp, act, obs, rew, done);
+    step_tile<T, JB>(E, tile_dof[t], e, sp, act, obs, rew, done, st);
   }
+  if (threadIdx.x == 0) advance_counter(E, st, reads);
 }
 
 template <typename T, int J, int M>
@@ -187,6 +196,15 @@ __global__ void __launch_bounds__(kBlk) k_tip(EnvDev<T> E, const T* __restrict__
   out[2 * E.N + e] = tip[2];
 }
 
+__global__ void k_set_counter(uint64_t* ctr, uint64_t v) {
+  if (threadIdx.x == 0) *ctr = v;
+}
+
+hipError_t launch_set_counter(const sg_ctx* c, uint64_t value) {
+  k_set_counter<<<1, 64, 0, c->stream>>>(c->rng_dev, value);
+  return hipGetLastError();
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_reset(EnvDev<T> E) {
   const int e = blockIdx.x * 256 + threadIdx.x;
@@ -237,11 +255,12 @@ static hipError_t launch_par(K kernel, const sg_ctx* c, Args... args) {
 
 template <typename T, int JB>
 static hipError_t step_tiles_t(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done, int tile0,
-                               int ntiles, int grid) {
+                               int ntiles, int grid, int add) {
   constexpr size_t lds = use_lds<T, JB>() ? par_lds_bytes<T, JB>() : 0;
   hipError_t e = lds_limit((const void*)k_step_tiles<T, JB>, lds);
   if (e != hipSuccess) return e;
   EnvDev<T> E = env_view<T>(c);
+  E.rng_add = (uint32_t)add;
   k_step_tiles<T, JB><<<dim3(grid), kBlk, lds, c->stream>>>(E, c->slot_env, c->tile_dof, tile0, ntiles, (const T*)act,
                                                            (T*)obs, (T*)rew, done);
   return hipGetLastError();
@@ -249,35 +268,39 @@ static hipError_t step_tiles_t(const sg_ctx* c, const void* act, void* obs, void
 
 template <typename T>
 static hipError_t tiles_t(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done, int tile0, int ntiles,
-                          int grid) {
+                          int grid, int add) {
   switch (dof_bucket(c->J)) {
-    case 1: return step_tiles_t<T, 1>(c, act, obs, rew, done, tile0, ntiles, grid);
-    case 2: return step_tiles_t<T, 2>(c, act, obs, rew, done, tile0, ntiles, grid);
-    case 4: return step_tiles_t<T, 4>(c, act, obs, rew, done, tile0, ntiles, grid);
-    case 7: return step_tiles_t<T, 7>(c, act, obs, rew, done, tile0, ntiles, grid);
-    case 9: return step_tiles_t<T, 9>(c, act, obs, rew, done, tile0, ntiles, grid);
-    default: return step_tiles_t<T, 16>(c, act, obs, rew, done, tile0, ntiles, grid);
+    case 1: return step_tiles_t<T, 1>(c, act, obs, rew, done, tile0, ntiles, grid, add);
+    case 2: return step_tiles_t<T, 2>(c, act, obs, rew, done, tile0, ntiles, grid, add);
+    case 4: return step_tiles_t<T, 4>(c, act, obs, rew, done, tile0, ntiles, grid, add);
+    case 7: return step_tiles_t<T, 7>(c, act, obs, rew, done, tile0, ntiles, grid, add);
+    case 9: return step_tiles_t<T, 9>(c, act, obs, rew, done, tile0, ntiles, grid, add);
+    default: return step_tiles_t<T, 16>(c, act, obs, rew, done, tile0, ntiles, grid, add);
   }
 }
 
+// One control step under the context's schedule; the launch that runs last
+// advances the noise counter by add.
 template <typename T>
-static hipError_t step_t(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done) {
+static hipError_t step_t(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done, int add) {
   // tiled schedules: FP32 revolute contexts only (sg_set_schedule enforces it)
   if constexpr (sizeof(T) == sizeof(float)) {
-    if (c->schedule == SG_SCHED_SORTED) return tiles_t<T>(c, act, obs, rew, done, 0, c->n_tiles, c->n_tiles);
+    if (c->schedule == SG_SCHED_SORTED) return tiles_t<T>(c, act, obs, rew, done, 0, c->n_tiles, c->n_tiles, add);
     if (c->schedule == SG_SCHED_PERSISTENT) {
       const int grid = c->n_tiles < 512 ? c->n_tiles : 512;
-      return tiles_t<T>(c, act, obs, rew, done, 0, c->n_tiles, grid);
+      return tiles_t<T>(c, act, obs, rew, done, 0, c->n_tiles, grid, add);
     }
     if (c->schedule == SG_SCHED_PER_CLASS) {
       for (size_t k = 0; k < c->cls_dof.size(); ++k) {
-        hipError_t e = tiles_t<T>(c, act, obs, rew, done, c->cls_tile0[k], c->cls_ntiles[k], c->cls_ntiles[k]);
+        const int a = k + 1 == c->cls_dof.size() ? add : 0;
+        hipError_t e = tiles_t<T>(c, act, obs, rew, done, c->cls_tile0[k], c->cls_ntiles[k], c->cls_ntiles[k], a);
         if (e != hipSuccess) return e;
       }
       return hipSuccess;
     }
   }
   EnvDev<T> E = env_view<T>(c);
+  E.rng_add = (uint32_t)add;
   SG_DISPATCH(k_step, T, E, (const T*)act, (T*)obs, (T*)rew, done);
 }
 
@@ -300,8 +323,9 @@ template <typename T> static hipError_t tip_t(const sg_ctx* c, const void* q, vo
   SG_DISPATCH(k_tip, T, E, (const T*)q, (T*)tip);
 }
 
-hipError_t launch_step(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done) {
-  return c->dtype == SG_F64 ? step_t<double>(c, act, obs, rew, done) : step_t<float>(c, act, obs, rew, done);
+hipError_t launch_step(const sg_ctx* c, const void* act, void* obs, void* rew, uint8_t* done, int rng_add) {
+  return c->dtype == SG_F64 ? step_t<double>(c, act, obs, rew, done, rng_add)
+                            : step_t<float>(c, act, obs, rew, done, rng_add);
 }
 hipError_t launch_observe(const sg_ctx* c, void* obs) {
   return c->dtype == SG_F64 ? observe_t<double>(c, obs) : observe_t<float>(c, obs);

@@ -486,6 +486,11 @@ __global__ void __launch_bounds__(256) k_sstep_f(SStepArgs A, float* __restrict_
                                                  uint8_t* __restrict__ done, int* __restrict__ n_fallback) {
   const EnvDev<float>& E = A.E;
   const int e = blockIdx.x * 256 + threadIdx.x;
+  const bool reads = E.task == TASK_TRACK;
+  const uint64_t step = reads ? read_counter(E) : 0;
+  settle(step);
+  __syncthreads();  // every wave of the block has read the counter
+  if (threadIdx.x == 0) advance_counter(E, step, reads);
   if (e == 0) {
     for (int s = 0; s < E.S; ++s) {
       if (n_fallback) n_fallback[s] = A.count[s];
@@ -501,7 +506,7 @@ __global__ void __launch_bounds__(256) k_sstep_f(SStepArgs A, float* __restrict_
   integrate<J>(E, P, n, A.qddbuf, e, q, qd);
   int prog = E.prog[e];
   float r;
-  const uint8_t d = post_step<float, J>(E, e, n, P, q, qd, prog, &r, obs, nullptr, nullptr, E.step);
+  const uint8_t d = post_step<float, J>(E, e, n, P, q, qd, prog, &r, obs, nullptr, nullptr, step);
   store_state<float, J>(E, e, n, q, qd, prog);
   rew[e] = r;
   done[e] = d;
@@ -900,6 +905,7 @@ sg_status sg_surrogate_step(sg_surrogate* s, const float* actions, float* obs, f
     else if (b <= 4) { k_sstep_a<4><<<gw, 64, 0, c->stream>>>(A); k_sstep_b<4><<<gb, 256, 0, c->stream>>>(A); }
     else { k_sstep_a<7><<<gw, 64, 0, c->stream>>>(A); k_sstep_b<7><<<gb, 256, 0, c->stream>>>(A); }
   }
+  A.E.rng_add = 1;  // the control step's last kernel advances the noise counter
   if (b <= 1) k_sstep_f<1><<<gb, 256, 0, c->stream>>>(A, obs, reward, done, n_fallback);
   else if (b <= 2) k_sstep_f<2><<<gb, 256, 0, c->stream>>>(A, obs, reward, done, n_fallback);
   else if (b <= 4) k_sstep_f<4><<<gb, 256, 0, c->stream>>>(A, obs, reward, done, n_fallback);
