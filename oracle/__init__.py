@@ -34,7 +34,8 @@ class _Task(C.Structure):
     _fields_ = [("task", C.c_int32), ("n_waypoints", C.c_int32), ("dwell", C.c_int32),
                 ("ep_len", C.c_int32), ("target", _dp), ("waypoints", _dp), ("trk_sigma", C.c_double),
                 ("trk_offset", C.c_double), ("trk_reset_std", C.c_double), ("trk_centre", C.c_double * 3),
-                ("chains", C.c_int32)]
+                ("chains", C.c_int32), ("rerand", C.c_int32), ("n_banks", C.c_int32),
+                ("rand_centre", C.c_double * 3), ("rand_half", C.c_double)]
 
 
 TASK_TRACK = 2
@@ -44,6 +45,14 @@ def _track_params(task):
     tr = getattr(task, "track", None) or {}
     return (float(tr.get("sigma", 0.0)), float(tr.get("offset", 0.0)), float(tr.get("reset_std", 0.0)),
             (C.c_double * 3)(*tr.get("centre", (0.0, 0.0, 0.0))))
+
+
+def _rerand_params(task):
+    rr = getattr(task, "rerand", None)
+    if rr is None:
+        return (0, 1, (C.c_double * 3)(0.0, 0.0, 0.0), 0.0)
+    return (1, int(getattr(task, "n_banks", 1) or 1), (C.c_double * 3)(*rr.get("centre", (0.0, 0.0, 0.0))),
+            float(rr.get("half", 0.0)))
 
 
 class _Policy(C.Structure):
@@ -94,9 +103,10 @@ class Oracle:
             wps = None if task.waypoints is None else _f64(task.waypoints)
             k.extend([tgt, wps])
             self.t = _Task(task.task, task.n_waypoints, task.dwell, task.ep_len, _ptr(tgt), _ptr(wps),
-                           *_track_params(task), int(getattr(task, "chains", 1) or 1))
+                           *_track_params(task), int(getattr(task, "chains", 1) or 1), *_rerand_params(task))
         else:
-            self.t = _Task(0, 0, 1, 0, None, None, 0.0, 0.0, 0.0, (C.c_double * 3)(0.0, 0.0, 0.0), 1)
+            self.t = _Task(0, 0, 1, 0, None, None, 0.0, 0.0, 0.0, (C.c_double * 3)(0.0, 0.0, 0.0), 1, 0, 1,
+                           (C.c_double * 3)(0.0, 0.0, 0.0), 0.0)
         self.seed = int(getattr(task, "seed", 0) or 0) if task is not None else 0
         self.p = None
         if policy is not None:

@@ -44,6 +44,8 @@ enum { kTaskReach = 0, kTaskPath = 1, kTaskTrack = 2 };
 // Philox blocks of the tracking task's draws (the action noise uses blocks
 // 0..3 of the same (env, step) counter).
 enum { kBlockGoalAccel = 8, kBlockGoalReset = 9 };
+// Philox block of the per-episode re-randomisation draw (reach, path).
+enum { kBlockRerand = 10 };
 enum { kDoneEnded = 1, kDoneTimeout = 2, kDoneNonFinite = 4 };
 
 template <class T> struct Drive {
@@ -61,6 +63,12 @@ struct TaskSpec {
   double trk_sigma, trk_offset, trk_reset_std, trk_centre[3];
   // multi-tool reaching (paper Sec. IV): C consecutive chains form one env
   int chains = 1;
+  // per-episode re-randomisation (reach and path, one chain per env): each
+  // new episode draws its target in the box centre +- half per axis (reach)
+  // or one of the n_banks waypoint sets (path; wp_all [n_banks K][3][N])
+  int rerand = 0, n_banks = 1, N = 0;
+  double rand_centre[3] = {0, 0, 0}, rand_half = 0;
+  const double* wp_all = nullptr;
 };
 
 // Moving goal of one env (tracking task): position, velocity (per control
@@ -109,6 +117,43 @@ template <class T> struct EnvGoal {
   V3<T> target;       // reach task
   V3<T> wp[32];       // path task waypoints
 };
+
+// Per-env episode goal under re-randomisation: the reach target, or the
+// index of the path's waypoint set.
+template <class T> struct Rerand {
+  V3<T> target;
+  int bank = 0;
+};
+
+// The goal of the episode rr describes, into g (env = its column).
+template <class T> inline void apply_rerand(const TaskSpec& ts, const Rerand<T>& rr, int env, EnvGoal<T>& g) {
+  if (ts.task == kTaskReach) {
+    g.target = rr.target;
+  } else {
+    for (int k = 0; k < ts.n_waypoints; ++k) {
+      const double* w = ts.wp_all + ((size_t)rr.bank * ts.n_waypoints + k) * 3 * ts.N;
+      g.wp[k] = v3(T(w[0 * ts.N + env]), T(w[1 * ts.N + env]), T(w[2 * ts.N + env]));
+    }
+  }
+}
+
+// A new episode's goal (paper Sec. III: resets start new trajectories; Sec.
+// IV: targets and paths are sampled per task instance): from the four words
+// of Philox block kBlockRerand of (env, step): reach: 24-bit uniforms u_k,
+// target_k = centre_k + half (2 u_k - 1), k = 0..2; path: the set
+// floor(m n_banks / 2^24) with m = word 0 >> 8 (integer arithmetic, so
+// every implementation picks the same set).
+template <class T>
+inline void rerand_reset(const TaskSpec& ts, Rerand<T>& rr, uint64_t seed, uint32_t env, uint64_t step) {
+  Philox4 c = {{env, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)kBlockRerand}};
+  const Philox4 x = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  if (ts.task == kTaskReach) {
+    T* t = &rr.target.x;
+    for (int k = 0; k < 3; ++k) t[k] = T(ts.rand_centre[k] + ts.rand_half * (2.0 * u24(x.v[k]) - 1.0));
+  } else {
+    rr.bank = (int)(((uint64_t)(x.v[0] >> 8) * (uint64_t)ts.n_banks) >> 24);
+  }
+}
 
 template <class T> inline V3<T> goal_for(const TaskSpec& ts, const EnvGoal<T>& g, int progress) {
   if (ts.task == kTaskReach) return g.target;
@@ -180,9 +225,9 @@ inline void observe(const Chain<T>& ch, int Jmax, const TaskSpec& ts, const EnvG
 // counter (seed; env, step).
 template <class T>
 inline uint8_t env_step(const Chain<T>& ch, const Drive<T>& dr, T dt, int S, int Jmax, const TaskSpec& ts,
-                        const EnvGoal<T>& g, const T* action, T* q, T* qd, int* progress, T* reward, T* obs,
+                        EnvGoal<T>& g, const T* action, T* q, T* qd, int* progress, T* reward, T* obs,
                         T* qdd_log, Track<T>* tr = nullptr, uint64_t seed = 0, uint32_t env = 0,
-                        uint64_t step = 0) {
+                        uint64_t step = 0, Rerand<T>* rr = nullptr) {
   physics_step(ch, dr, dt, S, action, q, qd, qdd_log);
   const int n = ch.n;
   Pose<T> P;
@@ -207,6 +252,10 @@ inline uint8_t env_step(const Chain<T>& ch, const Drive<T>& dr, T dt, int S, int
     }
     *progress = 0;
     if (tr) track_reset(ts, *tr, seed, env, step);
+    if (rr) {
+      rerand_reset(ts, *rr, seed, env, step);
+      apply_rerand(ts, *rr, (int)env, g);
+    }
   } else if (tr) {
     track_advance(ts, *tr, seed, env, step);
   }

@@ -50,6 +50,10 @@ typedef struct {
   const double* waypoints;  // [K][3][N]
   double trk_sigma, trk_offset, trk_reset_std, trk_centre[3];  // tracking task
   int32_t chains;           // chains per env (multi-tool reaching); <= 1: one
+  // per-episode re-randomisation (reach, path; one chain per env): waypoints
+  // then hold n_banks sets [n_banks K][3][N]
+  int32_t rerand, n_banks;
+  double rand_centre[3], rand_half;
 } ora_task;
 
 typedef struct {
@@ -100,7 +104,7 @@ template <class T> Drive<T> load_drive(const ora_robot* r, int e) {
   return d;
 }
 
-TaskSpec load_taskspec(const ora_task* t) {
+TaskSpec load_taskspec(const ora_task* t, int N) {
   TaskSpec s;
   s.task = t->task;
   s.n_waypoints = t->n_waypoints;
@@ -111,6 +115,12 @@ TaskSpec load_taskspec(const ora_task* t) {
   s.trk_reset_std = t->trk_reset_std;
   for (int k = 0; k < 3; ++k) s.trk_centre[k] = t->trk_centre[k];
   s.chains = t->chains > 1 ? t->chains : 1;
+  s.rerand = t->rerand;
+  s.n_banks = t->n_banks > 1 ? t->n_banks : 1;
+  for (int k = 0; k < 3; ++k) s.rand_centre[k] = t->rand_centre[k];
+  s.rand_half = t->rand_half;
+  s.wp_all = t->waypoints;
+  s.N = N;
   return s;
 }
 
@@ -269,11 +279,26 @@ static void store_track(double* gs, int N, int e, const Track<double>& tr) {
   const double v[9] = {tr.g.x, tr.g.y, tr.g.z, tr.gd.x, tr.gd.y, tr.gd.z, tr.gc.x, tr.gc.y, tr.gc.z};
   for (int k = 0; k < 9; ++k) gs[k * N + e] = v[k];
 }
+// Re-randomised reach / path tasks: goal_state [3][N] = the episode's target
+// (reach), [1][N] = the index of its waypoint set (path).
+static Rerand<double> load_rerand(const TaskSpec& ts, const double* gs, int N, int e) {
+  Rerand<double> rr;
+  if (ts.task == kTaskReach) rr.target = v3(gs[0 * N + e], gs[1 * N + e], gs[2 * N + e]);
+  else rr.bank = (int)gs[e];
+  return rr;
+}
+static void store_rerand(const TaskSpec& ts, double* gs, int N, int e, const Rerand<double>& rr) {
+  if (ts.task == kTaskReach) {
+    gs[0 * N + e] = rr.target.x; gs[1 * N + e] = rr.target.y; gs[2 * N + e] = rr.target.z;
+  } else {
+    gs[e] = (double)rr.bank;
+  }
+}
 
 int ora_observe(const ora_robot* r, const ora_task* t, const double* q, const double* qd, const int32_t* progress,
                 double* obs, const double* goal_state) {
   const int N = r->n_env, J = r->max_dof, W = 2 * J + 10;
-  TaskSpec ts = load_taskspec(t);
+  TaskSpec ts = load_taskspec(t, r->n_env);
   for (int e = 0; e < N; ++e) {
     Chain<double> ch = load_chain<double>(r, e);
     EnvGoal<double> g = load_goal<double>(t, N, e);
@@ -282,6 +307,7 @@ int ora_observe(const ora_robot* r, const ora_task* t, const double* q, const do
     gather(qd, J, N, e, ch.n, qde);
     Track<double> tr;
     if (ts.task == kTaskTrack) tr = load_track(goal_state, N, e);
+    if (ts.rerand) apply_rerand(ts, load_rerand(ts, goal_state, N, e), e, g);
     observe(ch, J, ts, g, qe, qde, progress[e], oe, ts.task == kTaskTrack ? &tr : nullptr);
     for (int w = 0; w < W; ++w) obs[w * N + e] = oe[w];
   }
@@ -295,7 +321,7 @@ int ora_step(const ora_robot* r, const ora_task* t, const double* action, double
              int32_t* progress, double* reward, uint8_t* done, double* obs, double* qdd_log, int e0, int e1,
              int n_threads, double* goal_state, uint64_t seed, uint64_t step) {
   const int N = r->n_env, J = r->max_dof, W = 2 * J + 10, S = r->substeps;
-  TaskSpec ts = load_taskspec(t);
+  TaskSpec ts = load_taskspec(t, r->n_env);
   (void)n_threads;
   if (ts.chains > 1) {
     // multi-chain envs: chains [k C, (k + 1) C) form env k
@@ -363,9 +389,17 @@ int ora_step(const ora_robot* r, const ora_task* t, const double* action, double
       tr = load_track(goal_state, N, e);
       trp = &tr;
     }
+    Rerand<double> rr;
+    Rerand<double>* rrp = nullptr;
+    if (ts.rerand) {
+      rr = load_rerand(ts, goal_state, N, e);
+      apply_rerand(ts, rr, e, g);
+      rrp = &rr;
+    }
     uint8_t d = env_step(ch, dr, r->dt, S, J, ts, g, ae, qe, qde, &prog, &rew, oe, qdd_log ? qlog : nullptr, trp,
-                         seed, (uint32_t)e, step);
+                         seed, (uint32_t)e, step, rrp);
     if (trp) store_track(goal_state, N, e, tr);
+    if (rrp) store_rerand(ts, goal_state, N, e, rr);
     scatter(q, J, N, e, n, qe);
     scatter(qd, J, N, e, n, qde);
     progress[e] = prog;
@@ -384,7 +418,7 @@ int ora_step(const ora_robot* r, const ora_task* t, const double* action, double
 // alone. counts: [add, mul, div, sqrt, trans] x 2 (step, physics).
 int ora_opcount_step(const ora_robot* r, const ora_task* t, int e, const double* action, long long* counts) {
   const int N = r->n_env, J = r->max_dof;
-  TaskSpec ts = load_taskspec(t);
+  TaskSpec ts = load_taskspec(t, r->n_env);
   Chain<Counted> ch = load_chain<Counted>(r, e);
   Drive<Counted> dr = load_drive<Counted>(r, e);
   EnvGoal<Counted> g = load_goal<Counted>(t, N, e);
@@ -506,7 +540,7 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
                 double* act, double* logp, double* rew, uint8_t* done, double* val_, double* adv, double* ret,
                 int e0, int e1, int n_threads, double* goal_state) {
   const int N = r->n_env, J = r->max_dof, W = 2 * J + 10, S = r->substeps;
-  TaskSpec ts = load_taskspec(t);
+  TaskSpec ts = load_taskspec(t, r->n_env);
   MlpLayer L[3];
   for (int l = 0; l < 3; ++l) L[l] = {p->dims[l], p->dims[l + 1], p->W[l], p->b[l]};
   const double half_log_2pi = 0.91893853320467274178032973640562;
@@ -601,6 +635,13 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
       tr = load_track(goal_state, N, e);
       trp = &tr;
     }
+    Rerand<double> rr;
+    Rerand<double>* rrp = nullptr;
+    if (ts.rerand) {
+      rr = load_rerand(ts, goal_state, N, e);
+      apply_rerand(ts, rr, e, g);
+      rrp = &rr;
+    }
     for (int w = 0; w < W; ++w) x[w] = obs[(size_t)w * N + e];
     for (int s = 0; s < T; ++s) {
       mlp_forward(L, 3, x, o, emulate != 0, sa, sb);
@@ -617,7 +658,7 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
       logp[(size_t)s * N + e] = lp;
       double rw;
       uint8_t d = env_step(ch, dr, r->dt, S, J, ts, g, a, qe, qde, &prog, &rw, x, (double*)nullptr, trp, seed,
-                           (uint32_t)e, step0 + (uint64_t)s);
+                           (uint32_t)e, step0 + (uint64_t)s, rrp);
       rew[(size_t)s * N + e] = rw;
       done[(size_t)s * N + e] = d;
       for (int w = 0; w < W; ++w) obs[((size_t)(s + 1) * W + w) * N + e] = x[w];
@@ -625,6 +666,7 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
     mlp_forward(L, 3, x, o, emulate != 0, sa, sb);
     val_[(size_t)T * N + e] = o[J];
     if (trp) store_track(goal_state, N, e, tr);
+    if (rrp) store_rerand(ts, goal_state, N, e, rr);
     scatter(q, J, N, e, n, qe);
     scatter(qd, J, N, e, n, qde);
     progress[e] = prog;
@@ -883,7 +925,7 @@ int ora_adjoint(const ora_robot* r, const ora_task* t, int T, const double* act,
                 const int32_t* prog0, const double* mass_scale, int want_grad, double* loss, double* g_act,
                 double* g_mass, int threads) {
   const int N = r->n_env, J = r->max_dof;
-  const TaskSpec ts = load_taskspec(t);
+  const TaskSpec ts = load_taskspec(t, r->n_env);
 #pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : 1)
   for (int e = 0; e < N; ++e) {
     Chain<double> ch = load_chain<double>(r, e);

@@ -86,10 +86,12 @@ class Task:
     progress0: np.ndarray          # int32 [N]
     track: dict | None = None      # tracking task: sigma, offset, reset_std, centre
     chains: int = 1                # chains per env (consecutive env indices)
+    rerand: dict | None = None     # per-episode re-randomisation: reach {centre, half}; path {} (banks)
+    n_banks: int = 1               # path: waypoint sets, waypoints [n_banks K][3][N]
 
     @property
     def n_waypoints(self):
-        return 0 if self.waypoints is None else self.waypoints.shape[0]
+        return 0 if self.waypoints is None else self.waypoints.shape[0] // max(self.n_banks, 1)
 
 
 @dataclasses.dataclass
@@ -260,8 +262,13 @@ def _round_task(t: Task, dtype) -> Task:
         f = lambda v: float(np.asarray(v, dtype=dtype))
         tr = dict(sigma=f(t.track["sigma"]), offset=f(t.track["offset"]), reset_std=f(t.track["reset_std"]),
                   centre=tuple(f(c) for c in t.track["centre"]))
+    rr = None
+    if t.rerand is not None:
+        f = lambda v: float(np.asarray(v, dtype=dtype))
+        rr = {k: (tuple(f(c) for c in v) if k == "centre" else f(v)) for k, v in t.rerand.items()}
     return Task(task=t.task, target=_as_dtype(t.target, dtype), waypoints=_as_dtype(t.waypoints, dtype),
-                dwell=t.dwell, ep_len=t.ep_len, progress0=t.progress0, track=tr, chains=t.chains)
+                dwell=t.dwell, ep_len=t.ep_len, progress0=t.progress0, track=tr, chains=t.chains, rerand=rr,
+                n_banks=t.n_banks)
 
 
 def make_policy(seed: int, dims=(24, 256, 128, 8), log_std: float = np.log(0.5)) -> Policy:
@@ -327,6 +334,38 @@ def tracking(n_env: int = 4096, seed: int = 1005, dtype=np.float32) -> Workload:
              progress0=stream(seed, "progress0").integers(0, 128, size=n_env).astype(np.int32),
              track=dict(sigma=1e-4, offset=0.2, reset_std=0.05, centre=tuple(WORK_CENTRE)))
     return Workload("tracking", _round_robot(r, dtype), _round_task(t, dtype), make_policy(seed + 7), dtype, seed)
+
+
+def reach_rerand(n_env: int = 4096, seed: int = 1007, dtype=np.float32) -> Workload:
+    """Target reaching with per-episode re-randomisation: 7-DOF FP32 chains,
+    4 substeps, 128-step episodes with staggered start progress; the first
+    target is W + U[-0.25, 0.25]^3, and each reset draws the next one in the
+    same box on the device; policy 24-256-128-8."""
+    r = make_chain(n_env, 7, seed, dt=1.0 / 120.0, substeps=4, q0_frac=0.25)
+    tgt = (WORK_CENTRE[None, :] + _per_env(seed, "target", n_env, 3, -0.25, 0.25)).T.copy()
+    t = Task(task=TASK_REACH, target=tgt, waypoints=None, dwell=1, ep_len=128,
+             progress0=stream(seed, "progress0").integers(0, 128, size=n_env).astype(np.int32),
+             rerand=dict(centre=tuple(WORK_CENTRE), half=0.25))
+    return Workload("reach_rerand", _round_robot(r, dtype), _round_task(t, dtype), make_policy(seed + 7), dtype, seed)
+
+
+def path_rerand(n_env: int = 4096, seed: int = 1008, banks: int = 4, dtype=np.float32) -> Workload:
+    """Path following with per-episode re-randomisation: every env holds
+    `banks` waypoint sets (each 8 waypoints on its own natural cubic spline
+    through 4 knots in the 0.3 m box, as in path_rollout); the first
+    episode follows set 0 and each reset picks a set on the device."""
+    r = make_chain(n_env, 7, seed, dt=1.0 / 120.0, substeps=4, q0_frac=0.25)
+    sets = []
+    for b in range(banks):
+        knots = (WORK_CENTRE[None, None, :] +
+                 _per_env(seed, f"knots{b}", n_env, 12, -0.15, 0.15).reshape(n_env, 4, 3))
+        sets.append(np.stack([spline_waypoints(knots[e]) for e in range(n_env)], axis=2))  # [K][3][N]
+    wps = np.concatenate(sets, axis=0)  # [banks K][3][N]
+    prog = stream(seed, "progress0").integers(0, 128, size=n_env).astype(np.int32)
+    t = Task(task=TASK_PATH, target=None, waypoints=wps, dwell=16, ep_len=128, progress0=prog, rerand={},
+             n_banks=banks)
+    return Workload("path_rerand", _round_robot(r, dtype), _round_task(t, dtype), make_policy(seed + 7), dtype,
+                    seed)
 
 
 def multi_arm(n_env: int = 2048, chains: int = 2, seed: int = 1006, dtype=np.float32) -> Workload:
