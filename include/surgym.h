@@ -152,6 +152,19 @@ typedef struct {
                              * output stays per chain (the reward repeated).
                              * 0 or 1: one chain per env. Tiled schedules
                              * need C = 1. */
+  /* Per-episode re-randomisation (Sec. III: resets start new trajectories;
+   * Sec. IV: targets and paths sampled per task instance), reach and path
+   * tasks with one chain per env. At each reset the env draws its next
+   * goal from Philox block 10 of (env, step) under `seed`: reach: target_k
+   * = rand_centre_k + rand_half_width (2 u_k - 1) with u_k = ((word_k >> 8)
+   * + 0.5) / 2^24, k = 0..2 (the first episode uses `target`); path: the
+   * waypoint set floor((word_0 >> 8) n_banks / 2^24) of the n_banks sets in
+   * `waypoints` [n_banks K][3][N] (the first episode uses set 0). The
+   * current goal is the env's goal state (sg_get_goal_state). */
+  int32_t rerandomize;      /* 0: goals fixed at create; 1: re-randomised */
+  int32_t n_banks;          /* path: waypoint sets (1..64); 0 is taken as 1 */
+  double rand_centre[3];    /* reach: centre of the target box (m) */
+  double rand_half_width;   /* reach: half-width of the target box (m), > 0 */
 } sg_task_desc;
 
 /* Rollout storage, all DEVICE memory, float32 unless noted:
@@ -242,8 +255,11 @@ sg_status sg_observe(sg_ctx* ctx, void* obs);
  * synchronizes the stream; sg_set_state enqueues a kernel that sets it). */
 sg_status sg_get_state(sg_ctx* ctx, void* q, void* qd, int32_t* progress, uint64_t* rng_step);
 sg_status sg_set_state(sg_ctx* ctx, const void* q, const void* qd, const int32_t* progress, uint64_t rng_step);
-/* Tracking task's goal state [9][N] real (device): goal (3), goal velocity
- * (3), episode centre (3). SG_E_STATE for other tasks. */
+/* An env's mutable goal state (device, context dtype): tracking [9][N] =
+ * goal (3), goal velocity (3), episode centre (3); re-randomised reach
+ * [3][N] = the episode's target; re-randomised path [1][N] = the index of
+ * the episode's waypoint set (an integer held as a real). SG_E_STATE for
+ * tasks without one. */
 sg_status sg_get_goal_state(sg_ctx* ctx, void* goal_state);
 sg_status sg_set_goal_state(sg_ctx* ctx, const void* goal_state);
 

@@ -40,7 +40,8 @@ class TaskDesc(C.Structure):
     _fields_ = [("task", C.c_int32), ("n_waypoints", C.c_int32), ("dwell", C.c_int32), ("ep_len", C.c_int32),
                 ("target", _dp), ("waypoints", _dp), ("progress0", _ip), ("seed", C.c_uint64),
                 ("track_sigma", C.c_double), ("track_offset", C.c_double), ("track_reset_std", C.c_double),
-                ("track_centre", C.c_double * 3), ("chains_per_env", C.c_int32)]
+                ("track_centre", C.c_double * 3), ("chains_per_env", C.c_int32), ("rerandomize", C.c_int32),
+                ("n_banks", C.c_int32), ("rand_centre", C.c_double * 3), ("rand_half_width", C.c_double)]
 
 
 class RolloutBufs(C.Structure):
@@ -137,6 +138,12 @@ def make_descs(robot, task, dtype, seed=0):
                   seed & 0xFFFFFFFFFFFFFFFF, float(tr.get("sigma", 0.0)), float(tr.get("offset", 0.0)),
                   float(tr.get("reset_std", 0.0)), (C.c_double * 3)(*tr.get("centre", (0.0, 0.0, 0.0))),
                   int(getattr(task, "chains", 1) or 1))
+    td.n_banks = int(getattr(task, "n_banks", 1) or 1)
+    rr = getattr(task, "rerand", None)
+    if rr is not None:
+        td.rerandomize = 1
+        td.rand_centre = (C.c_double * 3)(*rr.get("centre", (0.0, 0.0, 0.0)))
+        td.rand_half_width = float(rr.get("half", 0.0))
     return rd, td, keep
 
 
@@ -158,6 +165,7 @@ class Sim:
         if st != SG_OK:
             raise SgError(st, lib.sg_last_error(None).decode())
         self.ctx = ctx
+        self.task = task
         self.policy_dims = None
 
     def close(self):
@@ -591,9 +599,19 @@ lib.sg_get_goal_state.argtypes = [_vp, _vp]
 lib.sg_set_goal_state.argtypes = [_vp, _vp]
 
 
+def _goal_rows(task):
+    if task.task == SG_TASK_TRACK:
+        return 9
+    if getattr(task, "rerand", None) is not None:
+        return 3 if task.task == SG_TASK_REACH else 1
+    return 0
+
+
 def _get_goal_state(self):
-    """Tracking task: goal, goal velocity, episode centre [9][N]."""
-    gs = self._empty(9, self.N)
+    """The envs' goal state: tracking [9][N] (goal, goal velocity, episode
+    centre); re-randomised reach [3][N] (target); re-randomised path [1][N]
+    (waypoint-set index)."""
+    gs = self._empty(max(_goal_rows(self.task), 1), self.N)
     self._call(lib.sg_get_goal_state, _dptr(gs))
     return gs
 

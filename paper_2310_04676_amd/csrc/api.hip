@@ -70,6 +70,18 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
   if (t->task == SG_TASK_PATH &&
       (!t->waypoints || t->n_waypoints < 1 || t->n_waypoints > SG_MAX_WAYPOINTS || t->dwell < 1))
     return fail(nullptr, SG_E_INVAL, "sg_create: path task needs 1..32 waypoints and dwell >= 1");
+  const int n_banks = t->n_banks > 1 ? t->n_banks : 1;
+  if (t->rerandomize) {
+    if (t->task == SG_TASK_TRACK)
+      return fail(nullptr, SG_E_INVAL, "sg_create: tracking re-draws its goals already (rerandomize is for reach/path)");
+    if (t->chains_per_env > 1)
+      return fail(nullptr, SG_E_UNSUPPORTED, "sg_create: rerandomize needs one chain per env");
+    if (t->task == SG_TASK_REACH && !(t->rand_half_width > 0))
+      return fail(nullptr, SG_E_INVAL, "sg_create: rerandomize (reach) needs rand_half_width > 0");
+    if (t->task == SG_TASK_PATH && n_banks > 64) return fail(nullptr, SG_E_INVAL, "sg_create: n_banks must be 1..64");
+  } else if (n_banks != 1) {
+    return fail(nullptr, SG_E_INVAL, "sg_create: several waypoint sets need rerandomize");
+  }
   const int C = t->chains_per_env > 1 ? t->chains_per_env : 1;
   if (C != 1 && C != 2 && C != 4) return fail(nullptr, SG_E_UNSUPPORTED, "sg_create: chains_per_env must be 1, 2 or 4");
   if (N % C) return fail(nullptr, SG_E_INVAL, "sg_create: n_env must be a multiple of chains_per_env");
@@ -110,6 +122,12 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
     c->trk_sigma = t->track_sigma; c->trk_offset = t->track_offset; c->trk_reset_std = t->track_reset_std;
     for (int k = 0; k < 3; ++k) c->trk_c[k] = t->track_centre[k];
   }
+  if (t->rerandomize) {
+    c->rerand = 1;
+    c->n_banks = t->task == SG_TASK_PATH ? n_banks : 1;
+    c->rand_half = t->rand_half_width;
+    for (int k = 0; k < 3; ++k) c->rand_c[k] = t->rand_centre[k];
+  }
 
   // Device parameter block [P_NFIELDS][J][N]; padded joints stay zero.
   std::vector<double> par((size_t)sgk::P_NFIELDS * JN, 0.0);
@@ -144,7 +162,7 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
   std::vector<double> tip(r->tip, r->tip + 3 * (size_t)N);
   std::vector<double> tgt(3 * (size_t)N, 0.0), wps;
   if (t->target) tgt.assign(t->target, t->target + 3 * (size_t)N);
-  if (t->task == SG_TASK_PATH) wps.assign(t->waypoints, t->waypoints + (size_t)c->K * 3 * N);
+  if (t->task == SG_TASK_PATH) wps.assign(t->waypoints, t->waypoints + (size_t)c->n_banks * c->K * 3 * N);
   else wps.assign(3 * (size_t)N, 0.0);
   std::vector<int> nd(r->n_dof, r->n_dof + N), prog0(N, 0);
   // DOF-class tiles: envs of each class in env order, padded to 64 slots
@@ -179,6 +197,14 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
     std::vector<double> gs0(9 * (size_t)N, 0.0);
     for (int k = 0; k < 3; ++k)
       for (int i = 0; i < N; ++i) gs0[k * (size_t)N + i] = gs0[(6 + k) * (size_t)N + i] = tgt[k * (size_t)N + i];
+    e = up(&c->gs0, gs0);
+    if (e == hipSuccess) e = up(&c->gs, gs0);
+    c->gs_width = 9;
+  } else if (e == hipSuccess && c->rerand) {
+    // reach: the first episode's target; path: waypoint set 0
+    c->gs_width = t->task == SG_TASK_REACH ? 3 : 1;
+    std::vector<double> gs0((size_t)c->gs_width * N, 0.0);
+    if (t->task == SG_TASK_REACH) gs0 = tgt;
     e = up(&c->gs0, gs0);
     if (e == hipSuccess) e = up(&c->gs, gs0);
   }
@@ -290,7 +316,7 @@ sg_status sg_autotune_step(sg_ctx* c, const void* act, int32_t trials, int32_t* 
   if (e == hipSuccess) e = hipMemcpyAsync(qd, c->qd, JN * esz, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(pr, c->prog, c->N * sizeof(int), hipMemcpyDeviceToDevice, c->stream);
   void* gsv = nullptr;
-  const size_t gsb = 9 * (size_t)c->N * esz;
+  const size_t gsb = (size_t)c->gs_width * c->N * esz;
   if (e == hipSuccess && c->gs) e = hipMalloc(&gsv, gsb);
   if (e == hipSuccess && c->gs) e = hipMemcpyAsync(gsv, c->gs, gsb, hipMemcpyDeviceToDevice, c->stream);
   const int saved = c->schedule;
@@ -372,18 +398,18 @@ sg_status sg_set_state(sg_ctx* c, const void* q, const void* qd, const int32_t* 
 
 sg_status sg_get_goal_state(sg_ctx* c, void* gs) {
   if (!c) return SG_E_INVAL;
-  if (!c->gs) return fail(c, SG_E_STATE, "sg_get_goal_state: not a tracking task");
+  if (!c->gs) return fail(c, SG_E_STATE, "sg_get_goal_state: the task has no goal state");
   if (!gs) return fail(c, SG_E_INVAL, "sg_get_goal_state: null buffer");
-  const size_t b = 9 * (size_t)c->N * (c->dtype == SG_F64 ? sizeof(double) : sizeof(float));
+  const size_t b = (size_t)c->gs_width * c->N * (c->dtype == SG_F64 ? sizeof(double) : sizeof(float));
   hipError_t e = hipMemcpyAsync(gs, c->gs, b, hipMemcpyDeviceToDevice, c->stream);
   return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_get_goal_state");
 }
 
 sg_status sg_set_goal_state(sg_ctx* c, const void* gs) {
   if (!c) return SG_E_INVAL;
-  if (!c->gs) return fail(c, SG_E_STATE, "sg_set_goal_state: not a tracking task");
+  if (!c->gs) return fail(c, SG_E_STATE, "sg_set_goal_state: the task has no goal state");
   if (!gs) return fail(c, SG_E_INVAL, "sg_set_goal_state: null buffer");
-  const size_t b = 9 * (size_t)c->N * (c->dtype == SG_F64 ? sizeof(double) : sizeof(float));
+  const size_t b = (size_t)c->gs_width * c->N * (c->dtype == SG_F64 ? sizeof(double) : sizeof(float));
   hipError_t e = hipMemcpyAsync(c->gs, gs, b, hipMemcpyDeviceToDevice, c->stream);
   return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_set_goal_state");
 }

@@ -37,6 +37,10 @@ template <typename T> struct EnvDev {
   // random walk sigma, offset box, reset spread and nominal centre
   T* gs;
   T trk_sigma, trk_offset, trk_reset_std, trk_c[3];
+  // per-episode re-randomisation (reach: gs [3][N] = the episode's target;
+  // path: gs [1][N] = the index of its waypoint set of nbank sets)
+  int rerand, nbank;
+  T rc[3], rhalf;
   uint64_t seed;      // noise key
   uint64_t* rng;      // device noise counter: control steps drawn so far
   unsigned* tick;     // blocks of the current launch that have read *rng
@@ -240,13 +244,15 @@ __device__ __forceinline__ void goal_of(const EnvDev<T>& E, int e, int progress,
     g[1] = E.gs[E.N + e];
     g[2] = E.gs[2 * E.N + e];
   } else if (E.task == TASK_REACH) {
-    g[0] = E.target[e];
-    g[1] = E.target[E.N + e];
-    g[2] = E.target[2 * E.N + e];
+    const T* t = E.rerand ? E.gs : E.target;
+    g[0] = t[e];
+    g[1] = t[E.N + e];
+    g[2] = t[2 * E.N + e];
   } else {
     int k = progress / E.dwell;
     k = k > E.K - 1 ? E.K - 1 : k;
-    const T* w = E.wp + (size_t)k * 3 * E.N;
+    const int bank = E.rerand ? (int)E.gs[e] : 0;
+    const T* w = E.wp + ((size_t)bank * E.K + k) * 3 * E.N;
     g[0] = w[e];
     g[1] = w[E.N + e];
     g[2] = w[2 * E.N + e];
@@ -342,6 +348,25 @@ __device__ __forceinline__ void track_update(const EnvDev<T>& E, int e, bool res
   }
 }
 
+// Per-episode re-randomisation at a reset: the next episode's goal from
+// Philox block RNG_BLOCK_RERAND of (env, step). Reach: target_k = centre_k +
+// half (2 u_k - 1) with u_k the 24-bit uniform of word k; path: the
+// waypoint set (word 0 >> 8) nbank / 2^24 in integer arithmetic.
+template <typename T> __device__ __forceinline__ void rerand_draw(const EnvDev<T>& E, int e, uint64_t step) {
+  const U4 r = philox10(U4{(uint32_t)e, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)RNG_BLOCK_RERAND},
+                        (uint32_t)E.seed, (uint32_t)(E.seed >> 32));
+  if (E.task == TASK_REACH) {
+    const uint32_t w[3] = {r.x, r.y, r.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T u = ((T)(w[k] >> 8) + T(0.5)) * (T(1) / T(16777216));
+      E.gs[(size_t)k * E.N + e] = E.rc[k] + E.rhalf * (T(2) * u - T(1));
+    }
+  } else {
+    E.gs[e] = (T)(int)(((uint64_t)(r.x >> 8) * (uint64_t)E.nbank) >> 24);
+  }
+}
+
 // After the physics: reward on the post-step tip against the goal active
 // during the step, progress, time-out or non-finite reset, the tracking
 // goal's update, observation of the post-reset state. step = this control
@@ -391,6 +416,7 @@ __device__ __forceinline__ uint8_t post_step(const EnvDev<T>& E, int e, int n, P
     tip_fk<T, J>(ps, n, q, tipl, tip);
   }
   if (E.task == TASK_TRACK) track_update(E, e, done != 0, step);
+  if (E.rerand && done) rerand_draw(E, e, step);
   goal_of(E, e, prog, g);
   if (obs) write_obs<T, J>(E, e, n, q, qd, tip, g, obs);
   if (tip_out) { tip_out[0] = tip[0]; tip_out[1] = tip[1]; tip_out[2] = tip[2]; }

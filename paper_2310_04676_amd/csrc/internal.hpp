@@ -37,6 +37,10 @@ struct sg_ctx {
   // value at create (restored by sg_reset)
   void* gs = nullptr;
   void* gs0 = nullptr;
+  int gs_width = 0;  // rows of gs: 9 tracking, 3 re-randomised reach, 1 re-randomised path, 0 none
+  // per-episode re-randomisation of the reach target / path waypoint set
+  int rerand = 0, n_banks = 1;
+  double rand_c[3] = {0, 0, 0}, rand_half = 0;
   double trk_sigma = 0, trk_offset = 0, trk_reset_std = 0, trk_c[3] = {0, 0, 0};
   // DOF-class tiling for uneven batches: slots sorted by n_dof, each class
   // padded to whole 64-slot tiles (slot_env = -1 for padding).
@@ -71,6 +75,8 @@ template <typename T> inline EnvDev<T> env_view(const sg_ctx* c) {
   E.gs = (T*)c->gs;
   E.trk_sigma = (T)c->trk_sigma; E.trk_offset = (T)c->trk_offset; E.trk_reset_std = (T)c->trk_reset_std;
   for (int k = 0; k < 3; ++k) E.trk_c[k] = (T)c->trk_c[k];
+  E.rerand = c->rerand; E.nbank = c->n_banks; E.rhalf = (T)c->rand_half;
+  for (int k = 0; k < 3; ++k) E.rc[k] = (T)c->rand_c[k];
   E.seed = c->seed;
   E.rng = c->rng_dev;
   E.tick = c->rng_tick;

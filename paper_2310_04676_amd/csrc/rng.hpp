@@ -2,14 +2,14 @@
 // with Box-Muller normals. Counter (env, step lo, step hi, block), key
 // (seed lo, seed hi). Blocks 0..3 give the action noise of joints 0..15;
 // the tracking task's goal draws use blocks 8 (velocity increment) and 9
-// (new episode centre).
+// (new episode centre); per-episode re-randomisation uses block 10.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace sgk {
 
-enum { RNG_BLOCK_GOAL_ACCEL = 8, RNG_BLOCK_GOAL_RESET = 9 };
+enum { RNG_BLOCK_GOAL_ACCEL = 8, RNG_BLOCK_GOAL_RESET = 9, RNG_BLOCK_RERAND = 10 };
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) --------------------------------
 // Ten rounds of: two 32x32->64 multiplies by the round constants, with the

@@ -82,8 +82,8 @@ __global__ void __launch_bounds__(kBlk) k_step(EnvDev<T> E, const T* __restrict_
                                                T* __restrict__ rew, uint8_t* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int e = blockIdx.x * kBlk + threadIdx.x;
-  // only the tracking task draws noise in the step
-  const bool reads = E.task == TASK_TRACK;
+  // only the tracking task and re-randomised goals draw noise in the step
+  const bool reads = E.task == TASK_TRACK || E.rerand;
   const uint64_t step = reads ? read_counter(E) : 0;
   step_body<T, J, M, true>(E, e, e < E.N, reinterpret_cast<T*>(smem_raw), act, obs, rew, done, step);
   // one wave per block: every lane read the counter above
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(kBlk) k_step_tiles(EnvDev<T> E, const int* __r
                                                      T* __restrict__ rew, uint8_t* __restrict__ done) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sp = reinterpret_cast<T*>(smem_raw);
-  const bool reads = E.task == TASK_TRACK;
+  const bool reads = E.task == TASK_TRACK || E.rerand;
   const uint64_t st = reads ? read_counter(E) : 0;
   for (int t = tile0 + blockIdx.x; t < tile0 + ntiles; t += gridDim.x) {
     const int e = slot_env[(size_t)t * kBlk + threadIdx.x];
@@ -344,7 +344,7 @@ hipError_t launch_reset(const sg_ctx* c) {
   if (c->dtype == SG_F64) k_reset<double><<<g, 256, 0, c->stream>>>(env_view<double>(c));
   else k_reset<float><<<g, 256, 0, c->stream>>>(env_view<float>(c));
   if (c->gs) {
-    const size_t b = 9 * (size_t)c->N * (c->dtype == SG_F64 ? sizeof(double) : sizeof(float));
+    const size_t b = (size_t)c->gs_width * c->N * (c->dtype == SG_F64 ? sizeof(double) : sizeof(float));
     hipError_t e = hipMemcpyAsync(c->gs, c->gs0, b, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return e;
   }

@@ -486,7 +486,7 @@ __global__ void __launch_bounds__(256) k_sstep_f(SStepArgs A, float* __restrict_
                                                  uint8_t* __restrict__ done, int* __restrict__ n_fallback) {
   const EnvDev<float>& E = A.E;
   const int e = blockIdx.x * 256 + threadIdx.x;
-  const bool reads = E.task == TASK_TRACK;
+  const bool reads = E.task == TASK_TRACK || E.rerand;
   const uint64_t step = reads ? read_counter(E) : 0;
   settle(step);
   __syncthreads();  // every wave of the block has read the counter

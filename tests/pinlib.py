@@ -88,3 +88,70 @@ def bias_fd(links, tip, q, qd, grav, eps=1e-6):
 def energy(links, tip, q, qd, grav):
     M = mass_matrix(links, tip, q)
     return 0.5 * qd @ M @ qd + potential(links, tip, q, grav)
+
+
+# ---- expected share of BF16 rounding flips ---------------------------------
+def rne_bf16(x):
+    """Round float64 values to the nearest BF16 value (ties to even) via the
+    float32 bit pattern (values are first rounded to float32)."""
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _act(kind, z):
+    if kind == "tanh":
+        return np.tanh(z)
+    if kind == "elu":
+        return np.where(z > 0, z, np.expm1(np.minimum(z, 0)))
+    return z
+
+
+def flip_share(layers, acts, x, thr, trials=4, seed=0, rel_scale=None, x_err=None):
+    """Expected share of the outputs of a BF16-emulating MLP (each layer's
+    input and weights rounded to BF16, sums exact) that move by more than thr
+    when every hidden unit carries the error of an FP32 evaluation: the
+    pre-activation z + e with e ~ N(0, s^2), s = 2^-24 sqrt(K) |w . h|_2 (K
+    FP32 additions of the layer's products, K the fan-in), and the
+    activation a + f with f ~ N(0, 2^-46) (tanh or ELU formed from the
+    hardware exponential and reciprocal, whose absolute error is about one
+    FP32 unit of 1, 2^-23). Such errors only matter where they move an
+    activation across a BF16 rounding boundary (a flip of one BF16 unit), so
+    the share is the flip share to expect from a correct FP32 kernel. layers: [(W, b)]
+    with W [out][in]; acts: activation per layer ('tanh', 'elu', None);
+    x: [in][B]. x_err (optional, broadcastable to x): the standard deviation
+    of the inputs' own FP32 error where the kernel forms them itself.
+    rel_scale (per output row, optional) divides the output differences.
+    Returns the largest share over `trials` error draws."""
+    rng = np.random.default_rng(seed)
+
+    def forward(noise):
+        h = rne_bf16(x + x_err * rng.standard_normal(x.shape) if (noise and x_err is not None) else x)
+        for (W, b), kind in zip(layers, acts):
+            Wb = rne_bf16(W)
+            z = Wb @ h + b[:, None]
+            if kind is not None and noise:
+                s = 2.0 ** -24 * np.sqrt(W.shape[1]) * np.sqrt((Wb ** 2) @ (h ** 2))
+                z = z + s * rng.standard_normal(z.shape)
+            a = _act(kind, z)
+            if kind is not None and noise:
+                a = a + 2.0 ** -23 * rng.standard_normal(a.shape)
+            h = rne_bf16(a) if kind is not None else a
+        return h
+
+    ref = forward(False)
+    worst = 0.0
+    for _ in range(trials):
+        d = np.abs(forward(True) - ref)
+        if rel_scale is not None:
+            d = d / np.asarray(rel_scale)[:, None]
+        worst = max(worst, float((d > thr).mean()))
+    return worst
+
+
+def allowed_count(share, m):
+    """Outputs above the threshold allowed among m: twice the expected flip
+    share plus four binomial standard deviations (at least one output)."""
+    lam = 2.0 * share * m
+    return lam + 4.0 * np.sqrt(max(lam, 1.0))

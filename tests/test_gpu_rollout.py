@@ -3,14 +3,16 @@ GAE) and of the policy network alone, against the FP64 oracle.
 
 Tolerances:
 * policy outputs vs the oracle's BF16-emulating forward pass on the same
-  FP32 inputs: the GPU accumulates in FP32 and its tanh differs from the
-  exact one by ~1e-7, so a hidden activation can round to the neighbouring
-  BF16 value; one such flip moves an output by at most |w| * 2^-8 * |h| with
-  |w| <= 1/sqrt(fan_in), i.e. ~4e-4. A pre-activation's FP32 error
-  (~1e-7) makes a flip at one activation about 5e-5 likely, and each output
-  depends on 384 hidden activations, so ~2 % of outputs carry one flip.
-  Bound: |d out| <= 2e-3 everywhere, median <= 2e-5, at most 5 % of outputs
-  above 1e-4.
+  FP32 inputs: the GPU accumulates in FP32 and forms tanh from the hardware
+  exponential and reciprocal, so a hidden activation can round to the
+  neighbouring BF16 value; one such flip moves an output by at most
+  |w| * 2^-8 * |h| with |w| <= 1/sqrt(fan_in), i.e. ~4e-4. The share of
+  outputs that such FP32-level errors move by more than 1e-4 is derived
+  from the oracle side alone (pinlib.flip_share: the emulating forward pass
+  with every hidden unit perturbed by the error model of an FP32 evaluation,
+  on observations of the path workload): about 1.1 % for this network. The
+  check allows twice that share plus four binomial deviations of outputs
+  above 1e-4, |d out| <= 2e-3 everywhere and a median <= 2e-5.
 * log-density, GAE: relative 1e-5 (FP32 accumulation).
 * env step inside the rollout, replayed by the oracle from the stored
   observation (which holds q and qd exactly): as in the step tests.
@@ -28,11 +30,30 @@ def host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
+_SHARE = []
+
+
+def policy_flip_share():
+    """Expected share of policy outputs moved by more than 1e-4 by BF16
+    flips of a correct FP32 evaluation (see the module docstring)."""
+    if not _SHARE:
+        import pinlib
+        w = synth.path_rollout(512, seed=77)
+        o = oracle.Oracle(w.robot, w.task, w.policy)
+        q, qd = synth.random_states(5, w.robot, dtype=np.float32, qd_scale=2.0)
+        x = o.observe(q, qd, w.task.progress0)
+        layers = [(np.asarray(w.policy.W[l], np.float64), np.asarray(w.policy.b[l], np.float64)) for l in range(3)]
+        _SHARE.append(pinlib.flip_share(layers, ["tanh", "tanh", None], x.astype(np.float32), 1e-4))
+    return _SHARE[0]
+
+
 def check_policy_outputs(g, ref):
+    import pinlib
     d = np.abs(g - ref)
     assert d.max() <= 2e-3, d.max()
     assert np.median(d) <= 2e-5, np.median(d)
-    assert (d > 1e-4).mean() <= 0.05, (d > 1e-4).mean()
+    n = int((d > 1e-4).sum())
+    assert n <= pinlib.allowed_count(policy_flip_share(), d.size), (n, d.size, policy_flip_share())
 
 
 @pytest.mark.parametrize("n", [1, 64, 100, 1000])

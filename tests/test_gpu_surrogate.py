@@ -43,11 +43,17 @@ def _ref_net(W, b, norm):
                                [np.asarray(x, np.float64) for x in norm])
 
 
-def _check_outputs(g, ref, scale=1.0):
+def _check_outputs(g, ref, share, scale=1.0):
+    """Normalised outputs: |d| <= 2e-2, median <= 2e-4, and at most twice
+    the expected share of outputs above 2e-3 (plus four binomial
+    deviations), the share derived on the oracle side by pinlib.flip_share
+    for this network and these inputs."""
+    import pinlib
     d = np.abs(g - ref) / scale
     assert d.max() <= 2e-2, d.max()
     assert np.median(d) <= 2e-4, np.median(d)
-    assert (d > 2e-3).mean() <= 0.15, (d > 2e-3).mean()
+    n = int((d > 2e-3).sum())
+    assert n <= pinlib.allowed_count(share, d.size), (n, d.size, share, np.quantile(d, [0.5, 0.9, 0.99, 1.0]))
 
 
 def test_fit_norm_and_predict_match_oracle(sg):
@@ -68,7 +74,13 @@ def test_fit_norm_and_predict_match_oracle(sg):
     ref = _ref_net(W, b, norm)
     out, outn = ref.forward(x, emulate=True)
     gn = (g - norm[2][:, None]) / norm[3][:, None]
-    _check_outputs(gn, outn)
+    import pinlib
+    xn = (x - norm[0][:, None]) / norm[1][:, None]
+    layers = [(np.asarray(Wl, np.float64), np.asarray(bl, np.float64)) for Wl, bl in zip(W, b)]
+    # the kernel forms the features and their z-scores in FP32 itself
+    xerr = 2.0 ** -23 * (np.abs(x) + np.abs(norm[0][:, None])) / norm[1][:, None]
+    share = pinlib.flip_share(layers, ["elu", "elu", "elu", None], xn.astype(np.float32), 2e-3, x_err=xerr)
+    _check_outputs(gn, outn, share)
     S.close()
 
 
@@ -83,12 +95,17 @@ def test_gradients_match_oracle(sg):
     gW, gb = sg.unpack_params(host(g), S.dims)
     x = oracle.surrogate_features(o, N["q"], N["qd"], N["tau"], N["env"])
     L, rW, rb = _ref_net(W, b, norm).grad(x, N["qdd"], emulate=True)
+    _, xW, xb = _ref_net(W, b, norm).grad(x, N["qdd"], emulate=False)
     assert abs(host(loss)[0] - L) <= 1e-3 * L
     for l in range(4):
-        for a, r in ((gW[l], rW[l]), (gb[l], rb[l])):
+        for a, r, ex in ((gW[l], rW[l], xW[l]), (gb[l], rb[l], xb[l])):
             rel = np.linalg.norm(a - r) / np.linalg.norm(r)
             cos = (a.ravel() @ r.ravel()) / (np.linalg.norm(a) * np.linalg.norm(r))
             assert rel <= 2e-2 and cos >= 0.999, (l, rel, cos)
+            # element by element: within twice the whole BF16 quantisation
+            # effect (emulating minus exact gradient) plus a floor
+            bound = 2 * np.abs(r - ex) + 1e-3 * np.abs(r).max()
+            assert np.all(np.abs(a - r) <= bound), (l, np.max(np.abs(a - r) / bound))
     S.close()
 
 
