@@ -56,7 +56,17 @@ def _rerand_params(task):
 
 
 class _Policy(C.Structure):
-    _fields_ = [("dims", C.c_int32 * 4), ("W", _dp * 3), ("b", _dp * 3), ("log_std", _dp)]
+    _fields_ = [("n_layers", C.c_int32), ("dims", C.c_int32 * 5), ("W", _dp * 4), ("b", _dp * 4),
+                ("log_std", _dp), ("act", C.c_int32)]
+
+
+ACTS = {"tanh": 0, "elu": 1}
+
+
+def _arch(dims, act):
+    """PPO network code of the oracle: dims = (n_in, hidden sizes..., J)."""
+    L = len(dims) - 2
+    return (C.c_int * (L + 4))(L, dims[0], *dims[1:-1], dims[-1], ACTS[act])
 
 
 def lib():
@@ -114,8 +124,11 @@ class Oracle:
             bs = [_f64(b) for b in policy.b]
             ls = _f64(policy.log_std)
             k.extend(Ws + bs + [ls])
-            self.p = _Policy((C.c_int32 * 4)(*policy.dims), (_dp * 3)(*[_ptr(w) for w in Ws]),
-                             (_dp * 3)(*[_ptr(b) for b in bs]), _ptr(ls))
+            nl = len(policy.dims) - 1
+            dims = list(policy.dims) + [0] * (5 - len(policy.dims))
+            self.p = _Policy(nl, (C.c_int32 * 5)(*dims), (_dp * 4)(*([_ptr(w) for w in Ws] + [None] * (4 - nl))),
+                             (_dp * 4)(*([_ptr(b) for b in bs] + [None] * (4 - nl))), _ptr(ls),
+                             ACTS[getattr(policy, "act", "tanh")])
 
     # ---- dynamics -------------------------------------------------------
     def fk(self, q):
@@ -201,7 +214,7 @@ class Oracle:
     # ---- learning side ---------------------------------------------------
     def mlp(self, x, emulate=True):
         B = x.shape[1]
-        out = np.zeros((self.p.dims[3], B))
+        out = np.zeros((self.p.dims[self.p.n_layers], B))
         lib().ora_mlp_forward(C.byref(self.p), _ptr(_f64(x)), _ptr(out), C.c_int(B), C.c_int(int(emulate)))
         return out
 
@@ -367,12 +380,13 @@ def ppo_flat(policy):
     return np.concatenate([_f64(p) for p in parts])
 
 
-def ppo_grad(dims, p, x, a, logp_old, adv, ret, v_old, cfg=None, emulate=True):
-    """One minibatch: (loss, gradient [P], stats dict). x [n_in][B], a [J][B]."""
+def ppo_grad(dims, p, x, a, logp_old, adv, ret, v_old, cfg=None, emulate=True, act="tanh"):
+    """One minibatch: (loss, gradient [P], stats dict). dims = (n_in, hidden
+    sizes..., J); x [n_in][B], a [J][B]."""
     B = x.shape[1]
     g = np.zeros(p.size)
     st = np.zeros(5)
-    d = (C.c_int * 4)(*dims)
+    d = _arch(dims, act)
     f = lib().ora_ppo_grad
     f.restype = C.c_double
     loss = f(d, _ptr(_f64(p)), _ptr(_f64(x)), _ptr(_f64(a)), _ptr(_f64(logp_old)), _ptr(_f64(adv)), _ptr(_f64(ret)),
@@ -395,14 +409,14 @@ def clip_grad_norm(g, max_norm):
     return g, n
 
 
-def ppo_update(dims, p, m, v, t, bufs, T, N, perm=None, epochs=5, n_mb=4, cfg=None, emulate=True):
+def ppo_update(dims, p, m, v, t, bufs, T, N, perm=None, epochs=5, n_mb=4, cfg=None, emulate=True, act="tanh"):
     """Whole update on rollout buffers (dict of obs, act, logp, adv, ret, val
     arrays in the rollout layouts). Returns (p, m, v, t, stats)."""
     p, m, v = _f64(p).copy(), _f64(m).copy(), _f64(v).copy()
     tt = C.c_int(t)
     st = np.zeros(5)
     pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
-    rc = lib().ora_ppo_update((C.c_int * 4)(*dims), _ptr(p), _ptr(m), _ptr(v), C.byref(tt),
+    rc = lib().ora_ppo_update(_arch(dims, act), _ptr(p), _ptr(m), _ptr(v), C.byref(tt),
                               *[_ptr(_f64(bufs[k])) for k in ("obs", "act", "logp", "adv", "ret", "val")],
                               C.c_int(T), C.c_int(N), _ptr(pm, _ip), C.c_int(epochs), C.c_int(n_mb), _ppo_cfg(cfg),
                               C.c_int(int(emulate)), _ptr(st))

@@ -57,10 +57,12 @@ typedef struct {
 } ora_task;
 
 typedef struct {
-  int32_t dims[4];          // n_in, h1, h2, n_out
-  const double* W[3];       // row-major [n_out][n_in] per layer
-  const double* b[3];
+  int32_t n_layers;         // 3 or 4 (2 or 3 hidden layers)
+  int32_t dims[5];          // n_in, hidden sizes, n_out
+  const double* W[4];       // row-major [n_out][n_in] per layer
+  const double* b[4];
   const double* log_std;    // [n_out - 1]
+  int32_t act;              // hidden activation: 0 tanh, 1 ELU
 } ora_policy;
 
 }  // extern "C"
@@ -511,13 +513,14 @@ double ora_round_bf16(double x) { return round_bf16(x); }
 
 // Policy forward on B inputs: x [n_in][B], out [n_out][B] (SoA).
 int ora_mlp_forward(const ora_policy* p, const double* x, double* out, int B, int emulate) {
-  MlpLayer L[3];
-  for (int l = 0; l < 3; ++l) L[l] = {p->dims[l], p->dims[l + 1], p->W[l], p->b[l]};
-  const int n_in = p->dims[0], n_out = p->dims[3];
+  MlpLayer L[4];
+  const int nl = p->n_layers;
+  for (int l = 0; l < nl; ++l) L[l] = {p->dims[l], p->dims[l + 1], p->W[l], p->b[l]};
+  const int n_in = p->dims[0], n_out = p->dims[nl];
   double xe[1024], oe[1024], sa[1024], sb[1024];
   for (int e = 0; e < B; ++e) {
     for (int k = 0; k < n_in; ++k) xe[k] = x[k * B + e];
-    mlp_forward(L, 3, xe, oe, emulate != 0, sa, sb);
+    mlp_forward(L, nl, xe, oe, emulate != 0, sa, sb, p->act);
     for (int i = 0; i < n_out; ++i) out[i * B + e] = oe[i];
   }
   return 0;
@@ -541,8 +544,9 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
                 int e0, int e1, int n_threads, double* goal_state) {
   const int N = r->n_env, J = r->max_dof, W = 2 * J + 10, S = r->substeps;
   TaskSpec ts = load_taskspec(t, r->n_env);
-  MlpLayer L[3];
-  for (int l = 0; l < 3; ++l) L[l] = {p->dims[l], p->dims[l + 1], p->W[l], p->b[l]};
+  MlpLayer L[4];
+  const int nl = p->n_layers, hact = p->act;
+  for (int l = 0; l < nl; ++l) L[l] = {p->dims[l], p->dims[l + 1], p->W[l], p->b[l]};
   const double half_log_2pi = 0.91893853320467274178032973640562;
   if (ts.chains > 1) {
     // multi-chain envs: each chain acts on its own observation with the
@@ -580,7 +584,7 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
       for (int s = 0; s < T; ++s) {
         for (int c = 0; c < C; ++c) {
           const int e = kk * C + c, n = ch[c].n;
-          mlp_forward(L, 3, x[c], o, emulate != 0, sa, sb);
+          mlp_forward(L, nl, x[c], o, emulate != 0, sa, sb, hact);
           gaussian_noise(seed, (uint32_t)e, step0 + (uint64_t)s, n, eps);
           double lp = 0.0;
           for (int j = 0; j < n; ++j) {
@@ -605,7 +609,7 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
       }
       for (int c = 0; c < C; ++c) {
         const int e = kk * C + c;
-        mlp_forward(L, 3, x[c], o, emulate != 0, sa, sb);
+        mlp_forward(L, nl, x[c], o, emulate != 0, sa, sb, hact);
         val_[(size_t)T * N + e] = o[J];
         if (ts.task == kTaskTrack) store_track(goal_state, N, e, tr[c]);
         scatter(q, J, N, e, ch[c].n, qe[c]);
@@ -644,7 +648,7 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
     }
     for (int w = 0; w < W; ++w) x[w] = obs[(size_t)w * N + e];
     for (int s = 0; s < T; ++s) {
-      mlp_forward(L, 3, x, o, emulate != 0, sa, sb);
+      mlp_forward(L, nl, x, o, emulate != 0, sa, sb, hact);
       gaussian_noise(seed, (uint32_t)e, step0 + (uint64_t)s, n, eps);
       double lp = 0.0;
       for (int j = 0; j < n; ++j) {
@@ -663,7 +667,7 @@ int ora_rollout(const ora_robot* r, const ora_task* t, const ora_policy* p, int 
       done[(size_t)s * N + e] = d;
       for (int w = 0; w < W; ++w) obs[((size_t)(s + 1) * W + w) * N + e] = x[w];
     }
-    mlp_forward(L, 3, x, o, emulate != 0, sa, sb);
+    mlp_forward(L, nl, x, o, emulate != 0, sa, sb, hact);
     val_[(size_t)T * N + e] = o[J];
     if (trp) store_track(goal_state, N, e, tr);
     if (rrp) store_rerand(ts, goal_state, N, e, rr);
@@ -836,14 +840,22 @@ extern "C" {
 // cfg = {clip, c_v, c_e, max_norm, lr, beta1, beta2, adam_eps}
 static PpoCfg ppo_cfg(const double* c) { return PpoCfg{c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7]}; }
 
-// Gradient of one minibatch (no clipping, no update). dims = {n_in, h1, h2,
-// J}; x [n_in][B], a [J][B], logp_old, adv (already normalised), ret, v_old
+// Network of the PPO calls: arch = {L, n_in, h_1 .. h_L, J, act} (L hidden
+// layers, act 0 tanh / 1 ELU).
+static PpoNet ppo_net(const int* arch) {
+  const int L = arch[0];
+  std::vector<int> hidden(arch + 2, arch + 2 + L);
+  return PpoNet(arch[1], hidden, arch[2 + L], arch[3 + L]);
+}
+
+// Gradient of one minibatch (no clipping, no update); network arch as in
+// ppo_net; x [n_in][B], a [J][B], logp_old, adv (already normalised), ret, v_old
 // [B]. g [P] is overwritten; stats = {loss_pi, loss_v, entropy, approx_kl,
 // clip_frac}. Returns the total loss.
-double ora_ppo_grad(const int* dims, const double* p, const double* x, const double* a, const double* logp_old,
+double ora_ppo_grad(const int* arch, const double* p, const double* x, const double* a, const double* logp_old,
                     const double* adv, const double* ret, const double* v_old, int B, const double* cfg, int emulate,
                     double* g, double* stats) {
-  const PpoNet net(dims[0], dims[1], dims[2], dims[3]);
+  const PpoNet net = ppo_net(arch);
   const PpoCfg c = ppo_cfg(cfg);
   std::vector<std::vector<double>> xs(B, std::vector<double>(net.n_in)), as(B, std::vector<double>(net.J));
   std::vector<PpoSample> mb(B);
@@ -872,10 +884,10 @@ double ora_clip_grad_norm(int n, double* g, double max_norm) { return clip_grad_
 // Adam step (t counts the steps taken so far, updated). p, m, v [P] in place.
 // stats: the mean over minibatches of {loss_pi, loss_v, entropy, approx_kl,
 // clip_frac}.
-int ora_ppo_update(const int* dims, double* p, double* m, double* v, int* t, const double* obs, const double* act,
+int ora_ppo_update(const int* arch, double* p, double* m, double* v, int* t, const double* obs, const double* act,
                    const double* logp, const double* adv, const double* ret, const double* val_, int T, int N,
                    const int* perm, int epochs, int n_mb, const double* cfg, int emulate, double* stats) {
-  const PpoNet net(dims[0], dims[1], dims[2], dims[3]);
+  const PpoNet net = ppo_net(arch);
   const PpoCfg c = ppo_cfg(cfg);
   const int W = net.n_in, J = net.J, B = T * N, mbs = B / n_mb;
   if (mbs * n_mb != B) return -1;

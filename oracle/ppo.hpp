@@ -5,8 +5,10 @@
 // PPO update of the rollout policy (the paper trains with the GPU PPO of
 // Rudin et al., Sec. III "Policy learning and control"; the objective is the
 // clipped surrogate of Schulman et al., 2017). Written from the definitions:
-//   * network: x -> tanh(W1 x + b1) -> tanh(W2 h1 + b2) -> W3 h2 + b3 =
-//     [mu (J) | V]; Gaussian policy with state-independent log_std (J);
+//   * network: x -> act(W1 x + b1) -> ... -> act(W_L h + b_L) -> W_o h + b_o =
+//     [mu (J) | V], act = tanh or ELU (the rollout workload's 2 x tanh
+//     trunk, or the paper's Table II network of 256-128-64 ELU units);
+//     Gaussian policy with state-independent log_std (J);
 //   * log pi(a) = sum_j -0.5 ((a_j - mu_j) / sigma_j)^2 - log sigma_j
 //     - 0.5 log(2 pi);
 //   * ratio r = exp(log pi(a) - log pi_old(a));
@@ -38,21 +40,28 @@ struct PpoCfg {
   double lr, beta1, beta2, adam_eps;
 };
 
-// Flat parameter vector: W1 [h1][n_in], b1, W2 [h2][h1], b2, W3 [J+1][h2],
-// b3, log_std [J].
+// Flat parameter vector: per layer l (hidden layers, then the output layer
+// of J + 1 rows) W_l [out][in] then b_l [out]; then log_std [J].
 struct PpoNet {
-  int n_in, h1, h2, J;
-  int off[7];
-  int size;
-  PpoNet(int n_in_, int h1_, int h2_, int J_) : n_in(n_in_), h1(h1_), h2(h2_), J(J_) {
-    const int sz[7] = {h1 * n_in, h1, h2 * h1, h2, (J + 1) * h2, J + 1, J};
+  int n_in, J, act;
+  std::vector<int> dims;  // n_in, hidden sizes..., J + 1
+  std::vector<int> offW, offB;
+  int off_ls = 0, size = 0;
+  PpoNet(int n_in_, const std::vector<int>& hidden, int J_, int act_) : n_in(n_in_), J(J_), act(act_) {
+    dims.push_back(n_in);
+    for (int h : hidden) dims.push_back(h);
+    dims.push_back(J + 1);
     int o = 0;
-    for (int i = 0; i < 7; ++i) {
-      off[i] = o;
-      o += sz[i];
+    for (size_t l = 0; l + 1 < dims.size(); ++l) {
+      offW.push_back(o);
+      o += dims[l + 1] * dims[l];
+      offB.push_back(o);
+      o += dims[l + 1];
     }
-    size = o;
+    off_ls = o;
+    size = o + J;
   }
+  int layers() const { return (int)dims.size() - 1; }
 };
 
 struct PpoSample {
@@ -70,41 +79,37 @@ inline double bf(double x, bool emulate) { return emulate ? round_bf16(x) : x; }
 // Loss of one minibatch and its gradient (added into g, size net.size).
 inline PpoStats ppo_minibatch(const PpoNet& net, const double* p, const std::vector<PpoSample>& mb,
                               const PpoCfg& cfg, bool emulate, double* g) {
-  const int n_in = net.n_in, h1 = net.h1, h2 = net.h2, J = net.J, no = J + 1;
-  const double* W1 = p + net.off[0];
-  const double* b1 = p + net.off[1];
-  const double* W2 = p + net.off[2];
-  const double* b2 = p + net.off[3];
-  const double* W3 = p + net.off[4];
-  const double* b3 = p + net.off[5];
-  const double* ls = p + net.off[6];
+  const int L = net.layers(), J = net.J, no = J + 1;
+  const double* ls = p + net.off_ls;
   const double B = (double)mb.size();
   const double log2pi = std::log(2.0 * M_PI);
   PpoStats st;
   double H = 0;
   for (int j = 0; j < J; ++j) H += ls[j] + 0.5 + 0.5 * log2pi;
   st.entropy = H;
-  std::vector<double> x(n_in), z1(h1), a1(h1), z2(h2), a2(h2), out(no), d3(no), d2(h2), d1(h1);
+  // a[l]: input of layer l (a[0] = x), z[l]: its pre-activation
+  std::vector<std::vector<double>> a(L + 1), z(L), d(L);
+  for (int l = 0; l <= L; ++l) a[l].resize(net.dims[l]);
+  for (int l = 0; l < L; ++l) {
+    z[l].resize(net.dims[l + 1]);
+    d[l].resize(net.dims[l + 1]);
+  }
   for (const PpoSample& s : mb) {
     // forward
-    for (int k = 0; k < n_in; ++k) x[k] = bf(s.x[k], emulate);
-    for (int i = 0; i < h1; ++i) {
-      double acc = b1[i];
-      for (int k = 0; k < n_in; ++k) acc += bf(W1[i * n_in + k], emulate) * x[k];
-      z1[i] = acc;
-      a1[i] = bf(std::tanh(acc), emulate);
+    for (int k = 0; k < net.n_in; ++k) a[0][k] = bf(s.x[k], emulate);
+    for (int l = 0; l < L; ++l) {
+      const int ni = net.dims[l], nout = net.dims[l + 1];
+      const double* W = p + net.offW[l];
+      const double* b = p + net.offB[l];
+      for (int i = 0; i < nout; ++i) {
+        double acc = b[i];
+        for (int k = 0; k < ni; ++k) acc += bf(W[i * ni + k], emulate) * a[l][k];
+        z[l][i] = acc;
+        if (l + 1 < L) a[l + 1][i] = bf(hidden_act(net.act, acc), emulate);
+        else a[l + 1][i] = acc;
+      }
     }
-    for (int i = 0; i < h2; ++i) {
-      double acc = b2[i];
-      for (int k = 0; k < h1; ++k) acc += bf(W2[i * h1 + k], emulate) * a1[k];
-      z2[i] = acc;
-      a2[i] = bf(std::tanh(acc), emulate);
-    }
-    for (int i = 0; i < no; ++i) {
-      double acc = b3[i];
-      for (int k = 0; k < h2; ++k) acc += bf(W3[i * h2 + k], emulate) * a2[k];
-      out[i] = acc;
-    }
+    const std::vector<double>& out = a[L];
     // loss terms
     double logp = 0;
     for (int j = 0; j < J; ++j) {
@@ -125,47 +130,37 @@ inline PpoStats ppo_minibatch(const PpoNet& net, const double* p, const std::vec
     // the interval on the side the advantage favours
     const bool live = s.adv >= 0 ? r <= 1.0 + cfg.clip : r >= 1.0 - cfg.clip;
     const double dlogp = live ? -s.adv * r / B : 0.0;
+    std::vector<double>& dout = d[L - 1];
     for (int j = 0; j < J; ++j) {
       const double sig = std::exp(ls[j]);
       const double u = (s.a[j] - out[j]) / sig;
-      d3[j] = dlogp * u / sig;                           // dlogp/dmu = (a - mu) / sigma^2
-      g[net.off[6] + j] += dlogp * (u * u - 1.0);        // dlogp/dlog_std
+      dout[j] = dlogp * u / sig;                          // dlogp/dmu = (a - mu) / sigma^2
+      g[net.off_ls + j] += dlogp * (u * u - 1.0);         // dlogp/dlog_std
     }
     double dV;
     if (e1 >= e2) dV = 2.0 * (V - s.ret);
     else dV = std::fabs(dv) <= cfg.clip ? 2.0 * (Vc - s.ret) : 0.0;
-    d3[J] = cfg.c_v * dV / B;
-    // backward through the layers
-    for (int i = 0; i < no; ++i) {
-      const double gi = bf(d3[i], emulate);
-      g[net.off[5] + i] += d3[i];
-      for (int k = 0; k < h2; ++k) g[net.off[4] + i * h2 + k] += gi * a2[k];
-    }
-    for (int k = 0; k < h2; ++k) {
-      double acc = 0;
-      for (int i = 0; i < no; ++i) acc += bf(d3[i], emulate) * bf(W3[i * h2 + k], emulate);
-      const double t = std::tanh(z2[k]);
-      d2[k] = acc * (1.0 - t * t);
-    }
-    for (int i = 0; i < h2; ++i) {
-      const double gi = bf(d2[i], emulate);
-      g[net.off[3] + i] += d2[i];
-      for (int k = 0; k < h1; ++k) g[net.off[2] + i * h1 + k] += gi * a1[k];
-    }
-    for (int k = 0; k < h1; ++k) {
-      double acc = 0;
-      for (int i = 0; i < h2; ++i) acc += bf(d2[i], emulate) * bf(W2[i * h1 + k], emulate);
-      const double t = std::tanh(z1[k]);
-      d1[k] = acc * (1.0 - t * t);
-    }
-    for (int i = 0; i < h1; ++i) {
-      const double gi = bf(d1[i], emulate);
-      g[net.off[1] + i] += d1[i];
-      for (int k = 0; k < n_in; ++k) g[net.off[0] + i * n_in + k] += gi * x[k];
+    dout[J] = cfg.c_v * dV / B;
+    (void)no;
+    // backward through the layers: d[l] = dL/dz[l]
+    for (int l = L - 1; l >= 0; --l) {
+      const int ni = net.dims[l], nout = net.dims[l + 1];
+      const double* W = p + net.offW[l];
+      for (int i = 0; i < nout; ++i) {
+        const double gi = bf(d[l][i], emulate);
+        g[net.offB[l] + i] += d[l][i];
+        for (int k = 0; k < ni; ++k) g[net.offW[l] + i * ni + k] += gi * a[l][k];
+      }
+      if (l == 0) break;
+      for (int k = 0; k < ni; ++k) {
+        double acc = 0;
+        for (int i = 0; i < nout; ++i) acc += bf(d[l][i], emulate) * bf(W[i * ni + k], emulate);
+        d[l - 1][k] = acc * hidden_act_grad(net.act, z[l - 1][k]);
+      }
     }
   }
   // entropy bonus: dL/dlog_std_j = -c_e
-  for (int j = 0; j < J; ++j) g[net.off[6] + j] += -cfg.c_e;
+  for (int j = 0; j < J; ++j) g[net.off_ls + j] += -cfg.c_e;
   return st;
 }
 

@@ -103,7 +103,8 @@ inline void gaussian_block(uint64_t seed, uint32_t env, uint64_t step, uint32_t 
 }
 
 // ---- policy MLP ----------------------------------------------------------
-// Layer l maps n_in -> n_out with W row-major [n_out][n_in]. tanh after every
+// Layer l maps n_in -> n_out with W row-major [n_out][n_in]. A hidden
+// activation (tanh, or ELU: z for z > 0, e^z - 1 otherwise) after every
 // layer but the last.
 struct MlpLayer {
   int n_in, n_out;
@@ -111,12 +112,26 @@ struct MlpLayer {
   const double* b;
 };
 
+enum { kActTanh = 0, kActElu = 1 };
+
+template <class T> inline T hidden_act(int act, const T& z) {
+  using std::exp;
+  using std::tanh;
+  if (act == kActElu) return val(z) > 0.0 ? z : exp(z) - T(1.0);
+  return tanh(z);
+}
+// d act / dz at z
+inline double hidden_act_grad(int act, double z) {
+  if (act == kActElu) return z > 0.0 ? 1.0 : std::exp(z);
+  const double t = std::tanh(z);
+  return 1.0 - t * t;
+}
+
 // x: [n_in of layer 0]; out: [n_out of the last layer]. emulate: round each
 // layer's input to BF16 before the product.
 template <class T>
 inline void mlp_forward(const MlpLayer* layers, int n_layers, const T* x, T* out, bool emulate, T* scratch_a,
-                        T* scratch_b) {
-  using std::tanh;
+                        T* scratch_b, int act = kActTanh) {
   const T* in = x;
   T* buf[2] = {scratch_a, scratch_b};
   for (int l = 0; l < n_layers; ++l) {
@@ -127,7 +142,7 @@ inline void mlp_forward(const MlpLayer* layers, int n_layers, const T* x, T* out
     for (int i = 0; i < L.n_out; ++i) {
       T s = T(L.b[i]);
       for (int k = 0; k < L.n_in; ++k) s = s + T(L.W[i * L.n_in + k]) * xin[k];
-      o[i] = (l == n_layers - 1) ? s : tanh(s);
+      o[i] = (l == n_layers - 1) ? s : hidden_act(act, s);
     }
     in = o;
   }

@@ -96,13 +96,14 @@ class Task:
 
 @dataclasses.dataclass
 class Policy:
-    dims: tuple                    # (n_in, h1, h2, n_out)
-    W: list                        # 3 arrays [n_out][n_in], values exactly representable in BF16
-    b: list                        # 3 arrays [n_out], FP32 values
+    dims: tuple                    # (n_in, hidden sizes..., n_out)
+    W: list                        # per layer [n_out][n_in], values exactly representable in BF16
+    b: list                        # per layer [n_out], FP32 values
     log_std: np.ndarray            # [n_out - 1], FP32 values
+    act: str = "tanh"              # hidden activation: "tanh" or "elu"
 
     def w_bf16_bits(self) -> np.ndarray:
-        """Concatenated W1, W2, W3 as BF16 bit patterns (uint16)."""
+        """Concatenated layer weights as BF16 bit patterns (uint16)."""
         flat = np.concatenate([w.astype(np.float32).ravel() for w in self.W])
         return (flat.view(np.uint32) >> 16).astype(np.uint16)
 
@@ -271,11 +272,15 @@ def _round_task(t: Task, dtype) -> Task:
                 n_banks=t.n_banks)
 
 
-def make_policy(seed: int, dims=(24, 256, 128, 8), log_std: float = np.log(0.5)) -> Policy:
+TABLE2_DIMS = (24, 256, 128, 64, 8)  # the paper's Table II network: 256-128-64 ELU (+ J = 7 means and a value)
+
+
+def make_policy(seed: int, dims=(24, 256, 128, 8), log_std: float = np.log(0.5), act: str = "tanh") -> Policy:
     """Seeded policy: weights U(+-1/sqrt(fan_in)) truncated to BF16-representable
-    values (low 16 bits of the FP32 pattern cleared), FP32 biases."""
+    values (low 16 bits of the FP32 pattern cleared), FP32 biases; dims =
+    (n_in, hidden sizes..., J + 1)."""
     Ws, bs = [], []
-    for l in range(3):
+    for l in range(len(dims) - 1):
         n_in, n_out = dims[l], dims[l + 1]
         bound = 1.0 / np.sqrt(n_in)
         w = stream(seed, f"W{l}").uniform(-bound, bound, size=(n_out, n_in)).astype(np.float32)
@@ -283,8 +288,8 @@ def make_policy(seed: int, dims=(24, 256, 128, 8), log_std: float = np.log(0.5))
         b = stream(seed, f"b{l}").uniform(-bound, bound, size=n_out).astype(np.float32)
         Ws.append(w.astype(np.float64))
         bs.append(b.astype(np.float64))
-    ls = np.full(dims[3] - 1, np.float32(log_std), dtype=np.float32).astype(np.float64)
-    return Policy(dims=tuple(dims), W=Ws, b=bs, log_std=ls)
+    ls = np.full(dims[-1] - 1, np.float32(log_std), dtype=np.float32).astype(np.float64)
+    return Policy(dims=tuple(dims), W=Ws, b=bs, log_std=ls, act=act)
 
 
 def reach_fp64(n_env: int = 64, seed: int = 1001) -> Workload:

@@ -235,3 +235,66 @@ def test_ppo_emulate_gradient_matches_numpy_pass(dims, seed):
     np.testing.assert_allclose(g, ref, rtol=1e-10, atol=1e-13)
     _, gx, _ = oracle.ppo_grad(dims, p, x, a, logp_old, adv, ret, v_old, emulate=False)
     assert np.abs(gx - g).max() > 1e-6
+
+
+def _np_ppo_deep(sizes, pol, x, a, logp_old, adv, ret, v_old, cfg, act):
+    """The same emulated minibatch gradient for any depth and activation."""
+    f = (lambda z: np.tanh(z)) if act == "tanh" else (lambda z: np.where(z > 0, z, np.expm1(np.minimum(z, 0))))
+    df = (lambda z: 1 - np.tanh(z) ** 2) if act == "tanh" else (lambda z: np.where(z > 0, 1.0, np.exp(np.minimum(z, 0))))
+    L = len(pol.W)
+    J = sizes[-1] - 1
+    B = x.shape[1]
+    acts, zs = [bf16(x)], []
+    for l in range(L):
+        z = bf16(pol.W[l]) @ acts[-1] + pol.b[l][:, None]
+        zs.append(z)
+        acts.append(bf16(f(z)) if l + 1 < L else z)
+    out = acts[-1]
+    mu, V = out[:J], out[J]
+    ls = pol.log_std
+    sig = np.exp(ls)[:, None]
+    u = (a - mu) / sig
+    logp = (-0.5 * u * u - ls[:, None] - 0.5 * np.log(2 * np.pi)).sum(0)
+    r = np.exp(logp - logp_old)
+    eps = cfg["clip"]
+    live = np.where(adv >= 0, r <= 1 + eps, r >= 1 - eps)
+    dlogp = np.where(live, -adv * r / B, 0.0)
+    g_ls = (dlogp[None, :] * (u * u - 1)).sum(1) - cfg["c_e"]
+    d = np.zeros((J + 1, B))
+    d[:J] = dlogp[None, :] * u / sig
+    dv = V - v_old
+    Vc = v_old + np.clip(dv, -eps, eps)
+    e1, e2 = (V - ret) ** 2, (Vc - ret) ** 2
+    dV = np.where(e1 >= e2, 2 * (V - ret), np.where(np.abs(dv) <= eps, 2 * (Vc - ret), 0.0))
+    d[J] = cfg["c_v"] * dV / B
+    parts = []
+    for l in range(L - 1, -1, -1):
+        gd = bf16(d)
+        parts.append((gd @ acts[l].T, d.sum(1)))
+        if l > 0:
+            d = (bf16(pol.W[l]).T @ gd) * df(zs[l - 1])
+    out = []
+    for gW, gb in reversed(parts):
+        out += [gW.ravel(), gb]
+    return np.concatenate(out + [g_ls])
+
+
+@pytest.mark.parametrize("dims,seed,act", [((5, 6, 5, 4, 2), 5, "elu"), ((24, 64, 32, 16, 7), 6, "elu"),
+                                           ((5, 6, 4, 2), 7, "elu"), ((5, 6, 5, 4, 2), 8, "tanh")])
+def test_ppo_emulate_gradient_matches_numpy_pass_any_depth(dims, seed, act):
+    rng = np.random.default_rng(seed)
+    sizes = list(dims[:-1]) + [dims[-1] + 1]
+    W = [rng.normal(0, 0.7, (sizes[l + 1], sizes[l])) for l in range(len(sizes) - 1)]
+    b = [rng.normal(0, 0.3, sizes[l + 1]) for l in range(len(sizes) - 1)]
+    J = dims[-1]
+    pol = synth.Policy(dims=tuple(sizes), W=W, b=b, log_std=rng.normal(-0.5, 0.2, J), act=act)
+    p = oracle.ppo_flat(pol)
+    B = 64
+    x = rng.normal(0, 1, (dims[0], B))
+    a = rng.normal(0, 1, (J, B))
+    logp_old = rng.normal(-J, 1.0, B)
+    adv, ret, v_old = rng.normal(0, 1, B), rng.normal(0, 1, B), rng.normal(0, 1, B)
+    cfg = dict(oracle.PPO_DEFAULTS)
+    _, g, _ = oracle.ppo_grad(dims, p, x, a, logp_old, adv, ret, v_old, emulate=True, act=act)
+    ref = _np_ppo_deep(sizes, pol, x, a, logp_old, adv, ret, v_old, cfg, act)
+    np.testing.assert_allclose(g, ref, rtol=1e-10, atol=1e-13)

@@ -174,3 +174,67 @@ def test_update_is_minibatch_gradient_clip_and_adam():
     g, _ = oracle.clip_grad_norm(g, 1.0)
     ref, _, _ = oracle.adam(p, g, np.zeros_like(p), np.zeros_like(p), 1e-3, 1)
     np.testing.assert_allclose(p1, ref, rtol=1e-12, atol=1e-14)
+
+
+# ---- the paper's Table II network: three hidden layers, ELU units -----------
+DIMS3 = (5, 6, 5, 4, 2)  # n_in, h1, h2, h3, J
+
+
+def _net3(seed, dims=DIMS3, scale=0.7):
+    rng = np.random.default_rng(seed)
+    sizes = list(dims[:-1]) + [dims[-1] + 1]
+    W = [rng.normal(0, scale, (sizes[l + 1], sizes[l])) for l in range(len(sizes) - 1)]
+    b = [rng.normal(0, 0.3, sizes[l + 1]) for l in range(len(sizes) - 1)]
+    return synth.Policy(dims=tuple(sizes), W=W, b=b, log_std=rng.normal(-0.5, 0.2, dims[-1]), act="elu")
+
+
+def _elu(z):
+    return np.where(z > 0, z, np.expm1(np.minimum(z, 0)))
+
+
+def test_elu3_forward_matches_brute_force():
+    pol = _net3(11, dims=(24, 256, 128, 64, 7), scale=0.1)
+    o = oracle.Oracle(synth.make_chain(1, 1, 0, dt=0.01, substeps=1), policy=pol)
+    x = np.random.default_rng(12).normal(0, 1, (24, 40))
+    h = x
+    for l in range(3):
+        h = _elu(pol.W[l] @ h + pol.b[l][:, None])
+    out = pol.W[3] @ h + pol.b[3][:, None]
+    np.testing.assert_allclose(o.mlp(x, emulate=False), out, rtol=1e-12, atol=1e-12)
+    # ELU is the identity above zero and e^z - 1 below: a layer of positive
+    # pre-activations passes them unchanged
+    z = np.array([[0.5, -0.5, 2.0, -3.0]])
+    np.testing.assert_allclose(_elu(z), [[0.5, np.exp(-0.5) - 1, 2.0, np.exp(-3.0) - 1]], rtol=1e-15)
+
+
+def test_elu3_gradient_matches_central_differences_for_every_parameter():
+    pol = _net3(13)
+    p = oracle.ppo_flat(pol)
+    n_in, J = DIMS3[0], DIMS3[-1]
+    B = 9
+    rng = np.random.default_rng(14)
+    x = rng.normal(0, 1, (n_in, B))
+    a = rng.normal(0, 1, (J, B))
+    o = oracle.Oracle(synth.make_chain(1, 1, 0, dt=0.01, substeps=1), policy=pol)
+    mu = o.mlp(x, emulate=False)[:J]
+    logp = stats.norm.logpdf(a, mu, np.exp(pol.log_std)[:, None]).sum(0)
+    logp_old = logp - np.log(rng.uniform(0.6, 1.4, B))
+    adv, ret, vold = rng.normal(0, 1, B), rng.normal(0, 1, B), rng.normal(0, 1, B)
+    cfg = dict(clip=0.2, c_v=0.7, c_e=0.05)
+    L0, g, st = oracle.ppo_grad(DIMS3, p, x, a, logp_old, adv, ret, vold, cfg=cfg, emulate=False, act="elu")
+    assert 0 < st["clip_frac"] < 1
+    # the ELU's kink at 0 is not crossed by the differences (|z| >> h)
+    assert p.size == 6 * 5 + 6 + 5 * 6 + 5 + 4 * 5 + 4 + 3 * 4 + 3 + 2
+    h = 1e-6
+    fd = np.zeros_like(p)
+    for i in range(p.size):
+        e = np.zeros_like(p)
+        e[i] = h
+        fd[i] = (oracle.ppo_grad(DIMS3, p + e, x, a, logp_old, adv, ret, vold, cfg=cfg, emulate=False, act="elu")[0]
+                 - oracle.ppo_grad(DIMS3, p - e, x, a, logp_old, adv, ret, vold, cfg=cfg, emulate=False,
+                                   act="elu")[0]) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-8)
+    # the same network with tanh units has a different gradient: the
+    # activation is wired through
+    _, gt, _ = oracle.ppo_grad(DIMS3, p, x, a, logp_old, adv, ret, vold, cfg=cfg, emulate=False, act="tanh")
+    assert np.abs(gt - g).max() > 1e-3
