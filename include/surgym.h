@@ -276,13 +276,27 @@ sg_status sg_inverse_dynamics(sg_ctx* ctx, const void* q, const void* qd, const 
 /* Tool-tip position (forward kinematics) tip [3][N] real for q [J][N]. */
 sg_status sg_tip_position(sg_ctx* ctx, const void* q, void* tip);
 
-/* Policy of the rollout: MLP W -> h1 -> h2 -> J+1 with tanh hidden units;
- * outputs 0..J-1 are the action mean, output J the critic value.
- * w_bf16: HOST, BF16 bit patterns of W1 [h1][W], W2 [h2][h1], W3 [J+1][h2]
- * concatenated row-major; bias: HOST float32 b1 [h1], b2 [h2], b3 [J+1];
- * log_std: HOST float32 [J]. The library supports h1 = 256, h2 = 128, J <= 7
- * (SG_E_UNSUPPORTED otherwise); FP32 contexts only. */
-sg_status sg_set_policy(sg_ctx* ctx, int32_t h1, int32_t h2, const uint16_t* w_bf16, const float* bias,
+/* Architecture of the rollout policy: W -> hidden[0] -> .. ->
+ * hidden[n_hidden-1] -> J+1, hidden units tanh or ELU (z for z > 0, e^z - 1
+ * otherwise); outputs 0..J-1 are the action mean, output J the critic
+ * value. The library builds two networks: n_hidden = 2, hidden = {256, 128},
+ * tanh (the path-following rollout's policy), and n_hidden = 3, hidden =
+ * {256, 128, 64}, ELU (the network of the paper's Sec. IV Table II
+ * learning-dynamics benchmark; all-revolute chains). */
+typedef enum { SG_ACT_TANH = 0, SG_ACT_ELU = 1 } sg_activation;
+typedef struct {
+  int32_t n_hidden;   /* 2 or 3 */
+  int32_t hidden[3];  /* layer widths */
+  int32_t act;        /* sg_activation */
+} sg_policy_arch;
+
+/* Policy of the rollout (architecture arch, HOST). w_bf16: HOST, BF16 bit
+ * patterns of every layer's W [out][in] concatenated row-major (W1 [h1][W],
+ * W2 [h2][h1], (W3 [h3][h2],) Wo [J+1][h_last]); bias: HOST float32, every
+ * layer's b concatenated the same way; log_std: HOST float32 [J]. J <= 7,
+ * FP32 contexts; an architecture the library does not build returns
+ * SG_E_UNSUPPORTED. Synchronizes. */
+sg_status sg_set_policy(sg_ctx* ctx, const sg_policy_arch* arch, const uint16_t* w_bf16, const float* bias,
                         const float* log_std);
 
 /* The policy network alone on n inputs: x [W][n] float32 (device),
@@ -422,12 +436,14 @@ typedef struct {
   int32_t minibatches;  /* per pass, >= 1, dividing T N (4) */
 } sg_ppo_config;
 
-/* Create a trainer bound to an FP32 context (J <= 7) with initial FP32
- * parameters params (HOST, flat: W1 [256][W], b1 [256], W2 [128][256],
- * b2 [128], W3 [J+1][128], b3 [J+1], log_std [J]; W = 2 J + 10). The
- * context's rollout policy is set to them (BF16, round to nearest even).
- * max_samples bounds T N of later calls (1..16M). Synchronizes. */
-sg_status sg_ppo_create(sg_ctx* ctx, const float* params, int32_t max_samples, sg_ppo** out);
+/* Create a trainer bound to an FP32 context (J <= 7) for a policy of
+ * architecture arch (as in sg_set_policy) with initial FP32 parameters
+ * params (HOST, flat: per layer W [out][in] then b [out] -- W1, b1, W2, b2,
+ * (W3, b3,) Wo, bo -- then log_std [J]; W = 2 J + 10). The context's
+ * rollout policy is set to them (BF16, round to nearest even). max_samples
+ * bounds T N of later calls (1..16M). Synchronizes. */
+sg_status sg_ppo_create(sg_ctx* ctx, const sg_policy_arch* arch, const float* params, int32_t max_samples,
+                        sg_ppo** out);
 void sg_ppo_destroy(sg_ppo* ppo);
 /* Number of parameters P of the flat vector. */
 int32_t sg_ppo_param_count(const sg_ppo* ppo);

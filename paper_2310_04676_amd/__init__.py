@@ -44,6 +44,20 @@ class TaskDesc(C.Structure):
                 ("n_banks", C.c_int32), ("rand_centre", C.c_double * 3), ("rand_half_width", C.c_double)]
 
 
+class PolicyArch(C.Structure):
+    _fields_ = [("n_hidden", C.c_int32), ("hidden", C.c_int32 * 3), ("act", C.c_int32)]
+
+
+SG_ACT_TANH, SG_ACT_ELU = 0, 1
+
+
+def policy_arch(dims, act="tanh"):
+    """sg_policy_arch of a network dims = (n_in, hidden sizes..., n_out)."""
+    hidden = list(dims[1:-1])
+    return PolicyArch(len(hidden), (C.c_int32 * 3)(*(hidden + [0] * (3 - len(hidden)))),
+                      SG_ACT_ELU if act == "elu" else SG_ACT_TANH)
+
+
 class RolloutBufs(C.Structure):
     _fields_ = [("obs", _vp), ("act", _vp), ("logp", _vp), ("rew", _vp), ("done", _vp), ("val", _vp),
                 ("adv", _vp), ("ret", _vp), ("gamma", C.c_float), ("lam", C.c_float)]
@@ -66,7 +80,7 @@ lib.sg_set_state.argtypes = [_vp, _vp, _vp, _vp, C.c_uint64]
 lib.sg_forward_dynamics.argtypes = [_vp, _vp, _vp, _vp, C.c_int32, _vp]
 lib.sg_inverse_dynamics.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.sg_tip_position.argtypes = [_vp, _vp, _vp]
-lib.sg_set_policy.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp]
+lib.sg_set_policy.argtypes = [_vp, C.POINTER(PolicyArch), _vp, _vp, _vp]
 lib.sg_policy_forward.argtypes = [_vp, _vp, C.c_int32, _vp]
 lib.sg_rollout.argtypes = [_vp, C.c_int32, C.POINTER(RolloutBufs)]
 lib.sg_gae.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_float, C.c_float, _vp, _vp]
@@ -246,8 +260,9 @@ class Sim:
         w = np.ascontiguousarray(policy.w_bf16_bits())
         b = np.ascontiguousarray(policy.b_f32())
         ls = np.ascontiguousarray(policy.log_std.astype(np.float32))
-        self._call(lib.sg_set_policy, C.c_int32(policy.dims[1]), C.c_int32(policy.dims[2]),
-                   w.ctypes.data_as(_vp), b.ctypes.data_as(_vp), ls.ctypes.data_as(_vp))
+        arch = policy_arch(policy.dims, getattr(policy, "act", "tanh"))
+        self._call(lib.sg_set_policy, C.byref(arch), w.ctypes.data_as(_vp), b.ctypes.data_as(_vp),
+                   ls.ctypes.data_as(_vp))
         self.policy_dims = tuple(policy.dims)
 
     def policy_forward(self, x, out=None):
@@ -437,7 +452,7 @@ PPO_DEFAULTS = dict(clip=0.2, value_coef=1.0, entropy_coef=0.01, max_grad_norm=1
                     beta2=0.999, adam_eps=1e-8, epochs=5, minibatches=4)
 PPO_STATS = ("loss_pi", "loss_v", "entropy", "approx_kl", "clip_frac", "grad_norm")
 
-lib.sg_ppo_create.argtypes = [_vp, _vp, C.c_int32, C.POINTER(_vp)]
+lib.sg_ppo_create.argtypes = [_vp, C.POINTER(PolicyArch), _vp, C.c_int32, C.POINTER(_vp)]
 lib.sg_ppo_destroy.argtypes = [_vp]
 lib.sg_ppo_destroy.restype = None
 lib.sg_ppo_param_count.argtypes = [_vp]
@@ -465,18 +480,23 @@ def _ppo_cfg(cfg):
 class Ppo:
     """PPO trainer of a Sim's rollout policy (``sg_ppo``)."""
 
-    def __init__(self, sim: Sim, params, max_samples: int):
+    def __init__(self, sim: Sim, params, max_samples: int, dims=None, act="tanh"):
+        """dims = (n_in, hidden sizes..., J + 1) of the policy (default: the
+        rollout's 256-128 tanh network); act its hidden activation."""
         self.sim = sim
         p = np.ascontiguousarray(params, dtype=np.float32)
         W, J = 2 * sim.J + 10, sim.J
-        want = 256 * W + 256 + 128 * 256 + 128 + (J + 1) * 128 + (J + 1) + J
+        dims = tuple(dims) if dims is not None else (W, 256, 128, J + 1)
+        want = sum(dims[l + 1] * dims[l] + dims[l + 1] for l in range(len(dims) - 1)) + J
         if p.size != want:
             raise ValueError(f"expected {want} parameters, got {p.size}")
         h = _vp()
-        sim._call(lib.sg_ppo_create, p.ctypes.data_as(_vp), C.c_int32(max_samples), C.byref(h))
+        arch = policy_arch(dims, act)
+        sim._call(lib.sg_ppo_create, C.byref(arch), p.ctypes.data_as(_vp), C.c_int32(max_samples), C.byref(h))
         self.h = h
         self.P = lib.sg_ppo_param_count(h)
-        sim.policy_dims = (W, 256, 128, J + 1)
+        self.dims, self.act = dims, act
+        sim.policy_dims = dims
 
     def close(self):
         if getattr(self, "h", None):

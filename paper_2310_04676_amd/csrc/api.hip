@@ -43,6 +43,45 @@ void free_ctx(sg_ctx* c) {
 
 }  // namespace
 
+namespace {
+
+// The policy's weight and bias images (the layout of mlp.hpp, through
+// img_source) from per-layer BF16 weights and FP32 biases.
+template <int H3>
+void pack_policy_host(int W, int O, const uint16_t* const* Wl, const float* const* bl, std::vector<uint16_t>& img,
+                      std::vector<float>& bimg) {
+  using S = sgk::PolicyShape<H3>;
+  const int in[4] = {W, sgk::kH1, sgk::kH2, H3 ? H3 : sgk::kH2};
+  const int lo = H3 ? 3 : 2;  // index of the output layer among Wl
+  img.assign((size_t)S::kWFrags * 8, 0);
+  for (int f = 0; f < S::kWFrags / 64; ++f)
+    for (int l = 0; l < 64; ++l)
+      for (int s = 0; s < 8; ++s) {
+        int layer, row, k;
+        if (!sgk::img_source<H3>(f, l, s, W, O, &layer, &row, &k)) continue;
+        const int L = layer == 3 ? lo : layer;
+        const int K = layer == 3 ? in[3] : in[layer];
+        img[((size_t)f * 64 + l) * 8 + s] = Wl[L][(size_t)row * K + k];
+      }
+  bimg.assign(S::kBias, 0.f);
+  for (int i = 0; i < sgk::kH1; ++i) bimg[i] = bl[0][i];
+  for (int i = 0; i < sgk::kH2; ++i) bimg[sgk::kH1 + i] = bl[1][i];
+  for (int i = 0; i < H3; ++i) bimg[sgk::kH1 + sgk::kH2 + i] = bl[2][i];
+  for (int i = 0; i < O; ++i) bimg[sgk::kH1 + sgk::kH2 + H3 + i] = bl[lo][i];
+}
+
+}  // namespace
+
+// The two networks the kernels are built for; 0 for the 256-128 tanh one,
+// 64 (its third width) for the 256-128-64 ELU one, -1 otherwise.
+int policy_h3(const sg_policy_arch* a) {
+  if (!a) return -1;
+  if (a->n_hidden == 2 && a->hidden[0] == 256 && a->hidden[1] == 128 && a->act == SG_ACT_TANH) return 0;
+  if (a->n_hidden == 3 && a->hidden[0] == 256 && a->hidden[1] == 128 && a->hidden[2] == 64 && a->act == SG_ACT_ELU)
+    return 64;
+  return -1;
+}
+
 extern "C" {
 
 const char* sg_version(void) { return "surgym-mi355x 0.1 (gfx950)"; }
@@ -436,59 +475,46 @@ sg_status sg_tip_position(sg_ctx* c, const void* q, void* tip) {
   return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_tip_position");
 }
 
-sg_status sg_set_policy(sg_ctx* c, int32_t h1, int32_t h2, const uint16_t* w, const float* b, const float* log_std) {
+sg_status sg_set_policy(sg_ctx* c, const sg_policy_arch* arch, const uint16_t* w, const float* b,
+                        const float* log_std) {
   if (!c) return SG_E_INVAL;
-  if (!w || !b || !log_std) return fail(c, SG_E_INVAL, "sg_set_policy: null argument");
+  if (!arch || !w || !b || !log_std) return fail(c, SG_E_INVAL, "sg_set_policy: null argument");
   if (c->dtype != SG_F32) return fail(c, SG_E_UNSUPPORTED, "sg_set_policy: FP32 contexts only");
-  if (h1 != 256 || h2 != 128 || c->J > 7)
-    return fail(c, SG_E_UNSUPPORTED, "sg_set_policy: supported are h1 = 256, h2 = 128, max_dof <= 7");
+  const int h3 = policy_h3(arch);
+  if (h3 < 0 || c->J > 7)
+    return fail(c, SG_E_UNSUPPORTED,
+                "sg_set_policy: supported are 256-128 tanh and 256-128-64 ELU networks with max_dof <= 7");
+  if (h3 && c->prismatic) return fail(c, SG_E_UNSUPPORTED, "sg_set_policy: the 256-128-64 network needs revolute chains");
   const int W = 2 * c->J + 10, O = c->J + 1;
-  const uint16_t* W1 = w;
-  const uint16_t* W2 = W1 + (size_t)h1 * W;
-  const uint16_t* W3 = W2 + (size_t)h2 * h1;
-  // Weight image in MFMA fragment order (see mlp.hpp): fragment f, lane
-  // l = 16 g + i, slot s. Layer 1: row 16m + i, input 8g + s. Layers 2 and 3
-  // (K-block kb): input 32 kb + 4 g + s for s < 4, 32 kb + 16 + 4 g + s - 4
-  // otherwise -- the order in which the previous layer's results sit in the
-  // lanes.
-  std::vector<uint16_t> img((size_t)sgk::kWFrags * 8, 0);
-  auto kperm = [](int kb, int g, int s) { return 32 * kb + (s < 4 ? 4 * g + s : 16 + 4 * g + (s - 4)); };
-  for (int m = 0; m < 16; ++m)
-    for (int l = 0; l < 64; ++l)
-      for (int s = 0; s < 8; ++s) {
-        const int row = 16 * m + (l & 15), k = 8 * (l >> 4) + s;
-        img[((size_t)m * 64 + l) * 8 + s] = k < W ? W1[(size_t)row * W + k] : 0;
-      }
-  const size_t o2 = (size_t)sgk::kW1Frags * 8;
-  for (int m = 0; m < 8; ++m)
-    for (int kb = 0; kb < 8; ++kb)
-      for (int l = 0; l < 64; ++l)
-        for (int s = 0; s < 8; ++s) {
-          const int row = 16 * m + (l & 15), k = kperm(kb, l >> 4, s);
-          img[o2 + (((size_t)m * 8 + kb) * 64 + l) * 8 + s] = W2[(size_t)row * h1 + k];
-        }
-  const size_t o3 = o2 + (size_t)sgk::kW2Frags * 8;
-  for (int kb = 0; kb < 4; ++kb)
-    for (int l = 0; l < 64; ++l)
-      for (int s = 0; s < 8; ++s) {
-        const int row = l & 15, k = kperm(kb, l >> 4, s);
-        img[o3 + ((size_t)kb * 64 + l) * 8 + s] = row < O ? W3[(size_t)row * h2 + k] : 0;
-      }
-  std::vector<float> bimg(sgk::kBiasFloats, 0.f);
-  for (int i = 0; i < h1; ++i) bimg[i] = b[i];
-  for (int i = 0; i < h2; ++i) bimg[sgk::kH1 + i] = b[h1 + i];
-  for (int i = 0; i < O; ++i) bimg[sgk::kH1 + sgk::kH2 + i] = b[h1 + h2 + i];
+  const int dims[5] = {W, sgk::kH1, sgk::kH2, h3 ? h3 : O, O};
+  const int nl = h3 ? 4 : 3;
+  const uint16_t* Wl[4];
+  const float* bl[4];
+  size_t ow = 0, ob = 0;
+  for (int l = 0; l < nl; ++l) {
+    Wl[l] = w + ow;
+    bl[l] = b + ob;
+    ow += (size_t)dims[l + 1] * dims[l];
+    ob += dims[l + 1];
+  }
+  std::vector<uint16_t> img;
+  std::vector<float> bimg;
+  if (h3) pack_policy_host<64>(W, O, Wl, bl, img, bimg);
+  else pack_policy_host<0>(W, O, Wl, bl, img, bimg);
   hipError_t e = hipSuccess;
-  if (!c->w_bf16) e = hipMalloc((void**)&c->w_bf16, img.size() * sizeof(uint16_t));
-  if (e == hipSuccess && !c->bias) e = hipMalloc((void**)&c->bias, bimg.size() * sizeof(float));
+  // buffers sized for the larger network, so either can be set later
+  if (!c->w_bf16) e = hipMalloc((void**)&c->w_bf16, (size_t)sgk::kWFragsMax * 16);
+  if (e == hipSuccess && !c->bias) e = hipMalloc((void**)&c->bias, (size_t)sgk::kBiasMax * sizeof(float));
   if (e == hipSuccess && !c->log_std) e = hipMalloc((void**)&c->log_std, c->J * sizeof(float));
   if (e == hipSuccess) e = hipMemcpy(c->w_bf16, img.data(), img.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->bias, bimg.data(), bimg.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->log_std, log_std, c->J * sizeof(float), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(c, e, "sg_set_policy");
   c->has_policy = 1;
-  c->h1 = h1;
-  c->h2 = h2;
+  c->h1 = sgk::kH1;
+  c->h2 = sgk::kH2;
+  c->h3 = h3;
+  c->pact = arch->act;
   return SG_OK;
 }
 

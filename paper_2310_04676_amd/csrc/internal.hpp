@@ -50,7 +50,7 @@ struct sg_ctx {
   int* tile_dof = nullptr;        // [n_tiles]
   std::vector<int> cls_dof, cls_tile0, cls_ntiles;  // per DOF class (host)
   // policy (FP32 contexts)
-  int has_policy = 0, h1 = 0, h2 = 0;
+  int has_policy = 0, h1 = 0, h2 = 0, h3 = 0, pact = 0;  // policy widths (h3 = 0: two hidden layers), activation
   uint16_t* w_bf16 = nullptr;  // W1 | W2 | W3 row-major BF16
   float* bias = nullptr;       // b1 | b2 | b3
   float* log_std = nullptr;    // [J]
@@ -59,6 +59,10 @@ struct sg_ctx {
   size_t adj_ws_floats = 0;
   std::string err;
 };
+
+// Third hidden width of a supported policy architecture (0: two hidden
+// layers), or -1 for one the kernels are not built for.
+int policy_h3(const sg_policy_arch* a);
 
 namespace sgk {
 

@@ -1,6 +1,8 @@
 // Policy MLP on the matrix cores (gfx950 v_mfma_f32_16x16x32_bf16) for one
-// wave of 64 environments: [W<=24 -> 256 -> 128 -> 8], tanh hidden units,
-// BF16 operands, FP32 accumulation.
+// wave of 64 environments: [W<=24 -> 256 -> 128 (-> H3) -> 8], tanh or ELU
+// hidden units, BF16 operands, FP32 accumulation. Two networks are built:
+// 256-128 tanh (the rollout workload's policy) and 256-128-64 ELU (the
+// paper's Table II network).
 //
 // Formulation: each layer computes Y^T = W X^T, so the MFMA A operand is a
 // 16x32 weight tile, B is a 32x16 activation tile (16 environments), and the
@@ -23,13 +25,25 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kH1 = 256, kH2 = 128, kKin = 32, kOut = 16;  // padded sizes
+enum { PACT_TANH = 0, PACT_ELU = 1 };                        // hidden activation
 // LDS image of the weights, in 16-byte fragments (uint4):
 //   W1: [16 row tiles][64 lanes]          (K = 32 input features, padded)
 //   W2: [8 row tiles][8 K-blocks][64 lanes]
-//   W3: [4 K-blocks][64 lanes]            (16 rows, outputs >= J+1 zero)
-constexpr int kW1Frags = 16 * 64, kW2Frags = 8 * 8 * 64, kW3Frags = 4 * 64;
-constexpr int kWFrags = kW1Frags + kW2Frags + kW3Frags;   // 5376 x 16 B = 84 KB
-constexpr int kBiasFloats = kH1 + kH2 + kOut;              // 400
+//   W3: [H3/16 row tiles][4 K-blocks][64 lanes]   (third hidden layer, if any)
+//   Wo: [Ko/32 K-blocks][64 lanes]        (16 rows, outputs >= J+1 zero;
+//                                          Ko = H3 or 128)
+// and the bias image b1 (256) | b2 (128) | b3 (H3) | bo (16) floats.
+constexpr int kW1Frags = 16 * 64, kW2Frags = 8 * 8 * 64;
+template <int H3> struct PolicyShape {
+  static constexpr int kKo = H3 ? H3 : kH2;
+  static constexpr int kW3Frags = (H3 / 16) * (kH2 / 32) * 64;
+  static constexpr int kWoFrags = (kKo / 32) * 64;
+  static constexpr int kWFrags = kW1Frags + kW2Frags + kW3Frags + kWoFrags;  // 84 KB or 98 KB
+  static constexpr int kBias = kH1 + kH2 + H3 + kOut;
+};
+// the largest image (the weight buffer of a context holds any network)
+constexpr int kWFragsMax = PolicyShape<64>::kWFrags;
+constexpr int kBiasMax = PolicyShape<64>::kBias;
 
 // fast tanh: 1 - 2 / (exp(2x) + 1) with the hardware exp and reciprocal
 // (v_exp_f32, v_rcp_f32: about 1 ulp each) instead of an IEEE division
@@ -40,16 +54,23 @@ __device__ __forceinline__ float tanh_fast(float x) {
   return 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
 }
 
+// ELU with the hardware exponential (about 1 ulp), rounded to BF16 after.
+__device__ __forceinline__ float elu_fast(float x) { return x > 0.f ? x : __expf(x) - 1.f; }
+
+template <int ACT> __device__ __forceinline__ float pact(float x) {
+  return ACT == PACT_ELU ? elu_fast(x) : tanh_fast(x);
+}
+
 __device__ __forceinline__ f32x4 mfma16x16x32(const bf16x8& a, const bf16x8& b, const f32x4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ bf16x8 pack_act(const f32x4& lo, const f32x4& hi) {
+template <int ACT> __device__ __forceinline__ bf16x8 pack_act(const f32x4& lo, const f32x4& hi) {
   bf16x8 r;
-  r[0] = (__bf16)tanh_fast(lo[0]); r[1] = (__bf16)tanh_fast(lo[1]);
-  r[2] = (__bf16)tanh_fast(lo[2]); r[3] = (__bf16)tanh_fast(lo[3]);
-  r[4] = (__bf16)tanh_fast(hi[0]); r[5] = (__bf16)tanh_fast(hi[1]);
-  r[6] = (__bf16)tanh_fast(hi[2]); r[7] = (__bf16)tanh_fast(hi[3]);
+  r[0] = (__bf16)pact<ACT>(lo[0]); r[1] = (__bf16)pact<ACT>(lo[1]);
+  r[2] = (__bf16)pact<ACT>(lo[2]); r[3] = (__bf16)pact<ACT>(lo[3]);
+  r[4] = (__bf16)pact<ACT>(hi[0]); r[5] = (__bf16)pact<ACT>(hi[1]);
+  r[6] = (__bf16)pact<ACT>(hi[2]); r[7] = (__bf16)pact<ACT>(hi[3]);
   return r;
 }
 
@@ -70,14 +91,18 @@ __device__ __forceinline__ void stage_input(uint4* xs, int lane, const float* x,
 }
 
 // The forward pass for the wave's 64 staged inputs. ws: weight image,
-// bias: [b1 256 | b2 128 | b3 16] floats, xs: staged inputs, os: output
-// image [64 envs][16] floats. Callers synchronize around it.
+// bias: bias image, xs: staged inputs, os: output image [64 envs][16]
+// floats. Callers synchronize around it.
+template <int H3, int ACT>
 __device__ __forceinline__ void mlp_wave(const uint4* __restrict__ ws, const float* __restrict__ bias,
                                          const uint4* __restrict__ xs, float* __restrict__ os, int lane) {
+  using S = PolicyShape<H3>;
   const int g = lane >> 4, j = lane & 15;
   const uint4* W1 = ws;
   const uint4* W2 = ws + kW1Frags;
   const uint4* W3 = W2 + kW2Frags;
+  const uint4* Wo = W3 + S::kW3Frags;
+  const float* bo = bias + kH1 + kH2 + H3;
   bf16x8 xb[4];
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
@@ -105,7 +130,7 @@ __device__ __forceinline__ void mlp_wave(const uint4* __restrict__ ws, const flo
     }
     bf16x8 hb[4];
 #pragma unroll
-    for (int n = 0; n < 4; ++n) hb[n] = pack_act(d1[0][n], d1[1][n]);
+    for (int n = 0; n < 4; ++n) hb[n] = pack_act<ACT>(d1[0][n], d1[1][n]);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       uint4 t = W2[(m * 8 + kb) * 64 + lane];
@@ -114,25 +139,88 @@ __device__ __forceinline__ void mlp_wave(const uint4* __restrict__ ws, const flo
       for (int n = 0; n < 4; ++n) acc2[m][n] = mfma16x16x32(a, hb[n], acc2[m][n]);
     }
   }
-  f32x4 acc3[4];
+  f32x4 acco[4];
   {
-    const float4 bb = *reinterpret_cast<const float4*>(bias + kH1 + kH2 + 4 * g);
+    const float4 bb = *reinterpret_cast<const float4*>(bo + 4 * g);
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acc3[n] = f32x4{bb.x, bb.y, bb.z, bb.w};
+    for (int n = 0; n < 4; ++n) acco[n] = f32x4{bb.x, bb.y, bb.z, bb.w};
   }
+  if constexpr (H3 > 0) {
+    // third hidden layer: K-block kb of it is row tiles 2kb, 2kb+1 of layer 2
+    constexpr int M3 = H3 / 16;
+    f32x4 acc3[M3][4];
 #pragma unroll
-  for (int kb = 0; kb < 4; ++kb) {
-    uint4 t = W3[kb * 64 + lane];
-    const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
+    for (int m = 0; m < M3; ++m) {
+      const float4 bb = *reinterpret_cast<const float4*>(bias + kH1 + kH2 + 16 * m + 4 * g);
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acc3[n] = mfma16x16x32(a, pack_act(acc2[2 * kb][n], acc2[2 * kb + 1][n]), acc3[n]);
+      for (int n = 0; n < 4; ++n) acc3[m][n] = f32x4{bb.x, bb.y, bb.z, bb.w};
+    }
+#pragma unroll
+    for (int kb = 0; kb < kH2 / 32; ++kb) {
+      bf16x8 hb[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) hb[n] = pack_act<ACT>(acc2[2 * kb][n], acc2[2 * kb + 1][n]);
+#pragma unroll
+      for (int m = 0; m < M3; ++m) {
+        uint4 t = W3[(m * (kH2 / 32) + kb) * 64 + lane];
+        const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc3[m][n] = mfma16x16x32(a, hb[n], acc3[m][n]);
+      }
+    }
+#pragma unroll
+    for (int kb = 0; kb < H3 / 32; ++kb) {
+      uint4 t = Wo[kb * 64 + lane];
+      const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
+#pragma unroll
+      for (int n = 0; n < 4; ++n) acco[n] = mfma16x16x32(a, pack_act<ACT>(acc3[2 * kb][n], acc3[2 * kb + 1][n]), acco[n]);
+    }
+  } else {
+#pragma unroll
+    for (int kb = 0; kb < kH2 / 32; ++kb) {
+      uint4 t = Wo[kb * 64 + lane];
+      const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
+#pragma unroll
+      for (int n = 0; n < 4; ++n) acco[n] = mfma16x16x32(a, pack_act<ACT>(acc2[2 * kb][n], acc2[2 * kb + 1][n]), acco[n]);
+    }
   }
   if (g < 2) {
 #pragma unroll
     for (int n = 0; n < 4; ++n)
       *reinterpret_cast<float4*>(os + (16 * n + j) * kOut + 4 * g) =
-          make_float4(acc3[n][0], acc3[n][1], acc3[n][2], acc3[n][3]);
+          make_float4(acco[n][0], acco[n][1], acco[n][2], acco[n][3]);
   }
+}
+
+// Source of one element of the weight image: fragment f (0 .. kWFrags),
+// lane l, slot s -> layer (0 W1, 1 W2, 2 W3, 3 output), row and input k of
+// that layer's W [rows][K]; returns false for padding (an input past the
+// observation width W, an output row >= O). Shared by the host-visible
+// packer kernel so every writer of the image uses one layout.
+template <int H3>
+__host__ __device__ inline bool img_source(int f, int l, int s, int W, int O, int* layer, int* row, int* k) {
+  using S = PolicyShape<H3>;
+  const int g = l >> 4, i = l & 15;
+  const int kp_lo = s < 4 ? 4 * g + s : 16 + 4 * g + (s - 4);  // permuted K within a 32-block
+  if (f < kW1Frags / 64) {
+    *layer = 0; *row = 16 * f + i; *k = 8 * g + s;
+    return *k < W;
+  }
+  f -= kW1Frags / 64;
+  if (f < kW2Frags / 64) {
+    const int m = f / 8, kb = f % 8;
+    *layer = 1; *row = 16 * m + i; *k = 32 * kb + kp_lo;
+    return true;
+  }
+  f -= kW2Frags / 64;
+  if (f < S::kW3Frags / 64) {
+    const int m = f / (kH2 / 32), kb = f % (kH2 / 32);
+    *layer = 2; *row = 16 * m + i; *k = 32 * kb + kp_lo;
+    return true;
+  }
+  f -= S::kW3Frags / 64;
+  *layer = 3; *row = i; *k = 32 * f + kp_lo;
+  return i < O;
 }
 
 }  // namespace sgk

@@ -39,7 +39,11 @@
 struct sg_ppo {
   sg_ctx* ctx = nullptr;
   int J = 0, W = 0, O = 0, P = 0;
-  int off[7] = {0, 0, 0, 0, 0, 0, 0};  // W1 b1 W2 b2 W3 b3 log_std
+  // network: hidden layers 256, 128 (, h3), then J + 1 outputs; act the
+  // hidden activation (PACT_*); flat parameters per layer W then b, then
+  // log_std at oLS
+  int h3 = 0, act = 0, nl = 3;
+  int oW[4] = {0, 0, 0, 0}, oB[4] = {0, 0, 0, 0}, oLS = 0;
   int max_samples = 0;
   uint64_t* tstep = nullptr; // Adam steps taken (device, so captured updates advance it)
   unsigned* ttick = nullptr; // blocks of the current norm+Adam launch that have read it
@@ -56,7 +60,11 @@ struct sg_ppo {
   uint16_t* H1 = nullptr;    // [rows][256] (layer 1's pre-activations are recomputed, not kept)
   float* Z2 = nullptr;       // [rows][128]
   uint16_t* H2 = nullptr;
-  float* Z3 = nullptr;       // [rows][8]
+  float* Z3h = nullptr;      // [rows][h3] third hidden layer's pre-activations (h3 > 0)
+  uint16_t* H3 = nullptr;    // [rows][h3]
+  uint16_t* D3b = nullptr;   // [rows][h3]
+  float* cpart3 = nullptr;   // per-block column sums of dZ3 [rows / 64][h3]
+  float* Z3 = nullptr;       // [rows][8] outputs
   uint16_t* G3b = nullptr;   // [rows][8] dL/d(outputs)
   uint16_t* D2b = nullptr;   // [rows][128]
   uint16_t* D1b = nullptr;   // [rows][256]
@@ -509,41 +517,42 @@ __global__ void __launch_bounds__(kNormAdamThreads) k_ppo_norm_adam(NormAdamArgs
   norm_adam_ticket(a, step);
 }
 
-// Rollout weight image (fragment order of mlp.hpp; see sg_set_policy),
-// bias image and log_std from the master parameters.
-__global__ void __launch_bounds__(256) k_ppo_pack(const float* __restrict__ p, int W, int O, int J, int o1, int ob1,
-                                                  int o2, int ob2, int o3, int ob3, int ols, uint16_t* __restrict__ img,
-                                                  float* __restrict__ bias, float* __restrict__ log_std) {
+// Rollout weight image (fragment order of mlp.hpp, through img_source, as
+// sg_set_policy packs it), bias image and log_std from the master
+// parameters: per layer l, W at oW[l] ([out][in]) and b at oB[l]; the
+// output layer is the last of nl.
+struct PackArgs {
+  const float* p;
+  int W, O, J, nl;
+  int oW[4], oB[4], oLS;
+  uint16_t* img;
+  float* bias;
+  float* log_std;
+};
+template <int H3>
+__global__ void __launch_bounds__(256) k_ppo_pack(PackArgs a) {
+  using S = PolicyShape<H3>;
   const int i = blockIdx.x * 256 + threadIdx.x;
-  const int n1 = kW1Frags * 8, n2 = kW2Frags * 8, n3 = kW3Frags * 8;
-  if (i < n1 + n2 + n3) {
-    // slot, lane and 64-lane fragment of the image; kW*Frags count 16-byte
-    // lane entries, so a layer spans kW*Frags / 64 fragments
+  if (i < S::kWFrags * 8) {
     const int s = i & 7, l = (i >> 3) & 63, f = i >> 9;
-    const int gg = l >> 4, li = l & 15;
+    int layer, row, k;
     float x = 0.f;
-    if (i < n1) {
-      const int row = 16 * f + li, k = 8 * gg + s;
-      x = k < W ? p[o1 + row * W + k] : 0.f;
-    } else if (i < n1 + n2) {
-      const int f2 = f - kW1Frags / 64, mt = f2 >> 3, kb = f2 & 7;
-      const int row = 16 * mt + li, k = 32 * kb + (s < 4 ? 4 * gg + s : 16 + 4 * gg + (s - 4));
-      x = p[o2 + row * kH1 + k];
-    } else {
-      const int kb = f - (kW1Frags + kW2Frags) / 64;
-      const int row = li, k = 32 * kb + (s < 4 ? 4 * gg + s : 16 + 4 * gg + (s - 4));
-      x = row < O ? p[o3 + row * kH2 + k] : 0.f;
+    if (img_source<H3>(f, l, s, a.W, a.O, &layer, &row, &k)) {
+      const int L = layer == 3 ? a.nl - 1 : layer;
+      const int K = L == 0 ? a.W : (L == 1 ? kH1 : (L == 2 && H3 ? kH2 : (H3 ? H3 : kH2)));
+      x = a.p[a.oW[L] + row * K + k];
     }
-    img[i] = bf16_bits(x);
+    a.img[i] = bf16_bits(x);
   }
-  if (i < kBiasFloats) {
+  if (i < S::kBias) {
     float b = 0.f;
-    if (i < kH1) b = p[ob1 + i];
-    else if (i < kH1 + kH2) b = p[ob2 + i - kH1];
-    else if (i - kH1 - kH2 < O) b = p[ob3 + i - kH1 - kH2];
-    bias[i] = b;
+    if (i < kH1) b = a.p[a.oB[0] + i];
+    else if (i < kH1 + kH2) b = a.p[a.oB[1] + i - kH1];
+    else if (i < kH1 + kH2 + H3) b = a.p[a.oB[2] + i - kH1 - kH2];
+    else if (i - kH1 - kH2 - H3 < a.O) b = a.p[a.oB[a.nl - 1] + i - kH1 - kH2 - H3];
+    a.bias[i] = b;
   }
-  if (i < J) log_std[i] = p[ols + i];
+  if (i < a.J) a.log_std[i] = a.p[a.oLS + i];
 }
 
 // A fill kernel rather than a memset node, so the update can be captured.
@@ -561,62 +570,95 @@ static SumJob weight_grad(sg_ppo* o, hipStream_t st, int l, int M, int N, int K,
 
 // Gradient of one minibatch into o->g. With `finish`, the entropy term is
 // added to o->g, its norm goes to scal[2] and the statistics (weight
-// w_stats) to stats; without, k_ppo_norm_adam does both next.
-static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_config* cfg, float w_stats,
-                                 float* stats, bool finish, bool gathered = false) {
+// w_stats) to stats; without, k_ppo_norm_adam does both next. ACT: the
+// hidden activation (nn.hpp's ACT_TANH / ACT_ELU).
+template <int ACT>
+static hipError_t minibatch_grad_t(sg_ppo* o, const PpoRows& rows, const sg_ppo_config* cfg, float w_stats,
+                                   float* stats, bool finish, bool gathered) {
   sg_ctx* c = o->ctx;
   hipStream_t st = c->stream;
-  const int B = rows.rows, W = o->W, O = o->O, J = o->J;
+  const int B = rows.rows, W = o->W, O = o->O, J = o->J, h3 = o->h3, L = o->nl - 1;  // L: output layer
   const int gb = (B + 255) / 256;
   // every entry of o->g is written below (weight and bias sums), so no clear
   if (!gathered) k_ppo_gather<<<gb, 256, 0, st>>>(rows, o->X);
   GemmArgs f{};
-  // layer 1: Z1 = X W1^T + b1, H1 = tanh(Z1)
-  f.M = B; f.N = kH1; f.K = W; f.A = o->X; f.lda = kPX; f.B = o->pb + o->off[0]; f.ldb = W;
-  f.C = nullptr; f.ldc = kH1; f.bias = o->p + o->off[1]; f.Cb = o->H1;
-  launch_gemm<EPI_FWD_HIDDEN, false, true, ACT_TANH>(st, f);
-  // layer 2
-  f.N = kH2; f.K = kH1; f.A = o->H1; f.lda = kH1; f.B = o->pb + o->off[2]; f.ldb = kH1;
-  f.C = o->Z2; f.ldc = kH2; f.bias = o->p + o->off[3]; f.Cb = o->H2;
-  launch_gemm<EPI_FWD_HIDDEN, false, true, ACT_TANH>(st, f);
-  // layer 3 (linear): [mu | V]
-  f.N = O; f.K = kH2; f.A = o->H2; f.lda = kH2; f.B = o->pb + o->off[4]; f.ldb = kH2;
-  f.C = o->Z3; f.ldc = kPO; f.bias = o->p + o->off[5]; f.Cb = nullptr;
-  launch_gemm<EPI_FWD_OUT, false, true, ACT_TANH>(st, f);
+  // layer 1: Z1 = X W1^T + b1, H1 = act(Z1)
+  f.M = B; f.N = kH1; f.K = W; f.A = o->X; f.lda = kPX; f.B = o->pb + o->oW[0]; f.ldb = W;
+  f.C = nullptr; f.ldc = kH1; f.bias = o->p + o->oB[0]; f.Cb = o->H1;
+  launch_gemm<EPI_FWD_HIDDEN, false, true, ACT>(st, f);
+  // layer 2 (pre-activations kept for the backward pass)
+  f.N = kH2; f.K = kH1; f.A = o->H1; f.lda = kH1; f.B = o->pb + o->oW[1]; f.ldb = kH1;
+  f.C = o->Z2; f.ldc = kH2; f.bias = o->p + o->oB[1]; f.Cb = o->H2;
+  launch_gemm<EPI_FWD_HIDDEN, false, true, ACT>(st, f);
+  const uint16_t* Hlast = o->H2;
+  int hl = kH2;
+  if (h3) {
+    f.N = h3; f.K = kH2; f.A = o->H2; f.lda = kH2; f.B = o->pb + o->oW[2]; f.ldb = kH2;
+    f.C = o->Z3h; f.ldc = h3; f.bias = o->p + o->oB[2]; f.Cb = o->H3;
+    launch_gemm<EPI_FWD_HIDDEN, false, true, ACT>(st, f);
+    Hlast = o->H3;
+    hl = h3;
+  }
+  // output layer (linear): [mu | V]
+  f.N = O; f.K = hl; f.A = Hlast; f.lda = hl; f.B = o->pb + o->oW[L]; f.ldb = hl;
+  f.C = o->Z3; f.ldc = kPO; f.bias = o->p + o->oB[L]; f.Cb = nullptr;
+  launch_gemm<EPI_FWD_OUT, false, true, ACT>(st, f);
   PpoLossArgs la;
-  la.rows = rows; la.Z3 = o->Z3; la.ls = o->p + o->off[6]; la.clip = cfg->clip; la.c_v = cfg->value_coef;
+  la.rows = rows; la.Z3 = o->Z3; la.ls = o->p + o->oLS; la.clip = cfg->clip; la.c_v = cfg->value_coef;
   la.inv_b = 1.f / (float)B; la.w_stats = w_stats; la.G3b = o->G3b; la.part = o->lpart;
   k_ppo_loss<<<gb, 256, 0, st>>>(la);
-  // weight gradients as split-K partials; their sums and the bias sums
-  // (six jobs) run in one launch at the end. Output biases and log_std are
-  // adjacent in the flat vector (off[6] = off[5] + O).
-  SumJob jobs[6];
-  jobs[0] = weight_grad(o, st, 2, O, kH2, B, o->G3b, kPO, o->H2, kH2, o->g + o->off[4], kH2);
-  jobs[1] = partial_rows(o->lpart, gb, O + J, kLossPart, o->g + o->off[5]);
-  // dZ2 = (G3 W3) * tanh'(Z2), with the column sums of dZ2 (hidden-2 bias)
+  // weight gradients as split-K partials; their sums and the bias sums run
+  // in one launch at the end. Output biases and log_std are adjacent in the
+  // flat vector (oLS = oB[L] + O).
+  SumJob jobs[8];
+  int nj = 0;
+  jobs[nj++] = weight_grad(o, st, 3, O, hl, B, o->G3b, kPO, Hlast, hl, o->g + o->oW[L], hl);
+  jobs[nj++] = partial_rows(o->lpart, gb, O + J, kLossPart, o->g + o->oB[L]);
   const int rb = (B + 63) / 64;
   GemmArgs d{};
-  d.M = B; d.N = kH2; d.K = O; d.A = o->G3b; d.lda = kPO; d.B = o->pb + o->off[4]; d.ldb = kH2;
+  // the gradient entering the last hidden layer's pre-activations
+  const uint16_t* Gin = o->G3b;
+  int gin_ld = kPO, gin_k = O;
+  const uint16_t* Wnext = o->pb + o->oW[L];
+  if (h3) {
+    // dZ3 = (G Wo) * act'(Z3), with the column sums of dZ3 (hidden-3 bias)
+    d.M = B; d.N = h3; d.K = O; d.A = o->G3b; d.lda = kPO; d.B = Wnext; d.ldb = h3;
+    d.C = nullptr; d.ldc = h3; d.Cb = o->D3b; d.Zp = o->Z3h; d.colpart = o->cpart3;
+    launch_gemm<EPI_BWD_DX, false, false, ACT>(st, d);
+    jobs[nj++] = weight_grad(o, st, 2, h3, kH2, B, o->D3b, h3, o->H2, kH2, o->g + o->oW[2], kH2);
+    jobs[nj++] = partial_rows(o->cpart3, rb, h3, h3, o->g + o->oB[2]);
+    Gin = o->D3b; gin_ld = h3; gin_k = h3;
+    Wnext = o->pb + o->oW[2];
+  }
+  // dZ2 = (G_next W_next) * act'(Z2), with the column sums of dZ2 (hidden-2 bias)
+  d = GemmArgs{};
+  d.M = B; d.N = kH2; d.K = gin_k; d.A = Gin; d.lda = gin_ld; d.B = Wnext; d.ldb = kH2;
   d.C = nullptr; d.ldc = kH2; d.Cb = o->D2b; d.Zp = o->Z2; d.colpart = o->cpart2;
-  launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
-  jobs[2] = weight_grad(o, st, 1, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->off[2], kH1);
-  jobs[3] = partial_rows(o->cpart2, rb, kH2, kH2, o->g + o->off[3]);
-  // dZ1 = (dZ2 W2) * tanh'(Z1), with the column sums of dZ1 (hidden-1 bias);
+  launch_gemm<EPI_BWD_DX, false, false, ACT>(st, d);
+  jobs[nj++] = weight_grad(o, st, 1, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->oW[1], kH1);
+  jobs[nj++] = partial_rows(o->cpart2, rb, kH2, kH2, o->g + o->oB[1]);
+  // dZ1 = (dZ2 W2) * act'(Z1), with the column sums of dZ1 (hidden-1 bias);
   // Z1 (W inputs) is recomputed in the epilogue rather than stored
-  d.N = kH1; d.K = kH2; d.A = o->D2b; d.lda = kH2; d.B = o->pb + o->off[2]; d.ldb = kH1;
+  d.N = kH1; d.K = kH2; d.A = o->D2b; d.lda = kH2; d.B = o->pb + o->oW[1]; d.ldb = kH1;
   d.C = nullptr; d.ldc = kH1; d.Cb = o->D1b; d.colpart = o->cpart;
   d.Zp = nullptr;
-  d.RA = o->X; d.rlda = kPX; d.RB = o->pb + o->off[0]; d.rldb = W; d.RK = W; d.rbias = o->p + o->off[1];
-  launch_gemm<EPI_BWD_DX, false, false, ACT_TANH>(st, d);
-  jobs[4] = weight_grad(o, st, 0, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->off[0], W);
-  jobs[5] = partial_rows(o->cpart, rb, kH1, kH1, o->g + o->off[1]);
-  launch_sums(st, jobs, 6);
+  d.RA = o->X; d.rlda = kPX; d.RB = o->pb + o->oW[0]; d.rldb = W; d.RK = W; d.rbias = o->p + o->oB[0];
+  launch_gemm<EPI_BWD_DX, false, false, ACT>(st, d);
+  jobs[nj++] = weight_grad(o, st, 0, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->oW[0], W);
+  jobs[nj++] = partial_rows(o->cpart, rb, kH1, kH1, o->g + o->oB[0]);
+  launch_sums(st, jobs, nj);
   if (finish) {
     const int nb = (o->P + kGnormChunk - 1) / kGnormChunk;
-    k_gnorm_part<<<nb, 256, 0, st>>>(o->g, o->P, o->off[6], J, cfg->entropy_coef, o->gpart);
-    k_ppo_finish<<<1, 256, 0, st>>>(o->gpart, nb, o->lpart, gb, o->p + o->off[6], J, o->scal, stats, w_stats);
+    k_gnorm_part<<<nb, 256, 0, st>>>(o->g, o->P, o->oLS, J, cfg->entropy_coef, o->gpart);
+    k_ppo_finish<<<1, 256, 0, st>>>(o->gpart, nb, o->lpart, gb, o->p + o->oLS, J, o->scal, stats, w_stats);
   }
   return hipGetLastError();
+}
+
+static hipError_t minibatch_grad(sg_ppo* o, const PpoRows& rows, const sg_ppo_config* cfg, float w_stats,
+                                 float* stats, bool finish, bool gathered = false) {
+  return o->act == PACT_ELU ? minibatch_grad_t<ACT_ELU>(o, rows, cfg, w_stats, stats, finish, gathered)
+                            : minibatch_grad_t<ACT_TANH>(o, rows, cfg, w_stats, stats, finish, gathered);
 }
 
 static PpoRows rows_of(const sg_ppo* o, const sg_rollout_bufs* b, int T) {
@@ -642,10 +684,17 @@ static hipError_t prepare_batch(sg_ppo* o, const sg_rollout_bufs* b, int n) {
 
 static hipError_t pack_policy(sg_ppo* o) {
   sg_ctx* c = o->ctx;
-  const int n = (kW1Frags + kW2Frags + kW3Frags) * 8;
-  k_ppo_pack<<<(n + 255) / 256, 256, 0, c->stream>>>(o->p, o->W, o->O, o->J, o->off[0], o->off[1], o->off[2],
-                                                     o->off[3], o->off[4], o->off[5], o->off[6], c->w_bf16, c->bias,
-                                                     c->log_std);
+  PackArgs a;
+  a.p = o->p; a.W = o->W; a.O = o->O; a.J = o->J; a.nl = o->nl; a.oLS = o->oLS;
+  for (int l = 0; l < 4; ++l) { a.oW[l] = o->oW[l]; a.oB[l] = o->oB[l]; }
+  a.img = c->w_bf16; a.bias = c->bias; a.log_std = c->log_std;
+  if (o->h3) {
+    const int n = PolicyShape<64>::kWFrags * 8;
+    k_ppo_pack<64><<<(n + 255) / 256, 256, 0, c->stream>>>(a);
+  } else {
+    const int n = PolicyShape<0>::kWFrags * 8;
+    k_ppo_pack<0><<<(n + 255) / 256, 256, 0, c->stream>>>(a);
+  }
   return hipGetLastError();
 }
 
@@ -682,29 +731,41 @@ bool ok_bufs(const sg_rollout_bufs* b) {
 
 extern "C" {
 
-sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_ppo** out) {
+sg_status sg_ppo_create(sg_ctx* c, const sg_policy_arch* arch, const float* params, int32_t max_samples,
+                        sg_ppo** out) {
   if (!c || !out) return SG_E_INVAL;
   *out = nullptr;
-  if (!params) return pfail(c, SG_E_INVAL, "sg_ppo_create: null params");
+  if (!params || !arch) return pfail(c, SG_E_INVAL, "sg_ppo_create: null params or arch");
   if (c->dtype != SG_F32) return pfail(c, SG_E_UNSUPPORTED, "sg_ppo_create: FP32 contexts only");
   if (c->J > 7) return pfail(c, SG_E_UNSUPPORTED, "sg_ppo_create: max_dof <= 7");
+  const int h3 = policy_h3(arch);
+  if (h3 < 0) return pfail(c, SG_E_UNSUPPORTED, "sg_ppo_create: supported are 256-128 tanh and 256-128-64 ELU");
+  if (h3 && c->prismatic) return pfail(c, SG_E_UNSUPPORTED, "sg_ppo_create: the 256-128-64 network needs revolute chains");
   if (max_samples < 1 || max_samples > (1 << 24)) return pfail(c, SG_E_INVAL, "sg_ppo_create: max_samples in 1..16M");
   sg_ppo* o = new sg_ppo();
   o->ctx = c;
   o->J = c->J;
   o->W = 2 * c->J + 10;
   o->O = c->J + 1;
+  o->h3 = h3;
+  o->act = arch->act == SG_ACT_ELU ? PACT_ELU : PACT_TANH;
+  o->nl = h3 ? 4 : 3;
   o->max_samples = max_samples;
-  const int sz[7] = {kH1 * o->W, kH1, kH2 * kH1, kH2, o->O * kH2, o->O, o->J};
-  int acc = 0;
-  for (int i = 0; i < 7; ++i) {
-    o->off[i] = acc;
-    acc += sz[i];
+  {
+    const int dims[5] = {o->W, kH1, kH2, h3 ? h3 : o->O, o->O};
+    int acc = 0;
+    for (int l = 0; l < o->nl; ++l) {
+      o->oW[l] = acc;
+      acc += dims[l + 1] * dims[l];
+      o->oB[l] = acc;
+      acc += dims[l + 1];
+    }
+    o->oLS = acc;
+    o->P = acc + o->J;
   }
-  o->P = acc;
   const size_t R = (size_t)max_samples, P = (size_t)o->P;
   // split-K partials: one region per layer (launch_weight_grad_partials bound)
-  o->ws_floats = 3 * kWeightGradWs;
+  o->ws_floats = 4 * kWeightGradWs;
   hipError_t e = palloc(o, &o->p, P);
   uint64_t* tcount = nullptr;
   if (e == hipSuccess) e = palloc(o, &tcount, 1);  // the step count and (after it) the completion count, zeroed
@@ -721,6 +782,10 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   if (e == hipSuccess) e = palloc(o, &o->H1, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->Z2, R * kH2);
   if (e == hipSuccess) e = palloc(o, &o->H2, R * kH2);
+  if (e == hipSuccess && h3) e = palloc(o, &o->Z3h, R * h3);
+  if (e == hipSuccess && h3) e = palloc(o, &o->H3, R * h3);
+  if (e == hipSuccess && h3) e = palloc(o, &o->D3b, R * h3);
+  if (e == hipSuccess && h3) e = palloc(o, &o->cpart3, ((R + 63) / 64) * (size_t)h3);
   if (e == hipSuccess) e = palloc(o, &o->Z3, R * kPO);
   if (e == hipSuccess) e = palloc(o, &o->G3b, R * kPO);
   if (e == hipSuccess) e = palloc(o, &o->D2b, R * kH2);
@@ -731,8 +796,8 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   if (e == hipSuccess) e = palloc(o, &o->lpart, ((R + 255) / 256) * (size_t)kLossPart);
   if (e == hipSuccess) e = palloc(o, &o->gpart, (size_t)kGnormBlocks);
   if (e == hipSuccess && (o->P + kGnormChunk - 1) / kGnormChunk > kGnormBlocks) e = hipErrorInvalidValue;
-  if (e == hipSuccess && !c->w_bf16) e = hipMalloc((void**)&c->w_bf16, (size_t)kWFrags * 16);
-  if (e == hipSuccess && !c->bias) e = hipMalloc((void**)&c->bias, (size_t)kBiasFloats * sizeof(float));
+  if (e == hipSuccess && !c->w_bf16) e = hipMalloc((void**)&c->w_bf16, (size_t)kWFragsMax * 16);
+  if (e == hipSuccess && !c->bias) e = hipMalloc((void**)&c->bias, (size_t)kBiasMax * sizeof(float));
   if (e == hipSuccess && !c->log_std) e = hipMalloc((void**)&c->log_std, (size_t)c->J * sizeof(float));
   if (e == hipSuccess) e = hipMemcpy(o->p, params, P * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) {
@@ -749,6 +814,8 @@ sg_status sg_ppo_create(sg_ctx* c, const float* params, int32_t max_samples, sg_
   c->has_policy = 1;
   c->h1 = kH1;
   c->h2 = kH2;
+  c->h3 = h3;
+  c->pact = o->act;
   *out = o;
   return SG_OK;
 }
@@ -832,7 +899,7 @@ sg_status sg_ppo_update(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const sg
       e = minibatch_grad(o, r, cfg, w, stats, false, ep > 0 || k > 0);
       if (e != hipSuccess) break;
       NormAdamArgs na;
-      na.P = o->P; na.ls0 = o->off[6]; na.J = o->J;
+      na.P = o->P; na.ls0 = o->oLS; na.J = o->J;
       na.p = o->p; na.g = o->g; na.m = o->m; na.v = o->v; na.pb = o->pb; na.scal = o->scal;
       na.c_e = cfg->entropy_coef; na.max_norm = cfg->max_grad_norm; na.lr = cfg->lr;
       na.b1 = cfg->beta1; na.b2 = cfg->beta2; na.eps = cfg->adam_eps;

@@ -9,13 +9,16 @@ namespace sgk {
 constexpr int kWave = 64;
 constexpr int kXMax = 32;  // observation width padded to the first layer's K
 
-// LDS layout of the rollout kernel (bytes)
-constexpr size_t kLdsW = (size_t)kWFrags * 16;
-constexpr size_t kLdsBias = (size_t)kBiasFloats * 4;
+// LDS layout of the rollout kernel (bytes): weight image, bias image,
+// staged inputs, outputs, link parameters
+template <int H3> constexpr size_t lds_w_bytes() { return (size_t)PolicyShape<H3>::kWFrags * 16; }
+template <int H3> constexpr size_t lds_bias_bytes() { return (size_t)PolicyShape<H3>::kBias * 4; }
 constexpr size_t kLdsX = 256 * 16;
 constexpr size_t kLdsO = (size_t)kWave * kOut * 4;
 template <int J> constexpr size_t lds_par_bytes() { return (size_t)P_NSTAGE * J * kWave * 4; }
-template <int J> constexpr size_t rollout_lds_bytes() { return kLdsW + kLdsBias + kLdsX + kLdsO + lds_par_bytes<J>(); }
+template <int H3> constexpr size_t policy_lds_bytes() { return lds_w_bytes<H3>() + lds_bias_bytes<H3>() + kLdsX + kLdsO; }
+template <int J, int H3> constexpr size_t rollout_lds_bytes() { return policy_lds_bytes<H3>() + lds_par_bytes<J>(); }
+static_assert(rollout_lds_bytes<7, 64>() <= 160 * 1024, "the Table II network's rollout fits the LDS");
 
 struct RollArgs {
   EnvDev<float> E;
@@ -32,19 +35,21 @@ struct RollArgs {
   float* val;
 };
 
+template <int H3>
 __device__ __forceinline__ void fill_weights(uint4* sw, float* sb, const uint4* __restrict__ wimg,
                                              const float* __restrict__ bias, int lane) {
-  for (int i = lane; i < kWFrags; i += kWave) sw[i] = wimg[i];
-  for (int i = lane; i < kBiasFloats; i += kWave) sb[i] = bias[i];
+  for (int i = lane; i < PolicyShape<H3>::kWFrags; i += kWave) sw[i] = wimg[i];
+  for (int i = lane; i < PolicyShape<H3>::kBias; i += kWave) sb[i] = bias[i];
 }
 
 // One workgroup = one wave = 64 envs, for all T steps: weights and the
 // envs' link parameters are staged in LDS once, the chain state stays in
 // VGPRs; every step runs the policy on the matrix cores, samples the action,
 // advances the physics and writes the step's rollout rows.
-template <int J, int M>
+template <int J, int M, int H3, int ACT>
 __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
   extern __shared__ __align__(16) unsigned char lds[];
+  constexpr size_t kLdsW = lds_w_bytes<H3>(), kLdsBias = lds_bias_bytes<H3>();
   uint4* s_w = reinterpret_cast<uint4*>(lds);
   float* s_b = reinterpret_cast<float*>(lds + kLdsW);
   uint4* s_x = reinterpret_cast<uint4*>(lds + kLdsW + kLdsBias);
@@ -59,7 +64,7 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
   const size_t N = E.N;
   const uint64_t step0 = read_counter(E);
 
-  fill_weights(s_w, s_b, A.wimg, A.bias, lane);
+  fill_weights<H3>(s_w, s_b, A.wimg, A.bias, lane);
   stage_chain<float, J>(E, e, active ? n : 0, lane, s_p);
   __syncthreads();
   LdsPar<float, J, M == M_PRI> ps{s_p, lane};
@@ -92,7 +97,7 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
   for (int t = 0; t <= A.T; ++t) {
     stage_input(s_x, lane, x, Wd);
     __syncthreads();
-    mlp_wave(s_w, s_b, s_x, s_o, lane);
+    mlp_wave<H3, ACT>(s_w, s_b, s_x, s_o, lane);
     __syncthreads();
     float mu[J];
 #pragma unroll
@@ -124,23 +129,25 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
 }
 
 // The policy alone on n inputs x [W][n] -> out [J+1][n].
+template <int H3, int ACT>
 __global__ void __launch_bounds__(kWave) k_policy(const uint4* __restrict__ wimg, const float* __restrict__ bias,
                                                   int Wd, int n_out, int n, const float* __restrict__ xin,
                                                   float* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char lds[];
+  constexpr size_t kLdsW = lds_w_bytes<H3>(), kLdsBias = lds_bias_bytes<H3>();
   uint4* s_w = reinterpret_cast<uint4*>(lds);
   float* s_b = reinterpret_cast<float*>(lds + kLdsW);
   uint4* s_x = reinterpret_cast<uint4*>(lds + kLdsW + kLdsBias);
   float* s_o = reinterpret_cast<float*>(lds + kLdsW + kLdsBias + kLdsX);
   const int lane = threadIdx.x;
   const int e = blockIdx.x * kWave + lane;
-  fill_weights(s_w, s_b, wimg, bias, lane);
+  fill_weights<H3>(s_w, s_b, wimg, bias, lane);
   float x[kXMax];
 #pragma unroll
   for (int k = 0; k < kXMax; ++k) x[k] = (e < n && k < Wd) ? xin[(size_t)k * n + e] : 0.f;
   stage_input(s_x, lane, x, Wd);
   __syncthreads();
-  mlp_wave(s_w, s_b, s_x, s_o, lane);
+  mlp_wave<H3, ACT>(s_w, s_b, s_x, s_o, lane);
   __syncthreads();
   if (e < n)
     for (int i = 0; i < n_out; ++i) out[(size_t)i * n + e] = s_o[lane * kOut + i];
@@ -178,18 +185,24 @@ hipError_t launch_gae(hipStream_t s, int T, int n, const float* rew, const float
   return hipGetLastError();
 }
 
-hipError_t launch_policy_forward(const sg_ctx* c, const float* x, int n, float* out) {
-  const size_t lds = kLdsW + kLdsBias + kLdsX + kLdsO;
-  hipError_t e = lds_limit((const void*)k_policy, lds);
+template <int H3, int ACT> static hipError_t policy_forward_t(const sg_ctx* c, const float* x, int n, float* out) {
+  const size_t lds = policy_lds_bytes<H3>();
+  hipError_t e = lds_limit((const void*)k_policy<H3, ACT>, lds);
   if (e != hipSuccess) return e;
-  k_policy<<<dim3((n + kWave - 1) / kWave), kWave, lds, c->stream>>>(
+  k_policy<H3, ACT><<<dim3((n + kWave - 1) / kWave), kWave, lds, c->stream>>>(
       reinterpret_cast<const uint4*>(c->w_bf16), c->bias, 2 * c->J + 10, c->J + 1, n, x, out);
   return hipGetLastError();
 }
 
-template <int J, int M> static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_bufs* b) {
-  const size_t lds = rollout_lds_bytes<J>();
-  hipError_t e = lds_limit((const void*)k_rollout<J, M>, lds);
+hipError_t launch_policy_forward(const sg_ctx* c, const float* x, int n, float* out) {
+  if (c->h3) return policy_forward_t<64, PACT_ELU>(c, x, n, out);
+  return policy_forward_t<0, PACT_TANH>(c, x, n, out);
+}
+
+template <int J, int M, int H3 = 0, int ACT = PACT_TANH>
+static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_bufs* b) {
+  const size_t lds = rollout_lds_bytes<J, H3>();
+  hipError_t e = lds_limit((const void*)k_rollout<J, M, H3, ACT>, lds);
   if (e != hipSuccess) return e;
   RollArgs A;
   A.E = env_view<float>(c);
@@ -200,7 +213,7 @@ template <int J, int M> static hipError_t rollout_j(sg_ctx* c, int T, const sg_r
   A.T = T;
   A.seed = c->seed;
   A.obs = b->obs; A.act = b->act; A.logp = b->logp; A.rew = b->rew; A.done = b->done; A.val = b->val;
-  k_rollout<J, M><<<dim3((c->N + kWave - 1) / kWave), kWave, lds, c->stream>>>(A);
+  k_rollout<J, M, H3, ACT><<<dim3((c->N + kWave - 1) / kWave), kWave, lds, c->stream>>>(A);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_gae(c->stream, T, c->N, b->rew, b->val, b->done, b->gamma, b->lam, b->adv, b->ret);
@@ -208,6 +221,10 @@ template <int J, int M> static hipError_t rollout_j(sg_ctx* c, int T, const sg_r
 
 hipError_t launch_rollout(sg_ctx* c, int T, const sg_rollout_bufs* b) {
   const bool u = c->uniform;
+  if (c->h3) {
+    // the Table II network (256-128-64 ELU): revolute chains of up to 7 joints
+    return u && c->J == 7 ? rollout_j<7, M_UNI, 64, PACT_ELU>(c, T, b) : rollout_j<7, M_GEN, 64, PACT_ELU>(c, T, b);
+  }
   if (c->prismatic) return c->J <= 4 ? rollout_j<4, M_PRI>(c, T, b) : rollout_j<7, M_PRI>(c, T, b);
   switch (dof_bucket(c->J)) {
     case 1: return rollout_j<1, M_UNI>(c, T, b);
