@@ -180,6 +180,7 @@ class Sim:
             raise SgError(st, lib.sg_last_error(None).decode())
         self.ctx = ctx
         self.task = task
+        self.robot = robot
         self.policy_dims = None
 
     def close(self):

@@ -149,13 +149,17 @@ def test_training_reduces_loss(sg):
 
 
 def test_trained_surrogate_error_bound_and_gain(sg):
-    """Train on the simulator's own transitions, then (a) measure the
-    network's qdd error against the FP64 oracle on held-out samples, (b)
-    check the acceptance guarantee: a prediction whose residual is below the
-    threshold is within thr |tau| / lambda_min(H + arm) of the exact answer,
-    (c) time the surrogate step against plain ABA at 65536 envs and report
-    the ratio (no speed is asserted: the network costs ~312 k MFMA flops per
-    substep against ~3.4 k for ABA)."""
+    """Train on the simulator's own transitions (half of the torques the PD
+    drive torques the step forms, half N(0, 20^2)), then on held-out
+    stepping states (drive torques only): (a) the network's qdd error
+    against the FP64 oracle falls with training and stays below the
+    untrained network's, (b) the acceptance guarantee: a prediction whose
+    residual is below the threshold is within thr |tau| / lambda_min(H +
+    arm) of the exact answer, (c) the accepted fraction at each threshold
+    and the step's speed against plain ABA at 65536 envs are reported (no
+    speed is asserted: the network costs ~312 k MFMA flops per substep
+    against ~6 k for ABA; at 1e-2 the trained network is not accepted --
+    the recorded error curve shows where it stands)."""
     import json
     import os
     import time
@@ -165,38 +169,46 @@ def test_trained_surrogate_error_bound_and_gain(sg):
     from paper_2310_04676_amd import surrogate_train as st
     wd = synth.path_rollout(4096, seed=2002)
     simd = sg.from_workload(wd)
-    data = st.generate(simd, 400_000, seed=3)
+    data = st.generate(simd, 400_000, seed=3, robot=wd.robot, pd_share=0.5)
     tr, va = data.split(4096)
+    stepping = st.generate(simd, 4096, seed=4, robot=wd.robot, pd_share=1.0)
     S = sg.Surrogate(simd, 4096)
     W, b = synth.surrogate_init(4)
     S.set_params(W, b)
     S.fit_norm(tr.q, tr.qd, tr.tau, tr.env, tr.qdd)
-    hist = st.train(S, tr, epochs=4, batch=4096)
-    assert hist[-1] < hist[0]
-    pred = host(S.predict(va.q, va.qd, va.tau, va.env))
-    env = va.env.cpu().numpy()
+    env = stepping.env.cpu().numpy()
     rob = wd.robot
     import dataclasses
     sub = synth.Robot(**{f.name: (getattr(rob, f.name)[..., env] if isinstance(getattr(rob, f.name), np.ndarray)
                                   else getattr(rob, f.name)) for f in dataclasses.fields(rob)})
     sub.n_env = len(env)
     osub = oracle.Oracle(sub)
-    q, qd, tau = host(va.q), host(va.qd), host(va.tau)
+    q, qd, tau = host(stepping.q), host(stepping.qd), host(stepping.tau)
     arm = osub.drive_armature()
     ref = osub.aba(q, qd, tau, arm)
+    err0 = st.qdd_error(host(S.predict(stepping.q, stepping.qd, stepping.tau, stepping.env)), ref)
+    val_hist = []
+    hist = st.train(S, tr, epochs=6, batch=4096, val=va, val_hist=val_hist)
+    assert hist[-1] < hist[0]
+    assert val_hist[-1] < val_hist[0]
+    pred = host(S.predict(stepping.q, stepping.qd, stepping.tau, stepping.env))
     err = st.qdd_error(pred, ref)
+    assert np.median(err) < 0.5 * np.median(err0), (np.median(err), np.median(err0))
     rel = oracle.residual(osub, q, qd, tau, pred, arm)
-    thr = 1e-2
     H = osub.crba(q)
-    ok = rel <= thr
-    for e in np.nonzero(ok)[0]:
-        lmin = np.linalg.eigvalsh(H[e] + np.diag(arm[:, e])).min()
-        bound = thr * max(np.linalg.norm(tau[:, e]), 1e-3) / lmin
-        assert np.linalg.norm(pred[:, e] - ref[:, e]) <= 1.01 * bound + 1e-3
+    accepted = {}
+    for thr in (1e-2, 3e-2, 1e-1, 3e-1):
+        ok = rel <= thr
+        accepted[thr] = float(ok.mean())
+        for e in np.nonzero(ok)[0]:
+            lmin = np.linalg.eigvalsh(H[e] + np.diag(arm[:, e])).min()
+            bound = thr * max(np.linalg.norm(tau[:, e]), 1e-3) / lmin
+            assert np.linalg.norm(pred[:, e] - ref[:, e]) <= 1.01 * bound + 1e-3
     Wt, bt, norm = S.get_params()
     S.close()
     simd.close()
     n_env = 65536
+    thr = 1e-2
     w = synth.path_rollout(n_env, seed=2003)
     sim = sg.from_workload(w)
     S2 = sg.Surrogate(sim, 64)
@@ -219,10 +231,11 @@ def test_trained_surrogate_error_bound_and_gain(sg):
         sim.step(act)
     torch.cuda.synchronize()
     t_aba = (time.perf_counter() - t0) / 5
-    report = {"train_loss": hist, "qdd_err_vs_fp64_oracle": {"median": float(np.median(err)),
-                                                            "p99": float(np.quantile(err, 0.99)),
-                                                            "max": float(err.max())},
-              "accepted_fraction_heldout": float(ok.mean()), "fallback_rate_65536": fb / (5 * 4 * n_env),
+    report = {"train_loss": hist, "val_qdd_err_median_per_epoch": val_hist,
+              "stepping_qdd_err_vs_fp64_oracle": {"untrained_median": float(np.median(err0)),
+                                                  "median": float(np.median(err)),
+                                                  "p99": float(np.quantile(err, 0.99)), "max": float(err.max())},
+              "accepted_fraction_stepping_states": accepted, "fallback_rate_65536": fb / (5 * 4 * n_env),
               "env_steps_per_s_surrogate": n_env / t_sur, "env_steps_per_s_plain": n_env / t_aba,
               "surrogate_over_plain": t_aba / t_sur}
     print(json.dumps(report))
