@@ -90,12 +90,13 @@ __device__ __forceinline__ void stage_input(uint4* xs, int lane, const float* x,
   }
 }
 
-// The forward pass for the wave's 64 staged inputs. ws: weight image,
-// bias: bias image, xs: staged inputs, os: output image [64 envs][16]
-// floats. Callers synchronize around it.
-template <int H3, int ACT>
+// The forward pass for NT of the 4 staged 16-env tiles, starting at tile
+// t0 (a wave computes all four, or each of four waves one). ws: weight
+// image, bias: bias image, xs: staged inputs, os: output image [64
+// envs][16] floats. Callers synchronize around it.
+template <int H3, int ACT, int NT = 4>
 __device__ __forceinline__ void mlp_wave(const uint4* __restrict__ ws, const float* __restrict__ bias,
-                                         const uint4* __restrict__ xs, float* __restrict__ os, int lane) {
+                                         const uint4* __restrict__ xs, float* __restrict__ os, int lane, int t0 = 0) {
   using S = PolicyShape<H3>;
   const int g = lane >> 4, j = lane & 15;
   const uint4* W1 = ws;
@@ -103,22 +104,22 @@ __device__ __forceinline__ void mlp_wave(const uint4* __restrict__ ws, const flo
   const uint4* W3 = W2 + kW2Frags;
   const uint4* Wo = W3 + S::kW3Frags;
   const float* bo = bias + kH1 + kH2 + H3;
-  bf16x8 xb[4];
+  bf16x8 xb[NT];
 #pragma unroll
-  for (int n = 0; n < 4; ++n) {
-    uint4 t = xs[(n * 4 + g) * 16 + j];
+  for (int n = 0; n < NT; ++n) {
+    uint4 t = xs[((t0 + n) * 4 + g) * 16 + j];
     xb[n] = *reinterpret_cast<bf16x8*>(&t);
   }
-  f32x4 acc2[8][4];
+  f32x4 acc2[8][NT];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
     const float4 bb = *reinterpret_cast<const float4*>(bias + kH1 + 16 * m + 4 * g);
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acc2[m][n] = f32x4{bb.x, bb.y, bb.z, bb.w};
+    for (int n = 0; n < NT; ++n) acc2[m][n] = f32x4{bb.x, bb.y, bb.z, bb.w};
   }
 #pragma unroll
   for (int kb = 0; kb < 8; ++kb) {
-    f32x4 d1[2][4];
+    f32x4 d1[2][NT];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int m = 2 * kb + h;
@@ -126,46 +127,46 @@ __device__ __forceinline__ void mlp_wave(const uint4* __restrict__ ws, const flo
       const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
       const float4 bb = *reinterpret_cast<const float4*>(bias + 16 * m + 4 * g);
 #pragma unroll
-      for (int n = 0; n < 4; ++n) d1[h][n] = mfma16x16x32(a, xb[n], f32x4{bb.x, bb.y, bb.z, bb.w});
+      for (int n = 0; n < NT; ++n) d1[h][n] = mfma16x16x32(a, xb[n], f32x4{bb.x, bb.y, bb.z, bb.w});
     }
-    bf16x8 hb[4];
+    bf16x8 hb[NT];
 #pragma unroll
-    for (int n = 0; n < 4; ++n) hb[n] = pack_act<ACT>(d1[0][n], d1[1][n]);
+    for (int n = 0; n < NT; ++n) hb[n] = pack_act<ACT>(d1[0][n], d1[1][n]);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       uint4 t = W2[(m * 8 + kb) * 64 + lane];
       const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
 #pragma unroll
-      for (int n = 0; n < 4; ++n) acc2[m][n] = mfma16x16x32(a, hb[n], acc2[m][n]);
+      for (int n = 0; n < NT; ++n) acc2[m][n] = mfma16x16x32(a, hb[n], acc2[m][n]);
     }
   }
-  f32x4 acco[4];
+  f32x4 acco[NT];
   {
     const float4 bb = *reinterpret_cast<const float4*>(bo + 4 * g);
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acco[n] = f32x4{bb.x, bb.y, bb.z, bb.w};
+    for (int n = 0; n < NT; ++n) acco[n] = f32x4{bb.x, bb.y, bb.z, bb.w};
   }
   if constexpr (H3 > 0) {
     // third hidden layer: K-block kb of it is row tiles 2kb, 2kb+1 of layer 2
     constexpr int M3 = H3 / 16;
-    f32x4 acc3[M3][4];
+    f32x4 acc3[M3][NT];
 #pragma unroll
     for (int m = 0; m < M3; ++m) {
       const float4 bb = *reinterpret_cast<const float4*>(bias + kH1 + kH2 + 16 * m + 4 * g);
 #pragma unroll
-      for (int n = 0; n < 4; ++n) acc3[m][n] = f32x4{bb.x, bb.y, bb.z, bb.w};
+      for (int n = 0; n < NT; ++n) acc3[m][n] = f32x4{bb.x, bb.y, bb.z, bb.w};
     }
 #pragma unroll
     for (int kb = 0; kb < kH2 / 32; ++kb) {
-      bf16x8 hb[4];
+      bf16x8 hb[NT];
 #pragma unroll
-      for (int n = 0; n < 4; ++n) hb[n] = pack_act<ACT>(acc2[2 * kb][n], acc2[2 * kb + 1][n]);
+      for (int n = 0; n < NT; ++n) hb[n] = pack_act<ACT>(acc2[2 * kb][n], acc2[2 * kb + 1][n]);
 #pragma unroll
       for (int m = 0; m < M3; ++m) {
         uint4 t = W3[(m * (kH2 / 32) + kb) * 64 + lane];
         const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
 #pragma unroll
-        for (int n = 0; n < 4; ++n) acc3[m][n] = mfma16x16x32(a, hb[n], acc3[m][n]);
+        for (int n = 0; n < NT; ++n) acc3[m][n] = mfma16x16x32(a, hb[n], acc3[m][n]);
       }
     }
 #pragma unroll
@@ -173,7 +174,7 @@ __device__ __forceinline__ void mlp_wave(const uint4* __restrict__ ws, const flo
       uint4 t = Wo[kb * 64 + lane];
       const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
 #pragma unroll
-      for (int n = 0; n < 4; ++n) acco[n] = mfma16x16x32(a, pack_act<ACT>(acc3[2 * kb][n], acc3[2 * kb + 1][n]), acco[n]);
+      for (int n = 0; n < NT; ++n) acco[n] = mfma16x16x32(a, pack_act<ACT>(acc3[2 * kb][n], acc3[2 * kb + 1][n]), acco[n]);
     }
   } else {
 #pragma unroll
@@ -181,13 +182,13 @@ __device__ __forceinline__ void mlp_wave(const uint4* __restrict__ ws, const flo
       uint4 t = Wo[kb * 64 + lane];
       const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
 #pragma unroll
-      for (int n = 0; n < 4; ++n) acco[n] = mfma16x16x32(a, pack_act<ACT>(acc2[2 * kb][n], acc2[2 * kb + 1][n]), acco[n]);
+      for (int n = 0; n < NT; ++n) acco[n] = mfma16x16x32(a, pack_act<ACT>(acc2[2 * kb][n], acc2[2 * kb + 1][n]), acco[n]);
     }
   }
   if (g < 2) {
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
-      *reinterpret_cast<float4*>(os + (16 * n + j) * kOut + 4 * g) =
+    for (int n = 0; n < NT; ++n)
+      *reinterpret_cast<float4*>(os + (16 * (t0 + n) + j) * kOut + 4 * g) =
           make_float4(acco[n][0], acco[n][1], acco[n][2], acco[n][3]);
   }
 }

@@ -37,17 +37,21 @@ struct RollArgs {
 
 template <int H3>
 __device__ __forceinline__ void fill_weights(uint4* sw, float* sb, const uint4* __restrict__ wimg,
-                                             const float* __restrict__ bias, int lane) {
-  for (int i = lane; i < PolicyShape<H3>::kWFrags; i += kWave) sw[i] = wimg[i];
-  for (int i = lane; i < PolicyShape<H3>::kBias; i += kWave) sb[i] = bias[i];
+                                             const float* __restrict__ bias, int tid, int nthreads) {
+  for (int i = tid; i < PolicyShape<H3>::kWFrags; i += nthreads) sw[i] = wimg[i];
+  for (int i = tid; i < PolicyShape<H3>::kBias; i += nthreads) sb[i] = bias[i];
 }
 
-// One workgroup = one wave = 64 envs, for all T steps: weights and the
+// One workgroup = 64 envs and four waves, for all T steps: weights and the
 // envs' link parameters are staged in LDS once, the chain state stays in
-// VGPRs; every step runs the policy on the matrix cores, samples the action,
-// advances the physics and writes the step's rollout rows.
+// wave 0's VGPRs (one env per lane). Every step the four waves run the
+// policy on the matrix cores, one 16-env tile each (they share the LDS
+// weight image; each wave alone on its SIMD), then wave 0 samples the
+// action, advances the physics and writes the step's rollout rows while
+// the other three wait at the next step's barrier.
+constexpr int kRollWaves = 4;
 template <int J, int M, int H3, int ACT>
-__global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
+__global__ void __launch_bounds__(kWave * kRollWaves) k_rollout(RollArgs A) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr size_t kLdsW = lds_w_bytes<H3>(), kLdsBias = lds_bias_bytes<H3>();
   uint4* s_w = reinterpret_cast<uint4*>(lds);
@@ -56,16 +60,18 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
   float* s_o = reinterpret_cast<float*>(lds + kLdsW + kLdsBias + kLdsX);
   float* s_p = reinterpret_cast<float*>(lds + kLdsW + kLdsBias + kLdsX + kLdsO);
   const EnvDev<float>& E = A.E;
-  const int lane = threadIdx.x;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & (kWave - 1);
+  const bool phys = wave == 0;  // the wave that owns the envs' state
   const int e = blockIdx.x * kWave + lane;
-  const bool active = e < E.N;
+  const bool active = phys && e < E.N;
   const int n = M == M_UNI ? J : (active ? E.nd[e] : 0);
   const int Wd = 2 * E.J + 10;
   const size_t N = E.N;
   const uint64_t step0 = read_counter(E);
 
-  fill_weights<H3>(s_w, s_b, A.wimg, A.bias, lane);
-  stage_chain<float, J>(E, e, active ? n : 0, lane, s_p);
+  fill_weights<H3>(s_w, s_b, A.wimg, A.bias, threadIdx.x, kWave * kRollWaves);
+  if (phys) stage_chain<float, J>(E, e, active ? n : 0, lane, s_p);
   __syncthreads();
   LdsPar<float, J, M == M_PRI> ps{s_p, lane};
   float lstd[J], sig[J];
@@ -95,10 +101,14 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
   __syncthreads();
 
   for (int t = 0; t <= A.T; ++t) {
-    stage_input(s_x, lane, x, Wd);
+    if (phys) stage_input(s_x, lane, x, Wd);
     __syncthreads();
-    mlp_wave<H3, ACT>(s_w, s_b, s_x, s_o, lane);
+    mlp_wave<H3, ACT, 1>(s_w, s_b, s_x, s_o, lane, wave);
     __syncthreads();
+    if (!phys) {
+      if (t == A.T) break;
+      continue;
+    }
     float mu[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) mu[j] = s_o[lane * kOut + j];
@@ -125,7 +135,8 @@ __global__ void __launch_bounds__(kWave) k_rollout(RollArgs A) {
     A.done[(size_t)t * N + e] = d;
   }
   if (active) store_state<float, J>(E, e, n, q, qd, prog);
-  if (lane == 0) advance_counter(E, step0, true);  // one wave per block
+  // every wave read the counter before the loop's first barrier
+  if (threadIdx.x == 0) advance_counter(E, step0, true);
 }
 
 // The policy alone on n inputs x [W][n] -> out [J+1][n].
@@ -141,7 +152,7 @@ __global__ void __launch_bounds__(kWave) k_policy(const uint4* __restrict__ wimg
   float* s_o = reinterpret_cast<float*>(lds + kLdsW + kLdsBias + kLdsX);
   const int lane = threadIdx.x;
   const int e = blockIdx.x * kWave + lane;
-  fill_weights<H3>(s_w, s_b, wimg, bias, lane);
+  fill_weights<H3>(s_w, s_b, wimg, bias, lane, kWave);
   float x[kXMax];
 #pragma unroll
   for (int k = 0; k < kXMax; ++k) x[k] = (e < n && k < Wd) ? xin[(size_t)k * n + e] : 0.f;
@@ -213,7 +224,7 @@ static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_bufs* b) {
   A.T = T;
   A.seed = c->seed;
   A.obs = b->obs; A.act = b->act; A.logp = b->logp; A.rew = b->rew; A.done = b->done; A.val = b->val;
-  k_rollout<J, M, H3, ACT><<<dim3((c->N + kWave - 1) / kWave), kWave, lds, c->stream>>>(A);
+  k_rollout<J, M, H3, ACT><<<dim3((c->N + kWave - 1) / kWave), kWave * kRollWaves, lds, c->stream>>>(A);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_gae(c->stream, T, c->N, b->rew, b->val, b->done, b->gamma, b->lam, b->adv, b->ret);
