@@ -113,21 +113,36 @@ __device__ __forceinline__ void stage_block(const EnvDev<T>& E, int e0, int lane
     stage_chain<T, J>(E, e0 + lane, e0 + lane < E.N ? J : 0, lane, sp);
   } else {
     constexpr int rows = P_NSTAGE * J;
+    constexpr int kIter = (rows + 3) / 4;  // rows per lane group of 16
     const int sub = lane >> 4, c = (lane & 15) * 4;
-    const bool vec = (E.N & 3) == 0;
+    const bool full = (E.N & 3) == 0 && e0 + 64 <= E.N;
+    if (full) {
+      // every row whole: all of this lane's loads issued before any LDS
+      // store (a fixed trip count the compiler unrolls)
+      float4 v[kIter];
+#pragma unroll
+      for (int k = 0; k < kIter; ++k) {
+        const int r = 4 * k + sub;
+        const int f = r / J, j = r % J;
+        v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r < rows && j < E.J) v[k] = *reinterpret_cast<const float4*>(E.par + ((size_t)f * E.J + j) * E.N + e0 + c);
+      }
+#pragma unroll
+      for (int k = 0; k < kIter; ++k) {
+        const int r = 4 * k + sub;
+        if (r < rows) *reinterpret_cast<float4*>(sp + r * 64 + c) = v[k];
+      }
+      return;
+    }
     for (int r = sub; r < rows; r += 4) {
       const int f = r / J, j = r % J;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (j < E.J) {
         const T* src = E.par + ((size_t)f * E.J + j) * E.N + e0 + c;
-        if (vec && e0 + c + 3 < E.N) {
-          v = *reinterpret_cast<const float4*>(src);
-        } else {
-          v.x = e0 + c < E.N ? src[0] : 0.f;
-          v.y = e0 + c + 1 < E.N ? src[1] : 0.f;
-          v.z = e0 + c + 2 < E.N ? src[2] : 0.f;
-          v.w = e0 + c + 3 < E.N ? src[3] : 0.f;
-        }
+        v.x = e0 + c < E.N ? src[0] : 0.f;
+        v.y = e0 + c + 1 < E.N ? src[1] : 0.f;
+        v.z = e0 + c + 2 < E.N ? src[2] : 0.f;
+        v.w = e0 + c + 3 < E.N ? src[3] : 0.f;
       }
       *reinterpret_cast<float4*>(sp + r * 64 + c) = v;
     }
