@@ -10,7 +10,7 @@ Tolerances:
   outputs that such FP32-level errors move by more than 1e-4 is derived
   from the oracle side alone (pinlib.flip_share: the emulating forward pass
   with every hidden unit perturbed by the error model of an FP32 evaluation,
-  on observations of the path workload): about 1.1 % for this network. The
+  on observations of the path workload): about 1.5 % for this network. The
   check allows twice that share plus four binomial deviations of outputs
   above 1e-4, |d out| <= 2e-3 everywhere and a median <= 2e-5.
 * log-density, GAE: relative 1e-5 (FP32 accumulation).
