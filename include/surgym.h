@@ -239,12 +239,49 @@ enum { SG_SCHED_PADDED = 0, SG_SCHED_SORTED = 1, SG_SCHED_PER_CLASS = 2, SG_SCHE
 sg_status sg_set_schedule(sg_ctx* ctx, int32_t schedule);
 sg_status sg_get_schedule(const sg_ctx* ctx, int32_t* schedule);
 
+/* Mapping of the forward-dynamics solve onto waves (ABA, Featherstone
+ * Table 7.1; the step of Sec. III): waves = 1, one env per lane and one wave
+ * per 64 envs runs the whole solve; waves = 4, a wave team: the 64 envs'
+ * workgroup has four waves, wave 0 keeps the state and runs the serial
+ * recursions, and link j's inertia rotation and bias force (pass 1) run in
+ * wave j mod 4, exchanged through LDS (the four waves also stage the
+ * block's parameters together). The same operations in other waves: the
+ * results agree with the one-wave solve to FP32 rounding. waves = 0 (the
+ * default): the library picks: the team in sg_rollout, and in sg_step while
+ * the launch's blocks all fit at once (N <= 128 x compute units: a team
+ * block takes 62 KB of LDS, two per compute unit), one wave beyond. The
+ * team runs in sg_step's padded schedule for chains of 4 to 9 joints and in
+ * sg_rollout for chains of 4 to 7 joints with the 256-128 policy (the
+ * Table II network's weight image leaves no LDS for the exchange);
+ * elsewhere, and on FP64 contexts, the one-wave kernels run. SG_E_INVAL for
+ * other values, SG_E_UNSUPPORTED for 4 on an FP64 context. */
+sg_status sg_set_team(sg_ctx* ctx, int32_t waves);
+sg_status sg_get_team(const sg_ctx* ctx, int32_t* waves);
+
 /* Autotuner: time `trials` steps (after one warm-up) of every available
- * schedule with the given actions [J][N] (device), restoring the state after
- * each, select the fastest and report ms per step per schedule in
- * ms_per_step (host float[4], -1 for unavailable; may be NULL) and the
- * choice in *best. Synchronizes the context's stream. */
-sg_status sg_autotune_step(sg_ctx* ctx, const void* actions, int32_t trials, int32_t* best, float* ms_per_step);
+ * candidate with the given actions [J][N] (device), restoring the state
+ * after each, and make the fastest the context's schedule and mapping.
+ * Candidates, in the order of ms_per_step (host float[5], -1 for
+ * unavailable; may be NULL): padded, sorted, per-class, persistent (one wave
+ * per 64 envs), and padded with a wave team (sg_set_team; FP32 chains of 4
+ * to 9 joints). *best gets the schedule, *best_team the waves per block
+ * (either may be NULL). The choice is remembered for the rest of the
+ * process under the context's key (device architecture, N, number type,
+ * max joints, prismatic joints, chains per env, task, histogram of joint
+ * counts): sg_create of a context with the same key starts from it.
+ * Synchronizes the context's stream. */
+sg_status sg_autotune_step(sg_ctx* ctx, const void* actions, int32_t trials, int32_t* best, int32_t* best_team,
+                           float* ms_per_step);
+
+/* The remembered autotuner choices as text, one line per key: the key, the
+ * schedule and the waves per block, separated by spaces; for a caller to
+ * store and hand to sg_tuning_import in a later process. Writes at most cap
+ * bytes including the terminating 0 into buf (cap 0: none; buf may then be
+ * NULL) and sets *len to the full length including the 0. sg_tuning_import
+ * merges such lines into the process's choices (later lines win); a
+ * malformed line gives SG_E_INVAL, the lines before it stay merged. */
+sg_status sg_tuning_export(char* buf, size_t cap, size_t* len);
+sg_status sg_tuning_import(const char* text);
 
 /* Observation of the current state, obs [W][N] real (device). */
 sg_status sg_observe(sg_ctx* ctx, void* obs);

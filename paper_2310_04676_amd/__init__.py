@@ -108,6 +108,11 @@ def version() -> str:
     return lib.sg_version().decode()
 
 
+def _check(st):
+    if st != SG_OK:
+        raise SgError(st, lib.sg_last_error(None).decode())
+
+
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
@@ -414,7 +419,12 @@ SG_SCHED_PADDED, SG_SCHED_SORTED, SG_SCHED_PER_CLASS, SG_SCHED_PERSISTENT = 0, 1
 SCHEDULE_NAMES = ("padded", "sorted", "per_class", "persistent")
 lib.sg_set_schedule.argtypes = [_vp, C.c_int32]
 lib.sg_get_schedule.argtypes = [_vp, C.POINTER(C.c_int32)]
-lib.sg_autotune_step.argtypes = [_vp, _vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+lib.sg_set_team.argtypes = [_vp, C.c_int32]
+lib.sg_get_team.argtypes = [_vp, C.POINTER(C.c_int32)]
+lib.sg_autotune_step.argtypes = [_vp, _vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_float)]
+lib.sg_tuning_export.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
+lib.sg_tuning_import.argtypes = [C.c_char_p]
 
 
 def _set_schedule(self, schedule):
@@ -427,18 +437,58 @@ def _get_schedule(self):
     return s.value
 
 
+CANDIDATE_NAMES = SCHEDULE_NAMES + ("padded_team",)
+
+
 def _autotune_step(self, actions, trials=5):
-    """Time every step schedule on these actions (state restored after
-    each); the fastest becomes the context's schedule. Returns
-    (best, {name: ms per step})."""
-    best = C.c_int32()
-    ms = (C.c_float * 4)()
-    self._call(lib.sg_autotune_step, _dptr(actions, self.tdtype), C.c_int32(trials), C.byref(best), ms)
-    return best.value, {SCHEDULE_NAMES[i]: ms[i] for i in range(4) if ms[i] >= 0}
+    """Time every step schedule and mapping on these actions (state restored
+    after each); the fastest becomes the context's schedule and mapping.
+    Returns (schedule, waves per block, {candidate name: ms per step})."""
+    best, team = C.c_int32(), C.c_int32()
+    ms = (C.c_float * 5)()
+    self._call(lib.sg_autotune_step, _dptr(actions, self.tdtype), C.c_int32(trials), C.byref(best),
+               C.byref(team), ms)
+    return best.value, team.value, {CANDIDATE_NAMES[i]: ms[i] for i in range(5) if ms[i] >= 0}
+
+
+def tuning_export():
+    """The autotuner's remembered choices of this process as text."""
+    n = C.c_size_t()
+    _check(lib.sg_tuning_export(None, 0, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    _check(lib.sg_tuning_export(buf, n.value, C.byref(n)))
+    return buf.value.decode()
+
+
+def tuning_import(text):
+    """Merge choices from tuning_export() of an earlier process."""
+    _check(lib.sg_tuning_import(text.encode()))
+
+
+def save_tuning(path):
+    with open(path, "w") as f:
+        f.write(tuning_export())
+
+
+def load_tuning(path):
+    with open(path) as f:
+        tuning_import(f.read())
+
+
+def _set_team(self, waves):
+    self._call(lib.sg_set_team, C.c_int32(waves))
+
+
+def _get_team(self):
+    w = C.c_int32()
+    self._call(lib.sg_get_team, C.byref(w))
+    return w.value
 
 
 Sim.set_schedule = _set_schedule
 Sim.get_schedule = _get_schedule
+Sim.set_team = _set_team
+Sim.get_team = _get_team
 Sim.autotune_step = _autotune_step
 
 

@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(64) k_adjoint(AdjArgs A) {
             tau[j] = 0.f;
           }
         }
-        aba<float, J>(ps, n, q, qd, tau, arm, E.g, qdd);
+        aba_lwa<float, J>(ps, n, q, qd, tau, arm, E.g, qdd);
         ps.fence();
 #pragma unroll
         for (int j = 0; j < J; ++j) {

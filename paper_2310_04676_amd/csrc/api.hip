@@ -4,7 +4,11 @@
 #include <string.h>
 
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "internal.hpp"
@@ -44,6 +48,42 @@ void free_ctx(sg_ctx* c) {
 }  // namespace
 
 namespace {
+
+// Autotuner choices remembered for the rest of the process, keyed by what the
+// step's cost depends on: the device's architecture, N, the number type, the
+// chain shape (max joints, prismatic joints, chains per env), the task and
+// the histogram of joint counts. Value: (schedule, waves per block).
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;
+
+std::string tuning_key(const sg_ctx* c, const int32_t* n_dof) {
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+  }
+  std::vector<int> hist(c->J + 1, 0);
+  for (int e = 0; e < c->N; ++e) hist[n_dof[e]] += 1;
+  std::ostringstream k;
+  k << arch << "|n=" << c->N << "|" << (c->dtype == SG_F64 ? "f64" : "f32") << "|j=" << c->J
+    << "|pr=" << (c->prismatic ? 1 : 0) << "|c=" << c->chains << "|task=" << c->task << "|dof=";
+  bool first = true;
+  for (int d = 1; d <= c->J; ++d)
+    if (hist[d]) {
+      k << (first ? "" : ",") << d << "x" << hist[d];
+      first = false;
+    }
+  return k.str();
+}
+
+bool schedule_allowed(const sg_ctx* c, int s) {
+  if (s < SG_SCHED_PADDED || s > SG_SCHED_PERSISTENT) return false;
+  return s == SG_SCHED_PADDED || (c->dtype == SG_F32 && !c->prismatic && c->chains == 1);
+}
+
+bool team_allowed(const sg_ctx* c, int w) { return w == 1 || (w == sgk::kTeam && c->dtype == SG_F32); }
 
 // The policy's weight and bias images (the layout of mlp.hpp, through
 // img_source) from per-layer BF16 weights and FP32 biases.
@@ -146,6 +186,7 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
   }
   sg_ctx* c = new sg_ctx();
   hipError_t he = hipGetDevice(&c->device);
+  if (he == hipSuccess) he = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
   if (he != hipSuccess) {
     delete c;
     return hip_fail(nullptr, he, "hipGetDevice");
@@ -273,6 +314,16 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
     delete c;
     return hip_fail(nullptr, e, "sg_create");
   }
+  // a choice the autotuner made for a context of the same key
+  c->tune_key = tuning_key(c, r->n_dof);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(c->tune_key);
+    if (it != g_tune.end() && schedule_allowed(c, it->second.first) && team_allowed(c, it->second.second)) {
+      c->schedule = it->second.first;
+      c->team = it->second.second;
+    }
+  }
   *out = c;
   return SG_OK;
 }
@@ -333,7 +384,23 @@ sg_status sg_get_schedule(const sg_ctx* c, int32_t* schedule) {
   return SG_OK;
 }
 
-sg_status sg_autotune_step(sg_ctx* c, const void* act, int32_t trials, int32_t* best, float* ms_per_step) {
+sg_status sg_set_team(sg_ctx* c, int32_t waves) {
+  if (!c) return SG_E_INVAL;
+  if (waves != 0 && waves != 1 && waves != sgk::kTeam) return fail(c, SG_E_INVAL, "sg_set_team: waves must be 0, 1 or 4");
+  if (waves == sgk::kTeam && c->dtype != SG_F32)
+    return fail(c, SG_E_UNSUPPORTED, "sg_set_team: wave teams need an FP32 context");
+  c->team = waves;
+  return SG_OK;
+}
+
+sg_status sg_get_team(const sg_ctx* c, int32_t* waves) {
+  if (!c || !waves) return SG_E_INVAL;
+  *waves = c->team;
+  return SG_OK;
+}
+
+sg_status sg_autotune_step(sg_ctx* c, const void* act, int32_t trials, int32_t* best, int32_t* best_team,
+                           float* ms_per_step) {
   if (!c) return SG_E_INVAL;
   if (!act || !aligned(act) || trials < 1 || trials > 10000) return fail(c, SG_E_INVAL, "sg_autotune_step: bad argument");
   const size_t esz = c->dtype == SG_F64 ? sizeof(double) : sizeof(float);
@@ -358,16 +425,21 @@ sg_status sg_autotune_step(sg_ctx* c, const void* act, int32_t trials, int32_t* 
   const size_t gsb = (size_t)c->gs_width * c->N * esz;
   if (e == hipSuccess && c->gs) e = hipMalloc(&gsv, gsb);
   if (e == hipSuccess && c->gs) e = hipMemcpyAsync(gsv, c->gs, gsb, hipMemcpyDeviceToDevice, c->stream);
-  const int saved = c->schedule;
-  const int n_sched = (c->dtype == SG_F32 && !c->prismatic && c->chains == 1) ? 4 : 1;
+  const int saved = c->schedule, saved_team = c->team;
+  // candidates: the four schedules with one wave per 64 envs, then the
+  // padded schedule with a wave team
+  const int sched[5] = {SG_SCHED_PADDED, SG_SCHED_SORTED, SG_SCHED_PER_CLASS, SG_SCHED_PERSISTENT, SG_SCHED_PADDED};
+  const int team[5] = {1, 1, 1, 1, sgk::kTeam};
   float best_ms = 0.f;
-  int best_s = SG_SCHED_PADDED;
-  for (int s = 0; s < 4 && e == hipSuccess; ++s) {
-    if (ms_per_step) ms_per_step[s] = -1.f;
-    if (s >= n_sched) continue;
-    c->schedule = s;
-    for (int k = 0; k <= trials && e == hipSuccess; ++k) {
-      if (k == 1) e = hipEventRecord(e0, c->stream);
+  int best_k = 0;
+  for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+    if (ms_per_step) ms_per_step[k] = -1.f;
+    if (!schedule_allowed(c, sched[k]) || !team_allowed(c, team[k])) continue;
+    if (team[k] != 1 && !sgk::step_team_available(c)) continue;
+    c->schedule = sched[k];
+    c->team = team[k];
+    for (int i = 0; i <= trials && e == hipSuccess; ++i) {
+      if (i == 1) e = hipEventRecord(e0, c->stream);
       if (e == hipSuccess) e = sgk::launch_step(c, act, obs, rew, done, 0);
     }
     if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
@@ -375,10 +447,10 @@ sg_status sg_autotune_step(sg_ctx* c, const void* act, int32_t trials, int32_t* 
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     ms /= (float)trials;
-    if (ms_per_step) ms_per_step[s] = ms;
-    if (s == 0 || ms < best_ms) {
+    if (ms_per_step) ms_per_step[k] = ms;
+    if (k == 0 || ms < best_ms) {
       best_ms = ms;
-      best_s = s;
+      best_k = k;
     }
     if (e == hipSuccess) e = hipMemcpyAsync(c->q, q, JN * esz, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->qd, qd, JN * esz, hipMemcpyDeviceToDevice, c->stream);
@@ -386,8 +458,14 @@ sg_status sg_autotune_step(sg_ctx* c, const void* act, int32_t trials, int32_t* 
     if (e == hipSuccess && c->gs) e = hipMemcpyAsync(c->gs, gsv, gsb, hipMemcpyDeviceToDevice, c->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  c->schedule = e == hipSuccess ? best_s : saved;
-  if (best && e == hipSuccess) *best = best_s;
+  c->schedule = e == hipSuccess ? sched[best_k] : saved;
+  c->team = e == hipSuccess ? team[best_k] : saved_team;
+  if (e == hipSuccess) {
+    if (best) *best = sched[best_k];
+    if (best_team) *best_team = team[best_k];
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[c->tune_key] = {sched[best_k], team[best_k]};
+  }
   if (gsv) (void)hipFree(gsv);
   void* ptrs[] = {q, qd, pr, obs, rew, done};
   for (void* p : ptrs)
@@ -395,6 +473,41 @@ sg_status sg_autotune_step(sg_ctx* c, const void* act, int32_t trials, int32_t* 
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   return e == hipSuccess ? SG_OK : hip_fail(c, e, "sg_autotune_step");
+}
+
+sg_status sg_tuning_export(char* buf, size_t cap, size_t* len) {
+  if (!len || (cap && !buf)) return SG_E_INVAL;
+  std::string text;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (const auto& kv : g_tune)
+      text += kv.first + " " + std::to_string(kv.second.first) + " " + std::to_string(kv.second.second) + "\n";
+  }
+  *len = text.size() + 1;
+  if (cap) {
+    const size_t n = text.size() < cap - 1 ? text.size() : cap - 1;
+    memcpy(buf, text.data(), n);
+    buf[n] = 0;
+  }
+  return SG_OK;
+}
+
+sg_status sg_tuning_import(const char* text) {
+  if (!text) return SG_E_INVAL;
+  std::istringstream in(text);
+  std::string line;
+  while (std::getline(in, line)) {
+    if (line.empty()) continue;
+    std::istringstream ls(line);
+    std::string key, rest;
+    int s = -1, w = -1;
+    if (!(ls >> key >> s >> w) || (ls >> rest) || s < SG_SCHED_PADDED || s > SG_SCHED_PERSISTENT ||
+        (w != 1 && w != sgk::kTeam))
+      return fail(nullptr, SG_E_INVAL, "sg_tuning_import: malformed line");
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[key] = {s, w};
+  }
+  return SG_OK;
 }
 
 sg_status sg_observe(sg_ctx* c, void* obs) {

@@ -463,87 +463,100 @@ __device__ __forceinline__ void shift_inertia(const T* o, const AI<T>& I, AI<T>&
 // base-oriented axis, offset, velocity-product acceleration c, bias force
 // p and rotated link inertia; offsets stay at link scale, so no precision
 // is lost to distant reference points.
-template <typename T, int J, class PS>
-__device__ __forceinline__ void aba_lwa(PS& ps, int n, const T (&q)[J], const T (&qd)[J], const T (&tau)[J],
-                                        const T (&arm)[J], const T* grav, T (&qdd)[J]) {
-  T aw[J][3], ow[J][3], cj[J][6], pj[J][6], Iw[J][6], hw[J][3], U[J][6], invD[J], uj[J];
-  // pass 1
-  ps.fence();
-  {
-    T W[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)};
-    T w[3] = {T(0), T(0), T(0)}, vl[3] = {T(0), T(0), T(0)};
+//
+// Pass 1 splits into a serial part per joint (p1_chain: the joint's axis
+// and offset in the base orientation, the velocities carried to its origin,
+// c, and the next W) and a part that needs only that joint's W, w and v
+// (p1_link: the rotated inertia and the bias force), which other waves can
+// take over (aba_lwa_team below).
+
+// Pass 1, serial part for joint j: axis a and offset o in the base
+// orientation (from the parent's W), the parent's velocity moved to this
+// joint's origin, the joint's velocity added, c = v x (S qd), and W advanced
+// to link j's orientation. Returns true for a prismatic joint.
+template <class PS, typename T>
+__device__ __forceinline__ bool p1_chain(Jp<T>& p, T qj, T qv, T (&W)[9], T (&w)[3], T (&vl)[3], T* a, T* o,
+                                         T* cj) {
+  const bool pr = slide<PS>(p, qj);
+  o[0] = W[0] * p.ox + W[1] * p.oy + W[2] * p.oz;
+  o[1] = W[3] * p.ox + W[4] * p.oy + W[5] * p.oz;
+  o[2] = W[6] * p.ox + W[7] * p.oy + W[8] * p.oz;
+  a[0] = W[0] * p.ax + W[1] * p.ay + W[2] * p.az;
+  a[1] = W[3] * p.ax + W[4] * p.ay + W[5] * p.az;
+  a[2] = W[6] * p.ax + W[7] * p.ay + W[8] * p.az;
+  // the parent's velocity at this joint's origin
+  vl[0] += w[1] * o[2] - w[2] * o[1];
+  vl[1] += w[2] * o[0] - w[0] * o[2];
+  vl[2] += w[0] * o[1] - w[1] * o[0];
+  const T sx = a[0] * qv, sy = a[1] * qv, sz = a[2] * qv;
+  if (!pr) {
+    w[0] += sx; w[1] += sy; w[2] += sz;
+    // c = v x (S qd), S qd = (s; 0): (w x s; vl x s)
+    cj[0] = w[1] * sz - w[2] * sy;
+    cj[1] = w[2] * sx - w[0] * sz;
+    cj[2] = w[0] * sy - w[1] * sx;
+    cj[3] = vl[1] * sz - vl[2] * sy;
+    cj[4] = vl[2] * sx - vl[0] * sz;
+    cj[5] = vl[0] * sy - vl[1] * sx;
+    T sn, cs, R[9], Wn[9];
+    sc_hw(qj, &sn, &cs);
+    rodrigues(p, sn, cs, R);
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      if (j < n) {
-        Jp<T> p = ps.get(j);
-        const bool pr = slide<PS>(p, q[j]);
-        const T o[3] = {W[0] * p.ox + W[1] * p.oy + W[2] * p.oz, W[3] * p.ox + W[4] * p.oy + W[5] * p.oz,
-                        W[6] * p.ox + W[7] * p.oy + W[8] * p.oz};
-        const T a[3] = {W[0] * p.ax + W[1] * p.ay + W[2] * p.az, W[3] * p.ax + W[4] * p.ay + W[5] * p.az,
-                        W[6] * p.ax + W[7] * p.ay + W[8] * p.az};
-        // the parent's velocity at this joint's origin
-        vl[0] += w[1] * o[2] - w[2] * o[1];
-        vl[1] += w[2] * o[0] - w[0] * o[2];
-        vl[2] += w[0] * o[1] - w[1] * o[0];
-        const T qv = qd[j];
-        const T sx = a[0] * qv, sy = a[1] * qv, sz = a[2] * qv;
-        if (!pr) {
-          w[0] += sx; w[1] += sy; w[2] += sz;
-          // c = v x (S qd), S qd = (s; 0): (w x s; vl x s)
-          cj[j][0] = w[1] * sz - w[2] * sy;
-          cj[j][1] = w[2] * sx - w[0] * sz;
-          cj[j][2] = w[0] * sy - w[1] * sx;
-          cj[j][3] = vl[1] * sz - vl[2] * sy;
-          cj[j][4] = vl[2] * sx - vl[0] * sz;
-          cj[j][5] = vl[0] * sy - vl[1] * sx;
-          T s, c, R[9], Wn[9];
-          sc_hw(q[j], &s, &c);
-          rodrigues(p, s, c, R);
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-          for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k)
+        Wn[r * 3 + k] = W[r * 3 + 0] * R[0 * 3 + k] + W[r * 3 + 1] * R[1 * 3 + k] + W[r * 3 + 2] * R[2 * 3 + k];
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
-              Wn[r * 3 + k] = W[r * 3 + 0] * R[0 * 3 + k] + W[r * 3 + 1] * R[1 * 3 + k] + W[r * 3 + 2] * R[2 * 3 + k];
-#pragma unroll
-          for (int k = 0; k < 9; ++k) W[k] = Wn[k];
-        } else {
-          // prismatic: S qd = (0; s), c = (0; w x s), no rotation
-          vl[0] += sx; vl[1] += sy; vl[2] += sz;
-          cj[j][0] = T(0); cj[j][1] = T(0); cj[j][2] = T(0);
-          cj[j][3] = w[1] * sz - w[2] * sy;
-          cj[j][4] = w[2] * sx - w[0] * sz;
-          cj[j][5] = w[0] * sy - w[1] * sx;
-        }
-        // the link's inertia in the base orientation: W I_O W^T, W h
-        {
-          const T S6[6] = {p.ixx, p.iyy, p.izz, p.ixy, p.ixz, p.iyz};
-          sym_rot(W, S6, Iw[j]);
-          hw[j][0] = W[0] * p.hx + W[1] * p.hy + W[2] * p.hz;
-          hw[j][1] = W[3] * p.hx + W[4] * p.hy + W[5] * p.hz;
-          hw[j][2] = W[6] * p.hx + W[7] * p.hy + W[8] * p.hz;
-        }
-        // p = v x* (I v), I v = (Iw w + h x vl; m vl - h x w)
-        {
-          const T* I = Iw[j];
-          const T* h = hw[j];
-          const T n0 = I[S00] * w[0] + I[S01] * w[1] + I[S02] * w[2] + (h[1] * vl[2] - h[2] * vl[1]);
-          const T n1 = I[S01] * w[0] + I[S11] * w[1] + I[S12] * w[2] + (h[2] * vl[0] - h[0] * vl[2]);
-          const T n2 = I[S02] * w[0] + I[S12] * w[1] + I[S22] * w[2] + (h[0] * vl[1] - h[1] * vl[0]);
-          const T f0 = p.m * vl[0] - (h[1] * w[2] - h[2] * w[1]);
-          const T f1 = p.m * vl[1] - (h[2] * w[0] - h[0] * w[2]);
-          const T f2 = p.m * vl[2] - (h[0] * w[1] - h[1] * w[0]);
-          pj[j][0] = (w[1] * n2 - w[2] * n1) + (vl[1] * f2 - vl[2] * f1);
-          pj[j][1] = (w[2] * n0 - w[0] * n2) + (vl[2] * f0 - vl[0] * f2);
-          pj[j][2] = (w[0] * n1 - w[1] * n0) + (vl[0] * f1 - vl[1] * f0);
-          pj[j][3] = w[1] * f2 - w[2] * f1;
-          pj[j][4] = w[2] * f0 - w[0] * f2;
-          pj[j][5] = w[0] * f1 - w[1] * f0;
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) { aw[j][k] = a[k]; ow[j][k] = o[k]; }
-      }
-    }
+    for (int k = 0; k < 9; ++k) W[k] = Wn[k];
+  } else {
+    // prismatic: S qd = (0; s), c = (0; w x s), no rotation
+    vl[0] += sx; vl[1] += sy; vl[2] += sz;
+    cj[0] = T(0); cj[1] = T(0); cj[2] = T(0);
+    cj[3] = w[1] * sz - w[2] * sy;
+    cj[4] = w[2] * sx - w[0] * sz;
+    cj[5] = w[0] * sy - w[1] * sx;
   }
+  return pr;
+}
+
+// Pass 1, the part that needs only link j's orientation W and velocity
+// (w; vl) at its origin: the link's inertia in the base orientation
+// (W I_O W^T, W h) and its bias force p = v x* (I v) with
+// I v = (Iw w + h x vl; m vl - h x w).
+template <typename T>
+__device__ __forceinline__ void p1_link(const Jp<T>& p, const T (&W)[9], const T (&w)[3], const T (&vl)[3], T* Iw,
+                                        T* hw, T* pj) {
+  {
+    const T S6[6] = {p.ixx, p.iyy, p.izz, p.ixy, p.ixz, p.iyz};
+    sym_rot(W, S6, Iw);
+    hw[0] = W[0] * p.hx + W[1] * p.hy + W[2] * p.hz;
+    hw[1] = W[3] * p.hx + W[4] * p.hy + W[5] * p.hz;
+    hw[2] = W[6] * p.hx + W[7] * p.hy + W[8] * p.hz;
+  }
+  const T* I = Iw;
+  const T* h = hw;
+  const T n0 = I[S00] * w[0] + I[S01] * w[1] + I[S02] * w[2] + (h[1] * vl[2] - h[2] * vl[1]);
+  const T n1 = I[S01] * w[0] + I[S11] * w[1] + I[S12] * w[2] + (h[2] * vl[0] - h[0] * vl[2]);
+  const T n2 = I[S02] * w[0] + I[S12] * w[1] + I[S22] * w[2] + (h[0] * vl[1] - h[1] * vl[0]);
+  const T f0 = p.m * vl[0] - (h[1] * w[2] - h[2] * w[1]);
+  const T f1 = p.m * vl[1] - (h[2] * w[0] - h[0] * w[2]);
+  const T f2 = p.m * vl[2] - (h[0] * w[1] - h[1] * w[0]);
+  pj[0] = (w[1] * n2 - w[2] * n1) + (vl[1] * f2 - vl[2] * f1);
+  pj[1] = (w[2] * n0 - w[0] * n2) + (vl[2] * f0 - vl[0] * f2);
+  pj[2] = (w[0] * n1 - w[1] * n0) + (vl[0] * f1 - vl[1] * f0);
+  pj[3] = w[1] * f2 - w[2] * f1;
+  pj[4] = w[2] * f0 - w[0] * f2;
+  pj[5] = w[0] * f1 - w[1] * f0;
+}
+
+// Passes 2 and 3 of the base-oriented solve from pass 1's per-joint axis aw,
+// offset ow, c, bias force pj and rotated inertia (Iw, hw).
+template <typename T, int J, class PS>
+__device__ __forceinline__ void aba_lwa_io(PS& ps, int n, const T (&tau)[J], const T (&arm)[J], const T* grav,
+                                           const T (&aw)[J][3], const T (&ow)[J][3], const T (&cj)[J][6],
+                                           const T (&pj)[J][6], const T (&Iw)[J][6], const T (&hw)[J][3],
+                                           T (&qdd)[J]) {
+  T U[J][6], invD[J], uj[J];
   // pass 2
   ps.fence();
   AI<T> acc;
@@ -655,6 +668,150 @@ __device__ __forceinline__ void aba_lwa(PS& ps, int n, const T (&q)[J], const T 
       qdd[j] = T(0);
     }
   }
+}
+
+template <typename T, int J, class PS>
+__device__ __forceinline__ void aba_lwa(PS& ps, int n, const T (&q)[J], const T (&qd)[J], const T (&tau)[J],
+                                        const T (&arm)[J], const T* grav, T (&qdd)[J]) {
+  T aw[J][3], ow[J][3], cj[J][6], pj[J][6], Iw[J][6], hw[J][3];
+  // pass 1
+  ps.fence();
+  {
+    T W[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)};
+    T w[3] = {T(0), T(0), T(0)}, vl[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (j < n) {
+        Jp<T> p = ps.get(j);
+        p1_chain<PS>(p, q[j], qd[j], W, w, vl, aw[j], ow[j], cj[j]);
+        p1_link(p, W, w, vl, Iw[j], hw[j], pj[j]);
+      }
+    }
+  }
+  aba_lwa_io<T, J>(ps, n, tau, arm, grav, aw, ow, cj, pj, Iw, hw, qdd);
+}
+
+// Wave team: kTeam waves of one workgroup hold the same 64 envs (lane l of
+// every wave is env l of the block) and share pass 1 of the base-oriented
+// solve. Wave 0 owns the envs' state, runs the serial chain of pass 1 and
+// passes 2 and 3. The joint-independent work of link j (p1_link: its
+// inertia rotated into the base orientation and its bias force, about half
+// of pass 1) is done by wave j mod kTeam: each helper wave recomputes the
+// chain up to its links from the state wave 0 publishes in LDS and hands
+// back 15 numbers per link through LDS. Two workgroup barriers per solve:
+// after the state is published and after the links are handed back.
+// LDS: the state as [(2J+3)/4][64] float4, the links as
+// [team_links(J)][4][64] float4 (Iw 0-3 | Iw 4-5, hw 0-1 | hw 2, p 0-2 |
+// p 3-5, -); every lane touches only its own env's entries.
+constexpr int kTeam = 4;
+__host__ __device__ constexpr int team_slot(int j) { return j - (j + kTeam - 1) / kTeam; }
+__host__ __device__ constexpr int team_links(int J) { return team_slot(J); }
+__host__ __device__ constexpr int team_state_slots(int J) { return (2 * J + 3) / 4; }
+__host__ __device__ constexpr size_t team_lds_bytes(int J) { return (size_t)team_links(J) * 4 * 64 * 16; }
+
+struct TeamLds {
+  float4* st;  // [team_state_slots(J)][64]
+  float4* lk;  // [team_links(J)][4][64]
+  int wave, lane;
+};
+
+template <int J>
+__device__ __forceinline__ void team_put_state(const TeamLds& t, const float (&q)[J], const float (&qd)[J]) {
+  constexpr int S = team_state_slots(J);
+  float v[4 * S];
+#pragma unroll
+  for (int k = 0; k < 4 * S; ++k) v[k] = k < J ? q[k] : (k < 2 * J ? qd[k - J] : 0.f);
+#pragma unroll
+  for (int s = 0; s < S; ++s) t.st[s * 64 + t.lane] = make_float4(v[4 * s], v[4 * s + 1], v[4 * s + 2], v[4 * s + 3]);
+}
+
+template <int J>
+__device__ __forceinline__ void team_get_state(const TeamLds& t, float (&q)[J], float (&qd)[J]) {
+  constexpr int S = team_state_slots(J);
+  float v[4 * S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const float4 x = t.st[s * 64 + t.lane];
+    v[4 * s] = x.x; v[4 * s + 1] = x.y; v[4 * s + 2] = x.z; v[4 * s + 3] = x.w;
+  }
+#pragma unroll
+  for (int k = 0; k < J; ++k) { q[k] = v[k]; qd[k] = v[J + k]; }
+}
+
+__device__ __forceinline__ void team_put_link(const TeamLds& t, int slot, const float* Iw, const float* hw,
+                                              const float* pj) {
+  float4* d = t.lk + slot * 256 + t.lane;
+  d[0] = make_float4(Iw[0], Iw[1], Iw[2], Iw[3]);
+  d[64] = make_float4(Iw[4], Iw[5], hw[0], hw[1]);
+  d[128] = make_float4(hw[2], pj[0], pj[1], pj[2]);
+  d[192] = make_float4(pj[3], pj[4], pj[5], 0.f);
+}
+
+__device__ __forceinline__ void team_get_link(const TeamLds& t, int slot, float* Iw, float* hw, float* pj) {
+  const float4* d = t.lk + slot * 256 + t.lane;
+  const float4 a = d[0], b = d[64], c = d[128], e = d[192];
+  Iw[0] = a.x; Iw[1] = a.y; Iw[2] = a.z; Iw[3] = a.w;
+  Iw[4] = b.x; Iw[5] = b.y; hw[0] = b.z; hw[1] = b.w;
+  hw[2] = c.x; pj[0] = c.y; pj[1] = c.z; pj[2] = c.w;
+  pj[3] = e.x; pj[4] = e.y; pj[5] = e.z;
+}
+
+// The solve as wave 0 of a team runs it (same result as aba_lwa: every
+// quantity is computed by the same expressions, only in another wave).
+// Every wave of the workgroup must be in the matching aba_team_help call.
+template <int J, class PS>
+__device__ __forceinline__ void aba_lwa_team(PS& ps, int n, const float (&q)[J], const float (&qd)[J],
+                                             const float (&tau)[J], const float (&arm)[J], const float* grav,
+                                             float (&qdd)[J], const TeamLds& t) {
+  float aw[J][3], ow[J][3], cj[J][6], pj[J][6], Iw[J][6], hw[J][3];
+  team_put_state<J>(t, q, qd);
+  __syncthreads();
+  ps.fence();
+  {
+    float W[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+    float w[3] = {0.f, 0.f, 0.f}, vl[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (j < n) {
+        Jp<float> p = ps.get(j);
+        p1_chain<PS>(p, q[j], qd[j], W, w, vl, aw[j], ow[j], cj[j]);
+        if (j % kTeam == 0) p1_link(p, W, w, vl, Iw[j], hw[j], pj[j]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+    if (j % kTeam != 0 && j < n) team_get_link(t, team_slot(j), Iw[j], hw[j], pj[j]);
+  aba_lwa_io<float, J>(ps, n, tau, arm, grav, aw, ow, cj, pj, Iw, hw, qdd);
+}
+
+// A helper wave's part of one team solve (t.wave = 1 .. kTeam-1): the chain
+// up to its last link from the published state, and its links handed back.
+template <int J, class PS>
+__device__ __forceinline__ void aba_team_help(PS& ps, int n, const TeamLds& t) {
+  __syncthreads();
+  float q[J], qd[J];
+  team_get_state<J>(t, q, qd);
+  ps.fence();
+  float W[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+  float w[3] = {0.f, 0.f, 0.f}, vl[3] = {0.f, 0.f, 0.f};
+  // last link of this wave: the largest j < J with j % kTeam == wave
+  const int last = t.wave + ((J - 1 - t.wave) / kTeam) * kTeam;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (j <= last && j < n) {
+      Jp<float> p = ps.get(j);
+      float a[3], o[3], c[6];
+      p1_chain<PS>(p, q[j], qd[j], W, w, vl, a, o, c);
+      if (j % kTeam != 0 && j % kTeam == t.wave) {
+        float Iw[6], hw[3], pj[6];
+        p1_link(p, W, w, vl, Iw, hw, pj);
+        team_put_link(t, team_slot(j), Iw, hw, pj);
+      }
+    }
+  }
+  __syncthreads();
 }
 
 // Inverse dynamics for one env: tau = H qdd + C (gravity included).

@@ -104,37 +104,40 @@ __device__ __forceinline__ void stage_chain(const EnvDev<T>& E, int e, int n, in
 
 // The same staging for a block whose 64 envs are contiguous (e0 .. e0 + 63):
 // every [field][joint] row of the block is 64 consecutive values of the
-// parameter block, copied by 16 lanes as 16-byte pieces (FP32); values of
+// parameter block, copied by 16 threads as 16-byte pieces (FP32), NT / 16
+// rows at a time by the block's NT threads (tid = 0 .. NT-1); values of
 // envs past the last one, and of joints past max_dof, zero. The parameter
 // block holds zeros for joints >= an env's n_dof, as stage_chain writes.
-template <typename T, int J>
-__device__ __forceinline__ void stage_block(const EnvDev<T>& E, int e0, int lane, T* sp) {
+template <typename T, int J, int NT = 64>
+__device__ __forceinline__ void stage_block(const EnvDev<T>& E, int e0, int tid, T* sp) {
   if constexpr (sizeof(T) != 4) {
-    stage_chain<T, J>(E, e0 + lane, e0 + lane < E.N ? J : 0, lane, sp);
+    static_assert(NT == 64, "FP64 staging runs one lane per env");
+    stage_chain<T, J>(E, e0 + tid, e0 + tid < E.N ? J : 0, tid, sp);
   } else {
     constexpr int rows = P_NSTAGE * J;
-    constexpr int kIter = (rows + 3) / 4;  // rows per lane group of 16
-    const int sub = lane >> 4, c = (lane & 15) * 4;
+    constexpr int kRows = NT / 16;                     // rows per pass
+    constexpr int kIter = (rows + kRows - 1) / kRows;  // passes
+    const int sub = tid >> 4, c = (tid & 15) * 4;
     const bool full = (E.N & 3) == 0 && e0 + 64 <= E.N;
     if (full) {
-      // every row whole: all of this lane's loads issued before any LDS
+      // every row whole: all of this thread's loads issued before any LDS
       // store (a fixed trip count the compiler unrolls)
       float4 v[kIter];
 #pragma unroll
       for (int k = 0; k < kIter; ++k) {
-        const int r = 4 * k + sub;
+        const int r = kRows * k + sub;
         const int f = r / J, j = r % J;
         v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (r < rows && j < E.J) v[k] = *reinterpret_cast<const float4*>(E.par + ((size_t)f * E.J + j) * E.N + e0 + c);
       }
 #pragma unroll
       for (int k = 0; k < kIter; ++k) {
-        const int r = 4 * k + sub;
+        const int r = kRows * k + sub;
         if (r < rows) *reinterpret_cast<float4*>(sp + r * 64 + c) = v[k];
       }
       return;
     }
-    for (int r = sub; r < rows; r += 4) {
+    for (int r = sub; r < rows; r += kRows) {
       const int f = r / J, j = r % J;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (j < E.J) {
@@ -203,9 +206,11 @@ __device__ __forceinline__ void load_state(const EnvDev<T>& E, int e, int n, T (
 template <typename T> __device__ __forceinline__ T clamp1(T a) { return a > T(1) ? T(1) : (a < T(-1) ? T(-1) : a); }
 
 // S substeps of the implicit-PD step with the action held (zero-order hold).
-template <typename T, int J, class PS>
+// TEAM: the solve is shared with the workgroup's helper waves (aba_lwa_team;
+// the helpers run physics_help meanwhile).
+template <typename T, int J, class PS, bool TEAM = false>
 __device__ __forceinline__ void physics(const EnvDev<T>& E, PS& ps, int n, const T (&act)[J], T (&q)[J],
-                                        T (&qd)[J]) {
+                                        T (&qd)[J], const TeamLds& team = TeamLds{}) {
   const T h = E.h;
   T qs[J], arm[J], tau[J], qdd[J];
   ps.fence();
@@ -232,7 +237,8 @@ __device__ __forceinline__ void physics(const EnvDev<T>& E, PS& ps, int n, const
         tau[j] = T(0);
       }
     }
-    aba_lwa<T, J>(ps, n, q, qd, tau, arm, E.g, qdd);
+    if constexpr (TEAM) aba_lwa_team<J>(ps, n, q, qd, tau, arm, E.g, qdd, team);
+    else aba_lwa<T, J>(ps, n, q, qd, tau, arm, E.g, qdd);
     ps.fence();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -250,6 +256,12 @@ __device__ __forceinline__ void physics(const EnvDev<T>& E, PS& ps, int n, const
       }
     }
   }
+}
+
+// A helper wave's side of a team physics() call: one team solve per substep.
+template <int J, class PS>
+__device__ __forceinline__ void physics_help(const EnvDev<float>& E, PS& ps, int n, const TeamLds& team) {
+  for (int s = 0; s < E.S; ++s) aba_team_help<J>(ps, n, team);
 }
 
 template <typename T>

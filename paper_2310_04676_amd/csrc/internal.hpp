@@ -11,6 +11,7 @@
 
 struct sg_ctx {
   int device = 0;
+  int n_cu = 256;  // compute units of the device
   int N = 0, J = 0, dtype = SG_F32, S = 1;
   bool uniform = false;    // every env has J joints and J is a kernel instantiation
   bool prismatic = false;  // some env has a prismatic joint
@@ -45,6 +46,8 @@ struct sg_ctx {
   // DOF-class tiling for uneven batches: slots sorted by n_dof, each class
   // padded to whole 64-slot tiles (slot_env = -1 for padding).
   int schedule = 0;               // SG_SCHED_*
+  int team = 0;                   // waves per 64-env block sharing the solve: 1, sgk::kTeam, or 0 (auto)
+  std::string tune_key;           // the autotuner's key for this context (device, N, chains, DOF mix, task)
   int n_tiles = 0;
   int* slot_env = nullptr;        // [n_tiles * 64]
   int* tile_dof = nullptr;        // [n_tiles]
@@ -95,6 +98,9 @@ int dof_bucket(int J);
 // Raise the dynamic-LDS limit of kernel fn to bytes (when above the 64 KB
 // default) on the current device, once per (device, kernel address).
 hipError_t lds_limit(const void* fn, size_t bytes);
+
+// Whether the padded step has a wave-team kernel for this context.
+bool step_team_available(const sg_ctx* c);
 
 // rng_add: how far the launch advances the device noise counter (sg_step: 1;
 // the autotuner's trial steps: 0).

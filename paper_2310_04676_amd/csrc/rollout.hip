@@ -17,8 +17,17 @@ constexpr size_t kLdsX = 256 * 16;
 constexpr size_t kLdsO = (size_t)kWave * kOut * 4;
 template <int J> constexpr size_t lds_par_bytes() { return (size_t)P_NSTAGE * J * kWave * 4; }
 template <int H3> constexpr size_t policy_lds_bytes() { return lds_w_bytes<H3>() + lds_bias_bytes<H3>() + kLdsX + kLdsO; }
-template <int J, int H3> constexpr size_t rollout_lds_bytes() { return policy_lds_bytes<H3>() + lds_par_bytes<J>(); }
-static_assert(rollout_lds_bytes<7, 64>() <= 160 * 1024, "the Table II network's rollout fits the LDS");
+// ... plus, with a wave team, the links the helper waves hand back (the
+// published state reuses the staged-input area, idle during the physics)
+template <int J, int H3, bool TEAM = false> constexpr size_t rollout_lds_bytes() {
+  return policy_lds_bytes<H3>() + lds_par_bytes<J>() + (TEAM ? team_lds_bytes(J) : 0);
+}
+constexpr size_t kLdsMax = 160 * 1024;
+static_assert(rollout_lds_bytes<7, 64>() <= kLdsMax, "the Table II network's rollout fits the LDS");
+static_assert(rollout_lds_bytes<7, 0, true>() <= kLdsMax, "the 7-joint team rollout fits the LDS");
+static_assert((size_t)team_state_slots(7) * 64 * 16 <= kLdsX, "the team state fits the staged-input area");
+// a wave team where its exchange fits next to the weight image
+template <int J, int H3> constexpr bool team_fits() { return J >= 4 && rollout_lds_bytes<J, H3, true>() <= kLdsMax; }
 
 struct RollArgs {
   EnvDev<float> E;
@@ -47,10 +56,14 @@ __device__ __forceinline__ void fill_weights(uint4* sw, float* sb, const uint4* 
 // wave 0's VGPRs (one env per lane). Every step the four waves run the
 // policy on the matrix cores, one 16-env tile each (they share the LDS
 // weight image; each wave alone on its SIMD), then wave 0 samples the
-// action, advances the physics and writes the step's rollout rows while
-// the other three wait at the next step's barrier.
+// action, advances the physics and writes the step's rollout rows. With
+// TEAM the other three waves share every substep's solve as a wave team
+// (aba_lwa_team); without it they wait at the next step's barrier.
+// Control flow around the barriers is uniform per wave: wave 0 runs the
+// physics for all of its lanes (lanes past N on zeros, storing nothing).
 constexpr int kRollWaves = 4;
-template <int J, int M, int H3, int ACT>
+static_assert(kRollWaves == kTeam, "the rollout's waves form one team");
+template <int J, int M, int H3, int ACT, bool TEAM>
 __global__ void __launch_bounds__(kWave * kRollWaves) k_rollout(RollArgs A) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr size_t kLdsW = lds_w_bytes<H3>(), kLdsBias = lds_bias_bytes<H3>();
@@ -66,6 +79,12 @@ __global__ void __launch_bounds__(kWave * kRollWaves) k_rollout(RollArgs A) {
   const int e = blockIdx.x * kWave + lane;
   const bool active = phys && e < E.N;
   const int n = M == M_UNI ? J : (active ? E.nd[e] : 0);
+  // the team: state published in the staged-input area, links after the
+  // link parameters; a helper's joint count is its lane's env's
+  const TeamLds team{reinterpret_cast<float4*>(s_x),
+                     reinterpret_cast<float4*>(lds + kLdsW + kLdsBias + kLdsX + kLdsO + lds_par_bytes<J>()), wave,
+                     lane};
+  const int n_help = M == M_UNI ? J : (e < E.N ? E.nd[e] : 0);
   const int Wd = 2 * E.J + 10;
   const size_t N = E.N;
   const uint64_t step0 = read_counter(E);
@@ -84,6 +103,8 @@ __global__ void __launch_bounds__(kWave * kRollWaves) k_rollout(RollArgs A) {
   }
 
   float q[J], qd[J], x[kXMax];
+#pragma unroll
+  for (int j = 0; j < J; ++j) { q[j] = 0.f; qd[j] = 0.f; }
   int prog = 0;
   if (active) {
     load_state<float, J>(E, e, n, q, qd);
@@ -107,26 +128,36 @@ __global__ void __launch_bounds__(kWave * kRollWaves) k_rollout(RollArgs A) {
     __syncthreads();
     if (!phys) {
       if (t == A.T) break;
+      if constexpr (TEAM) physics_help<J>(E, ps, n_help, team);
       continue;
     }
     float mu[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) mu[j] = s_o[lane * kOut + j];
     const float V = s_o[lane * kOut + E.J];
-    if (!active) continue;
-    A.val[(size_t)t * N + e] = V;
+    if (active) A.val[(size_t)t * N + e] = V;
     if (t == A.T) break;
-    float eps[J], a[J];
-    normals<J>(A.seed, (uint32_t)e, step0 + (uint64_t)t, n, eps);
-    float lp = lp_const;
+    float a[J];
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      a[j] = j < n ? mu[j] + sig[j] * eps[j] : 0.f;
-      lp -= 0.5f * eps[j] * eps[j];
-      if (j < E.J) A.act[((size_t)t * E.J + j) * N + e] = a[j];
+    for (int j = 0; j < J; ++j) a[j] = 0.f;
+    if (active) {
+      float eps[J];
+      normals<J>(A.seed, (uint32_t)e, step0 + (uint64_t)t, n, eps);
+      float lp = lp_const;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        a[j] = j < n ? mu[j] + sig[j] * eps[j] : 0.f;
+        lp -= 0.5f * eps[j] * eps[j];
+        if (j < E.J) A.act[((size_t)t * E.J + j) * N + e] = a[j];
+      }
+      A.logp[(size_t)t * N + e] = lp;
     }
-    A.logp[(size_t)t * N + e] = lp;
-    physics<float, J>(E, ps, n, a, q, qd);
+    if constexpr (TEAM) {
+      physics<float, J, LdsPar<float, J, M == M_PRI>, true>(E, ps, n, a, q, qd, team);
+    } else {
+      if (active) physics<float, J>(E, ps, n, a, q, qd);
+    }
+    if (!active) continue;
     float r, tip[3], g[3];
     const uint8_t d = post_step<float, J>(E, e, n, ps, q, qd, prog, &r, A.obs + (size_t)(t + 1) * Wd * N, tip, g,
                                           step0 + (uint64_t)t);
@@ -212,8 +243,11 @@ hipError_t launch_policy_forward(const sg_ctx* c, const float* x, int n, float* 
 
 template <int J, int M, int H3 = 0, int ACT = PACT_TANH>
 static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_bufs* b) {
-  const size_t lds = rollout_lds_bytes<J, H3>();
-  hipError_t e = lds_limit((const void*)k_rollout<J, M, H3, ACT>, lds);
+  constexpr bool kFits = team_fits<J, H3>();
+  const bool team = kFits && c->team != 1;  // the team or auto: one block per compute unit either way
+  const size_t lds = team ? rollout_lds_bytes<J, H3, kFits>() : rollout_lds_bytes<J, H3>();
+  const void* fn = team ? (const void*)k_rollout<J, M, H3, ACT, kFits> : (const void*)k_rollout<J, M, H3, ACT, false>;
+  hipError_t e = lds_limit(fn, lds);
   if (e != hipSuccess) return e;
   RollArgs A;
   A.E = env_view<float>(c);
@@ -224,7 +258,9 @@ static hipError_t rollout_j(sg_ctx* c, int T, const sg_rollout_bufs* b) {
   A.T = T;
   A.seed = c->seed;
   A.obs = b->obs; A.act = b->act; A.logp = b->logp; A.rew = b->rew; A.done = b->done; A.val = b->val;
-  k_rollout<J, M, H3, ACT><<<dim3((c->N + kWave - 1) / kWave), kWave * kRollWaves, lds, c->stream>>>(A);
+  const dim3 grid((c->N + kWave - 1) / kWave);
+  if (team) k_rollout<J, M, H3, ACT, kFits><<<grid, kWave * kRollWaves, lds, c->stream>>>(A);
+  else k_rollout<J, M, H3, ACT, false><<<grid, kWave * kRollWaves, lds, c->stream>>>(A);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_gae(c->stream, T, c->N, b->rew, b->val, b->done, b->gamma, b->lam, b->adv, b->ret);

@@ -90,6 +90,62 @@ __global__ void __launch_bounds__(kBlk) k_step(EnvDev<T> E, const T* __restrict_
   if (threadIdx.x == 0) advance_counter(E, step, reads);
 }
 
+// One control step with a wave team (FP32; kTeam waves per 64 contiguous
+// envs): the four waves stage the block's parameters together, wave 0 runs
+// the step with every substep's solve shared as in the fused rollout
+// (aba_lwa_team), the other waves run their side of each solve. Wave 0 runs
+// the physics for all of its lanes (lanes past N on zero parameters, storing
+// nothing), so every wave meets every barrier.
+__host__ __device__ constexpr size_t team_state_bytes(int J) { return (size_t)team_state_slots(J) * 64 * 16; }
+template <int J> constexpr size_t team_step_lds_bytes() {
+  return par_lds_bytes<float, J>() + team_state_bytes(J) + team_lds_bytes(J);
+}
+static_assert(team_step_lds_bytes<9>() <= 160 * 1024, "the 9-joint team step fits the LDS");
+
+template <int J, int M>
+__global__ void __launch_bounds__(kBlk * kTeam) k_step_team(EnvDev<float> E, const float* __restrict__ act,
+                                                            float* __restrict__ obs, float* __restrict__ rew,
+                                                            uint8_t* __restrict__ done) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* sp = reinterpret_cast<float*>(smem_raw);
+  const TeamLds team{reinterpret_cast<float4*>(smem_raw + par_lds_bytes<float, J>()),
+                     reinterpret_cast<float4*>(smem_raw + par_lds_bytes<float, J>() + team_state_bytes(J)),
+                     (int)(threadIdx.x >> 6), (int)(threadIdx.x & (kBlk - 1))};
+  const int e = blockIdx.x * kBlk + team.lane;
+  const bool active = e < E.N;
+  const int n = M == M_UNI ? J : (active ? E.nd[e] : 0);
+  // only the tracking task and re-randomised goals draw noise in the step
+  const bool reads = E.task == TASK_TRACK || E.rerand;
+  const uint64_t step = reads ? read_counter(E) : 0;
+  float q[J], qd[J], a[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) { q[j] = 0.f; qd[j] = 0.f; a[j] = 0.f; }
+  if (team.wave == 0 && active) {
+    // issued before the staging, overlapping it
+    load_state<float, J>(E, e, n, q, qd);
+#pragma unroll
+    for (int j = 0; j < J; ++j) a[j] = j < n ? act[(size_t)j * E.N + e] : 0.f;
+  }
+  stage_block<float, J, kBlk * kTeam>(E, (int)blockIdx.x * kBlk, threadIdx.x, sp);
+  __syncthreads();
+  LdsPar<float, J, M == M_PRI> ps{sp, team.lane};
+  if (team.wave == 0) {
+    physics<float, J, LdsPar<float, J, M == M_PRI>, true>(E, ps, n, a, q, qd, team);
+    if (active) {
+      int prog = E.prog[e];
+      float r;
+      const uint8_t d = post_step<float, J>(E, e, n, ps, q, qd, prog, &r, obs, nullptr, nullptr, step);
+      store_state<float, J>(E, e, n, q, qd, prog);
+      rew[e] = r;
+      done[e] = d;
+    }
+  } else {
+    physics_help<J>(E, ps, n, team);
+  }
+  // every wave read the counter before the staging barrier
+  if (threadIdx.x == 0) advance_counter(E, step, reads);
+}
+
 // Uneven batches: envs bucketed by DOF class into 64-slot tiles, so every
 // block is class-homogeneous and runs the class's specialised code (exact
 // joint count where instantiated, else the next size with per-joint guards).
@@ -279,6 +335,49 @@ static hipError_t tiles_t(const sg_ctx* c, const void* act, void* obs, void* rew
   }
 }
 
+template <int J, int M>
+static hipError_t step_team_j(const sg_ctx* c, const EnvDev<float>& E, const float* act, float* obs, float* rew,
+                              uint8_t* done) {
+  constexpr size_t lds = team_step_lds_bytes<J>();
+  hipError_t e = lds_limit((const void*)k_step_team<J, M>, lds);
+  if (e != hipSuccess) return e;
+  k_step_team<J, M><<<dim3((c->N + kBlk - 1) / kBlk), kBlk * kTeam, lds, c->stream>>>(E, act, obs, rew, done);
+  return hipGetLastError();
+}
+
+// The padded step with a wave team where the context asks for one and the
+// chains' bucket has a team kernel (4 to 9 joints); false leaves the
+// one-wave kernels.
+bool step_team_available(const sg_ctx* c) {
+  const int b = dof_bucket(c->J);
+  return c->dtype == SG_F32 && b >= 4 && b <= 9;
+}
+
+// Auto (team 0): the team while every block is resident at once (two team
+// blocks fit a compute unit's LDS; one-wave blocks fit four, so beyond that
+// the one-wave kernel needs fewer rounds of blocks).
+static bool step_team(const sg_ctx* c, const EnvDev<float>& E, const float* act, float* obs, float* rew,
+                      uint8_t* done, hipError_t* err) {
+  const int blocks = (c->N + kBlk - 1) / kBlk;
+  const bool want = c->team == kTeam || (c->team == 0 && blocks <= 2 * c->n_cu);
+  if (!want || c->schedule != SG_SCHED_PADDED || !step_team_available(c)) return false;
+  const int b = dof_bucket(c->J);
+  if (c->prismatic) {
+    *err = b == 4 ? step_team_j<4, M_PRI>(c, E, act, obs, rew, done)
+                  : (b == 7 ? step_team_j<7, M_PRI>(c, E, act, obs, rew, done)
+                            : step_team_j<9, M_PRI>(c, E, act, obs, rew, done));
+  } else if (c->uniform) {
+    *err = b == 4 ? step_team_j<4, M_UNI>(c, E, act, obs, rew, done)
+                  : (b == 7 ? step_team_j<7, M_UNI>(c, E, act, obs, rew, done)
+                            : step_team_j<9, M_UNI>(c, E, act, obs, rew, done));
+  } else {
+    *err = b == 4 ? step_team_j<4, M_GEN>(c, E, act, obs, rew, done)
+                  : (b == 7 ? step_team_j<7, M_GEN>(c, E, act, obs, rew, done)
+                            : step_team_j<9, M_GEN>(c, E, act, obs, rew, done));
+  }
+  return true;
+}
+
 // One control step under the context's schedule; the launch that runs last
 // advances the noise counter by add.
 template <typename T>
@@ -301,6 +400,10 @@ static hipError_t step_t(const sg_ctx* c, const void* act, void* obs, void* rew,
   }
   EnvDev<T> E = env_view<T>(c);
   E.rng_add = (uint32_t)add;
+  if constexpr (sizeof(T) == sizeof(float)) {
+    hipError_t e = hipSuccess;
+    if (step_team(c, E, (const float*)act, (float*)obs, (float*)rew, done, &e)) return e;
+  }
   SG_DISPATCH(k_step, T, E, (const T*)act, (T*)obs, (T*)rew, done);
 }
 

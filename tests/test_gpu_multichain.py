@@ -17,13 +17,14 @@ def host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("C", [2, 4])
-def test_step_handoff(sg, C):
+@pytest.mark.parametrize("C,team", [(2, 1), (4, 1), (2, 4), (4, 4)])
+def test_step_handoff(sg, C, team):
     import torch
     n_env = 160 // C * 2 + 1   # a partial last wave
     w = synth.multi_arm(n_env, C)
     N = n_env * C
     sim = sg.Sim(w.robot, w.task)
+    sim.set_team(team)
     o = oracle.Oracle(w.robot, w.task)
     ended = 0
     for s in range(15):
@@ -61,13 +62,15 @@ def test_non_finite_chain_resets_its_env(sg):
     np.testing.assert_array_equal(q1[:, 4:6], w.robot.q0[:, 4:6].astype(np.float32))
 
 
-def test_rollout_replay(sg):
+@pytest.mark.parametrize("team", [1, 4])
+def test_rollout_replay(sg, team):
     from test_gpu_rollout import check_policy_outputs
     n_env, C, T = 100, 2, 12
     w = synth.multi_arm(n_env, C)
     w.task.progress0[:40] = 122
     N = n_env * C
     sim = sg.from_workload(w)
+    sim.set_team(team)
     o = oracle.Oracle(w.robot, w.task, w.policy)
     b = sim.rollout(T)
     obs, act, rew = host(b["obs"]), host(b["act"]), host(b["rew"])

@@ -53,8 +53,9 @@ def test_step_handoff_fp64(sg):
     _run_handoff(sg, synth.psm_like(64, dtype=np.float64), 40, 4100, qtol=1e-11, tol_qdd=1e-10)
 
 
-def test_step_handoff_fp32(sg):
-    _run_handoff(sg, synth.psm_like(300), 30, 4200, qtol=2e-5, tol_qdd=1e-4)
+@pytest.mark.parametrize("team", [1, 4])
+def test_step_handoff_fp32(sg, team):
+    _run_handoff(sg, synth.psm_like(300), 30, 4200, qtol=2e-5, tol_qdd=1e-4, team=team)
 
 
 def test_prismatic_contexts_keep_padded_schedule_and_refuse_surrogate(sg):
@@ -67,11 +68,13 @@ def test_prismatic_contexts_keep_padded_schedule_and_refuse_surrogate(sg):
         sg.Surrogate(sim, 256)
 
 
-def test_rollout_replay(sg):
+@pytest.mark.parametrize("team", [1, 4])
+def test_rollout_replay(sg, team):
     from test_gpu_rollout import check_policy_outputs
     w = synth.psm_like(200)
     w.policy = synth.make_policy(77, dims=(22, 256, 128, 7))
     sim = sg.from_workload(w)
+    sim.set_team(team)
     o = oracle.Oracle(w.robot, w.task, w.policy)
     N, J, T = w.robot.n_env, w.robot.max_dof, 12
     sigma = np.exp(w.policy.log_std)

@@ -18,13 +18,14 @@ def host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("kind", ["reach", "path"])
-def test_step_handoff_with_redrawn_goals(sg, kind):
+@pytest.mark.parametrize("kind,team", [("reach", 1), ("path", 1), ("reach", 4), ("path", 4)])
+def test_step_handoff_with_redrawn_goals(sg, kind, team):
     import torch
     N = 300
     w = synth.reach_rerand(N) if kind == "reach" else synth.path_rerand(N)
     w.task.progress0[:60] = 122  # a fifth of the envs start a new episode inside the run
     sim = sg.Sim(w.robot, w.task, seed=w.seed)
+    sim.set_team(team)
     o = oracle.Oracle(w.robot, w.task)
     resets = 0
     for s in range(12):
@@ -55,13 +56,15 @@ def test_step_handoff_with_redrawn_goals(sg, kind):
         assert not np.allclose(g[:, :60], w.task.target[:, :60])
 
 
-@pytest.mark.parametrize("kind,N", [("reach", 200), ("path", 200), ("path", 1024)])
-def test_rollout_replay_across_resets(sg, kind, N):
+@pytest.mark.parametrize("kind,N,team", [("reach", 200, 1), ("path", 200, 1), ("path", 1024, 1), ("reach", 200, 4),
+                                         ("path", 1024, 4)])
+def test_rollout_replay_across_resets(sg, kind, N, team):
     from test_gpu_rollout import check_policy_outputs
     T = 16
     w = synth.reach_rerand(N) if kind == "reach" else synth.path_rerand(N)
     w.task.progress0[: N // 5] = 120
     sim = sg.from_workload(w)
+    sim.set_team(team)
     o = oracle.Oracle(w.robot, w.task, w.policy)
     gs = np.ascontiguousarray(host(sim.get_goal_state()))
     b = sim.rollout(T)

@@ -80,9 +80,10 @@ def test_policy_forward_matches_oracle(sg, n):
     assert np.abs(out - ex).max() < 0.05
 
 
-def _replay_rollout(sg, w, T, n_rollouts=1):
+def _replay_rollout(sg, w, T, n_rollouts=1, team=1):
     import torch
     sim = sg.from_workload(w)
+    sim.set_team(team)
     o = oracle.Oracle(w.robot, w.task, w.policy)
     N, J, W = w.robot.n_env, w.robot.max_dof, 2 * w.robot.max_dof + 10
     sigma = np.exp(w.policy.log_std)

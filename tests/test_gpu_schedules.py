@@ -65,13 +65,35 @@ def test_autotune_restores_state_and_picks_a_schedule(sg):
     sim = sg.Sim(w.robot, w.task)
     q0, qd0, pr0, _ = sim.get_state()
     a = torch.rand(9, 4096, device="cuda") * 2 - 1
-    best, ms = sim.autotune_step(a, trials=3)
-    assert best in (0, 1, 2, 3) and set(ms) == {"padded", "sorted", "per_class", "persistent"}
-    assert ms[sg.SCHEDULE_NAMES[best]] == min(ms.values())
+    best, team, ms = sim.autotune_step(a, trials=3)
+    assert best in (0, 1, 2, 3) and team in (1, 4)
+    assert set(ms) == {"padded", "sorted", "per_class", "persistent", "padded_team"}
+    chosen = "padded_team" if team == 4 else sg.SCHEDULE_NAMES[best]
+    assert team == 1 or best == sg.SG_SCHED_PADDED
+    assert ms[chosen] == min(ms.values())
     q1, qd1, pr1, _ = sim.get_state()
     assert np.array_equal(host(q0), host(q1)) and np.array_equal(host(qd0), host(qd1))
     assert np.array_equal(pr0.cpu().numpy(), pr1.cpu().numpy())
-    assert sim.get_schedule() == best
+    assert sim.get_schedule() == best and sim.get_team() == team
+    # the choice is remembered: a new context of the same mix starts from it,
+    # and it survives an export / import round trip
+    sim2 = sg.Sim(w.robot, w.task)
+    assert (sim2.get_schedule(), sim2.get_team()) == (best, team)
+    text = sg.tuning_export()
+    line = [l for l in text.splitlines() if "|n=4096|f32|j=9|" in l]
+    assert len(line) == 1 and line[0].split()[1:] == [str(best), str(team)], text
+    key = line[0].split()[0]
+    other = 1 if best != 1 else 0
+    sg.tuning_import(f"{key} {other} 1\n")
+    sim3 = sg.Sim(w.robot, w.task)
+    assert (sim3.get_schedule(), sim3.get_team()) == (other, 1)
+    sg.tuning_import(f"{key} {best} {team}\n")
+    with pytest.raises(sg.SgError):
+        sg.tuning_import("key-without-values\n")
+    with pytest.raises(sg.SgError):
+        sg.tuning_import(f"{key} 7 1\n")
+    for s_ in (sim, sim2, sim3):
+        s_.close()
     # FP64 contexts keep the padded schedule
     w64 = synth.reach_fp64(64)
     s64 = sg.Sim(w64.robot, w64.task, dtype=np.float64)

@@ -77,10 +77,11 @@ def test_forward_inverse_dynamics_and_tip(sg, name, n_env):
     sim.synchronize()
 
 
-def _run_handoff(sg, w, steps, act_seed, qtol, tol_qdd):
+def _run_handoff(sg, w, steps, act_seed, qtol, tol_qdd, team=1):
     import torch
     td = torch.float64 if w.dtype == np.float64 else torch.float32
     sim = sg.Sim(w.robot, w.task, dtype=w.dtype)
+    sim.set_team(team)
     o = oracle.Oracle(w.robot, w.task)
     J, N = w.robot.max_dof, w.robot.n_env
     worst = 0.0

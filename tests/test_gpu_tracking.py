@@ -16,12 +16,14 @@ def host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-def test_step_handoff_with_goal_state(sg):
+@pytest.mark.parametrize("team", [1, 4])
+def test_step_handoff_with_goal_state(sg, team):
     import torch
     N = 300
     w = synth.tracking(N)
     w.task.progress0[:60] = 122  # a fifth of the envs start a new episode inside the run
     sim = sg.Sim(w.robot, w.task, seed=w.seed)
+    sim.set_team(team)
     o = oracle.Oracle(w.robot, w.task)
     resets = 0
     for s in range(12):
@@ -44,12 +46,14 @@ def test_step_handoff_with_goal_state(sg):
     assert resets >= 60
 
 
-def test_rollout_replay_with_moving_goal(sg):
+@pytest.mark.parametrize("team", [1, 4])
+def test_rollout_replay_with_moving_goal(sg, team):
     from test_gpu_rollout import check_policy_outputs
     N, T = 200, 16
     w = synth.tracking(N)
     w.task.progress0[:40] = 120
     sim = sg.from_workload(w)
+    sim.set_team(team)
     o = oracle.Oracle(w.robot, w.task, w.policy)
     gs = np.ascontiguousarray(host(sim.get_goal_state()))
     b = sim.rollout(T)
