@@ -204,6 +204,7 @@ __global__ void __launch_bounds__(64) k_pack(const uint16_t* __restrict__ W0, co
 // later layer takes the previous layer's D tiles straight from registers.
 struct InferWeights {
   const uint4* img;    // fragment image
+  const uint4* ch;     // the same fragments in infer_block's chunk order
   const float* b[4];   // biases [out]
   const float* norm;   // mu_x sd_x mu_y sd_y
 };
@@ -393,22 +394,240 @@ __device__ __forceinline__ void integrate(const EnvDev<float>& E, const RegPar<f
   }
 }
 
+// ---------------------------------------------------------------------------
+// Inference with the weights shared through LDS: the kSW waves of one
+// workgroup (64 samples each) run infer_wave's sequence of MFMAs on the same
+// weight fragments, which the workgroup copies chunk by chunk from the image
+// into a double-buffered LDS area (the next chunk's loads in flight while the
+// current one is multiplied), so each fragment leaves L2 once per workgroup
+// and half instead of once per wave and half. Chunk c of phase A (layers 0
+// and 1, c = infer_wave's kb2): W0's fragments of M-tiles 2c and 2c+1 (3
+// K-blocks each), then W1's fragments (m, c) of the 16 M-tiles; chunk c of
+// phase B (layers 2 and 3, c = kb3): W2's fragments of M-tiles 2c and 2c+1
+// (8 K-blocks each), then W3's fragment c. Every MFMA takes the operands of
+// infer_wave in the same order: the same results.
+constexpr int kSW = 4;
+constexpr int kChunkA = (2 * 3 + 16) * 64;  // fragments (uint4 per lane)
+constexpr int kChunkB = (2 * 8 + 1) * 64;
+constexpr int kChunkIt = (kChunkA + kSW * 64 - 1) / (kSW * 64);  // loads per thread
+constexpr int kChunks = 2 * 2 * 8;  // halves x phases x chunks
+static_assert(kChunkB <= kChunkA, "phase B chunks fit the buffer");
+
+__device__ __forceinline__ const uint4* chunk_src(const uint4* img, int phase, int c, int i) {
+  if (phase == 0) {
+    if (i < 6 * 64) {
+      const int h = i / 192, r = i % 192;
+      return img + s_frag_off(0) + ((2 * c + h) * 3 + r / 64) * 64 + r % 64;
+    }
+    const int r = i - 6 * 64;
+    return img + s_frag_off(1) + ((r / 64) * 8 + c) * 64 + r % 64;
+  }
+  if (i < 16 * 64) {
+    const int h = i / 512, r = i % 512;
+    return img + s_frag_off(2) + ((2 * c + h) * 8 + r / 64) * 64 + r % 64;
+  }
+  return img + s_frag_off(3) + c * 64 + (i - 16 * 64);
+}
+
+// The chunk-ordered copy of the image: the 8 phase-A chunks, then the 8
+// phase-B chunks, each contiguous (a permutation of the image's fragments).
+__host__ __device__ constexpr int chunk_base(int qc) { return qc < 8 ? qc * kChunkA : 8 * kChunkA + (qc - 8) * kChunkB; }
+static_assert(chunk_base(16) == kSFrags, "the chunk order is a permutation of the image");
+
+__global__ void __launch_bounds__(256) k_pack_chunks(const uint4* __restrict__ img, uint4* __restrict__ ch) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= kSFrags) return;
+  const int ph = t < 8 * kChunkA ? 0 : 1;
+  const int r = ph == 0 ? t : t - 8 * kChunkA, n = ph == 0 ? kChunkA : kChunkB;
+  ch[t] = *chunk_src(img, ph, r / n, r % n);
+}
+
+// chunk q of the sequence: half q / 16, phase (q / 8) % 2, chunk q % 8
+__device__ __forceinline__ void chunk_load(const uint4* ch, int q, int tid, uint4 (&r)[kChunkIt]) {
+  const int qc = q & 15, n = qc < 8 ? kChunkA : kChunkB;
+  const uint4* src = ch + chunk_base(qc);
+#pragma unroll
+  for (int k = 0; k < kChunkIt; ++k) {
+    const int i = tid + k * kSW * 64;
+    r[k] = i < n ? src[i] : make_uint4(0u, 0u, 0u, 0u);
+  }
+}
+__device__ __forceinline__ void chunk_store(uint4* buf, int q, int tid, const uint4 (&r)[kChunkIt]) {
+  const int n = ((q >> 3) & 1) == 0 ? kChunkA : kChunkB;
+#pragma unroll
+  for (int k = 0; k < kChunkIt; ++k) {
+    const int i = tid + k * kSW * 64;
+    if (i < n) buf[i] = r[k];
+  }
+}
+
+// The biases of the four layers in LDS (so the chunk loop waits on no
+// global load but the next chunk's): [256 | 256 | 256 | 16] floats.
+constexpr int kSBias = 3 * kSH + kSO;
+__device__ __forceinline__ void stage_biases(const InferWeights& w, float* sb, int tid) {
+  for (int i = tid; i < kSBias; i += kSW * 64) sb[i] = i < 3 * kSH ? w.b[i / kSH][i % kSH] : w.b[3][i - 3 * kSH];
+}
+__device__ __forceinline__ f32x4 lbias4(const float* sb, int row0) {
+  const float4 v = *reinterpret_cast<const float4*>(sb + row0);
+  return f32x4{v.x, v.y, v.z, v.w};
+}
+
+// wb: LDS [2][kChunkA] fragment buffers; sb: LDS biases (stage_biases,
+// ordered by this function's first barrier); xs: this wave's staged
+// features (stage layout of infer_wave); os: this wave's [64][16] outputs.
+// Every thread of the workgroup calls it (tid = 0 .. kSW*64-1).
+__device__ __forceinline__ void infer_block(const InferWeights& w, uint4* wb, const float* sb, const uint4* xs,
+                                            float* os, int lane, int tid) {
+  const int g = lane >> 4, j = lane & 15;
+  const float* sb0 = sb;
+  const float* sb1 = sb + kSH;
+  const float* sb2 = sb + 2 * kSH;
+  const float* sb3 = sb + 3 * kSH;
+  uint4 r[kChunkIt];
+  chunk_load(w.ch, 0, tid, r);
+  chunk_store(wb, 0, tid, r);
+  __syncthreads();
+  // one pipeline step: the next chunk's loads issued, this one multiplied,
+  // the next one stored, then the workgroup meets (the buffer just read is
+  // overwritten only after that barrier)
+  auto step = [&](int q, auto&& mul) __attribute__((always_inline)) {
+    const bool more = q + 1 < kChunks;
+    if (more) chunk_load(w.ch, q + 1, tid, r);
+    mul(wb + (q & 1) * kChunkA);
+    if (more) chunk_store(wb + ((q + 1) & 1) * kChunkA, q + 1, tid, r);
+    __syncthreads();
+  };
+#pragma unroll 1
+  for (int half = 0; half < 2; ++half) {
+    bf16x8 xb[2][3];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int kb = 0; kb < 3; ++kb) xb[t][kb] = ldfrag(xs + (((2 * half + t) * 3 + kb) * 4 + g) * 16 + j);
+    f32x4 acc2[16][2];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const f32x4 b = lbias4(sb1, 16 * m + 4 * g);
+      acc2[m][0] = b;
+      acc2[m][1] = b;
+    }
+#pragma unroll 1
+    for (int kb2 = 0; kb2 < 8; ++kb2) {
+      step(half * 16 + kb2, [&](const uint4* B) __attribute__((always_inline)) {
+        f32x4 d[2][2];
+        bf16x8 a0[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) a0[i] = ldfrag(B + i * 64 + lane);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const f32x4 b = lbias4(sb0, 16 * (2 * kb2 + h) + 4 * g);
+          d[h][0] = b;
+          d[h][1] = b;
+        }
+        // the first W1 fragments in flight while layer 0's tiles finish
+        bf16x8 a1[2] = {ldfrag(B + 6 * 64 + lane), ldfrag(B + 7 * 64 + lane)};
+#pragma unroll
+        for (int kb = 0; kb < 3; ++kb)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            d[h][0] = mfma16x16x32(a0[h * 3 + kb], xb[0][kb], d[h][0]);
+            d[h][1] = mfma16x16x32(a0[h * 3 + kb], xb[1][kb], d[h][1]);
+          }
+        const bf16x8 hb0 = pack_elu(d[0][0], d[1][0]), hb1 = pack_elu(d[0][1], d[1][1]);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          // two fragments ahead
+          const bf16x8 a = a1[m & 1];
+          if (m + 2 < 16) a1[m & 1] = ldfrag(B + (6 + m + 2) * 64 + lane);
+          acc2[m][0] = mfma16x16x32(a, hb0, acc2[m][0]);
+          acc2[m][1] = mfma16x16x32(a, hb1, acc2[m][1]);
+        }
+      });
+    }
+    bf16x8 h2[8][2];
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      h2[kb][0] = pack_elu(acc2[2 * kb][0], acc2[2 * kb + 1][0]);
+      h2[kb][1] = pack_elu(acc2[2 * kb][1], acc2[2 * kb + 1][1]);
+    }
+    f32x4 acc4[2];
+    acc4[0] = acc4[1] = lbias4(sb3, 4 * g);
+#pragma unroll 1
+    for (int kb3 = 0; kb3 < 8; ++kb3) {
+      step(half * 16 + 8 + kb3, [&](const uint4* B) __attribute__((always_inline)) {
+        f32x4 d[2][2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const f32x4 b = lbias4(sb2, 16 * (2 * kb3 + h) + 4 * g);
+          d[h][0] = b;
+          d[h][1] = b;
+        }
+        bf16x8 a2[2] = {ldfrag(B + 0 * 64 + lane), ldfrag(B + 1 * 64 + lane)};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          // fragment i = (h, kb) = (i / 8, i % 8), two ahead
+          const bf16x8 a = a2[i & 1];
+          if (i + 2 < 16) a2[i & 1] = ldfrag(B + (i + 2) * 64 + lane);
+          const int h = i >> 3, kb = i & 7;
+          d[h][0] = mfma16x16x32(a, h2[kb][0], d[h][0]);
+          d[h][1] = mfma16x16x32(a, h2[kb][1], d[h][1]);
+        }
+        const bf16x8 a = ldfrag(B + 16 * 64 + lane);
+        acc4[0] = mfma16x16x32(a, pack_elu(d[0][0], d[1][0]), acc4[0]);
+        acc4[1] = mfma16x16x32(a, pack_elu(d[0][1], d[1][1]), acc4[1]);
+      });
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int smp = 32 * half + 16 * t + j;
+      *reinterpret_cast<float4*>(os + smp * kSO + 4 * g) = make_float4(acc4[t][0], acc4[t][1], acc4[t][2], acc4[t][3]);
+    }
+  }
+}
+
+// Normalised feature f of this lane's sample into a wave's staged features
+// (infer_wave's layout), rounded to BF16 as stage_features does.
+__device__ __forceinline__ void put_feature(uint4* xs, int lane, int f, float v) {
+  const int kb = f >> 5, g = (f >> 3) & 3, s = f & 7, tile = lane >> 4, j = lane & 15;
+  const __bf16 b = (__bf16)v;
+  reinterpret_cast<uint16_t*>(xs + ((tile * 3 + kb) * 4 + g) * 16 + j)[s] = *reinterpret_cast<const uint16_t*>(&b);
+}
+
 // (a) integrate the previous substep (s > 0), then predict qdd for this
-// substep, check the residual, queue the envs that fail.
+// substep, check the residual, queue the envs that fail. A workgroup of kSW
+// waves holds kSW x 64 envs (one per lane) and shares the weights in LDS
+// (infer_block); features go straight into LDS.
+constexpr size_t kSStepXs = (size_t)kSW * 64 * 12 * 16;     // staged features
+constexpr size_t kSStepOs = (size_t)kSW * 64 * kSO * 4;     // outputs
+constexpr size_t kSStepWb = (size_t)2 * kChunkA * 16;       // weight chunks
+constexpr size_t kSStepLds = kSStepXs + kSStepOs + kSStepWb + kSBias * 4;
+static_assert(kSStepLds <= 160 * 1024, "the surrogate step's LDS fits");
 template <int J>
-__global__ void __launch_bounds__(64) k_sstep_a(SStepArgs A) {
-  __shared__ __align__(16) uint4 xs[64 * 12];
-  __shared__ __align__(16) float os[64 * kSO];
+__global__ void __launch_bounds__(kSW * 64) k_sstep_a(SStepArgs A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  uint4* xs = reinterpret_cast<uint4*>(smem_raw) + wave * 64 * 12;
+  float* os = reinterpret_cast<float*>(smem_raw + kSStepXs) + wave * 64 * kSO;
+  uint4* wb = reinterpret_cast<uint4*>(smem_raw + kSStepXs + kSStepOs);
+  float* sb = reinterpret_cast<float*>(smem_raw + kSStepXs + kSStepOs + kSStepWb);
+  stage_biases(A.w, sb, tid);
   const EnvDev<float>& E = A.E;
-  const int lane = threadIdx.x, e = blockIdx.x * 64 + lane;
+  const int e = blockIdx.x * (kSW * 64) + tid;
   const bool active = e < E.N;
   const int n = active ? E.nd[e] : 0;
-  RegPar<float, J> P;
   float q[J], qd[J], tau[J], arm[J];
-  float x[kSF];
+  {
+    // this lane's features: zeros, then the defined ones
+    const int tile = lane >> 4, j16 = lane & 15;
 #pragma unroll
-  for (int f = 0; f < kSF; ++f) x[f] = 0.f;
+    for (int kb = 0; kb < 3; ++kb)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) xs[((tile * 3 + kb) * 4 + g) * 16 + j16] = make_uint4(0u, 0u, 0u, 0u);
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) { q[j] = 0.f; qd[j] = 0.f; tau[j] = 0.f; arm[j] = 0.f; }
   if (active) {
+    RegPar<float, J> P;
     load_chain<float, J>(E, e, n, P);
     load_state<float, J>(E, e, n, q, qd);
     if (A.s > 0) {
@@ -417,27 +636,31 @@ __global__ void __launch_bounds__(64) k_sstep_a(SStepArgs A) {
     }
     drive_terms<J>(E, P, n, A.act, e, q, qd, tau, arm);
     const float* nm = A.w.norm;
+    const int JE = E.J;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       if (j < n) {
-        x[j] = (q[j] - nm[j]) / nm[kSF + j];
-        x[E.J + j] = (qd[j] - nm[E.J + j]) / nm[kSF + E.J + j];
-        x[2 * E.J + j] = (tau[j] - nm[2 * E.J + j]) / nm[kSF + 2 * E.J + j];
+        put_feature(xs, lane, j, (q[j] - nm[j]) / nm[kSF + j]);
+        put_feature(xs, lane, JE + j, (qd[j] - nm[JE + j]) / nm[kSF + JE + j]);
+        put_feature(xs, lane, 2 * JE + j, (tau[j] - nm[2 * JE + j]) / nm[kSF + 2 * JE + j]);
         const Jp<float>& pj = P.P[j];
         const float p[10] = {pj.m, pj.hx, pj.hy, pj.hz, pj.ixx, pj.iyy, pj.izz, pj.ixy, pj.ixz, pj.iyz};
 #pragma unroll
         for (int k = 0; k < 10; ++k) {
-          const int f = 3 * E.J + 10 * j + k;
-          x[f] = (p[k] - nm[f]) / nm[kSF + f];
+          const int f = 3 * JE + 10 * j + k;
+          put_feature(xs, lane, f, (p[k] - nm[f]) / nm[kSF + f]);
         }
       }
     }
   }
-  stage_features(xs, lane, x);
-  __syncthreads();
-  infer_wave(A.w, xs, os, lane);
-  __syncthreads();
+  infer_block(A.w, wb, sb, xs, os, lane, tid);  // barriers inside; the first orders features and biases
   if (!active) return;
+  // the link parameters again for the residual (not held across the
+  // inference: its accumulators need the registers)
+  EnvDev<float> E2 = E;
+  asm volatile("" : "+s"(E2.par));
+  RegPar<float, J> P;
+  load_chain<float, J>(E2, e, n, P);
   const float* nm = A.w.norm;
   float qh[J], id[J];
 #pragma unroll
@@ -529,6 +752,7 @@ struct sg_surrogate {
   float* vb[kSL] = {};
   uint16_t* Wb[kSL] = {};  // BF16 copies [out][in]
   uint16_t* img = nullptr; // inference fragment image
+  uint16_t* img_ch = nullptr;  // the same in the surrogate step's chunk order
   float* norm = nullptr;   // mu_x[96] sd_x[96] mu_y[16] sd_y[16]
   // training scratch
   uint16_t* X[kSL] = {};   // layer inputs [B][in] bf16
@@ -567,6 +791,7 @@ sg_status sfail(sg_ctx* c, sg_status st, const char* msg) {
 InferWeights infer_weights(const sg_surrogate* s) {
   InferWeights w;
   w.img = reinterpret_cast<const uint4*>(s->img);
+  w.ch = reinterpret_cast<const uint4*>(s->img_ch);
   for (int l = 0; l < kSL; ++l) w.b[l] = s->bm[l];
   w.norm = s->norm;
   return w;
@@ -685,6 +910,7 @@ sg_status sg_surrogate_create(sg_ctx* c, int32_t max_batch, sg_surrogate** out) 
     if (e == hipSuccess) e = dalloc(s, &s->Z[l], B * s_out(l));
   }
   if (e == hipSuccess) e = dalloc(s, &s->img, (size_t)kSFrags * 8);
+  if (e == hipSuccess) e = dalloc(s, &s->img_ch, (size_t)kSFrags * 8);
   if (e == hipSuccess) e = dalloc(s, &s->norm, 2 * kSF + 2 * kSO);
   if (e == hipSuccess) e = dalloc(s, &s->Gb, B * kSH);
   if (e == hipSuccess) e = dalloc(s, &s->Gb2, B * kSH);
@@ -896,14 +1122,28 @@ sg_status sg_surrogate_step(sg_surrogate* s, const float* actions, float* obs, f
   A.count = s->count;
   A.list = s->list;
   A.thresh = thresh;
-  const dim3 gw((c->N + 63) / 64), gb((c->N + 255) / 256);
+  const dim3 gw((c->N + kSW * 64 - 1) / (kSW * 64)), gb((c->N + 255) / 256);
   const int b = dof_bucket(c->J);
+  {
+    const void* fa = b <= 1 ? (const void*)k_sstep_a<1> : b <= 2 ? (const void*)k_sstep_a<2>
+                   : b <= 4 ? (const void*)k_sstep_a<4> : (const void*)k_sstep_a<7>;
+    hipError_t e = lds_limit(fa, kSStepLds);
+    if (e != hipSuccess) {
+      c->err = std::string("sg_surrogate_step: ") + hipGetErrorString(e);
+      return SG_E_HIP;
+    }
+  }
+  const size_t la = kSStepLds;
+  // the chunk-ordered image of the current weights (320 KB, every call, so
+  // a captured step follows later training)
+  k_pack_chunks<<<(kSFrags + 255) / 256, 256, 0, c->stream>>>(reinterpret_cast<const uint4*>(s->img),
+                                                             reinterpret_cast<uint4*>(s->img_ch));
   for (int st = 0; st < c->S; ++st) {
     A.s = st;
-    if (b <= 1) { k_sstep_a<1><<<gw, 64, 0, c->stream>>>(A); k_sstep_b<1><<<gb, 256, 0, c->stream>>>(A); }
-    else if (b <= 2) { k_sstep_a<2><<<gw, 64, 0, c->stream>>>(A); k_sstep_b<2><<<gb, 256, 0, c->stream>>>(A); }
-    else if (b <= 4) { k_sstep_a<4><<<gw, 64, 0, c->stream>>>(A); k_sstep_b<4><<<gb, 256, 0, c->stream>>>(A); }
-    else { k_sstep_a<7><<<gw, 64, 0, c->stream>>>(A); k_sstep_b<7><<<gb, 256, 0, c->stream>>>(A); }
+    if (b <= 1) { k_sstep_a<1><<<gw, kSW * 64, la, c->stream>>>(A); k_sstep_b<1><<<gb, 256, 0, c->stream>>>(A); }
+    else if (b <= 2) { k_sstep_a<2><<<gw, kSW * 64, la, c->stream>>>(A); k_sstep_b<2><<<gb, 256, 0, c->stream>>>(A); }
+    else if (b <= 4) { k_sstep_a<4><<<gw, kSW * 64, la, c->stream>>>(A); k_sstep_b<4><<<gb, 256, 0, c->stream>>>(A); }
+    else { k_sstep_a<7><<<gw, kSW * 64, la, c->stream>>>(A); k_sstep_b<7><<<gb, 256, 0, c->stream>>>(A); }
   }
   A.E.rng_add = 1;  // the control step's last kernel advances the noise counter
   if (b <= 1) k_sstep_f<1><<<gb, 256, 0, c->stream>>>(A, obs, reward, done, n_fallback);
