@@ -54,3 +54,32 @@ def test_create_rejects_bad_descriptions_without_gpu_work():
     # calls on a null context fail cleanly
     assert sg.lib.sg_step(None, None, None, None, None) == sg.SG_E_INVAL
     assert sg.lib.sg_rollout(None, 1, None) == sg.SG_E_INVAL
+
+
+def test_tuning_text_round_trip_and_errors_without_gpu():
+    """The autotuner's remembered choices as text (host code only): lines
+    merge, later lines win, export lists every key once, malformed lines and
+    out-of-range values are rejected, a short buffer is truncated with its
+    full length reported."""
+    import paper_2310_04676_amd as sg
+    # env counts no test creates, so no later context in this process matches
+    key_a = "gfx950|n=100003|f32|j=7|pr=0|c=1|task=1|dof=7x100003"
+    key_b = "gfx950|n=100019|f32|j=9|pr=0|c=1|task=0|dof=4x50000,9x50019"
+    sg.tuning_import(f"{key_a} 1 1\n{key_b} 0 4\n\n{key_a} 3 1\n")
+    lines = {l.split()[0]: l.split()[1:] for l in sg.tuning_export().splitlines()}
+    assert lines[key_a] == ["3", "1"] and lines[key_b] == ["0", "4"]
+    for bad in ("lonely-key\n", f"{key_a} 4 1\n", f"{key_a} 0 2\n", f"{key_a} 0 1 extra\n", f"{key_a} x 1\n"):
+        with pytest.raises(sg.SgError):
+            sg.tuning_import(bad)
+    # lines before a malformed one stay merged
+    with pytest.raises(sg.SgError):
+        sg.tuning_import(f"{key_b} 2 1\nbroken\n")
+    assert {l.split()[0]: l.split()[1:] for l in sg.tuning_export().splitlines()}[key_b] == ["2", "1"]
+    n = C.c_size_t()
+    assert sg.lib.sg_tuning_export(None, 0, C.byref(n)) == sg.SG_OK
+    full = n.value
+    buf = C.create_string_buffer(8)
+    assert sg.lib.sg_tuning_export(buf, 8, C.byref(n)) == sg.SG_OK
+    assert n.value == full and len(buf.value) == 7
+    assert sg.lib.sg_tuning_export(None, 8, C.byref(n)) == sg.SG_E_INVAL
+    assert sg.lib.sg_tuning_import(None) == sg.SG_E_INVAL
