@@ -161,6 +161,17 @@ def test_team_step_matches_one_wave_step_at_16384(sg):
     assert np.abs(r1 - r4).max() <= 4e-4
 
 
+@pytest.mark.parametrize("n_env", [1, 63, 65, 301])
+def test_team_small_and_ragged_sizes(sg, n_env):
+    """Sizes that exercise the staging's partial paths (N not a multiple of
+    4, a partial last block, a single env): the team step and a short team
+    rollout from the oracle's state, each checked against the oracle."""
+    from test_gpu_step import _run_handoff
+    w = synth.path_rollout(n_env)
+    _run_handoff(sg, w, 6, 5400 + n_env, qtol=2e-5, tol_qdd=1e-4, team=4)
+    _replay_rollout(sg, synth.path_rollout(n_env), 6, team=4)
+
+
 def test_team_argument_checks(sg):
     w = synth.path_rollout(64)
     sim = sg.from_workload(w)
