@@ -258,10 +258,20 @@ __device__ __forceinline__ void physics(const EnvDev<T>& E, PS& ps, int n, const
   }
 }
 
-// A helper wave's side of a team physics() call: one team solve per substep.
+// A helper wave's side of a team physics() call: one team solve per substep;
+// after_first() runs once the first substep's links are handed back, while
+// wave 0 runs that substep's inward and outward passes.
+template <int J, class PS, class F>
+__device__ __forceinline__ void physics_help(const EnvDev<float>& E, PS& ps, int n, const TeamLds& team,
+                                             F&& after_first) {
+  for (int s = 0; s < E.S; ++s) {
+    aba_team_help<J>(ps, n, team);
+    if (s == 0) after_first();
+  }
+}
 template <int J, class PS>
 __device__ __forceinline__ void physics_help(const EnvDev<float>& E, PS& ps, int n, const TeamLds& team) {
-  for (int s = 0; s < E.S; ++s) aba_team_help<J>(ps, n, team);
+  physics_help<J>(E, ps, n, team, [] {});
 }
 
 template <typename T>

@@ -18,9 +18,13 @@ constexpr size_t kLdsO = (size_t)kWave * kOut * 4;
 template <int J> constexpr size_t lds_par_bytes() { return (size_t)P_NSTAGE * J * kWave * 4; }
 template <int H3> constexpr size_t policy_lds_bytes() { return lds_w_bytes<H3>() + lds_bias_bytes<H3>() + kLdsX + kLdsO; }
 // ... plus, with a wave team, the links the helper waves hand back (the
-// published state reuses the staged-input area, idle during the physics)
+// published state reuses the staged-input area, idle during the physics),
+// plus the exploration noise the helper waves draw one step ahead: two
+// step-parity slots of one float4 per Philox block and lane
+constexpr int kNoiseBlocks = 2;  // Philox blocks of four normals: chains of up to 7 joints
+constexpr size_t kLdsEps = (size_t)2 * kNoiseBlocks * kWave * 16;
 template <int J, int H3, bool TEAM = false> constexpr size_t rollout_lds_bytes() {
-  return policy_lds_bytes<H3>() + lds_par_bytes<J>() + (TEAM ? team_lds_bytes(J) : 0);
+  return policy_lds_bytes<H3>() + lds_par_bytes<J>() + (TEAM ? team_lds_bytes(J) : 0) + kLdsEps;
 }
 constexpr size_t kLdsMax = 160 * 1024;
 static_assert(rollout_lds_bytes<7, 64>() <= kLdsMax, "the Table II network's rollout fits the LDS");
@@ -88,9 +92,22 @@ __global__ void __launch_bounds__(kWave * kRollWaves) k_rollout(RollArgs A) {
   const int Wd = 2 * E.J + 10;
   const size_t N = E.N;
   const uint64_t step0 = read_counter(E);
+  // the noise slots: [2 step parities][noise block][64 lanes]; helper wave w
+  // (1 .. blocks) draws block w-1 of the next step's normals
+  float4* s_eps = reinterpret_cast<float4*>(lds + rollout_lds_bytes<J, H3, TEAM>() - kLdsEps);
+  constexpr int kNb = (J + 3) / 4;
+  static_assert(kNb <= kNoiseBlocks && kNb < kRollWaves, "one helper wave per noise block");
+  auto draw = [&](int t) __attribute__((always_inline)) {
+    if (wave >= 1 && wave <= kNb) {
+      float v[4];
+      normals4(A.seed, (uint32_t)e, step0 + (uint64_t)t, (uint32_t)(wave - 1), v);
+      s_eps[((t & 1) * kNoiseBlocks + wave - 1) * kWave + lane] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  };
 
   fill_weights<H3>(s_w, s_b, A.wimg, A.bias, threadIdx.x, kWave * kRollWaves);
   if (phys) stage_chain<float, J>(E, e, active ? n : 0, lane, s_p);
+  draw(0);
   __syncthreads();
   LdsPar<float, J, M == M_PRI> ps{s_p, lane};
   float lstd[J], sig[J];
@@ -128,7 +145,10 @@ __global__ void __launch_bounds__(kWave * kRollWaves) k_rollout(RollArgs A) {
     __syncthreads();
     if (!phys) {
       if (t == A.T) break;
-      if constexpr (TEAM) physics_help<J>(E, ps, n_help, team);
+      // the next step's noise: with a team once the first substep's links
+      // are handed back (wave 0 is in that substep's inward pass), else now
+      if constexpr (TEAM) physics_help<J>(E, ps, n_help, team, [&] { draw(t + 1); });
+      else draw(t + 1);
       continue;
     }
     float mu[J];
@@ -141,8 +161,17 @@ __global__ void __launch_bounds__(kWave * kRollWaves) k_rollout(RollArgs A) {
 #pragma unroll
     for (int j = 0; j < J; ++j) a[j] = 0.f;
     if (active) {
+      // this step's normals, drawn by the helper waves (the same values as
+      // normals(): block b holds joints 4b .. 4b+3; joints >= n take 0)
       float eps[J];
-      normals<J>(A.seed, (uint32_t)e, step0 + (uint64_t)t, n, eps);
+#pragma unroll
+      for (int b = 0; b < kNb; ++b) {
+        const float4 v = s_eps[((t & 1) * kNoiseBlocks + b) * kWave + lane];
+        const float w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (4 * b + k < J) eps[4 * b + k] = 4 * b + k < n ? w4[k] : 0.f;
+      }
       float lp = lp_const;
 #pragma unroll
       for (int j = 0; j < J; ++j) {
