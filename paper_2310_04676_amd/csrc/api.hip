@@ -39,7 +39,7 @@ template <typename T> hipError_t upload(void** dst, const std::vector<double>& s
 }
 
 void free_ctx(sg_ctx* c) {
-  void* ptrs[] = {c->par, c->tip, c->nd, c->target, c->wp, c->prog0, c->q, c->qd, c->prog, c->w_bf16, c->bias,
+  void* ptrs[] = {c->par, c->tip, c->tip0, c->nd, c->target, c->wp, c->prog0, c->q, c->qd, c->prog, c->w_bf16, c->bias,
                   c->log_std, c->slot_env, c->tile_dof, c->adj_ws, c->gs, c->gs0, c->rng_dev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -307,6 +307,10 @@ sg_status sg_create(const sg_robot_desc* r, const sg_task_desc* t, sg_ctx** out)
   if (e == hipSuccess) e = hipMalloc(&c->qd, JN * esz);
   if (e == hipSuccess) e = hipMemset(c->q, 0, JN * esz);
   if (e == hipSuccess) e = hipMemset(c->qd, 0, JN * esz);
+  // the tool tip at q0 (the pose a reset returns to), for the step's resets
+  if (e == hipSuccess) e = hipMalloc(&c->tip0, 3 * (size_t)N * esz);
+  if (e == hipSuccess)
+    e = sgk::launch_tip(c, static_cast<const char*>(c->par) + (size_t)sgk::P_Q0 * J * N * esz, c->tip0);
   if (e == hipSuccess) e = sgk::launch_reset(c);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {

@@ -885,8 +885,9 @@ __device__ __forceinline__ void rnea(PS& ps, int n, const T (&q)[J], const T (&q
 
 // Tool-tip position: p_j = p_{j-1} + R_{j-1} o_j, R_j = R_{j-1} Rot(a_j, q_j),
 // tip = p + R tip_local (prismatic: o_j + q_j a_j, no rotation).
-template <typename T, int J, class PS>
+template <typename T, int J, class PS, bool HW = false>
 __device__ __forceinline__ void tip_fk(PS& ps, int n, const T (&q)[J], const T* tipl, T* out) {
+  // HW: sin and cos from sc_hw (the hardware in FP32) instead of the library
   T W[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)};
   T px = T(0), py = T(0), pz = T(0);
   ps.fence();
@@ -899,7 +900,8 @@ __device__ __forceinline__ void tip_fk(PS& ps, int n, const T (&q)[J], const T* 
       py += W[3] * p.ox + W[4] * p.oy + W[5] * p.oz;
       pz += W[6] * p.ox + W[7] * p.oy + W[8] * p.oz;
       T s, c, Rj[9], Wn[9];
-      sc(pr ? T(0) : q[j], &s, &c);
+      if constexpr (HW) sc_hw(pr ? T(0) : q[j], &s, &c);
+      else sc(pr ? T(0) : q[j], &s, &c);
       rodrigues(p, s, c, Rj);
 #pragma unroll
       for (int r = 0; r < 3; ++r)

@@ -26,6 +26,7 @@ template <typename T> struct EnvDev {
   T dt, h, g[3];
   const T* par;       // [P_NFIELDS][J][N]
   const T* tip;       // [3][N]
+  const T* tip0;      // [3][N] tool tip at q0 (the reset pose)
   const int* nd;      // [N]
   const T* target;    // [3][N]
   const T* wp;        // [K][3][N]
@@ -415,7 +416,9 @@ __device__ __forceinline__ uint8_t post_step(const EnvDev<T>& E, int e, int n, P
                                              T* goal_out = nullptr, uint64_t step = 0) {
   const T tipl[3] = {E.tip[e], E.tip[E.N + e], E.tip[2 * E.N + e]};
   T tip[3], g[3];
-  tip_fk<T, J>(ps, n, q, tipl, tip);
+  // the joint angles' sin and cos from the hardware in FP32 (about 1e-6 m
+  // on the tip, far inside the reward's and observation's rounding budget)
+  tip_fk<T, J, PS, true>(ps, n, q, tipl, tip);
   goal_of(E, e, prog, g);
   const T dx = tip[0] - g[0], dy = tip[1] - g[1], dz = tip[2] - g[2];
   T r = -rsq(dx * dx + dy * dy + dz * dz);
@@ -450,7 +453,10 @@ __device__ __forceinline__ uint8_t post_step(const EnvDev<T>& E, int e, int n, P
       }
     }
     prog = 0;
-    tip_fk<T, J>(ps, n, q, tipl, tip);
+    // the reset pose's tip, computed once at create
+    tip[0] = E.tip0[e];
+    tip[1] = E.tip0[E.N + e];
+    tip[2] = E.tip0[2 * E.N + e];
   }
   if (E.task == TASK_TRACK) track_update(E, e, done != 0, step);
   if (E.rerand && done) rerand_draw(E, e, step);

@@ -27,6 +27,7 @@ struct sg_ctx {
   // device memory (dtype-typed unless noted)
   void* par = nullptr;      // [P_NFIELDS][J][N]
   void* tip = nullptr;      // [3][N]
+  void* tip0 = nullptr;     // [3][N] tool tip at q0
   int* nd = nullptr;        // [N]
   void* target = nullptr;   // [3][N]
   void* wp = nullptr;       // [K][3][N]
@@ -76,7 +77,7 @@ template <typename T> inline EnvDev<T> env_view(const sg_ctx* c) {
   E.dt = (T)c->dt;
   E.h = E.dt / (T)c->S;
   E.g[0] = (T)c->g[0]; E.g[1] = (T)c->g[1]; E.g[2] = (T)c->g[2];
-  E.par = (const T*)c->par; E.tip = (const T*)c->tip; E.nd = c->nd;
+  E.par = (const T*)c->par; E.tip = (const T*)c->tip; E.tip0 = (const T*)c->tip0; E.nd = c->nd;
   E.target = (const T*)c->target; E.wp = (const T*)c->wp; E.prog0 = c->prog0;
   E.q = (T*)c->q; E.qd = (T*)c->qd; E.prog = c->prog;
   E.gs = (T*)c->gs;
