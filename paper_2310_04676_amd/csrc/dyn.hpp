@@ -756,16 +756,24 @@ __device__ __forceinline__ void team_get_link(const TeamLds& t, int slot, float*
   pj[3] = e.x; pj[4] = e.y; pj[5] = e.z;
 }
 
-// The solve as wave 0 of a team runs it (same result as aba_lwa: every
-// quantity is computed by the same expressions, only in another wave).
-// Every wave of the workgroup must be in the matching aba_team_help call.
+// Wave 0's start of a team solve: the state published to the helpers
+// (their aba_team_help starts at this barrier). Work that pass 1 does not
+// need (the drive torques) can follow it and overlap the helpers' chain.
+template <int J>
+__device__ __forceinline__ void team_publish(const TeamLds& t, const float (&q)[J], const float (&qd)[J]) {
+  team_put_state<J>(t, q, qd);
+  __syncthreads();
+}
+
+// The rest of the solve as wave 0 of a team runs it, after team_publish
+// (same result as aba_lwa: every quantity is computed by the same
+// expressions, only in another wave). Every wave of the workgroup must be in
+// the matching aba_team_help call.
 template <int J, class PS>
 __device__ __forceinline__ void aba_lwa_team(PS& ps, int n, const float (&q)[J], const float (&qd)[J],
                                              const float (&tau)[J], const float (&arm)[J], const float* grav,
                                              float (&qdd)[J], const TeamLds& t) {
   float aw[J][3], ow[J][3], cj[J][6], pj[J][6], Iw[J][6], hw[J][3];
-  team_put_state<J>(t, q, qd);
-  __syncthreads();
   ps.fence();
   {
     float W[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};

@@ -228,6 +228,8 @@ __device__ __forceinline__ void physics(const EnvDev<T>& E, PS& ps, int n, const
     }
   }
   for (int s = 0; s < E.S; ++s) {
+    // the helpers start on the published state while the torques are formed
+    if constexpr (TEAM) team_publish<J>(team, q, qd);
     ps.fence();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
