@@ -549,96 +549,92 @@ __device__ __forceinline__ void p1_link(const Jp<T>& p, const T (&W)[9], const T
   pj[5] = w[0] * f1 - w[1] * f0;
 }
 
-// Passes 2 and 3 of the base-oriented solve from pass 1's per-joint axis aw,
-// offset ow, c, bias force pj and rotated inertia (Iw, hw).
+// One step of the base-oriented inward pass (pass 2) for joint j: acc and
+// accp hold the articulated inertia and bias force its children hand to
+// joint j's origin, and receive this joint's contribution at its parent's
+// origin; U, invD and uj of joint j are kept for pass 3.
 template <typename T, int J, class PS>
-__device__ __forceinline__ void aba_lwa_io(PS& ps, int n, const T (&tau)[J], const T (&arm)[J], const T* grav,
-                                           const T (&aw)[J][3], const T (&ow)[J][3], const T (&cj)[J][6],
-                                           const T (&pj)[J][6], const T (&Iw)[J][6], const T (&hw)[J][3],
-                                           T (&qdd)[J]) {
-  T U[J][6], invD[J], uj[J];
-  // pass 2
-  ps.fence();
-  AI<T> acc;
-  T accp[6];
+__device__ __forceinline__ void p2_step(PS& ps, int j, int n, const T (&tau)[J], const T (&arm)[J],
+                                        const T (&aw)[J][3], const T (&ow)[J][3], const T (&cj)[J][6],
+                                        const T (&pj)[J][6], const T (&Iw)[J][6], const T (&hw)[J][3], AI<T>& acc,
+                                        T (&accp)[6], T (&U)[J][6], T (&invD)[J], T (&uj)[J]) {
+  if (j < n) {
+    T m, pr_;
+    {
+      const Jp<T> p = ps.get(j);
+      m = p.m;
+      pr_ = p.pr;
+    }
+    const bool pr = PS::kPris && pr_ != T(0);
+    const T* h = hw[j];
+    AI<T> I;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) { acc.A[k] = T(0); acc.C[k] = T(0); accp[k] = T(0); }
+    for (int k = 0; k < 6; ++k) I.A[k] = Iw[j][k] + acc.A[k];
+    I.B[0] = acc.B[0];        I.B[1] = acc.B[1] - h[2]; I.B[2] = acc.B[2] + h[1];
+    I.B[3] = acc.B[3] + h[2]; I.B[4] = acc.B[4];        I.B[5] = acc.B[5] - h[0];
+    I.B[6] = acc.B[6] - h[1]; I.B[7] = acc.B[7] + h[0]; I.B[8] = acc.B[8];
+    I.C[S00] = m + acc.C[S00]; I.C[S11] = m + acc.C[S11]; I.C[S22] = m + acc.C[S22];
+    I.C[S01] = acc.C[S01];     I.C[S02] = acc.C[S02];     I.C[S12] = acc.C[S12];
+    T pa[6];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) acc.B[k] = T(0);
+    for (int k = 0; k < 6; ++k) pa[k] = pj[j][k] + accp[k];
+    const T ax = aw[j][0], ay = aw[j][1], az = aw[j][2];
+    if (!pr) {
+      U[j][0] = I.A[S00] * ax + I.A[S01] * ay + I.A[S02] * az;
+      U[j][1] = I.A[S01] * ax + I.A[S11] * ay + I.A[S12] * az;
+      U[j][2] = I.A[S02] * ax + I.A[S12] * ay + I.A[S22] * az;
+      U[j][3] = I.B[0] * ax + I.B[3] * ay + I.B[6] * az;
+      U[j][4] = I.B[1] * ax + I.B[4] * ay + I.B[7] * az;
+      U[j][5] = I.B[2] * ax + I.B[5] * ay + I.B[8] * az;
+      invD[j] = recip(U[j][0] * ax + U[j][1] * ay + U[j][2] * az + arm[j]);
+      uj[j] = tau[j] - (pa[0] * ax + pa[1] * ay + pa[2] * az);
+    } else {
+      U[j][0] = I.B[0] * ax + I.B[1] * ay + I.B[2] * az;
+      U[j][1] = I.B[3] * ax + I.B[4] * ay + I.B[5] * az;
+      U[j][2] = I.B[6] * ax + I.B[7] * ay + I.B[8] * az;
+      U[j][3] = I.C[S00] * ax + I.C[S01] * ay + I.C[S02] * az;
+      U[j][4] = I.C[S01] * ax + I.C[S11] * ay + I.C[S12] * az;
+      U[j][5] = I.C[S02] * ax + I.C[S12] * ay + I.C[S22] * az;
+      invD[j] = recip(U[j][3] * ax + U[j][4] * ay + U[j][5] * az + arm[j]);
+      uj[j] = tau[j] - (pa[3] * ax + pa[4] * ay + pa[5] * az);
+    }
+    if (j > 0) {
+      T Ud[6];
 #pragma unroll
-  for (int j = J - 1; j >= 0; --j) {
-    if (j < n) {
-      T m, pr_;
-      {
-        const Jp<T> p = ps.get(j);
-        m = p.m;
-        pr_ = p.pr;
-      }
-      const bool pr = PS::kPris && pr_ != T(0);
-      const T* h = hw[j];
-      AI<T> I;
+      for (int k = 0; k < 6; ++k) Ud[k] = U[j][k] * invD[j];
+      I.A[S00] -= U[j][0] * Ud[0]; I.A[S11] -= U[j][1] * Ud[1]; I.A[S22] -= U[j][2] * Ud[2];
+      I.A[S01] -= U[j][0] * Ud[1]; I.A[S02] -= U[j][0] * Ud[2]; I.A[S12] -= U[j][1] * Ud[2];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) I.A[k] = Iw[j][k] + acc.A[k];
-      I.B[0] = acc.B[0];        I.B[1] = acc.B[1] - h[2]; I.B[2] = acc.B[2] + h[1];
-      I.B[3] = acc.B[3] + h[2]; I.B[4] = acc.B[4];        I.B[5] = acc.B[5] - h[0];
-      I.B[6] = acc.B[6] - h[1]; I.B[7] = acc.B[7] + h[0]; I.B[8] = acc.B[8];
-      I.C[S00] = m + acc.C[S00]; I.C[S11] = m + acc.C[S11]; I.C[S22] = m + acc.C[S22];
-      I.C[S01] = acc.C[S01];     I.C[S02] = acc.C[S02];     I.C[S12] = acc.C[S12];
-      T pa[6];
+      for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int k = 0; k < 6; ++k) pa[k] = pj[j][k] + accp[k];
-      const T ax = aw[j][0], ay = aw[j][1], az = aw[j][2];
-      if (!pr) {
-        U[j][0] = I.A[S00] * ax + I.A[S01] * ay + I.A[S02] * az;
-        U[j][1] = I.A[S01] * ax + I.A[S11] * ay + I.A[S12] * az;
-        U[j][2] = I.A[S02] * ax + I.A[S12] * ay + I.A[S22] * az;
-        U[j][3] = I.B[0] * ax + I.B[3] * ay + I.B[6] * az;
-        U[j][4] = I.B[1] * ax + I.B[4] * ay + I.B[7] * az;
-        U[j][5] = I.B[2] * ax + I.B[5] * ay + I.B[8] * az;
-        invD[j] = recip(U[j][0] * ax + U[j][1] * ay + U[j][2] * az + arm[j]);
-        uj[j] = tau[j] - (pa[0] * ax + pa[1] * ay + pa[2] * az);
-      } else {
-        U[j][0] = I.B[0] * ax + I.B[1] * ay + I.B[2] * az;
-        U[j][1] = I.B[3] * ax + I.B[4] * ay + I.B[5] * az;
-        U[j][2] = I.B[6] * ax + I.B[7] * ay + I.B[8] * az;
-        U[j][3] = I.C[S00] * ax + I.C[S01] * ay + I.C[S02] * az;
-        U[j][4] = I.C[S01] * ax + I.C[S11] * ay + I.C[S12] * az;
-        U[j][5] = I.C[S02] * ax + I.C[S12] * ay + I.C[S22] * az;
-        invD[j] = recip(U[j][3] * ax + U[j][4] * ay + U[j][5] * az + arm[j]);
-        uj[j] = tau[j] - (pa[3] * ax + pa[4] * ay + pa[5] * az);
-      }
-      if (j > 0) {
-        T Ud[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) Ud[k] = U[j][k] * invD[j];
-        I.A[S00] -= U[j][0] * Ud[0]; I.A[S11] -= U[j][1] * Ud[1]; I.A[S22] -= U[j][2] * Ud[2];
-        I.A[S01] -= U[j][0] * Ud[1]; I.A[S02] -= U[j][0] * Ud[2]; I.A[S12] -= U[j][1] * Ud[2];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int s2 = 0; s2 < 3; ++s2) I.B[r * 3 + s2] -= U[j][r] * Ud[3 + s2];
-        I.C[S00] -= U[j][3] * Ud[3]; I.C[S11] -= U[j][4] * Ud[4]; I.C[S22] -= U[j][5] * Ud[5];
-        I.C[S01] -= U[j][3] * Ud[4]; I.C[S02] -= U[j][3] * Ud[5]; I.C[S12] -= U[j][4] * Ud[5];
-        const T* c = cj[j];
-        const T uD = uj[j] * invD[j];
-        T f[6];
-        f[0] = pa[0] + I.A[S00] * c[0] + I.A[S01] * c[1] + I.A[S02] * c[2] + I.B[0] * c[3] + I.B[1] * c[4] + I.B[2] * c[5] + U[j][0] * uD;
-        f[1] = pa[1] + I.A[S01] * c[0] + I.A[S11] * c[1] + I.A[S12] * c[2] + I.B[3] * c[3] + I.B[4] * c[4] + I.B[5] * c[5] + U[j][1] * uD;
-        f[2] = pa[2] + I.A[S02] * c[0] + I.A[S12] * c[1] + I.A[S22] * c[2] + I.B[6] * c[3] + I.B[7] * c[4] + I.B[8] * c[5] + U[j][2] * uD;
-        f[3] = pa[3] + I.B[0] * c[0] + I.B[3] * c[1] + I.B[6] * c[2] + I.C[S00] * c[3] + I.C[S01] * c[4] + I.C[S02] * c[5] + U[j][3] * uD;
-        f[4] = pa[4] + I.B[1] * c[0] + I.B[4] * c[1] + I.B[7] * c[2] + I.C[S01] * c[3] + I.C[S11] * c[4] + I.C[S12] * c[5] + U[j][4] * uD;
-        f[5] = pa[5] + I.B[2] * c[0] + I.B[5] * c[1] + I.B[8] * c[2] + I.C[S02] * c[3] + I.C[S12] * c[4] + I.C[S22] * c[5] + U[j][5] * uD;
-        // to the parent's origin: translate by o = this joint's offset
-        const T* o = ow[j];
-        shift_inertia(o, I, acc);
-        accp[0] = f[0] + (o[1] * f[5] - o[2] * f[4]);
-        accp[1] = f[1] + (o[2] * f[3] - o[0] * f[5]);
-        accp[2] = f[2] + (o[0] * f[4] - o[1] * f[3]);
-        accp[3] = f[3]; accp[4] = f[4]; accp[5] = f[5];
-      }
+        for (int s2 = 0; s2 < 3; ++s2) I.B[r * 3 + s2] -= U[j][r] * Ud[3 + s2];
+      I.C[S00] -= U[j][3] * Ud[3]; I.C[S11] -= U[j][4] * Ud[4]; I.C[S22] -= U[j][5] * Ud[5];
+      I.C[S01] -= U[j][3] * Ud[4]; I.C[S02] -= U[j][3] * Ud[5]; I.C[S12] -= U[j][4] * Ud[5];
+      const T* c = cj[j];
+      const T uD = uj[j] * invD[j];
+      T f[6];
+      f[0] = pa[0] + I.A[S00] * c[0] + I.A[S01] * c[1] + I.A[S02] * c[2] + I.B[0] * c[3] + I.B[1] * c[4] + I.B[2] * c[5] + U[j][0] * uD;
+      f[1] = pa[1] + I.A[S01] * c[0] + I.A[S11] * c[1] + I.A[S12] * c[2] + I.B[3] * c[3] + I.B[4] * c[4] + I.B[5] * c[5] + U[j][1] * uD;
+      f[2] = pa[2] + I.A[S02] * c[0] + I.A[S12] * c[1] + I.A[S22] * c[2] + I.B[6] * c[3] + I.B[7] * c[4] + I.B[8] * c[5] + U[j][2] * uD;
+      f[3] = pa[3] + I.B[0] * c[0] + I.B[3] * c[1] + I.B[6] * c[2] + I.C[S00] * c[3] + I.C[S01] * c[4] + I.C[S02] * c[5] + U[j][3] * uD;
+      f[4] = pa[4] + I.B[1] * c[0] + I.B[4] * c[1] + I.B[7] * c[2] + I.C[S01] * c[3] + I.C[S11] * c[4] + I.C[S12] * c[5] + U[j][4] * uD;
+      f[5] = pa[5] + I.B[2] * c[0] + I.B[5] * c[1] + I.B[8] * c[2] + I.C[S02] * c[3] + I.C[S12] * c[4] + I.C[S22] * c[5] + U[j][5] * uD;
+      // to the parent's origin: translate by o = this joint's offset
+      const T* o = ow[j];
+      shift_inertia(o, I, acc);
+      accp[0] = f[0] + (o[1] * f[5] - o[2] * f[4]);
+      accp[1] = f[1] + (o[2] * f[3] - o[0] * f[5]);
+      accp[2] = f[2] + (o[0] * f[4] - o[1] * f[3]);
+      accp[3] = f[3]; accp[4] = f[4]; accp[5] = f[5];
     }
   }
-  // pass 3
+}
+
+// Pass 3 (outward accelerations) from pass 2's U, invD and uj.
+template <typename T, int J, class PS>
+__device__ __forceinline__ void p3_pass(PS& ps, int n, const T* grav, const T (&aw)[J][3], const T (&ow)[J][3],
+                                        const T (&cj)[J][6], const T (&U)[J][6], const T (&invD)[J],
+                                        const T (&uj)[J], T (&qdd)[J]) {
   T a[6] = {T(0), T(0), T(0), -grav[0], -grav[1], -grav[2]};
 #pragma unroll
   for (int j = 0; j < J; ++j) {
@@ -670,6 +666,32 @@ __device__ __forceinline__ void aba_lwa_io(PS& ps, int n, const T (&tau)[J], con
   }
 }
 
+
+template <typename T> __device__ __forceinline__ void ai_zero(AI<T>& acc, T (&accp)[6]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) { acc.A[k] = T(0); acc.C[k] = T(0); accp[k] = T(0); }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc.B[k] = T(0);
+}
+
+// Passes 2 and 3 of the base-oriented solve from pass 1's per-joint axis aw,
+// offset ow, c, bias force pj and rotated inertia (Iw, hw).
+template <typename T, int J, class PS>
+__device__ __forceinline__ void aba_lwa_io(PS& ps, int n, const T (&tau)[J], const T (&arm)[J], const T* grav,
+                                           const T (&aw)[J][3], const T (&ow)[J][3], const T (&cj)[J][6],
+                                           const T (&pj)[J][6], const T (&Iw)[J][6], const T (&hw)[J][3],
+                                           T (&qdd)[J]) {
+  T U[J][6], invD[J], uj[J];
+  // pass 2
+  ps.fence();
+  AI<T> acc;
+  T accp[6];
+  ai_zero(acc, accp);
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j) p2_step<T, J>(ps, j, n, tau, arm, aw, ow, cj, pj, Iw, hw, acc, accp, U, invD, uj);
+  p3_pass<T, J>(ps, n, grav, aw, ow, cj, U, invD, uj, qdd);
+}
+
 template <typename T, int J, class PS>
 __device__ __forceinline__ void aba_lwa(PS& ps, int n, const T (&q)[J], const T (&qd)[J], const T (&tau)[J],
                                         const T (&arm)[J], const T* grav, T (&qdd)[J]) {
@@ -696,18 +718,33 @@ __device__ __forceinline__ void aba_lwa(PS& ps, int n, const T (&q)[J], const T 
 // solve. Wave 0 owns the envs' state, runs the serial chain of pass 1 and
 // passes 2 and 3. The joint-independent work of link j (p1_link: its
 // inertia rotated into the base orientation and its bias force, about half
-// of pass 1) is done by wave j mod kTeam: each helper wave recomputes the
-// chain up to its links from the state wave 0 publishes in LDS and hands
-// back 15 numbers per link through LDS. Two workgroup barriers per solve:
-// after the state is published and after the links are handed back.
+// of pass 1) is done by wave team_owner(j, J): each helper wave recomputes
+// the chain up to its links from the state wave 0 publishes in LDS and
+// hands back 15 numbers per link through LDS. Two workgroup barriers per
+// solve: after the state is published and after the links are handed back.
+// Ownership: for 7-joint chains wave 0 keeps the last link, whose inward
+// step (the first of pass 2) it then runs before the second barrier while
+// the helpers finish, and links 0-5 go to the helpers as {1, 4}, {2, 5},
+// {0, 3}; other lengths use j mod kTeam.
 // LDS: the state as [(2J+3)/4][64] float4, the links as
 // [team_links(J)][4][64] float4 (Iw 0-3 | Iw 4-5, hw 0-1 | hw 2, p 0-2 |
 // p 3-5, -); every lane touches only its own env's entries.
 constexpr int kTeam = 4;
-__host__ __device__ constexpr int team_slot(int j) { return j - (j + kTeam - 1) / kTeam; }
-__host__ __device__ constexpr int team_links(int J) { return team_slot(J); }
+__host__ __device__ constexpr int team_owner(int j, int J) {
+  return J == 7 ? (j == J - 1 ? 0 : 1 + (j + 2) % (kTeam - 1)) : j % kTeam;
+}
+// index of link j among the links the helpers hand back
+__host__ __device__ constexpr int team_slot(int j, int J) { return J == 7 ? j : j - (j + kTeam - 1) / kTeam; }
+__host__ __device__ constexpr int team_links(int J) { return J == 7 ? J - 1 : J - (J + kTeam - 1) / kTeam; }
 __host__ __device__ constexpr int team_state_slots(int J) { return (2 * J + 3) / 4; }
 __host__ __device__ constexpr size_t team_lds_bytes(int J) { return (size_t)team_links(J) * 4 * 64 * 16; }
+// the last link of helper wave w (-1: none)
+__host__ __device__ constexpr int team_last(int w, int J) {
+  int last = -1;
+  for (int j = 0; j < J; ++j)
+    if (team_owner(j, J) == w) last = j;
+  return last;
+}
 
 struct TeamLds {
   float4* st;  // [team_state_slots(J)][64]
@@ -783,15 +820,26 @@ __device__ __forceinline__ void aba_lwa_team(PS& ps, int n, const float (&q)[J],
       if (j < n) {
         Jp<float> p = ps.get(j);
         p1_chain<PS>(p, q[j], qd[j], W, w, vl, aw[j], ow[j], cj[j]);
-        if (j % kTeam == 0) p1_link(p, W, w, vl, Iw[j], hw[j], pj[j]);
+        if (team_owner(j, J) == 0) p1_link(p, W, w, vl, Iw[j], hw[j], pj[j]);
       }
     }
   }
+  float U[J][6], invD[J], uj[J];
+  AI<float> acc;
+  float accp[6];
+  ps.fence();
+  ai_zero(acc, accp);
+  // the last link is wave 0's: its inward step needs nothing from the helpers
+  constexpr bool kEarly = team_owner(J - 1, J) == 0;
+  if constexpr (kEarly) p2_step<float, J>(ps, J - 1, n, tau, arm, aw, ow, cj, pj, Iw, hw, acc, accp, U, invD, uj);
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < J; ++j)
-    if (j % kTeam != 0 && j < n) team_get_link(t, team_slot(j), Iw[j], hw[j], pj[j]);
-  aba_lwa_io<float, J>(ps, n, tau, arm, grav, aw, ow, cj, pj, Iw, hw, qdd);
+    if (team_owner(j, J) != 0 && j < n) team_get_link(t, team_slot(j, J), Iw[j], hw[j], pj[j]);
+#pragma unroll
+  for (int j = kEarly ? J - 2 : J - 1; j >= 0; --j)
+    p2_step<float, J>(ps, j, n, tau, arm, aw, ow, cj, pj, Iw, hw, acc, accp, U, invD, uj);
+  p3_pass<float, J>(ps, n, grav, aw, ow, cj, U, invD, uj, qdd);
 }
 
 // A helper wave's part of one team solve (t.wave = 1 .. kTeam-1): the chain
@@ -804,18 +852,17 @@ __device__ __forceinline__ void aba_team_help(PS& ps, int n, const TeamLds& t) {
   ps.fence();
   float W[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
   float w[3] = {0.f, 0.f, 0.f}, vl[3] = {0.f, 0.f, 0.f};
-  // last link of this wave: the largest j < J with j % kTeam == wave
-  const int last = t.wave + ((J - 1 - t.wave) / kTeam) * kTeam;
+  const int last = team_last(t.wave, J);
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (j <= last && j < n) {
       Jp<float> p = ps.get(j);
       float a[3], o[3], c[6];
       p1_chain<PS>(p, q[j], qd[j], W, w, vl, a, o, c);
-      if (j % kTeam != 0 && j % kTeam == t.wave) {
+      if (team_owner(j, J) != 0 && team_owner(j, J) == t.wave) {
         float Iw[6], hw[3], pj[6];
         p1_link(p, W, w, vl, Iw, hw, pj);
-        team_put_link(t, team_slot(j), Iw, hw, pj);
+        team_put_link(t, team_slot(j, J), Iw, hw, pj);
       }
     }
   }
