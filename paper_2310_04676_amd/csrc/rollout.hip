@@ -48,6 +48,52 @@ struct RollArgs {
   float* val;
 };
 
+// GAE for env e: one lane walks t = T-1 .. 0; each step reads one
+// coalesced row of rew / val / done and writes one row of adv / ret.
+// delta_t = r_t + gamma V_{t+1} (1 - d_t) - V_t with r_t += gamma V_t on a
+// time-out; A_t = delta_t + gamma lam (1 - d_t) A_{t+1}; R_t = A_t + V_t.
+// The rows of kGaeChunk steps are loaded before the chunk's recursion runs,
+// so the loads overlap instead of each waiting on the last.
+constexpr int kGaeChunk = 16;
+constexpr int kGaeBlock = 64;
+__device__ __forceinline__ void gae_env(int T, int n, int e, const float* __restrict__ rew,
+                                        const float* __restrict__ val, const uint8_t* __restrict__ done,
+                                        float gamma, float lam, float* __restrict__ adv, float* __restrict__ ret) {
+  float A = 0.f;
+  float vnext = val[(size_t)T * n + e];
+  for (int t1 = T; t1 > 0; t1 -= kGaeChunk) {
+    const int t0 = t1 > kGaeChunk ? t1 - kGaeChunk : 0;  // this chunk: t0 .. t1-1
+    float rr[kGaeChunk], vv[kGaeChunk];
+    uint8_t dd[kGaeChunk];
+#pragma unroll
+    for (int k = 0; k < kGaeChunk; ++k) {
+      const int t = t0 + k;
+      if (t < t1) {
+        const size_t i = (size_t)t * n + e;
+        rr[k] = rew[i];
+        vv[k] = val[i];
+        dd[k] = done[i];
+      }
+    }
+#pragma unroll
+    for (int k = kGaeChunk - 1; k >= 0; --k) {
+      const int t = t0 + k;
+      if (t < t1) {
+        const size_t i = (size_t)t * n + e;
+        const uint8_t d = dd[k];
+        const float v = vv[k];
+        const float nd = (d & DONE_ENDED) ? 0.f : 1.f;
+        const float r = rr[k] + ((d & DONE_TIMEOUT) ? gamma * v : 0.f);
+        const float delta = r + gamma * vnext * nd - v;
+        A = delta + gamma * lam * nd * A;
+        adv[i] = A;
+        ret[i] = A + v;
+        vnext = v;
+      }
+    }
+  }
+}
+
 template <int H3>
 __device__ __forceinline__ void fill_weights(uint4* sw, float* sb, const uint4* __restrict__ wimg,
                                              const float* __restrict__ bias, int tid, int nthreads) {
@@ -224,35 +270,18 @@ __global__ void __launch_bounds__(kWave) k_policy(const uint4* __restrict__ wimg
     for (int i = 0; i < n_out; ++i) out[(size_t)i * n + e] = s_o[lane * kOut + i];
 }
 
-// One lane per env walks t = T-1 .. 0; each step reads one coalesced row of
-// rew / val / done and writes one row of adv / ret (HBM-bound).
-// delta_t = r_t + gamma V_{t+1} (1 - d_t) - V_t with r_t += gamma V_t on a
-// time-out; A_t = delta_t + gamma lam (1 - d_t) A_{t+1}; R_t = A_t + V_t.
-__global__ void __launch_bounds__(256) k_gae(int T, int n, const float* __restrict__ rew,
-                                             const float* __restrict__ val, const uint8_t* __restrict__ done,
-                                             float gamma, float lam, float* __restrict__ adv,
-                                             float* __restrict__ ret) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= n) return;
-  float A = 0.f;
-  float vnext = val[(size_t)T * n + e];
-  for (int t = T - 1; t >= 0; --t) {
-    const size_t i = (size_t)t * n + e;
-    const uint8_t d = done[i];
-    const float v = val[i];
-    const float nd = (d & DONE_ENDED) ? 0.f : 1.f;
-    const float r = rew[i] + ((d & DONE_TIMEOUT) ? gamma * v : 0.f);
-    const float delta = r + gamma * vnext * nd - v;
-    A = delta + gamma * lam * nd * A;
-    adv[i] = A;
-    ret[i] = A + v;
-    vnext = v;
-  }
+// The GAE scan (after each rollout, and sg_gae): one lane per env.
+__global__ void __launch_bounds__(kGaeBlock) k_gae(int T, int n, const float* __restrict__ rew,
+                                                   const float* __restrict__ val, const uint8_t* __restrict__ done,
+                                                   float gamma, float lam, float* __restrict__ adv,
+                                                   float* __restrict__ ret) {
+  const int e = blockIdx.x * kGaeBlock + threadIdx.x;
+  if (e < n) gae_env(T, n, e, rew, val, done, gamma, lam, adv, ret);
 }
 
 hipError_t launch_gae(hipStream_t s, int T, int n, const float* rew, const float* val, const uint8_t* done,
                       float gamma, float lam, float* adv, float* ret) {
-  k_gae<<<dim3((n + 255) / 256), 256, 0, s>>>(T, n, rew, val, done, gamma, lam, adv, ret);
+  k_gae<<<dim3((n + kGaeBlock - 1) / kGaeBlock), kGaeBlock, 0, s>>>(T, n, rew, val, done, gamma, lam, adv, ret);
   return hipGetLastError();
 }
 
