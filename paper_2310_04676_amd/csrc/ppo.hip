@@ -11,18 +11,18 @@
 //   k_ppo_gather   the minibatch's rows -> X [B][32] (in sg_ppo_update
 //                  only for the first minibatch: later ones are gathered
 //                  by extra blocks of the previous k_ppo_norm_adam launch)
-//   forward        three BF16 MFMA GEMMs (nn.hpp), tanh units; layer 2's
-//                  pre-activations stay in HBM for the backward pass, layer
-//                  1's (W = 2J + 10 inputs) are recomputed there
-//   k_ppo_loss     ratio, clipped objectives, dL/d(outputs) [B][8] (BF16
-//                  for the GEMMs) and per-block sums of the output-bias and
-//                  log_std gradients and of the loss statistics
-//   backward       data gradients as GEMMs with the tanh' epilogue, which
+//   k_ppo_front    (256-128 network) the forward pass, the loss and the
+//                  gradient down to hidden layer 2's pre-activations in one
+//                  launch on the matrix cores, activations in registers;
+//                  the 256-128-64 network runs the same steps as GEMMs
+//                  (nn.hpp) and k_ppo_loss
+//   backward       data gradients as GEMMs with the act' epilogue, which
 //                  also emits per-block column sums (the hidden biases'
-//                  gradients); weight gradients as split-K GEMMs (the batch
-//                  is the reduction axis); every partial is summed in a
-//                  fixed order -- deterministic; the three split sums and
-//                  the three bias sums share one launch (k_sum_jobs)
+//                  gradients; layer 1's pre-activations are recomputed
+//                  there from its W = 2J + 10 inputs); weight gradients as
+//                  split-K GEMMs (the batch is the reduction axis); every
+//                  partial is summed in a fixed order -- deterministic; the
+//                  split sums and bias sums share one launch (k_sum_jobs)
 //   k_ppo_norm_adam  entropy term, global gradient norm, statistics, norm
 //                  clip and Adam on the FP32 master weights + BF16 copy, in
 //                  one launch (sg_ppo_grad: k_gnorm_part and k_ppo_finish
@@ -58,21 +58,21 @@ struct sg_ppo {
   uint16_t* Xall = nullptr;  // [max_samples][32] sample-major BF16 observations
   float* Aux = nullptr;      // [max_samples][kAux] sample-major act, logp, adv, value, return
   uint16_t* H1 = nullptr;    // [rows][256] (layer 1's pre-activations are recomputed, not kept)
-  float* Z2 = nullptr;       // [rows][128]
+  float* Z2 = nullptr;       // [rows][128] (h3 > 0; the fused front keeps them in registers)
   uint16_t* H2 = nullptr;
   float* Z3h = nullptr;      // [rows][h3] third hidden layer's pre-activations (h3 > 0)
   uint16_t* H3 = nullptr;    // [rows][h3]
   uint16_t* D3b = nullptr;   // [rows][h3]
   float* cpart3 = nullptr;   // per-block column sums of dZ3 [rows / 64][h3]
-  float* Z3 = nullptr;       // [rows][8] outputs
+  float* Z3 = nullptr;       // [rows][8] outputs (h3 > 0)
   uint16_t* G3b = nullptr;   // [rows][8] dL/d(outputs)
   uint16_t* D2b = nullptr;   // [rows][128]
   uint16_t* D1b = nullptr;   // [rows][256]
   float* ws = nullptr;       // split-K partials, one kWeightGradWs region per layer
   size_t ws_floats = 0;
   float* cpart = nullptr;    // per-block column sums of dZ1 [rows / 64][256]
-  float* cpart2 = nullptr;   // per-block column sums of dZ2 [rows / 64][128]
-  float* lpart = nullptr;    // k_ppo_loss block sums [rows / 256][kLossPart]
+  float* cpart2 = nullptr;   // per-block column sums of dZ2 [blocks of 64 or kFrontRows rows][128]
+  float* lpart = nullptr;    // loss block sums [loss_blocks(rows)][kLossPart]
   double* gpart = nullptr;   // block sums [kGnormBlocks]: advantage statistics, then gradient norm
   std::vector<void*> allocs;
 };
@@ -218,8 +218,63 @@ struct PpoLossArgs {
   float* part;          // [gridDim.x][kLossPart] block sums (see kLossPart)
 };
 
-// Per row: log pi(a) under the current outputs, ratio, clipped objectives,
-// gradients w.r.t. the outputs (mu, V) and log_std.
+// One minibatch row with loss inputs x (action, old log-probability,
+// normalised advantage, old value, return): log pi(a) under the outputs z
+// (mu | V), ratio, clipped objectives; g receives dL/d(outputs), dl the
+// log_std terms, and the loss terms lpi, lv, kl and the clip indicator cf.
+// A row whose sample id is outside [0, T N) contributes zeros (the caller
+// skips it).
+// The loss inputs of row r (ppo_row_loss's x); false for a sample id
+// outside [0, T N).
+__device__ __forceinline__ bool ppo_row_inputs(const PpoRows& R, int r, float (&x)[kAux]) {
+  const int s = ppo_sample(R, r);
+  if (s < 0 || s >= R.total) return false;
+  const float4* src = reinterpret_cast<const float4*>(R.aux + (size_t)s * kAux);
+#pragma unroll
+  for (int q = 0; q < kAux / 4; ++q) {
+    const float4 v = src[q];
+    x[4 * q] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
+  }
+  return true;
+}
+__device__ __forceinline__ void ppo_row_loss(int J, const float (&x)[kAux], const float* z,
+                                             const float* __restrict__ ls, float clip, float c_v, float inv_b,
+                                             float (&g)[kPO], float (&dl)[kPO], float& lpi, float& lv, float& kl,
+                                             float& cf) {
+  float logp = 0.f;
+  float u[kPO];
+  for (int j = 0; j < J; ++j) {
+    const float sig = __expf(ls[j]);
+    u[j] = (x[j] - z[j]) / sig;
+    logp += -0.5f * u[j] * u[j] - ls[j] - 0.91893853320467274f;
+  }
+  const float lold = x[kAux - 4];
+  const float A = x[kAux - 3];
+  const float ratio = __expf(logp - lold);
+  const float rc = fminf(fmaxf(ratio, 1.f - clip), 1.f + clip);
+  lpi = -fminf(ratio * A, rc * A);
+  kl = lold - logp;
+  cf = fabsf(ratio - 1.f) > clip ? 1.f : 0.f;
+  const bool live = A >= 0.f ? ratio <= 1.f + clip : ratio >= 1.f - clip;
+  const float dlogp = live ? -A * ratio * inv_b : 0.f;
+  for (int j = 0; j < J; ++j) {
+    const float sig = __expf(ls[j]);
+    g[j] = dlogp * u[j] / sig;
+    dl[j] = dlogp * (u[j] * u[j] - 1.f);
+  }
+  const float V = z[J], vold = x[kAux - 2], ret = x[kAux - 1];
+  const float dv = V - vold;
+  const float Vc = vold + fminf(fmaxf(dv, -clip), clip);
+  const float e1 = (V - ret) * (V - ret), e2 = (Vc - ret) * (Vc - ret);
+  lv = fmaxf(e1, e2);
+  float dV;
+  if (e1 >= e2) dV = 2.f * (V - ret);
+  else dV = fabsf(dv) <= clip ? 2.f * (Vc - ret) : 0.f;
+  g[J] = c_v * dV * inv_b;
+}
+
+// Per row: the loss of ppo_row_loss on the output rows Z3; BF16 dL/d(outputs)
+// and per-block sums.
 __global__ void __launch_bounds__(256) k_ppo_loss(PpoLossArgs a) {
   const int r = blockIdx.x * 256 + threadIdx.x;
   const PpoRows& R = a.rows;
@@ -228,49 +283,9 @@ __global__ void __launch_bounds__(256) k_ppo_loss(PpoLossArgs a) {
 #pragma unroll
   for (int k = 0; k < kPO; ++k) { g[k] = 0.f; dl[k] = 0.f; }
   if (r < R.rows) {
-    const int s = ppo_sample(R, r);
-    const bool ok = s >= 0 && s < R.total;
-    if (ok) {
-      const int J = R.J;
-      const float* z = a.Z3 + (size_t)r * kPO;
-      float x[kAux];
-      const float4* src = reinterpret_cast<const float4*>(R.aux + (size_t)s * kAux);
-#pragma unroll
-      for (int q = 0; q < kAux / 4; ++q) {
-        const float4 v = src[q];
-        x[4 * q] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
-      }
-      float logp = 0.f;
-      float u[kPO];
-      for (int j = 0; j < J; ++j) {
-        const float sig = __expf(a.ls[j]);
-        u[j] = (x[j] - z[j]) / sig;
-        logp += -0.5f * u[j] * u[j] - a.ls[j] - 0.91893853320467274f;
-      }
-      const float lold = x[kAux - 4];
-      const float A = x[kAux - 3];
-      const float ratio = __expf(logp - lold);
-      const float rc = fminf(fmaxf(ratio, 1.f - a.clip), 1.f + a.clip);
-      lpi = -fminf(ratio * A, rc * A);
-      kl = lold - logp;
-      cf = fabsf(ratio - 1.f) > a.clip ? 1.f : 0.f;
-      const bool live = A >= 0.f ? ratio <= 1.f + a.clip : ratio >= 1.f - a.clip;
-      const float dlogp = live ? -A * ratio * a.inv_b : 0.f;
-      for (int j = 0; j < J; ++j) {
-        const float sig = __expf(a.ls[j]);
-        g[j] = dlogp * u[j] / sig;
-        dl[j] = dlogp * (u[j] * u[j] - 1.f);
-      }
-      const float V = z[J], vold = x[kAux - 2], ret = x[kAux - 1];
-      const float dv = V - vold;
-      const float Vc = vold + fminf(fmaxf(dv, -a.clip), a.clip);
-      const float e1 = (V - ret) * (V - ret), e2 = (Vc - ret) * (Vc - ret);
-      lv = fmaxf(e1, e2);
-      float dV;
-      if (e1 >= e2) dV = 2.f * (V - ret);
-      else dV = fabsf(dv) <= a.clip ? 2.f * (Vc - ret) : 0.f;
-      g[J] = a.c_v * dV * a.inv_b;
-    }
+    float x[kAux];
+    if (ppo_row_inputs(R, r, x))
+      ppo_row_loss(R.J, x, a.Z3 + (size_t)r * kPO, a.ls, a.clip, a.c_v, a.inv_b, g, dl, lpi, lv, kl, cf);
 #pragma unroll
     for (int k = 0; k < kPO; ++k) a.G3b[(size_t)r * kPO + k] = bf16_bits(g[k]);
   }
@@ -307,6 +322,328 @@ __global__ void __launch_bounds__(256) k_ppo_loss(PpoLossArgs a) {
           src < 0 ? 0.f : (red[0][src] + red[1][src]) + (red[2][src] + red[3][src]);
     }
   }
+}
+
+// Fused front of a minibatch for the two-hidden-layer network (256-128,
+// J + 1 outputs): per chunk of kFrontRows rows (one 16-row tile per wave)
+// layer 1, layer 2 and the output layer on the matrix cores, the loss of
+// ppo_row_loss, and the gradient through the output layer and hidden layer
+// 2's activation -- the work of the three forward GEMMs, k_ppo_loss and the
+// first data-gradient GEMM, with the same arithmetic per element: each
+// layer's z = (sum over K) + bias and act(z) rounded to BF16 as in the GEMM
+// epilogues, the outputs' gradient rounded to BF16 before it meets the
+// output weights, dZ2 = (G Wo) act'(Z2) from the FP32 pre-activations.
+// Within a 32-wide K block the matrix cores sum in their own order, so
+// results agree with the GEMM path to FP32 rounding, not bit for bit.
+// Writes H1, H2 (the weight gradients' operands), G3b, D2b, and per chunk
+// the column sums of dZ2 (cpart2) and the loss sums (lpart, kLossPart
+// columns). The weights are staged in LDS once per workgroup in the
+// fragment order of mlp.hpp (W2 and Wo with the permuted K, so layer
+// outputs feed the next layer's B operand from registers), plus Wo^T for
+// the output gradient; a workgroup walks chunks blockIdx.x,
+// blockIdx.x + gridDim.x, ... Eight waves (two per SIMD) hide each other's
+// matrix-core and LDS latencies.
+constexpr int kFrontWaves = 8;                // one 16-row tile per wave
+constexpr int kFrontRows = 16 * kFrontWaves;  // rows per chunk
+constexpr int kFrontThreads = 64 * kFrontWaves;
+constexpr int kFrontWo = (kH2 / 32) * 64;   // Wo fragments: [4 K-blocks][64 lanes]
+constexpr int kFrontWoT = (kH2 / 16) * 64;  // Wo^T fragments: [8 row tiles][64 lanes]
+constexpr size_t kFrontLdsW = (size_t)(kW1Frags + kW2Frags + kFrontWo + kFrontWoT) * 16;
+constexpr size_t kFrontLds = kFrontLdsW + (size_t)(kH1 + kH2 + kOut) * 4  // biases
+                             + (size_t)kFrontWaves * 16 * kPO * 4          // outputs, [wave][row][kPO]
+                             + (size_t)kFrontWaves * (2 * kPO + 4) * 4     // loss sums, [wave][..]
+                             + (size_t)kFrontWaves * kH2 * 4;              // dZ2 column sums, [wave][kH2]
+static_assert(kFrontLds <= 160 * 1024, "the fused front fits the LDS");
+
+struct FrontArgs {
+  const uint16_t* X;   // [rows][kPX] BF16 inputs
+  const uint16_t* pb;  // BF16 parameters (W1 at oW0 [256][W], W2 at oW1 [128][256], Wo at oW2 [O][128])
+  const float* p;      // FP32 parameters (biases at oB0, oB1, oB2; log_std at oLS)
+  int oW0, oB0, oW1, oB1, oW2, oB2, oLS;
+  int W, O;
+  PpoRows rows;
+  float clip, c_v, inv_b, w_stats;
+  uint16_t* H1;        // [rows][256]
+  uint16_t* H2;        // [rows][128]
+  uint16_t* G3b;       // [rows][kPO]
+  uint16_t* D2b;       // [rows][128]
+  float* cpart2;       // [chunks][128]
+  float* lpart;        // [chunks][kLossPart]
+  int nchunks;
+};
+
+__device__ __forceinline__ uint4 pack8(const uint16_t (&v)[8]) {
+  return make_uint4((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+                    (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16));
+}
+__device__ __forceinline__ uint2 bf16x4_bits(const bf16x8& v, int h) {
+  const uint32_t* u = reinterpret_cast<const uint32_t*>(&v);
+  return make_uint2(u[2 * h], u[2 * h + 1]);
+}
+
+// Sums over the 16 lanes of a DPP row (lanes 16g .. 16g + 15) of N values
+// at once, stage by stage so that no add waits on the one before it; lane
+// 16g receives the row's sums (the others partial sums in other orders).
+// update_dpp with a zero old value and bound_ctrl lets the compiler fold
+// the moves into the adds (v_add_f32 with a DPP source).
+template <int N> __device__ __forceinline__ void row16_sums(float (&v)[N]) {
+#define SG_DPP_STAGE(ctrl)                                                                            \
+  _Pragma("unroll") for (int k = 0; k < N; ++k) v[k] +=                                              \
+      __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[k]), ctrl, 0xF, 0xF, true));
+  SG_DPP_STAGE(0xB1)   // quad_perm 1,0,3,2
+  SG_DPP_STAGE(0x4E)   // quad_perm 2,3,0,1
+  SG_DPP_STAGE(0x124)  // row_ror 4
+  SG_DPP_STAGE(0x128)  // row_ror 8
+#undef SG_DPP_STAGE
+}
+
+template <int ACT>
+__global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  uint4* sW1 = reinterpret_cast<uint4*>(lds);
+  uint4* sW2 = sW1 + kW1Frags;
+  uint4* sWo = sW2 + kW2Frags;
+  uint4* sWoT = sWo + kFrontWo;
+  float* sb1 = reinterpret_cast<float*>(lds + kFrontLdsW);
+  float* sb2 = sb1 + kH1;
+  float* sbo = sb2 + kH2;
+  float* sO = sbo + kOut;
+  float* sRed = sO + kFrontWaves * 16 * kPO;
+  float* sCol = sRed + kFrontWaves * (2 * kPO + 4);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int g = lane >> 4, i = lane & 15;
+  const PpoRows& R = a.rows;
+  // the first chunk's input tile, in flight during the weight staging
+  int c = blockIdx.x;
+  uint4 xn = make_uint4(0, 0, 0, 0);
+  {
+    const int r = c * kFrontRows + 16 * wave + i;
+    if (r < R.rows) xn = *reinterpret_cast<const uint4*>(a.X + (size_t)r * kPX + 8 * g);
+  }
+  // weight images in LDS: every thread issues all of its loads before its
+  // first LDS store. W1 rows are read as BF16 pairs (W is even), W2 and Wo
+  // as the two 4-element runs of a permuted-K fragment, Wo^T element-wise
+  // (lane group 0 only: the outputs are K 0..7)
+  {
+    constexpr int NT = kFrontThreads;
+    constexpr int nW1 = kW1Frags / NT, nW2 = kW2Frags / NT, nWoT = kFrontWoT / NT;
+    static_assert(kW1Frags % NT == 0 && kW2Frags % NT == 0 && kFrontWoT % NT == 0 && kFrontWo <= NT &&
+                      kH1 <= NT, "the staging loops are exact");
+    uint32_t w1[nW1][4];
+    uint2 w2[nW2][2], wo[2];
+    uint16_t wt[nWoT][8];
+#pragma unroll
+    for (int u = 0; u < nW1; ++u) {
+      const int f = tid + NT * u, l = f & 63, row = 16 * (f >> 6) + (l & 15), k0 = 8 * (l >> 4);
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.pb + a.oW0 + (size_t)row * a.W);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w1[u][q] = k0 + 2 * q < a.W ? src[(k0 >> 1) + q] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < nW2; ++u) {
+      const int f = tid + NT * u, l = f & 63, mk = f >> 6, m = mk >> 3, kb = mk & 7;
+      const uint16_t* src = a.pb + a.oW1 + (size_t)(16 * m + (l & 15)) * kH1 + 32 * kb + 4 * (l >> 4);
+      w2[u][0] = *reinterpret_cast<const uint2*>(src);
+      w2[u][1] = *reinterpret_cast<const uint2*>(src + 16);
+    }
+    wo[0] = wo[1] = make_uint2(0, 0);
+    if (tid < kFrontWo) {
+      const int l = tid & 63, kb = tid >> 6, row = l & 15;
+      if (row < a.O) {
+        const uint16_t* src = a.pb + a.oW2 + (size_t)row * kH2 + 32 * kb + 4 * (l >> 4);
+        wo[0] = *reinterpret_cast<const uint2*>(src);
+        wo[1] = *reinterpret_cast<const uint2*>(src + 16);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < nWoT; ++u) {
+      const int f = tid + NT * u, l = f & 63, unit = 16 * (f >> 6) + (l & 15), k0 = 8 * (l >> 4);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) wt[u][q] = k0 + q < a.O ? a.pb[a.oW2 + (size_t)(k0 + q) * kH2 + unit] : 0;
+    }
+    const float b1 = tid < kH1 ? a.p[a.oB0 + tid] : 0.f;
+    const float b2 = tid < kH2 ? a.p[a.oB1 + tid] : 0.f;
+    const float bo = tid < a.O ? a.p[a.oB2 + tid] : 0.f;
+#pragma unroll
+    for (int u = 0; u < nW1; ++u) sW1[tid + NT * u] = make_uint4(w1[u][0], w1[u][1], w1[u][2], w1[u][3]);
+#pragma unroll
+    for (int u = 0; u < nW2; ++u) sW2[tid + NT * u] = make_uint4(w2[u][0].x, w2[u][0].y, w2[u][1].x, w2[u][1].y);
+    if (tid < kFrontWo) sWo[tid] = make_uint4(wo[0].x, wo[0].y, wo[1].x, wo[1].y);
+#pragma unroll
+    for (int u = 0; u < nWoT; ++u) sWoT[tid + NT * u] = pack8(wt[u]);
+    if (tid < kH1) sb1[tid] = b1;
+    if (tid < kH2) sb2[tid] = b2;
+    if (tid < kOut) sbo[tid] = bo;
+  }
+  __syncthreads();
+  const float* ls = a.p + a.oLS;
+  const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+
+  for (; c < a.nchunks; c += gridDim.x) {
+    // this wave's tile: rows rb .. rb + 15; lane 16 g + i works on row rb + i
+    const int rb = c * kFrontRows + 16 * wave, rj = rb + i;
+    const bool rv = rj < R.rows;
+    bf16x8 xb = *reinterpret_cast<const bf16x8*>(&xn);
+    // the next chunk's input tile and this chunk's loss inputs, in flight
+    // during the layers
+    {
+      const int r = rj + gridDim.x * kFrontRows;
+      xn = c + (int)gridDim.x < a.nchunks && r < R.rows ? *reinterpret_cast<const uint4*>(a.X + (size_t)r * kPX + 8 * g)
+                                                       : make_uint4(0, 0, 0, 0);
+    }
+    float xa[kAux];
+    bool ok = false;
+    if (g == 0 && rv) ok = ppo_row_inputs(R, rj, xa);
+    // layers 1 and 2: K-block kb of layer 2 is layer 1's row tiles 2kb, 2kb+1
+    f32x4 acc2[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) acc2[m] = zero4;
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      bf16x8 hb;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint4 t = sW1[(2 * kb + h) * 64 + lane];
+        const f32x4 d = mfma16x16x32(*reinterpret_cast<const bf16x8*>(&t), xb, zero4);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) hb[4 * h + r] = (__bf16)act_f<ACT>(d[r] + sb1[32 * kb + 16 * h + 4 * g + r]);
+      }
+      if (rv) {
+        uint16_t* dst = a.H1 + (size_t)rj * kH1 + 32 * kb + 4 * g;
+        *reinterpret_cast<uint2*>(dst) = bf16x4_bits(hb, 0);
+        *reinterpret_cast<uint2*>(dst + 16) = bf16x4_bits(hb, 1);
+      }
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const uint4 t = sW2[(m * 8 + kb) * 64 + lane];
+        acc2[m] = mfma16x16x32(*reinterpret_cast<const bf16x8*>(&t), hb, acc2[m]);
+      }
+    }
+    // layer 2's activations (BF16, the output layer's B operand) and act'
+    float dact[8][4];
+    bf16x8 h2b[4];
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float z = acc2[m][r] + sb2[16 * m + 4 * g + r];
+        float hv;
+        if (ACT == ACT_TANH) {
+          const float t = tanh_fast(z);
+          hv = t;
+          dact[m][r] = 1.f - t * t;
+        } else {
+          hv = elu_f(z);
+          dact[m][r] = elu_grad_f(z);
+        }
+        h2b[m >> 1][4 * (m & 1) + r] = (__bf16)hv;
+      }
+    if (rv) {
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        uint16_t* dst = a.H2 + (size_t)rj * kH2 + 32 * kb + 4 * g;
+        *reinterpret_cast<uint2*>(dst) = bf16x4_bits(h2b[kb], 0);
+        *reinterpret_cast<uint2*>(dst + 16) = bf16x4_bits(h2b[kb], 1);
+      }
+    }
+    f32x4 acco = zero4;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const uint4 t = sWo[kb * 64 + lane];
+      acco = mfma16x16x32(*reinterpret_cast<const bf16x8*>(&t), h2b[kb], acco);
+    }
+    // outputs to LDS (lane groups 0 and 1 hold outputs 0..7 of row rb + i)
+    if (g < 2) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sO[(wave * 16 + i) * kPO + 4 * g + r] = acco[r] + sbo[4 * g + r];
+    }
+    __syncthreads();
+    // the loss, one row per lane of lane group 0
+    float lpi = 0.f, lv = 0.f, kl = 0.f, cf = 0.f;
+    float gk[kPO], dl[kPO];
+#pragma unroll
+    for (int k = 0; k < kPO; ++k) { gk[k] = 0.f; dl[k] = 0.f; }
+    bf16x8 gb;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) gb[k] = (__bf16)0.f;
+    if (g == 0 && rv) {
+      if (ok) {
+        float z[kPO];
+#pragma unroll
+        for (int k = 0; k < kPO; ++k) z[k] = sO[(wave * 16 + i) * kPO + k];
+        ppo_row_loss(R.J, xa, z, ls, a.clip, a.c_v, a.inv_b, gk, dl, lpi, lv, kl, cf);
+#pragma unroll
+        for (int k = 0; k < kPO; ++k) gb[k] = (__bf16)gk[k];
+      }
+      *reinterpret_cast<uint4*>(a.G3b + (size_t)rj * kPO) = *reinterpret_cast<const uint4*>(&gb);
+    }
+    // dZ2 = (G Wo) act'(Z2): B operand = the rows' BF16 output gradients
+    // (K = outputs, held by lane group 0), A = Wo^T; column sums over the
+    // tile's 16 rows (one DPP row per lane group), then over the four waves
+    // in order
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const uint4 t = sWoT[m * 64 + lane];
+      const f32x4 d = mfma16x16x32(*reinterpret_cast<const bf16x8*>(&t), gb, zero4);
+      bf16x8 o;
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[r] = d[r] * dact[m][r];
+        o[r] = (__bf16)v[r];
+      }
+      row16_sums(v);
+      if (i == 0) *reinterpret_cast<float4*>(sCol + wave * kH2 + 16 * m + 4 * g) = make_float4(v[0], v[1], v[2], v[3]);
+      if (rv) *reinterpret_cast<uint2*>(a.D2b + (size_t)rj * kH2 + 16 * m + 4 * g) = bf16x4_bits(o, 0);
+    }
+    {
+      const float w = a.w_stats * a.inv_b;
+      constexpr int L = 2 * kPO + 4;
+      float v[L];
+#pragma unroll
+      for (int k = 0; k < kPO; ++k) { v[k] = gk[k]; v[kPO + k] = dl[k]; }
+      v[2 * kPO] = lpi * w; v[2 * kPO + 1] = lv * w; v[2 * kPO + 2] = kl * w; v[2 * kPO + 3] = cf * w;
+      row16_sums(v);
+      if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < L; ++k) sRed[wave * L + k] = v[k];
+      }
+    }
+    __syncthreads();
+    if (tid < kH2) {
+      float v = 0.f;
+#pragma unroll
+      for (int w = 0; w < kFrontWaves; ++w) v += sCol[w * kH2 + tid];
+      a.cpart2[(size_t)c * kH2 + tid] = v;
+    }
+    if (tid >= kH2 && tid < kH2 + kLossPart) {
+      // column cc of the row: output cc, log_std cc - O, zero, or statistic
+      const int cc = tid - kH2, O = a.O;
+      const int src = cc < O ? cc : (cc < O + R.J ? kPO + cc - O : (cc >= 16 ? 2 * kPO + cc - 16 : -1));
+      constexpr int L = 2 * kPO + 4;
+      float v = 0.f;
+#pragma unroll
+      for (int w = 0; w < kFrontWaves; ++w) v += src < 0 ? 0.f : sRed[w * L + src];
+      a.lpart[(size_t)c * kLossPart + cc] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Rows per block of the loss sums: the fused front sums kFrontRows-row
+// chunks, k_ppo_loss 256-row blocks.
+static int loss_blocks(const sg_ppo* o, int rows) {
+  return o->h3 ? (rows + 255) / 256 : (rows + kFrontRows - 1) / kFrontRows;
+}
+
+// One workgroup per compute unit at most (104 KB of LDS each), walking the
+// chunks.
+template <int ACT> static hipError_t launch_front(hipStream_t st, const FrontArgs& a, int n_cu) {
+  hipError_t e = lds_limit((const void*)k_ppo_front<ACT>, kFrontLds);
+  if (e != hipSuccess) return e;
+  const int grid = a.nchunks < n_cu ? a.nchunks : n_cu;
+  k_ppo_front<ACT><<<grid, kFrontThreads, kFrontLds, st>>>(a);
+  return hipGetLastError();
 }
 
 // Entropy bonus on the log_std gradient, then per-block sums of squares
@@ -578,68 +915,74 @@ static hipError_t minibatch_grad_t(sg_ppo* o, const PpoRows& rows, const sg_ppo_
   sg_ctx* c = o->ctx;
   hipStream_t st = c->stream;
   const int B = rows.rows, W = o->W, O = o->O, J = o->J, h3 = o->h3, L = o->nl - 1;  // L: output layer
-  const int gb = (B + 255) / 256;
+  const int gb = (B + 255) / 256, lb = loss_blocks(o, B);
   // every entry of o->g is written below (weight and bias sums), so no clear
   if (!gathered) k_ppo_gather<<<gb, 256, 0, st>>>(rows, o->X);
-  GemmArgs f{};
-  // layer 1: Z1 = X W1^T + b1, H1 = act(Z1)
-  f.M = B; f.N = kH1; f.K = W; f.A = o->X; f.lda = kPX; f.B = o->pb + o->oW[0]; f.ldb = W;
-  f.C = nullptr; f.ldc = kH1; f.bias = o->p + o->oB[0]; f.Cb = o->H1;
-  launch_gemm<EPI_FWD_HIDDEN, false, true, ACT>(st, f);
-  // layer 2 (pre-activations kept for the backward pass)
-  f.N = kH2; f.K = kH1; f.A = o->H1; f.lda = kH1; f.B = o->pb + o->oW[1]; f.ldb = kH1;
-  f.C = o->Z2; f.ldc = kH2; f.bias = o->p + o->oB[1]; f.Cb = o->H2;
-  launch_gemm<EPI_FWD_HIDDEN, false, true, ACT>(st, f);
-  const uint16_t* Hlast = o->H2;
-  int hl = kH2;
-  if (h3) {
+  SumJob jobs[8];
+  int nj = 0;
+  const int rb = (B + 63) / 64;
+  GemmArgs d{};
+  if (!h3) {
+    // forward, loss and the gradient down to dZ2 in one launch
+    FrontArgs fa;
+    fa.X = o->X; fa.pb = o->pb; fa.p = o->p;
+    fa.oW0 = o->oW[0]; fa.oB0 = o->oB[0]; fa.oW1 = o->oW[1]; fa.oB1 = o->oB[1];
+    fa.oW2 = o->oW[L]; fa.oB2 = o->oB[L]; fa.oLS = o->oLS;
+    fa.W = W; fa.O = O; fa.rows = rows;
+    fa.clip = cfg->clip; fa.c_v = cfg->value_coef; fa.inv_b = 1.f / (float)B; fa.w_stats = w_stats;
+    fa.H1 = o->H1; fa.H2 = o->H2; fa.G3b = o->G3b; fa.D2b = o->D2b; fa.cpart2 = o->cpart2; fa.lpart = o->lpart;
+    fa.nchunks = lb;
+    const hipError_t e = launch_front<ACT>(st, fa, c->n_cu);
+    if (e != hipSuccess) return e;
+    jobs[nj++] = weight_grad(o, st, 3, O, kH2, B, o->G3b, kPO, o->H2, kH2, o->g + o->oW[L], kH2);
+    jobs[nj++] = partial_rows(o->lpart, lb, O + J, kLossPart, o->g + o->oB[L]);
+    jobs[nj++] = weight_grad(o, st, 1, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->oW[1], kH1);
+    jobs[nj++] = partial_rows(o->cpart2, lb, kH2, kH2, o->g + o->oB[1]);
+  } else {
+    GemmArgs f{};
+    // layer 1: Z1 = X W1^T + b1, H1 = act(Z1)
+    f.M = B; f.N = kH1; f.K = W; f.A = o->X; f.lda = kPX; f.B = o->pb + o->oW[0]; f.ldb = W;
+    f.C = nullptr; f.ldc = kH1; f.bias = o->p + o->oB[0]; f.Cb = o->H1;
+    launch_gemm<EPI_FWD_HIDDEN, false, true, ACT>(st, f);
+    // layer 2 (pre-activations kept for the backward pass)
+    f.N = kH2; f.K = kH1; f.A = o->H1; f.lda = kH1; f.B = o->pb + o->oW[1]; f.ldb = kH1;
+    f.C = o->Z2; f.ldc = kH2; f.bias = o->p + o->oB[1]; f.Cb = o->H2;
+    launch_gemm<EPI_FWD_HIDDEN, false, true, ACT>(st, f);
+    // layer 3
     f.N = h3; f.K = kH2; f.A = o->H2; f.lda = kH2; f.B = o->pb + o->oW[2]; f.ldb = kH2;
     f.C = o->Z3h; f.ldc = h3; f.bias = o->p + o->oB[2]; f.Cb = o->H3;
     launch_gemm<EPI_FWD_HIDDEN, false, true, ACT>(st, f);
-    Hlast = o->H3;
-    hl = h3;
-  }
-  // output layer (linear): [mu | V]
-  f.N = O; f.K = hl; f.A = Hlast; f.lda = hl; f.B = o->pb + o->oW[L]; f.ldb = hl;
-  f.C = o->Z3; f.ldc = kPO; f.bias = o->p + o->oB[L]; f.Cb = nullptr;
-  launch_gemm<EPI_FWD_OUT, false, true, ACT>(st, f);
-  PpoLossArgs la;
-  la.rows = rows; la.Z3 = o->Z3; la.ls = o->p + o->oLS; la.clip = cfg->clip; la.c_v = cfg->value_coef;
-  la.inv_b = 1.f / (float)B; la.w_stats = w_stats; la.G3b = o->G3b; la.part = o->lpart;
-  k_ppo_loss<<<gb, 256, 0, st>>>(la);
-  // weight gradients as split-K partials; their sums and the bias sums run
-  // in one launch at the end. Output biases and log_std are adjacent in the
-  // flat vector (oLS = oB[L] + O).
-  SumJob jobs[8];
-  int nj = 0;
-  jobs[nj++] = weight_grad(o, st, 3, O, hl, B, o->G3b, kPO, Hlast, hl, o->g + o->oW[L], hl);
-  jobs[nj++] = partial_rows(o->lpart, gb, O + J, kLossPart, o->g + o->oB[L]);
-  const int rb = (B + 63) / 64;
-  GemmArgs d{};
-  // the gradient entering the last hidden layer's pre-activations
-  const uint16_t* Gin = o->G3b;
-  int gin_ld = kPO, gin_k = O;
-  const uint16_t* Wnext = o->pb + o->oW[L];
-  if (h3) {
+    // output layer (linear): [mu | V]
+    f.N = O; f.K = h3; f.A = o->H3; f.lda = h3; f.B = o->pb + o->oW[L]; f.ldb = h3;
+    f.C = o->Z3; f.ldc = kPO; f.bias = o->p + o->oB[L]; f.Cb = nullptr;
+    launch_gemm<EPI_FWD_OUT, false, true, ACT>(st, f);
+    PpoLossArgs la;
+    la.rows = rows; la.Z3 = o->Z3; la.ls = o->p + o->oLS; la.clip = cfg->clip; la.c_v = cfg->value_coef;
+    la.inv_b = 1.f / (float)B; la.w_stats = w_stats; la.G3b = o->G3b; la.part = o->lpart;
+    k_ppo_loss<<<gb, 256, 0, st>>>(la);
+    // weight gradients as split-K partials; their sums and the bias sums run
+    // in one launch at the end. Output biases and log_std are adjacent in the
+    // flat vector (oLS = oB[L] + O).
+    jobs[nj++] = weight_grad(o, st, 3, O, h3, B, o->G3b, kPO, o->H3, h3, o->g + o->oW[L], h3);
+    jobs[nj++] = partial_rows(o->lpart, lb, O + J, kLossPart, o->g + o->oB[L]);
     // dZ3 = (G Wo) * act'(Z3), with the column sums of dZ3 (hidden-3 bias)
-    d.M = B; d.N = h3; d.K = O; d.A = o->G3b; d.lda = kPO; d.B = Wnext; d.ldb = h3;
+    d.M = B; d.N = h3; d.K = O; d.A = o->G3b; d.lda = kPO; d.B = o->pb + o->oW[L]; d.ldb = h3;
     d.C = nullptr; d.ldc = h3; d.Cb = o->D3b; d.Zp = o->Z3h; d.colpart = o->cpart3;
     launch_gemm<EPI_BWD_DX, false, false, ACT>(st, d);
     jobs[nj++] = weight_grad(o, st, 2, h3, kH2, B, o->D3b, h3, o->H2, kH2, o->g + o->oW[2], kH2);
     jobs[nj++] = partial_rows(o->cpart3, rb, h3, h3, o->g + o->oB[2]);
-    Gin = o->D3b; gin_ld = h3; gin_k = h3;
-    Wnext = o->pb + o->oW[2];
+    // dZ2 = (dZ3 W3) * act'(Z2), with the column sums of dZ2 (hidden-2 bias)
+    d = GemmArgs{};
+    d.M = B; d.N = kH2; d.K = h3; d.A = o->D3b; d.lda = h3; d.B = o->pb + o->oW[2]; d.ldb = kH2;
+    d.C = nullptr; d.ldc = kH2; d.Cb = o->D2b; d.Zp = o->Z2; d.colpart = o->cpart2;
+    launch_gemm<EPI_BWD_DX, false, false, ACT>(st, d);
+    jobs[nj++] = weight_grad(o, st, 1, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->oW[1], kH1);
+    jobs[nj++] = partial_rows(o->cpart2, rb, kH2, kH2, o->g + o->oB[1]);
   }
-  // dZ2 = (G_next W_next) * act'(Z2), with the column sums of dZ2 (hidden-2 bias)
-  d = GemmArgs{};
-  d.M = B; d.N = kH2; d.K = gin_k; d.A = Gin; d.lda = gin_ld; d.B = Wnext; d.ldb = kH2;
-  d.C = nullptr; d.ldc = kH2; d.Cb = o->D2b; d.Zp = o->Z2; d.colpart = o->cpart2;
-  launch_gemm<EPI_BWD_DX, false, false, ACT>(st, d);
-  jobs[nj++] = weight_grad(o, st, 1, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->oW[1], kH1);
-  jobs[nj++] = partial_rows(o->cpart2, rb, kH2, kH2, o->g + o->oB[1]);
   // dZ1 = (dZ2 W2) * act'(Z1), with the column sums of dZ1 (hidden-1 bias);
   // Z1 (W inputs) is recomputed in the epilogue rather than stored
-  d.N = kH1; d.K = kH2; d.A = o->D2b; d.lda = kH2; d.B = o->pb + o->oW[1]; d.ldb = kH1;
+  d = GemmArgs{};
+  d.M = B; d.N = kH1; d.K = kH2; d.A = o->D2b; d.lda = kH2; d.B = o->pb + o->oW[1]; d.ldb = kH1;
   d.C = nullptr; d.ldc = kH1; d.Cb = o->D1b; d.colpart = o->cpart;
   d.Zp = nullptr;
   d.RA = o->X; d.rlda = kPX; d.RB = o->pb + o->oW[0]; d.rldb = W; d.RK = W; d.rbias = o->p + o->oB[0];
@@ -650,7 +993,7 @@ static hipError_t minibatch_grad_t(sg_ppo* o, const PpoRows& rows, const sg_ppo_
   if (finish) {
     const int nb = (o->P + kGnormChunk - 1) / kGnormChunk;
     k_gnorm_part<<<nb, 256, 0, st>>>(o->g, o->P, o->oLS, J, cfg->entropy_coef, o->gpart);
-    k_ppo_finish<<<1, 256, 0, st>>>(o->gpart, nb, o->lpart, gb, o->p + o->oLS, J, o->scal, stats, w_stats);
+    k_ppo_finish<<<1, 256, 0, st>>>(o->gpart, nb, o->lpart, lb, o->p + o->oLS, J, o->scal, stats, w_stats);
   }
   return hipGetLastError();
 }
@@ -780,20 +1123,20 @@ sg_status sg_ppo_create(sg_ctx* c, const sg_policy_arch* arch, const float* para
   if (e == hipSuccess) e = palloc(o, &o->Xall, R * kPX);
   if (e == hipSuccess) e = palloc(o, &o->Aux, R * kAux);
   if (e == hipSuccess) e = palloc(o, &o->H1, R * kH1);
-  if (e == hipSuccess) e = palloc(o, &o->Z2, R * kH2);
+  if (e == hipSuccess && h3) e = palloc(o, &o->Z2, R * kH2);
   if (e == hipSuccess) e = palloc(o, &o->H2, R * kH2);
   if (e == hipSuccess && h3) e = palloc(o, &o->Z3h, R * h3);
   if (e == hipSuccess && h3) e = palloc(o, &o->H3, R * h3);
   if (e == hipSuccess && h3) e = palloc(o, &o->D3b, R * h3);
   if (e == hipSuccess && h3) e = palloc(o, &o->cpart3, ((R + 63) / 64) * (size_t)h3);
-  if (e == hipSuccess) e = palloc(o, &o->Z3, R * kPO);
+  if (e == hipSuccess && h3) e = palloc(o, &o->Z3, R * kPO);
   if (e == hipSuccess) e = palloc(o, &o->G3b, R * kPO);
   if (e == hipSuccess) e = palloc(o, &o->D2b, R * kH2);
   if (e == hipSuccess) e = palloc(o, &o->D1b, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->ws, o->ws_floats);
   if (e == hipSuccess) e = palloc(o, &o->cpart, ((R + 63) / 64) * (size_t)kH1);
   if (e == hipSuccess) e = palloc(o, &o->cpart2, ((R + 63) / 64) * (size_t)kH2);
-  if (e == hipSuccess) e = palloc(o, &o->lpart, ((R + 255) / 256) * (size_t)kLossPart);
+  if (e == hipSuccess) e = palloc(o, &o->lpart, ((R + 63) / 64) * (size_t)kLossPart);
   if (e == hipSuccess) e = palloc(o, &o->gpart, (size_t)kGnormBlocks);
   if (e == hipSuccess && (o->P + kGnormChunk - 1) / kGnormChunk > kGnormBlocks) e = hipErrorInvalidValue;
   if (e == hipSuccess && !c->w_bf16) e = hipMalloc((void**)&c->w_bf16, (size_t)kWFragsMax * 16);
@@ -904,7 +1247,7 @@ sg_status sg_ppo_update(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const sg
       na.c_e = cfg->entropy_coef; na.max_norm = cfg->max_grad_norm; na.lr = cfg->lr;
       na.b1 = cfg->beta1; na.b2 = cfg->beta2; na.eps = cfg->adam_eps;
       na.tstep = o->tstep; na.ttick = o->ttick;
-      na.lpart = o->lpart; na.lb = (mb + 255) / 256; na.stats = stats; na.w = w;
+      na.lpart = o->lpart; na.lb = loss_blocks(o, mb); na.stats = stats; na.w = w;
       na.nadam = (o->P + kNormAdamThreads - 1) / kNormAdamThreads;
       const bool last = k + 1 == cfg->minibatches && ep + 1 == cfg->epochs;
       na.next = last ? PpoRows{} : rows_at(k + 1 < cfg->minibatches ? ep : ep + 1, (k + 1) % cfg->minibatches);
