@@ -11,11 +11,9 @@
 //   k_ppo_gather   the minibatch's rows -> X [B][32] (in sg_ppo_update
 //                  only for the first minibatch: later ones are gathered
 //                  by extra blocks of the previous k_ppo_norm_adam launch)
-//   k_ppo_front    (256-128 network) the forward pass, the loss and the
-//                  gradient down to hidden layer 2's pre-activations in one
-//                  launch on the matrix cores, activations in registers;
-//                  the 256-128-64 network runs the same steps as GEMMs
-//                  (nn.hpp) and k_ppo_loss
+//   k_ppo_front    the forward pass, the loss and the gradient down to
+//                  hidden layer 2's pre-activations in one launch on the
+//                  matrix cores, activations in registers
 //   backward       data gradients as GEMMs with the act' epilogue, which
 //                  also emits per-block column sums (the hidden biases'
 //                  gradients; layer 1's pre-activations are recomputed
@@ -58,21 +56,18 @@ struct sg_ppo {
   uint16_t* Xall = nullptr;  // [max_samples][32] sample-major BF16 observations
   float* Aux = nullptr;      // [max_samples][kAux] sample-major act, logp, adv, value, return
   uint16_t* H1 = nullptr;    // [rows][256] (layer 1's pre-activations are recomputed, not kept)
-  float* Z2 = nullptr;       // [rows][128] (h3 > 0; the fused front keeps them in registers)
   uint16_t* H2 = nullptr;
-  float* Z3h = nullptr;      // [rows][h3] third hidden layer's pre-activations (h3 > 0)
   uint16_t* H3 = nullptr;    // [rows][h3]
   uint16_t* D3b = nullptr;   // [rows][h3]
-  float* cpart3 = nullptr;   // per-block column sums of dZ3 [rows / 64][h3]
-  float* Z3 = nullptr;       // [rows][8] outputs (h3 > 0)
+  float* cpart3 = nullptr;   // per-chunk column sums of dZ3 [loss_blocks(rows)][h3]
   uint16_t* G3b = nullptr;   // [rows][8] dL/d(outputs)
   uint16_t* D2b = nullptr;   // [rows][128]
   uint16_t* D1b = nullptr;   // [rows][256]
   float* ws = nullptr;       // split-K partials, one kWeightGradWs region per layer
   size_t ws_floats = 0;
   float* cpart = nullptr;    // per-block column sums of dZ1 [rows / 64][256]
-  float* cpart2 = nullptr;   // per-block column sums of dZ2 [blocks of 64 or kFrontRows rows][128]
-  float* lpart = nullptr;    // loss block sums [loss_blocks(rows)][kLossPart]
+  float* cpart2 = nullptr;   // per-chunk column sums of dZ2 [loss_blocks(rows)][128]
+  float* lpart = nullptr;    // per-chunk loss sums [loss_blocks(rows)][kLossPart]
   double* gpart = nullptr;   // block sums [kGnormBlocks]: advantage statistics, then gradient norm
   std::vector<void*> allocs;
 };
@@ -84,8 +79,9 @@ constexpr int kPX = 32;   // padded input width
 // normalised advantage, old value and return at kAux - 4 .. kAux - 1.
 constexpr int kAux = 12;
 constexpr int kPO = 8;    // padded output width (J + 1 <= 8)
-// k_ppo_loss block row: dL/d(outputs) sums (O columns) then dL/dlog_std
-// sums (J columns), zero to column 16, then the four weighted loss sums.
+// Loss-sum row (one per chunk of k_ppo_front): dL/d(outputs) sums (O
+// columns) then dL/dlog_std sums (J columns), zero to column 16, then the
+// four weighted loss sums.
 constexpr int kLossPart = 20;
 constexpr int kGnormChunk = 1024;  // gradient entries per k_gnorm_part block
 constexpr int kGnormBlocks = 128;  // capacity of the partial-sum buffer (norm; advantage statistics)
@@ -207,17 +203,6 @@ __global__ void __launch_bounds__(256) k_adv_norm(const float* __restrict__ adv,
   if (i < n) an[i] = (adv[i] - m) / (sd + 1e-8f);
 }
 
-struct PpoLossArgs {
-  PpoRows rows;
-  const float* Z3;      // [rows][8] network outputs (mu | V)
-  const float* ls;      // log_std [J]
-  float clip, c_v;
-  float inv_b;          // 1 / rows
-  float w_stats;        // weight of this minibatch in the statistics
-  uint16_t* G3b;        // [rows][8] BF16 dL/d(outputs)
-  float* part;          // [gridDim.x][kLossPart] block sums (see kLossPart)
-};
-
 // One minibatch row with loss inputs x (action, old log-probability,
 // normalised advantage, old value, return): log pi(a) under the outputs z
 // (mu | V), ratio, clipped objectives; g receives dL/d(outputs), dl the
@@ -273,101 +258,65 @@ __device__ __forceinline__ void ppo_row_loss(int J, const float (&x)[kAux], cons
   g[J] = c_v * dV * inv_b;
 }
 
-// Per row: the loss of ppo_row_loss on the output rows Z3; BF16 dL/d(outputs)
-// and per-block sums.
-__global__ void __launch_bounds__(256) k_ppo_loss(PpoLossArgs a) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  const PpoRows& R = a.rows;
-  float lpi = 0.f, lv = 0.f, kl = 0.f, cf = 0.f;
-  float g[kPO], dl[kPO];
-#pragma unroll
-  for (int k = 0; k < kPO; ++k) { g[k] = 0.f; dl[k] = 0.f; }
-  if (r < R.rows) {
-    float x[kAux];
-    if (ppo_row_inputs(R, r, x))
-      ppo_row_loss(R.J, x, a.Z3 + (size_t)r * kPO, a.ls, a.clip, a.c_v, a.inv_b, g, dl, lpi, lv, kl, cf);
-#pragma unroll
-    for (int k = 0; k < kPO; ++k) a.G3b[(size_t)r * kPO + k] = bf16_bits(g[k]);
-  }
-  {
-    // block sums of the FP32 gradients and of the weighted loss terms, in a
-    // fixed order (no atomics: the statistics are summed by k_ppo_finish)
-    const float w = a.w_stats * a.inv_b;
-    float v4[4] = {lpi * w, lv * w, kl * w, cf * w};
-    __shared__ float red[4][2 * kPO + 4];
-#pragma unroll
-    for (int k = 0; k < kPO; ++k)
-      for (int o = 32; o > 0; o >>= 1) {
-        g[k] += __shfl_xor(g[k], o, 64);
-        dl[k] += __shfl_xor(dl[k], o, 64);
-      }
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      for (int o = 32; o > 0; o >>= 1) v4[k] += __shfl_xor(v4[k], o, 64);
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-      for (int k = 0; k < kPO; ++k) {
-        red[threadIdx.x >> 6][k] = g[k];
-        red[threadIdx.x >> 6][kPO + k] = dl[k];
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) red[threadIdx.x >> 6][2 * kPO + k] = v4[k];
-    }
-    __syncthreads();
-    const int c = threadIdx.x, O = R.J + 1;
-    if (c < kLossPart) {
-      // column c of the row: output c, log_std c - O, zero, or statistic
-      const int src = c < O ? c : (c < O + R.J ? kPO + c - O : (c >= 16 ? 2 * kPO + c - 16 : -1));
-      a.part[(size_t)blockIdx.x * kLossPart + c] =
-          src < 0 ? 0.f : (red[0][src] + red[1][src]) + (red[2][src] + red[3][src]);
-    }
-  }
-}
-
-// Fused front of a minibatch for the two-hidden-layer network (256-128,
-// J + 1 outputs): per chunk of kFrontRows rows (one 16-row tile per wave)
-// layer 1, layer 2 and the output layer on the matrix cores, the loss of
-// ppo_row_loss, and the gradient through the output layer and hidden layer
-// 2's activation -- the work of the three forward GEMMs, k_ppo_loss and the
-// first data-gradient GEMM, with the same arithmetic per element: each
-// layer's z = (sum over K) + bias and act(z) rounded to BF16 as in the GEMM
-// epilogues, the outputs' gradient rounded to BF16 before it meets the
-// output weights, dZ2 = (G Wo) act'(Z2) from the FP32 pre-activations.
-// Within a 32-wide K block the matrix cores sum in their own order, so
-// results agree with the GEMM path to FP32 rounding, not bit for bit.
-// Writes H1, H2 (the weight gradients' operands), G3b, D2b, and per chunk
-// the column sums of dZ2 (cpart2) and the loss sums (lpart, kLossPart
-// columns). The weights are staged in LDS once per workgroup in the
-// fragment order of mlp.hpp (W2 and Wo with the permuted K, so layer
-// outputs feed the next layer's B operand from registers), plus Wo^T for
-// the output gradient; a workgroup walks chunks blockIdx.x,
-// blockIdx.x + gridDim.x, ... Eight waves (two per SIMD) hide each other's
+// Fused front of a minibatch: per chunk of kFrontRows rows (one 16-row
+// tile per wave) the hidden layers (256, 128, and H3 = 64 for the paper's
+// Table II network) and the output layer on the matrix cores, the loss of
+// ppo_row_loss, and the gradient back through the output layer down to
+// hidden layer 2's pre-activations (through hidden layer 3 when there is
+// one) -- the work of the forward GEMMs, a per-row loss kernel and the
+// data-gradient GEMMs above hidden layer 1, with the same arithmetic per
+// element: each layer's z = (sum over K) + bias and act(z) rounded to BF16
+// as in the GEMM epilogues, the outputs' gradient rounded to BF16 before it
+// meets the output weights, dZ = (G_next W_next) act'(Z) from the FP32
+// pre-activations, rounded to BF16 for the next product. Within a 32-wide
+// K block the matrix cores sum in their own order, so results agree with a
+// GEMM formulation to FP32 rounding, not bit for bit. Writes H1, H2 (, H3)
+// (the weight gradients' operands), G3b, D2b (, D3b), and per chunk the
+// column sums of dZ2 (, dZ3) (cpart2, cpart3) and the loss sums (lpart,
+// kLossPart columns). The weights are staged in LDS once per workgroup in
+// the fragment order of mlp.hpp (the K of every layer above the first
+// permuted, so a layer's result tile is the next layer's B operand straight
+// from registers), plus the transposed output layer (and hidden layer 3)
+// for the backward products, whose B operands are gradient tiles in the
+// same register layout. A workgroup walks chunks blockIdx.x,
+// blockIdx.x + gridDim.x, ...; eight waves (two per SIMD) hide each other's
 // matrix-core and LDS latencies.
 constexpr int kFrontWaves = 8;                // one 16-row tile per wave
 constexpr int kFrontRows = 16 * kFrontWaves;  // rows per chunk
 constexpr int kFrontThreads = 64 * kFrontWaves;
-constexpr int kFrontWo = (kH2 / 32) * 64;   // Wo fragments: [4 K-blocks][64 lanes]
-constexpr int kFrontWoT = (kH2 / 16) * 64;  // Wo^T fragments: [8 row tiles][64 lanes]
-constexpr size_t kFrontLdsW = (size_t)(kW1Frags + kW2Frags + kFrontWo + kFrontWoT) * 16;
-constexpr size_t kFrontLds = kFrontLdsW + (size_t)(kH1 + kH2 + kOut) * 4  // biases
-                             + (size_t)kFrontWaves * 16 * kPO * 4          // outputs, [wave][row][kPO]
-                             + (size_t)kFrontWaves * (2 * kPO + 4) * 4     // loss sums, [wave][..]
-                             + (size_t)kFrontWaves * kH2 * 4;              // dZ2 column sums, [wave][kH2]
-static_assert(kFrontLds <= 160 * 1024, "the fused front fits the LDS");
+template <int H3> struct FrontShape {
+  static constexpr int kKo = H3 ? H3 : kH2;              // the output layer's K
+  static constexpr int kW3 = (H3 / 16) * (kH2 / 32) * 64;  // W3 [H3/16 row tiles][4 K-blocks][64 lanes]
+  static constexpr int kWo = (kKo / 32) * 64;              // Wo [K-blocks][64 lanes]
+  static constexpr int kWoT = (kKo / 16) * 64;             // Wo^T [row tiles of the last hidden layer][64 lanes]
+  static constexpr int kW3T = (kH2 / 16) * (H3 / 32) * 64; // W3^T [8 row tiles][H3/32 K-blocks][64 lanes]
+  static constexpr int kFrags = kW1Frags + kW2Frags + kW3 + kWo + kWoT + kW3T;
+  static constexpr int kBias = kH1 + kH2 + H3 + kOut;
+  static constexpr int kCols = kH2 + H3;                   // column sums per wave (dZ2 | dZ3)
+  static constexpr size_t kLds = (size_t)kFrags * 16 + (size_t)kBias * 4 +
+                                 (size_t)kFrontWaves * 16 * kPO * 4 +        // outputs, [wave][row][kPO]
+                                 (size_t)kFrontWaves * (2 * kPO + 4) * 4 +   // loss sums, [wave][..]
+                                 (size_t)kFrontWaves * kCols * 4;            // column sums, [wave][kCols]
+};
+static_assert(FrontShape<0>::kLds <= 160 * 1024 && FrontShape<64>::kLds <= 160 * 1024, "the fused front fits the LDS");
 
 struct FrontArgs {
   const uint16_t* X;   // [rows][kPX] BF16 inputs
-  const uint16_t* pb;  // BF16 parameters (W1 at oW0 [256][W], W2 at oW1 [128][256], Wo at oW2 [O][128])
-  const float* p;      // FP32 parameters (biases at oB0, oB1, oB2; log_std at oLS)
-  int oW0, oB0, oW1, oB1, oW2, oB2, oLS;
+  const uint16_t* pb;  // BF16 parameters: W1 at oW[0] [256][W], W2 at oW[1] [128][256],
+                       // W3 at oW[2] [H3][128], Wo at oWo [O][Ko]
+  const float* p;      // FP32 parameters (biases at oB[], oBo; log_std at oLS)
+  int oW[3], oB[3], oWo, oBo, oLS;
   int W, O;
   PpoRows rows;
   float clip, c_v, inv_b, w_stats;
   uint16_t* H1;        // [rows][256]
   uint16_t* H2;        // [rows][128]
+  uint16_t* H3;        // [rows][H3]
   uint16_t* G3b;       // [rows][kPO]
   uint16_t* D2b;       // [rows][128]
+  uint16_t* D3b;       // [rows][H3]
   float* cpart2;       // [chunks][128]
+  float* cpart3;       // [chunks][H3]
   float* lpart;        // [chunks][kLossPart]
   int nchunks;
 };
@@ -379,6 +328,10 @@ __device__ __forceinline__ uint4 pack8(const uint16_t (&v)[8]) {
 __device__ __forceinline__ uint2 bf16x4_bits(const bf16x8& v, int h) {
   const uint32_t* u = reinterpret_cast<const uint32_t*>(&v);
   return make_uint2(u[2 * h], u[2 * h + 1]);
+}
+__device__ __forceinline__ bf16x8 frag(const uint4* s, int i) {
+  const uint4 t = s[i];
+  return *reinterpret_cast<const bf16x8*>(&t);
 }
 
 // Sums over the 16 lanes of a DPP row (lanes 16g .. 16g + 15) of N values
@@ -397,16 +350,48 @@ template <int N> __device__ __forceinline__ void row16_sums(float (&v)[N]) {
 #undef SG_DPP_STAGE
 }
 
-template <int ACT>
+// Fragment f of a permuted-K image of a row-major [rows][K] BF16 matrix:
+// [row tiles][K / 32 K-blocks][64 lanes], lane 16 g + i holding row
+// 16 t + i and K 32 kb + {4g .. 4g + 3, 16 + 4g .. 16 + 4g + 3} (two
+// 8-byte runs); rows >= nrows are zero.
+template <int K>
+__device__ __forceinline__ void permk_load(const uint16_t* __restrict__ w, int f, int nrows, uint2 (&v)[2]) {
+  const int l = f & 63, tk = f >> 6, t = tk / (K / 32), kb = tk % (K / 32), row = 16 * t + (l & 15);
+  v[0] = v[1] = make_uint2(0, 0);
+  if (row < nrows) {
+    const uint16_t* src = w + (size_t)row * K + 32 * kb + 4 * (l >> 4);
+    v[0] = *reinterpret_cast<const uint2*>(src);
+    v[1] = *reinterpret_cast<const uint2*>(src + 16);
+  }
+}
+
+// Per-element activation, its derivative from the FP32 pre-activation z
+template <int ACT> __device__ __forceinline__ float act_and_grad(float z, float& d) {
+  if (ACT == ACT_TANH) {
+    const float t = tanh_fast(z);
+    d = 1.f - t * t;
+    return t;
+  }
+  d = elu_grad_f(z);
+  return elu_f(z);
+}
+
+template <int ACT, int H3>
 __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
+  using S = FrontShape<H3>;
+  constexpr int NT = kFrontThreads;
+  constexpr int KO = S::kKo;
   extern __shared__ __align__(16) unsigned char lds[];
   uint4* sW1 = reinterpret_cast<uint4*>(lds);
   uint4* sW2 = sW1 + kW1Frags;
-  uint4* sWo = sW2 + kW2Frags;
-  uint4* sWoT = sWo + kFrontWo;
-  float* sb1 = reinterpret_cast<float*>(lds + kFrontLdsW);
+  uint4* sW3 = sW2 + kW2Frags;
+  uint4* sWo = sW3 + S::kW3;
+  uint4* sWoT = sWo + S::kWo;
+  uint4* sW3T = sWoT + S::kWoT;
+  float* sb1 = reinterpret_cast<float*>(lds + (size_t)S::kFrags * 16);
   float* sb2 = sb1 + kH1;
-  float* sbo = sb2 + kH2;
+  float* sb3 = sb2 + kH2;
+  float* sbo = sb3 + H3;
   float* sO = sbo + kOut;
   float* sRed = sO + kFrontWaves * 16 * kPO;
   float* sCol = sRed + kFrontWaves * (2 * kPO + 4);
@@ -421,58 +406,71 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
     if (r < R.rows) xn = *reinterpret_cast<const uint4*>(a.X + (size_t)r * kPX + 8 * g);
   }
   // weight images in LDS: every thread issues all of its loads before its
-  // first LDS store. W1 rows are read as BF16 pairs (W is even), W2 and Wo
-  // as the two 4-element runs of a permuted-K fragment, Wo^T element-wise
-  // (lane group 0 only: the outputs are K 0..7)
+  // first LDS store. W1 rows are read as BF16 pairs (W is even), the
+  // permuted-K images as two 4-element runs per fragment, the transposed
+  // images element-wise
   {
-    constexpr int NT = kFrontThreads;
-    constexpr int nW1 = kW1Frags / NT, nW2 = kW2Frags / NT, nWoT = kFrontWoT / NT;
-    static_assert(kW1Frags % NT == 0 && kW2Frags % NT == 0 && kFrontWoT % NT == 0 && kFrontWo <= NT &&
-                      kH1 <= NT, "the staging loops are exact");
+    constexpr int nW1 = kW1Frags / NT, nW2 = kW2Frags / NT, nW3 = S::kW3 / NT, nWoT = (S::kWoT + NT - 1) / NT,
+                  nW3T = S::kW3T / NT, KB3 = H3 ? H3 / 32 : 1;
+    static_assert(kW1Frags % NT == 0 && kW2Frags % NT == 0 && S::kW3 % NT == 0 && S::kW3T % NT == 0 &&
+                      S::kWo <= NT && kH1 <= NT,
+                  "the staging loops are exact");
     uint32_t w1[nW1][4];
-    uint2 w2[nW2][2], wo[2];
-    uint16_t wt[nWoT][8];
+    uint2 w2[nW2][2], w3[nW3 ? nW3 : 1][2], wo[2];
+    uint16_t wt[nWoT][8], w3t[nW3T ? nW3T : 1][8];  // (w3 and w3t unused without a third layer)
 #pragma unroll
     for (int u = 0; u < nW1; ++u) {
       const int f = tid + NT * u, l = f & 63, row = 16 * (f >> 6) + (l & 15), k0 = 8 * (l >> 4);
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.pb + a.oW0 + (size_t)row * a.W);
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.pb + a.oW[0] + (size_t)row * a.W);
 #pragma unroll
       for (int q = 0; q < 4; ++q) w1[u][q] = k0 + 2 * q < a.W ? src[(k0 >> 1) + q] : 0u;
     }
 #pragma unroll
-    for (int u = 0; u < nW2; ++u) {
-      const int f = tid + NT * u, l = f & 63, mk = f >> 6, m = mk >> 3, kb = mk & 7;
-      const uint16_t* src = a.pb + a.oW1 + (size_t)(16 * m + (l & 15)) * kH1 + 32 * kb + 4 * (l >> 4);
-      w2[u][0] = *reinterpret_cast<const uint2*>(src);
-      w2[u][1] = *reinterpret_cast<const uint2*>(src + 16);
-    }
+    for (int u = 0; u < nW2; ++u) permk_load<kH1>(a.pb + a.oW[1], tid + NT * u, kH2, w2[u]);
+#pragma unroll
+    for (int u = 0; u < nW3; ++u) permk_load<kH2>(a.pb + a.oW[2], tid + NT * u, H3, w3[u]);
     wo[0] = wo[1] = make_uint2(0, 0);
-    if (tid < kFrontWo) {
-      const int l = tid & 63, kb = tid >> 6, row = l & 15;
-      if (row < a.O) {
-        const uint16_t* src = a.pb + a.oW2 + (size_t)row * kH2 + 32 * kb + 4 * (l >> 4);
-        wo[0] = *reinterpret_cast<const uint2*>(src);
-        wo[1] = *reinterpret_cast<const uint2*>(src + 16);
-      }
-    }
+    if (tid < S::kWo) permk_load<KO>(a.pb + a.oWo, tid, a.O, wo);
 #pragma unroll
     for (int u = 0; u < nWoT; ++u) {
+      // row tile of Wo^T (units of the last hidden layer), K = the outputs
+      // in natural order (lane group 0 holds outputs 0..7, the others zero)
       const int f = tid + NT * u, l = f & 63, unit = 16 * (f >> 6) + (l & 15), k0 = 8 * (l >> 4);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) wt[u][q] = k0 + q < a.O ? a.pb[a.oW2 + (size_t)(k0 + q) * kH2 + unit] : 0;
+      for (int q = 0; q < 8; ++q)
+        wt[u][q] = f < S::kWoT && k0 + q < a.O ? a.pb[a.oWo + (size_t)(k0 + q) * KO + unit] : 0;
     }
-    const float b1 = tid < kH1 ? a.p[a.oB0 + tid] : 0.f;
-    const float b2 = tid < kH2 ? a.p[a.oB1 + tid] : 0.f;
-    const float bo = tid < a.O ? a.p[a.oB2 + tid] : 0.f;
+#pragma unroll
+    for (int u = 0; u < nW3T; ++u) {
+      // row tile t of W3^T (units of hidden layer 2), K-block kb = hidden-3
+      // units 32 kb + the permuted K of this lane and slot
+      const int f = tid + NT * u, l = f & 63, tk = f >> 6, t = tk / KB3, kb = tk % KB3;
+      const int unit = 16 * t + (l & 15), gg = l >> 4;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = 32 * kb + (q < 4 ? 4 * gg + q : 16 + 4 * gg + (q - 4));
+        w3t[u][q] = a.pb[a.oW[2] + (size_t)k * kH2 + unit];
+      }
+    }
+    const float b1 = tid < kH1 ? a.p[a.oB[0] + tid] : 0.f;
+    const float b2 = tid < kH2 ? a.p[a.oB[1] + tid] : 0.f;
+    const float b3 = tid < H3 ? a.p[a.oB[2] + tid] : 0.f;
+    const float bo = tid < a.O ? a.p[a.oBo + tid] : 0.f;
 #pragma unroll
     for (int u = 0; u < nW1; ++u) sW1[tid + NT * u] = make_uint4(w1[u][0], w1[u][1], w1[u][2], w1[u][3]);
 #pragma unroll
     for (int u = 0; u < nW2; ++u) sW2[tid + NT * u] = make_uint4(w2[u][0].x, w2[u][0].y, w2[u][1].x, w2[u][1].y);
-    if (tid < kFrontWo) sWo[tid] = make_uint4(wo[0].x, wo[0].y, wo[1].x, wo[1].y);
 #pragma unroll
-    for (int u = 0; u < nWoT; ++u) sWoT[tid + NT * u] = pack8(wt[u]);
+    for (int u = 0; u < nW3; ++u) sW3[tid + NT * u] = make_uint4(w3[u][0].x, w3[u][0].y, w3[u][1].x, w3[u][1].y);
+    if (tid < S::kWo) sWo[tid] = make_uint4(wo[0].x, wo[0].y, wo[1].x, wo[1].y);
+#pragma unroll
+    for (int u = 0; u < nWoT; ++u)
+      if (tid + NT * u < S::kWoT) sWoT[tid + NT * u] = pack8(wt[u]);
+#pragma unroll
+    for (int u = 0; u < nW3T; ++u) sW3T[tid + NT * u] = pack8(w3t[u]);
     if (tid < kH1) sb1[tid] = b1;
     if (tid < kH2) sb2[tid] = b2;
+    if (tid < H3) sb3[tid] = b3;
     if (tid < kOut) sbo[tid] = bo;
   }
   __syncthreads();
@@ -503,8 +501,7 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
       bf16x8 hb;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const uint4 t = sW1[(2 * kb + h) * 64 + lane];
-        const f32x4 d = mfma16x16x32(*reinterpret_cast<const bf16x8*>(&t), xb, zero4);
+        const f32x4 d = mfma16x16x32(frag(sW1, (2 * kb + h) * 64 + lane), xb, zero4);
 #pragma unroll
         for (int r = 0; r < 4; ++r) hb[4 * h + r] = (__bf16)act_f<ACT>(d[r] + sb1[32 * kb + 16 * h + 4 * g + r]);
       }
@@ -514,30 +511,16 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
         *reinterpret_cast<uint2*>(dst + 16) = bf16x4_bits(hb, 1);
       }
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const uint4 t = sW2[(m * 8 + kb) * 64 + lane];
-        acc2[m] = mfma16x16x32(*reinterpret_cast<const bf16x8*>(&t), hb, acc2[m]);
-      }
+      for (int m = 0; m < 8; ++m) acc2[m] = mfma16x16x32(frag(sW2, (m * 8 + kb) * 64 + lane), hb, acc2[m]);
     }
-    // layer 2's activations (BF16, the output layer's B operand) and act'
-    float dact[8][4];
+    // layer 2's activations (BF16, the next layer's B operand) and act'
+    float dact2[8][4];
     bf16x8 h2b[4];
 #pragma unroll
     for (int m = 0; m < 8; ++m)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float z = acc2[m][r] + sb2[16 * m + 4 * g + r];
-        float hv;
-        if (ACT == ACT_TANH) {
-          const float t = tanh_fast(z);
-          hv = t;
-          dact[m][r] = 1.f - t * t;
-        } else {
-          hv = elu_f(z);
-          dact[m][r] = elu_grad_f(z);
-        }
-        h2b[m >> 1][4 * (m & 1) + r] = (__bf16)hv;
-      }
+      for (int r = 0; r < 4; ++r)
+        h2b[m >> 1][4 * (m & 1) + r] = (__bf16)act_and_grad<ACT>(acc2[m][r] + sb2[16 * m + 4 * g + r], dact2[m][r]);
     if (rv) {
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb) {
@@ -546,11 +529,37 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
         *reinterpret_cast<uint2*>(dst + 16) = bf16x4_bits(h2b[kb], 1);
       }
     }
+    // layer 3 (if any), then the output layer on the last hidden layer
+    constexpr int M3 = H3 / 16;
+    float dact3[M3 ? M3 : 1][4];
+    bf16x8 h3b[M3 ? M3 / 2 : 1];
     f32x4 acco = zero4;
+    if constexpr (H3 > 0) {
+      f32x4 acc3[M3];
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      const uint4 t = sWo[kb * 64 + lane];
-      acco = mfma16x16x32(*reinterpret_cast<const bf16x8*>(&t), h2b[kb], acco);
+      for (int m = 0; m < M3; ++m) acc3[m] = zero4;
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int m = 0; m < M3; ++m) acc3[m] = mfma16x16x32(frag(sW3, (m * 4 + kb) * 64 + lane), h2b[kb], acc3[m]);
+#pragma unroll
+      for (int m = 0; m < M3; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          h3b[m >> 1][4 * (m & 1) + r] = (__bf16)act_and_grad<ACT>(acc3[m][r] + sb3[16 * m + 4 * g + r], dact3[m][r]);
+      if (rv) {
+#pragma unroll
+        for (int kb = 0; kb < M3 / 2; ++kb) {
+          uint16_t* dst = a.H3 + (size_t)rj * H3 + 32 * kb + 4 * g;
+          *reinterpret_cast<uint2*>(dst) = bf16x4_bits(h3b[kb], 0);
+          *reinterpret_cast<uint2*>(dst + 16) = bf16x4_bits(h3b[kb], 1);
+        }
+      }
+#pragma unroll
+      for (int kb = 0; kb < M3 / 2; ++kb) acco = mfma16x16x32(frag(sWo, kb * 64 + lane), h3b[kb], acco);
+    } else {
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) acco = mfma16x16x32(frag(sWo, kb * 64 + lane), h2b[kb], acco);
     }
     // outputs to LDS (lane groups 0 and 1 hold outputs 0..7 of row rb + i)
     if (g < 2) {
@@ -577,24 +586,47 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
       }
       *reinterpret_cast<uint4*>(a.G3b + (size_t)rj * kPO) = *reinterpret_cast<const uint4*>(&gb);
     }
-    // dZ2 = (G Wo) act'(Z2): B operand = the rows' BF16 output gradients
-    // (K = outputs, held by lane group 0), A = Wo^T; column sums over the
-    // tile's 16 rows (one DPP row per lane group), then over the four waves
-    // in order
+    // the gradient through the output layer: B operand = the rows' BF16
+    // output gradients (K = outputs, held by lane group 0), A = Wo^T; then,
+    // with a third hidden layer, through it: B = the BF16 dZ3 tiles, A =
+    // W3^T. Column sums over the tile's 16 rows (one DPP row per lane
+    // group), then over the waves in order.
+    bf16x8 d3b[M3 ? M3 / 2 : 1];
+    if constexpr (H3 > 0) {
+#pragma unroll
+      for (int m = 0; m < M3; ++m) {
+        const f32x4 d = mfma16x16x32(frag(sWoT, m * 64 + lane), gb, zero4);
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          v[r] = d[r] * dact3[m][r];
+          d3b[m >> 1][4 * (m & 1) + r] = (__bf16)v[r];
+        }
+        if (rv) *reinterpret_cast<uint2*>(a.D3b + (size_t)rj * H3 + 16 * m + 4 * g) = bf16x4_bits(d3b[m >> 1], m & 1);
+        row16_sums(v);
+        if (i == 0) *reinterpret_cast<float4*>(sCol + wave * S::kCols + kH2 + 16 * m + 4 * g) = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const uint4 t = sWoT[m * 64 + lane];
-      const f32x4 d = mfma16x16x32(*reinterpret_cast<const bf16x8*>(&t), gb, zero4);
+      f32x4 d;
+      if constexpr (H3 > 0) {
+        d = zero4;
+#pragma unroll
+        for (int kb = 0; kb < M3 / 2; ++kb) d = mfma16x16x32(frag(sW3T, (m * (M3 / 2) + kb) * 64 + lane), d3b[kb], d);
+      } else {
+        d = mfma16x16x32(frag(sWoT, m * 64 + lane), gb, zero4);
+      }
       bf16x8 o;
       float v[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        v[r] = d[r] * dact[m][r];
+        v[r] = d[r] * dact2[m][r];
         o[r] = (__bf16)v[r];
       }
-      row16_sums(v);
-      if (i == 0) *reinterpret_cast<float4*>(sCol + wave * kH2 + 16 * m + 4 * g) = make_float4(v[0], v[1], v[2], v[3]);
       if (rv) *reinterpret_cast<uint2*>(a.D2b + (size_t)rj * kH2 + 16 * m + 4 * g) = bf16x4_bits(o, 0);
+      row16_sums(v);
+      if (i == 0) *reinterpret_cast<float4*>(sCol + wave * S::kCols + 16 * m + 4 * g) = make_float4(v[0], v[1], v[2], v[3]);
     }
     {
       const float w = a.w_stats * a.inv_b;
@@ -610,15 +642,16 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
       }
     }
     __syncthreads();
-    if (tid < kH2) {
+    if (tid < S::kCols) {
       float v = 0.f;
 #pragma unroll
-      for (int w = 0; w < kFrontWaves; ++w) v += sCol[w * kH2 + tid];
-      a.cpart2[(size_t)c * kH2 + tid] = v;
+      for (int w = 0; w < kFrontWaves; ++w) v += sCol[w * S::kCols + tid];
+      if (tid < kH2) a.cpart2[(size_t)c * kH2 + tid] = v;
+      else a.cpart3[(size_t)c * H3 + tid - kH2] = v;
     }
-    if (tid >= kH2 && tid < kH2 + kLossPart) {
+    if (tid >= S::kCols && tid < S::kCols + kLossPart) {
       // column cc of the row: output cc, log_std cc - O, zero, or statistic
-      const int cc = tid - kH2, O = a.O;
+      const int cc = tid - S::kCols, O = a.O;
       const int src = cc < O ? cc : (cc < O + R.J ? kPO + cc - O : (cc >= 16 ? 2 * kPO + cc - 16 : -1));
       constexpr int L = 2 * kPO + 4;
       float v = 0.f;
@@ -630,19 +663,17 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
   }
 }
 
-// Rows per block of the loss sums: the fused front sums kFrontRows-row
-// chunks, k_ppo_loss 256-row blocks.
-static int loss_blocks(const sg_ppo* o, int rows) {
-  return o->h3 ? (rows + 255) / 256 : (rows + kFrontRows - 1) / kFrontRows;
-}
+// Rows per block of the loss sums and the fused front's column sums
+static int loss_blocks(int rows) { return (rows + kFrontRows - 1) / kFrontRows; }
 
-// One workgroup per compute unit at most (104 KB of LDS each), walking the
-// chunks.
-template <int ACT> static hipError_t launch_front(hipStream_t st, const FrontArgs& a, int n_cu) {
-  hipError_t e = lds_limit((const void*)k_ppo_front<ACT>, kFrontLds);
+// One workgroup per compute unit at most (104 KB or 131 KB of LDS), walking
+// the chunks.
+template <int ACT, int H3> static hipError_t launch_front(hipStream_t st, const FrontArgs& a, int n_cu) {
+  constexpr size_t lds = FrontShape<H3>::kLds;
+  hipError_t e = lds_limit((const void*)k_ppo_front<ACT, H3>, lds);
   if (e != hipSuccess) return e;
   const int grid = a.nchunks < n_cu ? a.nchunks : n_cu;
-  k_ppo_front<ACT><<<grid, kFrontThreads, kFrontLds, st>>>(a);
+  k_ppo_front<ACT, H3><<<grid, kFrontThreads, lds, st>>>(a);
   return hipGetLastError();
 }
 
@@ -673,7 +704,7 @@ __global__ void __launch_bounds__(256) k_gnorm_part(float* __restrict__ g, int P
   if (threadIdx.x == 0) gpart[blockIdx.x] = red[0];
 }
 
-// Block-wide: the minibatch's loss statistics (block sums of k_ppo_loss,
+// Block-wide: the minibatch's loss statistics (chunk sums of k_ppo_front,
 // in a fixed order), entropy and the gradient norm n, added to stats with
 // weight w.
 __device__ void add_stats(const float* __restrict__ lpart, int lb, const float* __restrict__ ls, int J, float n,
@@ -915,70 +946,42 @@ static hipError_t minibatch_grad_t(sg_ppo* o, const PpoRows& rows, const sg_ppo_
   sg_ctx* c = o->ctx;
   hipStream_t st = c->stream;
   const int B = rows.rows, W = o->W, O = o->O, J = o->J, h3 = o->h3, L = o->nl - 1;  // L: output layer
-  const int gb = (B + 255) / 256, lb = loss_blocks(o, B);
+  const int gb = (B + 255) / 256, lb = loss_blocks(B);
   // every entry of o->g is written below (weight and bias sums), so no clear
   if (!gathered) k_ppo_gather<<<gb, 256, 0, st>>>(rows, o->X);
+  // forward, loss and the gradient down to dZ2 in one launch
+  FrontArgs fa;
+  fa.X = o->X; fa.pb = o->pb; fa.p = o->p;
+  for (int l = 0; l < 3; ++l) { fa.oW[l] = o->oW[l]; fa.oB[l] = o->oB[l]; }
+  fa.oWo = o->oW[L]; fa.oBo = o->oB[L]; fa.oLS = o->oLS;
+  fa.W = W; fa.O = O; fa.rows = rows;
+  fa.clip = cfg->clip; fa.c_v = cfg->value_coef; fa.inv_b = 1.f / (float)B; fa.w_stats = w_stats;
+  fa.H1 = o->H1; fa.H2 = o->H2; fa.H3 = o->H3; fa.G3b = o->G3b; fa.D2b = o->D2b; fa.D3b = o->D3b;
+  fa.cpart2 = o->cpart2; fa.cpart3 = o->cpart3; fa.lpart = o->lpart;
+  fa.nchunks = lb;
+  {
+    // the two networks sg_ppo_create accepts: 256-128 tanh, 256-128-64 ELU
+    if ((ACT == ACT_TANH) != (h3 == 0)) return hipErrorInvalidValue;
+    const hipError_t e = ACT == ACT_TANH ? launch_front<ACT_TANH, 0>(st, fa, c->n_cu)
+                                         : launch_front<ACT_ELU, 64>(st, fa, c->n_cu);
+    if (e != hipSuccess) return e;
+  }
+  // weight gradients as split-K partials; their sums and the bias sums run
+  // in one launch at the end. Output biases and log_std are adjacent in the
+  // flat vector (oLS = oB[L] + O).
   SumJob jobs[8];
   int nj = 0;
+  const int hl = h3 ? h3 : kH2;
+  jobs[nj++] = weight_grad(o, st, 3, O, hl, B, o->G3b, kPO, h3 ? o->H3 : o->H2, hl, o->g + o->oW[L], hl);
+  jobs[nj++] = partial_rows(o->lpart, lb, O + J, kLossPart, o->g + o->oB[L]);
+  if (h3) {
+    jobs[nj++] = weight_grad(o, st, 2, h3, kH2, B, o->D3b, h3, o->H2, kH2, o->g + o->oW[2], kH2);
+    jobs[nj++] = partial_rows(o->cpart3, lb, h3, h3, o->g + o->oB[2]);
+  }
+  jobs[nj++] = weight_grad(o, st, 1, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->oW[1], kH1);
+  jobs[nj++] = partial_rows(o->cpart2, lb, kH2, kH2, o->g + o->oB[1]);
   const int rb = (B + 63) / 64;
   GemmArgs d{};
-  if (!h3) {
-    // forward, loss and the gradient down to dZ2 in one launch
-    FrontArgs fa;
-    fa.X = o->X; fa.pb = o->pb; fa.p = o->p;
-    fa.oW0 = o->oW[0]; fa.oB0 = o->oB[0]; fa.oW1 = o->oW[1]; fa.oB1 = o->oB[1];
-    fa.oW2 = o->oW[L]; fa.oB2 = o->oB[L]; fa.oLS = o->oLS;
-    fa.W = W; fa.O = O; fa.rows = rows;
-    fa.clip = cfg->clip; fa.c_v = cfg->value_coef; fa.inv_b = 1.f / (float)B; fa.w_stats = w_stats;
-    fa.H1 = o->H1; fa.H2 = o->H2; fa.G3b = o->G3b; fa.D2b = o->D2b; fa.cpart2 = o->cpart2; fa.lpart = o->lpart;
-    fa.nchunks = lb;
-    const hipError_t e = launch_front<ACT>(st, fa, c->n_cu);
-    if (e != hipSuccess) return e;
-    jobs[nj++] = weight_grad(o, st, 3, O, kH2, B, o->G3b, kPO, o->H2, kH2, o->g + o->oW[L], kH2);
-    jobs[nj++] = partial_rows(o->lpart, lb, O + J, kLossPart, o->g + o->oB[L]);
-    jobs[nj++] = weight_grad(o, st, 1, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->oW[1], kH1);
-    jobs[nj++] = partial_rows(o->cpart2, lb, kH2, kH2, o->g + o->oB[1]);
-  } else {
-    GemmArgs f{};
-    // layer 1: Z1 = X W1^T + b1, H1 = act(Z1)
-    f.M = B; f.N = kH1; f.K = W; f.A = o->X; f.lda = kPX; f.B = o->pb + o->oW[0]; f.ldb = W;
-    f.C = nullptr; f.ldc = kH1; f.bias = o->p + o->oB[0]; f.Cb = o->H1;
-    launch_gemm<EPI_FWD_HIDDEN, false, true, ACT>(st, f);
-    // layer 2 (pre-activations kept for the backward pass)
-    f.N = kH2; f.K = kH1; f.A = o->H1; f.lda = kH1; f.B = o->pb + o->oW[1]; f.ldb = kH1;
-    f.C = o->Z2; f.ldc = kH2; f.bias = o->p + o->oB[1]; f.Cb = o->H2;
-    launch_gemm<EPI_FWD_HIDDEN, false, true, ACT>(st, f);
-    // layer 3
-    f.N = h3; f.K = kH2; f.A = o->H2; f.lda = kH2; f.B = o->pb + o->oW[2]; f.ldb = kH2;
-    f.C = o->Z3h; f.ldc = h3; f.bias = o->p + o->oB[2]; f.Cb = o->H3;
-    launch_gemm<EPI_FWD_HIDDEN, false, true, ACT>(st, f);
-    // output layer (linear): [mu | V]
-    f.N = O; f.K = h3; f.A = o->H3; f.lda = h3; f.B = o->pb + o->oW[L]; f.ldb = h3;
-    f.C = o->Z3; f.ldc = kPO; f.bias = o->p + o->oB[L]; f.Cb = nullptr;
-    launch_gemm<EPI_FWD_OUT, false, true, ACT>(st, f);
-    PpoLossArgs la;
-    la.rows = rows; la.Z3 = o->Z3; la.ls = o->p + o->oLS; la.clip = cfg->clip; la.c_v = cfg->value_coef;
-    la.inv_b = 1.f / (float)B; la.w_stats = w_stats; la.G3b = o->G3b; la.part = o->lpart;
-    k_ppo_loss<<<gb, 256, 0, st>>>(la);
-    // weight gradients as split-K partials; their sums and the bias sums run
-    // in one launch at the end. Output biases and log_std are adjacent in the
-    // flat vector (oLS = oB[L] + O).
-    jobs[nj++] = weight_grad(o, st, 3, O, h3, B, o->G3b, kPO, o->H3, h3, o->g + o->oW[L], h3);
-    jobs[nj++] = partial_rows(o->lpart, lb, O + J, kLossPart, o->g + o->oB[L]);
-    // dZ3 = (G Wo) * act'(Z3), with the column sums of dZ3 (hidden-3 bias)
-    d.M = B; d.N = h3; d.K = O; d.A = o->G3b; d.lda = kPO; d.B = o->pb + o->oW[L]; d.ldb = h3;
-    d.C = nullptr; d.ldc = h3; d.Cb = o->D3b; d.Zp = o->Z3h; d.colpart = o->cpart3;
-    launch_gemm<EPI_BWD_DX, false, false, ACT>(st, d);
-    jobs[nj++] = weight_grad(o, st, 2, h3, kH2, B, o->D3b, h3, o->H2, kH2, o->g + o->oW[2], kH2);
-    jobs[nj++] = partial_rows(o->cpart3, rb, h3, h3, o->g + o->oB[2]);
-    // dZ2 = (dZ3 W3) * act'(Z2), with the column sums of dZ2 (hidden-2 bias)
-    d = GemmArgs{};
-    d.M = B; d.N = kH2; d.K = h3; d.A = o->D3b; d.lda = h3; d.B = o->pb + o->oW[2]; d.ldb = kH2;
-    d.C = nullptr; d.ldc = kH2; d.Cb = o->D2b; d.Zp = o->Z2; d.colpart = o->cpart2;
-    launch_gemm<EPI_BWD_DX, false, false, ACT>(st, d);
-    jobs[nj++] = weight_grad(o, st, 1, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->oW[1], kH1);
-    jobs[nj++] = partial_rows(o->cpart2, rb, kH2, kH2, o->g + o->oB[1]);
-  }
   // dZ1 = (dZ2 W2) * act'(Z1), with the column sums of dZ1 (hidden-1 bias);
   // Z1 (W inputs) is recomputed in the epilogue rather than stored
   d = GemmArgs{};
@@ -1123,20 +1126,17 @@ sg_status sg_ppo_create(sg_ctx* c, const sg_policy_arch* arch, const float* para
   if (e == hipSuccess) e = palloc(o, &o->Xall, R * kPX);
   if (e == hipSuccess) e = palloc(o, &o->Aux, R * kAux);
   if (e == hipSuccess) e = palloc(o, &o->H1, R * kH1);
-  if (e == hipSuccess && h3) e = palloc(o, &o->Z2, R * kH2);
   if (e == hipSuccess) e = palloc(o, &o->H2, R * kH2);
-  if (e == hipSuccess && h3) e = palloc(o, &o->Z3h, R * h3);
   if (e == hipSuccess && h3) e = palloc(o, &o->H3, R * h3);
   if (e == hipSuccess && h3) e = palloc(o, &o->D3b, R * h3);
-  if (e == hipSuccess && h3) e = palloc(o, &o->cpart3, ((R + 63) / 64) * (size_t)h3);
-  if (e == hipSuccess && h3) e = palloc(o, &o->Z3, R * kPO);
+  if (e == hipSuccess && h3) e = palloc(o, &o->cpart3, (size_t)loss_blocks((int)R) * h3);
   if (e == hipSuccess) e = palloc(o, &o->G3b, R * kPO);
   if (e == hipSuccess) e = palloc(o, &o->D2b, R * kH2);
   if (e == hipSuccess) e = palloc(o, &o->D1b, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->ws, o->ws_floats);
   if (e == hipSuccess) e = palloc(o, &o->cpart, ((R + 63) / 64) * (size_t)kH1);
-  if (e == hipSuccess) e = palloc(o, &o->cpart2, ((R + 63) / 64) * (size_t)kH2);
-  if (e == hipSuccess) e = palloc(o, &o->lpart, ((R + 63) / 64) * (size_t)kLossPart);
+  if (e == hipSuccess) e = palloc(o, &o->cpart2, (size_t)loss_blocks((int)R) * kH2);
+  if (e == hipSuccess) e = palloc(o, &o->lpart, (size_t)loss_blocks((int)R) * kLossPart);
   if (e == hipSuccess) e = palloc(o, &o->gpart, (size_t)kGnormBlocks);
   if (e == hipSuccess && (o->P + kGnormChunk - 1) / kGnormChunk > kGnormBlocks) e = hipErrorInvalidValue;
   if (e == hipSuccess && !c->w_bf16) e = hipMalloc((void**)&c->w_bf16, (size_t)kWFragsMax * 16);
@@ -1247,7 +1247,7 @@ sg_status sg_ppo_update(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const sg
       na.c_e = cfg->entropy_coef; na.max_norm = cfg->max_grad_norm; na.lr = cfg->lr;
       na.b1 = cfg->beta1; na.b2 = cfg->beta2; na.eps = cfg->adam_eps;
       na.tstep = o->tstep; na.ttick = o->ttick;
-      na.lpart = o->lpart; na.lb = loss_blocks(o, mb); na.stats = stats; na.w = w;
+      na.lpart = o->lpart; na.lb = loss_blocks(mb); na.stats = stats; na.w = w;
       na.nadam = (o->P + kNormAdamThreads - 1) / kNormAdamThreads;
       const bool last = k + 1 == cfg->minibatches && ep + 1 == cfg->epochs;
       na.next = last ? PpoRows{} : rows_at(k + 1 < cfg->minibatches ? ep : ep + 1, (k + 1) % cfg->minibatches);
