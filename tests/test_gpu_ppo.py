@@ -110,6 +110,45 @@ def test_minibatch_gradient_matches_oracle(sg, perturb):
     ppo.close()
 
 
+def test_minibatch_gradient_six_dof_chain(sg):
+    """A 6-DOF RRPRRR reaching workload (22 inputs, 7 outputs): the
+    narrower input and output layers, with a minibatch of 777 rows (six
+    whole 128-row chunks of the fused front and a ragged one); the same
+    criteria as the 7-DOF gradient test."""
+    import torch
+    T, N, J = 8, 256, 6
+    dims = (2 * J + 10, 256, 128, J)
+    w = synth.psm_like(N)
+    w.policy = synth.make_policy(35, dims=(dims[0], 256, 128, J + 1))
+    sim = sg.Sim(w.robot, w.task, seed=w.seed)
+    params = sg.ppo_flat_params(w.policy)
+    ppo = sg.Ppo(sim, params, T * N)
+    bufs = sim.rollout(T)
+    idx = torch.randperm(T * N, device="cuda", generator=torch.Generator(device="cuda").manual_seed(2))[:777]
+    idx = idx.to(torch.int32)
+    gg, st = ppo.grad(bufs, T, idx)
+    h, x, a = _rows(bufs, T, N, J)
+    an = oracle.ppo_normalise(h["adv"]).ravel()
+    s = idx.cpu().numpy()
+    args = (x[:, s], a[:, s], h["logp"].ravel()[s], an[s], h["ret"].ravel()[s], h["val"][:T].ravel()[s])
+    _, gr, so = oracle.ppo_grad(dims, params.astype(np.float64), *args, emulate=True)
+    _, gx, _ = oracle.ppo_grad(dims, params.astype(np.float64), *args, emulate=False)
+    st = host(st)
+    for k, name in enumerate(("loss_pi", "loss_v", "entropy", "approx_kl", "clip_frac")):
+        assert abs(st[k] - so[name]) <= 1e-3 * max(1.0, abs(so[name])) + 1e-5, (name, st[k], so[name])
+    n_in, h1, h2, _ = dims
+    sz = [h1 * n_in, h1, h2 * h1, h2, (J + 1) * h2, J + 1, J]
+    o = np.cumsum([0] + sz)
+    for i in range(7):
+        gb, rb, xb = host(gg)[o[i]:o[i + 1]], gr[o[i]:o[i + 1]], gx[o[i]:o[i + 1]]
+        rel = np.linalg.norm(gb - rb) / np.linalg.norm(rb)
+        cos = (gb @ rb) / (np.linalg.norm(gb) * np.linalg.norm(rb))
+        assert rel <= 2e-2 and cos >= 0.999, (i, rel, cos)
+        bound = 2 * np.abs(rb - xb) + 1e-3 * np.abs(rb).max()
+        assert np.all(np.abs(gb - rb) <= bound), (i, np.max(np.abs(gb - rb) / bound))
+    ppo.close()
+
+
 def test_one_update_step_is_clip_and_adam_of_the_gradient(sg):
     T, N = 4, 256
     w, sim, ppo, params, bufs = _setup(sg, N, T, seed=32)
