@@ -65,7 +65,7 @@ struct sg_ppo {
   uint16_t* D1b = nullptr;   // [rows][256]
   float* ws = nullptr;       // split-K partials, one kWeightGradWs region per layer
   size_t ws_floats = 0;
-  float* cpart = nullptr;    // per-block column sums of dZ1 [rows / 64][256]
+  float* cpart = nullptr;    // per-chunk column sums of dZ1 [loss_blocks(rows)][256]
   float* cpart2 = nullptr;   // per-chunk column sums of dZ2 [loss_blocks(rows)][128]
   float* lpart = nullptr;    // per-chunk loss sums [loss_blocks(rows)][kLossPart]
   double* gpart = nullptr;   // block sums [kGnormBlocks]: advantage statistics, then gradient norm
@@ -663,6 +663,121 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
   }
 }
 
+// Hidden layer 1's gradient, dZ1 = (dZ2 W2) act'(Z1), per chunk of
+// kFrontRows rows (one 16-row tile per wave): Z1 = X W1^T + b1 recomputed
+// with the forward's own operands and order (so act'(Z1) sees the forward's
+// FP32 values), then per 16-unit tile the product with W2 on the matrix
+// cores (B operand = the BF16 dZ2 rows, K natural), act' applied, BF16
+// rows of D1b out and per-chunk column sums (the hidden-1 bias gradient,
+// cpart). W1's image (as in k_ppo_front) and W2^T's (A fragments [16 row
+// tiles][4 K-blocks][64 lanes], K natural) are staged in LDS once per
+// workgroup. Same arithmetic per element as the data-gradient GEMM it
+// replaces, to FP32 rounding.
+struct Dz1Args {
+  const uint16_t* X;    // [rows][kPX]
+  const uint16_t* D2b;  // [rows][128]
+  const uint16_t* pb;   // W1 at oW0 [256][W], W2 at oW1 [128][256]
+  const float* p;       // b1 at oB0
+  int oW0, oW1, oB0, W, rows;
+  uint16_t* D1b;        // [rows][256]
+  float* cpart;         // [chunks][256]
+  int nchunks;
+};
+constexpr int kW2TFrags = (kH1 / 16) * (kH2 / 32) * 64;
+constexpr size_t kDz1Lds = (size_t)(kW1Frags + kW2TFrags) * 16 + (size_t)kH1 * 4 + (size_t)kFrontWaves * kH1 * 4;
+
+template <int ACT>
+__global__ void __launch_bounds__(kFrontThreads) k_ppo_dz1(Dz1Args a) {
+  constexpr int NT = kFrontThreads;
+  extern __shared__ __align__(16) unsigned char lds[];
+  uint4* sW1 = reinterpret_cast<uint4*>(lds);
+  uint4* sW2T = sW1 + kW1Frags;
+  float* sb1 = reinterpret_cast<float*>(lds + (size_t)(kW1Frags + kW2TFrags) * 16);
+  float* sCol = sb1 + kH1;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int g = lane >> 4, i = lane & 15;
+  {
+    // loads first: W1 as BF16 pairs; W2^T fragment by fragment, eight
+    // elements of one W2 column each (lane 16 g + i of row tile t, K-block
+    // kb: W2[32 kb + 8 g + s][16 t + i]), so each fragment is one 16-byte
+    // LDS store
+    constexpr int nW1 = kW1Frags / NT, nW2T = kW2TFrags / NT;
+    static_assert(kW1Frags % NT == 0 && kW2TFrags % NT == 0 && kH1 <= NT, "the staging loops are exact");
+    uint32_t w1[nW1][4];
+    uint16_t w2t[nW2T][8];
+#pragma unroll
+    for (int u = 0; u < nW1; ++u) {
+      const int f = tid + NT * u, l = f & 63, row = 16 * (f >> 6) + (l & 15), k0 = 8 * (l >> 4);
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.pb + a.oW0 + (size_t)row * a.W);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w1[u][q] = k0 + 2 * q < a.W ? src[(k0 >> 1) + q] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < nW2T; ++u) {
+      const int f = tid + NT * u, l = f & 63, tk = f >> 6, t = tk / (kH2 / 32), kb = tk % (kH2 / 32);
+      const uint16_t* src = a.pb + a.oW1 + (size_t)(32 * kb + 8 * (l >> 4)) * kH1 + 16 * t + (l & 15);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) w2t[u][q] = src[(size_t)q * kH1];
+    }
+    const float b1 = tid < kH1 ? a.p[a.oB0 + tid] : 0.f;
+#pragma unroll
+    for (int u = 0; u < nW1; ++u) sW1[tid + NT * u] = make_uint4(w1[u][0], w1[u][1], w1[u][2], w1[u][3]);
+#pragma unroll
+    for (int u = 0; u < nW2T; ++u) sW2T[tid + NT * u] = pack8(w2t[u]);
+    if (tid < kH1) sb1[tid] = b1;
+  }
+  __syncthreads();
+  const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+  for (int c = blockIdx.x; c < a.nchunks; c += gridDim.x) {
+    const int rj = c * kFrontRows + 16 * wave + i;
+    const bool rv = rj < a.rows;
+    bf16x8 xb, db[kH2 / 32];
+    {
+      const uint4 t = rv ? *reinterpret_cast<const uint4*>(a.X + (size_t)rj * kPX + 8 * g) : make_uint4(0, 0, 0, 0);
+      xb = *reinterpret_cast<const bf16x8*>(&t);
+    }
+#pragma unroll
+    for (int kb = 0; kb < kH2 / 32; ++kb) {
+      const uint4 t =
+          rv ? *reinterpret_cast<const uint4*>(a.D2b + (size_t)rj * kH2 + 32 * kb + 8 * g) : make_uint4(0, 0, 0, 0);
+      db[kb] = *reinterpret_cast<const bf16x8*>(&t);
+    }
+#pragma unroll 4
+    for (int t = 0; t < kH1 / 16; ++t) {
+      const f32x4 z1 = mfma16x16x32(frag(sW1, t * 64 + lane), xb, zero4);
+      f32x4 d = zero4;
+#pragma unroll
+      for (int kb = 0; kb < kH2 / 32; ++kb) d = mfma16x16x32(frag(sW2T, (t * (kH2 / 32) + kb) * 64 + lane), db[kb], d);
+      bf16x8 o;
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[r] = d[r] * act_grad<ACT>(z1[r] + sb1[16 * t + 4 * g + r]);
+        o[r] = (__bf16)v[r];
+      }
+      if (rv) *reinterpret_cast<uint2*>(a.D1b + (size_t)rj * kH1 + 16 * t + 4 * g) = bf16x4_bits(o, 0);
+      row16_sums(v);
+      if (i == 0) *reinterpret_cast<float4*>(sCol + wave * kH1 + 16 * t + 4 * g) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    __syncthreads();
+    if (tid < kH1) {
+      float v = 0.f;
+#pragma unroll
+      for (int w = 0; w < kFrontWaves; ++w) v += sCol[w * kH1 + tid];
+      a.cpart[(size_t)c * kH1 + tid] = v;
+    }
+    __syncthreads();
+  }
+}
+
+template <int ACT> static hipError_t launch_dz1(hipStream_t st, const Dz1Args& a, int n_cu) {
+  hipError_t e = lds_limit((const void*)k_ppo_dz1<ACT>, kDz1Lds);
+  if (e != hipSuccess) return e;
+  const int grid = a.nchunks < n_cu ? a.nchunks : n_cu;
+  k_ppo_dz1<ACT><<<grid, kFrontThreads, kDz1Lds, st>>>(a);
+  return hipGetLastError();
+}
+
 // Rows per block of the loss sums and the fused front's column sums
 static int loss_blocks(int rows) { return (rows + kFrontRows - 1) / kFrontRows; }
 
@@ -980,18 +1095,18 @@ static hipError_t minibatch_grad_t(sg_ppo* o, const PpoRows& rows, const sg_ppo_
   }
   jobs[nj++] = weight_grad(o, st, 1, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->oW[1], kH1);
   jobs[nj++] = partial_rows(o->cpart2, lb, kH2, kH2, o->g + o->oB[1]);
-  const int rb = (B + 63) / 64;
-  GemmArgs d{};
   // dZ1 = (dZ2 W2) * act'(Z1), with the column sums of dZ1 (hidden-1 bias);
-  // Z1 (W inputs) is recomputed in the epilogue rather than stored
-  d = GemmArgs{};
-  d.M = B; d.N = kH1; d.K = kH2; d.A = o->D2b; d.lda = kH2; d.B = o->pb + o->oW[1]; d.ldb = kH1;
-  d.C = nullptr; d.ldc = kH1; d.Cb = o->D1b; d.colpart = o->cpart;
-  d.Zp = nullptr;
-  d.RA = o->X; d.rlda = kPX; d.RB = o->pb + o->oW[0]; d.rldb = W; d.RK = W; d.rbias = o->p + o->oB[0];
-  launch_gemm<EPI_BWD_DX, false, false, ACT>(st, d);
+  // Z1 (W inputs) is recomputed rather than stored
+  {
+    Dz1Args da;
+    da.X = o->X; da.D2b = o->D2b; da.pb = o->pb; da.p = o->p;
+    da.oW0 = o->oW[0]; da.oW1 = o->oW[1]; da.oB0 = o->oB[0]; da.W = W; da.rows = B;
+    da.D1b = o->D1b; da.cpart = o->cpart; da.nchunks = lb;
+    const hipError_t e = launch_dz1<ACT>(st, da, c->n_cu);
+    if (e != hipSuccess) return e;
+  }
   jobs[nj++] = weight_grad(o, st, 0, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->oW[0], W);
-  jobs[nj++] = partial_rows(o->cpart, rb, kH1, kH1, o->g + o->oB[0]);
+  jobs[nj++] = partial_rows(o->cpart, lb, kH1, kH1, o->g + o->oB[0]);
   launch_sums(st, jobs, nj);
   if (finish) {
     const int nb = (o->P + kGnormChunk - 1) / kGnormChunk;
@@ -1134,7 +1249,7 @@ sg_status sg_ppo_create(sg_ctx* c, const sg_policy_arch* arch, const float* para
   if (e == hipSuccess) e = palloc(o, &o->D2b, R * kH2);
   if (e == hipSuccess) e = palloc(o, &o->D1b, R * kH1);
   if (e == hipSuccess) e = palloc(o, &o->ws, o->ws_floats);
-  if (e == hipSuccess) e = palloc(o, &o->cpart, ((R + 63) / 64) * (size_t)kH1);
+  if (e == hipSuccess) e = palloc(o, &o->cpart, (size_t)loss_blocks((int)R) * kH1);
   if (e == hipSuccess) e = palloc(o, &o->cpart2, (size_t)loss_blocks((int)R) * kH2);
   if (e == hipSuccess) e = palloc(o, &o->lpart, (size_t)loss_blocks((int)R) * kLossPart);
   if (e == hipSuccess) e = palloc(o, &o->gpart, (size_t)kGnormBlocks);
