@@ -34,6 +34,15 @@
 #include "mlp.hpp"
 #include "nn.hpp"
 
+namespace sgk {
+// Fragment images of the fused PPO kernels' weights: layout (see img_scatter)
+struct PpoImg {
+  int W, O, KO, H3;   // inputs, outputs, the output layer's K, hidden-3 width (0: none)
+  int oW1, oW2, oW3, oWo;  // weight offsets in the flat parameters
+  int fW1, fW2, fW3, fWo, fWoT, fW3T, fW2T, frags;  // image sections (uint4 offsets), total
+};
+}  // namespace sgk
+
 struct sg_ppo {
   sg_ctx* ctx = nullptr;
   int J = 0, W = 0, O = 0, P = 0;
@@ -47,6 +56,7 @@ struct sg_ppo {
   unsigned* ttick = nullptr; // blocks of the current norm+Adam launch that have read it
   float* p = nullptr;        // master parameters [P]
   uint16_t* pb = nullptr;    // BF16 copy [P]
+  uint16_t* img = nullptr;   // fragment images of the fused kernels' weights [im.frags][8]
   float* g = nullptr;        // gradient [P]
   float* m = nullptr;        // Adam moments [P]
   float* v = nullptr;
@@ -69,6 +79,7 @@ struct sg_ppo {
   float* cpart2 = nullptr;   // per-chunk column sums of dZ2 [loss_blocks(rows)][128]
   float* lpart = nullptr;    // per-chunk loss sums [loss_blocks(rows)][kLossPart]
   double* gpart = nullptr;   // block sums [kGnormBlocks]: advantage statistics, then gradient norm
+  sgk::PpoImg im{};
   std::vector<void*> allocs;
 };
 
@@ -258,6 +269,52 @@ __device__ __forceinline__ void ppo_row_loss(int J, const float (&x)[kAux], cons
   g[J] = c_v * dV * inv_b;
 }
 
+// Fragment images of the fused kernels' weights (BF16, the MFMA operand
+// order the kernels stage into LDS, in uint4 units: [fragment row][64
+// lanes] x 8 slots), kept next to the flat BF16 copy: the Adam step writes
+// every updated weight into its one or two image positions, so a
+// workgroup stages its weights with coalesced 16-byte loads. Padding
+// positions (inputs past W, outputs past O) stay zero from allocation.
+// PpoImg (above) gives the sections.
+// permuted position of K index p (0..31) within a 32-wide K block: lane
+// group g, slot s (mlp.hpp's layout)
+__device__ __forceinline__ void perm_slot(int p, int& g, int& s) {
+  if (p < 16) { g = p >> 2; s = p & 3; }
+  else { g = (p - 16) >> 2; s = 4 + ((p - 16) & 3); }
+}
+__device__ __forceinline__ void img_put(uint16_t* img, int base, int row, int lane, int slot, uint16_t v) {
+  img[((size_t)(base + row * 64 + lane)) * 8 + slot] = v;
+}
+// Writes the BF16 value v of flat parameter idx into the images that hold it
+__device__ __forceinline__ void img_scatter(const PpoImg& m, int idx, uint16_t v, uint16_t* img) {
+  int g, s;
+  if (idx >= m.oW1 && idx < m.oW1 + kH1 * m.W) {
+    const int r = (idx - m.oW1) / m.W, k = (idx - m.oW1) % m.W;
+    img_put(img, m.fW1, r >> 4, 16 * (k >> 3) + (r & 15), k & 7, v);
+  } else if (idx >= m.oW2 && idx < m.oW2 + kH2 * kH1) {
+    const int u2 = (idx - m.oW2) / kH1, u1 = (idx - m.oW2) % kH1;
+    perm_slot(u1 & 31, g, s);
+    img_put(img, m.fW2, (u2 >> 4) * (kH1 / 32) + (u1 >> 5), 16 * g + (u2 & 15), s, v);
+    img_put(img, m.fW2T, (u1 >> 4) * (kH2 / 32) + (u2 >> 5), 16 * ((u2 & 31) >> 3) + (u1 & 15), u2 & 7, v);
+  } else if (m.H3 && idx >= m.oW3 && idx < m.oW3 + m.H3 * kH2) {
+    const int u3 = (idx - m.oW3) / kH2, u2 = (idx - m.oW3) % kH2;
+    perm_slot(u2 & 31, g, s);
+    img_put(img, m.fW3, (u3 >> 4) * (kH2 / 32) + (u2 >> 5), 16 * g + (u3 & 15), s, v);
+    perm_slot(u3 & 31, g, s);
+    img_put(img, m.fW3T, (u2 >> 4) * (m.H3 / 32) + (u3 >> 5), 16 * g + (u2 & 15), s, v);
+  } else if (idx >= m.oWo && idx < m.oWo + m.O * m.KO) {
+    const int o = (idx - m.oWo) / m.KO, k = (idx - m.oWo) % m.KO;
+    perm_slot(k & 31, g, s);
+    img_put(img, m.fWo, k >> 5, 16 * g + o, s, v);
+    img_put(img, m.fWoT, k >> 4, 16 * (o >> 3) + (k & 15), o & 7, v);
+  }
+}
+__global__ void __launch_bounds__(256) k_ppo_img(PpoImg m, int n, const uint16_t* __restrict__ pb,
+                                                 uint16_t* __restrict__ img) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) img_scatter(m, i, pb[i], img);
+}
+
 // Fused front of a minibatch: per chunk of kFrontRows rows (one 16-row
 // tile per wave) the hidden layers (256, 128, and H3 = 64 for the paper's
 // Table II network) and the output layer on the matrix cores, the loss of
@@ -307,6 +364,8 @@ struct FrontArgs {
   const float* p;      // FP32 parameters (biases at oB[], oBo; log_std at oLS)
   int oW[3], oB[3], oWo, oBo, oLS;
   int W, O;
+  const uint4* img;    // the fragment images (PpoImg)
+  PpoImg im;
   PpoRows rows;
   float clip, c_v, inv_b, w_stats;
   uint16_t* H1;        // [rows][256]
@@ -321,10 +380,6 @@ struct FrontArgs {
   int nchunks;
 };
 
-__device__ __forceinline__ uint4 pack8(const uint16_t (&v)[8]) {
-  return make_uint4((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
-                    (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16));
-}
 __device__ __forceinline__ uint2 bf16x4_bits(const bf16x8& v, int h) {
   const uint32_t* u = reinterpret_cast<const uint32_t*>(&v);
   return make_uint2(u[2 * h], u[2 * h + 1]);
@@ -348,21 +403,6 @@ template <int N> __device__ __forceinline__ void row16_sums(float (&v)[N]) {
   SG_DPP_STAGE(0x124)  // row_ror 4
   SG_DPP_STAGE(0x128)  // row_ror 8
 #undef SG_DPP_STAGE
-}
-
-// Fragment f of a permuted-K image of a row-major [rows][K] BF16 matrix:
-// [row tiles][K / 32 K-blocks][64 lanes], lane 16 g + i holding row
-// 16 t + i and K 32 kb + {4g .. 4g + 3, 16 + 4g .. 16 + 4g + 3} (two
-// 8-byte runs); rows >= nrows are zero.
-template <int K>
-__device__ __forceinline__ void permk_load(const uint16_t* __restrict__ w, int f, int nrows, uint2 (&v)[2]) {
-  const int l = f & 63, tk = f >> 6, t = tk / (K / 32), kb = tk % (K / 32), row = 16 * t + (l & 15);
-  v[0] = v[1] = make_uint2(0, 0);
-  if (row < nrows) {
-    const uint16_t* src = w + (size_t)row * K + 32 * kb + 4 * (l >> 4);
-    v[0] = *reinterpret_cast<const uint2*>(src);
-    v[1] = *reinterpret_cast<const uint2*>(src + 16);
-  }
 }
 
 // Per-element activation, its derivative from the FP32 pre-activation z
@@ -405,69 +445,43 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
     const int r = c * kFrontRows + 16 * wave + i;
     if (r < R.rows) xn = *reinterpret_cast<const uint4*>(a.X + (size_t)r * kPX + 8 * g);
   }
-  // weight images in LDS: every thread issues all of its loads before its
-  // first LDS store. W1 rows are read as BF16 pairs (W is even), the
-  // permuted-K images as two 4-element runs per fragment, the transposed
-  // images element-wise
+  // weight images in LDS from their fragment-order copies: every thread
+  // issues all of its 16-byte loads before its first LDS store
   {
     constexpr int nW1 = kW1Frags / NT, nW2 = kW2Frags / NT, nW3 = S::kW3 / NT, nWoT = (S::kWoT + NT - 1) / NT,
-                  nW3T = S::kW3T / NT, KB3 = H3 ? H3 / 32 : 1;
+                  nW3T = S::kW3T / NT;
     static_assert(kW1Frags % NT == 0 && kW2Frags % NT == 0 && S::kW3 % NT == 0 && S::kW3T % NT == 0 &&
                       S::kWo <= NT && kH1 <= NT,
                   "the staging loops are exact");
-    uint32_t w1[nW1][4];
-    uint2 w2[nW2][2], w3[nW3 ? nW3 : 1][2], wo[2];
-    uint16_t wt[nWoT][8], w3t[nW3T ? nW3T : 1][8];  // (w3 and w3t unused without a third layer)
+    const PpoImg& m = a.im;
+    uint4 w1[nW1], w2[nW2], w3[nW3 ? nW3 : 1], wo, wt[nWoT], w3t[nW3T ? nW3T : 1];
 #pragma unroll
-    for (int u = 0; u < nW1; ++u) {
-      const int f = tid + NT * u, l = f & 63, row = 16 * (f >> 6) + (l & 15), k0 = 8 * (l >> 4);
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.pb + a.oW[0] + (size_t)row * a.W);
+    for (int u = 0; u < nW1; ++u) w1[u] = a.img[m.fW1 + tid + NT * u];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) w1[u][q] = k0 + 2 * q < a.W ? src[(k0 >> 1) + q] : 0u;
-    }
+    for (int u = 0; u < nW2; ++u) w2[u] = a.img[m.fW2 + tid + NT * u];
 #pragma unroll
-    for (int u = 0; u < nW2; ++u) permk_load<kH1>(a.pb + a.oW[1], tid + NT * u, kH2, w2[u]);
+    for (int u = 0; u < nW3; ++u) w3[u] = a.img[m.fW3 + tid + NT * u];
+    wo = tid < S::kWo ? a.img[m.fWo + tid] : make_uint4(0, 0, 0, 0);
 #pragma unroll
-    for (int u = 0; u < nW3; ++u) permk_load<kH2>(a.pb + a.oW[2], tid + NT * u, H3, w3[u]);
-    wo[0] = wo[1] = make_uint2(0, 0);
-    if (tid < S::kWo) permk_load<KO>(a.pb + a.oWo, tid, a.O, wo);
+    for (int u = 0; u < nWoT; ++u) wt[u] = tid + NT * u < S::kWoT ? a.img[m.fWoT + tid + NT * u] : make_uint4(0, 0, 0, 0);
 #pragma unroll
-    for (int u = 0; u < nWoT; ++u) {
-      // row tile of Wo^T (units of the last hidden layer), K = the outputs
-      // in natural order (lane group 0 holds outputs 0..7, the others zero)
-      const int f = tid + NT * u, l = f & 63, unit = 16 * (f >> 6) + (l & 15), k0 = 8 * (l >> 4);
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        wt[u][q] = f < S::kWoT && k0 + q < a.O ? a.pb[a.oWo + (size_t)(k0 + q) * KO + unit] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < nW3T; ++u) {
-      // row tile t of W3^T (units of hidden layer 2), K-block kb = hidden-3
-      // units 32 kb + the permuted K of this lane and slot
-      const int f = tid + NT * u, l = f & 63, tk = f >> 6, t = tk / KB3, kb = tk % KB3;
-      const int unit = 16 * t + (l & 15), gg = l >> 4;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int k = 32 * kb + (q < 4 ? 4 * gg + q : 16 + 4 * gg + (q - 4));
-        w3t[u][q] = a.pb[a.oW[2] + (size_t)k * kH2 + unit];
-      }
-    }
+    for (int u = 0; u < nW3T; ++u) w3t[u] = a.img[m.fW3T + tid + NT * u];
     const float b1 = tid < kH1 ? a.p[a.oB[0] + tid] : 0.f;
     const float b2 = tid < kH2 ? a.p[a.oB[1] + tid] : 0.f;
     const float b3 = tid < H3 ? a.p[a.oB[2] + tid] : 0.f;
     const float bo = tid < a.O ? a.p[a.oBo + tid] : 0.f;
 #pragma unroll
-    for (int u = 0; u < nW1; ++u) sW1[tid + NT * u] = make_uint4(w1[u][0], w1[u][1], w1[u][2], w1[u][3]);
+    for (int u = 0; u < nW1; ++u) sW1[tid + NT * u] = w1[u];
 #pragma unroll
-    for (int u = 0; u < nW2; ++u) sW2[tid + NT * u] = make_uint4(w2[u][0].x, w2[u][0].y, w2[u][1].x, w2[u][1].y);
+    for (int u = 0; u < nW2; ++u) sW2[tid + NT * u] = w2[u];
 #pragma unroll
-    for (int u = 0; u < nW3; ++u) sW3[tid + NT * u] = make_uint4(w3[u][0].x, w3[u][0].y, w3[u][1].x, w3[u][1].y);
-    if (tid < S::kWo) sWo[tid] = make_uint4(wo[0].x, wo[0].y, wo[1].x, wo[1].y);
+    for (int u = 0; u < nW3; ++u) sW3[tid + NT * u] = w3[u];
+    if (tid < S::kWo) sWo[tid] = wo;
 #pragma unroll
     for (int u = 0; u < nWoT; ++u)
-      if (tid + NT * u < S::kWoT) sWoT[tid + NT * u] = pack8(wt[u]);
+      if (tid + NT * u < S::kWoT) sWoT[tid + NT * u] = wt[u];
 #pragma unroll
-    for (int u = 0; u < nW3T; ++u) sW3T[tid + NT * u] = pack8(w3t[u]);
+    for (int u = 0; u < nW3T; ++u) sW3T[tid + NT * u] = w3t[u];
     if (tid < kH1) sb1[tid] = b1;
     if (tid < kH2) sb2[tid] = b2;
     if (tid < H3) sb3[tid] = b3;
@@ -678,6 +692,8 @@ struct Dz1Args {
   const uint16_t* D2b;  // [rows][128]
   const uint16_t* pb;   // W1 at oW0 [256][W], W2 at oW1 [128][256]
   const float* p;       // b1 at oB0
+  const uint4* img;     // the fragment images (PpoImg): W1 at fW1, W2^T at fW2T
+  int fW1, fW2T;
   int oW0, oW1, oB0, W, rows;
   uint16_t* D1b;        // [rows][256]
   float* cpart;         // [chunks][256]
@@ -697,33 +713,19 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_dz1(Dz1Args a) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, i = lane & 15;
   {
-    // loads first: W1 as BF16 pairs; W2^T fragment by fragment, eight
-    // elements of one W2 column each (lane 16 g + i of row tile t, K-block
-    // kb: W2[32 kb + 8 g + s][16 t + i]), so each fragment is one 16-byte
-    // LDS store
+    // the two images' 16-byte fragments, all loads before the LDS stores
     constexpr int nW1 = kW1Frags / NT, nW2T = kW2TFrags / NT;
     static_assert(kW1Frags % NT == 0 && kW2TFrags % NT == 0 && kH1 <= NT, "the staging loops are exact");
-    uint32_t w1[nW1][4];
-    uint16_t w2t[nW2T][8];
+    uint4 w1[nW1], w2t[nW2T];
 #pragma unroll
-    for (int u = 0; u < nW1; ++u) {
-      const int f = tid + NT * u, l = f & 63, row = 16 * (f >> 6) + (l & 15), k0 = 8 * (l >> 4);
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.pb + a.oW0 + (size_t)row * a.W);
+    for (int u = 0; u < nW1; ++u) w1[u] = a.img[a.fW1 + tid + NT * u];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) w1[u][q] = k0 + 2 * q < a.W ? src[(k0 >> 1) + q] : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < nW2T; ++u) {
-      const int f = tid + NT * u, l = f & 63, tk = f >> 6, t = tk / (kH2 / 32), kb = tk % (kH2 / 32);
-      const uint16_t* src = a.pb + a.oW1 + (size_t)(32 * kb + 8 * (l >> 4)) * kH1 + 16 * t + (l & 15);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) w2t[u][q] = src[(size_t)q * kH1];
-    }
+    for (int u = 0; u < nW2T; ++u) w2t[u] = a.img[a.fW2T + tid + NT * u];
     const float b1 = tid < kH1 ? a.p[a.oB0 + tid] : 0.f;
 #pragma unroll
-    for (int u = 0; u < nW1; ++u) sW1[tid + NT * u] = make_uint4(w1[u][0], w1[u][1], w1[u][2], w1[u][3]);
+    for (int u = 0; u < nW1; ++u) sW1[tid + NT * u] = w1[u];
 #pragma unroll
-    for (int u = 0; u < nW2T; ++u) sW2T[tid + NT * u] = pack8(w2t[u]);
+    for (int u = 0; u < nW2T; ++u) sW2T[tid + NT * u] = w2t[u];
     if (tid < kH1) sb1[tid] = b1;
   }
   __syncthreads();
@@ -894,6 +896,8 @@ struct NormAdamArgs {
   float* m;
   float* v;
   uint16_t* pb;
+  uint16_t* img;    // the fragment images, kept in step with pb
+  PpoImg im;
   float* scal;
   float c_e, max_norm, lr, b1, b2, eps;
   uint64_t* tstep;  // Adam steps taken before this one; the launch advances it by one
@@ -989,7 +993,10 @@ __global__ void __launch_bounds__(kNormAdamThreads) k_ppo_norm_adam(NormAdamArgs
   const float c1 = csh[0], c2 = csh[1];
   const int i0 = blockIdx.x * NT;
   const int i = i0 + t;
-  if (i < a.ls0) adam_one(i, a.g[i], coef, a.p, a.m, a.v, a.lr, a.b1, a.b2, a.eps, c1, c2, a.pb);
+  if (i < a.ls0) {
+    adam_one(i, a.g[i], coef, a.p, a.m, a.v, a.lr, a.b1, a.b2, a.eps, c1, c2, a.pb);
+    img_scatter(a.im, i, a.pb[i], a.img);
+  }
   if (a.ls0 >= i0 && a.ls0 < i0 + NT) {
     if (t == 0) a.scal[2] = n;
     if (a.stats) add_stats(a.lpart, a.lb, a.p + a.ls0, a.J, n, a.stats, a.w);
@@ -1066,7 +1073,7 @@ static hipError_t minibatch_grad_t(sg_ppo* o, const PpoRows& rows, const sg_ppo_
   if (!gathered) k_ppo_gather<<<gb, 256, 0, st>>>(rows, o->X);
   // forward, loss and the gradient down to dZ2 in one launch
   FrontArgs fa;
-  fa.X = o->X; fa.pb = o->pb; fa.p = o->p;
+  fa.X = o->X; fa.pb = o->pb; fa.p = o->p; fa.img = reinterpret_cast<const uint4*>(o->img); fa.im = o->im;
   for (int l = 0; l < 3; ++l) { fa.oW[l] = o->oW[l]; fa.oB[l] = o->oB[l]; }
   fa.oWo = o->oW[L]; fa.oBo = o->oB[L]; fa.oLS = o->oLS;
   fa.W = W; fa.O = O; fa.rows = rows;
@@ -1100,6 +1107,7 @@ static hipError_t minibatch_grad_t(sg_ppo* o, const PpoRows& rows, const sg_ppo_
   {
     Dz1Args da;
     da.X = o->X; da.D2b = o->D2b; da.pb = o->pb; da.p = o->p;
+    da.img = reinterpret_cast<const uint4*>(o->img); da.fW1 = o->im.fW1; da.fW2T = o->im.fW2T;
     da.oW0 = o->oW[0]; da.oW1 = o->oW[1]; da.oB0 = o->oB[0]; da.W = W; da.rows = B;
     da.D1b = o->D1b; da.cpart = o->cpart; da.nchunks = lb;
     const hipError_t e = launch_dz1<ACT>(st, da, c->n_cu);
@@ -1224,6 +1232,19 @@ sg_status sg_ppo_create(sg_ctx* c, const sg_policy_arch* arch, const float* para
     o->oLS = acc;
     o->P = acc + o->J;
   }
+  {
+    PpoImg& m = o->im;
+    m.W = o->W; m.O = o->O; m.KO = h3 ? h3 : kH2; m.H3 = h3;
+    m.oW1 = o->oW[0]; m.oW2 = o->oW[1]; m.oW3 = h3 ? o->oW[2] : 0; m.oWo = o->oW[o->nl - 1];
+    m.fW1 = 0;
+    m.fW2 = m.fW1 + kW1Frags;
+    m.fW3 = m.fW2 + kW2Frags;
+    m.fWo = m.fW3 + (h3 ? FrontShape<64>::kW3 : 0);
+    m.fWoT = m.fWo + (m.KO / 32) * 64;
+    m.fW3T = m.fWoT + (m.KO / 16) * 64;
+    m.fW2T = m.fW3T + (h3 ? FrontShape<64>::kW3T : 0);
+    m.frags = m.fW2T + kW2TFrags;
+  }
   const size_t R = (size_t)max_samples, P = (size_t)o->P;
   // split-K partials: one region per layer (launch_weight_grad_partials bound)
   o->ws_floats = 4 * kWeightGradWs;
@@ -1232,6 +1253,7 @@ sg_status sg_ppo_create(sg_ctx* c, const sg_policy_arch* arch, const float* para
   if (e == hipSuccess) e = palloc(o, &tcount, 1);  // the step count and (after it) the completion count, zeroed
   if (e == hipSuccess) { o->tstep = tcount; o->ttick = reinterpret_cast<unsigned*>(tcount + 1); }
   if (e == hipSuccess) e = palloc(o, &o->pb, P);
+  if (e == hipSuccess) e = palloc(o, &o->img, (size_t)o->im.frags * 8);
   if (e == hipSuccess) e = palloc(o, &o->g, P);
   if (e == hipSuccess) e = palloc(o, &o->m, P);
   if (e == hipSuccess) e = palloc(o, &o->v, P);
@@ -1260,6 +1282,8 @@ sg_status sg_ppo_create(sg_ctx* c, const sg_policy_arch* arch, const float* para
   if (e == hipSuccess) e = hipMemcpy(o->p, params, P * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     k_to_bf16<<<(o->P + 255) / 256, 256, 0, c->stream>>>(o->P, o->p, o->pb);
+    // (palloc zeroed the images' padding)
+    k_ppo_img<<<(o->oLS + 255) / 256, 256, 0, c->stream>>>(o->im, o->oLS, o->pb, o->img);
     e = pack_policy(o);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1359,6 +1383,7 @@ sg_status sg_ppo_update(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const sg
       NormAdamArgs na;
       na.P = o->P; na.ls0 = o->oLS; na.J = o->J;
       na.p = o->p; na.g = o->g; na.m = o->m; na.v = o->v; na.pb = o->pb; na.scal = o->scal;
+      na.img = o->img; na.im = o->im;
       na.c_e = cfg->entropy_coef; na.max_norm = cfg->max_grad_norm; na.lr = cfg->lr;
       na.b1 = cfg->beta1; na.b2 = cfg->beta2; na.eps = cfg->adam_eps;
       na.tstep = o->tstep; na.ttick = o->ttick;
