@@ -939,7 +939,7 @@ __device__ __forceinline__ void norm_adam_ticket(const NormAdamArgs& a, uint64_t
 // (which read log_std) before it updates them, and no other block writes
 // them. Blocks past the Adam blocks gather the next minibatch's rows.
 __global__ void __launch_bounds__(kNormAdamThreads) k_ppo_norm_adam(NormAdamArgs a) {
-  constexpr int NT = kNormAdamThreads, NL = 16;
+  constexpr int NT = kNormAdamThreads, NL = 12;
   __shared__ double red[NT / 64];
   __shared__ float nsh;
   __shared__ float csh[2];
