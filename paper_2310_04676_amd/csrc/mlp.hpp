@@ -93,15 +93,23 @@ __device__ __forceinline__ void stage_input(uint4* xs, int lane, const float* x,
 // The forward pass for NT of the 4 staged 16-env tiles, starting at tile
 // t0 (a wave computes all four, or each of four waves one). ws: weight
 // image, bias: bias image, xs: staged inputs, os: output image [64
-// envs][16] floats. Callers synchronize around it.
-template <int H3, int ACT, int NT = 4>
+// envs][16] floats. With W1G the image in ws starts at W2 and layer 1's
+// fragments come from w1 (the global image; all 16 loaded at the start).
+// Callers synchronize around it.
+template <int H3, int ACT, int NT = 4, bool W1G = false>
 __device__ __forceinline__ void mlp_wave(const uint4* __restrict__ ws, const float* __restrict__ bias,
-                                         const uint4* __restrict__ xs, float* __restrict__ os, int lane, int t0 = 0) {
+                                         const uint4* __restrict__ xs, float* __restrict__ os, int lane, int t0 = 0,
+                                         const uint4* __restrict__ w1 = nullptr) {
   using S = PolicyShape<H3>;
   const int g = lane >> 4, j = lane & 15;
-  const uint4* W1 = ws;
-  const uint4* W2 = ws + kW1Frags;
+  const uint4* W1 = W1G ? w1 : ws;
+  const uint4* W2 = W1G ? ws : ws + kW1Frags;
   const uint4* W3 = W2 + kW2Frags;
+  uint4 w1r[W1G ? kW1Frags / 64 : 1];
+  if constexpr (W1G) {
+#pragma unroll
+    for (int m = 0; m < kW1Frags / 64; ++m) w1r[m] = W1[m * 64 + lane];
+  }
   const uint4* Wo = W3 + S::kW3Frags;
   const float* bo = bias + kH1 + kH2 + H3;
   bf16x8 xb[NT];
@@ -123,7 +131,7 @@ __device__ __forceinline__ void mlp_wave(const uint4* __restrict__ ws, const flo
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int m = 2 * kb + h;
-      uint4 t = W1[m * 64 + lane];
+      uint4 t = W1G ? w1r[m] : W1[m * 64 + lane];
       const bf16x8 a = *reinterpret_cast<bf16x8*>(&t);
       const float4 bb = *reinterpret_cast<const float4*>(bias + 16 * m + 4 * g);
 #pragma unroll

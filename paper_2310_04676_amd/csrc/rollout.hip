@@ -11,12 +11,20 @@ constexpr int kXMax = 32;  // observation width padded to the first layer's K
 
 // LDS layout of the rollout kernel (bytes): weight image, bias image,
 // staged inputs, outputs, link parameters
-template <int H3> constexpr size_t lds_w_bytes() { return (size_t)PolicyShape<H3>::kWFrags * 16; }
+// With a wave team, the Table II network's image does not fit beside the
+// team's exchange: its layer-1 fragments (16 KB) are then read from the
+// global image (L2) instead of LDS.
+template <int H3, bool TEAM> constexpr bool w1_global() { return TEAM && H3 > 0; }
+template <int H3, bool TEAM = false> constexpr size_t lds_w_bytes() {
+  return (size_t)(PolicyShape<H3>::kWFrags - (w1_global<H3, TEAM>() ? kW1Frags : 0)) * 16;
+}
 template <int H3> constexpr size_t lds_bias_bytes() { return (size_t)PolicyShape<H3>::kBias * 4; }
 constexpr size_t kLdsX = 256 * 16;
 constexpr size_t kLdsO = (size_t)kWave * kOut * 4;
 template <int J> constexpr size_t lds_par_bytes() { return (size_t)P_NSTAGE * J * kWave * 4; }
-template <int H3> constexpr size_t policy_lds_bytes() { return lds_w_bytes<H3>() + lds_bias_bytes<H3>() + kLdsX + kLdsO; }
+template <int H3, bool TEAM = false> constexpr size_t policy_lds_bytes() {
+  return lds_w_bytes<H3, TEAM>() + lds_bias_bytes<H3>() + kLdsX + kLdsO;
+}
 // ... plus, with a wave team, the links the helper waves hand back (the
 // published state reuses the staged-input area, idle during the physics),
 // plus the exploration noise the helper waves draw one step ahead: two
@@ -24,11 +32,12 @@ template <int H3> constexpr size_t policy_lds_bytes() { return lds_w_bytes<H3>()
 constexpr int kNoiseBlocks = 2;  // Philox blocks of four normals: chains of up to 7 joints
 constexpr size_t kLdsEps = (size_t)2 * kNoiseBlocks * kWave * 16;
 template <int J, int H3, bool TEAM = false> constexpr size_t rollout_lds_bytes() {
-  return policy_lds_bytes<H3>() + lds_par_bytes<J>() + (TEAM ? team_lds_bytes(J) : 0) + kLdsEps;
+  return policy_lds_bytes<H3, TEAM>() + lds_par_bytes<J>() + (TEAM ? team_lds_bytes(J) : 0) + kLdsEps;
 }
 constexpr size_t kLdsMax = 160 * 1024;
 static_assert(rollout_lds_bytes<7, 64>() <= kLdsMax, "the Table II network's rollout fits the LDS");
 static_assert(rollout_lds_bytes<7, 0, true>() <= kLdsMax, "the 7-joint team rollout fits the LDS");
+static_assert(rollout_lds_bytes<7, 64, true>() <= kLdsMax, "the Table II network's 7-joint team rollout fits the LDS");
 static_assert((size_t)team_state_slots(7) * 64 * 16 <= kLdsX, "the team state fits the staged-input area");
 // a wave team where its exchange fits next to the weight image
 template <int J, int H3> constexpr bool team_fits() { return J >= 4 && rollout_lds_bytes<J, H3, true>() <= kLdsMax; }
@@ -94,10 +103,12 @@ __device__ __forceinline__ void gae_env(int T, int n, int e, const float* __rest
   }
 }
 
+// the weight image from fragment f0 on (f0 = kW1Frags: layer 1 stays in
+// the global image) and the bias image
 template <int H3>
 __device__ __forceinline__ void fill_weights(uint4* sw, float* sb, const uint4* __restrict__ wimg,
-                                             const float* __restrict__ bias, int tid, int nthreads) {
-  for (int i = tid; i < PolicyShape<H3>::kWFrags; i += nthreads) sw[i] = wimg[i];
+                                             const float* __restrict__ bias, int tid, int nthreads, int f0 = 0) {
+  for (int i = tid; i < PolicyShape<H3>::kWFrags - f0; i += nthreads) sw[i] = wimg[f0 + i];
   for (int i = tid; i < PolicyShape<H3>::kBias; i += nthreads) sb[i] = bias[i];
 }
 
@@ -116,7 +127,8 @@ static_assert(kRollWaves == kTeam, "the rollout's waves form one team");
 template <int J, int M, int H3, int ACT, bool TEAM>
 __global__ void __launch_bounds__(kWave * kRollWaves) k_rollout(RollArgs A) {
   extern __shared__ __align__(16) unsigned char lds[];
-  constexpr size_t kLdsW = lds_w_bytes<H3>(), kLdsBias = lds_bias_bytes<H3>();
+  constexpr bool kW1G = w1_global<H3, TEAM>();
+  constexpr size_t kLdsW = lds_w_bytes<H3, TEAM>(), kLdsBias = lds_bias_bytes<H3>();
   uint4* s_w = reinterpret_cast<uint4*>(lds);
   float* s_b = reinterpret_cast<float*>(lds + kLdsW);
   uint4* s_x = reinterpret_cast<uint4*>(lds + kLdsW + kLdsBias);
@@ -151,7 +163,7 @@ __global__ void __launch_bounds__(kWave * kRollWaves) k_rollout(RollArgs A) {
     }
   };
 
-  fill_weights<H3>(s_w, s_b, A.wimg, A.bias, threadIdx.x, kWave * kRollWaves);
+  fill_weights<H3>(s_w, s_b, A.wimg, A.bias, threadIdx.x, kWave * kRollWaves, kW1G ? kW1Frags : 0);
   if (phys) stage_chain<float, J>(E, e, active ? n : 0, lane, s_p);
   draw(0);
   __syncthreads();
@@ -187,7 +199,7 @@ __global__ void __launch_bounds__(kWave * kRollWaves) k_rollout(RollArgs A) {
   for (int t = 0; t <= A.T; ++t) {
     if (phys) stage_input(s_x, lane, x, Wd);
     __syncthreads();
-    mlp_wave<H3, ACT, 1>(s_w, s_b, s_x, s_o, lane, wave);
+    mlp_wave<H3, ACT, 1, kW1G>(s_w, s_b, s_x, s_o, lane, wave, A.wimg);
     __syncthreads();
     if (!phys) {
       if (t == A.T) break;

@@ -47,10 +47,14 @@ def test_policy_forward_matches_oracle(sg, n):
     assert np.abs(oracle.Oracle(w.robot, w.task, tanh).mlp(x.astype(np.float64), emulate=True) - ref).max() > 1e-2
 
 
-def test_rollout_replay(sg):
+@pytest.mark.parametrize("team", [1, 0])
+def test_rollout_replay(sg, team):
+    """One wave per 64 envs (team 1), and the library's default (0), which
+    for this network is the wave team with layer 1's weights read from the
+    global image."""
     from test_gpu_rollout import _replay_rollout
     w = _workload(300)
-    _replay_rollout(sg, w, 16)
+    _replay_rollout(sg, w, 16, team=team)
 
 
 def test_ppo_minibatch_gradient_matches_oracle(sg):
