@@ -70,10 +70,10 @@ struct GemmArgs {
   float* colpart;    // EPI_BWD_DX: per-block column sums of the result [gridDim.y][N] (may be null)
 };
 
-// At most 64 VGPRs (8 waves per SIMD), so 8 blocks fit on a CU: the wide
-// forward and data-gradient GEMMs launch 8 blocks per CU.
+// One 64x64 output tile (block lin of a gx x gy x gz grid) of the GEMM g,
+// for k_gemm and the grouped launch k_gemm_group.
 template <int EPI, bool AT, bool BT, int ACT>
-__global__ void __launch_bounds__(256, 8) k_gemm(GemmArgs g) {
+__device__ __forceinline__ void gemm_block(const GemmArgs& g, int lin, int gx, int gy, int gz) {
   // LDS tiles [row][k], 32 k + 8 pad; the four 8-k blocks of a row are
   // stored XOR-swizzled by (row / 8) mod 4, which spreads the transposing
   // stores below (one column of eight rows 8 apart per instruction) over
@@ -86,8 +86,7 @@ __global__ void __launch_bounds__(256, 8) k_gemm(GemmArgs g) {
   // the remap hands each XCD a contiguous range of tiles (x fastest), so the
   // tiles that share a row slab (and a K-chunk) run on one XCD and re-read
   // it from that XCD's L2 instead of across the fabric.
-  const int gx = gridDim.x, gy = gridDim.y, nblk = gx * gy * gridDim.z;
-  int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int nblk = gx * gy * gz;
   if ((nblk & 7) == 0) lin = (lin & 7) * (nblk >> 3) + (lin >> 3);
   const int bx = lin % gx, by = (lin / gx) % gy, bz = lin / (gx * gy);
   const int m0 = by * 64, n0 = bx * 64;
@@ -256,6 +255,32 @@ __global__ void __launch_bounds__(256, 8) k_gemm(GemmArgs g) {
   }
 }
 
+// At most 64 VGPRs (8 waves per SIMD), so 8 blocks fit on a CU: the wide
+// forward and data-gradient GEMMs launch 8 blocks per CU.
+template <int EPI, bool AT, bool BT, int ACT>
+__global__ void __launch_bounds__(256, 8) k_gemm(GemmArgs g) {
+  gemm_block<EPI, AT, BT, ACT>(g, blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), gridDim.x,
+                               gridDim.y, gridDim.z);
+}
+
+// Up to kMaxGemmGroup GEMMs of one kind in one launch: blocks [blk0[k],
+// blk0[k + 1]) are GEMM k's grid gx[k] x gy[k] x gz[k] (each a multiple of
+// 8 blocks where the XCD remap applies, so the groups' blocks keep their
+// XCD assignment).
+constexpr int kMaxGemmGroup = 4;
+struct GemmGroup {
+  GemmArgs g[kMaxGemmGroup];
+  int gx[kMaxGemmGroup], gy[kMaxGemmGroup], gz[kMaxGemmGroup];
+  int blk0[kMaxGemmGroup + 1];
+  int count;
+};
+template <int EPI, bool AT, bool BT, int ACT>
+__global__ void __launch_bounds__(256, 8) k_gemm_group(GemmGroup a) {
+  int k = 0;
+  while (k + 1 < a.count && (int)blockIdx.x >= a.blk0[k + 1]) ++k;
+  gemm_block<EPI, AT, BT, ACT>(a.g[k], (int)blockIdx.x - a.blk0[k], a.gx[k], a.gy[k], a.gz[k]);
+}
+
 template <int EPI, bool AT, bool BT, int ACT>
 static inline void launch_gemm(hipStream_t s, const GemmArgs& a, int splits = 1) {
   dim3 grid((a.N + 63) / 64, (a.M + 63) / 64, EPI == EPI_PARTIAL ? splits : 1);
@@ -364,6 +389,35 @@ static inline SumJob launch_weight_grad_partials(hipStream_t st, int M, int N, i
   launch_gemm<EPI_PARTIAL, true, false, ACT>(st, g, S_eff);
   return sum_job(ws, S_eff, M, N, out, ldo, 0);
 }
+// Several weight gradients (split-K partials) in one grouped launch: add()
+// sets up one and returns the job that sums its partials; launch() runs
+// them all.
+template <int ACT> struct WeightGradGroup {
+  GemmGroup grp{};
+  int blocks = 0;
+  SumJob add(int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb, float* out, int ldo,
+             float* ws) {
+    const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    const int S = splits_for(tiles, K);
+    GemmArgs& g = grp.g[grp.count];
+    g = GemmArgs{};
+    g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = ws; g.ldc = N;
+    g.kchunk = chunk_for(K, S);
+    const int S_eff = (K + g.kchunk - 1) / g.kchunk;
+    grp.gx[grp.count] = (N + 63) / 64;
+    grp.gy[grp.count] = (M + 63) / 64;
+    grp.gz[grp.count] = S_eff;
+    grp.blk0[grp.count] = blocks;
+    blocks += grp.gx[grp.count] * grp.gy[grp.count] * S_eff;
+    ++grp.count;
+    return sum_job(ws, S_eff, M, N, out, ldo, 0);
+  }
+  void launch(hipStream_t st) {
+    grp.blk0[grp.count] = blocks;
+    if (grp.count) k_gemm_group<EPI_PARTIAL, true, false, ACT><<<blocks, 256, 0, st>>>(grp);
+  }
+};
+
 // The same with the split sums launched at once, sharing their launch with
 // `bias`, the reduction of a bias gradient's per-block partial rows.
 template <int ACT>

@@ -14,15 +14,17 @@
 //   k_ppo_front    the forward pass, the loss and the gradient down to
 //                  hidden layer 2's pre-activations in one launch on the
 //                  matrix cores, activations in registers
-//   backward       data gradients as GEMMs with the act' epilogue, which
-//                  also emits per-block column sums (the hidden biases'
-//                  gradients; layer 1's pre-activations are recomputed
-//                  there from its W = 2J + 10 inputs); weight gradients as
-//                  split-K GEMMs (the batch is the reduction axis); every
-//                  partial is summed in a fixed order -- deterministic; the
-//                  split sums and bias sums share one launch (k_sum_jobs)
+//   k_ppo_dz1      hidden layer 1's gradient (its pre-activations
+//                  recomputed from the W = 2J + 10 inputs) with per-chunk
+//                  column sums (the hidden-1 bias gradient)
+//   backward       weight gradients as split-K GEMMs (nn.hpp; the batch is
+//                  the reduction axis), all of a minibatch's in one grouped
+//                  launch; every partial is summed in a fixed order --
+//                  deterministic; the split sums and bias sums share one
+//                  launch (k_sum_jobs)
 //   k_ppo_norm_adam  entropy term, global gradient norm, statistics, norm
-//                  clip and Adam on the FP32 master weights + BF16 copy, in
+//                  clip and Adam on the FP32 master weights + BF16 copy (and
+//                  the fused kernels' fragment-order weight images), in
 //                  one launch (sg_ppo_grad: k_gnorm_part and k_ppo_finish
 //                  give the norm and statistics without the Adam step)
 // After an update k_ppo_pack rewrites the context's rollout weight image
@@ -1051,13 +1053,6 @@ __global__ void __launch_bounds__(256) k_zero(float* __restrict__ x, int n) {
   if (i < n) x[i] = 0.f;
 }
 
-// dW [M][N] (leading dim ldo) over the minibatch: the split-K GEMM into
-// layer l's region of o->ws; returns the job that sums the partials.
-static SumJob weight_grad(sg_ppo* o, hipStream_t st, int l, int M, int N, int K, const uint16_t* A, int lda,
-                          const uint16_t* B, int ldb, float* out, int ldo) {
-  return launch_weight_grad_partials<ACT_TANH>(st, M, N, K, A, lda, B, ldb, out, ldo, o->ws + l * kWeightGradWs);
-}
-
 // Gradient of one minibatch into o->g. With `finish`, the entropy term is
 // added to o->g, its norm goes to scal[2] and the statistics (weight
 // w_stats) to stats; without, k_ppo_norm_adam does both next. ACT: the
@@ -1093,14 +1088,15 @@ static hipError_t minibatch_grad_t(sg_ppo* o, const PpoRows& rows, const sg_ppo_
   // flat vector (oLS = oB[L] + O).
   SumJob jobs[8];
   int nj = 0;
+  WeightGradGroup<ACT_TANH> wg;  // all weight gradients in one launch, after hidden layer 1's gradient
   const int hl = h3 ? h3 : kH2;
-  jobs[nj++] = weight_grad(o, st, 3, O, hl, B, o->G3b, kPO, h3 ? o->H3 : o->H2, hl, o->g + o->oW[L], hl);
+  jobs[nj++] = wg.add(O, hl, B, o->G3b, kPO, h3 ? o->H3 : o->H2, hl, o->g + o->oW[L], hl, o->ws + 3 * kWeightGradWs);
   jobs[nj++] = partial_rows(o->lpart, lb, O + J, kLossPart, o->g + o->oB[L]);
   if (h3) {
-    jobs[nj++] = weight_grad(o, st, 2, h3, kH2, B, o->D3b, h3, o->H2, kH2, o->g + o->oW[2], kH2);
+    jobs[nj++] = wg.add(h3, kH2, B, o->D3b, h3, o->H2, kH2, o->g + o->oW[2], kH2, o->ws + 2 * kWeightGradWs);
     jobs[nj++] = partial_rows(o->cpart3, lb, h3, h3, o->g + o->oB[2]);
   }
-  jobs[nj++] = weight_grad(o, st, 1, kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->oW[1], kH1);
+  jobs[nj++] = wg.add(kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->oW[1], kH1, o->ws + 1 * kWeightGradWs);
   jobs[nj++] = partial_rows(o->cpart2, lb, kH2, kH2, o->g + o->oB[1]);
   // dZ1 = (dZ2 W2) * act'(Z1), with the column sums of dZ1 (hidden-1 bias);
   // Z1 (W inputs) is recomputed rather than stored
@@ -1113,8 +1109,9 @@ static hipError_t minibatch_grad_t(sg_ppo* o, const PpoRows& rows, const sg_ppo_
     const hipError_t e = launch_dz1<ACT>(st, da, c->n_cu);
     if (e != hipSuccess) return e;
   }
-  jobs[nj++] = weight_grad(o, st, 0, kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->oW[0], W);
+  jobs[nj++] = wg.add(kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->oW[0], W, o->ws + 0 * kWeightGradWs);
   jobs[nj++] = partial_rows(o->cpart, lb, kH1, kH1, o->g + o->oB[0]);
+  wg.launch(st);
   launch_sums(st, jobs, nj);
   if (finish) {
     const int nb = (o->P + kGnormChunk - 1) / kGnormChunk;
