@@ -757,8 +757,8 @@ struct sg_surrogate {
   // training scratch
   uint16_t* X[kSL] = {};   // layer inputs [B][in] bf16
   float* Z[kSL] = {};      // pre-activations [B][out]
-  uint16_t* Gb = nullptr;  // gradient [B][256] bf16
-  uint16_t* Gb2 = nullptr;
+  uint16_t* Gb = nullptr;  // gradient [B][256] bf16 of layer 3's outputs (the loss), then of layers 2, 1, 0 in G[]
+  uint16_t* G[3] = {nullptr, nullptr, nullptr};  // each layer's output gradient, kept for the grouped weight gradients
   float* ws = nullptr;     // split-K partials of the weight gradients, one kWeightGradWs region per layer
   float* cpart = nullptr;  // per-block column sums of the hidden layers' gradients [kSL - 1][B / 64][256]
   float* lpart = nullptr;  // k_loss block sums [B / 256][kSLossRow]
@@ -844,21 +844,24 @@ hipError_t forward_backward(sg_surrogate* s, hipStream_t st, const float* q, con
     }
   }
   uint16_t* Gbc = s->Gb;
-  uint16_t* Gbn = s->Gb2;
   const int gb = (B + 255) / 256, rb = (B + 63) / 64;
   k_loss<<<gb, 256, 0, st>>>(s->Z[kSL - 1], qdd, n_total, idx, B, s->J, s->norm, Gbc, s->lpart);
-  // Weight gradients as split-K partials (layer l in region l of ws); their
-  // sums, the bias sums and the loss (adjacent to the output layer's bias
-  // gradient in gb[kSL - 1]) run as one launch of 2 kSL jobs at the end.
+  // Weight gradients as split-K partials (layer l in region l of ws), all
+  // four in one grouped launch once the data gradients are done (each
+  // layer's output gradient has a buffer of its own); their sums, the bias
+  // sums and the loss (adjacent to the output layer's bias gradient in
+  // gb[kSL - 1]) run as one launch of 2 kSL jobs at the end.
   SumJob jobs[2 * kSL];
   int nj = 0;
+  WeightGradGroup<ACT_ELU> wg;
   jobs[nj++] = partial_rows(s->lpart, gb, kSO + 1, kSLossRow, s->gb[kSL - 1]);
   const size_t cstride = (size_t)((s->maxB + 63) / 64) * kSH;
   for (int l = kSL - 1; l >= 0; --l) {
     // dW[o][i] = sum_b G[b][o] X[b][i]
-    jobs[nj++] = launch_weight_grad_partials<ACT_ELU>(st, s_out(l), s_in(l), B, Gbc, s_out(l), s->X[l], s_in(l),
-                                                      s->gW[l], s_in(l), s->ws + (size_t)l * kWeightGradWs);
+    jobs[nj++] = wg.add(s_out(l), s_in(l), B, Gbc, s_out(l), s->X[l], s_in(l), s->gW[l], s_in(l),
+                        s->ws + (size_t)l * kWeightGradWs);
     if (l == 0) break;
+    uint16_t* Gbn = s->G[l - 1];
     // G_prev[b][i] = (sum_o G[b][o] W[o][i]) * elu'(Z_prev[b][i]), with the
     // per-block column sums of G_prev (the previous layer's bias gradient)
     GemmArgs d{};
@@ -871,8 +874,9 @@ hipError_t forward_backward(sg_surrogate* s, hipStream_t st, const float* q, con
     d.colpart = s->cpart + (size_t)(l - 1) * cstride;
     launch_gemm<EPI_BWD_DX, false, false, ACT_ELU>(st, d);
     jobs[nj++] = partial_rows(d.colpart, rb, s_out(l - 1), s_out(l - 1), s->gb[l - 1]);
-    std::swap(Gbc, Gbn);
+    Gbc = Gbn;
   }
+  wg.launch(st);
   launch_sums(st, jobs, nj);
   return hipGetLastError();
 }
@@ -913,7 +917,7 @@ sg_status sg_surrogate_create(sg_ctx* c, int32_t max_batch, sg_surrogate** out) 
   if (e == hipSuccess) e = dalloc(s, &s->img_ch, (size_t)kSFrags * 8);
   if (e == hipSuccess) e = dalloc(s, &s->norm, 2 * kSF + 2 * kSO);
   if (e == hipSuccess) e = dalloc(s, &s->Gb, B * kSH);
-  if (e == hipSuccess) e = dalloc(s, &s->Gb2, B * kSH);
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) e = dalloc(s, &s->G[l], B * kSH);
   if (e == hipSuccess) e = dalloc(s, &s->ws, kSL * kWeightGradWs);
   if (e == hipSuccess) e = dalloc(s, &s->cpart, (kSL - 1) * ((B + 63) / 64) * (size_t)kSH);
   if (e == hipSuccess) e = dalloc(s, &s->lpart, ((B + 255) / 256) * (size_t)kSLossRow);
