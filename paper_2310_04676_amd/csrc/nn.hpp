@@ -310,8 +310,20 @@ static inline int sum_job_blocks(const SumJob& j) {
   const int per = 256 / j.groups;
   return (j.M * j.N + per - 1) / per;
 }
-// Block blk of job j (256 threads).
-__device__ __forceinline__ void sum_block(const SumJob& j, int blk) {
+// Optional squared-norm partials of the summed values (the PPO update's
+// gradient clip): an output at flat index [adj0, adj0 + adjn) of the vector
+// at base is shifted by -adj before squaring (the entropy term on log_std),
+// and block b of the launch writes its sum of squares (double, in a fixed
+// order) to npart[b]. npart null: none.
+struct SumNorm {
+  const float* base;
+  int adj0, adjn;
+  float adj;
+  double* npart;
+};
+// Block blk of job j (256 threads); returns this thread's squared
+// contribution to the norm partial (0 unless nm.npart).
+__device__ __forceinline__ double sum_block(const SumJob& j, int blk, const SumNorm& nm = SumNorm{}) {
   __shared__ float red[256];
   const int G = j.groups, per = 256 / G;
   const int slot = threadIdx.x % per, grp = threadIdx.x / per;
@@ -323,11 +335,19 @@ __device__ __forceinline__ void sum_block(const SumJob& j, int blk) {
     for (int z = grp; z < j.splits; z += G) s += j.part[(size_t)z * st + o];
   red[threadIdx.x] = s;
   __syncthreads();
+  double sq = 0;
   if (grp == 0 && o < MN) {
     float t = 0.f;
     for (int k = 0; k < G; ++k) t += red[k * per + slot];
-    j.out[(size_t)(o / j.N) * j.ldo + o % j.N] = t;
+    float* dst = j.out + (size_t)(o / j.N) * j.ldo + o % j.N;
+    *dst = t;
+    if (nm.npart) {
+      const long idx = dst - nm.base;
+      const float v = idx >= nm.adj0 && idx < nm.adj0 + nm.adjn ? t - nm.adj : t;
+      sq = (double)v * v;
+    }
   }
+  return sq;
 }
 static __global__ void __launch_bounds__(256) k_sum_two(SumJob a, int blocks_a, SumJob b) {
   if ((int)blockIdx.x < blocks_a) sum_block(a, blockIdx.x);
@@ -340,15 +360,28 @@ struct SumJobs {
   SumJob j[kMaxSumJobs];
   int blk0[kMaxSumJobs + 1];
   int count;
+  SumNorm nm;
 };
 static __global__ void __launch_bounds__(256) k_sum_jobs(SumJobs a) {
   int k = 0;
   while (k + 1 < a.count && (int)blockIdx.x >= a.blk0[k + 1]) ++k;
-  sum_block(a.j[k], blockIdx.x - a.blk0[k]);
+  double sq = sum_block(a.j[k], blockIdx.x - a.blk0[k], a.nm);
+  if (a.nm.npart) {
+    // the block's sum of squares: wave butterflies, then the four waves in order
+    __shared__ double wsum[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) a.nm.npart[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+  }
 }
-static inline void launch_sums(hipStream_t st, const SumJob* jobs, int n) {
+// Launches the jobs (with norm partials if nm.npart); returns the number of
+// blocks (= norm partials written).
+static inline int launch_sums(hipStream_t st, const SumJob* jobs, int n, const SumNorm& nm = SumNorm{}) {
   SumJobs a{};
   a.count = n;
+  a.nm = nm;
   int b = 0;
   for (int k = 0; k < n; ++k) {
     a.j[k] = jobs[k];
@@ -357,6 +390,7 @@ static inline void launch_sums(hipStream_t st, const SumJob* jobs, int n) {
   }
   a.blk0[n] = b;
   k_sum_jobs<<<b, 256, 0, st>>>(a);
+  return b;
 }
 
 // Split-K shape for a weight gradient: about 256 blocks over the output

@@ -81,6 +81,8 @@ struct sg_ppo {
   float* cpart2 = nullptr;   // per-chunk column sums of dZ2 [loss_blocks(rows)][128]
   float* lpart = nullptr;    // per-chunk loss sums [loss_blocks(rows)][kLossPart]
   double* gpart = nullptr;   // block sums [kGnormBlocks]: advantage statistics, then gradient norm
+  double* npart = nullptr;   // the last minibatch's gradient-norm partials [kNormParts] (from k_sum_jobs)
+  int nparts = 0;            // how many (0: k_ppo_norm_adam sums the gradient itself)
   sgk::PpoImg im{};
   std::vector<void*> allocs;
 };
@@ -98,6 +100,7 @@ constexpr int kPO = 8;    // padded output width (J + 1 <= 8)
 constexpr int kLossPart = 20;
 constexpr int kGnormChunk = 1024;  // gradient entries per k_gnorm_part block
 constexpr int kGnormBlocks = 128;  // capacity of the partial-sum buffer (norm; advantage statistics)
+constexpr int kNormParts = 16384;  // capacity of the sum launch's gradient-norm partials
 
 struct PpoRows {
   const float* obs;   // [T+1][W][N]
@@ -906,6 +909,8 @@ struct NormAdamArgs {
   unsigned* ttick;
   const float* lpart;
   int lb;
+  const double* npart;  // the gradient's squared-norm partials (entropy term included), nparts of them;
+  int nparts;           // 0: sum the gradient here
   float* stats;
   float w;
   int nadam;       // blocks [0, nadam) take the Adam step
@@ -954,10 +959,12 @@ __global__ void __launch_bounds__(kNormAdamThreads) k_ppo_norm_adam(NormAdamArgs
     return;
   }
   const uint64_t step = __atomic_load_n(a.tstep, __ATOMIC_RELAXED) + 1;
-  // entries below ls0 as 16-byte vectors, NL loads in flight per thread;
-  // the rest (at most 3 + J entries) one per thread
   double s = 0;
-  const int n4 = a.ls0 >> 2;
+  // the squared norm: from the sum launch's partials when it wrote them,
+  // else entries below ls0 as 16-byte vectors, NL loads in flight per
+  // thread, the rest (at most 3 + J entries) one per thread
+  const int n4 = a.nparts > 0 ? 0 : a.ls0 >> 2;
+  for (int i = t; i < a.nparts; i += NT) s += a.npart[i];
   const float4* g4 = reinterpret_cast<const float4*>(a.g);
   for (int base = 0; base < n4; base += NL * NT) {
     float4 x[NL];
@@ -970,7 +977,7 @@ __global__ void __launch_bounds__(kNormAdamThreads) k_ppo_norm_adam(NormAdamArgs
     for (int u = 0; u < NL; ++u)
       s += ((double)x[u].x * x[u].x + (double)x[u].y * x[u].y) + ((double)x[u].z * x[u].z + (double)x[u].w * x[u].w);
   }
-  for (int i = 4 * n4 + t; i < a.P; i += NT) {
+  for (int i = 4 * n4 + t; a.nparts == 0 && i < a.P; i += NT) {
     float gi = a.g[i];
     if (i >= a.ls0) gi -= a.c_e;
     s += (double)gi * gi;
@@ -1112,7 +1119,18 @@ static hipError_t minibatch_grad_t(sg_ppo* o, const PpoRows& rows, const sg_ppo_
   jobs[nj++] = wg.add(kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->oW[0], W, o->ws + 0 * kWeightGradWs);
   jobs[nj++] = partial_rows(o->cpart, lb, kH1, kH1, o->g + o->oB[0]);
   wg.launch(st);
-  launch_sums(st, jobs, nj);
+  {
+    // with the Adam step next, the sums also leave the gradient's
+    // squared-norm partials for it
+    SumNorm nm{};
+    int blocks = 0;
+    for (int k = 0; k < nj; ++k) blocks += sum_job_blocks(jobs[k]);
+    if (!finish && blocks <= kNormParts) {
+      nm.base = o->g; nm.adj0 = o->oLS; nm.adjn = J; nm.adj = cfg->entropy_coef; nm.npart = o->npart;
+    }
+    const int nb = launch_sums(st, jobs, nj, nm);
+    o->nparts = nm.npart ? nb : 0;
+  }
   if (finish) {
     const int nb = (o->P + kGnormChunk - 1) / kGnormChunk;
     k_gnorm_part<<<nb, 256, 0, st>>>(o->g, o->P, o->oLS, J, cfg->entropy_coef, o->gpart);
@@ -1272,6 +1290,7 @@ sg_status sg_ppo_create(sg_ctx* c, const sg_policy_arch* arch, const float* para
   if (e == hipSuccess) e = palloc(o, &o->cpart2, (size_t)loss_blocks((int)R) * kH2);
   if (e == hipSuccess) e = palloc(o, &o->lpart, (size_t)loss_blocks((int)R) * kLossPart);
   if (e == hipSuccess) e = palloc(o, &o->gpart, (size_t)kGnormBlocks);
+  if (e == hipSuccess) e = palloc(o, &o->npart, (size_t)kNormParts);
   if (e == hipSuccess && (o->P + kGnormChunk - 1) / kGnormChunk > kGnormBlocks) e = hipErrorInvalidValue;
   if (e == hipSuccess && !c->w_bf16) e = hipMalloc((void**)&c->w_bf16, (size_t)kWFragsMax * 16);
   if (e == hipSuccess && !c->bias) e = hipMalloc((void**)&c->bias, (size_t)kBiasMax * sizeof(float));
@@ -1385,6 +1404,7 @@ sg_status sg_ppo_update(sg_ppo* o, const sg_rollout_bufs* b, int32_t T, const sg
       na.b1 = cfg->beta1; na.b2 = cfg->beta2; na.eps = cfg->adam_eps;
       na.tstep = o->tstep; na.ttick = o->ttick;
       na.lpart = o->lpart; na.lb = loss_blocks(mb); na.stats = stats; na.w = w;
+      na.npart = o->npart; na.nparts = o->nparts;
       na.nadam = (o->P + kNormAdamThreads - 1) / kNormAdamThreads;
       const bool last = k + 1 == cfg->minibatches && ep + 1 == cfg->epochs;
       na.next = last ? PpoRows{} : rows_at(k + 1 < cfg->minibatches ? ep : ep + 1, (k + 1) % cfg->minibatches);
