@@ -12,11 +12,9 @@
 //                  only for the first minibatch: later ones are gathered
 //                  by extra blocks of the previous k_ppo_norm_adam launch)
 //   k_ppo_front    the forward pass, the loss and the gradient down to
-//                  hidden layer 2's pre-activations in one launch on the
-//                  matrix cores, activations in registers
-//   k_ppo_dz1      hidden layer 1's gradient (its pre-activations
-//                  recomputed from the W = 2J + 10 inputs) with per-chunk
-//                  column sums (the hidden-1 bias gradient)
+//                  hidden layer 1's pre-activations in one launch on the
+//                  matrix cores, activations and act' in registers, with
+//                  per-chunk column sums (the hidden biases' gradients)
 //   backward       weight gradients as split-K GEMMs (nn.hpp; the batch is
 //                  the reduction axis), all of a minibatch's in one grouped
 //                  launch; every partial is summed in a fixed order --
@@ -300,7 +298,8 @@ __device__ __forceinline__ void img_scatter(const PpoImg& m, int idx, uint16_t v
     const int u2 = (idx - m.oW2) / kH1, u1 = (idx - m.oW2) % kH1;
     perm_slot(u1 & 31, g, s);
     img_put(img, m.fW2, (u2 >> 4) * (kH1 / 32) + (u1 >> 5), 16 * g + (u2 & 15), s, v);
-    img_put(img, m.fW2T, (u1 >> 4) * (kH2 / 32) + (u2 >> 5), 16 * ((u2 & 31) >> 3) + (u1 & 15), u2 & 7, v);
+    perm_slot(u2 & 31, g, s);
+    img_put(img, m.fW2T, (u1 >> 4) * (kH2 / 32) + (u2 >> 5), 16 * g + (u1 & 15), s, v);
   } else if (m.H3 && idx >= m.oW3 && idx < m.oW3 + m.H3 * kH2) {
     const int u3 = (idx - m.oW3) / kH2, u2 = (idx - m.oW3) % kH2;
     perm_slot(u2 & 31, g, s);
@@ -324,23 +323,23 @@ __global__ void __launch_bounds__(256) k_ppo_img(PpoImg m, int n, const uint16_t
 // tile per wave) the hidden layers (256, 128, and H3 = 64 for the paper's
 // Table II network) and the output layer on the matrix cores, the loss of
 // ppo_row_loss, and the gradient back through the output layer down to
-// hidden layer 2's pre-activations (through hidden layer 3 when there is
+// hidden layer 1's pre-activations (through hidden layer 3 when there is
 // one) -- the work of the forward GEMMs, a per-row loss kernel and the
-// data-gradient GEMMs above hidden layer 1, with the same arithmetic per
-// element: each layer's z = (sum over K) + bias and act(z) rounded to BF16
+// data-gradient GEMMs, with the same arithmetic per element: each layer's z = (sum over K) + bias and act(z) rounded to BF16
 // as in the GEMM epilogues, the outputs' gradient rounded to BF16 before it
 // meets the output weights, dZ = (G_next W_next) act'(Z) from the FP32
 // pre-activations, rounded to BF16 for the next product. Within a 32-wide
 // K block the matrix cores sum in their own order, so results agree with a
 // GEMM formulation to FP32 rounding, not bit for bit. Writes H1, H2 (, H3)
-// (the weight gradients' operands), G3b, D2b (, D3b), and per chunk the
-// column sums of dZ2 (, dZ3) (cpart2, cpart3) and the loss sums (lpart,
-// kLossPart columns). The weights are staged in LDS once per workgroup in
-// the fragment order of mlp.hpp (the K of every layer above the first
-// permuted, so a layer's result tile is the next layer's B operand straight
-// from registers), plus the transposed output layer (and hidden layer 3)
-// for the backward products, whose B operands are gradient tiles in the
-// same register layout. A workgroup walks chunks blockIdx.x,
+// (the weight gradients' operands), G3b, D2b (, D3b), D1b, and per chunk
+// the column sums of dZ2 (, dZ3), dZ1 (cpart2, cpart3, cpart) and the loss
+// sums (lpart, kLossPart columns). The weights are staged in LDS once per
+// workgroup in the fragment order of mlp.hpp (the K of every layer above
+// the first permuted, so a layer's result tile is the next layer's B
+// operand straight from registers), plus the transposed output layer (and
+// hidden layer 3) for the backward products, whose B operands are gradient
+// tiles in the same register layout; for the last product W2^T takes W2's
+// place in LDS (and W2 returns before a next chunk). A workgroup walks chunks blockIdx.x,
 // blockIdx.x + gridDim.x, ...; eight waves (two per SIMD) hide each other's
 // matrix-core and LDS latencies.
 constexpr int kFrontWaves = 8;                // one 16-row tile per wave
@@ -354,7 +353,7 @@ template <int H3> struct FrontShape {
   static constexpr int kW3T = (kH2 / 16) * (H3 / 32) * 64; // W3^T [8 row tiles][H3/32 K-blocks][64 lanes]
   static constexpr int kFrags = kW1Frags + kW2Frags + kW3 + kWo + kWoT + kW3T;
   static constexpr int kBias = kH1 + kH2 + H3 + kOut;
-  static constexpr int kCols = kH2 + H3;                   // column sums per wave (dZ2 | dZ3)
+  static constexpr int kCols = kH2 + H3 + kH1;             // column sums per wave (dZ2 | dZ3 | dZ1)
   static constexpr size_t kLds = (size_t)kFrags * 16 + (size_t)kBias * 4 +
                                  (size_t)kFrontWaves * 16 * kPO * 4 +        // outputs, [wave][row][kPO]
                                  (size_t)kFrontWaves * (2 * kPO + 4) * 4 +   // loss sums, [wave][..]
@@ -379,8 +378,10 @@ struct FrontArgs {
   uint16_t* G3b;       // [rows][kPO]
   uint16_t* D2b;       // [rows][128]
   uint16_t* D3b;       // [rows][H3]
+  uint16_t* D1b;       // [rows][256]
   float* cpart2;       // [chunks][128]
   float* cpart3;       // [chunks][H3]
+  float* cpart;        // [chunks][256] (dZ1)
   float* lpart;        // [chunks][kLossPart]
   int nchunks;
 };
@@ -511,7 +512,9 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
     float xa[kAux];
     bool ok = false;
     if (g == 0 && rv) ok = ppo_row_inputs(R, rj, xa);
-    // layers 1 and 2: K-block kb of layer 2 is layer 1's row tiles 2kb, 2kb+1
+    // layers 1 and 2: K-block kb of layer 2 is layer 1's row tiles 2kb, 2kb+1;
+    // layer 1's act' kept for the gradient at the end
+    float dact1[kH1 / 16][4];
     f32x4 acc2[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) acc2[m] = zero4;
@@ -522,7 +525,8 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
       for (int h = 0; h < 2; ++h) {
         const f32x4 d = mfma16x16x32(frag(sW1, (2 * kb + h) * 64 + lane), xb, zero4);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) hb[4 * h + r] = (__bf16)act_f<ACT>(d[r] + sb1[32 * kb + 16 * h + 4 * g + r]);
+        for (int r = 0; r < 4; ++r)
+          hb[4 * h + r] = (__bf16)act_and_grad<ACT>(d[r] + sb1[32 * kb + 16 * h + 4 * g + r], dact1[2 * kb + h][r]);
       }
       if (rv) {
         uint16_t* dst = a.H1 + (size_t)rj * kH1 + 32 * kb + 4 * g;
@@ -626,6 +630,7 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
         if (i == 0) *reinterpret_cast<float4*>(sCol + wave * S::kCols + kH2 + 16 * m + 4 * g) = make_float4(v[0], v[1], v[2], v[3]);
       }
     }
+    bf16x8 d2b[kH2 / 32];  // dZ2 as the B operand of dZ1's product (permuted K)
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       f32x4 d;
@@ -642,6 +647,7 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
       for (int r = 0; r < 4; ++r) {
         v[r] = d[r] * dact2[m][r];
         o[r] = (__bf16)v[r];
+        d2b[m >> 1][4 * (m & 1) + r] = o[r];
       }
       if (rv) *reinterpret_cast<uint2*>(a.D2b + (size_t)rj * kH2 + 16 * m + 4 * g) = bf16x4_bits(o, 0);
       row16_sums(v);
@@ -660,17 +666,48 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
         for (int k = 0; k < L; ++k) sRed[wave * L + k] = v[k];
       }
     }
+    // hidden layer 1's gradient: W2^T (permuted K) replaces W2 in LDS once
+    // every wave is past its last read of the layer images; dZ1^T =
+    // W2^T dZ2^T with dZ2's tiles as B operands, times act'(Z1)
     __syncthreads();
-    if (tid < S::kCols) {
+    {
+      constexpr int nW2 = kW2Frags / NT;
+      uint4 w2t[nW2];
+#pragma unroll
+      for (int u = 0; u < nW2; ++u) w2t[u] = a.img[a.im.fW2T + tid + NT * u];
+#pragma unroll
+      for (int u = 0; u < nW2; ++u) sW2[tid + NT * u] = w2t[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kH1 / 16; ++t) {
+      f32x4 d = zero4;
+#pragma unroll
+      for (int kb = 0; kb < kH2 / 32; ++kb) d = mfma16x16x32(frag(sW2, (t * (kH2 / 32) + kb) * 64 + lane), d2b[kb], d);
+      bf16x8 o;
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[r] = d[r] * dact1[t][r];
+        o[r] = (__bf16)v[r];
+      }
+      if (rv) *reinterpret_cast<uint2*>(a.D1b + (size_t)rj * kH1 + 16 * t + 4 * g) = bf16x4_bits(o, 0);
+      row16_sums(v);
+      if (i == 0)
+        *reinterpret_cast<float4*>(sCol + wave * S::kCols + kH2 + H3 + 16 * t + 4 * g) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    __syncthreads();
+    for (int col = tid; col < S::kCols; col += NT) {
       float v = 0.f;
 #pragma unroll
-      for (int w = 0; w < kFrontWaves; ++w) v += sCol[w * S::kCols + tid];
-      if (tid < kH2) a.cpart2[(size_t)c * kH2 + tid] = v;
-      else a.cpart3[(size_t)c * H3 + tid - kH2] = v;
+      for (int w = 0; w < kFrontWaves; ++w) v += sCol[w * S::kCols + col];
+      if (col < kH2) a.cpart2[(size_t)c * kH2 + col] = v;
+      else if (col < kH2 + H3) a.cpart3[(size_t)c * H3 + col - kH2] = v;
+      else a.cpart[(size_t)c * kH1 + col - kH2 - H3] = v;
     }
-    if (tid >= S::kCols && tid < S::kCols + kLossPart) {
-      // column cc of the row: output cc, log_std cc - O, zero, or statistic
-      const int cc = tid - S::kCols, O = a.O;
+    if (tid < kLossPart) {
+      // column tid of the row: output, log_std, zero, or statistic
+      const int cc = tid, O = a.O;
       const int src = cc < O ? cc : (cc < O + R.J ? kPO + cc - O : (cc >= 16 ? 2 * kPO + cc - 16 : -1));
       constexpr int L = 2 * kPO + 4;
       float v = 0.f;
@@ -678,111 +715,17 @@ __global__ void __launch_bounds__(kFrontThreads) k_ppo_front(FrontArgs a) {
       for (int w = 0; w < kFrontWaves; ++w) v += src < 0 ? 0.f : sRed[w * L + src];
       a.lpart[(size_t)c * kLossPart + cc] = v;
     }
-    __syncthreads();
-  }
-}
-
-// Hidden layer 1's gradient, dZ1 = (dZ2 W2) act'(Z1), per chunk of
-// kFrontRows rows (one 16-row tile per wave): Z1 = X W1^T + b1 recomputed
-// with the forward's own operands and order (so act'(Z1) sees the forward's
-// FP32 values), then per 16-unit tile the product with W2 on the matrix
-// cores (B operand = the BF16 dZ2 rows, K natural), act' applied, BF16
-// rows of D1b out and per-chunk column sums (the hidden-1 bias gradient,
-// cpart). W1's image (as in k_ppo_front) and W2^T's (A fragments [16 row
-// tiles][4 K-blocks][64 lanes], K natural) are staged in LDS once per
-// workgroup. Same arithmetic per element as the data-gradient GEMM it
-// replaces, to FP32 rounding.
-struct Dz1Args {
-  const uint16_t* X;    // [rows][kPX]
-  const uint16_t* D2b;  // [rows][128]
-  const uint16_t* pb;   // W1 at oW0 [256][W], W2 at oW1 [128][256]
-  const float* p;       // b1 at oB0
-  const uint4* img;     // the fragment images (PpoImg): W1 at fW1, W2^T at fW2T
-  int fW1, fW2T;
-  int oW0, oW1, oB0, W, rows;
-  uint16_t* D1b;        // [rows][256]
-  float* cpart;         // [chunks][256]
-  int nchunks;
-};
-constexpr int kW2TFrags = (kH1 / 16) * (kH2 / 32) * 64;
-constexpr size_t kDz1Lds = (size_t)(kW1Frags + kW2TFrags) * 16 + (size_t)kH1 * 4 + (size_t)kFrontWaves * kH1 * 4;
-
-template <int ACT>
-__global__ void __launch_bounds__(kFrontThreads) k_ppo_dz1(Dz1Args a) {
-  constexpr int NT = kFrontThreads;
-  extern __shared__ __align__(16) unsigned char lds[];
-  uint4* sW1 = reinterpret_cast<uint4*>(lds);
-  uint4* sW2T = sW1 + kW1Frags;
-  float* sb1 = reinterpret_cast<float*>(lds + (size_t)(kW1Frags + kW2TFrags) * 16);
-  float* sCol = sb1 + kH1;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int g = lane >> 4, i = lane & 15;
-  {
-    // the two images' 16-byte fragments, all loads before the LDS stores
-    constexpr int nW1 = kW1Frags / NT, nW2T = kW2TFrags / NT;
-    static_assert(kW1Frags % NT == 0 && kW2TFrags % NT == 0 && kH1 <= NT, "the staging loops are exact");
-    uint4 w1[nW1], w2t[nW2T];
+    // W2 back in LDS for the next chunk, if any
+    if (c + (int)gridDim.x < a.nchunks) {
+      constexpr int nW2 = kW2Frags / NT;
+      uint4 w2[nW2];
 #pragma unroll
-    for (int u = 0; u < nW1; ++u) w1[u] = a.img[a.fW1 + tid + NT * u];
+      for (int u = 0; u < nW2; ++u) w2[u] = a.img[a.im.fW2 + tid + NT * u];
 #pragma unroll
-    for (int u = 0; u < nW2T; ++u) w2t[u] = a.img[a.fW2T + tid + NT * u];
-    const float b1 = tid < kH1 ? a.p[a.oB0 + tid] : 0.f;
-#pragma unroll
-    for (int u = 0; u < nW1; ++u) sW1[tid + NT * u] = w1[u];
-#pragma unroll
-    for (int u = 0; u < nW2T; ++u) sW2T[tid + NT * u] = w2t[u];
-    if (tid < kH1) sb1[tid] = b1;
-  }
-  __syncthreads();
-  const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
-  for (int c = blockIdx.x; c < a.nchunks; c += gridDim.x) {
-    const int rj = c * kFrontRows + 16 * wave + i;
-    const bool rv = rj < a.rows;
-    bf16x8 xb, db[kH2 / 32];
-    {
-      const uint4 t = rv ? *reinterpret_cast<const uint4*>(a.X + (size_t)rj * kPX + 8 * g) : make_uint4(0, 0, 0, 0);
-      xb = *reinterpret_cast<const bf16x8*>(&t);
-    }
-#pragma unroll
-    for (int kb = 0; kb < kH2 / 32; ++kb) {
-      const uint4 t =
-          rv ? *reinterpret_cast<const uint4*>(a.D2b + (size_t)rj * kH2 + 32 * kb + 8 * g) : make_uint4(0, 0, 0, 0);
-      db[kb] = *reinterpret_cast<const bf16x8*>(&t);
-    }
-#pragma unroll 4
-    for (int t = 0; t < kH1 / 16; ++t) {
-      const f32x4 z1 = mfma16x16x32(frag(sW1, t * 64 + lane), xb, zero4);
-      f32x4 d = zero4;
-#pragma unroll
-      for (int kb = 0; kb < kH2 / 32; ++kb) d = mfma16x16x32(frag(sW2T, (t * (kH2 / 32) + kb) * 64 + lane), db[kb], d);
-      bf16x8 o;
-      float v[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        v[r] = d[r] * act_grad<ACT>(z1[r] + sb1[16 * t + 4 * g + r]);
-        o[r] = (__bf16)v[r];
-      }
-      if (rv) *reinterpret_cast<uint2*>(a.D1b + (size_t)rj * kH1 + 16 * t + 4 * g) = bf16x4_bits(o, 0);
-      row16_sums(v);
-      if (i == 0) *reinterpret_cast<float4*>(sCol + wave * kH1 + 16 * t + 4 * g) = make_float4(v[0], v[1], v[2], v[3]);
-    }
-    __syncthreads();
-    if (tid < kH1) {
-      float v = 0.f;
-#pragma unroll
-      for (int w = 0; w < kFrontWaves; ++w) v += sCol[w * kH1 + tid];
-      a.cpart[(size_t)c * kH1 + tid] = v;
+      for (int u = 0; u < nW2; ++u) sW2[tid + NT * u] = w2[u];
     }
     __syncthreads();
   }
-}
-
-template <int ACT> static hipError_t launch_dz1(hipStream_t st, const Dz1Args& a, int n_cu) {
-  hipError_t e = lds_limit((const void*)k_ppo_dz1<ACT>, kDz1Lds);
-  if (e != hipSuccess) return e;
-  const int grid = a.nchunks < n_cu ? a.nchunks : n_cu;
-  k_ppo_dz1<ACT><<<grid, kFrontThreads, kDz1Lds, st>>>(a);
-  return hipGetLastError();
 }
 
 // Rows per block of the loss sums and the fused front's column sums
@@ -1080,8 +1023,8 @@ static hipError_t minibatch_grad_t(sg_ppo* o, const PpoRows& rows, const sg_ppo_
   fa.oWo = o->oW[L]; fa.oBo = o->oB[L]; fa.oLS = o->oLS;
   fa.W = W; fa.O = O; fa.rows = rows;
   fa.clip = cfg->clip; fa.c_v = cfg->value_coef; fa.inv_b = 1.f / (float)B; fa.w_stats = w_stats;
-  fa.H1 = o->H1; fa.H2 = o->H2; fa.H3 = o->H3; fa.G3b = o->G3b; fa.D2b = o->D2b; fa.D3b = o->D3b;
-  fa.cpart2 = o->cpart2; fa.cpart3 = o->cpart3; fa.lpart = o->lpart;
+  fa.H1 = o->H1; fa.H2 = o->H2; fa.H3 = o->H3; fa.G3b = o->G3b; fa.D2b = o->D2b; fa.D3b = o->D3b; fa.D1b = o->D1b;
+  fa.cpart2 = o->cpart2; fa.cpart3 = o->cpart3; fa.cpart = o->cpart; fa.lpart = o->lpart;
   fa.nchunks = lb;
   {
     // the two networks sg_ppo_create accepts: 256-128 tanh, 256-128-64 ELU
@@ -1105,17 +1048,7 @@ static hipError_t minibatch_grad_t(sg_ppo* o, const PpoRows& rows, const sg_ppo_
   }
   jobs[nj++] = wg.add(kH2, kH1, B, o->D2b, kH2, o->H1, kH1, o->g + o->oW[1], kH1, o->ws + 1 * kWeightGradWs);
   jobs[nj++] = partial_rows(o->cpart2, lb, kH2, kH2, o->g + o->oB[1]);
-  // dZ1 = (dZ2 W2) * act'(Z1), with the column sums of dZ1 (hidden-1 bias);
-  // Z1 (W inputs) is recomputed rather than stored
-  {
-    Dz1Args da;
-    da.X = o->X; da.D2b = o->D2b; da.pb = o->pb; da.p = o->p;
-    da.img = reinterpret_cast<const uint4*>(o->img); da.fW1 = o->im.fW1; da.fW2T = o->im.fW2T;
-    da.oW0 = o->oW[0]; da.oW1 = o->oW[1]; da.oB0 = o->oB[0]; da.W = W; da.rows = B;
-    da.D1b = o->D1b; da.cpart = o->cpart; da.nchunks = lb;
-    const hipError_t e = launch_dz1<ACT>(st, da, c->n_cu);
-    if (e != hipSuccess) return e;
-  }
+  // hidden layer 1's weight gradient from the front's D1b
   jobs[nj++] = wg.add(kH1, W, B, o->D1b, kH1, o->X, kPX, o->g + o->oW[0], W, o->ws + 0 * kWeightGradWs);
   jobs[nj++] = partial_rows(o->cpart, lb, kH1, kH1, o->g + o->oB[0]);
   wg.launch(st);
@@ -1258,7 +1191,7 @@ sg_status sg_ppo_create(sg_ctx* c, const sg_policy_arch* arch, const float* para
     m.fWoT = m.fWo + (m.KO / 32) * 64;
     m.fW3T = m.fWoT + (m.KO / 16) * 64;
     m.fW2T = m.fW3T + (h3 ? FrontShape<64>::kW3T : 0);
-    m.frags = m.fW2T + kW2TFrags;
+    m.frags = m.fW2T + kW2Frags;  // W2^T: as many fragments as W2
   }
   const size_t R = (size_t)max_samples, P = (size_t)o->P;
   // split-K partials: one region per layer (launch_weight_grad_partials bound)
