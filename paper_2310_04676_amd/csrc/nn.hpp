@@ -331,8 +331,19 @@ __device__ __forceinline__ double sum_block(const SumJob& j, int blk, const SumN
   const int MN = j.M * j.N;
   const size_t st = j.stride > 0 ? (size_t)j.stride : (size_t)MN;
   float s = 0.f;
-  if (o < MN)
-    for (int z = grp; z < j.splits; z += G) s += j.part[(size_t)z * st + o];
+  if (o < MN) {
+    // this thread's slabs grp, grp + G, ... in order; eight loads in flight
+    // at a time (the sum order is unchanged)
+    int z = grp;
+    for (; z + 7 * G < j.splits; z += 8 * G) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = j.part[(size_t)(z + u * G) * st + o];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; z < j.splits; z += G) s += j.part[(size_t)z * st + o];
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   double sq = 0;
