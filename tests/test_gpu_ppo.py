@@ -17,7 +17,9 @@ Tolerances:
 * several steps: Adam's first steps move every parameter by about the
   learning rate with the sign of its gradient, so parameters whose gradient
   is below the gradient's error can flip; the update direction is compared
-  by cosine >= 0.95 and the averaged statistics within 2e-2 relative.
+  by cosine >= 0.95 and the averaged statistics within 2e-2 relative. That
+  a longer update is exactly the single step repeated is checked bit for
+  bit (two one-epoch updates against one two-epoch update).
 """
 import numpy as np
 import pytest
@@ -172,6 +174,27 @@ def test_one_update_step_is_clip_and_adam_of_the_gradient(sg):
     ref_sim.set_policy(upd)
     assert torch.equal(sim.policy_forward(x), ref_sim.policy_forward(x))
     ppo.close()
+
+
+def test_epochs_compose_exactly(sg):
+    """An update of two epochs (one minibatch each) equals two one-epoch
+    updates bit for bit (the Adam step count, the advantage statistics and
+    the gathered rows carry over): with the single step pinned above to clip
+    + Adam of the GPU's own gradient, every step of a longer update is that
+    step."""
+    T, N = 4, 128
+    outs = []
+    for split in (False, True):
+        w, sim, ppo, params, bufs = _setup(sg, N, T, seed=36)
+        if split:
+            ppo.update(bufs, T, cfg=dict(epochs=1, minibatches=1))
+            ppo.update(bufs, T, cfg=dict(epochs=1, minibatches=1))
+        else:
+            ppo.update(bufs, T, cfg=dict(epochs=2, minibatches=1))
+        outs.append(ppo.params())
+        ppo.close()
+    np.testing.assert_array_equal(outs[0], outs[1])
+    assert not np.array_equal(outs[0], params)
 
 
 def test_update_matches_oracle(sg):
